@@ -1,0 +1,283 @@
+"""ctypes wrapper of the FP64 oracle (``oracle.c``).  Test infrastructure only.
+
+Each wrapper takes numpy arrays (any float dtype; they are promoted to
+float64, which is exact for the float32/float16 storage values) and returns
+float64 numpy arrays.  ``forward`` and ``train_step`` chain the stages in the
+order of Fig. 2 of the paper: march -> deform -> encode -> MLP -> composite.
+"""
+from __future__ import annotations
+
+import ctypes
+import functools
+
+import numpy as np
+
+from .build import ensure_built
+
+_d = ctypes.POINTER(ctypes.c_double)
+_f = ctypes.POINTER(ctypes.c_float)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+_i64 = ctypes.POINTER(ctypes.c_int64)
+_u8 = ctypes.POINTER(ctypes.c_uint8)
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_D = ctypes.c_double
+
+
+@functools.lru_cache(maxsize=None)
+def lib():
+    L = ctypes.CDLL(ensure_built())
+    L.oracle_march.restype = _I64
+    L.oracle_march.argtypes = [_f, _f, _I64, _u8, _I32, _f, ctypes.c_float, _I32, _I32,
+                               _d, _d, _i64, _I64, _i64, _i32, _d]
+    L.oracle_skin_weights.restype = None
+    L.oracle_skin_weights.argtypes = [_d, _I32, _I32, _I32, _I32, _d, _d, _I64, _d, _d]
+    L.oracle_lbs.restype = None
+    L.oracle_lbs.argtypes = [_d, _I32, _d, _I32, _I32, _I32, _d, _d, _I64, _d]
+    L.oracle_deform.restype = None
+    L.oracle_deform.argtypes = [_d, _I64, _d, _I32, _d, _I32, _I32, _I32, _d, _d, _I32, _D, _D,
+                                _d, _i32, _d, _d, _d, _i32, _i32, _d]
+    L.oracle_deform_bwd.restype = None
+    L.oracle_deform_bwd.argtypes = [_d, _d, _i32, _I64, _d, _I32, _d, _I32, _I32, _I32, _d, _d, _d, _d]
+    L.oracle_hash_resolutions.restype = None
+    L.oracle_hash_resolutions.argtypes = [_I32, _D, _D, _i32]
+    L.oracle_hash_encode.restype = None
+    L.oracle_hash_encode.argtypes = [_d, _i32, _I64, _d, _I32, _I32, _I64, _i32, _d, _d]
+    L.oracle_hash_encode_bwd.restype = None
+    L.oracle_hash_encode_bwd.argtypes = [_d, _d, _i32, _I64, _d, _I32, _I32, _I64, _i32, _d, _d, _d]
+    L.oracle_mlp_fwd.restype = None
+    L.oracle_mlp_fwd.argtypes = [_d, _i32, _I64, _d, _i32, _I32, _d, _d]
+    L.oracle_mlp_bwd.restype = None
+    L.oracle_mlp_bwd.argtypes = [_d, _d, _d, _i32, _I64, _d, _i32, _I32, _d, _d]
+    L.oracle_composite_fwd.restype = None
+    L.oracle_composite_fwd.argtypes = [_d, _d, _i64, _d, _I64, _D, _d, _d, _i32, _d]
+    L.oracle_composite_bwd.restype = None
+    L.oracle_composite_bwd.argtypes = [_d, _d, _d, _d, _i64, _d, _i32, _I64, _d, _d]
+    L.oracle_l2_loss.restype = _D
+    L.oracle_l2_loss.argtypes = [_d, _d, _I64, _d]
+    return L
+
+
+def _p(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(np.asarray(a, dtype=dt))
+
+
+# ---------------------------------------------------------------- march
+def march(rays_o, rays_d, occ, aabb, dt=0.0, n_per_ray=0, max_steps=128):
+    """Sec. 3.2-3.3: uniform midpoint samples along each ray inside the
+    occupancy box, keeping those in occupied cells (FP32 decisions)."""
+    ro = _c(rays_o, np.float32)
+    rd = _c(rays_d, np.float32)
+    R = ro.shape[0]
+    occ_p = None
+    G = 0
+    if occ is not None:
+        occ = _c(occ, np.uint8)
+        G = occ.shape[0]
+        occ_p = _p(occ, _u8)
+    box = _c(aabb, np.float32)
+    ray_off = np.zeros(R + 1, np.int64)
+    ray_cnt = np.zeros(R, np.int32)
+    ray_dt = np.zeros(R, np.float64)
+    z = np.zeros(1)
+    zi = np.zeros(1, np.int64)
+    total = lib().oracle_march(_p(ro, _f), _p(rd, _f), R, occ_p, G, _p(box, _f), float(dt), n_per_ray,
+                               max_steps, _p(z, _d), _p(z, _d), _p(zi, _i64), 0,
+                               _p(ray_off, _i64), _p(ray_cnt, _i32), _p(ray_dt, _d))
+    xs = np.zeros((total, 3))
+    ts = np.zeros(total)
+    rid = np.zeros(total, np.int64)
+    lib().oracle_march(_p(ro, _f), _p(rd, _f), R, occ_p, G, _p(box, _f), float(dt), n_per_ray,
+                       max_steps, _p(xs, _d), _p(ts, _d), _p(rid, _i64), total,
+                       _p(ray_off, _i64), _p(ray_cnt, _i32), _p(ray_dt, _d))
+    return dict(xs=xs, ts=ts, ray_id=rid, ray_off=ray_off, ray_cnt=ray_cnt, ray_dt=ray_dt)
+
+
+# ------------------------------------------------------- skinning / LBS
+def skin_weights(W, skin_aabb, x, grad=False):
+    W = _f64(W)
+    Dz, Dy, Dx, nb = W.shape
+    x = _f64(x).reshape(-1, 3)
+    n = x.shape[0]
+    w = np.zeros((n, nb))
+    dw = np.zeros((n, nb, 3)) if grad else None
+    box = _f64(skin_aabb)
+    lib().oracle_skin_weights(_p(W, _d), Dx, Dy, Dz, nb, _p(box, _d), _p(x, _d), n, _p(w, _d), _p(dw, _d))
+    return (w, dw) if grad else w
+
+
+def lbs(B, W, skin_aabb, x):
+    """Eq. (7): posed position of canonical points x."""
+    W = _f64(W)
+    Dz, Dy, Dx, nb = W.shape
+    B = _f64(B)
+    x = _f64(x).reshape(-1, 3)
+    out = np.zeros_like(x)
+    lib().oracle_lbs(_p(B, _d), nb, _p(W, _d), Dx, Dy, Dz, _p(_f64(skin_aabb), _d), _p(x, _d), x.shape[0],
+                     _p(out, _d))
+    return out
+
+
+def deform(xp, B, W, skin_aabb, hash_aabb, max_iter=10, tol_stop=1e-6, tol_valid=1e-5, details=False):
+    """Sec. 3.1: canonical correspondences x* of posed points by multi-init
+    Broyden root finding.  Returns dict(xc, bone, resid[, init_x, init_r,
+    init_it, n_roots, roots])."""
+    W = _f64(W)
+    Dz, Dy, Dx, nb = W.shape
+    B = _f64(B)
+    xp = _f64(xp).reshape(-1, 3)
+    S = xp.shape[0]
+    out = dict(xc=np.zeros((S, 3)), bone=np.zeros(S, np.int32), resid=np.zeros(S))
+    if details:
+        out.update(init_x=np.zeros((S, nb, 3)), init_r=np.zeros((S, nb)), init_it=np.zeros((S, nb), np.int32),
+                   n_roots=np.zeros(S, np.int32), roots=np.zeros((S, nb, 3)))
+    g = out.get
+    lib().oracle_deform(_p(xp, _d), S, _p(B, _d), nb, _p(W, _d), Dx, Dy, Dz, _p(_f64(skin_aabb), _d),
+                        _p(_f64(hash_aabb), _d), max_iter, tol_stop, tol_valid,
+                        _p(out["xc"], _d), _p(out["bone"], _i32), _p(out["resid"], _d),
+                        _p(g("init_x"), _d), _p(g("init_r"), _d), _p(g("init_it"), _i32),
+                        _p(g("n_roots"), _i32), _p(g("roots"), _d))
+    return out
+
+
+def deform_bwd(grad_xc, xc, bone, B, W, skin_aabb):
+    """Implicit-function-theorem backward through the root finder."""
+    W = _f64(W)
+    Dz, Dy, Dx, nb = W.shape
+    B = _f64(B)
+    xc = _f64(xc).reshape(-1, 3)
+    S = xc.shape[0]
+    gxp = np.zeros((S, 3))
+    gB = np.zeros(B.shape)
+    gW = np.zeros(W.shape)
+    lib().oracle_deform_bwd(_p(_f64(grad_xc), _d), _p(xc, _d), _p(_c(bone, np.int32), _i32), S, _p(B, _d), nb,
+                            _p(W, _d), Dx, Dy, Dz, _p(_f64(skin_aabb), _d), _p(gxp, _d), _p(gB, _d), _p(gW, _d))
+    return gxp, gB, gW
+
+
+# ----------------------------------------------------------- hash grid
+def resolutions(L, base=16.0, growth=1.38):
+    res = np.zeros(L, np.int32)
+    lib().oracle_hash_resolutions(L, base, growth, _p(res, _i32))
+    return res
+
+
+def hash_encode(x, table, res, aabb, valid=None):
+    table = _f64(table)
+    L, T, F = table.shape
+    x = _f64(x).reshape(-1, 3)
+    S = x.shape[0]
+    feat = np.zeros((S, L * F))
+    v = None if valid is None else _c(valid, np.int32)
+    lib().oracle_hash_encode(_p(x, _d), _p(v, _i32), S, _p(table, _d), L, F, T, _p(_c(res, np.int32), _i32),
+                             _p(_f64(aabb), _d), _p(feat, _d))
+    return feat
+
+
+def hash_encode_bwd(grad_feat, x, table, res, aabb, valid=None):
+    table = _f64(table)
+    L, T, F = table.shape
+    x = _f64(x).reshape(-1, 3)
+    S = x.shape[0]
+    gt = np.zeros(table.shape)
+    gx = np.zeros((S, 3))
+    v = None if valid is None else _c(valid, np.int32)
+    lib().oracle_hash_encode_bwd(_p(_f64(grad_feat), _d), _p(x, _d), _p(v, _i32), S, _p(table, _d), L, F, T,
+                                 _p(_c(res, np.int32), _i32), _p(_f64(aabb), _d), _p(gt, _d), _p(gx, _d))
+    return gt, gx
+
+
+# ----------------------------------------------------------------- MLP
+def mlp_fwd(feat, params, widths=(32, 64, 64, 4), valid=None):
+    feat = _f64(feat)
+    S = feat.shape[0]
+    sigma = np.zeros(S)
+    rgb = np.zeros((S, 3))
+    v = None if valid is None else _c(valid, np.int32)
+    w = np.asarray(widths, np.int32)
+    lib().oracle_mlp_fwd(_p(feat, _d), _p(v, _i32), S, _p(_f64(params), _d), _p(w, _i32), len(widths) - 1,
+                         _p(sigma, _d), _p(rgb, _d))
+    return sigma, rgb
+
+
+def mlp_bwd(grad_sigma, grad_rgb, feat, params, widths=(32, 64, 64, 4), valid=None):
+    feat = _f64(feat)
+    S = feat.shape[0]
+    params = _f64(params)
+    gp = np.zeros(params.shape)
+    gf = np.zeros(feat.shape)
+    v = None if valid is None else _c(valid, np.int32)
+    w = np.asarray(widths, np.int32)
+    lib().oracle_mlp_bwd(_p(_f64(grad_sigma), _d), _p(_f64(grad_rgb), _d), _p(feat, _d), _p(v, _i32), S,
+                         _p(params, _d), _p(w, _i32), len(widths) - 1, _p(gp, _d), _p(gf, _d))
+    return gp, gf
+
+
+# ----------------------------------------------------------- composite
+def composite_fwd(sigma, rgb, ray_off, ray_dt, T_thresh=0.0):
+    ray_off = _c(ray_off, np.int64)
+    R = ray_off.shape[0] - 1
+    color = np.zeros((R, 3))
+    opac = np.zeros(R)
+    n_used = np.zeros(R, np.int32)
+    Tf = np.zeros(R)
+    lib().oracle_composite_fwd(_p(_f64(sigma), _d), _p(_f64(rgb), _d), _p(ray_off, _i64), _p(_f64(ray_dt), _d),
+                               R, float(T_thresh), _p(color, _d), _p(opac, _d), _p(n_used, _i32), _p(Tf, _d))
+    return dict(color=color, opacity=opac, n_used=n_used, T_final=Tf)
+
+
+def composite_bwd(grad_color, sigma, rgb, ray_off, ray_dt, n_used, grad_opacity=None):
+    ray_off = _c(ray_off, np.int64)
+    R = ray_off.shape[0] - 1
+    S = int(ray_off[-1])
+    gs = np.zeros(S)
+    gr = np.zeros((S, 3))
+    go = None if grad_opacity is None else _f64(grad_opacity)
+    lib().oracle_composite_bwd(_p(_f64(grad_color), _d), _p(go, _d), _p(_f64(sigma), _d), _p(_f64(rgb), _d),
+                               _p(ray_off, _i64), _p(_f64(ray_dt), _d), _p(_c(n_used, np.int32), _i32), R,
+                               _p(gs, _d), _p(gr, _d))
+    return gs, gr
+
+
+def l2_loss(color, target):
+    color = _f64(color)
+    g = np.zeros(color.shape)
+    Lv = lib().oracle_l2_loss(_p(color, _d), _p(_f64(target), _d), color.shape[0], _p(g, _d))
+    return Lv, g
+
+
+# ------------------------------------------------------- whole chain
+def forward(w, details=False, table=None, params=None):
+    """Fig. 2 order on a synth.Workload: march, deform, encode, MLP, composite.
+    ``table`` / ``params`` override the workload's (e.g. FP16/BF16-rounded copies)."""
+    m = march(w.rays_o, w.rays_d, w.occ, w.occ_aabb, w.dt, w.n_per_ray, w.max_steps)
+    d = deform(m["xs"], w.B, w.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop, w.tol_valid, details=details)
+    res = resolutions(w.L, w.base_res, w.growth)
+    tab = w.table if table is None else table
+    prm = w.mlp if params is None else params
+    feat = hash_encode(d["xc"], tab, res, w.hash_aabb, valid=d["bone"])
+    sigma, rgb = mlp_fwd(feat, prm, w.widths, valid=d["bone"])
+    c = composite_fwd(sigma, rgb, m["ray_off"], m["ray_dt"], w.T_thresh)
+    return dict(march=m, deform=d, res=res, feat=feat, sigma=sigma, rgb=rgb, **c)
+
+
+def train_step(w):
+    """Forward, L2 loss against w.target, and every backward pass:
+    composite -> MLP -> hash encode (table and x*) -> deform (x', B, W)."""
+    f = forward(w)
+    loss, gC = l2_loss(f["color"], w.target)
+    gs, gr = composite_bwd(gC, f["sigma"], f["rgb"], f["march"]["ray_off"], f["march"]["ray_dt"], f["n_used"])
+    gp, gfeat = mlp_bwd(gs, gr, f["feat"], w.mlp, w.widths, valid=f["deform"]["bone"])
+    gt, gx = hash_encode_bwd(gfeat, f["deform"]["xc"], w.table, f["res"], w.hash_aabb, valid=f["deform"]["bone"])
+    gxp, gB, gW = deform_bwd(gx, f["deform"]["xc"], f["deform"]["bone"], w.B, w.W, w.skin_aabb)
+    f.update(loss=loss, grad_color=gC, grad_sigma=gs, grad_rgb=gr, grad_params=gp, grad_feat=gfeat,
+             grad_table=gt, grad_xc=gx, grad_xp=gxp, grad_B=gB, grad_W=gW)
+    return f

@@ -1,0 +1,213 @@
+/*
+ * ia355.h -- C ABI of libia355.so, the MI355X (gfx950) deform-and-query path
+ * of InstantAvatar (arXiv 2212.10550): march posed rays through an occupancy
+ * grid, map each posed sample to canonical space by root finding on linear
+ * blend skinning, encode it with a multiresolution hash grid, decode it with
+ * a small MLP and alpha-composite per ray -- forward and backward.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array pointers are DEVICE pointers owned by the caller unless marked
+ *    "host".  The library never allocates or frees device memory and keeps
+ *    no global state; scratch space is a caller buffer sized by the matching
+ *    *_workspace_size() call.
+ *  - Every call only enqueues work on `stream` (a hipStream_t; NULL = the
+ *    default stream) and returns without synchronising.  The return value
+ *    reports argument validation and launch errors only.
+ *  - Point sets are structure-of-arrays: [3][ld] floats (x row, y row,
+ *    z row, each of leading dimension ld >= S).  Rays are [R][3] floats.
+ *    Bone transforms B are [nb][3][4] row-major rigid transforms
+ *    (canonical -> posed).  The skinning grid W is [Dz][Dy][Dx][nb].  The hash
+ *    table is [L][T][F] with T = 2^log2T.  Features are level-major
+ *    [L][S][F].  Boxes (aabb) are host float[6] = (lo x, lo y, lo z,
+ *    hi x, hi y, hi z).
+ *  - A sample whose `bone` is negative has no canonical correspondence: it
+ *    gets density 0, zero features and zero gradients (the paper's "set
+ *    their density to zero" for skipped points, Sec. 3.3).
+ *  - grad_* outputs documented as "accumulated" are added to (+=), so the
+ *    caller zeroes them (ia355_zero) or sums over several calls.
+ */
+#ifndef IA355_H
+#define IA355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IA355_OK 0
+#define IA355_ERR_INVALID_ARG 1 /* null required pointer, bad size, dtype or shape */
+#define IA355_ERR_WORKSPACE 2   /* workspace smaller than *_workspace_size() */
+#define IA355_ERR_UNSUPPORTED 3 /* valid but unimplemented combination */
+#define IA355_ERR_HIP 4         /* a HIP launch failed; see ia355_error_string */
+
+#define IA355_F32 0
+#define IA355_F16 1
+#define IA355_BF16 2
+
+typedef void *ia355_stream_t; /* hipStream_t */
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t ia355_version(void);
+/* Human-readable text for a status code (static storage, never NULL). */
+const char *ia355_error_string(int32_t status);
+
+/* Fill `bytes` bytes at device pointer p with zeros (a kernel, not a
+ * memset node, so the call may be captured in a HIP graph). */
+int32_t ia355_zero(void *p, size_t bytes, ia355_stream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Occupancy grid (Sec. 3.3, "Empty Space Skipping").                  */
+/* ------------------------------------------------------------------ */
+/* Pack a binary occupancy grid occ [G][G][G] (uint8, z-major, x fastest,
+ * non-zero = occupied) into bits [ceil(G^3/32)] (bit i of word i/32 is cell
+ * i = x + G*(y + G*z)). */
+int32_t ia355_occ_pack(const uint8_t *occ, int32_t G, uint32_t *bits, ia355_stream_t stream);
+
+/* Ray marching with empty-space skipping (Sec. 3.2 ray r = o + t d with N
+ * samples between the near and far bound; Sec. 3.3 samples in
+ * non-occupied cells are skipped).
+ * Each ray is clipped to `aabb` (t >= 0); samples sit at the midpoints
+ * t_k = t_near + (k + 1/2) dt, k < max_steps, t_k < t_far; with n_per_ray > 0
+ * the step is dt = (t_far - t_near) / n_per_ray, otherwise `dt`.  A sample is
+ * kept iff its cell in the G^3 grid over `aabb` is occupied (occ_bits NULL:
+ * all cells occupied).  Positions and decisions use IEEE single precision
+ * with no fused operations.
+ * Outputs (compacted, rays in order, samples in t order):
+ *   xs [3][cap] positions, ts [cap] ray parameter, ray_id [cap],
+ *   ray_off [R+1] first-sample offsets (int64), ray_cnt [R], ray_dt [R]
+ *   (the ray's uniform step: every kept sample's delta, Eq. 8),
+ *   n_samples [1] device int64 total kept count.
+ * If *n_samples > cap, samples at offsets >= cap are not written: the caller
+ * must compare after the stream completes.
+ * ws: ia355_march_workspace_size(R) bytes. */
+size_t ia355_march_workspace_size(int64_t R);
+int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d, int64_t R,
+                            const uint32_t *occ_bits, int32_t G, const float *aabb,
+                            float dt, int32_t n_per_ray, int32_t max_steps,
+                            float *xs, float *ts, int32_t *ray_id, int64_t cap,
+                            int64_t *ray_off, int32_t *ray_cnt, float *ray_dt, int64_t *n_samples,
+                            void *ws, size_t ws_bytes, ia355_stream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Articulation (Sec. 3.1, Eq. 5-7): canonical correspondences x* of    */
+/* posed points x' as roots of x' = sum_i w_i(x) B_i x, by multi-init   */
+/* Broyden root finding (the paper's Fast-SNARF root finding).         */
+/* ------------------------------------------------------------------ */
+/* w(x) is the trilinear interpolant of W over skin_aabb (vertices on the
+ * box corners, coordinates clamped to the box).  For each bone i the solver
+ * starts at x0 = B_i^{-1} x' with the inverse Jacobian H0 = J(x0)^{-1},
+ * takes up to max_iter Broyden steps (good update, Sherman-Morrison form)
+ * and stops once ||g|| < tol_stop.  An init is valid when its final
+ * ||g|| < tol_valid and its point lies in hash_aabb; the valid init with the
+ * lowest residual is kept (ties: lowest bone).  All arithmetic is FP32.
+ *   xp [3][ld]   posed points
+ *   xc [3][ld]   canonical roots (the start point of bone 0 when invalid)
+ *   bone [S]     chosen init, -1 when no init is valid
+ *   resid [S]    residual of the chosen init (nullable)
+ *   steps [S]    Broyden steps summed over all inits (nullable)
+ * ws: ia355_deform_workspace_size(Dx, Dy, Dz) bytes (the per-pose blended
+ * transform grid sum_i W[v][i] B_i). */
+size_t ia355_deform_workspace_size(int32_t Dx, int32_t Dy, int32_t Dz);
+int32_t ia355_snarf_deform(const float *xp, int64_t S, int64_t ld,
+                           const float *B, int32_t nb, const float *W,
+                           int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb, const float *hash_aabb,
+                           int32_t max_iter, float tol_stop, float tol_valid,
+                           float *xc, int16_t *bone, float *resid, int16_t *steps,
+                           void *ws, size_t ws_bytes, ia355_stream_t stream);
+
+/* Backward through the root finder by the implicit function theorem (no
+ * unrolling of Broyden): with J = dg/dx at x* and v = J^{-T} grad_xc,
+ *   grad_xp [3][ld] = v                            (overwritten, nullable)
+ *   grad_B  [nb][3][4] += -sum_s w_b(x*) v x*_h^T   (accumulated, nullable)
+ *   grad_W  [Dz][Dy][Dx][nb] += -tri_c(x*) v^T (B_b x*_h) (accumulated, nullable)
+ * Samples with bone < 0 contribute nothing (grad_xp = 0). */
+int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int16_t *bone, int64_t S, int64_t ld,
+                               const float *B, int32_t nb, const float *W,
+                               int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
+                               float *grad_xp, float *grad_B, float *grad_W, ia355_stream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Canonical field, Sec. 3.1 Eq. 1-2 (Instant-NGP encoding + MLP).      */
+/* ------------------------------------------------------------------ */
+/* Multiresolution hash encoding: level l has resolution
+ * N_l = floor(base_res * growth^l); a canonical point (clamped to `aabb`)
+ * is scaled to u = x_n N_l, the eight surrounding vertices are looked up --
+ * densely (index x + (N+1)(y + (N+1) z)) when (N_l+1)^3 <= T, else by the
+ * spatial hash (x*1 ^ y*2654435761 ^ z*805459861) mod 2^32 mod T -- and
+ * trilinearly interpolated; the levels are concatenated.
+ *   xc [3][ld], bone [S] (nullable: all valid)
+ *   table [L][T][F] of table_dtype (IA355_F32 or IA355_F16)
+ *   feat  [L][S][F] of feat_dtype (IA355_F32 or IA355_BF16); zero for
+ *         invalid samples.  F must be 2.  Interpolation is FP32. */
+int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, int64_t ld,
+                              const void *table, int32_t table_dtype, int32_t L, int32_t F, int32_t log2T,
+                              double base_res, double growth, const float *aabb,
+                              void *feat, int32_t feat_dtype, ia355_stream_t stream);
+
+/* Backward of the encoding.  grad_feat [L][S][F] FP32.
+ *   grad_table [L][T][F] FP32 accumulated (atomic adds; nullable)
+ *   grad_xc [3][ld] overwritten with sum_l sum_c (grad w_c)(theta_c . grad_feat_l)
+ *   (nullable; needs the table). */
+int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone,
+                                  int64_t S, int64_t ld, const void *table, int32_t table_dtype,
+                                  int32_t L, int32_t F, int32_t log2T, double base_res, double growth,
+                                  const float *aabb, float *grad_table, float *grad_xc, ia355_stream_t stream);
+
+/* The decoder MLP 32 -> 64 -> 64 -> 4 with ReLU hidden layers; outputs
+ * sigma = exp(o_0) (clamped at exp(80)) and c = sigmoid(o_1..3).
+ *   feat [L][S][F] (L*F = 32) of feat_dtype; params FP32 flat
+ *   (per layer W [out][in] row-major, then b [out]; 6532 floats)
+ *   dtype: IA355_F32 (FP32 MFMA) or IA355_BF16 (BF16 MFMA, FP32 accumulate;
+ *   requires feat_dtype BF16)
+ *   sigma [S], rgb [3][ld] FP32; invalid samples (bone < 0) get 0. */
+int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int16_t *bone, int64_t S, int64_t ld,
+                      const float *params, int32_t dtype, float *sigma, float *rgb, ia355_stream_t stream);
+
+/* Backward of the MLP (the forward is recomputed from feat; nothing is
+ * saved).  grad_sigma [S], grad_rgb [3][ld] FP32.
+ *   grad_params [6532] FP32 accumulated
+ *   grad_feat [L][S][F] FP32 overwritten (nullable)
+ * ws: ia355_mlp_bwd_workspace_size(S) bytes (per-block weight-gradient
+ * partials, reduced in a fixed order: the result is deterministic). */
+size_t ia355_mlp_bwd_workspace_size(int64_t S);
+int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb, const void *feat, int32_t feat_dtype,
+                      const int16_t *bone, int64_t S, int64_t ld, const float *params, int32_t dtype,
+                      float *grad_params, float *grad_feat, void *ws, size_t ws_bytes, ia355_stream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Volume rendering, Sec. 3.2 Eq. 8 (alpha_i = 1 - exp(-sigma_i delta_i)) */
+/* with early termination (Sec. 3.4: stop once opacity reaches one).   */
+/* ------------------------------------------------------------------ */
+/* Per ray r, over its samples ray_off[r] .. ray_off[r+1]-1 in order, with
+ * delta = ray_dt[r]: T_0 = 1, sample i is used iff T_i >= T_thresh (every
+ * later one is then skipped), C = sum T_i alpha_i c_i, A = sum T_i alpha_i,
+ * T_{i+1} = T_i (1 - alpha_i).  sigma [S], rgb [3][ld].
+ * Outputs: color [R][3], opacity [R], n_used [R], T_final [R]. */
+int32_t ia355_volrender_fwd(const float *sigma, const float *rgb, int64_t ld, const int64_t *ray_off,
+                            const float *ray_dt, int64_t R, float T_thresh,
+                            float *color, float *opacity, int32_t *n_used, float *T_final, ia355_stream_t stream);
+
+/* Backward: grad_rgb_i = T_i alpha_i g_C,
+ * grad_sigma_i = delta [T_{i+1} (g_C . c_i) - g_C . (C - C_<=i)] + g_A delta T_final;
+ * unused samples get 0.  grad_color [R][3], grad_opacity [R] (nullable);
+ * color, T_final are the forward outputs.  grad_sigma [S], grad_rgb [3][ld]
+ * overwritten for every sample of every ray. */
+int32_t ia355_volrender_bwd(const float *grad_color, const float *grad_opacity,
+                            const float *sigma, const float *rgb, int64_t ld, const int64_t *ray_off,
+                            const float *ray_dt, const int32_t *n_used, const float *color, const float *T_final,
+                            int64_t R, float *grad_sigma, float *grad_rgb, ia355_stream_t stream);
+
+/* Photometric L2 loss (the benchmark's stand-in for the Huber loss of
+ * Eq. 9, whose threshold the paper does not give): loss[0] = mean over R*3
+ * of (color - target)^2 (device float, overwritten); grad_color [R][3] =
+ * dloss/dcolor (overwritten).  color, target [R][3]. */
+int32_t ia355_l2_loss(const float *color, const float *target, int64_t R, float *loss, float *grad_color,
+                      ia355_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IA355_H */

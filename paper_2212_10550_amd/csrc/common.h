@@ -1,0 +1,69 @@
+// Internal helpers of libia355 (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ia355.h"
+
+#define IA355_VERSION 100
+
+namespace ia355 {
+
+constexpr int kWave = 64;
+
+inline int32_t launch_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? IA355_OK : IA355_ERR_HIP;
+}
+
+inline hipStream_t as_stream(ia355_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Grid size for a grid-stride kernel over n items: enough blocks to fill
+// every CU several times (256 CUs on MI355X), never more than needed.
+inline unsigned grid_for(int64_t n, int block, int64_t max_blocks = 256 * 16) {
+  int64_t g = ceil_div(n, block);
+  if (g > max_blocks) g = max_blocks;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// Workspace carving: 256-byte aligned slices.
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Wave-level reductions / scans with cross-lane shuffles (wave64).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int t = __shfl_up(v, o, kWave);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ float wave_incl_scan_f(float v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    float t = __shfl_up(v, o, kWave);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Multiresolution grid resolution of level l: floor(base * growth^l),
+// computed on the host in double precision.
+inline int32_t level_resolution(double base, double growth, int l) {
+  return (int32_t)floor(base * pow(growth, (double)l));
+}
+
+}  // namespace ia355

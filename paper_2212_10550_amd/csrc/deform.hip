@@ -1,0 +1,429 @@
+// Articulation (Sec. 3.1, Eq. 5-7): posed point x' -> canonical root x* of
+// x' = sum_i w_i(x) B_i x, by multi-init Broyden root finding, and its
+// backward by the implicit function theorem.
+//
+// Forward design (gfx950):
+//  * blend kernel: because trilinear interpolation is linear in the vertex
+//    values, sum_i w_i(x) B_i = sum_c tri_c(x) A_c with A_v = sum_i W[v][i] B_i
+//    the per-pose blended transform of vertex v.  A is a 12-float-per-vertex
+//    grid (3 x float4 per corner) built once per pose, which halves the
+//    gathered bytes and removes the 24-bone blend from every residual.
+//  * solve kernel: one thread per posed sample runs the nb Broyden solves in
+//    FP32 registers; bone inverses are staged in LDS once per block; the
+//    blended grid is read through the vector L1/L2 with float4 gathers.
+#include "common.h"
+
+using namespace ia355;
+
+namespace {
+
+constexpr int kMaxBones = 64;
+
+struct Grid {
+  int D[3];       // Dx, Dy, Dz
+  float lo[3];    // box low corner
+  float scale[3]; // (D - 1) / (hi - lo)
+};
+
+struct Box {
+  float lo[3], hi[3];
+};
+
+__global__ void blend_kernel(const float *__restrict__ W, const float *__restrict__ B, int nb, int64_t nvert,
+                             float *__restrict__ A) {
+  __shared__ float sB[kMaxBones * 12];
+  for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) sB[i] = B[i];
+  __syncthreads();
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvert) return;
+  float acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0f;
+  const float *w = W + v * nb;
+  for (int b = 0; b < nb; ++b) {
+    const float wb = w[b];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] += wb * sB[12 * b + k];
+  }
+  float4 *out = reinterpret_cast<float4 *>(A + 12 * v);
+  out[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+  out[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+  out[2] = make_float4(acc[8], acc[9], acc[10], acc[11]);
+}
+
+// Cell lookup with align-corners vertices and clamping to the box: base
+// vertex, fractional position and d(p)/dx (zero along a clamped axis).
+struct Cell {
+  int i0[3];
+  float f[3];
+  float dp[3];
+};
+
+__device__ __forceinline__ Cell locate(const Grid &g, const float x[3]) {
+  Cell c;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float p = (x[a] - g.lo[a]) * g.scale[a];
+    float s = g.scale[a];
+    const float pmax = (float)(g.D[a] - 1);
+    if (!(p >= 0.0f)) { p = 0.0f; s = 0.0f; }  // also catches NaN
+    if (p > pmax) { p = pmax; s = 0.0f; }
+    int i = (int)floorf(p);
+    i = i > g.D[a] - 2 ? g.D[a] - 2 : i;
+    i = i < 0 ? 0 : i;
+    c.i0[a] = i;
+    c.f[a] = p - (float)i;
+    c.dp[a] = s;
+  }
+  return c;
+}
+
+__device__ __forceinline__ const float4 *corner_ptr(const float *A, const Grid &g, const Cell &c, int k) {
+  const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
+  const int64_t v = ((int64_t)(c.i0[2] + cz) * g.D[1] + (c.i0[1] + cy)) * g.D[0] + (c.i0[0] + cx);
+  return reinterpret_cast<const float4 *>(A + 12 * v);
+}
+
+// g = sum_c tri_c (A_c x_h) - x'.
+__device__ __forceinline__ void residual(const float *__restrict__ A, const Grid &gr, const float x[3],
+                                         const float xp[3], float g[3]) {
+  const Cell c = locate(gr, x);
+  g[0] = -xp[0];
+  g[1] = -xp[1];
+  g[2] = -xp[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float4 *p = corner_ptr(A, gr, c, k);
+    const float4 r0 = p[0], r1 = p[1], r2 = p[2];
+    const float wx = (k & 1) ? c.f[0] : 1.0f - c.f[0];
+    const float wy = (k & 2) ? c.f[1] : 1.0f - c.f[1];
+    const float wz = (k & 4) ? c.f[2] : 1.0f - c.f[2];
+    const float t = wx * wy * wz;
+    g[0] += t * (r0.x * x[0] + r0.y * x[1] + r0.z * x[2] + r0.w);
+    g[1] += t * (r1.x * x[0] + r1.y * x[1] + r1.z * x[2] + r1.w);
+    g[2] += t * (r2.x * x[0] + r2.y * x[1] + r2.z * x[2] + r2.w);
+  }
+}
+
+// Residual and Jacobian J = sum_c tri_c M_c + sum_c (A_c x_h) (grad tri_c)^T.
+__device__ __forceinline__ void residual_jac(const float *__restrict__ A, const Grid &gr, const float x[3],
+                                             const float xp[3], float g[3], float J[3][3]) {
+  const Cell c = locate(gr, x);
+  g[0] = -xp[0];
+  g[1] = -xp[1];
+  g[2] = -xp[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) J[i][j] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float4 *p = corner_ptr(A, gr, c, k);
+    const float4 r[3] = {p[0], p[1], p[2]};
+    const float wx = (k & 1) ? c.f[0] : 1.0f - c.f[0];
+    const float wy = (k & 2) ? c.f[1] : 1.0f - c.f[1];
+    const float wz = (k & 4) ? c.f[2] : 1.0f - c.f[2];
+    const float sx = (k & 1) ? c.dp[0] : -c.dp[0];
+    const float sy = (k & 2) ? c.dp[1] : -c.dp[1];
+    const float sz = (k & 4) ? c.dp[2] : -c.dp[2];
+    const float t = wx * wy * wz;
+    const float dt[3] = {sx * wy * wz, wx * sy * wz, wx * wy * sz};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const float y = r[i].x * x[0] + r[i].y * x[1] + r[i].z * x[2] + r[i].w;
+      g[i] += t * y;
+      J[i][0] += t * r[i].x + y * dt[0];
+      J[i][1] += t * r[i].y + y * dt[1];
+      J[i][2] += t * r[i].z + y * dt[2];
+    }
+  }
+}
+
+__device__ __forceinline__ float inv3(const float A[3][3], float Ai[3][3]) {
+  const float c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  const float c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+  const float c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  const float det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+  const float id = 1.0f / det;
+  Ai[0][0] = c00 * id;
+  Ai[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+  Ai[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+  Ai[1][0] = c01 * id;
+  Ai[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+  Ai[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+  Ai[2][0] = c02 * id;
+  Ai[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+  Ai[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+  return det;
+}
+
+__device__ __forceinline__ float norm3(const float v[3]) { return sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+constexpr int kSolveBlock = 256;
+
+// One posed sample per thread; all nb inits run in sequence.
+__global__ void __launch_bounds__(kSolveBlock) solve_kernel(
+    const float *__restrict__ xp_soa, int64_t S, int64_t ld, const float *__restrict__ B, int nb,
+    const float *__restrict__ A, Grid gr, Box hbox, int max_iter, float tol_stop, float tol_valid,
+    float *__restrict__ xc_soa, int16_t *__restrict__ bone_out, float *__restrict__ resid_out,
+    int16_t *__restrict__ steps_out) {
+  // per-bone inverse transform [M^-1 | -M^-1 t] and a singularity flag
+  __shared__ float sBinv[kMaxBones * 12];
+  __shared__ int sBok[kMaxBones];
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    float M[3][3], Mi[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M[i][j] = B[12 * b + 4 * i + j];
+    const float det = inv3(M, Mi);
+    sBok[b] = fabsf(det) >= 1e-12f;
+    for (int i = 0; i < 3; ++i) {
+      for (int j = 0; j < 3; ++j) sBinv[12 * b + 4 * i + j] = Mi[i][j];
+      sBinv[12 * b + 4 * i + 3] = -(Mi[i][0] * B[12 * b + 3] + Mi[i][1] * B[12 * b + 7] + Mi[i][2] * B[12 * b + 11]);
+    }
+  }
+  __syncthreads();
+  const int64_t n = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
+  if (n >= S) return;
+  const float xp[3] = {xp_soa[n], xp_soa[ld + n], xp_soa[2 * ld + n]};
+  float best_r = INFINITY, best_x[3] = {0.0f, 0.0f, 0.0f};
+  int best = -1, steps = 0;
+  for (int i = 0; i < nb; ++i) {
+    const float *Bi = sBinv + 12 * i;
+    float x[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = Bi[4 * a] * xp[0] + Bi[4 * a + 1] * xp[1] + Bi[4 * a + 2] * xp[2] + Bi[4 * a + 3];
+    float g[3], J[3][3], H[3][3];
+    residual_jac(A, gr, x, xp, g, J);
+    const float detJ = inv3(J, H);
+    bool ok = sBok[i] && fabsf(detJ) >= 1e-12f;
+    int k = 0;
+    if (ok) {
+      for (; k < max_iter; ++k) {
+        if (norm3(g) < tol_stop) break;
+        float dx[3], xn[3], gn[3], dg[3], Hdg[3], dxH[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dx[a] = -(H[a][0] * g[0] + H[a][1] * g[1] + H[a][2] * g[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xn[a] = x[a] + dx[a];
+        residual(A, gr, xn, xp, gn);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dg[a] = gn[a] - g[a];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Hdg[a] = H[a][0] * dg[0] + H[a][1] * dg[1] + H[a][2] * dg[2];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) dxH[b] = dx[0] * H[0][b] + dx[1] * H[1][b] + dx[2] * H[2][b];
+        const float den = dx[0] * Hdg[0] + dx[1] * Hdg[1] + dx[2] * Hdg[2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          x[a] = xn[a];
+          g[a] = gn[a];
+        }
+        if (fabsf(den) < 1e-30f) {
+          ok = false;
+          ++k;
+          break;
+        }
+        const float iden = 1.0f / den;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) H[a][b] += (dx[a] - Hdg[a]) * dxH[b] * iden;
+      }
+    }
+    steps += k;
+    const float r = norm3(g);
+    if (i == 0) {
+      best_x[0] = x[0];
+      best_x[1] = x[1];
+      best_x[2] = x[2];
+    }
+    const bool inside = x[0] >= hbox.lo[0] && x[0] <= hbox.hi[0] && x[1] >= hbox.lo[1] && x[1] <= hbox.hi[1] &&
+                        x[2] >= hbox.lo[2] && x[2] <= hbox.hi[2];
+    if (ok && r < tol_valid && inside && r < best_r) {
+      best_r = r;
+      best = i;
+      best_x[0] = x[0];
+      best_x[1] = x[1];
+      best_x[2] = x[2];
+    }
+  }
+  xc_soa[n] = best_x[0];
+  xc_soa[ld + n] = best_x[1];
+  xc_soa[2 * ld + n] = best_x[2];
+  bone_out[n] = (int16_t)best;
+  if (resid_out) resid_out[n] = best_r;
+  if (steps_out) steps_out[n] = (int16_t)steps;
+}
+
+// ------------------------------------------------------------------------
+// Backward (implicit function theorem).  One sample per thread:
+//   w_b, grad w_b from the skinning grid; J = sum_b w_b M_b + sum_b y_b grad w_b^T
+//   with y_b = B_b x*_h; v = J^{-T} u;
+//   grad_xp = v; grad_B_b -= w_b v x_h^T (wave-reduced, then one atomic per
+//   wave and entry); grad_W[c][b] -= tri_c v.y_b (atomics).
+// ------------------------------------------------------------------------
+constexpr int kBwdBlock = 256;
+
+__global__ void __launch_bounds__(kBwdBlock) ift_kernel(
+    const float *__restrict__ gxc, const float *__restrict__ xc_soa, const int16_t *__restrict__ bone, int64_t S,
+    int64_t ld, const float *__restrict__ B, int nb, const float *__restrict__ W, Grid gr,
+    float *__restrict__ gxp, float *__restrict__ gB, float *__restrict__ gW) {
+  __shared__ float sB[kMaxBones * 12];
+  __shared__ float sGB[kMaxBones * 12];
+  for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) {
+    sB[i] = B[i];
+    sGB[i] = 0.0f;
+  }
+  __syncthreads();
+  const int64_t n = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x;
+  const bool act = n < S && bone[n] >= 0;
+  float v[3] = {0.0f, 0.0f, 0.0f}, x[3] = {0.0f, 0.0f, 0.0f};
+  Cell c;
+  if (act) {
+    x[0] = xc_soa[n];
+    x[1] = xc_soa[ld + n];
+    x[2] = xc_soa[2 * ld + n];
+    c = locate(gr, x);
+    float J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int k = 0; k < 8; ++k) {
+      const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
+      const float wx = cx ? c.f[0] : 1.0f - c.f[0];
+      const float wy = cy ? c.f[1] : 1.0f - c.f[1];
+      const float wz = cz ? c.f[2] : 1.0f - c.f[2];
+      const float t = wx * wy * wz;
+      const float dt[3] = {(cx ? c.dp[0] : -c.dp[0]) * wy * wz, wx * (cy ? c.dp[1] : -c.dp[1]) * wz,
+                           wx * wy * (cz ? c.dp[2] : -c.dp[2])};
+      const int64_t vtx = ((int64_t)(c.i0[2] + cz) * gr.D[1] + (c.i0[1] + cy)) * gr.D[0] + (c.i0[0] + cx);
+      const float *Wv = W + vtx * nb;
+      for (int b = 0; b < nb; ++b) {
+        const float wv = Wv[b];
+        const float *Bb = sB + 12 * b;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const float y = Bb[4 * i] * x[0] + Bb[4 * i + 1] * x[1] + Bb[4 * i + 2] * x[2] + Bb[4 * i + 3];
+          J[i][0] += wv * (t * Bb[4 * i] + y * dt[0]);
+          J[i][1] += wv * (t * Bb[4 * i + 1] + y * dt[1]);
+          J[i][2] += wv * (t * Bb[4 * i + 2] + y * dt[2]);
+        }
+      }
+    }
+    // v = J^{-T} u  (J^{-T} = (J^{-1})^T)
+    float Ji[3][3];
+    inv3(J, Ji);
+    const float u[3] = {gxc[n], gxc[ld + n], gxc[2 * ld + n]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = Ji[0][a] * u[0] + Ji[1][a] * u[1] + Ji[2][a] * u[2];
+  }
+  if (n < S && gxp) {
+    gxp[n] = v[0];
+    gxp[ld + n] = v[1];
+    gxp[2 * ld + n] = v[2];
+  }
+  if (gW && act) {
+    for (int k = 0; k < 8; ++k) {
+      const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
+      const float t = (cx ? c.f[0] : 1.0f - c.f[0]) * (cy ? c.f[1] : 1.0f - c.f[1]) * (cz ? c.f[2] : 1.0f - c.f[2]);
+      const int64_t vtx = ((int64_t)(c.i0[2] + cz) * gr.D[1] + (c.i0[1] + cy)) * gr.D[0] + (c.i0[0] + cx);
+      float *g = gW + vtx * nb;
+      for (int b = 0; b < nb; ++b) {
+        const float *Bb = sB + 12 * b;
+        float vy = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          vy += v[i] * (Bb[4 * i] * x[0] + Bb[4 * i + 1] * x[1] + Bb[4 * i + 2] * x[2] + Bb[4 * i + 3]);
+        atomicAdd(g + b, -t * vy);
+      }
+    }
+  }
+  if (gB) {
+    // skinning weights at x* for the B gradient (zero for inactive lanes)
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int b = 0; b < nb; ++b) {
+      float wb = 0.0f;
+      if (act) {
+        for (int k = 0; k < 8; ++k) {
+          const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
+          const float t =
+              (cx ? c.f[0] : 1.0f - c.f[0]) * (cy ? c.f[1] : 1.0f - c.f[1]) * (cz ? c.f[2] : 1.0f - c.f[2]);
+          const int64_t vtx = ((int64_t)(c.i0[2] + cz) * gr.D[1] + (c.i0[1] + cy)) * gr.D[0] + (c.i0[0] + cx);
+          wb += t * W[vtx * nb + b];
+        }
+      }
+      const float xh[4] = {x[0], x[1], x[2], 1.0f};
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float s = wave_sum(-wb * v[i] * xh[j]);
+          if (lane == 0) atomicAdd(&sGB[12 * b + 4 * i + j], s);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) atomicAdd(gB + i, sGB[i]);
+  }
+}
+
+Grid make_grid(int Dx, int Dy, int Dz, const float *aabb) {
+  Grid g;
+  g.D[0] = Dx;
+  g.D[1] = Dy;
+  g.D[2] = Dz;
+  for (int a = 0; a < 3; ++a) {
+    g.lo[a] = aabb[a];
+    g.scale[a] = (float)(g.D[a] - 1) / (aabb[3 + a] - aabb[a]);
+  }
+  return g;
+}
+
+bool grid_ok(int Dx, int Dy, int Dz, const float *aabb) {
+  if (Dx < 2 || Dy < 2 || Dz < 2 || !aabb) return false;
+  for (int a = 0; a < 3; ++a)
+    if (!(aabb[3 + a] > aabb[a])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" size_t ia355_deform_workspace_size(int32_t Dx, int32_t Dy, int32_t Dz) {
+  if (Dx <= 0 || Dy <= 0 || Dz <= 0) return 0;
+  return align256(sizeof(float) * 12 * (size_t)Dx * Dy * Dz);
+}
+
+extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, int64_t ld, const float *B, int32_t nb,
+                                      const float *W, int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
+                                      const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
+                                      float *xc, int16_t *bone, float *resid, int16_t *steps, void *ws,
+                                      size_t ws_bytes, ia355_stream_t stream) {
+  if (S < 0 || ld < S || nb <= 0 || nb > kMaxBones || max_iter < 0 || max_iter > 1000) return IA355_ERR_INVALID_ARG;
+  if (!B || !W || !grid_ok(Dx, Dy, Dz, skin_aabb) || !hash_aabb) return IA355_ERR_INVALID_ARG;
+  if (S > 0 && (!xp || !xc || !bone)) return IA355_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < ia355_deform_workspace_size(Dx, Dy, Dz)) return IA355_ERR_WORKSPACE;
+  hipStream_t s = as_stream(stream);
+  const int64_t nvert = (int64_t)Dx * Dy * Dz;
+  float *A = (float *)ws;
+  blend_kernel<<<(unsigned)ceil_div(nvert, 256), 256, 0, s>>>(W, B, nb, nvert, A);
+  if (S == 0) return launch_status();
+  const Grid g = make_grid(Dx, Dy, Dz, skin_aabb);
+  Box hb;
+  for (int a = 0; a < 3; ++a) {
+    hb.lo[a] = hash_aabb[a];
+    hb.hi[a] = hash_aabb[3 + a];
+  }
+  solve_kernel<<<(unsigned)ceil_div(S, kSolveBlock), kSolveBlock, 0, s>>>(xp, S, ld, B, nb, A, g, hb, max_iter,
+                                                                         tol_stop, tol_valid, xc, bone, resid, steps);
+  return launch_status();
+}
+
+extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int16_t *bone, int64_t S,
+                                          int64_t ld, const float *B, int32_t nb, const float *W, int32_t Dx,
+                                          int32_t Dy, int32_t Dz, const float *skin_aabb, float *grad_xp,
+                                          float *grad_B, float *grad_W, ia355_stream_t stream) {
+  if (S < 0 || ld < S || nb <= 0 || nb > kMaxBones) return IA355_ERR_INVALID_ARG;
+  if (!B || !W || !grid_ok(Dx, Dy, Dz, skin_aabb)) return IA355_ERR_INVALID_ARG;
+  if (S > 0 && (!grad_xc || !xc || !bone)) return IA355_ERR_INVALID_ARG;
+  if (S == 0) return IA355_OK;
+  const Grid g = make_grid(Dx, Dy, Dz, skin_aabb);
+  ift_kernel<<<(unsigned)ceil_div(S, kBwdBlock), kBwdBlock, 0, as_stream(stream)>>>(grad_xc, xc, bone, S, ld, B, nb,
+                                                                                    W, g, grad_xp, grad_B, grad_W);
+  return launch_status();
+}

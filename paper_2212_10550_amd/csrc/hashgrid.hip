@@ -1,0 +1,268 @@
+// Multiresolution hash encoding (Sec. 3.1, Instant-NGP) forward and backward.
+//
+// Forward design (gfx950, 8 XCDs with a private 4 MB L2 each):
+//  * one thread per (sample, level); a block covers 256 consecutive samples
+//    of ONE level, so its gathers stay inside one level's table;
+//  * workgroups are dispatched round-robin over the 8 XCDs, so block b runs
+//    on XCD b % 8.  Levels are assigned to XCDs by that residue (XCD k gets
+//    levels k, k+8, ...), so each XCD's L2 caches only its own levels'
+//    tables (2 x 2 MiB at T = 2^19 in FP16) instead of all sixteen;
+//  * the position scaling u = x N_l is split into a rounded product and its
+//    exact FMA remainder, so the cell and fraction are accurate to FP32
+//    relative precision even at N_l ~ 2000;
+//  * features are written level-major [L][S][F]: each block writes one
+//    contiguous run (coalesced 8-byte / 4-byte stores per lane).
+// Backward: one wave covers 4 samples x 16 levels (lane = level + 16 *
+// sample); table gradients are FP32 atomic adds, the position gradient is
+// reduced across the 16 level lanes with shuffles (deterministic).
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+
+using namespace ia355;
+
+namespace {
+
+constexpr int kMaxLevels = 32;
+constexpr int kXcd = 8;
+
+struct Levels {
+  int res[kMaxLevels];
+  int dense[kMaxLevels];
+};
+
+struct Box {
+  float lo[3], inv[3];
+};
+
+struct Corners {
+  uint32_t idx[8];
+  float w[8];
+  float dw[8][3];
+};
+
+__device__ __forceinline__ void level_cell(const float x[3], const Box &box, int N, bool dense, uint32_t Tmask,
+                                           Corners &c, bool want_grad) {
+  // no contraction: (uh - i) must stay a separately rounded difference, or
+  // the compiler folds the product back in and the remainder counts twice
+#pragma clang fp contract(off)
+  int v0[3];
+  float f[3], sc[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float xn = (x[a] - box.lo[a]) * box.inv[a];
+    sc[a] = (float)N * box.inv[a];
+    if (!(xn >= 0.0f)) { xn = 0.0f; sc[a] = 0.0f; }  // also catches NaN
+    if (xn > 1.0f) { xn = 1.0f; sc[a] = 0.0f; }
+    const float uh = xn * (float)N;
+    const float ul = fmaf(xn, (float)N, -uh);  // exact remainder of the product
+    int i = (int)floorf(uh);
+    float fr = (uh - (float)i) + ul;
+    if (fr < 0.0f && i > 0) { i -= 1; fr += 1.0f; }
+    if (i > N - 1) { fr += (float)(i - (N - 1)); i = N - 1; }
+    if (i < 0) { i = 0; }
+    v0[a] = i;
+    f[a] = fr;
+  }
+  const uint32_t side = (uint32_t)N + 1u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t vx = (uint32_t)(v0[0] + (k & 1));
+    const uint32_t vy = (uint32_t)(v0[1] + ((k >> 1) & 1));
+    const uint32_t vz = (uint32_t)(v0[2] + ((k >> 2) & 1));
+    c.idx[k] = dense ? vx + side * (vy + side * vz) : ((vx * 1u) ^ (vy * 2654435761u) ^ (vz * 805459861u)) & Tmask;
+    const float wx = (k & 1) ? f[0] : 1.0f - f[0];
+    const float wy = (k & 2) ? f[1] : 1.0f - f[1];
+    const float wz = (k & 4) ? f[2] : 1.0f - f[2];
+    c.w[k] = wx * wy * wz;
+    if (want_grad) {
+      c.dw[k][0] = ((k & 1) ? sc[0] : -sc[0]) * wy * wz;
+      c.dw[k][1] = wx * ((k & 2) ? sc[1] : -sc[1]) * wz;
+      c.dw[k][2] = wx * wy * ((k & 4) ? sc[2] : -sc[2]);
+    }
+  }
+}
+
+__device__ __forceinline__ float2 load_feat2(const float *t, uint32_t i) {
+  return reinterpret_cast<const float2 *>(t)[i];
+}
+__device__ __forceinline__ float2 load_feat2(const __half *t, uint32_t i) {
+  return __half22float2(reinterpret_cast<const __half2 *>(t)[i]);
+}
+
+__device__ __forceinline__ void store_feat2(float *f, int64_t i, float a, float b) {
+  reinterpret_cast<float2 *>(f)[i] = make_float2(a, b);
+}
+__device__ __forceinline__ void store_feat2(__hip_bfloat16 *f, int64_t i, float a, float b) {
+  __hip_bfloat162 v;
+  v.x = __float2bfloat16(a);
+  v.y = __float2bfloat16(b);
+  reinterpret_cast<__hip_bfloat162 *>(f)[i] = v;
+}
+
+constexpr int kFwdBlock = 256;
+
+template <typename TT, typename FT>
+__global__ void __launch_bounds__(kFwdBlock) encode_kernel(const float *__restrict__ xc, const int16_t *__restrict__ bone,
+                                                           int64_t S, int64_t ld, const TT *__restrict__ table, int L,
+                                                           int log2T, Levels lv, Box box, FT *__restrict__ feat,
+                                                           int per_xcd) {
+  const int xcd = blockIdx.x % kXcd;
+  const int slot = blockIdx.x / kXcd;
+  const int level = xcd + kXcd * (slot % per_xcd);
+  const int64_t chunk = slot / per_xcd;
+  if (level >= L) return;
+  const int64_t n = chunk * kFwdBlock + threadIdx.x;
+  if (n >= S) return;
+  float a = 0.0f, b = 0.0f;
+  if (!bone || bone[n] >= 0) {
+    const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
+    Corners c;
+    const uint32_t T = 1u << log2T;
+    level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
+    const TT *tl = table + (int64_t)level * T * 2;
+    float2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = load_feat2(tl, c.idx[k]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      a += c.w[k] * v[k].x;
+      b += c.w[k] * v[k].y;
+    }
+  }
+  store_feat2(feat, (int64_t)level * S + n, a, b);
+}
+
+constexpr int kBwdBlock = 256;
+
+// lane = level (low 4 bits) + 16 * sample-in-wave; requires L <= 16.
+template <typename TT>
+__global__ void __launch_bounds__(kBwdBlock) encode_bwd_kernel(
+    const float *__restrict__ gfeat, const float *__restrict__ xc, const int16_t *__restrict__ bone, int64_t S,
+    int64_t ld, const TT *__restrict__ table, int L, int log2T, Levels lv, Box box, float *__restrict__ gtable,
+    float *__restrict__ gxc) {
+  const int level = threadIdx.x & 15;
+  const int64_t n = ((int64_t)blockIdx.x * kBwdBlock + threadIdx.x) >> 4;
+  float gx[3] = {0.0f, 0.0f, 0.0f};
+  const bool act = n < S && level < L && (!bone || bone[n] >= 0);
+  if (act) {
+    const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
+    const float2 g = reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * S + n];
+    Corners c;
+    const uint32_t T = 1u << log2T;
+    level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, gxc != nullptr);
+    if (gtable) {
+      float *gl = gtable + (int64_t)level * T * 2;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        atomicAdd(gl + 2 * c.idx[k], c.w[k] * g.x);
+        atomicAdd(gl + 2 * c.idx[k] + 1, c.w[k] * g.y);
+      }
+    }
+    if (gxc) {
+      const TT *tl = table + (int64_t)level * T * 2;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float2 v = load_feat2(tl, c.idx[k]);
+        const float d = v.x * g.x + v.y * g.y;
+        gx[0] += c.dw[k][0] * d;
+        gx[1] += c.dw[k][1] * d;
+        gx[2] += c.dw[k][2] * d;
+      }
+    }
+  }
+  if (gxc) {
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      gx[0] += __shfl_xor(gx[0], o, 16);
+      gx[1] += __shfl_xor(gx[1], o, 16);
+      gx[2] += __shfl_xor(gx[2], o, 16);
+    }
+    if (level == 0 && n < S) {
+      gxc[n] = gx[0];
+      gxc[ld + n] = gx[1];
+      gxc[2 * ld + n] = gx[2];
+    }
+  }
+}
+
+int32_t make_levels(int L, int log2T, double base, double growth, Levels *lv) {
+  const uint64_t T = 1ull << log2T;
+  for (int l = 0; l < L; ++l) {
+    const int N = level_resolution(base, growth, l);
+    if (N < 1 || N > (1 << 22)) return IA355_ERR_INVALID_ARG;
+    lv->res[l] = N;
+    const uint64_t side = (uint64_t)N + 1;
+    lv->dense[l] = side * side * side <= T;
+  }
+  return IA355_OK;
+}
+
+int32_t make_box(const float *aabb, Box *b) {
+  if (!aabb) return IA355_ERR_INVALID_ARG;
+  for (int a = 0; a < 3; ++a) {
+    if (!(aabb[3 + a] > aabb[a])) return IA355_ERR_INVALID_ARG;
+    b->lo[a] = aabb[a];
+    b->inv[a] = 1.0f / (aabb[3 + a] - aabb[a]);
+  }
+  return IA355_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, int64_t ld, const void *table,
+                                         int32_t table_dtype, int32_t L, int32_t F, int32_t log2T, double base_res,
+                                         double growth, const float *aabb, void *feat, int32_t feat_dtype,
+                                         ia355_stream_t stream) {
+  if (S < 0 || ld < S || L <= 0 || L > kMaxLevels || F != 2 || log2T < 1 || log2T > 30) return IA355_ERR_INVALID_ARG;
+  if (!table || (S > 0 && (!xc || !feat))) return IA355_ERR_INVALID_ARG;
+  if (table_dtype != IA355_F32 && table_dtype != IA355_F16) return IA355_ERR_INVALID_ARG;
+  if (feat_dtype != IA355_F32 && feat_dtype != IA355_BF16) return IA355_ERR_INVALID_ARG;
+  Levels lv;
+  Box box;
+  if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
+  if (S == 0) return IA355_OK;
+  const int per_xcd = (L + kXcd - 1) / kXcd;
+  const int64_t chunks = ceil_div(S, kFwdBlock);
+  const int64_t blocks = chunks * per_xcd * kXcd;
+  if (blocks > 0x7fffffffLL) return IA355_ERR_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  const unsigned g = (unsigned)blocks;
+  if (table_dtype == IA355_F32 && feat_dtype == IA355_F32)
+    encode_kernel<float, float><<<g, kFwdBlock, 0, s>>>(xc, bone, S, ld, (const float *)table, L, log2T, lv, box,
+                                                        (float *)feat, per_xcd);
+  else if (table_dtype == IA355_F32)
+    encode_kernel<float, __hip_bfloat16><<<g, kFwdBlock, 0, s>>>(xc, bone, S, ld, (const float *)table, L, log2T, lv,
+                                                                 box, (__hip_bfloat16 *)feat, per_xcd);
+  else if (feat_dtype == IA355_F32)
+    encode_kernel<__half, float><<<g, kFwdBlock, 0, s>>>(xc, bone, S, ld, (const __half *)table, L, log2T, lv, box,
+                                                         (float *)feat, per_xcd);
+  else
+    encode_kernel<__half, __hip_bfloat16><<<g, kFwdBlock, 0, s>>>(xc, bone, S, ld, (const __half *)table, L, log2T,
+                                                                  lv, box, (__hip_bfloat16 *)feat, per_xcd);
+  return launch_status();
+}
+
+extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone, int64_t S,
+                                             int64_t ld, const void *table, int32_t table_dtype, int32_t L, int32_t F,
+                                             int32_t log2T, double base_res, double growth, const float *aabb,
+                                             float *grad_table, float *grad_xc, ia355_stream_t stream) {
+  if (S < 0 || ld < S || L <= 0 || L > 16 || F != 2 || log2T < 1 || log2T > 30) return IA355_ERR_INVALID_ARG;
+  if (S > 0 && (!grad_feat || !xc)) return IA355_ERR_INVALID_ARG;
+  if (grad_xc && !table) return IA355_ERR_INVALID_ARG;
+  if (table_dtype != IA355_F32 && table_dtype != IA355_F16) return IA355_ERR_INVALID_ARG;
+  Levels lv;
+  Box box;
+  if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
+  if (S == 0 || (!grad_table && !grad_xc)) return IA355_OK;
+  const int64_t blocks = ceil_div(S * 16, kBwdBlock);
+  hipStream_t s = as_stream(stream);
+  if (table_dtype == IA355_F32)
+    encode_bwd_kernel<float><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, ld, (const float *)table,
+                                                                    L, log2T, lv, box, grad_table, grad_xc);
+  else
+    encode_bwd_kernel<__half><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, ld, (const __half *)table,
+                                                                     L, log2T, lv, box, grad_table, grad_xc);
+  return launch_status();
+}

@@ -1,0 +1,560 @@
+// Decoder MLP 32 -> 64 -> 64 -> 4 (Sec. 3.1, Eq. 1-2: the shallow MLP that
+// turns concatenated hash features into density and colour) on MFMA.
+//
+// Layer products are out[m][n] = sum_k W[m][k] in[k][n] with m = neuron,
+// n = sample (16 per tile), k = input.  One wave owns a 16-sample tile.
+// MFMA operand layouts (lane l, r = l % 16, g = l / 16):
+//   v_mfma_f32_16x16x4_f32   : A[r][g], B[g][r] (one value each), D[4g+i][r]
+//   v_mfma_f32_16x16x32_bf16 : A[r][8g+j], B[8g+j][r] (8 bf16 each), D[4g+i][r]
+// A lane therefore ends a layer holding neurons {16t + 4g + i} of sample r.
+// The next layer consumes exactly those registers as its B operand by
+// ordering its K dimension the same way (k-step (t, i), slot g = neuron
+// 16t + 4g + i); its weight fragments are gathered in that order.  So the
+// activations never leave registers between layers.  Features arrive
+// level-major [L][S][2]: lane group g reads levels 4g..4g+3 of its sample,
+// i.e. features 8g..8g+7, which fixes the K order of the first layer.
+#include <hip/hip_bf16.h>
+
+#include "common.h"
+
+using namespace ia355;
+
+namespace {
+
+constexpr int NIN = 32, NH = 64, NOUT = 4;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NIN, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
+              OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NOUT * NH, NPARAM = OFF_B3 + NOUT;
+static_assert(NPARAM == 6532, "parameter count");
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float relu(float z) { return z < 0.0f ? 0.0f : z; }
+
+__device__ __forceinline__ void head(const float o[4], float *sig, float c[3]) {
+  *sig = expf(fminf(o[0], 80.0f));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c[k] = 1.0f / (1.0f + expf(-o[1 + k]));
+}
+
+// --------------------------------------------------------------- FP32 fwd
+// Loads the 8 features of lane group g for sample s (levels 4g..4g+3).
+__device__ __forceinline__ void load_x(const float *feat, int64_t S, int64_t s, int g, bool ok, float X[8]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float2 v = make_float2(0.0f, 0.0f);
+    if (ok) v = reinterpret_cast<const float2 *>(feat)[(int64_t)(4 * g + j) * S + s];
+    X[2 * j] = v.x;
+    X[2 * j + 1] = v.y;
+  }
+}
+
+struct Frag32 {
+  float w1[4][8];   // [mt][c]  = W1[16mt + r][8g + c]
+  float w2[4][16];  // [mt][4t+i] = W2[16mt + r][16t + 4g + i]
+  float w3[16];     // [4t+i]   = W3[r][16t + 4g + i] (r < 4)
+  float b1[4][4], b2[4][4], b3[4];  // [mt][i] = b[16mt + 4g + i]
+};
+
+__device__ __forceinline__ void load_frag32(const float *P, int r, int g, Frag32 &f) {
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) f.w1[mt][c] = P[OFF_W1 + (16 * mt + r) * NIN + 8 * g + c];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) f.w2[mt][4 * t + i] = P[OFF_W2 + (16 * mt + r) * NH + 16 * t + 4 * g + i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      f.b1[mt][i] = P[OFF_B1 + 16 * mt + 4 * g + i];
+      f.b2[mt][i] = P[OFF_B2 + 16 * mt + 4 * g + i];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f.w3[4 * t + i] = r < NOUT ? P[OFF_W3 + r * NH + 16 * t + 4 * g + i] : 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f.b3[i] = (4 * g + i) < NOUT ? P[OFF_B3 + 4 * g + i] : 0.0f;
+}
+
+// Forward of one tile; z1/z2 are pre-activations, o the 4 outputs (valid in
+// lanes g == 0).
+__device__ __forceinline__ void fwd32(const Frag32 &f, const float X[8], f32x4 z1[4], f32x4 z2[4], f32x4 &o) {
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {f.b1[mt][0], f.b1[mt][1], f.b1[mt][2], f.b1[mt][3]};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc = mfma4(f.w1[mt][c], X[c], acc);
+    z1[mt] = acc;
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {f.b2[mt][0], f.b2[mt][1], f.b2[mt][2], f.b2[mt][3]};
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc = mfma4(f.w2[mt][4 * t + i], relu(z1[t][i]), acc);
+    z2[mt] = acc;
+  }
+  f32x4 acc = {f.b3[0], f.b3[1], f.b3[2], f.b3[3]};
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc = mfma4(f.w3[4 * t + i], relu(z2[t][i]), acc);
+  o = acc;
+}
+
+constexpr int kFwdBlock = 256;
+
+__global__ void __launch_bounds__(kFwdBlock) mlp_fwd_f32(const float *__restrict__ feat,
+                                                         const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                         const float *__restrict__ P, float *__restrict__ sigma,
+                                                         float *__restrict__ rgb) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  Frag32 f;
+  load_frag32(P, r, g, f);
+  const int64_t ntile = ceil_div(S, 16);
+  const int64_t wstride = (int64_t)gridDim.x * (kFwdBlock / 64);
+  for (int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6); tile < ntile; tile += wstride) {
+    const int64_t s = tile * 16 + r;
+    const bool ok = s < S;
+    float X[8];
+    load_x(feat, S, s, g, ok, X);
+    f32x4 z1[4], z2[4], o;
+    fwd32(f, X, z1, z2, o);
+    if (g == 0 && ok) {
+      float sg = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
+      if (!bone || bone[s] >= 0) {
+        const float ov[4] = {o[0], o[1], o[2], o[3]};
+        head(ov, &sg, c);
+      }
+      sigma[s] = sg;
+      rgb[s] = c[0];
+      rgb[ld + s] = c[1];
+      rgb[2 * ld + s] = c[2];
+    }
+  }
+}
+
+// --------------------------------------------------------------- BF16 fwd
+__device__ __forceinline__ bf16x8 load_x_bf16(const __hip_bfloat16 *feat, int64_t S, int64_t s, int g, bool ok) {
+  bf16x8 x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t v = 0;
+    if (ok) v = reinterpret_cast<const uint32_t *>(feat)[(int64_t)(4 * g + j) * S + s];
+    x[2 * j] = __builtin_bit_cast(__bf16, (uint16_t)(v & 0xffffu));
+    x[2 * j + 1] = __builtin_bit_cast(__bf16, (uint16_t)(v >> 16));
+  }
+  return x;
+}
+
+struct FragBf {
+  bf16x8 w1[4];     // [mt]: W1[16mt + r][8g + j]
+  bf16x8 w2[4][2];  // [mt][c]: W2[16mt + r][16(2c + j/4) + 4g + j%4]
+  bf16x8 w3[2];     // [c]: W3[r][...] (r < 4)
+  float b1[4][4], b2[4][4], b3[4];
+};
+
+__device__ __forceinline__ void load_frag_bf(const float *P, int r, int g, FragBf &f) {
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) f.w1[mt][j] = (__bf16)P[OFF_W1 + (16 * mt + r) * NIN + 8 * g + j];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        f.w2[mt][c][j] = (__bf16)P[OFF_W2 + (16 * mt + r) * NH + 16 * (2 * c + j / 4) + 4 * g + (j % 4)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      f.b1[mt][i] = P[OFF_B1 + 16 * mt + 4 * g + i];
+      f.b2[mt][i] = P[OFF_B2 + 16 * mt + 4 * g + i];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      f.w3[c][j] = (__bf16)(r < NOUT ? P[OFF_W3 + r * NH + 16 * (2 * c + j / 4) + 4 * g + (j % 4)] : 0.0f);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f.b3[i] = (4 * g + i) < NOUT ? P[OFF_B3 + 4 * g + i] : 0.0f;
+}
+
+// Pack the relu'd accumulators of tiles t = 2c, 2c+1 into one B operand.
+__device__ __forceinline__ bf16x8 pack_act(const f32x4 z[4], int c) {
+  bf16x8 b;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) b[j] = (__bf16)relu(z[2 * c + j / 4][j % 4]);
+  return b;
+}
+
+__device__ __forceinline__ void fwd_bf(const FragBf &f, const bf16x8 &X, f32x4 z1[4], f32x4 z2[4], f32x4 &o) {
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {f.b1[mt][0], f.b1[mt][1], f.b1[mt][2], f.b1[mt][3]};
+    z1[mt] = mfma32(f.w1[mt], X, acc);
+  }
+  const bf16x8 h1a = pack_act(z1, 0), h1b = pack_act(z1, 1);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {f.b2[mt][0], f.b2[mt][1], f.b2[mt][2], f.b2[mt][3]};
+    acc = mfma32(f.w2[mt][0], h1a, acc);
+    z2[mt] = mfma32(f.w2[mt][1], h1b, acc);
+  }
+  const bf16x8 h2a = pack_act(z2, 0), h2b = pack_act(z2, 1);
+  f32x4 acc = {f.b3[0], f.b3[1], f.b3[2], f.b3[3]};
+  acc = mfma32(f.w3[0], h2a, acc);
+  o = mfma32(f.w3[1], h2b, acc);
+}
+
+__global__ void __launch_bounds__(kFwdBlock) mlp_fwd_bf16(const __hip_bfloat16 *__restrict__ feat,
+                                                          const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                          const float *__restrict__ P, float *__restrict__ sigma,
+                                                          float *__restrict__ rgb) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  FragBf f;
+  load_frag_bf(P, r, g, f);
+  const int64_t ntile = ceil_div(S, 16);
+  const int64_t wstride = (int64_t)gridDim.x * (kFwdBlock / 64);
+  for (int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6); tile < ntile; tile += wstride) {
+    const int64_t s = tile * 16 + r;
+    const bool ok = s < S;
+    const bf16x8 X = load_x_bf16(feat, S, s, g, ok);
+    f32x4 z1[4], z2[4], o;
+    fwd_bf(f, X, z1, z2, o);
+    if (g == 0 && ok) {
+      float sg = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
+      if (!bone || bone[s] >= 0) {
+        const float ov[4] = {o[0], o[1], o[2], o[3]};
+        head(ov, &sg, c);
+      }
+      sigma[s] = sg;
+      rgb[s] = c[0];
+      rgb[ld + s] = c[1];
+      rgb[2 * ld + s] = c[2];
+    }
+  }
+}
+
+// --------------------------------------------------------------- FP32 bwd
+// Per 16-sample tile (one wave): recompute the forward, then
+//   d3 = dL/do (exp / sigmoid heads), gh2 = W3^T d3, d2 = gh2 * [z2 >= 0],
+//   gh1 = W2^T d2, d1 = gh1 * [z1 >= 0], gfeat = W1^T d1,
+//   dW3 += d3 h2^T, dW2 += d2 h1^T, dW1 += d1 x^T, db += sum d.
+// The transposed products chain in registers like the forward; the weight
+// gradients (K = samples) read tiles transposed through a per-wave LDS
+// scratch.  Block partials are reduced in a fixed order.
+constexpr int kBwdWaves = 2;
+constexpr int kBwdBlock = 64 * kBwdWaves;
+constexpr int LDP = 17;  // padded sample stride of the scratch tiles
+constexpr int SCR_X = 0, SCR_H1 = SCR_X + 32 * LDP, SCR_H2 = SCR_H1 + 64 * LDP, SCR_D = SCR_H2 + 64 * LDP,
+              SCR_D3 = SCR_D + 64 * LDP, SCR_SIZE = SCR_D3 + 4 * LDP;
+// transposed-weight fragments in LDS, stored lane-contiguous: [mfma][lane]
+constexpr int FT3 = 0;                 // 4 mfma   : W3[g][16mt + r]
+constexpr int FT2 = FT3 + 4 * 64;      // 64 mfma  : W2[16t + 4g + i][16mt + r]   (mt, 4t+i)
+constexpr int FT1 = FT2 + 64 * 64;     // 32 mfma  : W1[16t + 4g + i][16mt + r]   (mt in 0..1, 4t+i)
+constexpr int FT_SIZE = FT1 + 32 * 64;
+constexpr int LDS_FLOATS = FT_SIZE + kBwdWaves * SCR_SIZE;
+static_assert(kBwdWaves * SCR_SIZE >= NPARAM, "block partial reuses the scratch region");
+static_assert(LDS_FLOATS * 4 <= 65536, "one workgroup's LDS");
+
+__global__ void __launch_bounds__(kBwdBlock) mlp_bwd_f32(const float *__restrict__ gsig, const float *__restrict__ grgb,
+                                                         const float *__restrict__ feat,
+                                                         const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                         const float *__restrict__ P, float *__restrict__ gfeat,
+                                                         float *__restrict__ partial) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4, wid = threadIdx.x >> 6;
+  float *ft = lds;
+  float *scr = lds + FT_SIZE + wid * SCR_SIZE;
+  // stage transposed fragments
+  for (int e = threadIdx.x; e < FT_SIZE; e += kBwdBlock) {
+    const int L = e & 63, rr = L & 15, gg = L >> 4;
+    float v;
+    if (e < FT2) {
+      const int mt = e >> 6;
+      v = P[OFF_W3 + gg * NH + 16 * mt + rr];
+    } else if (e < FT1) {
+      const int q = (e - FT2) >> 6, mt = q >> 4, ti = q & 15, t = ti >> 2, i = ti & 3;
+      v = P[OFF_W2 + (16 * t + 4 * gg + i) * NH + 16 * mt + rr];
+    } else {
+      const int q = (e - FT1) >> 6, mt = q >> 4, ti = q & 15, t = ti >> 2, i = ti & 3;
+      v = P[OFF_W1 + (16 * t + 4 * gg + i) * NIN + 16 * mt + rr];
+    }
+    ft[e] = v;
+  }
+  __syncthreads();
+  Frag32 f;
+  load_frag32(P, r, g, f);
+  f32x4 aW1[4][2], aW2[4][4], aW3[4];
+  float ab1[4][4], ab2[4][4], ab3[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    aW3[a] = f32x4{0, 0, 0, 0};
+    ab3[a] = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      aW2[a][b] = f32x4{0, 0, 0, 0};
+      ab1[a][b] = 0.0f;
+      ab2[a][b] = 0.0f;
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) aW1[a][b] = f32x4{0, 0, 0, 0};
+  }
+  const int64_t ntile = ceil_div(S, 16);
+  const int64_t wstride = (int64_t)gridDim.x * kBwdWaves;
+  for (int64_t tile = (int64_t)blockIdx.x * kBwdWaves + wid; tile < ntile; tile += wstride) {
+    const int64_t s = tile * 16 + r;
+    const bool ok = s < S;
+    float X[8];
+    load_x(feat, S, s, g, ok, X);
+    f32x4 z1[4], z2[4], o;
+    fwd32(f, X, z1, z2, o);
+    // output-head gradient (lanes g == 0 hold sample r's four outputs)
+    float d3[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (g == 0 && ok && (!bone || bone[s] >= 0)) {
+      const float ov[4] = {o[0], o[1], o[2], o[3]};
+      float sg, c[3];
+      head(ov, &sg, c);
+      d3[0] = ov[0] < 80.0f ? gsig[s] * sg : 0.0f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) d3[1 + k] = grgb[k * ld + s] * c[k] * (1.0f - c[k]);
+    }
+    // scratch: x, h1, h2, d3 tiles [feature/neuron][sample]
+#pragma unroll
+    for (int c = 0; c < 8; ++c) scr[SCR_X + (8 * g + c) * LDP + r] = X[c];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        scr[SCR_H1 + (16 * t + 4 * g + i) * LDP + r] = relu(z1[t][i]);
+        scr[SCR_H2 + (16 * t + 4 * g + i) * LDP + r] = relu(z2[t][i]);
+      }
+    if (g == 0)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) scr[SCR_D3 + k * LDP + r] = d3[k];
+    // B operand of gh2 = W3^T d3: d3[output g][sample r]
+    float b3 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float t = __shfl(d3[k], r, 64);
+      b3 = (g == k) ? t : b3;
+    }
+    f32x4 d2[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 acc = mfma4(ft[FT3 + mt * 64 + lane], b3, f32x4{0, 0, 0, 0});
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc[i] = z2[mt][i] < 0.0f ? 0.0f : acc[i];
+        ab2[mt][i] += acc[i];
+      }
+      d2[mt] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ab3[i] += (g == 0) ? d3[i] : 0.0f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) scr[SCR_D + (16 * t + 4 * g + i) * LDP + r] = d2[t][i];
+    wave_sync();
+    // dW3 += d3 h2^T ; dW2 += d2 h1^T   (K = 16 samples, 4 steps)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float a3 = r < NOUT ? scr[SCR_D3 + r * LDP + 4 * c + g] : 0.0f;
+      float bh2[4], bh1[4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        bh2[nt] = scr[SCR_H2 + (16 * nt + r) * LDP + 4 * c + g];
+        bh1[nt] = scr[SCR_H1 + (16 * nt + r) * LDP + 4 * c + g];
+      }
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) aW3[nt] = mfma4(a3, bh2[nt], aW3[nt]);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const float ad = scr[SCR_D + (16 * mt + r) * LDP + 4 * c + g];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) aW2[mt][nt] = mfma4(ad, bh1[nt], aW2[mt][nt]);
+      }
+    }
+    wave_sync();
+    // gh1 = W2^T d2 ; d1
+    f32x4 d1[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc = mfma4(ft[FT2 + (mt * 16 + 4 * t + i) * 64 + lane], d2[t][i], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc[i] = z1[mt][i] < 0.0f ? 0.0f : acc[i];
+        ab1[mt][i] += acc[i];
+      }
+      d1[mt] = acc;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) scr[SCR_D + (16 * t + 4 * g + i) * LDP + r] = d1[t][i];
+    // gfeat = W1^T d1 -> feature 16mt + 4g + i = level 8mt + 2g + i/2, f = i%2
+    if (gfeat) {
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        f32x4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc = mfma4(ft[FT1 + (mt * 16 + 4 * t + i) * 64 + lane], d1[t][i], acc);
+        if (ok) {
+          float2 *gf = reinterpret_cast<float2 *>(gfeat);
+          gf[(int64_t)(8 * mt + 2 * g) * S + s] = make_float2(acc[0], acc[1]);
+          gf[(int64_t)(8 * mt + 2 * g + 1) * S + s] = make_float2(acc[2], acc[3]);
+        }
+      }
+    }
+    wave_sync();
+    // dW1 += d1 x^T
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float bx[2];
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) bx[nt] = scr[SCR_X + (16 * nt + r) * LDP + 4 * c + g];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const float ad = scr[SCR_D + (16 * mt + r) * LDP + 4 * c + g];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) aW1[mt][nt] = mfma4(ad, bx[nt], aW1[mt][nt]);
+      }
+    }
+    wave_sync();
+  }
+  // bias partials: sum over the 16 sample lanes r
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        ab1[a][b] += __shfl_xor(ab1[a][b], o, 16);
+        ab2[a][b] += __shfl_xor(ab2[a][b], o, 16);
+      }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) ab3[a] += __shfl_xor(ab3[a], o, 16);
+  // block partial in the (now free) scratch region, waves added in order
+  __syncthreads();
+  float *bp = lds + FT_SIZE;
+  for (int w = 0; w < kBwdWaves; ++w) {
+    if (wid == w) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = 16 * mt + 4 * g + i;
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt) {
+            const int e = OFF_W1 + m * NIN + 16 * nt + r;
+            bp[e] = (w ? bp[e] : 0.0f) + aW1[mt][nt][i];
+          }
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) {
+            const int e = OFF_W2 + m * NH + 16 * nt + r;
+            bp[e] = (w ? bp[e] : 0.0f) + aW2[mt][nt][i];
+          }
+          if (r == 0) {
+            bp[OFF_B1 + m] = (w ? bp[OFF_B1 + m] : 0.0f) + ab1[mt][i];
+            bp[OFF_B2 + m] = (w ? bp[OFF_B2 + m] : 0.0f) + ab2[mt][i];
+          }
+        }
+      if (g == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) {
+            const int e = OFF_W3 + i * NH + 16 * nt + r;
+            bp[e] = (w ? bp[e] : 0.0f) + aW3[nt][i];
+          }
+          if (r == 0) bp[OFF_B3 + i] = (w ? bp[OFF_B3 + i] : 0.0f) + ab3[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < NPARAM; e += kBwdBlock) partial[(int64_t)blockIdx.x * NPARAM + e] = bp[e];
+}
+
+__global__ void reduce_partials(const float *__restrict__ partial, int nblk, float *__restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NPARAM) return;
+  float acc = 0.0f;
+  for (int b = 0; b < nblk; ++b) acc += partial[(int64_t)b * NPARAM + e];
+  out[e] += acc;
+}
+
+constexpr int kMaxBwdBlocks = 512;
+
+int bwd_blocks(int64_t S) {
+  int64_t b = ceil_div(ceil_div(S, 16), kBwdWaves);
+  if (b > kMaxBwdBlocks) b = kMaxBwdBlocks;
+  return b < 1 ? 1 : (int)b;
+}
+
+unsigned fwd_blocks(int64_t S) { return grid_for(ceil_div(S, 16) * 64, kFwdBlock, 256 * 8); }
+
+}  // namespace
+
+extern "C" int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int16_t *bone, int64_t S, int64_t ld,
+                                 const float *params, int32_t dtype, float *sigma, float *rgb, ia355_stream_t stream) {
+  if (S < 0 || ld < S || !params) return IA355_ERR_INVALID_ARG;
+  if (S > 0 && (!feat || !sigma || !rgb)) return IA355_ERR_INVALID_ARG;
+  if (dtype == IA355_F32 && feat_dtype != IA355_F32) return IA355_ERR_UNSUPPORTED;
+  if (dtype == IA355_BF16 && feat_dtype != IA355_BF16) return IA355_ERR_UNSUPPORTED;
+  if (dtype != IA355_F32 && dtype != IA355_BF16) return IA355_ERR_INVALID_ARG;
+  if (S == 0) return IA355_OK;
+  hipStream_t s = as_stream(stream);
+  if (dtype == IA355_F32)
+    mlp_fwd_f32<<<fwd_blocks(S), kFwdBlock, 0, s>>>((const float *)feat, bone, S, ld, params, sigma, rgb);
+  else
+    mlp_fwd_bf16<<<fwd_blocks(S), kFwdBlock, 0, s>>>((const __hip_bfloat16 *)feat, bone, S, ld, params, sigma, rgb);
+  return launch_status();
+}
+
+extern "C" size_t ia355_mlp_bwd_workspace_size(int64_t S) {
+  return align256(sizeof(float) * (size_t)NPARAM * bwd_blocks(S));
+}
+
+extern "C" int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb, const void *feat, int32_t feat_dtype,
+                                 const int16_t *bone, int64_t S, int64_t ld, const float *params, int32_t dtype,
+                                 float *grad_params, float *grad_feat, void *ws, size_t ws_bytes,
+                                 ia355_stream_t stream) {
+  if (S < 0 || ld < S || !params || !grad_params) return IA355_ERR_INVALID_ARG;
+  if (S > 0 && (!grad_sigma || !grad_rgb || !feat)) return IA355_ERR_INVALID_ARG;
+  if (dtype != IA355_F32 || feat_dtype != IA355_F32) return IA355_ERR_UNSUPPORTED;
+  if (S == 0) return IA355_OK;
+  if (!ws || ws_bytes < ia355_mlp_bwd_workspace_size(S)) return IA355_ERR_WORKSPACE;
+  hipStream_t s = as_stream(stream);
+  const int nb = bwd_blocks(S);
+  mlp_bwd_f32<<<nb, kBwdBlock, LDS_FLOATS * sizeof(float), s>>>(grad_sigma, grad_rgb, (const float *)feat, bone, S, ld,
+                                                                params, grad_feat, (float *)ws);
+  reduce_partials<<<(unsigned)ceil_div(NPARAM, 256), 256, 0, s>>>((const float *)ws, nb, grad_params);
+  return launch_status();
+}

@@ -1,0 +1,211 @@
+"""Thin ctypes binding of ``libia355.so`` (the C ABI in ``include/ia355.h``).
+
+Argument marshalling only: every function takes torch tensors that already
+live on the GPU, checks dtype/contiguity/device, passes raw pointers and the
+current HIP stream, and raises on a non-zero status.  All arithmetic happens
+in the library's HIP kernels.  There is no fallback: if the library is
+missing or the tensors are not on a GPU, the call fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libia355.so")
+
+F32, F16, BF16 = 0, 1, 2
+_DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_f = ctypes.c_float
+_d = ctypes.c_double
+_sz = ctypes.c_size_t
+_fp = ctypes.POINTER(ctypes.c_float)
+
+# name -> (restype, argtypes); names are the C entry points without "ia355_"
+_SIGS = {
+    "version": (_i32, []),
+    "error_string": (ctypes.c_char_p, [_i32]),
+    "zero": (_i32, [_vp, _sz, _vp]),
+    "occ_pack": (_i32, [_vp, _i32, _vp, _vp]),
+    "march_workspace_size": (_sz, [_i64]),
+    "occgrid_march": (_i32, [_vp, _vp, _i64, _vp, _i32, _fp, _f, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
+                             _vp, _vp, _sz, _vp]),
+    "deform_workspace_size": (_sz, [_i32, _i32, _i32]),
+    "snarf_deform": (_i32, [_vp, _i64, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _vp, _vp,
+                            _vp, _vp, _sz, _vp]),
+    "snarf_deform_bwd": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _vp, _vp, _vp,
+                                _vp]),
+    "hashgrid_encode": (_i32, [_vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _i32, _vp]),
+    "hashgrid_encode_bwd": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _vp,
+                                   _vp]),
+    "mlp_fwd": (_i32, [_vp, _i32, _vp, _i64, _i64, _vp, _i32, _vp, _vp, _vp]),
+    "mlp_bwd_workspace_size": (_sz, [_i64]),
+    "mlp_bwd": (_i32, [_vp, _vp, _vp, _i32, _vp, _i64, _i64, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "volrender_fwd": (_i32, [_vp, _vp, _i64, _vp, _vp, _i64, _f, _vp, _vp, _vp, _vp, _vp]),
+    "volrender_bwd": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "l2_loss": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; "
+                               "g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, "ia355_" + name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    return _vp(t.data_ptr())
+
+
+def _box(b):
+    b = [float(v) for v in b]
+    if len(b) != 6:
+        raise ValueError("box must have 6 values")
+    return (ctypes.c_float * 6)(*b)
+
+
+def _check(status, name):
+    if status != 0:
+        raise RuntimeError(f"ia355_{name}: {lib().ia355_error_string(status).decode()} (status {status})")
+
+
+def version():
+    return lib().ia355_version()
+
+
+def zero(t):
+    _check(lib().ia355_zero(_p(t), t.numel() * t.element_size(), _stream()), "zero")
+
+
+def occ_pack(occ_u8, bits):
+    G = occ_u8.shape[0]
+    _check(lib().ia355_occ_pack(_p(occ_u8, torch.uint8, "occ"), G, _p(bits, torch.int32, "bits"), _stream()),
+           "occ_pack")
+
+
+def march_workspace_size(R):
+    return lib().ia355_march_workspace_size(R)
+
+
+def occgrid_march(rays_o, rays_d, occ_bits, G, aabb, dt, n_per_ray, max_steps, xs, ts, ray_id, cap, ray_off,
+                  ray_cnt, ray_dt, n_samples, ws):
+    R = rays_o.shape[0]
+    _check(lib().ia355_occgrid_march(
+        _p(rays_o, torch.float32, "rays_o"), _p(rays_d, torch.float32, "rays_d"), R,
+        _p(occ_bits, torch.int32, "occ_bits"), G, _box(aabb), float(dt), n_per_ray, max_steps,
+        _p(xs, torch.float32, "xs"), _p(ts, torch.float32, "ts"), _p(ray_id, torch.int32, "ray_id"), cap,
+        _p(ray_off, torch.int64, "ray_off"), _p(ray_cnt, torch.int32, "ray_cnt"), _p(ray_dt, torch.float32, "ray_dt"),
+        _p(n_samples, torch.int64, "n_samples"), _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()),
+        "occgrid_march")
+
+
+def deform_workspace_size(Dx, Dy, Dz):
+    return lib().ia355_deform_workspace_size(Dx, Dy, Dz)
+
+
+def snarf_deform(xp, S, ld, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, ws):
+    Dz, Dy, Dx, nb = W.shape
+    _check(lib().ia355_snarf_deform(
+        _p(xp, torch.float32, "xp"), S, ld, _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"), Dx, Dy, Dz,
+        _box(skin_aabb), _box(hash_aabb), max_iter, tol_stop, tol_valid, _p(xc, torch.float32, "xc"),
+        _p(bone, torch.int16, "bone"), _p(resid, torch.float32, "resid"), _p(steps, torch.int16, "steps"),
+        _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "snarf_deform")
+
+
+def snarf_deform_bwd(grad_xc, xc, bone, S, ld, B, W, skin_aabb, grad_xp, grad_B, grad_W):
+    Dz, Dy, Dx, nb = W.shape
+    _check(lib().ia355_snarf_deform_bwd(
+        _p(grad_xc, torch.float32, "grad_xc"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S, ld,
+        _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"), Dx, Dy, Dz, _box(skin_aabb),
+        _p(grad_xp, torch.float32, "grad_xp"), _p(grad_B, torch.float32, "grad_B"),
+        _p(grad_W, torch.float32, "grad_W"), _stream()), "snarf_deform_bwd")
+
+
+def hashgrid_encode(xc, bone, S, ld, table, base_res, growth, aabb, feat):
+    L, T, F = table.shape
+    _check(lib().ia355_hashgrid_encode(
+        _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S, ld, _p(table, name="table"), _DT[table.dtype],
+        L, F, T.bit_length() - 1, base_res, growth, _box(aabb), _p(feat, name="feat"), _DT[feat.dtype], _stream()),
+        "hashgrid_encode")
+
+
+def hashgrid_encode_bwd(grad_feat, xc, bone, S, ld, table, base_res, growth, aabb, grad_table, grad_xc):
+    L, T, F = table.shape
+    _check(lib().ia355_hashgrid_encode_bwd(
+        _p(grad_feat, torch.float32, "grad_feat"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S, ld,
+        _p(table, name="table"), _DT[table.dtype], L, F, T.bit_length() - 1, base_res, growth, _box(aabb),
+        _p(grad_table, torch.float32, "grad_table"), _p(grad_xc, torch.float32, "grad_xc"), _stream()),
+        "hashgrid_encode_bwd")
+
+
+def mlp_fwd(feat, bone, S, ld, params, dtype, sigma, rgb):
+    _check(lib().ia355_mlp_fwd(
+        _p(feat, name="feat"), _DT[feat.dtype], _p(bone, torch.int16, "bone"), S, ld,
+        _p(params, torch.float32, "params"), dtype, _p(sigma, torch.float32, "sigma"), _p(rgb, torch.float32, "rgb"),
+        _stream()), "mlp_fwd")
+
+
+def mlp_bwd_workspace_size(S):
+    return lib().ia355_mlp_bwd_workspace_size(S)
+
+
+def mlp_bwd(grad_sigma, grad_rgb, feat, bone, S, ld, params, dtype, grad_params, grad_feat, ws):
+    _check(lib().ia355_mlp_bwd(
+        _p(grad_sigma, torch.float32, "grad_sigma"), _p(grad_rgb, torch.float32, "grad_rgb"), _p(feat, name="feat"),
+        _DT[feat.dtype], _p(bone, torch.int16, "bone"), S, ld, _p(params, torch.float32, "params"), dtype,
+        _p(grad_params, torch.float32, "grad_params"), _p(grad_feat, torch.float32, "grad_feat"),
+        _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "mlp_bwd")
+
+
+def volrender_fwd(sigma, rgb, ld, ray_off, ray_dt, R, T_thresh, color, opacity, n_used, T_final):
+    _check(lib().ia355_volrender_fwd(
+        _p(sigma, torch.float32, "sigma"), _p(rgb, torch.float32, "rgb"), ld, _p(ray_off, torch.int64, "ray_off"),
+        _p(ray_dt, torch.float32, "ray_dt"), R, T_thresh, _p(color, torch.float32, "color"),
+        _p(opacity, torch.float32, "opacity"), _p(n_used, torch.int32, "n_used"), _p(T_final, torch.float32, "T_final"),
+        _stream()), "volrender_fwd")
+
+
+def volrender_bwd(grad_color, grad_opacity, sigma, rgb, ld, ray_off, ray_dt, n_used, color, T_final, R, grad_sigma,
+                  grad_rgb):
+    _check(lib().ia355_volrender_bwd(
+        _p(grad_color, torch.float32, "grad_color"), _p(grad_opacity, torch.float32, "grad_opacity"),
+        _p(sigma, torch.float32, "sigma"), _p(rgb, torch.float32, "rgb"), ld, _p(ray_off, torch.int64, "ray_off"),
+        _p(ray_dt, torch.float32, "ray_dt"), _p(n_used, torch.int32, "n_used"), _p(color, torch.float32, "color"),
+        _p(T_final, torch.float32, "T_final"), R, _p(grad_sigma, torch.float32, "grad_sigma"),
+        _p(grad_rgb, torch.float32, "grad_rgb"), _stream()), "volrender_bwd")
+
+
+def l2_loss(color, target, loss, grad_color):
+    R = color.shape[0]
+    _check(lib().ia355_l2_loss(_p(color, torch.float32, "color"), _p(target, torch.float32, "target"), R,
+                               _p(loss, torch.float32, "loss"), _p(grad_color, torch.float32, "grad_color"),
+                               _stream()), "l2_loss")

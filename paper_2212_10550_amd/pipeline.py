@@ -1,0 +1,156 @@
+"""Device-resident pipeline: one training step or one frame of the
+deform-and-query path (Fig. 2 of the paper) as a fixed sequence of C-ABI
+calls on preallocated HBM buffers.
+
+    march -> deform -> hash encode -> MLP -> composite           (forward)
+    L2 loss -> composite bwd -> MLP bwd -> encode bwd -> deform bwd (IFT)
+
+PyTorch only provides the device allocations and the stream; no torch
+operator runs inside ``forward`` / ``backward`` / ``train_step``.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import lib as K
+
+NPARAM = 6532
+
+
+class Pipeline:
+    def __init__(self, w, device="cuda", table_dtype=torch.float32, mlp_dtype=K.F32, cap=None,
+                 grad_W=True, grad_B=True):
+        self.w = w
+        self.dev = torch.device(device)
+        dev = self.dev
+        t = lambda a, dt=None: torch.as_tensor(np.ascontiguousarray(a), device=dev, dtype=dt)
+        self.R = w.R
+        self.rays_o = t(w.rays_o, torch.float32)
+        self.rays_d = t(w.rays_d, torch.float32)
+        self.G = 0
+        self.occ_bits = None
+        if w.occ is not None:
+            self.G = w.occ.shape[0]
+            occ = t(w.occ, torch.uint8)
+            self.occ_bits = torch.empty((self.G ** 3 + 31) // 32, dtype=torch.int32, device=dev)
+            K.occ_pack(occ, self.occ_bits)
+        self.B = t(w.B, torch.float32)
+        self.W = t(w.W, torch.float32)
+        self.table32 = t(w.table, torch.float32)
+        self.table = self.table32 if table_dtype == torch.float32 else self.table32.to(table_dtype)
+        self.params = t(w.mlp, torch.float32)
+        self.target = None if w.target is None else t(w.target, torch.float32)
+        self.mlp_dtype = mlp_dtype
+        self.feat_dtype = torch.float32 if mlp_dtype == K.F32 else torch.bfloat16
+        self.cap = int(cap) if cap is not None else self.R * w.max_steps
+        cap = self.cap
+        L = w.L
+        e = lambda *shape, dt=torch.float32: torch.empty(*shape, dtype=dt, device=dev)
+        # march outputs
+        self.xs = e(3, cap)
+        self.ts = e(cap)
+        self.ray_id = e(cap, dt=torch.int32)
+        self.ray_off = e(self.R + 1, dt=torch.int64)
+        self.ray_cnt = e(self.R, dt=torch.int32)
+        self.ray_dt = e(self.R)
+        self.n_samples = e(1, dt=torch.int64)
+        self.ws_march = e(K.march_workspace_size(self.R), dt=torch.uint8)
+        # deform
+        Dz, Dy, Dx, nb = w.W.shape
+        self.ws_deform = e(K.deform_workspace_size(Dx, Dy, Dz), dt=torch.uint8)
+        self.xc = e(3, cap)
+        self.bone = e(cap, dt=torch.int16)
+        self.resid = e(cap)
+        self.steps = e(cap, dt=torch.int16)
+        # field
+        self.feat = e(L * cap * 2, dt=self.feat_dtype)
+        self.sigma = e(cap)
+        self.rgb = e(3, cap)
+        # composite
+        self.color = e(self.R, 3)
+        self.opacity = e(self.R)
+        self.n_used = e(self.R, dt=torch.int32)
+        self.T_final = e(self.R)
+        # backward
+        self.loss = e(1)
+        self.grad_color = e(self.R, 3)
+        self.grad_sigma = e(cap)
+        self.grad_rgb = e(3, cap)
+        self.grad_feat = e(L * cap * 2)
+        self.grad_params = e(NPARAM)
+        self.ws_mlp = e(K.mlp_bwd_workspace_size(cap), dt=torch.uint8)
+        self.grad_table = e(*self.table32.shape)
+        self.grad_xc = e(3, cap)
+        self.grad_xp = e(3, cap)
+        self.grad_B = e(*self.B.shape) if grad_B else None
+        self.grad_W = e(*self.W.shape) if grad_W else None
+        self.S = None
+
+    # ------------------------------------------------------------ forward
+    def march(self):
+        w = self.w
+        K.occgrid_march(self.rays_o, self.rays_d, self.occ_bits, self.G, w.occ_aabb, w.dt, w.n_per_ray, w.max_steps,
+                        self.xs, self.ts, self.ray_id, self.cap, self.ray_off, self.ray_cnt, self.ray_dt,
+                        self.n_samples, self.ws_march)
+
+    def read_count(self):
+        S = int(self.n_samples.item())
+        if S > self.cap:
+            raise RuntimeError(f"sample buffer too small: {S} > {self.cap}")
+        self.S = S
+        return S
+
+    def field(self, S):
+        w = self.w
+        K.snarf_deform(self.xs, S, self.cap, self.B, self.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop,
+                       w.tol_valid, self.xc, self.bone, self.resid, self.steps, self.ws_deform)
+        feat = self.feat[: w.L * S * 2]
+        K.hashgrid_encode(self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth, w.hash_aabb, feat)
+        K.mlp_fwd(feat, self.bone, S, self.cap, self.params, self.mlp_dtype, self.sigma, self.rgb)
+
+    def composite(self):
+        K.volrender_fwd(self.sigma, self.rgb, self.cap, self.ray_off, self.ray_dt, self.R, self.w.T_thresh,
+                        self.color, self.opacity, self.n_used, self.T_final)
+
+    def forward(self):
+        self.march()
+        S = self.read_count()
+        self.field(S)
+        self.composite()
+        return S
+
+    # ----------------------------------------------------------- backward
+    def backward(self, S):
+        w = self.w
+        K.l2_loss(self.color, self.target, self.loss, self.grad_color)
+        K.volrender_bwd(self.grad_color, None, self.sigma, self.rgb, self.cap, self.ray_off, self.ray_dt, self.n_used,
+                        self.color, self.T_final, self.R, self.grad_sigma, self.grad_rgb)
+        K.zero(self.grad_params)
+        feat = self.feat[: w.L * S * 2]
+        gfeat = self.grad_feat[: w.L * S * 2]
+        K.mlp_bwd(self.grad_sigma, self.grad_rgb, feat, self.bone, S, self.cap, self.params, self.mlp_dtype,
+                  self.grad_params, gfeat, self.ws_mlp)
+        K.zero(self.grad_table)
+        K.hashgrid_encode_bwd(gfeat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth, w.hash_aabb,
+                              self.grad_table, self.grad_xc)
+        if self.grad_B is not None:
+            K.zero(self.grad_B)
+        if self.grad_W is not None:
+            K.zero(self.grad_W)
+        K.snarf_deform_bwd(self.grad_xc, self.xc, self.bone, S, self.cap, self.B, self.W, w.skin_aabb, self.grad_xp,
+                           self.grad_B, self.grad_W)
+
+    def train_step(self):
+        S = self.forward()
+        self.backward(S)
+        return S
+
+    # ------------------------------------------------------------ readback
+    def soa(self, t, S=None):
+        S = self.S if S is None else S
+        return t[:, :S].T.double().cpu().numpy()
+
+    def feat_samples(self, S=None):
+        S = self.S if S is None else S
+        return self.feat[: self.w.L * S * 2].float().view(self.w.L, S, 2).permute(1, 0, 2).reshape(S, -1).double().cpu().numpy()

@@ -1,0 +1,40 @@
+"""Helpers for the GPU parity tests (tolerance checks, device uploads)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def up(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), device=dev(), dtype=dtype)
+
+
+def soa(a, ld=None, dtype=torch.float32):
+    """[n,3] host array -> [3][ld] device tensor (zero padded)."""
+    a = np.asarray(a)
+    n = a.shape[0]
+    ld = n if ld is None else ld
+    out = np.zeros((3, ld), np.float64)
+    out[:, :n] = a.T
+    return up(out, dtype)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def assert_mixed(got, ref, tol, what="", scale=1.0):
+    """|got - ref| <= tol * max(scale, |ref|) elementwise (mixed relative)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    assert got.shape == ref.shape, (what, got.shape, ref.shape)
+    err = np.abs(got - ref) / np.maximum(scale, np.abs(ref))
+    if err.size and not (err <= tol).all():
+        i = np.unravel_index(np.argmax(err), err.shape)
+        raise AssertionError(f"{what}: max mixed error {err.max():.3e} > {tol:.1e} at {i}: got {got[i]!r} "
+                             f"ref {ref[i]!r} ({(err > tol).sum()} of {err.size} elements)")
+    return float(err.max()) if err.size else 0.0

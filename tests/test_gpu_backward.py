@@ -1,0 +1,156 @@
+"""GPU parity of the backward stages and of a whole training step against the
+FP64 oracle, through the C ABI.
+
+Bar for gradients: |gpu - oracle| <= 1e-4 * max(|oracle|, 1e-3 * max|oracle|)
+(summation order and atomics make per-element bits order dependent; the
+floor keeps near-zero entries of a large gradient from dominating).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2212_10550_amd import synth
+from tests.gpu_util import assert_mixed, dev, host, soa, up
+
+pytestmark = pytest.mark.gpu
+
+GTOL = 1e-4
+
+
+def _K():
+    from paper_2212_10550_amd import lib as K
+    return K
+
+
+def gclose(got, ref, what):
+    ref = np.asarray(ref, np.float64)
+    scale = 1e-3 * (np.abs(ref).max() if ref.size else 1.0)
+    return assert_mixed(got, ref, GTOL, what, scale=max(scale, 1e-30))
+
+
+@pytest.mark.parametrize("thr", [0.0, 0.2])
+def test_volrender_bwd(orc, thr):
+    K = _K()
+    rng = np.random.default_rng(1)
+    cnt = rng.integers(0, 70, 999)
+    cnt[:3] = [0, 1, 128]
+    off = np.r_[0, np.cumsum(cnt)].astype(np.int64)
+    S, R = int(off[-1]), len(cnt)
+    sig = rng.uniform(0, 40, S).astype(np.float32)
+    rgb = rng.uniform(0, 1, (S, 3)).astype(np.float32)
+    dt = rng.uniform(0.005, 0.02, R).astype(np.float32)
+    gC = rng.normal(size=(R, 3)).astype(np.float32)
+    gA = rng.normal(size=R).astype(np.float32)
+    color, opac = torch.empty(R, 3, device=dev()), torch.empty(R, device=dev())
+    n_used, Tf = torch.empty(R, dtype=torch.int32, device=dev()), torch.empty(R, device=dev())
+    sig_t, rgb_t, off_t, dt_t = up(sig), soa(rgb), up(off), up(dt)
+    K.volrender_fwd(sig_t, rgb_t, S, off_t, dt_t, R, thr, color, opac, n_used, Tf)
+    gs, gr = torch.full((S,), 7.0, device=dev()), torch.full((3, S), 7.0, device=dev())
+    K.volrender_bwd(up(gC), up(gA), sig_t, rgb_t, S, off_t, dt_t, n_used, color, Tf, R, gs, gr)
+    torch.cuda.synchronize()
+    fwd = orc.composite_fwd(sig, rgb, off, dt, thr)
+    assert (host(n_used) == fwd["n_used"]).all()
+    rs, rr = orc.composite_bwd(gC, sig, rgb, off, dt, fwd["n_used"], grad_opacity=gA)
+    # per-ray scale: the gradient of a ray is bounded by |g| (delta + ...)
+    assert_mixed(host(gs), rs, GTOL, "grad_sigma", scale=1e-3)
+    assert_mixed(host(gr).T, rr, GTOL, "grad_rgb", scale=1e-3)
+
+
+def test_l2_loss(orc):
+    K = _K()
+    rng = np.random.default_rng(2)
+    C, T = rng.uniform(size=(8192, 3)).astype(np.float32), rng.uniform(size=(8192, 3)).astype(np.float32)
+    loss, g = torch.empty(1, device=dev()), torch.empty(8192, 3, device=dev())
+    K.l2_loss(up(C), up(T), loss, g)
+    torch.cuda.synchronize()
+    Lr, gr = orc.l2_loss(C, T)
+    assert_mixed(host(loss), [Lr], 1e-5, "loss")
+    assert_mixed(host(g), gr, 1e-5, "grad_color", scale=1e-6)
+
+
+@pytest.mark.parametrize("S", [7, 16, 4099, 40000])
+def test_mlp_bwd_f32(orc, S):
+    K = _K()
+    rng = np.random.default_rng(S)
+    feat = rng.normal(0, 0.5, (S, 32)).astype(np.float32)
+    params = synth.make_mlp(seed=3, sigma_bias=0.3).astype(np.float32)
+    bone = np.where(rng.uniform(size=S) < 0.1, -1, 1).astype(np.int16)
+    gsig = rng.normal(size=S).astype(np.float32)
+    grgb = rng.normal(size=(S, 3)).astype(np.float32)
+    ld = S + 3
+    ft = up(feat.reshape(S, 16, 2).transpose(1, 0, 2).reshape(-1))
+    gp = torch.full((6532,), 0.25, device=dev())  # accumulated into
+    gf = torch.empty(16 * S * 2, device=dev())
+    ws = torch.empty(K.mlp_bwd_workspace_size(S), dtype=torch.uint8, device=dev())
+    K.mlp_bwd(up(gsig), soa(grgb, ld), ft, up(bone), S, ld, up(params), K.F32, gp, gf, ws)
+    torch.cuda.synchronize()
+    rp, rf = orc.mlp_bwd(gsig, grgb, feat, params, valid=bone)
+    gclose(host(gp) - 0.25, rp, "grad_params")
+    gclose(host(gf).reshape(16, S, 2).transpose(1, 0, 2).reshape(S, 32), rf, "grad_feat")
+
+
+@pytest.mark.parametrize("log2T,tdt", [(14, np.float32), (19, np.float32), (19, np.float16)])
+def test_hash_bwd(orc, log2T, tdt):
+    K = _K()
+    S = 6007
+    x = synth.random_points(S, 41)
+    table = synth.make_hash_table(16, 1 << log2T, 2, seed=6, scale=0.3).astype(tdt)
+    rng = np.random.default_rng(7)
+    gfeat = rng.normal(size=(S, 32)).astype(np.float32)
+    bone = np.where(np.arange(S) % 11 == 5, -1, 0).astype(np.int16)
+    gt = torch.zeros(16, 1 << log2T, 2, device=dev())
+    gx = torch.full((3, S), 3.0, device=dev())
+    K.hashgrid_encode_bwd(up(gfeat.reshape(S, 16, 2).transpose(1, 0, 2).reshape(-1)), soa(x), up(bone), S, S,
+                          up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, gx)
+    torch.cuda.synchronize()
+    rt, rx = orc.hash_encode_bwd(gfeat, x, table, orc.resolutions(16), np.array([0, 0, 0, 1, 1, 1.0]), valid=bone)
+    gclose(host(gt), rt, "grad_table")
+    # the position gradient scales with N_l |theta|; FP32 weights carry ~1e-7 relative error
+    gclose(host(gx).T, rx, "grad_x")
+    assert (host(gx).T[bone < 0] == 0).all()
+
+
+def test_deform_bwd(orc):
+    K = _K()
+    w = synth.train_step()
+    rng = np.random.default_rng(8)
+    S = 3001
+    xc = np.c_[rng.uniform(0.05, 0.95, S), rng.uniform(0.05, 0.95, S), rng.uniform(0.3, 0.7, S)].astype(np.float32)
+    xc[:2] = [[0.5, 0.5, 0.2], [0.5, 0.5, 0.8]]  # outside the skinning box along z (clamped)
+    u = rng.normal(size=(S, 3)).astype(np.float32)
+    bone = np.where(np.arange(S) % 13 == 4, -1, 2).astype(np.int16)
+    ld = S + 1
+    gxp = torch.full((3, ld), 5.0, device=dev())
+    gB = torch.full(w.B.shape, 0.5, device=dev())
+    gW = torch.zeros(w.W.shape, device=dev())
+    Dz, Dy, Dx, nb = w.W.shape
+    K.snarf_deform_bwd(soa(u, ld), soa(xc, ld), up(bone), S, ld, up(w.B), up(w.W), w.skin_aabb, gxp, gB, gW)
+    torch.cuda.synchronize()
+    rxp, rB, rW = orc.deform_bwd(u, xc, bone, w.B, w.W, w.skin_aabb)
+    gclose(host(gxp[:, :S]).T, rxp, "grad_xp")
+    gclose(host(gB) - 0.5, rB, "grad_B")
+    gclose(host(gW), rW, "grad_W")
+
+
+def test_train_step_subset(orc):
+    """A whole training step (forward, L2 loss, every backward) on 1/8 of the
+    training rays: loss, colours and every gradient against the oracle."""
+    from paper_2212_10550_amd.pipeline import Pipeline
+    w = synth.ray_subset(synth.train_step(), np.arange(0, 8192, 8))
+    p = Pipeline(w)
+    S = p.train_step()
+    torch.cuda.synchronize()
+    ref = orc.train_step(w)
+    assert S == ref["march"]["xs"].shape[0]
+    gb = host(p.bone[:S]).astype(int)
+    assert ((gb >= 0) == (ref["deform"]["bone"] >= 0)).all(), "validity differs: gradients not comparable"
+    assert_mixed(host(p.color), ref["color"], 1e-5, "colour")
+    assert_mixed(host(p.loss), [ref["loss"]], 1e-5, "loss")
+    gclose(host(p.grad_sigma[:S]), ref["grad_sigma"], "grad_sigma")
+    gclose(host(p.grad_params), ref["grad_params"], "grad_params")
+    gclose(host(p.grad_table), ref["grad_table"], "grad_table")
+    gclose(p.soa(p.grad_xc), ref["grad_xc"], "grad_xc")
+    gclose(p.soa(p.grad_xp), ref["grad_xp"], "grad_xp")
+    gclose(host(p.grad_B), ref["grad_B"], "grad_B")
+    gclose(host(p.grad_W), ref["grad_W"], "grad_W")
+    print(f"train subset: S={S} loss={float(p.loss.item()):.6f}")

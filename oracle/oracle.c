@@ -23,8 +23,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MAXB 64
+
+/* Number of threads the parallel loops use (1 without OpenMP). */
+int32_t oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Sec. 3.2 (ray r = o + t d, N samples between near and far) and      */

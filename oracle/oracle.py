@@ -27,6 +27,8 @@ _D = ctypes.c_double
 @functools.lru_cache(maxsize=None)
 def lib():
     L = ctypes.CDLL(ensure_built())
+    L.oracle_num_threads.restype = _I32
+    L.oracle_num_threads.argtypes = []
     L.oracle_march.restype = _I64
     L.oracle_march.argtypes = [_f, _f, _I64, _u8, _I32, _f, ctypes.c_float, _I32, _I32,
                                _d, _d, _i64, _I64, _i64, _i32, _d]
@@ -56,6 +58,10 @@ def lib():
     L.oracle_l2_loss.restype = _D
     L.oracle_l2_loss.argtypes = [_d, _d, _I64, _d]
     return L
+
+
+def num_threads():
+    return int(lib().oracle_num_threads())
 
 
 def _p(a, t):

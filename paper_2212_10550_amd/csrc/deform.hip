@@ -105,13 +105,27 @@ __device__ __forceinline__ void residual(const float *__restrict__ A, const Grid
   }
 }
 
-// Residual and Jacobian J = sum_c tri_c M_c + sum_c (A_c x_h) (grad tri_c)^T.
+// Derivatives of a trilinear interpolant along its cell axes, from the
+// eight corner values v[c] (c = cx + 2 cy + 4 cz) and the fractions f:
+// differences of neighbouring corners are taken first, so the result does
+// not cancel when the corner values are close (they are smooth fields).
+__device__ __forceinline__ void tri_grad(const float v[8], const float f[3], float d[3]) {
+  const float gx = 1.0f - f[0], gy = 1.0f - f[1], gz = 1.0f - f[2];
+  d[0] = gy * gz * (v[1] - v[0]) + f[1] * gz * (v[3] - v[2]) + gy * f[2] * (v[5] - v[4]) + f[1] * f[2] * (v[7] - v[6]);
+  d[1] = gx * gz * (v[2] - v[0]) + f[0] * gz * (v[3] - v[1]) + gx * f[2] * (v[6] - v[4]) + f[0] * f[2] * (v[7] - v[5]);
+  d[2] = gx * gy * (v[4] - v[0]) + f[0] * gy * (v[5] - v[1]) + gx * f[1] * (v[6] - v[2]) + f[0] * f[1] * (v[7] - v[3]);
+}
+
+__device__ __forceinline__ float tri_weight(const float f[3], int k) {
+  return ((k & 1) ? f[0] : 1.0f - f[0]) * ((k & 2) ? f[1] : 1.0f - f[1]) * ((k & 4) ? f[2] : 1.0f - f[2]);
+}
+
+// Residual and Jacobian: with y_c = A_c x_h, g = sum_c tri_c y_c - x' and
+// J = sum_c tri_c M_c + (d/dx of the interpolant of y_c at fixed x_h).
 __device__ __forceinline__ void residual_jac(const float *__restrict__ A, const Grid &gr, const float x[3],
                                              const float xp[3], float g[3], float J[3][3]) {
   const Cell c = locate(gr, x);
-  g[0] = -xp[0];
-  g[1] = -xp[1];
-  g[2] = -xp[2];
+  float y[3][8];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -120,22 +134,24 @@ __device__ __forceinline__ void residual_jac(const float *__restrict__ A, const 
   for (int k = 0; k < 8; ++k) {
     const float4 *p = corner_ptr(A, gr, c, k);
     const float4 r[3] = {p[0], p[1], p[2]};
-    const float wx = (k & 1) ? c.f[0] : 1.0f - c.f[0];
-    const float wy = (k & 2) ? c.f[1] : 1.0f - c.f[1];
-    const float wz = (k & 4) ? c.f[2] : 1.0f - c.f[2];
-    const float sx = (k & 1) ? c.dp[0] : -c.dp[0];
-    const float sy = (k & 2) ? c.dp[1] : -c.dp[1];
-    const float sz = (k & 4) ? c.dp[2] : -c.dp[2];
-    const float t = wx * wy * wz;
-    const float dt[3] = {sx * wy * wz, wx * sy * wz, wx * wy * sz};
+    const float t = tri_weight(c.f, k);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const float y = r[i].x * x[0] + r[i].y * x[1] + r[i].z * x[2] + r[i].w;
-      g[i] += t * y;
-      J[i][0] += t * r[i].x + y * dt[0];
-      J[i][1] += t * r[i].y + y * dt[1];
-      J[i][2] += t * r[i].z + y * dt[2];
+      y[i][k] = r[i].x * x[0] + r[i].y * x[1] + r[i].z * x[2] + r[i].w;
+      J[i][0] += t * r[i].x;
+      J[i][1] += t * r[i].y;
+      J[i][2] += t * r[i].z;
     }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float d[3];
+    tri_grad(y[i], c.f, d);
+    g[i] = -xp[i];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g[i] += tri_weight(c.f, k) * y[i][k];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) J[i][j] += c.dp[j] * d[j];
   }
 }
 
@@ -263,6 +279,7 @@ __global__ void __launch_bounds__(kSolveBlock) solve_kernel(
 //   wave and entry); grad_W[c][b] -= tri_c v.y_b (atomics).
 // ------------------------------------------------------------------------
 constexpr int kBwdBlock = 256;
+constexpr int kMaxBonesBwd = 32;  // skinning weights of one sample kept in registers
 
 __global__ void __launch_bounds__(kBwdBlock) ift_kernel(
     const float *__restrict__ gxc, const float *__restrict__ xc_soa, const int16_t *__restrict__ bone, int64_t S,
@@ -278,33 +295,39 @@ __global__ void __launch_bounds__(kBwdBlock) ift_kernel(
   const int64_t n = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x;
   const bool act = n < S && bone[n] >= 0;
   float v[3] = {0.0f, 0.0f, 0.0f}, x[3] = {0.0f, 0.0f, 0.0f};
+  float wb[kMaxBonesBwd];
+  int64_t vtx[8];
   Cell c;
+#pragma unroll
+  for (int b = 0; b < kMaxBonesBwd; ++b) wb[b] = 0.0f;
   if (act) {
     x[0] = xc_soa[n];
     x[1] = xc_soa[ld + n];
     x[2] = xc_soa[2 * ld + n];
     c = locate(gr, x);
-    float J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int k = 0; k < 8; ++k) {
-      const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
-      const float wx = cx ? c.f[0] : 1.0f - c.f[0];
-      const float wy = cy ? c.f[1] : 1.0f - c.f[1];
-      const float wz = cz ? c.f[2] : 1.0f - c.f[2];
-      const float t = wx * wy * wz;
-      const float dt[3] = {(cx ? c.dp[0] : -c.dp[0]) * wy * wz, wx * (cy ? c.dp[1] : -c.dp[1]) * wz,
-                           wx * wy * (cz ? c.dp[2] : -c.dp[2])};
-      const int64_t vtx = ((int64_t)(c.i0[2] + cz) * gr.D[1] + (c.i0[1] + cy)) * gr.D[0] + (c.i0[0] + cx);
-      const float *Wv = W + vtx * nb;
-      for (int b = 0; b < nb; ++b) {
-        const float wv = Wv[b];
-        const float *Bb = sB + 12 * b;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const float y = Bb[4 * i] * x[0] + Bb[4 * i + 1] * x[1] + Bb[4 * i + 2] * x[2] + Bb[4 * i + 3];
-          J[i][0] += wv * (t * Bb[4 * i] + y * dt[0]);
-          J[i][1] += wv * (t * Bb[4 * i + 1] + y * dt[1]);
-          J[i][2] += wv * (t * Bb[4 * i + 2] + y * dt[2]);
-        }
+    for (int k = 0; k < 8; ++k)
+      vtx[k] = ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] +
+               (c.i0[0] + (k & 1));
+    // J = sum_b w_b M_b + sum_b y_b (grad w_b)^T, y_b = B_b x_h
+    float J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int b = 0; b < kMaxBonesBwd; ++b) {
+      if (b >= nb) break;
+      float cv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) cv[k] = W[vtx[k] * nb + b];
+      float w = 0.0f, d[3];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w += tri_weight(c.f, k) * cv[k];
+      tri_grad(cv, c.f, d);
+      wb[b] = w;
+      const float *Bb = sB + 12 * b;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float y = Bb[4 * i] * x[0] + Bb[4 * i + 1] * x[1] + Bb[4 * i + 2] * x[2] + Bb[4 * i + 3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) J[i][j] += w * Bb[4 * i + j] + y * (c.dp[j] * d[j]);
       }
     }
     // v = J^{-T} u  (J^{-T} = (J^{-1})^T)
@@ -320,41 +343,31 @@ __global__ void __launch_bounds__(kBwdBlock) ift_kernel(
     gxp[2 * ld + n] = v[2];
   }
   if (gW && act) {
-    for (int k = 0; k < 8; ++k) {
-      const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
-      const float t = (cx ? c.f[0] : 1.0f - c.f[0]) * (cy ? c.f[1] : 1.0f - c.f[1]) * (cz ? c.f[2] : 1.0f - c.f[2]);
-      const int64_t vtx = ((int64_t)(c.i0[2] + cz) * gr.D[1] + (c.i0[1] + cy)) * gr.D[0] + (c.i0[0] + cx);
-      float *g = gW + vtx * nb;
-      for (int b = 0; b < nb; ++b) {
-        const float *Bb = sB + 12 * b;
-        float vy = 0.0f;
+    float t[8];
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-          vy += v[i] * (Bb[4 * i] * x[0] + Bb[4 * i + 1] * x[1] + Bb[4 * i + 2] * x[2] + Bb[4 * i + 3]);
-        atomicAdd(g + b, -t * vy);
-      }
+    for (int k = 0; k < 8; ++k) t[k] = tri_weight(c.f, k);
+    for (int b = 0; b < nb; ++b) {
+      const float *Bb = sB + 12 * b;
+      float vy = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        vy += v[i] * (Bb[4 * i] * x[0] + Bb[4 * i + 1] * x[1] + Bb[4 * i + 2] * x[2] + Bb[4 * i + 3]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) atomicAdd(gW + vtx[k] * nb + b, -t[k] * vy);
     }
   }
   if (gB) {
-    // skinning weights at x* for the B gradient (zero for inactive lanes)
+    // wave-reduce -w_b v x_h^T, one LDS add per wave, one global add per block
     const int lane = threadIdx.x & (kWave - 1);
-    for (int b = 0; b < nb; ++b) {
-      float wb = 0.0f;
-      if (act) {
-        for (int k = 0; k < 8; ++k) {
-          const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
-          const float t =
-              (cx ? c.f[0] : 1.0f - c.f[0]) * (cy ? c.f[1] : 1.0f - c.f[1]) * (cz ? c.f[2] : 1.0f - c.f[2]);
-          const int64_t vtx = ((int64_t)(c.i0[2] + cz) * gr.D[1] + (c.i0[1] + cy)) * gr.D[0] + (c.i0[0] + cx);
-          wb += t * W[vtx * nb + b];
-        }
-      }
-      const float xh[4] = {x[0], x[1], x[2], 1.0f};
+    const float xh[4] = {x[0], x[1], x[2], 1.0f};
+#pragma unroll
+    for (int b = 0; b < kMaxBonesBwd; ++b) {
+      if (b >= nb) break;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float s = wave_sum(-wb * v[i] * xh[j]);
+          const float s = wave_sum(-wb[b] * v[i] * xh[j]);
           if (lane == 0) atomicAdd(&sGB[12 * b + 4 * i + j], s);
         }
     }
@@ -419,6 +432,7 @@ extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc,
                                           int32_t Dy, int32_t Dz, const float *skin_aabb, float *grad_xp,
                                           float *grad_B, float *grad_W, ia355_stream_t stream) {
   if (S < 0 || ld < S || nb <= 0 || nb > kMaxBones) return IA355_ERR_INVALID_ARG;
+  if (nb > kMaxBonesBwd) return IA355_ERR_UNSUPPORTED;
   if (!B || !W || !grid_ok(Dx, Dy, Dz, skin_aabb)) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_xc || !xc || !bone)) return IA355_ERR_INVALID_ARG;
   if (S == 0) return IA355_OK;

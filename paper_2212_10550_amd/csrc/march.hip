@@ -32,8 +32,8 @@ __device__ __forceinline__ RaySpan ray_span(const float o[3], const float d[3], 
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (d[a] != 0.0f) {
-      const float ta = __fdiv_rn(__fsub_rn(b.lo[a], o[a]), d[a]);
-      const float tb = __fdiv_rn(__fsub_rn(b.hi[a], o[a]), d[a]);
+      const float ta = (b.lo[a] - o[a]) / d[a];
+      const float tb = (b.hi[a] - o[a]) / d[a];
       const float t0 = ta < tb ? ta : tb;
       const float t1 = ta < tb ? tb : ta;
       if (t0 > tmin) tmin = t0;
@@ -46,7 +46,7 @@ __device__ __forceinline__ RaySpan ray_span(const float o[3], const float d[3], 
   if (!(tmax > tn)) return s;
   s.tn = tn;
   s.tf = tmax;
-  s.dt = n_per_ray > 0 ? __fdiv_rn(__fsub_rn(tmax, tn), (float)n_per_ray) : dt_fixed;
+  s.dt = n_per_ray > 0 ? (tmax - tn) / (float)n_per_ray : dt_fixed;
   s.hit = true;
   return s;
 }
@@ -55,13 +55,13 @@ __device__ __forceinline__ RaySpan ray_span(const float o[3], const float d[3], 
 __device__ __forceinline__ bool sample_at(const float o[3], const float d[3], const RaySpan &s, int k, const Box &b,
                                           const uint32_t *bits, int G, float *t_out, float x[3]) {
 #pragma clang fp contract(off)
-  const float t = __fadd_rn(s.tn, __fmul_rn(__fadd_rn((float)k, 0.5f), s.dt));
+  const float t = s.tn + ((float)k + 0.5f) * s.dt;
   *t_out = t;
   int cell[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    x[a] = __fadd_rn(o[a], __fmul_rn(t, d[a]));
-    const float u = __fmul_rn(__fdiv_rn(__fsub_rn(x[a], b.lo[a]), __fsub_rn(b.hi[a], b.lo[a])), (float)G);
+    x[a] = o[a] + t * d[a];
+    const float u = (x[a] - b.lo[a]) / (b.hi[a] - b.lo[a]) * (float)G;
     int c = (int)floorf(u);
     cell[a] = c < 0 ? 0 : (c > G - 1 ? G - 1 : c);
   }

@@ -505,9 +505,9 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_f32(const float *__restrict
 __global__ void reduce_partials(const float *__restrict__ partial, int nblk, float *__restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= NPARAM) return;
-  float acc = 0.0f;
-  for (int b = 0; b < nblk; ++b) acc += partial[(int64_t)b * NPARAM + e];
-  out[e] += acc;
+  double acc = 0.0;  // up to 512 partials: summed in double, in block order
+  for (int b = 0; b < nblk; ++b) acc += (double)partial[(int64_t)b * NPARAM + e];
+  out[e] += (float)acc;
 }
 
 constexpr int kMaxBwdBlocks = 512;

@@ -18,6 +18,36 @@ from . import lib as K
 NPARAM = 6532
 
 
+class StageTimer:
+    """HIP events on the launch stream around each named stage; ``mark(name)``
+    closes the open stage and opens ``name`` (None closes only).  Durations
+    are summed per stage after a synchronisation."""
+
+    def __init__(self):
+        self.events = []  # (name, start, end)
+        self._open = None
+
+    def mark(self, name):
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(torch.cuda.current_stream())
+        if self._open is not None:
+            self.events.append((self._open[0], self._open[1], ev))
+        self._open = (name, ev) if name is not None else None
+
+    def totals_ms(self):
+        torch.cuda.synchronize()
+        out = {}
+        for name, a, b in self.events:
+            out[name] = out.get(name, 0.0) + a.elapsed_time(b)
+        return out
+
+    def counts(self):
+        out = {}
+        for name, _, _ in self.events:
+            out[name] = out.get(name, 0) + 1
+        return out
+
+
 class Pipeline:
     def __init__(self, w, device="cuda", table_dtype=torch.float32, mlp_dtype=K.F32, cap=None,
                  grad_W=True, grad_B=True):
@@ -86,6 +116,11 @@ class Pipeline:
         self.grad_B = e(*self.B.shape) if grad_B else None
         self.grad_W = e(*self.W.shape) if grad_W else None
         self.S = None
+        self.timer = None  # optional StageTimer: HIP events around each stage
+
+    def _mark(self, name):
+        if self.timer is not None:
+            self.timer.mark(name)
 
     # ------------------------------------------------------------ forward
     def march(self):
@@ -103,18 +138,25 @@ class Pipeline:
 
     def field(self, S):
         w = self.w
+        self._mark("deform")
         K.snarf_deform(self.xs, S, self.cap, self.B, self.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop,
                        w.tol_valid, self.xc, self.bone, self.resid, self.steps, self.ws_deform)
         feat = self.feat[: w.L * S * 2]
+        self._mark("hash_fwd")
         K.hashgrid_encode(self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth, w.hash_aabb, feat)
+        self._mark("mlp_fwd")
         K.mlp_fwd(feat, self.bone, S, self.cap, self.params, self.mlp_dtype, self.sigma, self.rgb)
 
     def composite(self):
+        self._mark("render_fwd")
         K.volrender_fwd(self.sigma, self.rgb, self.cap, self.ray_off, self.ray_dt, self.R, self.w.T_thresh,
                         self.color, self.opacity, self.n_used, self.T_final)
+        self._mark(None)
 
     def forward(self):
+        self._mark("march")
         self.march()
+        self._mark(None)
         S = self.read_count()
         self.field(S)
         self.composite()
@@ -123,23 +165,28 @@ class Pipeline:
     # ----------------------------------------------------------- backward
     def backward(self, S):
         w = self.w
+        self._mark("loss+render_bwd")
         K.l2_loss(self.color, self.target, self.loss, self.grad_color)
         K.volrender_bwd(self.grad_color, None, self.sigma, self.rgb, self.cap, self.ray_off, self.ray_dt, self.n_used,
                         self.color, self.T_final, self.R, self.grad_sigma, self.grad_rgb)
+        self._mark("mlp_bwd")
         K.zero(self.grad_params)
         feat = self.feat[: w.L * S * 2]
         gfeat = self.grad_feat[: w.L * S * 2]
         K.mlp_bwd(self.grad_sigma, self.grad_rgb, feat, self.bone, S, self.cap, self.params, self.mlp_dtype,
                   self.grad_params, gfeat, self.ws_mlp)
+        self._mark("hash_bwd")
         K.zero(self.grad_table)
         K.hashgrid_encode_bwd(gfeat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth, w.hash_aabb,
                               self.grad_table, self.grad_xc)
+        self._mark("deform_bwd")
         if self.grad_B is not None:
             K.zero(self.grad_B)
         if self.grad_W is not None:
             K.zero(self.grad_W)
         K.snarf_deform_bwd(self.grad_xc, self.xc, self.bone, S, self.cap, self.B, self.W, w.skin_aabb, self.grad_xp,
                            self.grad_B, self.grad_W)
+        self._mark(None)
 
     def train_step(self):
         S = self.forward()

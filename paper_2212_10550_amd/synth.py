@@ -230,15 +230,18 @@ def make_hash_table(L: int, T: int, F: int, seed: int = 2, scale: float = 1e-4) 
     return rng.uniform(-scale, scale, size=(L, T, F))
 
 
-def make_mlp(widths=(32, 64, 64, 4), seed: int = 3, sigma_bias: float = 0.0) -> np.ndarray:
-    """He-normal weights N(0, 2/fan_in), zero biases (the density output bias
-    may be set).  Flat layout: for each layer W [out][in] row-major, then b [out]."""
+def make_mlp(widths=(32, 64, 64, 4), seed: int = 3, sigma_bias: float = 0.0, bias_std: float = 0.1) -> np.ndarray:
+    """Seeded Gaussian init: He-normal weights N(0, 2/fan_in) and biases
+    N(0, bias_std^2) (the density output bias is then set to sigma_bias).
+    Non-zero biases keep the hidden pre-activations away from the ReLU kink
+    when the hash features are tiny.  Flat layout: for each layer W [out][in]
+    row-major, then b [out]."""
     rng = np.random.default_rng(seed)
     parts = []
     for li in range(len(widths) - 1):
         fi, fo = widths[li], widths[li + 1]
         Wl = rng.normal(0.0, math.sqrt(2.0 / fi), size=(fo, fi))
-        bl = np.zeros(fo)
+        bl = rng.normal(0.0, bias_std, size=fo)
         if li == len(widths) - 2:
             bl[0] = sigma_bias
         parts += [Wl.ravel(), bl]

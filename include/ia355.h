@@ -43,6 +43,9 @@ extern "C" {
 #define IA355_ERR_UNSUPPORTED 3 /* valid but unimplemented combination */
 #define IA355_ERR_HIP 4         /* a HIP launch failed; see ia355_error_string */
 
+/* flags of the backward entry points */
+#define IA355_OVERWRITE 1u /* write the gradient instead of adding to it */
+
 #define IA355_F32 0
 #define IA355_F16 1
 #define IA355_BF16 2
@@ -120,14 +123,18 @@ int32_t ia355_snarf_deform(const float *xp, int64_t S, int64_t ld,
 
 /* Backward through the root finder by the implicit function theorem (no
  * unrolling of Broyden): with J = dg/dx at x* and v = J^{-T} grad_xc,
- *   grad_xp [3][ld] = v                            (overwritten, nullable)
- *   grad_B  [nb][3][4] += -sum_s w_b(x*) v x*_h^T   (accumulated, nullable)
- *   grad_W  [Dz][Dy][Dx][nb] += -tri_c(x*) v^T (B_b x*_h) (accumulated, nullable)
- * Samples with bone < 0 contribute nothing (grad_xp = 0). */
+ *   grad_xp [3][ld] = v                                  (overwritten, nullable)
+ *   grad_B  [nb][3][4]       += -sum_s w_b(x*) v x*_h^T  (nullable)
+ *   grad_W  [Dz][Dy][Dx][nb] += -tri_c(x*) v^T (B_b x*_h) (nullable)
+ * With IA355_OVERWRITE in flags grad_B / grad_W are written instead (every
+ * entry).  Samples with bone < 0 contribute nothing (grad_xp = 0).
+ * ws: ia355_deform_bwd_workspace_size(S, Dx, Dy, Dz, nb) bytes. */
+size_t ia355_deform_bwd_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz, int32_t nb);
 int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int16_t *bone, int64_t S, int64_t ld,
                                const float *B, int32_t nb, const float *W,
                                int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
-                               float *grad_xp, float *grad_B, float *grad_W, ia355_stream_t stream);
+                               float *grad_xp, float *grad_B, float *grad_W, uint32_t flags,
+                               void *ws, size_t ws_bytes, ia355_stream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Canonical field, Sec. 3.1 Eq. 1-2 (Instant-NGP encoding + MLP).      */
@@ -148,13 +155,17 @@ int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, i
                               void *feat, int32_t feat_dtype, ia355_stream_t stream);
 
 /* Backward of the encoding.  grad_feat [L][S][F] FP32.
- *   grad_table [L][T][F] FP32 accumulated (atomic adds; nullable)
+ *   grad_table [L][T][F] FP32 += sum over samples of w_c * grad_feat_l at each
+ *   corner (nullable); with IA355_OVERWRITE in flags it is written instead
+ *   (every entry, untouched ones set to 0).  Summation order inside a table
+ *   entry is not fixed (LDS atomics), so the last bits may vary run to run.
  *   grad_xc [3][ld] overwritten with sum_l sum_c (grad w_c)(theta_c . grad_feat_l)
  *   (nullable; needs the table). */
 int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone,
                                   int64_t S, int64_t ld, const void *table, int32_t table_dtype,
                                   int32_t L, int32_t F, int32_t log2T, double base_res, double growth,
-                                  const float *aabb, float *grad_table, float *grad_xc, ia355_stream_t stream);
+                                  const float *aabb, float *grad_table, float *grad_xc, uint32_t flags,
+                                  ia355_stream_t stream);
 
 /* The decoder MLP 32 -> 64 -> 64 -> 4 with ReLU hidden layers; outputs
  * sigma = exp(o_0) (clamped at exp(80)) and c = sigmoid(o_1..3).
@@ -168,14 +179,15 @@ int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int16_t *bone,
 
 /* Backward of the MLP (the forward is recomputed from feat; nothing is
  * saved).  grad_sigma [S], grad_rgb [3][ld] FP32.
- *   grad_params [6532] FP32 accumulated
+ *   grad_params [6532] FP32 accumulated (written with IA355_OVERWRITE)
  *   grad_feat [L][S][F] FP32 overwritten (nullable)
  * ws: ia355_mlp_bwd_workspace_size(S) bytes (per-block weight-gradient
  * partials, reduced in a fixed order: the result is deterministic). */
 size_t ia355_mlp_bwd_workspace_size(int64_t S);
 int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb, const void *feat, int32_t feat_dtype,
                       const int16_t *bone, int64_t S, int64_t ld, const float *params, int32_t dtype,
-                      float *grad_params, float *grad_feat, void *ws, size_t ws_bytes, ia355_stream_t stream);
+                      float *grad_params, float *grad_feat, uint32_t flags, void *ws, size_t ws_bytes,
+                      ia355_stream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Volume rendering, Sec. 3.2 Eq. 8 (alpha_i = 1 - exp(-sigma_i delta_i)) */

@@ -8,9 +8,10 @@
 //    the per-pose blended transform of vertex v.  A is a 12-float-per-vertex
 //    grid (3 x float4 per corner) built once per pose, which halves the
 //    gathered bytes and removes the 24-bone blend from every residual.
-//  * solve kernel: one thread per posed sample runs the nb Broyden solves in
-//    FP32 registers; bone inverses are staged in LDS once per block; the
-//    blended grid is read through the vector L1/L2 with float4 gathers.
+//  * solve kernel: eight lanes per posed sample each run a third of the nb
+//    Broyden solves in FP32 registers and pick the lowest residual with
+//    shuffles; bone inverses are staged in LDS once per block; the blended
+//    grid is read through the vector L1/L2 with float4 gathers.
 #include "common.h"
 
 using namespace ia355;
@@ -176,8 +177,72 @@ __device__ __forceinline__ float inv3(const float A[3][3], float Ai[3][3]) {
 __device__ __forceinline__ float norm3(const float v[3]) { return sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
 
 constexpr int kSolveBlock = 256;
+// kGroup lanes share one posed sample; lane j runs inits j, j + kGroup, ...
+// (3 of the 24 bones each), then the group selects the lowest residual by
+// shuffles.  Many more threads than samples keep the CUs busy at the
+// training-step sample counts (tens of thousands).
+constexpr int kGroup = 8;
 
-// One posed sample per thread; all nb inits run in sequence.
+struct InitResult {
+  float x[3];
+  float r;
+  bool ok;
+  int steps;
+};
+
+// One Broyden solve from bone init i.
+__device__ __forceinline__ InitResult broyden(const float *__restrict__ A, const Grid &gr, const float *Bi, bool bone_ok,
+                                             const float xp[3], int max_iter, float tol_stop) {
+  InitResult res;
+  float x[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) x[a] = Bi[4 * a] * xp[0] + Bi[4 * a + 1] * xp[1] + Bi[4 * a + 2] * xp[2] + Bi[4 * a + 3];
+  float g[3], J[3][3], H[3][3];
+  residual_jac(A, gr, x, xp, g, J);
+  const float detJ = inv3(J, H);
+  bool ok = bone_ok && fabsf(detJ) >= 1e-12f;
+  int k = 0;
+  if (ok) {
+    for (; k < max_iter; ++k) {
+      if (norm3(g) < tol_stop) break;
+      float dx[3], xn[3], gn[3], dg[3], Hdg[3], dxH[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dx[a] = -(H[a][0] * g[0] + H[a][1] * g[1] + H[a][2] * g[2]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xn[a] = x[a] + dx[a];
+      residual(A, gr, xn, xp, gn);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dg[a] = gn[a] - g[a];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) Hdg[a] = H[a][0] * dg[0] + H[a][1] * dg[1] + H[a][2] * dg[2];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) dxH[b] = dx[0] * H[0][b] + dx[1] * H[1][b] + dx[2] * H[2][b];
+      const float den = dx[0] * Hdg[0] + dx[1] * Hdg[1] + dx[2] * Hdg[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        x[a] = xn[a];
+        g[a] = gn[a];
+      }
+      if (fabsf(den) < 1e-30f) {
+        ok = false;
+        ++k;
+        break;
+      }
+      const float iden = 1.0f / den;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) H[a][b] += (dx[a] - Hdg[a]) * dxH[b] * iden;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) res.x[a] = x[a];
+  res.r = norm3(g);
+  res.ok = ok;
+  res.steps = k;
+  return res;
+}
+
 __global__ void __launch_bounds__(kSolveBlock) solve_kernel(
     const float *__restrict__ xp_soa, int64_t S, int64_t ld, const float *__restrict__ B, int nb,
     const float *__restrict__ A, Grid gr, Box hbox, int max_iter, float tol_stop, float tol_valid,
@@ -198,122 +263,108 @@ __global__ void __launch_bounds__(kSolveBlock) solve_kernel(
     }
   }
   __syncthreads();
-  const int64_t n = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
-  if (n >= S) return;
-  const float xp[3] = {xp_soa[n], xp_soa[ld + n], xp_soa[2 * ld + n]};
-  float best_r = INFINITY, best_x[3] = {0.0f, 0.0f, 0.0f};
-  int best = -1, steps = 0;
-  for (int i = 0; i < nb; ++i) {
-    const float *Bi = sBinv + 12 * i;
-    float x[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) x[a] = Bi[4 * a] * xp[0] + Bi[4 * a + 1] * xp[1] + Bi[4 * a + 2] * xp[2] + Bi[4 * a + 3];
-    float g[3], J[3][3], H[3][3];
-    residual_jac(A, gr, x, xp, g, J);
-    const float detJ = inv3(J, H);
-    bool ok = sBok[i] && fabsf(detJ) >= 1e-12f;
-    int k = 0;
-    if (ok) {
-      for (; k < max_iter; ++k) {
-        if (norm3(g) < tol_stop) break;
-        float dx[3], xn[3], gn[3], dg[3], Hdg[3], dxH[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) dx[a] = -(H[a][0] * g[0] + H[a][1] * g[1] + H[a][2] * g[2]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) xn[a] = x[a] + dx[a];
-        residual(A, gr, xn, xp, gn);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) dg[a] = gn[a] - g[a];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) Hdg[a] = H[a][0] * dg[0] + H[a][1] * dg[1] + H[a][2] * dg[2];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) dxH[b] = dx[0] * H[0][b] + dx[1] * H[1][b] + dx[2] * H[2][b];
-        const float den = dx[0] * Hdg[0] + dx[1] * Hdg[1] + dx[2] * Hdg[2];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          x[a] = xn[a];
-          g[a] = gn[a];
-        }
-        if (fabsf(den) < 1e-30f) {
-          ok = false;
-          ++k;
-          break;
-        }
-        const float iden = 1.0f / den;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) H[a][b] += (dx[a] - Hdg[a]) * dxH[b] * iden;
+  const int j = threadIdx.x % kGroup;
+  const int64_t n = ((int64_t)blockIdx.x * kSolveBlock + threadIdx.x) / kGroup;
+  const bool act = n < S;
+  float xp[3] = {0.0f, 0.0f, 0.0f};
+  if (act) {
+    xp[0] = xp_soa[n];
+    xp[1] = xp_soa[ld + n];
+    xp[2] = xp_soa[2 * ld + n];
+  }
+  // this lane's best valid init (lowest residual, then lowest index)
+  float best_r = INFINITY, best_x[3] = {0.0f, 0.0f, 0.0f}, x0[3] = {0.0f, 0.0f, 0.0f};
+  int best = 0x7fffffff, steps = 0;
+  if (act) {
+    for (int i = j; i < nb; i += kGroup) {
+      const InitResult q = broyden(A, gr, sBinv + 12 * i, sBok[i], xp, max_iter, tol_stop);
+      steps += q.steps;
+      if (i == 0) {
+        x0[0] = q.x[0];
+        x0[1] = q.x[1];
+        x0[2] = q.x[2];
+      }
+      const bool inside = q.x[0] >= hbox.lo[0] && q.x[0] <= hbox.hi[0] && q.x[1] >= hbox.lo[1] &&
+                          q.x[1] <= hbox.hi[1] && q.x[2] >= hbox.lo[2] && q.x[2] <= hbox.hi[2];
+      if (q.ok && q.r < tol_valid && inside && q.r < best_r) {
+        best_r = q.r;
+        best = i;
+        best_x[0] = q.x[0];
+        best_x[1] = q.x[1];
+        best_x[2] = q.x[2];
       }
     }
-    steps += k;
-    const float r = norm3(g);
-    if (i == 0) {
-      best_x[0] = x[0];
-      best_x[1] = x[1];
-      best_x[2] = x[2];
-    }
-    const bool inside = x[0] >= hbox.lo[0] && x[0] <= hbox.hi[0] && x[1] >= hbox.lo[1] && x[1] <= hbox.hi[1] &&
-                        x[2] >= hbox.lo[2] && x[2] <= hbox.hi[2];
-    if (ok && r < tol_valid && inside && r < best_r) {
-      best_r = r;
-      best = i;
-      best_x[0] = x[0];
-      best_x[1] = x[1];
-      best_x[2] = x[2];
+  }
+  // group reduction: (residual, init index) lexicographic minimum
+#pragma unroll
+  for (int o = kGroup / 2; o > 0; o >>= 1) {
+    const float r2 = __shfl_xor(best_r, o, kGroup);
+    const int b2 = __shfl_xor(best, o, kGroup);
+    const float x20 = __shfl_xor(best_x[0], o, kGroup);
+    const float x21 = __shfl_xor(best_x[1], o, kGroup);
+    const float x22 = __shfl_xor(best_x[2], o, kGroup);
+    steps += __shfl_xor(steps, o, kGroup);
+    if (r2 < best_r || (r2 == best_r && b2 < best)) {
+      best_r = r2;
+      best = b2;
+      best_x[0] = x20;
+      best_x[1] = x21;
+      best_x[2] = x22;
     }
   }
-  xc_soa[n] = best_x[0];
-  xc_soa[ld + n] = best_x[1];
-  xc_soa[2 * ld + n] = best_x[2];
-  bone_out[n] = (int16_t)best;
-  if (resid_out) resid_out[n] = best_r;
-  if (steps_out) steps_out[n] = (int16_t)steps;
+  // the start-of-group lane ran init 0: its final iterate stands for invalid samples
+  if (act && j == 0) {
+    const bool valid = best != 0x7fffffff;
+    xc_soa[n] = valid ? best_x[0] : x0[0];
+    xc_soa[ld + n] = valid ? best_x[1] : x0[1];
+    xc_soa[2 * ld + n] = valid ? best_x[2] : x0[2];
+    bone_out[n] = valid ? (int16_t)best : (int16_t)-1;
+    if (resid_out) resid_out[n] = valid ? best_r : INFINITY;
+    if (steps_out) steps_out[n] = (int16_t)steps;
+  }
 }
 
 // ------------------------------------------------------------------------
-// Backward (implicit function theorem).  One sample per thread:
-//   w_b, grad w_b from the skinning grid; J = sum_b w_b M_b + sum_b y_b grad w_b^T
-//   with y_b = B_b x*_h; v = J^{-T} u;
-//   grad_xp = v; grad_B_b -= w_b v x_h^T (wave-reduced, then one atomic per
-//   wave and entry); grad_W[c][b] -= tri_c v.y_b (atomics).
+// Backward (implicit function theorem), three kernels:
+//  ift_v: one thread per sample: J = sum_b w_b M_b + sum_b y_b grad w_b^T
+//         (y_b = B_b x*_h), v = J^{-T} dL/dx*; dL/dx' = v.
+//  ift_q: owner-computes over the skinning grid: workgroup q owns vertices
+//         [q*kOwnV, (q+1)*kOwnV) and accumulates, in LDS,
+//         Q_v = sum_s tri_v(x*_s) v_s x*_h,s^T   (3 x 4 per vertex)
+//         over every sample whose cell touches them.  Both parameter
+//         gradients are contractions of Q:
+//           dL/dW[v][b] = -sum_ij B_b[i][j] Q_v[i][j]
+//           dL/dB_b     = -sum_v W[v][b] Q_v
+//         so the workgroup writes its vertices' dL/dW rows directly and a
+//         partial of dL/dB -- no global atomics.
+//  ift_b: sums the dL/dB partials in a fixed order (double).
 // ------------------------------------------------------------------------
 constexpr int kBwdBlock = 256;
 constexpr int kMaxBonesBwd = 32;  // skinning weights of one sample kept in registers
+constexpr int kOwnV = 512;        // vertices per workgroup (x 12 floats = 24 KiB LDS)
+constexpr int kOwnBlock = 256;
 
-__global__ void __launch_bounds__(kBwdBlock) ift_kernel(
-    const float *__restrict__ gxc, const float *__restrict__ xc_soa, const int16_t *__restrict__ bone, int64_t S,
-    int64_t ld, const float *__restrict__ B, int nb, const float *__restrict__ W, Grid gr,
-    float *__restrict__ gxp, float *__restrict__ gB, float *__restrict__ gW) {
+__global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restrict__ gxc, const float *__restrict__ xc_soa,
+                                                        const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                        const float *__restrict__ B, int nb,
+                                                        const float *__restrict__ W, Grid gr,
+                                                        float *__restrict__ gxp, float *__restrict__ vbuf) {
   __shared__ float sB[kMaxBones * 12];
-  __shared__ float sGB[kMaxBones * 12];
-  for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) {
-    sB[i] = B[i];
-    sGB[i] = 0.0f;
-  }
+  for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) sB[i] = B[i];
   __syncthreads();
   const int64_t n = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x;
-  const bool act = n < S && bone[n] >= 0;
-  float v[3] = {0.0f, 0.0f, 0.0f}, x[3] = {0.0f, 0.0f, 0.0f};
-  float wb[kMaxBonesBwd];
-  int64_t vtx[8];
-  Cell c;
-#pragma unroll
-  for (int b = 0; b < kMaxBonesBwd; ++b) wb[b] = 0.0f;
-  if (act) {
-    x[0] = xc_soa[n];
-    x[1] = xc_soa[ld + n];
-    x[2] = xc_soa[2 * ld + n];
-    c = locate(gr, x);
+  if (n >= S) return;
+  float v[3] = {0.0f, 0.0f, 0.0f};
+  if (bone[n] >= 0) {
+    const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
+    const Cell c = locate(gr, x);
+    int64_t vtx[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       vtx[k] = ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] +
                (c.i0[0] + (k & 1));
-    // J = sum_b w_b M_b + sum_b y_b (grad w_b)^T, y_b = B_b x_h
     float J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-    for (int b = 0; b < kMaxBonesBwd; ++b) {
-      if (b >= nb) break;
+    for (int b = 0; b < nb; ++b) {
       float cv[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) cv[k] = W[vtx[k] * nb + b];
@@ -321,7 +372,6 @@ __global__ void __launch_bounds__(kBwdBlock) ift_kernel(
 #pragma unroll
       for (int k = 0; k < 8; ++k) w += tri_weight(c.f, k) * cv[k];
       tri_grad(cv, c.f, d);
-      wb[b] = w;
       const float *Bb = sB + 12 * b;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -330,50 +380,88 @@ __global__ void __launch_bounds__(kBwdBlock) ift_kernel(
         for (int j = 0; j < 3; ++j) J[i][j] += w * Bb[4 * i + j] + y * (c.dp[j] * d[j]);
       }
     }
-    // v = J^{-T} u  (J^{-T} = (J^{-1})^T)
     float Ji[3][3];
     inv3(J, Ji);
     const float u[3] = {gxc[n], gxc[ld + n], gxc[2 * ld + n]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[a] = Ji[0][a] * u[0] + Ji[1][a] * u[1] + Ji[2][a] * u[2];
   }
-  if (n < S && gxp) {
+  if (gxp) {
     gxp[n] = v[0];
     gxp[ld + n] = v[1];
     gxp[2 * ld + n] = v[2];
   }
-  if (gW && act) {
-    float t[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) t[k] = tri_weight(c.f, k);
-    for (int b = 0; b < nb; ++b) {
-      const float *Bb = sB + 12 * b;
-      float vy = 0.0f;
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-        vy += v[i] * (Bb[4 * i] * x[0] + Bb[4 * i + 1] * x[1] + Bb[4 * i + 2] * x[2] + Bb[4 * i + 3]);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) atomicAdd(gW + vtx[k] * nb + b, -t[k] * vy);
-    }
-  }
-  if (gB) {
-    // wave-reduce -w_b v x_h^T, one LDS add per wave, one global add per block
-    const int lane = threadIdx.x & (kWave - 1);
+  vbuf[n] = v[0];
+  vbuf[S + n] = v[1];
+  vbuf[2 * S + n] = v[2];
+}
+
+__global__ void __launch_bounds__(kOwnBlock) ift_q_kernel(const float *__restrict__ xc_soa,
+                                                        const int16_t *__restrict__ bone, const float *__restrict__ vbuf,
+                                                        int64_t S, int64_t ld, const float *__restrict__ B, int nb,
+                                                        const float *__restrict__ W, Grid gr, int64_t nvert,
+                                                        float *__restrict__ gW, float *__restrict__ partB,
+                                                        int overwrite) {
+  __shared__ float Q[kOwnV * 12];
+  __shared__ float sB[kMaxBones * 12];
+  for (int i = threadIdx.x; i < kOwnV * 12; i += kOwnBlock) Q[i] = 0.0f;
+  for (int i = threadIdx.x; i < nb * 12; i += kOwnBlock) sB[i] = B[i];
+  __syncthreads();
+  const int64_t v0 = (int64_t)blockIdx.x * kOwnV;
+  const int64_t plane = (int64_t)gr.D[0] * gr.D[1];
+  const int64_t z_lo = v0 / plane, z_hi = (v0 + kOwnV - 1) / plane;
+  for (int64_t n = threadIdx.x; n < S; n += kOwnBlock) {
+    if (bone[n] < 0) continue;
+    const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
+    const Cell c = locate(gr, x);
+    if (c.i0[2] + 1 < z_lo || c.i0[2] > z_hi) continue;
+    const float v[3] = {vbuf[n], vbuf[S + n], vbuf[2 * S + n]};
     const float xh[4] = {x[0], x[1], x[2], 1.0f};
 #pragma unroll
-    for (int b = 0; b < kMaxBonesBwd; ++b) {
-      if (b >= nb) break;
+    for (int k = 0; k < 8; ++k) {
+      const int64_t e = ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] +
+                        (c.i0[0] + (k & 1)) - v0;
+      if (e >= 0 && e < kOwnV) {
+        const float t = tri_weight(c.f, k);
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float s = wave_sum(-wb[b] * v[i] * xh[j]);
-          if (lane == 0) atomicAdd(&sGB[12 * b + 4 * i + j], s);
-        }
+          for (int j = 0; j < 4; ++j) atomicAdd(&Q[12 * e + 4 * i + j], t * v[i] * xh[j]);
+      }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) atomicAdd(gB + i, sGB[i]);
   }
+  __syncthreads();
+  const int64_t nv = min((int64_t)kOwnV, nvert - v0);
+  // dL/dW rows of the owned vertices
+  for (int64_t e = threadIdx.x; e < nv; e += kOwnBlock) {
+    const float *q = Q + 12 * e;
+    float *out = gW ? gW + (v0 + e) * nb : nullptr;
+    if (!out) break;
+    for (int b = 0; b < nb; ++b) {
+      const float *Bb = sB + 12 * b;
+      float s = 0.0f;
+#pragma unroll
+      for (int m = 0; m < 12; ++m) s += Bb[m] * q[m];
+      out[b] = overwrite ? -s : out[b] - s;
+    }
+  }
+  // partial of dL/dB: one (bone, entry) pair per thread
+  if (partB) {
+    for (int p = threadIdx.x; p < nb * 12; p += kOwnBlock) {
+      const int b = p / 12, m = p % 12;
+      float s = 0.0f;
+      for (int64_t e = 0; e < nv; ++e) s += W[(v0 + e) * nb + b] * Q[12 * e + m];
+      partB[(int64_t)blockIdx.x * nb * 12 + p] = s;
+    }
+  }
+}
+
+__global__ void ift_b_kernel(const float *__restrict__ partB, int nblk, int n, float *__restrict__ gB, int overwrite) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double s = 0.0;
+  for (int q = 0; q < nblk; ++q) s += (double)partB[(int64_t)q * n + p];
+  gB[p] = overwrite ? (float)(-s) : gB[p] - (float)s;
 }
 
 Grid make_grid(int Dx, int Dy, int Dz, const float *aabb) {
@@ -422,22 +510,41 @@ extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, int64_t ld, co
     hb.lo[a] = hash_aabb[a];
     hb.hi[a] = hash_aabb[3 + a];
   }
-  solve_kernel<<<(unsigned)ceil_div(S, kSolveBlock), kSolveBlock, 0, s>>>(xp, S, ld, B, nb, A, g, hb, max_iter,
+  solve_kernel<<<(unsigned)ceil_div(S * kGroup, kSolveBlock), kSolveBlock, 0, s>>>(xp, S, ld, B, nb, A, g, hb, max_iter,
                                                                          tol_stop, tol_valid, xc, bone, resid, steps);
   return launch_status();
+}
+
+extern "C" size_t ia355_deform_bwd_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz, int32_t nb) {
+  if (S < 0 || Dx <= 0 || Dy <= 0 || Dz <= 0 || nb <= 0) return 0;
+  const int64_t nvert = (int64_t)Dx * Dy * Dz;
+  return align256(sizeof(float) * 3 * (size_t)S) + align256(sizeof(float) * 12 * (size_t)nb * ceil_div(nvert, kOwnV));
 }
 
 extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int16_t *bone, int64_t S,
                                           int64_t ld, const float *B, int32_t nb, const float *W, int32_t Dx,
                                           int32_t Dy, int32_t Dz, const float *skin_aabb, float *grad_xp,
-                                          float *grad_B, float *grad_W, ia355_stream_t stream) {
+                                          float *grad_B, float *grad_W, uint32_t flags, void *ws, size_t ws_bytes,
+                                          ia355_stream_t stream) {
   if (S < 0 || ld < S || nb <= 0 || nb > kMaxBones) return IA355_ERR_INVALID_ARG;
-  if (nb > kMaxBonesBwd) return IA355_ERR_UNSUPPORTED;
   if (!B || !W || !grid_ok(Dx, Dy, Dz, skin_aabb)) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_xc || !xc || !bone)) return IA355_ERR_INVALID_ARG;
-  if (S == 0) return IA355_OK;
+  if (flags & ~(uint32_t)IA355_OVERWRITE) return IA355_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < ia355_deform_bwd_workspace_size(S, Dx, Dy, Dz, nb)) return IA355_ERR_WORKSPACE;
+  const int overwrite = (flags & IA355_OVERWRITE) != 0;
   const Grid g = make_grid(Dx, Dy, Dz, skin_aabb);
-  ift_kernel<<<(unsigned)ceil_div(S, kBwdBlock), kBwdBlock, 0, as_stream(stream)>>>(grad_xc, xc, bone, S, ld, B, nb,
-                                                                                    W, g, grad_xp, grad_B, grad_W);
+  hipStream_t s = as_stream(stream);
+  const int64_t nvert = (int64_t)Dx * Dy * Dz;
+  const int nq = (int)ceil_div(nvert, kOwnV);
+  float *vbuf = (float *)ws;
+  float *partB = (float *)((char *)ws + align256(sizeof(float) * 3 * (size_t)S));
+  if (S > 0)
+    ift_v_kernel<<<(unsigned)ceil_div(S, kBwdBlock), kBwdBlock, 0, s>>>(grad_xc, xc, bone, S, ld, B, nb, W, g,
+                                                                        grad_xp, vbuf);
+  if (grad_W || grad_B) {
+    ift_q_kernel<<<(unsigned)nq, kOwnBlock, 0, s>>>(xc, bone, vbuf, S, ld, B, nb, W, g, nvert, grad_W,
+                                                    grad_B ? partB : nullptr, overwrite);
+    if (grad_B) ift_b_kernel<<<(unsigned)ceil_div(nb * 12, 256), 256, 0, s>>>(partB, nq, nb * 12, grad_B, overwrite);
+  }
   return launch_status();
 }

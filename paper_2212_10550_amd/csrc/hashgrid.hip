@@ -12,9 +12,10 @@
 //    relative precision even at N_l ~ 2000;
 //  * features are written level-major [L][S][F]: each block writes one
 //    contiguous run (coalesced 8-byte / 4-byte stores per lane).
-// Backward: one wave covers 4 samples x 16 levels (lane = level + 16 *
-// sample); table gradients are FP32 atomic adds, the position gradient is
-// reduced across the 16 level lanes with shuffles (deterministic).
+// Backward: the table gradient is accumulated owner-computes in LDS (one
+// workgroup per level slab, see table_grad_kernel); the position gradient
+// runs one wave per 4 samples x 16 levels (lane = level + 16 * sample) and
+// is reduced across the 16 level lanes with shuffles (deterministic).
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -187,6 +188,60 @@ __global__ void __launch_bounds__(kBwdBlock) encode_bwd_kernel(
   }
 }
 
+// Table gradient, owner-computes: workgroup (level l, slab q) owns table
+// entries [q*kSlab, (q+1)*kSlab) of level l.  It walks every sample, finds
+// the level-l corners that fall in its slab and adds w_c * dL/dfeat_l into an
+// LDS copy of the slab (LDS atomics), then writes the slab to grad_table once
+// (plain loads/stores: no other workgroup touches those entries).  This
+// replaces 16 x 8 x 2 global atomics per sample, whose throughput and
+// same-address contention on the coarse levels dominate otherwise.  Slabs
+// beyond a dense level's (N+1)^3 entries only write (overwrite mode).
+constexpr int kSlab = 8192;  // entries; x 2 floats = 64 KiB of LDS
+constexpr int kOwnBlock = 512;
+
+__global__ void __launch_bounds__(kOwnBlock) table_grad_kernel(const float *__restrict__ gfeat,
+                                                             const float *__restrict__ xc,
+                                                             const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                             int log2T, Levels lv, Box box, float *__restrict__ gtable,
+                                                             int slabs, int overwrite) {
+  __shared__ float acc[2 * kSlab];
+  const int level = blockIdx.x / slabs;
+  const uint32_t e0 = (uint32_t)(blockIdx.x % slabs) * kSlab;
+  const uint32_t T = 1u << log2T;
+  const uint32_t e1 = min(e0 + (uint32_t)kSlab, T);
+  const int N = lv.res[level];
+  const bool dense = lv.dense[level];
+  const uint64_t side = (uint64_t)N + 1;
+  const uint64_t used = dense ? side * side * side : (uint64_t)T;
+  for (int i = threadIdx.x; i < 2 * kSlab; i += kOwnBlock) acc[i] = 0.0f;
+  __syncthreads();
+  if ((uint64_t)e0 < used) {
+    const float2 *g2 = reinterpret_cast<const float2 *>(gfeat) + (int64_t)level * S;
+    for (int64_t n = threadIdx.x; n < S; n += kOwnBlock) {
+      if (bone && bone[n] < 0) continue;
+      const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
+      Corners c;
+      level_cell(x, box, N, dense, T - 1u, c, false);
+      const float2 g = g2[n];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t e = c.idx[k] - e0;
+        if (e < (uint32_t)kSlab) {
+          atomicAdd(&acc[2 * e], c.w[k] * g.x);
+          atomicAdd(&acc[2 * e + 1], c.w[k] * g.y);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  float *out = gtable + ((int64_t)level * T + e0) * 2;
+  const int cnt = 2 * (int)(e1 - e0);
+  if (overwrite)
+    for (int i = threadIdx.x; i < cnt; i += kOwnBlock) out[i] = acc[i];
+  else
+    for (int i = threadIdx.x; i < cnt; i += kOwnBlock) out[i] += acc[i];
+}
+
 int32_t make_levels(int L, int log2T, double base, double growth, Levels *lv) {
   const uint64_t T = 1ull << log2T;
   for (int l = 0; l < L; ++l) {
@@ -247,22 +302,32 @@ extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, i
 extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone, int64_t S,
                                              int64_t ld, const void *table, int32_t table_dtype, int32_t L, int32_t F,
                                              int32_t log2T, double base_res, double growth, const float *aabb,
-                                             float *grad_table, float *grad_xc, ia355_stream_t stream) {
+                                             float *grad_table, float *grad_xc, uint32_t flags, ia355_stream_t stream) {
   if (S < 0 || ld < S || L <= 0 || L > 16 || F != 2 || log2T < 1 || log2T > 30) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_feat || !xc)) return IA355_ERR_INVALID_ARG;
   if (grad_xc && !table) return IA355_ERR_INVALID_ARG;
   if (table_dtype != IA355_F32 && table_dtype != IA355_F16) return IA355_ERR_INVALID_ARG;
+  if (flags & ~(uint32_t)IA355_OVERWRITE) return IA355_ERR_INVALID_ARG;
   Levels lv;
   Box box;
   if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
-  if (S == 0 || (!grad_table && !grad_xc)) return IA355_OK;
-  const int64_t blocks = ceil_div(S * 16, kBwdBlock);
   hipStream_t s = as_stream(stream);
-  if (table_dtype == IA355_F32)
-    encode_bwd_kernel<float><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, ld, (const float *)table,
-                                                                    L, log2T, lv, box, grad_table, grad_xc);
-  else
-    encode_bwd_kernel<__half><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, ld, (const __half *)table,
-                                                                     L, log2T, lv, box, grad_table, grad_xc);
+  const int overwrite = (flags & IA355_OVERWRITE) != 0;
+  if (grad_table && (S > 0 || overwrite)) {
+    const int slabs = (int)ceil_div((int64_t)1 << log2T, kSlab);
+    table_grad_kernel<<<(unsigned)(slabs * L), kOwnBlock, 0, s>>>(grad_feat, xc, bone, S, ld, log2T, lv, box,
+                                                                  grad_table, slabs, overwrite);
+  }
+  if (grad_xc && S > 0) {
+    const int64_t blocks = ceil_div(S * 16, kBwdBlock);
+    if (table_dtype == IA355_F32)
+      encode_bwd_kernel<float><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, ld,
+                                                                      (const float *)table, L, log2T, lv, box, nullptr,
+                                                                      grad_xc);
+    else
+      encode_bwd_kernel<__half><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, ld,
+                                                                       (const __half *)table, L, log2T, lv, box,
+                                                                       nullptr, grad_xc);
+  }
   return launch_status();
 }

@@ -1,10 +1,12 @@
 // Ray marching with empty-space skipping (Sec. 3.2 ray sampling, Sec. 3.3
 // occupancy-grid skipping), as a three-kernel stream compaction:
-//   count  -- one thread per ray walks its midpoint samples, counts the ones
-//             in occupied cells and writes its block-local exclusive offset;
+//   count  -- one wave per ray, one lane per midpoint sample: a ballot of
+//             the samples in occupied cells gives the ray's count;
 //   scan   -- one block turns the per-block totals into global offsets;
-//   fill   -- one thread per ray walks again and writes its kept samples
-//             at its global offset (structure-of-arrays, coalesced per row).
+//   fill   -- one wave per ray again; each kept sample's slot is the ray's
+//             offset plus the popcount of kept lanes below it, so a ray's
+//             samples are written in t order by consecutive lanes
+//             (structure-of-arrays, coalesced).
 // Every position and keep/skip decision is computed with individually
 // rounded IEEE single operations (contraction is switched off: the
 // compiler would otherwise fuse o + t d into one FMA), so the sample set is
@@ -70,39 +72,62 @@ __device__ __forceinline__ bool sample_at(const float o[3], const float d[3], co
   return (bits[idx >> 5] >> (idx & 31)) & 1u;
 }
 
-constexpr int kBlock = 256;
+// One wave per ray: lane l handles steps k = l, l + 64, ... of its ray, so a
+// 128-step ray is two ballots.  kRays rays per workgroup.
+constexpr int kRays = 4;
+constexpr int kBlock = kRays * kWave;
+
+__device__ __forceinline__ void load_ray(const float *ro, const float *rd, int64_t r, float o[3], float d[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    o[a] = ro[3 * r + a];
+    d[a] = rd[3 * r + a];
+  }
+}
 
 __global__ void __launch_bounds__(kBlock) march_count(const float *ro, const float *rd, int64_t R,
                                                       const uint32_t *bits, int G, Box box, float dt_fixed,
                                                       int n_per_ray, int max_steps, int64_t *ray_off,
                                                       int32_t *ray_cnt, float *ray_dt, int64_t *block_sum) {
-  __shared__ int wsum[kBlock / kWave];
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  __shared__ int cnts[kRays];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t r = (int64_t)blockIdx.x * kRays + wid;
   int cnt = 0;
   if (r < R) {
-    const float o[3] = {ro[3 * r], ro[3 * r + 1], ro[3 * r + 2]};
-    const float d[3] = {rd[3 * r], rd[3 * r + 1], rd[3 * r + 2]};
+    float o[3], d[3];
+    load_ray(ro, rd, r, o, d);
     const RaySpan s = ray_span(o, d, box, dt_fixed, n_per_ray);
     if (s.hit) {
-      for (int k = 0; k < max_steps; ++k) {
-        float t, x[3];
-        const bool keep = sample_at(o, d, s, k, box, bits, G, &t, x);
-        if (!(t < s.tf)) break;
-        cnt += keep;
+      for (int k0 = 0; k0 < max_steps; k0 += kWave) {
+        const int k = k0 + lane;
+        float t = 0.0f, x[3];
+        bool keep = false, inside = false;
+        if (k < max_steps) {
+          keep = sample_at(o, d, s, k, box, bits, G, &t, x);
+          inside = t < s.tf;
+          keep = keep && inside;
+        }
+        cnt += __popcll(__ballot(keep));
+        // t grows with k: once the last lane is beyond t_far, so is every later step
+        if (!__shfl((int)inside, kWave - 1, kWave)) break;
       }
     }
-    ray_cnt[r] = cnt;
-    ray_dt[r] = s.dt;
+    if (lane == 0) {
+      ray_cnt[r] = cnt;
+      ray_dt[r] = s.dt;
+    }
   }
-  // block-local exclusive scan of the counts
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int incl = wave_incl_scan(cnt);
-  if (lane == kWave - 1) wsum[wid] = incl;
+  if (lane == 0) cnts[wid] = cnt;
   __syncthreads();
-  int base = 0;
-  for (int i = 0; i < wid; ++i) base += wsum[i];
-  if (r < R) ray_off[r] = base + incl - cnt;
-  if (threadIdx.x == kBlock - 1) block_sum[blockIdx.x] = base + incl;
+  if (threadIdx.x == 0) {
+    int64_t acc = 0;
+    for (int i = 0; i < kRays; ++i) {
+      const int64_t ri = (int64_t)blockIdx.x * kRays + i;
+      if (ri < R) ray_off[ri] = acc;
+      acc += cnts[i];
+    }
+    block_sum[blockIdx.x] = acc;
+  }
 }
 
 // Exclusive scan of the per-block totals in one block (in place), total to
@@ -143,35 +168,47 @@ __global__ void __launch_bounds__(kBlock) march_fill(const float *ro, const floa
                                                      const int64_t *block_off, int64_t *ray_off,
                                                      const float *ray_dt, float *xs, float *ts, int32_t *ray_id,
                                                      int64_t cap) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t r = (int64_t)blockIdx.x * kRays + wid;
   if (r >= R) return;
   int64_t off = ray_off[r] + block_off[blockIdx.x];
-  ray_off[r] = off;
-  const float o[3] = {ro[3 * r], ro[3 * r + 1], ro[3 * r + 2]};
-  const float d[3] = {rd[3 * r], rd[3 * r + 1], rd[3 * r + 2]};
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) ray_off[r] = off;
+  float o[3], d[3];
+  load_ray(ro, rd, r, o, d);
   RaySpan s = ray_span(o, d, box, ray_dt[r], 0);
   if (!s.hit) return;
   s.dt = ray_dt[r];
-  for (int k = 0; k < max_steps; ++k) {
-    float t, x[3];
-    const bool keep = sample_at(o, d, s, k, box, bits, G, &t, x);
-    if (!(t < s.tf)) break;
-    if (!keep) continue;
-    if (off < cap) {
-      xs[off] = x[0];
-      xs[cap + off] = x[1];
-      xs[2 * cap + off] = x[2];
-      ts[off] = t;
-      ray_id[off] = (int32_t)r;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  for (int k0 = 0; k0 < max_steps; k0 += kWave) {
+    const int k = k0 + lane;
+    float t = 0.0f, x[3];
+    bool keep = false, inside = false;
+    if (k < max_steps) {
+      keep = sample_at(o, d, s, k, box, bits, G, &t, x);
+      inside = t < s.tf;
+      keep = keep && inside;
     }
-    ++off;
+    const uint64_t m = __ballot(keep);
+    if (keep) {
+      const int64_t at = off + __popcll(m & below);
+      if (at < cap) {
+        xs[at] = x[0];
+        xs[cap + at] = x[1];
+        xs[2 * cap + at] = x[2];
+        ts[at] = t;
+        ray_id[at] = (int32_t)r;
+      }
+    }
+    off += __popcll(m);
+    if (!__shfl((int)inside, kWave - 1, kWave)) break;
   }
 }
 
 }  // namespace
 
 extern "C" size_t ia355_march_workspace_size(int64_t R) {
-  return align256(sizeof(int64_t) * (size_t)(ceil_div(R > 0 ? R : 1, kBlock)));
+  return align256(sizeof(int64_t) * (size_t)(ceil_div(R > 0 ? R : 1, kRays)));
 }
 
 extern "C" int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d, int64_t R, const uint32_t *occ_bits,
@@ -195,7 +232,7 @@ extern "C" int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d,
   }
   hipStream_t s = as_stream(stream);
   int64_t *block_sum = (int64_t *)ws;
-  const int64_t nblk = ceil_div(R, kBlock);
+  const int64_t nblk = ceil_div(R, kRays);
   if (R > 0)
     march_count<<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray, max_steps,
                                                   ray_off, ray_cnt, ray_dt, block_sum);

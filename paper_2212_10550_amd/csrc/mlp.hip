@@ -502,12 +502,34 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_f32(const float *__restrict
   for (int e = threadIdx.x; e < NPARAM; e += kBwdBlock) partial[(int64_t)blockIdx.x * NPARAM + e] = bp[e];
 }
 
-__global__ void reduce_partials(const float *__restrict__ partial, int nblk, float *__restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= NPARAM) return;
-  double acc = 0.0;  // up to 512 partials: summed in double, in block order
-  for (int b = 0; b < nblk; ++b) acc += (double)partial[(int64_t)b * NPARAM + e];
-  out[e] += (float)acc;
+// Sum of the block partials per parameter: 64 parameters x 16 partial groups
+// per workgroup; each thread sums its group in double with four independent
+// accumulators, then the 16 groups are combined in a fixed order (the
+// result does not depend on scheduling).
+constexpr int kRedP = 64, kRedG = 16;
+__global__ void __launch_bounds__(kRedP *kRedG) reduce_partials(const float *__restrict__ partial, int nblk,
+                                                                float *__restrict__ out, int overwrite) {
+  __shared__ double part[kRedG][kRedP];
+  const int pl = threadIdx.x % kRedP, grp = threadIdx.x / kRedP;
+  const int e = blockIdx.x * kRedP + pl;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (e < NPARAM) {
+    int b = grp;
+    for (; b + 3 * kRedG < nblk; b += 4 * kRedG) {
+      a0 += (double)partial[(int64_t)b * NPARAM + e];
+      a1 += (double)partial[(int64_t)(b + kRedG) * NPARAM + e];
+      a2 += (double)partial[(int64_t)(b + 2 * kRedG) * NPARAM + e];
+      a3 += (double)partial[(int64_t)(b + 3 * kRedG) * NPARAM + e];
+    }
+    for (; b < nblk; b += kRedG) a0 += (double)partial[(int64_t)b * NPARAM + e];
+  }
+  part[grp][pl] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (grp == 0 && e < NPARAM) {
+    double s = 0.0;
+    for (int g = 0; g < kRedG; ++g) s += part[g][pl];
+    out[e] = overwrite ? (float)s : out[e] + (float)s;
+  }
 }
 
 constexpr int kMaxBwdBlocks = 512;
@@ -544,17 +566,19 @@ extern "C" size_t ia355_mlp_bwd_workspace_size(int64_t S) {
 
 extern "C" int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb, const void *feat, int32_t feat_dtype,
                                  const int16_t *bone, int64_t S, int64_t ld, const float *params, int32_t dtype,
-                                 float *grad_params, float *grad_feat, void *ws, size_t ws_bytes,
+                                 float *grad_params, float *grad_feat, uint32_t flags, void *ws, size_t ws_bytes,
                                  ia355_stream_t stream) {
   if (S < 0 || ld < S || !params || !grad_params) return IA355_ERR_INVALID_ARG;
+  if (flags & ~(uint32_t)IA355_OVERWRITE) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_sigma || !grad_rgb || !feat)) return IA355_ERR_INVALID_ARG;
   if (dtype != IA355_F32 || feat_dtype != IA355_F32) return IA355_ERR_UNSUPPORTED;
-  if (S == 0) return IA355_OK;
+  if (S == 0) return (flags & IA355_OVERWRITE) ? ia355_zero(grad_params, sizeof(float) * NPARAM, stream) : IA355_OK;
   if (!ws || ws_bytes < ia355_mlp_bwd_workspace_size(S)) return IA355_ERR_WORKSPACE;
   hipStream_t s = as_stream(stream);
   const int nb = bwd_blocks(S);
   mlp_bwd_f32<<<nb, kBwdBlock, LDS_FLOATS * sizeof(float), s>>>(grad_sigma, grad_rgb, (const float *)feat, bone, S, ld,
                                                                 params, grad_feat, (float *)ws);
-  reduce_partials<<<(unsigned)ceil_div(NPARAM, 256), 256, 0, s>>>((const float *)ws, nb, grad_params);
+  reduce_partials<<<(unsigned)ceil_div(NPARAM, kRedP), kRedP * kRedG, 0, s>>>((const float *)ws, nb, grad_params,
+                                                                                     (flags & IA355_OVERWRITE) != 0);
   return launch_status();
 }

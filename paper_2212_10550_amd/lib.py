@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libia355.so")
 
 F32, F16, BF16 = 0, 1, 2
+OVERWRITE = 1  # backward flag: write gradients instead of adding to them
 _DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 
 _vp = ctypes.c_void_p
@@ -39,14 +40,15 @@ _SIGS = {
     "deform_workspace_size": (_sz, [_i32, _i32, _i32]),
     "snarf_deform": (_i32, [_vp, _i64, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _vp, _vp,
                             _vp, _vp, _sz, _vp]),
+    "deform_bwd_workspace_size": (_sz, [_i64, _i32, _i32, _i32, _i32]),
     "snarf_deform_bwd": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _vp, _vp, _vp,
-                                _vp]),
+                                ctypes.c_uint32, _vp, _sz, _vp]),
     "hashgrid_encode": (_i32, [_vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _i32, _vp]),
     "hashgrid_encode_bwd": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _vp,
-                                   _vp]),
+                                   ctypes.c_uint32, _vp]),
     "mlp_fwd": (_i32, [_vp, _i32, _vp, _i64, _i64, _vp, _i32, _vp, _vp, _vp]),
     "mlp_bwd_workspace_size": (_sz, [_i64]),
-    "mlp_bwd": (_i32, [_vp, _vp, _vp, _i32, _vp, _i64, _i64, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "mlp_bwd": (_i32, [_vp, _vp, _vp, _i32, _vp, _i64, _i64, _vp, _i32, _vp, _vp, ctypes.c_uint32, _vp, _sz, _vp]),
     "volrender_fwd": (_i32, [_vp, _vp, _i64, _vp, _vp, _i64, _f, _vp, _vp, _vp, _vp, _vp]),
     "volrender_bwd": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "l2_loss": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
@@ -141,13 +143,18 @@ def snarf_deform(xp, S, ld, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_
         _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "snarf_deform")
 
 
-def snarf_deform_bwd(grad_xc, xc, bone, S, ld, B, W, skin_aabb, grad_xp, grad_B, grad_W):
+def deform_bwd_workspace_size(S, Dx, Dy, Dz, nb):
+    return lib().ia355_deform_bwd_workspace_size(S, Dx, Dy, Dz, nb)
+
+
+def snarf_deform_bwd(grad_xc, xc, bone, S, ld, B, W, skin_aabb, grad_xp, grad_B, grad_W, ws, flags=0):
     Dz, Dy, Dx, nb = W.shape
     _check(lib().ia355_snarf_deform_bwd(
         _p(grad_xc, torch.float32, "grad_xc"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S, ld,
         _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"), Dx, Dy, Dz, _box(skin_aabb),
         _p(grad_xp, torch.float32, "grad_xp"), _p(grad_B, torch.float32, "grad_B"),
-        _p(grad_W, torch.float32, "grad_W"), _stream()), "snarf_deform_bwd")
+        _p(grad_W, torch.float32, "grad_W"), flags, _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()),
+        "snarf_deform_bwd")
 
 
 def hashgrid_encode(xc, bone, S, ld, table, base_res, growth, aabb, feat):
@@ -158,12 +165,12 @@ def hashgrid_encode(xc, bone, S, ld, table, base_res, growth, aabb, feat):
         "hashgrid_encode")
 
 
-def hashgrid_encode_bwd(grad_feat, xc, bone, S, ld, table, base_res, growth, aabb, grad_table, grad_xc):
+def hashgrid_encode_bwd(grad_feat, xc, bone, S, ld, table, base_res, growth, aabb, grad_table, grad_xc, flags=0):
     L, T, F = table.shape
     _check(lib().ia355_hashgrid_encode_bwd(
         _p(grad_feat, torch.float32, "grad_feat"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S, ld,
         _p(table, name="table"), _DT[table.dtype], L, F, T.bit_length() - 1, base_res, growth, _box(aabb),
-        _p(grad_table, torch.float32, "grad_table"), _p(grad_xc, torch.float32, "grad_xc"), _stream()),
+        _p(grad_table, torch.float32, "grad_table"), _p(grad_xc, torch.float32, "grad_xc"), flags, _stream()),
         "hashgrid_encode_bwd")
 
 
@@ -178,11 +185,11 @@ def mlp_bwd_workspace_size(S):
     return lib().ia355_mlp_bwd_workspace_size(S)
 
 
-def mlp_bwd(grad_sigma, grad_rgb, feat, bone, S, ld, params, dtype, grad_params, grad_feat, ws):
+def mlp_bwd(grad_sigma, grad_rgb, feat, bone, S, ld, params, dtype, grad_params, grad_feat, ws, flags=0):
     _check(lib().ia355_mlp_bwd(
         _p(grad_sigma, torch.float32, "grad_sigma"), _p(grad_rgb, torch.float32, "grad_rgb"), _p(feat, name="feat"),
         _DT[feat.dtype], _p(bone, torch.int16, "bone"), S, ld, _p(params, torch.float32, "params"), dtype,
-        _p(grad_params, torch.float32, "grad_params"), _p(grad_feat, torch.float32, "grad_feat"),
+        _p(grad_params, torch.float32, "grad_params"), _p(grad_feat, torch.float32, "grad_feat"), flags,
         _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "mlp_bwd")
 
 

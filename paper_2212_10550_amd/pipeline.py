@@ -115,6 +115,7 @@ class Pipeline:
         self.grad_xp = e(3, cap)
         self.grad_B = e(*self.B.shape) if grad_B else None
         self.grad_W = e(*self.W.shape) if grad_W else None
+        self.ws_ift = e(K.deform_bwd_workspace_size(cap, Dx, Dy, Dz, nb), dt=torch.uint8)
         self.S = None
         self.timer = None  # optional StageTimer: HIP events around each stage
 
@@ -170,22 +171,16 @@ class Pipeline:
         K.volrender_bwd(self.grad_color, None, self.sigma, self.rgb, self.cap, self.ray_off, self.ray_dt, self.n_used,
                         self.color, self.T_final, self.R, self.grad_sigma, self.grad_rgb)
         self._mark("mlp_bwd")
-        K.zero(self.grad_params)
         feat = self.feat[: w.L * S * 2]
         gfeat = self.grad_feat[: w.L * S * 2]
         K.mlp_bwd(self.grad_sigma, self.grad_rgb, feat, self.bone, S, self.cap, self.params, self.mlp_dtype,
-                  self.grad_params, gfeat, self.ws_mlp)
+                  self.grad_params, gfeat, self.ws_mlp, flags=K.OVERWRITE)
         self._mark("hash_bwd")
-        K.zero(self.grad_table)
         K.hashgrid_encode_bwd(gfeat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth, w.hash_aabb,
-                              self.grad_table, self.grad_xc)
+                              self.grad_table, self.grad_xc, flags=K.OVERWRITE)
         self._mark("deform_bwd")
-        if self.grad_B is not None:
-            K.zero(self.grad_B)
-        if self.grad_W is not None:
-            K.zero(self.grad_W)
         K.snarf_deform_bwd(self.grad_xc, self.xc, self.bone, S, self.cap, self.B, self.W, w.skin_aabb, self.grad_xp,
-                           self.grad_B, self.grad_W)
+                           self.grad_B, self.grad_W, self.ws_ift, flags=K.OVERWRITE)
         self._mark(None)
 
     def train_step(self):

@@ -153,7 +153,8 @@ def test_deform_bwd(orc):
     gB = torch.full(w.B.shape, 0.5, device=dev())
     gW = torch.zeros(w.W.shape, device=dev())
     Dz, Dy, Dx, nb = w.W.shape
-    K.snarf_deform_bwd(soa(u, ld), soa(xc, ld), up(bone), S, ld, up(w.B), up(w.W), w.skin_aabb, gxp, gB, gW)
+    ws = torch.empty(K.deform_bwd_workspace_size(S, Dx, Dy, Dz, nb), dtype=torch.uint8, device=dev())
+    K.snarf_deform_bwd(soa(u, ld), soa(xc, ld), up(bone), S, ld, up(w.B), up(w.W), w.skin_aabb, gxp, gB, gW, ws)
     torch.cuda.synchronize()
     rxp, rB, rW = orc.deform_bwd(u, xc, bone, w.B, w.W, w.skin_aabb)
     e1 = gclose_rows(host(gxp[:, :S]).T, rxp, "grad_xp")

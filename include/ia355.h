@@ -136,6 +136,35 @@ int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int1
                                float *grad_xp, float *grad_B, float *grad_W, uint32_t flags,
                                void *ws, size_t ws_bytes, ia355_stream_t stream);
 
+/* Learned root initialiser (an addition to the paper's root finding of
+ * Sec. 3.1): an MLP (3 + 6 nb) -> 64 -> 64 -> (nb + 3) with ReLU hidden
+ * layers maps (x', pose) to nb bone logits and a canonical offset; the start
+ * point is x0 = B_k^{-1} x' + offset with k = argmax of the logits (ties:
+ * lowest bone).
+ *   xp [3][ld]; pose [nb][6] (axis-angle, translation per bone, device);
+ *   params FP32 flat (per layer W [out][in] row-major, then b [out]);
+ *   hidden must be 64 and nb + 3 <= 32; dtype IA355_F32 or IA355_BF16
+ *   (BF16 MFMA for the two hidden-to-hidden/output layers, FP32 accumulate)
+ *   init_bone [S] int16, x0 [3][ld] outputs. */
+int32_t ia355_rootinit_fwd(const float *xp, int64_t S, int64_t ld, const float *pose, const float *params,
+                           int32_t hidden, const float *B, int32_t nb, int32_t dtype, int16_t *init_bone,
+                           float *x0, ia355_stream_t stream);
+
+/* Guided root finding: one Broyden solve per sample from x0 (H0 = J(x0)^{-1},
+ * the same iteration as ia355_snarf_deform).  A root with residual below
+ * tol_valid inside hash_aabb is accepted with bone = init_bone; every other
+ * sample falls back to the multi-init solve of ia355_snarf_deform.
+ *   steps [S] (nullable) counts the guided steps plus, on fallback, every
+ *   init's steps; n_fallback [1] (device int32, nullable) receives the
+ *   number of fallback samples.
+ * ws: ia355_deform_guided_workspace_size(S, Dx, Dy, Dz) bytes. */
+size_t ia355_deform_guided_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz);
+int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, int64_t ld, const float *x0, const int16_t *init_bone,
+                                  const float *B, int32_t nb, const float *W, int32_t Dx, int32_t Dy, int32_t Dz,
+                                  const float *skin_aabb, const float *hash_aabb, int32_t max_iter, float tol_stop,
+                                  float tol_valid, float *xc, int16_t *bone, float *resid, int16_t *steps,
+                                  int32_t *n_fallback, void *ws, size_t ws_bytes, ia355_stream_t stream);
+
 /* ------------------------------------------------------------------ */
 /* Canonical field, Sec. 3.1 Eq. 1-2 (Instant-NGP encoding + MLP).      */
 /* ------------------------------------------------------------------ */
@@ -158,7 +187,7 @@ int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, i
  *   grad_table [L][T][F] FP32 += sum over samples of w_c * grad_feat_l at each
  *   corner (nullable); with IA355_OVERWRITE in flags it is written instead
  *   (every entry, untouched ones set to 0).  Summation order inside a table
- *   entry is not fixed (LDS atomics), so the last bits may vary run to run.
+ *   entry is not fixed (atomic adds), so the last bits may vary run to run.
  *   grad_xc [3][ld] overwritten with sum_l sum_c (grad w_c)(theta_c . grad_feat_l)
  *   (nullable; needs the table). */
 int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone,

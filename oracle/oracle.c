@@ -768,3 +768,113 @@ double oracle_l2_loss(const double *color, const double *target, int64_t R, doub
     }
     return L;
 }
+
+/* ------------------------------------------------------------------ */
+/* Learned root initialiser (this build's addition; not in the paper).  */
+/* An MLP maps (x', pose) -> (bone logits, canonical offset):          */
+/* input = (x'_xyz, then per bone axis-angle(3) and translation(3)),   */
+/* ReLU hidden layers, linear outputs: nb logits then 3 offsets.       */
+/* The predicted start is x0 = B_k^{-1} x' + offset with k = argmax     */
+/* of the logits (ties: lowest bone).                                  */
+/* params: per layer W [out][in] row-major, then b [out].              */
+/* ------------------------------------------------------------------ */
+void oracle_rootinit_fwd(const double *xp, int64_t S, const double *pose, int32_t nb, const double *params,
+                         int32_t hidden, const double *B, int32_t *bone, double *x0)
+{
+    const int nin = 3 + 6 * nb, nout = nb + 3;
+    const int widths[4] = {nin, hidden, hidden, nout};
+    #pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < S; ++n) {
+        double a[MAXW], h[MAXW];
+        for (int i = 0; i < 3; ++i) a[i] = xp[3 * n + i];
+        for (int i = 0; i < 6 * nb; ++i) a[3 + i] = pose[i];
+        int64_t off = 0;
+        for (int l = 0; l < 3; ++l) {
+            const double *Wl = params + off;
+            const double *bl = Wl + (int64_t)widths[l] * widths[l + 1];
+            for (int o = 0; o < widths[l + 1]; ++o) {
+                double z = bl[o];
+                for (int i = 0; i < widths[l]; ++i) z += Wl[(int64_t)o * widths[l] + i] * a[i];
+                h[o] = (l < 2 && z < 0.0) ? 0.0 : z;
+            }
+            memcpy(a, h, sizeof(double) * widths[l + 1]);
+            off += (int64_t)widths[l] * widths[l + 1] + widths[l + 1];
+        }
+        int k = 0;
+        for (int b = 1; b < nb; ++b)
+            if (a[b] > a[k]) k = b;
+        bone[n] = k;
+        const double *Bk = B + 12 * k;
+        double M[3][3], Mi[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) M[i][j] = Bk[4 * i + j];
+        inv3(M, Mi);
+        for (int i = 0; i < 3; ++i)
+            x0[3 * n + i] = Mi[i][0] * (xp[3 * n] - Bk[3]) + Mi[i][1] * (xp[3 * n + 1] - Bk[7])
+                          + Mi[i][2] * (xp[3 * n + 2] - Bk[11]) + a[nb + i];
+    }
+}
+
+/* Guided root finding: one Broyden solve from the given start x0 (same
+ * iteration as oracle_deform's per-bone solves); it is accepted when its
+ * residual is below tol_valid and its point lies in the canonical box.
+ * Otherwise the sample falls back to the multi-init solve of oracle_deform.
+ * Outputs: xc (polished), bone (the guide's bone on success, the chosen
+ * init on fallback, -1 invalid), steps [S] (guided steps plus, on fallback,
+ * every init's steps), fallback [S] (0/1). */
+void oracle_deform_guided(const double *xp, int64_t S, const double *x0, const int32_t *guide_bone,
+                          const double *B, int32_t nb, const double *W, int32_t dx, int32_t dy, int32_t dz,
+                          const double *skin_aabb, const double *hash_aabb, int32_t max_iter, double tol_stop,
+                          double tol_valid, double *xc, int32_t *bone, int32_t *steps, int32_t *fallback)
+{
+    skin_t s;
+    make_skin(&s, W, dx, dy, dz, nb, skin_aabb);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t n = 0; n < S; ++n) {
+        const double *p = xp + 3 * n;
+        double x[3], g[3], J[3][3], H[3][3], r = INFINITY;
+        int k = 0, ok = 1;
+        memcpy(x, x0 + 3 * n, sizeof x);
+        lbs_residual(&s, B, p, x, g, J);
+        if (fabs(det3(J)) < 1e-12) ok = 0;
+        else inv3(J, H);
+        for (; ok && k < max_iter; ++k) {
+            if (norm3(g) < tol_stop) break;
+            double dxv[3], xn[3], gn[3], dg[3], Hdg[3], dxH[3];
+            for (int i = 0; i < 3; ++i) dxv[i] = -(H[i][0] * g[0] + H[i][1] * g[1] + H[i][2] * g[2]);
+            for (int i = 0; i < 3; ++i) xn[i] = x[i] + dxv[i];
+            lbs_residual(&s, B, p, xn, gn, NULL);
+            for (int i = 0; i < 3; ++i) dg[i] = gn[i] - g[i];
+            for (int i = 0; i < 3; ++i) Hdg[i] = H[i][0] * dg[0] + H[i][1] * dg[1] + H[i][2] * dg[2];
+            for (int j = 0; j < 3; ++j) dxH[j] = dxv[0] * H[0][j] + dxv[1] * H[1][j] + dxv[2] * H[2][j];
+            const double den = dxv[0] * Hdg[0] + dxv[1] * Hdg[1] + dxv[2] * Hdg[2];
+            memcpy(x, xn, sizeof x);
+            memcpy(g, gn, sizeof g);
+            if (fabs(den) < 1e-30) { ok = 0; ++k; break; }
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) H[i][j] += (dxv[i] - Hdg[i]) * dxH[j] / den;
+        }
+        if (ok) r = norm3(g);
+        steps[n] = k;
+        if (ok && r < tol_valid && in_box(x, hash_aabb)) {
+            newton_polish(&s, B, p, x);
+            memcpy(xc + 3 * n, x, sizeof x);
+            bone[n] = guide_bone[n];
+            fallback[n] = 0;
+            continue;
+        }
+        fallback[n] = 1;
+        double xi[MAXB][3], ri[MAXB];
+        int iti[MAXB], oki[MAXB], best = -1;
+        for (int i = 0; i < nb; ++i) {
+            oki[i] = broyden_one(&s, B, p, i, max_iter, tol_stop, xi[i], &ri[i], &iti[i]);
+            oki[i] = oki[i] && ri[i] < tol_valid && in_box(xi[i], hash_aabb);
+            steps[n] += iti[i];
+            if (oki[i] && (best < 0 || ri[i] < ri[best])) best = i;
+        }
+        bone[n] = best;
+        memcpy(x, xi[best >= 0 ? best : 0], sizeof x);
+        if (best >= 0) newton_polish(&s, B, p, x);
+        memcpy(xc + 3 * n, x, sizeof x);
+    }
+}

@@ -55,6 +55,11 @@ def lib():
     L.oracle_composite_fwd.argtypes = [_d, _d, _i64, _d, _I64, _D, _d, _d, _i32, _d]
     L.oracle_composite_bwd.restype = None
     L.oracle_composite_bwd.argtypes = [_d, _d, _d, _d, _i64, _d, _i32, _I64, _d, _d]
+    L.oracle_rootinit_fwd.restype = None
+    L.oracle_rootinit_fwd.argtypes = [_d, _I64, _d, _I32, _d, _I32, _d, _i32, _d]
+    L.oracle_deform_guided.restype = None
+    L.oracle_deform_guided.argtypes = [_d, _I64, _d, _i32, _d, _I32, _d, _I32, _I32, _I32, _d, _d, _I32, _D, _D,
+                                       _d, _i32, _i32, _i32]
     L.oracle_l2_loss.restype = _D
     L.oracle_l2_loss.argtypes = [_d, _d, _I64, _d]
     return L
@@ -258,6 +263,37 @@ def l2_loss(color, target):
     g = np.zeros(color.shape)
     Lv = lib().oracle_l2_loss(_p(color, _d), _p(_f64(target), _d), color.shape[0], _p(g, _d))
     return Lv, g
+
+
+# ------------------------------------------------ learned root initialiser
+def rootinit_fwd(xp, pose, params, B, hidden=64):
+    """Predicted bone and start point x0 = B_k^{-1} x' + offset per posed point."""
+    xp = _f64(xp).reshape(-1, 3)
+    pose = _f64(pose).reshape(-1)
+    B = _f64(B)
+    nb = B.shape[0]
+    S = xp.shape[0]
+    bone = np.zeros(S, np.int32)
+    x0 = np.zeros((S, 3))
+    lib().oracle_rootinit_fwd(_p(xp, _d), S, _p(pose, _d), nb, _p(_f64(params), _d), hidden, _p(B, _d),
+                              _p(bone, _i32), _p(x0, _d))
+    return bone, x0
+
+
+def deform_guided(xp, x0, guide_bone, B, W, skin_aabb, hash_aabb, max_iter=10, tol_stop=1e-6, tol_valid=1e-5):
+    """One Broyden solve from x0, falling back to the multi-init solve."""
+    W = _f64(W)
+    Dz, Dy, Dx, nb = W.shape
+    B = _f64(B)
+    xp = _f64(xp).reshape(-1, 3)
+    S = xp.shape[0]
+    out = dict(xc=np.zeros((S, 3)), bone=np.zeros(S, np.int32), steps=np.zeros(S, np.int32),
+               fallback=np.zeros(S, np.int32))
+    lib().oracle_deform_guided(_p(xp, _d), S, _p(_f64(x0), _d), _p(_c(guide_bone, np.int32), _i32), _p(B, _d), nb,
+                               _p(W, _d), Dx, Dy, Dz, _p(_f64(skin_aabb), _d), _p(_f64(hash_aabb), _d), max_iter,
+                               tol_stop, tol_valid, _p(out["xc"], _d), _p(out["bone"], _i32), _p(out["steps"], _i32),
+                               _p(out["fallback"], _i32))
+    return out
 
 
 # ------------------------------------------------------- whole chain

@@ -13,6 +13,7 @@
 //    shuffles; bone inverses are staged in LDS once per block; the blended
 //    grid is read through the vector L1/L2 with float4 gathers.
 #include "common.h"
+#include "geometry.h"
 
 using namespace ia355;
 
@@ -156,24 +157,6 @@ __device__ __forceinline__ void residual_jac(const float *__restrict__ A, const 
   }
 }
 
-__device__ __forceinline__ float inv3(const float A[3][3], float Ai[3][3]) {
-  const float c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
-  const float c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
-  const float c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
-  const float det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
-  const float id = 1.0f / det;
-  Ai[0][0] = c00 * id;
-  Ai[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
-  Ai[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
-  Ai[1][0] = c01 * id;
-  Ai[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
-  Ai[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
-  Ai[2][0] = c02 * id;
-  Ai[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
-  Ai[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
-  return det;
-}
-
 __device__ __forceinline__ float norm3(const float v[3]) { return sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
 
 constexpr int kSolveBlock = 256;
@@ -190,13 +173,11 @@ struct InitResult {
   int steps;
 };
 
-// One Broyden solve from bone init i.
-__device__ __forceinline__ InitResult broyden(const float *__restrict__ A, const Grid &gr, const float *Bi, bool bone_ok,
-                                             const float xp[3], int max_iter, float tol_stop) {
+// One Broyden solve from the start point x (H0 = J(x)^{-1}).
+__device__ __forceinline__ InitResult broyden_from(const float *__restrict__ A, const Grid &gr, float x[3], bool start_ok,
+                                                  const float xp[3], int max_iter, float tol_stop) {
   InitResult res;
-  float x[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) x[a] = Bi[4 * a] * xp[0] + Bi[4 * a + 1] * xp[1] + Bi[4 * a + 2] * xp[2] + Bi[4 * a + 3];
+  const bool bone_ok = start_ok;
   float g[3], J[3][3], H[3][3];
   residual_jac(A, gr, x, xp, g, J);
   const float detJ = inv3(J, H);
@@ -243,36 +224,31 @@ __device__ __forceinline__ InitResult broyden(const float *__restrict__ A, const
   return res;
 }
 
-__global__ void __launch_bounds__(kSolveBlock) solve_kernel(
-    const float *__restrict__ xp_soa, int64_t S, int64_t ld, const float *__restrict__ B, int nb,
-    const float *__restrict__ A, Grid gr, Box hbox, int max_iter, float tol_stop, float tol_valid,
-    float *__restrict__ xc_soa, int16_t *__restrict__ bone_out, float *__restrict__ resid_out,
-    int16_t *__restrict__ steps_out) {
-  // per-bone inverse transform [M^-1 | -M^-1 t] and a singularity flag
-  __shared__ float sBinv[kMaxBones * 12];
-  __shared__ int sBok[kMaxBones];
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    float M[3][3], Mi[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) M[i][j] = B[12 * b + 4 * i + j];
-    const float det = inv3(M, Mi);
-    sBok[b] = fabsf(det) >= 1e-12f;
-    for (int i = 0; i < 3; ++i) {
-      for (int j = 0; j < 3; ++j) sBinv[12 * b + 4 * i + j] = Mi[i][j];
-      sBinv[12 * b + 4 * i + 3] = -(Mi[i][0] * B[12 * b + 3] + Mi[i][1] * B[12 * b + 7] + Mi[i][2] * B[12 * b + 11]);
-    }
-  }
-  __syncthreads();
-  const int j = threadIdx.x % kGroup;
-  const int64_t n = ((int64_t)blockIdx.x * kSolveBlock + threadIdx.x) / kGroup;
-  const bool act = n < S;
-  float xp[3] = {0.0f, 0.0f, 0.0f};
-  if (act) {
-    xp[0] = xp_soa[n];
-    xp[1] = xp_soa[ld + n];
-    xp[2] = xp_soa[2 * ld + n];
-  }
-  // this lane's best valid init (lowest residual, then lowest index)
+// One Broyden solve from bone init i: x0 = B_i^{-1} x'.
+__device__ __forceinline__ InitResult broyden(const float *__restrict__ A, const Grid &gr, const float *Bi, bool bone_ok,
+                                             const float xp[3], int max_iter, float tol_stop) {
+  float x[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) x[a] = Bi[4 * a] * xp[0] + Bi[4 * a + 1] * xp[1] + Bi[4 * a + 2] * xp[2] + Bi[4 * a + 3];
+  return broyden_from(A, gr, x, bone_ok, xp, max_iter, tol_stop);
+}
+
+__device__ __forceinline__ bool in_hbox(const float x[3], const Box &b) {
+  return x[0] >= b.lo[0] && x[0] <= b.hi[0] && x[1] >= b.lo[1] && x[1] <= b.hi[1] && x[2] >= b.lo[2] &&
+         x[2] <= b.hi[2];
+}
+
+// Multi-init solve of one sample by a group of kGroup lanes (j = lane in
+// group): lowest valid residual, ties to the lowest bone.  Every lane of the
+// group returns the group's result; steps are summed over the inits.
+struct Choice {
+  float x[3], r, x0[3];
+  int bone, steps;
+};
+
+__device__ __forceinline__ Choice multi_init(const float *__restrict__ A, const Grid &gr, const float *sBinv,
+                                             const int *sBok, int nb, const float xp[3], bool act, int j, Box hbox,
+                                             int max_iter, float tol_stop, float tol_valid) {
   float best_r = INFINITY, best_x[3] = {0.0f, 0.0f, 0.0f}, x0[3] = {0.0f, 0.0f, 0.0f};
   int best = 0x7fffffff, steps = 0;
   if (act) {
@@ -284,9 +260,7 @@ __global__ void __launch_bounds__(kSolveBlock) solve_kernel(
         x0[1] = q.x[1];
         x0[2] = q.x[2];
       }
-      const bool inside = q.x[0] >= hbox.lo[0] && q.x[0] <= hbox.hi[0] && q.x[1] >= hbox.lo[1] &&
-                          q.x[1] <= hbox.hi[1] && q.x[2] >= hbox.lo[2] && q.x[2] <= hbox.hi[2];
-      if (q.ok && q.r < tol_valid && inside && q.r < best_r) {
+      if (q.ok && q.r < tol_valid && in_hbox(q.x, hbox) && q.r < best_r) {
         best_r = q.r;
         best = i;
         best_x[0] = q.x[0];
@@ -295,7 +269,6 @@ __global__ void __launch_bounds__(kSolveBlock) solve_kernel(
       }
     }
   }
-  // group reduction: (residual, init index) lexicographic minimum
 #pragma unroll
   for (int o = kGroup / 2; o > 0; o >>= 1) {
     const float r2 = __shfl_xor(best_r, o, kGroup);
@@ -312,36 +285,124 @@ __global__ void __launch_bounds__(kSolveBlock) solve_kernel(
       best_x[2] = x22;
     }
   }
-  // the start-of-group lane ran init 0: its final iterate stands for invalid samples
-  if (act && j == 0) {
-    const bool valid = best != 0x7fffffff;
-    xc_soa[n] = valid ? best_x[0] : x0[0];
-    xc_soa[ld + n] = valid ? best_x[1] : x0[1];
-    xc_soa[2 * ld + n] = valid ? best_x[2] : x0[2];
-    bone_out[n] = valid ? (int16_t)best : (int16_t)-1;
-    if (resid_out) resid_out[n] = valid ? best_r : INFINITY;
-    if (steps_out) steps_out[n] = (int16_t)steps;
+  Choice c;
+  const bool valid = best != 0x7fffffff;
+  // the group's first lane ran init 0: its final iterate stands for invalid samples
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    c.x[a] = best_x[a];
+    c.x0[a] = x0[a];
   }
+  c.r = valid ? best_r : INFINITY;
+  c.bone = valid ? best : -1;
+  c.steps = steps;
+  return c;
+}
+
+__device__ __forceinline__ void write_choice(const Choice &c, int64_t n, int64_t ld, int extra_steps, float *xc_soa,
+                                             int16_t *bone_out, float *resid_out, int16_t *steps_out) {
+  const bool valid = c.bone >= 0;
+  xc_soa[n] = valid ? c.x[0] : c.x0[0];
+  xc_soa[ld + n] = valid ? c.x[1] : c.x0[1];
+  xc_soa[2 * ld + n] = valid ? c.x[2] : c.x0[2];
+  bone_out[n] = (int16_t)c.bone;
+  if (resid_out) resid_out[n] = c.r;
+  if (steps_out) steps_out[n] = (int16_t)(c.steps + extra_steps);
+}
+
+__global__ void __launch_bounds__(kSolveBlock) solve_kernel(
+    const float *__restrict__ xp_soa, int64_t S, int64_t ld, const float *__restrict__ B, int nb,
+    const float *__restrict__ A, Grid gr, Box hbox, int max_iter, float tol_stop, float tol_valid,
+    float *__restrict__ xc_soa, int16_t *__restrict__ bone_out, float *__restrict__ resid_out,
+    int16_t *__restrict__ steps_out) {
+  __shared__ float sBinv[kMaxBones * 12];
+  __shared__ int sBok[kMaxBones];
+  stage_bone_inverses(B, nb, sBinv, sBok);
+  __syncthreads();
+  const int j = threadIdx.x % kGroup;
+  const int64_t n = ((int64_t)blockIdx.x * kSolveBlock + threadIdx.x) / kGroup;
+  const bool act = n < S;
+  float xp[3] = {0.0f, 0.0f, 0.0f};
+  if (act) {
+    xp[0] = xp_soa[n];
+    xp[1] = xp_soa[ld + n];
+    xp[2] = xp_soa[2 * ld + n];
+  }
+  const Choice c = multi_init(A, gr, sBinv, sBok, nb, xp, act, j, hbox, max_iter, tol_stop, tol_valid);
+  if (act && j == 0) write_choice(c, n, ld, 0, xc_soa, bone_out, resid_out, steps_out);
+}
+
+// Guided solve: one lane per sample starts Broyden at the given x0; an
+// accepted root (residual < tol_valid, inside the canonical box) is final,
+// otherwise the sample index is appended to the fallback queue.
+__global__ void __launch_bounds__(kSolveBlock) guided_kernel(
+    const float *__restrict__ xp_soa, const float *__restrict__ x0_soa, const int16_t *__restrict__ guide,
+    int64_t S, int64_t ld, const float *__restrict__ A, Grid gr, Box hbox, int max_iter, float tol_stop,
+    float tol_valid, float *__restrict__ xc_soa, int16_t *__restrict__ bone_out, float *__restrict__ resid_out,
+    int16_t *__restrict__ steps_out, int32_t *__restrict__ queue, int32_t *__restrict__ qlen,
+    int16_t *__restrict__ gsteps) {
+  const int64_t n = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
+  if (n >= S) return;
+  const float xp[3] = {xp_soa[n], xp_soa[ld + n], xp_soa[2 * ld + n]};
+  float x[3] = {x0_soa[n], x0_soa[ld + n], x0_soa[2 * ld + n]};
+  const InitResult q = broyden_from(A, gr, x, true, xp, max_iter, tol_stop);
+  gsteps[n] = (int16_t)q.steps;
+  if (q.ok && q.r < tol_valid && in_hbox(q.x, hbox)) {
+    xc_soa[n] = q.x[0];
+    xc_soa[ld + n] = q.x[1];
+    xc_soa[2 * ld + n] = q.x[2];
+    bone_out[n] = guide[n];
+    if (resid_out) resid_out[n] = q.r;
+    if (steps_out) steps_out[n] = (int16_t)q.steps;
+  } else {
+    queue[atomicAdd(qlen, 1)] = (int32_t)n;
+  }
+}
+
+// Fallback: multi-init solve of the queued samples (the grid covers every
+// sample; groups past the queue length exit at once).
+__global__ void __launch_bounds__(kSolveBlock) fallback_kernel(
+    const float *__restrict__ xp_soa, int64_t ld, const float *__restrict__ B, int nb, const float *__restrict__ A,
+    Grid gr, Box hbox, int max_iter, float tol_stop, float tol_valid, float *__restrict__ xc_soa,
+    int16_t *__restrict__ bone_out, float *__restrict__ resid_out, int16_t *__restrict__ steps_out,
+    const int32_t *__restrict__ queue, const int32_t *__restrict__ qlen, const int16_t *__restrict__ gsteps) {
+  const int64_t q = ((int64_t)blockIdx.x * kSolveBlock + threadIdx.x) / kGroup;
+  const int32_t nq = *qlen;
+  if ((int64_t)blockIdx.x * (kSolveBlock / kGroup) >= nq) return;  // whole block past the queue
+  __shared__ float sBinv[kMaxBones * 12];
+  __shared__ int sBok[kMaxBones];
+  stage_bone_inverses(B, nb, sBinv, sBok);
+  __syncthreads();
+  const int j = threadIdx.x % kGroup;
+  const bool act = q < nq;
+  const int64_t n = act ? queue[q] : 0;
+  float xp[3] = {0.0f, 0.0f, 0.0f};
+  if (act) {
+    xp[0] = xp_soa[n];
+    xp[1] = xp_soa[ld + n];
+    xp[2] = xp_soa[2 * ld + n];
+  }
+  const Choice c = multi_init(A, gr, sBinv, sBok, nb, xp, act, j, hbox, max_iter, tol_stop, tol_valid);
+  if (act && j == 0) write_choice(c, n, ld, gsteps[n], xc_soa, bone_out, resid_out, steps_out);
 }
 
 // ------------------------------------------------------------------------
 // Backward (implicit function theorem), three kernels:
 //  ift_v: one thread per sample: J = sum_b w_b M_b + sum_b y_b grad w_b^T
 //         (y_b = B_b x*_h), v = J^{-T} dL/dx*; dL/dx' = v.
-//  ift_q: owner-computes over the skinning grid: workgroup q owns vertices
-//         [q*kOwnV, (q+1)*kOwnV) and accumulates, in LDS,
+//  ift_q: accumulates the per-vertex moment
 //         Q_v = sum_s tri_v(x*_s) v_s x*_h,s^T   (3 x 4 per vertex)
-//         over every sample whose cell touches them.  Both parameter
-//         gradients are contractions of Q:
+//         with FP32 atomics laid out for few cache lines per instruction
+//         (12 floats per corner instead of the 24-bone products).  Both
+//         parameter gradients are contractions of Q:
 //           dL/dW[v][b] = -sum_ij B_b[i][j] Q_v[i][j]
 //           dL/dB_b     = -sum_v W[v][b] Q_v
-//         so the workgroup writes its vertices' dL/dW rows directly and a
-//         partial of dL/dB -- no global atomics.
+//  ift_contract: one thread per vertex writes its dL/dW row and adds to a
+//         block partial of dL/dB;
 //  ift_b: sums the dL/dB partials in a fixed order (double).
 // ------------------------------------------------------------------------
 constexpr int kBwdBlock = 256;
 constexpr int kMaxBonesBwd = 32;  // skinning weights of one sample kept in registers
-constexpr int kOwnV = 512;        // vertices per workgroup (x 12 floats = 24 KiB LDS)
 constexpr int kOwnBlock = 256;
 
 __global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restrict__ gxc, const float *__restrict__ xc_soa,
@@ -396,47 +457,52 @@ __global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restric
   vbuf[2 * S + n] = v[2];
 }
 
+// Q_v += tri_v(x*) v x*_h^T: 64 lanes per sample, lane = 8 * corner + slot,
+// slots j and j + 8 (< 12) of the corner's 12 floats.  A corner's 12 floats
+// are 48 contiguous bytes and x-neighbouring corners are adjacent vertices,
+// so each wave instruction touches about four cache lines (FP32 atomics to
+// random lines are limited by L2 requests, not by floats).
 __global__ void __launch_bounds__(kOwnBlock) ift_q_kernel(const float *__restrict__ xc_soa,
                                                         const int16_t *__restrict__ bone, const float *__restrict__ vbuf,
-                                                        int64_t S, int64_t ld, const float *__restrict__ B, int nb,
-                                                        const float *__restrict__ W, Grid gr, int64_t nvert,
-                                                        float *__restrict__ gW, float *__restrict__ partB,
-                                                        int overwrite) {
-  __shared__ float Q[kOwnV * 12];
+                                                        int64_t S, int64_t ld, Grid gr, float *__restrict__ Q) {
+  const int64_t t = (int64_t)blockIdx.x * kOwnBlock + threadIdx.x;
+  const int64_t n = t >> 6;
+  if (n >= S || bone[n] < 0) return;
+  const int lane = (int)(t & 63), k = lane >> 3, j = lane & 7;
+  const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
+  const float v[3] = {vbuf[n], vbuf[S + n], vbuf[2 * S + n]};
+  const Cell c = locate(gr, x);
+  const int64_t vtx = ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] +
+                      (c.i0[0] + (k & 1));
+  const float tw = tri_weight(c.f, k);
+  const float xh[4] = {x[0], x[1], x[2], 1.0f};
+  float *q = Q + 12 * vtx;
+  atomicAdd(q + j, tw * v[j >> 2] * xh[j & 3]);
+  if (j < 4) atomicAdd(q + 8 + j, tw * v[2] * xh[j]);
+}
+
+// Contractions of Q, one vertex per thread: dL/dW[v][b] = -sum_m B_b[m] Q_v[m];
+// and a block partial of sum_v W[v][b] Q_v[m] for dL/dB (LDS-staged).
+constexpr int kConBlock = 256;
+
+__global__ void __launch_bounds__(kConBlock) ift_contract_kernel(const float *__restrict__ Q,
+                                                               const float *__restrict__ B, int nb,
+                                                               const float *__restrict__ W, int64_t nvert,
+                                                               float *__restrict__ gW, float *__restrict__ partB,
+                                                               int overwrite) {
   __shared__ float sB[kMaxBones * 12];
-  for (int i = threadIdx.x; i < kOwnV * 12; i += kOwnBlock) Q[i] = 0.0f;
-  for (int i = threadIdx.x; i < nb * 12; i += kOwnBlock) sB[i] = B[i];
+  __shared__ float sQ[kConBlock * 12];
+  for (int i = threadIdx.x; i < nb * 12; i += kConBlock) sB[i] = B[i];
+  const int64_t v0 = (int64_t)blockIdx.x * kConBlock;
+  const int64_t v = v0 + threadIdx.x;
+  float q[12];
+#pragma unroll
+  for (int m = 0; m < 12; ++m) q[m] = v < nvert ? Q[12 * v + m] : 0.0f;
+#pragma unroll
+  for (int m = 0; m < 12; ++m) sQ[12 * threadIdx.x + m] = q[m];
   __syncthreads();
-  const int64_t v0 = (int64_t)blockIdx.x * kOwnV;
-  const int64_t plane = (int64_t)gr.D[0] * gr.D[1];
-  const int64_t z_lo = v0 / plane, z_hi = (v0 + kOwnV - 1) / plane;
-  for (int64_t n = threadIdx.x; n < S; n += kOwnBlock) {
-    if (bone[n] < 0) continue;
-    const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
-    const Cell c = locate(gr, x);
-    if (c.i0[2] + 1 < z_lo || c.i0[2] > z_hi) continue;
-    const float v[3] = {vbuf[n], vbuf[S + n], vbuf[2 * S + n]};
-    const float xh[4] = {x[0], x[1], x[2], 1.0f};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int64_t e = ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] +
-                        (c.i0[0] + (k & 1)) - v0;
-      if (e >= 0 && e < kOwnV) {
-        const float t = tri_weight(c.f, k);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) atomicAdd(&Q[12 * e + 4 * i + j], t * v[i] * xh[j]);
-      }
-    }
-  }
-  __syncthreads();
-  const int64_t nv = min((int64_t)kOwnV, nvert - v0);
-  // dL/dW rows of the owned vertices
-  for (int64_t e = threadIdx.x; e < nv; e += kOwnBlock) {
-    const float *q = Q + 12 * e;
-    float *out = gW ? gW + (v0 + e) * nb : nullptr;
-    if (!out) break;
+  if (gW && v < nvert) {
+    float *out = gW + v * nb;
     for (int b = 0; b < nb; ++b) {
       const float *Bb = sB + 12 * b;
       float s = 0.0f;
@@ -445,12 +511,12 @@ __global__ void __launch_bounds__(kOwnBlock) ift_q_kernel(const float *__restric
       out[b] = overwrite ? -s : out[b] - s;
     }
   }
-  // partial of dL/dB: one (bone, entry) pair per thread
   if (partB) {
-    for (int p = threadIdx.x; p < nb * 12; p += kOwnBlock) {
+    const int64_t nv = min((int64_t)kConBlock, nvert - v0);
+    for (int p = threadIdx.x; p < nb * 12; p += kConBlock) {
       const int b = p / 12, m = p % 12;
       float s = 0.0f;
-      for (int64_t e = 0; e < nv; ++e) s += W[(v0 + e) * nb + b] * Q[12 * e + m];
+      for (int64_t e = 0; e < nv; ++e) s += W[(v0 + e) * nb + b] * sQ[12 * e + m];
       partB[(int64_t)blockIdx.x * nb * 12 + p] = s;
     }
   }
@@ -515,10 +581,55 @@ extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, int64_t ld, co
   return launch_status();
 }
 
+extern "C" size_t ia355_deform_guided_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz) {
+  if (S < 0) return 0;
+  return ia355_deform_workspace_size(Dx, Dy, Dz) + align256(sizeof(int32_t) * (size_t)(S + 1)) +
+         align256(sizeof(int16_t) * (size_t)(S > 0 ? S : 1));
+}
+
+extern "C" int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, int64_t ld, const float *x0,
+                                             const int16_t *guide_bone, const float *B, int32_t nb, const float *W,
+                                             int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
+                                             const float *hash_aabb, int32_t max_iter, float tol_stop,
+                                             float tol_valid, float *xc, int16_t *bone, float *resid, int16_t *steps,
+                                             int32_t *n_fallback, void *ws, size_t ws_bytes, ia355_stream_t stream) {
+  if (S < 0 || ld < S || nb <= 0 || nb > kMaxBones || max_iter < 0 || max_iter > 1000) return IA355_ERR_INVALID_ARG;
+  if (S > 0x7ffffffeLL) return IA355_ERR_INVALID_ARG;
+  if (!B || !W || !grid_ok(Dx, Dy, Dz, skin_aabb) || !hash_aabb) return IA355_ERR_INVALID_ARG;
+  if (S > 0 && (!xp || !x0 || !guide_bone || !xc || !bone)) return IA355_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < ia355_deform_guided_workspace_size(S, Dx, Dy, Dz)) return IA355_ERR_WORKSPACE;
+  hipStream_t s = as_stream(stream);
+  const int64_t nvert = (int64_t)Dx * Dy * Dz;
+  float *A = (float *)ws;
+  char *p = (char *)ws + ia355_deform_workspace_size(Dx, Dy, Dz);
+  int32_t *qlen = (int32_t *)p;
+  int32_t *queue = qlen + 1;
+  int16_t *gsteps = (int16_t *)(p + align256(sizeof(int32_t) * (size_t)(S + 1)));
+  blend_kernel<<<(unsigned)ceil_div(nvert, 256), 256, 0, s>>>(W, B, nb, nvert, A);
+  int32_t st = ia355_zero(qlen, sizeof(int32_t), stream);
+  if (st != IA355_OK) return st;
+  if (S > 0) {
+    const Grid g = make_grid(Dx, Dy, Dz, skin_aabb);
+    Box hb;
+    for (int a = 0; a < 3; ++a) {
+      hb.lo[a] = hash_aabb[a];
+      hb.hi[a] = hash_aabb[3 + a];
+    }
+    guided_kernel<<<(unsigned)ceil_div(S, kSolveBlock), kSolveBlock, 0, s>>>(
+        xp, x0, guide_bone, S, ld, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, queue, qlen,
+        gsteps);
+    fallback_kernel<<<(unsigned)ceil_div(S * kGroup, kSolveBlock), kSolveBlock, 0, s>>>(
+        xp, ld, B, nb, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, queue, qlen, gsteps);
+  }
+  if (n_fallback) hipMemcpyAsync(n_fallback, qlen, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+  return launch_status();
+}
+
 extern "C" size_t ia355_deform_bwd_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz, int32_t nb) {
   if (S < 0 || Dx <= 0 || Dy <= 0 || Dz <= 0 || nb <= 0) return 0;
   const int64_t nvert = (int64_t)Dx * Dy * Dz;
-  return align256(sizeof(float) * 3 * (size_t)S) + align256(sizeof(float) * 12 * (size_t)nb * ceil_div(nvert, kOwnV));
+  return align256(sizeof(float) * 3 * (size_t)S) + align256(sizeof(float) * 12 * (size_t)nvert) +
+         align256(sizeof(float) * 12 * (size_t)nb * ceil_div(nvert, kConBlock));
 }
 
 extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int16_t *bone, int64_t S,
@@ -535,16 +646,21 @@ extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc,
   const Grid g = make_grid(Dx, Dy, Dz, skin_aabb);
   hipStream_t s = as_stream(stream);
   const int64_t nvert = (int64_t)Dx * Dy * Dz;
-  const int nq = (int)ceil_div(nvert, kOwnV);
+  const int nblk = (int)ceil_div(nvert, kConBlock);
   float *vbuf = (float *)ws;
-  float *partB = (float *)((char *)ws + align256(sizeof(float) * 3 * (size_t)S));
+  float *Q = (float *)((char *)ws + align256(sizeof(float) * 3 * (size_t)S));
+  float *partB = (float *)((char *)Q + align256(sizeof(float) * 12 * (size_t)nvert));
   if (S > 0)
     ift_v_kernel<<<(unsigned)ceil_div(S, kBwdBlock), kBwdBlock, 0, s>>>(grad_xc, xc, bone, S, ld, B, nb, W, g,
                                                                         grad_xp, vbuf);
   if (grad_W || grad_B) {
-    ift_q_kernel<<<(unsigned)nq, kOwnBlock, 0, s>>>(xc, bone, vbuf, S, ld, B, nb, W, g, nvert, grad_W,
-                                                    grad_B ? partB : nullptr, overwrite);
-    if (grad_B) ift_b_kernel<<<(unsigned)ceil_div(nb * 12, 256), 256, 0, s>>>(partB, nq, nb * 12, grad_B, overwrite);
+    const int32_t st = ia355_zero(Q, sizeof(float) * 12 * (size_t)nvert, stream);
+    if (st != IA355_OK) return st;
+    if (S > 0)
+      ift_q_kernel<<<(unsigned)ceil_div(S * 64, kOwnBlock), kOwnBlock, 0, s>>>(xc, bone, vbuf, S, ld, g, Q);
+    ift_contract_kernel<<<(unsigned)nblk, kConBlock, 0, s>>>(Q, B, nb, W, nvert, grad_W, grad_B ? partB : nullptr,
+                                                             overwrite);
+    if (grad_B) ift_b_kernel<<<(unsigned)ceil_div(nb * 12, 256), 256, 0, s>>>(partB, nblk, nb * 12, grad_B, overwrite);
   }
   return launch_status();
 }

@@ -12,10 +12,11 @@
 //    relative precision even at N_l ~ 2000;
 //  * features are written level-major [L][S][F]: each block writes one
 //    contiguous run (coalesced 8-byte / 4-byte stores per lane).
-// Backward: the table gradient is accumulated owner-computes in LDS (one
-// workgroup per level slab, see table_grad_kernel); the position gradient
-// runs one wave per 4 samples x 16 levels (lane = level + 16 * sample) and
-// is reduced across the 16 level lanes with shuffles (deterministic).
+// Backward: the table gradient is FP32 atomics laid out so that each wave
+// instruction touches few cache lines (see table_grad_kernel); the position
+// gradient runs one wave per 4 samples x 16 levels (lane = level + 16 *
+// sample) and is reduced across the 16 level lanes with shuffles
+// (deterministic).
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -188,58 +189,36 @@ __global__ void __launch_bounds__(kBwdBlock) encode_bwd_kernel(
   }
 }
 
-// Table gradient, owner-computes: workgroup (level l, slab q) owns table
-// entries [q*kSlab, (q+1)*kSlab) of level l.  It walks every sample, finds
-// the level-l corners that fall in its slab and adds w_c * dL/dfeat_l into an
-// LDS copy of the slab (LDS atomics), then writes the slab to grad_table once
-// (plain loads/stores: no other workgroup touches those entries).  This
-// replaces 16 x 8 x 2 global atomics per sample, whose throughput and
-// same-address contention on the coarse levels dominate otherwise.  Slabs
-// beyond a dense level's (N+1)^3 entries only write (overwrite mode).
-constexpr int kSlab = 8192;  // entries; x 2 floats = 64 KiB of LDS
-constexpr int kOwnBlock = 512;
+// Table gradient with coalesced atomics.  FP32 atomics to random addresses
+// are limited by L2 requests (one per touched cache line per instruction),
+// not by the number of floats added, so the mapping packs updates that
+// share lines into the same wave instruction: 16 lanes per (level, sample)
+// item, lane = 2 * corner + feature.  The two features of a corner are
+// adjacent floats and x-neighbouring corners are adjacent entries (dense
+// levels) or differ only in low bits (hashed levels, x prime = 1), so the
+// 16 updates of an item touch about four lines.  Items are level-major, so
+// the four items of a wave are consecutive samples of one level and share
+// lines on the coarse levels as well.
+constexpr int kTgBlock = 256;
 
-__global__ void __launch_bounds__(kOwnBlock) table_grad_kernel(const float *__restrict__ gfeat,
+__global__ void __launch_bounds__(kTgBlock) table_grad_kernel(const float *__restrict__ gfeat,
                                                              const float *__restrict__ xc,
                                                              const int16_t *__restrict__ bone, int64_t S, int64_t ld,
-                                                             int log2T, Levels lv, Box box, float *__restrict__ gtable,
-                                                             int slabs, int overwrite) {
-  __shared__ float acc[2 * kSlab];
-  const int level = blockIdx.x / slabs;
-  const uint32_t e0 = (uint32_t)(blockIdx.x % slabs) * kSlab;
+                                                             int L, int log2T, Levels lv, Box box,
+                                                             float *__restrict__ gtable) {
+  const int64_t t = (int64_t)blockIdx.x * kTgBlock + threadIdx.x;
+  const int64_t item = t >> 4;
+  if (item >= (int64_t)L * S) return;
+  const int level = (int)(item / S);
+  const int64_t n = item - (int64_t)level * S;
+  if (bone && bone[n] < 0) return;
+  const int sub = (int)(t & 15), k = sub >> 1, f = sub & 1;
+  const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
   const uint32_t T = 1u << log2T;
-  const uint32_t e1 = min(e0 + (uint32_t)kSlab, T);
-  const int N = lv.res[level];
-  const bool dense = lv.dense[level];
-  const uint64_t side = (uint64_t)N + 1;
-  const uint64_t used = dense ? side * side * side : (uint64_t)T;
-  for (int i = threadIdx.x; i < 2 * kSlab; i += kOwnBlock) acc[i] = 0.0f;
-  __syncthreads();
-  if ((uint64_t)e0 < used) {
-    const float2 *g2 = reinterpret_cast<const float2 *>(gfeat) + (int64_t)level * S;
-    for (int64_t n = threadIdx.x; n < S; n += kOwnBlock) {
-      if (bone && bone[n] < 0) continue;
-      const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
-      Corners c;
-      level_cell(x, box, N, dense, T - 1u, c, false);
-      const float2 g = g2[n];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const uint32_t e = c.idx[k] - e0;
-        if (e < (uint32_t)kSlab) {
-          atomicAdd(&acc[2 * e], c.w[k] * g.x);
-          atomicAdd(&acc[2 * e + 1], c.w[k] * g.y);
-        }
-      }
-    }
-  }
-  __syncthreads();
-  float *out = gtable + ((int64_t)level * T + e0) * 2;
-  const int cnt = 2 * (int)(e1 - e0);
-  if (overwrite)
-    for (int i = threadIdx.x; i < cnt; i += kOwnBlock) out[i] = acc[i];
-  else
-    for (int i = threadIdx.x; i < cnt; i += kOwnBlock) out[i] += acc[i];
+  Corners c;
+  level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
+  const float g = gfeat[2 * ((int64_t)level * S + n) + f];
+  atomicAdd(gtable + 2 * ((int64_t)level * T + c.idx[k]) + f, c.w[k] * g);
 }
 
 int32_t make_levels(int L, int log2T, double base, double growth, Levels *lv) {
@@ -313,11 +292,13 @@ extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float
   if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
   const int overwrite = (flags & IA355_OVERWRITE) != 0;
-  if (grad_table && (S > 0 || overwrite)) {
-    const int slabs = (int)ceil_div((int64_t)1 << log2T, kSlab);
-    table_grad_kernel<<<(unsigned)(slabs * L), kOwnBlock, 0, s>>>(grad_feat, xc, bone, S, ld, log2T, lv, box,
-                                                                  grad_table, slabs, overwrite);
+  if (grad_table && overwrite) {
+    const int32_t st = ia355_zero(grad_table, sizeof(float) * 2 * (size_t)L * ((size_t)1 << log2T), stream);
+    if (st != IA355_OK) return st;
   }
+  if (grad_table && S > 0)
+    table_grad_kernel<<<(unsigned)ceil_div((int64_t)L * S * 16, kTgBlock), kTgBlock, 0, s>>>(
+        grad_feat, xc, bone, S, ld, L, log2T, lv, box, grad_table);
   if (grad_xc && S > 0) {
     const int64_t blocks = ceil_div(S * 16, kBwdBlock);
     if (table_dtype == IA355_F32)

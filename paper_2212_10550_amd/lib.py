@@ -43,6 +43,10 @@ _SIGS = {
     "deform_bwd_workspace_size": (_sz, [_i64, _i32, _i32, _i32, _i32]),
     "snarf_deform_bwd": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _vp, _vp, _vp,
                                 ctypes.c_uint32, _vp, _sz, _vp]),
+    "rootinit_fwd": (_i32, [_vp, _i64, _i64, _vp, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp]),
+    "deform_guided_workspace_size": (_sz, [_i64, _i32, _i32, _i32]),
+    "snarf_deform_guided": (_i32, [_vp, _i64, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f,
+                                   _f, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "hashgrid_encode": (_i32, [_vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _i32, _vp]),
     "hashgrid_encode_bwd": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _vp,
                                    ctypes.c_uint32, _vp]),
@@ -155,6 +159,29 @@ def snarf_deform_bwd(grad_xc, xc, bone, S, ld, B, W, skin_aabb, grad_xp, grad_B,
         _p(grad_xp, torch.float32, "grad_xp"), _p(grad_B, torch.float32, "grad_B"),
         _p(grad_W, torch.float32, "grad_W"), flags, _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()),
         "snarf_deform_bwd")
+
+
+def rootinit_fwd(xp, S, ld, pose, params, B, dtype, init_bone, x0, hidden=64):
+    nb = B.shape[0]
+    _check(lib().ia355_rootinit_fwd(
+        _p(xp, torch.float32, "xp"), S, ld, _p(pose, torch.float32, "pose"), _p(params, torch.float32, "params"),
+        hidden, _p(B, torch.float32, "B"), nb, dtype, _p(init_bone, torch.int16, "init_bone"),
+        _p(x0, torch.float32, "x0"), _stream()), "rootinit_fwd")
+
+
+def deform_guided_workspace_size(S, Dx, Dy, Dz):
+    return lib().ia355_deform_guided_workspace_size(S, Dx, Dy, Dz)
+
+
+def snarf_deform_guided(xp, S, ld, x0, init_bone, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, xc,
+                        bone, resid, steps, n_fallback, ws):
+    Dz, Dy, Dx, nb = W.shape
+    _check(lib().ia355_snarf_deform_guided(
+        _p(xp, torch.float32, "xp"), S, ld, _p(x0, torch.float32, "x0"), _p(init_bone, torch.int16, "init_bone"),
+        _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"), Dx, Dy, Dz, _box(skin_aabb), _box(hash_aabb),
+        max_iter, tol_stop, tol_valid, _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"),
+        _p(resid, torch.float32, "resid"), _p(steps, torch.int16, "steps"), _p(n_fallback, torch.int32, "n_fallback"),
+        _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "snarf_deform_guided")
 
 
 def hashgrid_encode(xc, bone, S, ld, table, base_res, growth, aabb, feat):

@@ -377,3 +377,28 @@ def random_points(n: int, seed: int, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> 
     lo = np.asarray(lo)
     hi = np.asarray(hi)
     return _f32(lo + (hi - lo) * rng.uniform(size=(n, 3)))
+
+
+def make_rootinit_params(nb: int = NB, hidden: int = 64, seed: int = 11) -> np.ndarray:
+    """He-normal initial weights of the root-initialiser MLP
+    (3 + 6 nb) -> hidden -> hidden -> (nb + 3), zero biases; flat layout as
+    make_mlp."""
+    return make_mlp((3 + 6 * nb, hidden, hidden, nb + 3), seed=seed, bias_std=0.0)
+
+
+def sample_posed_points(skel: Skeleton, B: np.ndarray, n: int, seed: int, radius: float = 0.05) -> np.ndarray:
+    """n points uniform in the union of capsules of the given radius around
+    the posed bone segments (rejection sampling in their bounding box)."""
+    rng = np.random.default_rng(seed)
+    a, b = _posed_segments(skel, B)
+    lo = np.minimum(a, b).min(0) - radius
+    hi = np.maximum(a, b).max(0) + radius
+    out = []
+    got = 0
+    while got < n:
+        p = lo + (hi - lo) * rng.uniform(size=(4 * n, 3))
+        d = np.min(np.stack([_seg_dist(p, a[i], b[i]) for i in range(a.shape[0])], -1), -1)
+        p = p[d <= radius]
+        out.append(p)
+        got += p.shape[0]
+    return _f32(np.concatenate(out)[:n])

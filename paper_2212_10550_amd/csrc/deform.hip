@@ -481,8 +481,10 @@ __global__ void __launch_bounds__(kOwnBlock) ift_q_kernel(const float *__restric
   if (j < 4) atomicAdd(q + 8 + j, tw * v[2] * xh[j]);
 }
 
-// Contractions of Q, one vertex per thread: dL/dW[v][b] = -sum_m B_b[m] Q_v[m];
-// and a block partial of sum_v W[v][b] Q_v[m] for dL/dB (LDS-staged).
+// Contractions of Q over a block of kConBlock vertices:
+//   dL/dW[v][b] = -sum_m B_b[m] Q_v[m]      (one vertex per thread)
+//   partial of sum_v W[v][b] Q_v[m]         (one (b, m) pair per thread)
+// The block's W rows and Q rows are staged in LDS with coalesced loads.
 constexpr int kConBlock = 256;
 
 __global__ void __launch_bounds__(kConBlock) ift_contract_kernel(const float *__restrict__ Q,
@@ -492,17 +494,18 @@ __global__ void __launch_bounds__(kConBlock) ift_contract_kernel(const float *__
                                                                int overwrite) {
   __shared__ float sB[kMaxBones * 12];
   __shared__ float sQ[kConBlock * 12];
+  __shared__ float sW[kConBlock * 32];  // nb <= 32 for the grad_B partial
   for (int i = threadIdx.x; i < nb * 12; i += kConBlock) sB[i] = B[i];
   const int64_t v0 = (int64_t)blockIdx.x * kConBlock;
-  const int64_t v = v0 + threadIdx.x;
-  float q[12];
-#pragma unroll
-  for (int m = 0; m < 12; ++m) q[m] = v < nvert ? Q[12 * v + m] : 0.0f;
-#pragma unroll
-  for (int m = 0; m < 12; ++m) sQ[12 * threadIdx.x + m] = q[m];
+  const int nv = (int)min((int64_t)kConBlock, nvert - v0);
+  for (int i = threadIdx.x; i < kConBlock * 12; i += kConBlock) sQ[i] = i < nv * 12 ? Q[v0 * 12 + i] : 0.0f;
+  const bool wpart = partB && nb <= 32;
+  if (wpart)
+    for (int i = threadIdx.x; i < nv * nb; i += kConBlock) sW[(i / nb) * 32 + (i % nb)] = W[v0 * nb + i];
   __syncthreads();
-  if (gW && v < nvert) {
-    float *out = gW + v * nb;
+  if (gW && (int)threadIdx.x < nv) {
+    const float *q = sQ + 12 * threadIdx.x;
+    float *out = gW + (v0 + threadIdx.x) * nb;
     for (int b = 0; b < nb; ++b) {
       const float *Bb = sB + 12 * b;
       float s = 0.0f;
@@ -512,12 +515,22 @@ __global__ void __launch_bounds__(kConBlock) ift_contract_kernel(const float *__
     }
   }
   if (partB) {
-    const int64_t nv = min((int64_t)kConBlock, nvert - v0);
     for (int p = threadIdx.x; p < nb * 12; p += kConBlock) {
       const int b = p / 12, m = p % 12;
-      float s = 0.0f;
-      for (int64_t e = 0; e < nv; ++e) s += W[(v0 + e) * nb + b] * sQ[12 * e + m];
-      partB[(int64_t)blockIdx.x * nb * 12 + p] = s;
+      float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+      if (wpart) {
+        int e = 0;
+        for (; e + 3 < nv; e += 4) {
+          s0 += sW[e * 32 + b] * sQ[12 * e + m];
+          s1 += sW[(e + 1) * 32 + b] * sQ[12 * (e + 1) + m];
+          s2 += sW[(e + 2) * 32 + b] * sQ[12 * (e + 2) + m];
+          s3 += sW[(e + 3) * 32 + b] * sQ[12 * (e + 3) + m];
+        }
+        for (; e < nv; ++e) s0 += sW[e * 32 + b] * sQ[12 * e + m];
+      } else {
+        for (int e = 0; e < nv; ++e) s0 += W[(v0 + e) * nb + b] * sQ[12 * e + m];
+      }
+      partB[(int64_t)blockIdx.x * nb * 12 + p] = (s0 + s1) + (s2 + s3);
     }
   }
 }

@@ -502,6 +502,235 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_f32(const float *__restrict
   for (int e = threadIdx.x; e < NPARAM; e += kBwdBlock) partial[(int64_t)blockIdx.x * NPARAM + e] = bp[e];
 }
 
+// --------------------------------------------------------------- BF16 bwd
+// Same algebra as the FP32 backward, on BF16 MFMA 16x16x32 (FP32
+// accumulate).  A wave owns a 32-sample tile: two 16-sample sub-tiles run
+// the BF16 forward and the chained backward (gh1 = W2^T d2, gfeat = W1^T d1
+// with transposed weight fragments; the 4-wide head gh2 = W3^T d3 on FP32
+// MFMA), then the weight gradients take K = 32 samples per MFMA from
+// [neuron][sample] BF16 tiles in LDS.
+constexpr int LDB = 40;  // BF16 row stride of the sample tiles (32 + 8 pad)
+constexpr int BR_X = 0, BR_H1 = 32, BR_H2 = 96, BR_D2 = 160, BR_D1 = 224, BR_D3 = 288, BR_ROWS = 292;
+constexpr int SCRB_BYTES = BR_ROWS * LDB * 2;
+constexpr int LDS_BF_BYTES = kBwdWaves * SCRB_BYTES;
+static_assert(LDS_BF_BYTES >= NPARAM * 4, "block partial reuses the scratch region");
+static_assert(LDS_BF_BYTES <= 65536, "one workgroup's LDS");
+
+struct FragBfT {
+  bf16x8 w2t[4][2];  // [mt][c]: W2[16(2c + j/4) + 4g + j%4][16mt + r]
+  bf16x8 w1t[2][2];  // [mt][c]: W1[16(2c + j/4) + 4g + j%4][16mt + r]
+  float w3t[4];      // [mt]: W3[g][16mt + r]
+};
+
+__device__ __forceinline__ void load_frag_bft(const float *P, int r, int g, FragBfT &f) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 16 * (2 * c + j / 4) + 4 * g + (j % 4);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) f.w2t[mt][c][j] = (__bf16)P[OFF_W2 + k * NH + 16 * mt + r];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) f.w1t[mt][c][j] = (__bf16)P[OFF_W1 + k * NIN + 16 * mt + r];
+    }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) f.w3t[mt] = P[OFF_W3 + g * NH + 16 * mt + r];
+}
+
+__device__ __forceinline__ bf16x8 pack_raw(const f32x4 z[4], int c) {
+  bf16x8 b;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) b[j] = (__bf16)z[2 * c + j / 4][j % 4];
+  return b;
+}
+
+__device__ __forceinline__ bf16x8 lds_row8(const __bf16 *scr, int row, int col) {
+  return *reinterpret_cast<const bf16x8 *>(scr + row * LDB + col);
+}
+
+__global__ void __launch_bounds__(kBwdBlock) mlp_bwd_bf16(const float *__restrict__ gsig,
+                                                          const float *__restrict__ grgb,
+                                                          const __hip_bfloat16 *__restrict__ feat,
+                                                          const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                          const float *__restrict__ P, float *__restrict__ gfeat,
+                                                          float *__restrict__ partial) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char ldsb[];
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4, wid = threadIdx.x >> 6;
+  __bf16 *scr = reinterpret_cast<__bf16 *>(ldsb + wid * SCRB_BYTES);
+  FragBf f;
+  load_frag_bf(P, r, g, f);
+  FragBfT ft;
+  load_frag_bft(P, r, g, ft);
+  f32x4 aW1[4][2], aW2[4][4], aW3[4];
+  float ab1[4][4], ab2[4][4], ab3[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    aW3[a] = f32x4{0, 0, 0, 0};
+    ab3[a] = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      aW2[a][b] = f32x4{0, 0, 0, 0};
+      ab1[a][b] = 0.0f;
+      ab2[a][b] = 0.0f;
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) aW1[a][b] = f32x4{0, 0, 0, 0};
+  }
+  const int64_t ntile = ceil_div(S, 32);
+  const int64_t wstride = (int64_t)gridDim.x * kBwdWaves;
+  for (int64_t tile = (int64_t)blockIdx.x * kBwdWaves + wid; tile < ntile; tile += wstride) {
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int col = 16 * half + r;
+      const int64_t s = tile * 32 + col;
+      const bool ok = s < S;
+      const bf16x8 X = load_x_bf16(feat, S, s, g, ok);
+      f32x4 z1[4], z2[4], o;
+      fwd_bf(f, X, z1, z2, o);
+      float d3[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (g == 0 && ok && (!bone || bone[s] >= 0)) {
+        const float ov[4] = {o[0], o[1], o[2], o[3]};
+        float sg, c[3];
+        head(ov, &sg, c);
+        d3[0] = ov[0] < 80.0f ? gsig[s] * sg : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d3[1 + k] = grgb[k * ld + s] * c[k] * (1.0f - c[k]);
+      }
+      float b3 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float t = __shfl(d3[k], r, 64);
+        b3 = (g == k) ? t : b3;
+      }
+      f32x4 d2[4], d1[4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = mfma4(ft.w3t[mt], b3, f32x4{0, 0, 0, 0});
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          acc[i] = z2[mt][i] < 0.0f ? 0.0f : acc[i];
+          ab2[mt][i] += acc[i];
+        }
+        d2[mt] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ab3[i] += (g == 0) ? d3[i] : 0.0f;
+      const bf16x8 d2a = pack_raw(d2, 0), d2b = pack_raw(d2, 1);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = mfma32(ft.w2t[mt][0], d2a, f32x4{0, 0, 0, 0});
+        acc = mfma32(ft.w2t[mt][1], d2b, acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          acc[i] = z1[mt][i] < 0.0f ? 0.0f : acc[i];
+          ab1[mt][i] += acc[i];
+        }
+        d1[mt] = acc;
+      }
+      if (gfeat) {
+        const bf16x8 d1a = pack_raw(d1, 0), d1b = pack_raw(d1, 1);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          f32x4 acc = mfma32(ft.w1t[mt][0], d1a, f32x4{0, 0, 0, 0});
+          acc = mfma32(ft.w1t[mt][1], d1b, acc);
+          if (ok) {
+            float2 *gf = reinterpret_cast<float2 *>(gfeat);
+            gf[(int64_t)(8 * mt + 2 * g) * S + s] = make_float2(acc[0], acc[1]);
+            gf[(int64_t)(8 * mt + 2 * g + 1) * S + s] = make_float2(acc[2], acc[3]);
+          }
+        }
+      }
+      // [neuron][sample] tiles for the weight gradients
+#pragma unroll
+      for (int j = 0; j < 8; ++j) scr[(BR_X + 8 * g + j) * LDB + col] = X[j];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int n = 16 * t + 4 * g + i;
+          scr[(BR_H1 + n) * LDB + col] = (__bf16)relu(z1[t][i]);
+          scr[(BR_H2 + n) * LDB + col] = (__bf16)relu(z2[t][i]);
+          scr[(BR_D2 + n) * LDB + col] = (__bf16)d2[t][i];
+          scr[(BR_D1 + n) * LDB + col] = (__bf16)d1[t][i];
+        }
+      if (g == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) scr[(BR_D3 + k) * LDB + col] = (__bf16)d3[k];
+    }
+    wave_sync();
+    // weight gradients, K = the tile's 32 samples
+    const bf16x8 zero8 = {};
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const bf16x8 bh1 = lds_row8(scr, BR_H1 + 16 * nt + r, 8 * g);
+      const bf16x8 bh2 = lds_row8(scr, BR_H2 + 16 * nt + r, 8 * g);
+      const bf16x8 a3 = r < NOUT ? lds_row8(scr, BR_D3 + r, 8 * g) : zero8;
+      aW3[nt] = mfma32(a3, bh2, aW3[nt]);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) aW2[mt][nt] = mfma32(lds_row8(scr, BR_D2 + 16 * mt + r, 8 * g), bh1, aW2[mt][nt]);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const bf16x8 bx = lds_row8(scr, BR_X + 16 * nt + r, 8 * g);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) aW1[mt][nt] = mfma32(lds_row8(scr, BR_D1 + 16 * mt + r, 8 * g), bx, aW1[mt][nt]);
+    }
+    wave_sync();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        ab1[a][b] += __shfl_xor(ab1[a][b], o, 16);
+        ab2[a][b] += __shfl_xor(ab2[a][b], o, 16);
+      }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) ab3[a] += __shfl_xor(ab3[a], o, 16);
+  __syncthreads();
+  float *bp = reinterpret_cast<float *>(ldsb);
+  for (int w = 0; w < kBwdWaves; ++w) {
+    if (wid == w) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = 16 * mt + 4 * g + i;
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt) {
+            const int e = OFF_W1 + m * NIN + 16 * nt + r;
+            bp[e] = (w ? bp[e] : 0.0f) + aW1[mt][nt][i];
+          }
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) {
+            const int e = OFF_W2 + m * NH + 16 * nt + r;
+            bp[e] = (w ? bp[e] : 0.0f) + aW2[mt][nt][i];
+          }
+          if (r == 0) {
+            bp[OFF_B1 + m] = (w ? bp[OFF_B1 + m] : 0.0f) + ab1[mt][i];
+            bp[OFF_B2 + m] = (w ? bp[OFF_B2 + m] : 0.0f) + ab2[mt][i];
+          }
+        }
+      if (g == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) {
+            const int e = OFF_W3 + i * NH + 16 * nt + r;
+            bp[e] = (w ? bp[e] : 0.0f) + aW3[nt][i];
+          }
+          if (r == 0) bp[OFF_B3 + i] = (w ? bp[OFF_B3 + i] : 0.0f) + ab3[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < NPARAM; e += kBwdBlock) partial[(int64_t)blockIdx.x * NPARAM + e] = bp[e];
+}
+
 // Sum of the block partials per parameter: 64 parameters x 16 partial groups
 // per workgroup; each thread sums its group in double with four independent
 // accumulators, then the 16 groups are combined in a fixed order (the
@@ -571,13 +800,18 @@ extern "C" int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb,
   if (S < 0 || ld < S || !params || !grad_params) return IA355_ERR_INVALID_ARG;
   if (flags & ~(uint32_t)IA355_OVERWRITE) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_sigma || !grad_rgb || !feat)) return IA355_ERR_INVALID_ARG;
-  if (dtype != IA355_F32 || feat_dtype != IA355_F32) return IA355_ERR_UNSUPPORTED;
+  if (!((dtype == IA355_F32 && feat_dtype == IA355_F32) || (dtype == IA355_BF16 && feat_dtype == IA355_BF16)))
+    return IA355_ERR_UNSUPPORTED;
   if (S == 0) return (flags & IA355_OVERWRITE) ? ia355_zero(grad_params, sizeof(float) * NPARAM, stream) : IA355_OK;
   if (!ws || ws_bytes < ia355_mlp_bwd_workspace_size(S)) return IA355_ERR_WORKSPACE;
   hipStream_t s = as_stream(stream);
   const int nb = bwd_blocks(S);
-  mlp_bwd_f32<<<nb, kBwdBlock, LDS_FLOATS * sizeof(float), s>>>(grad_sigma, grad_rgb, (const float *)feat, bone, S, ld,
-                                                                params, grad_feat, (float *)ws);
+  if (dtype == IA355_F32)
+    mlp_bwd_f32<<<nb, kBwdBlock, LDS_FLOATS * sizeof(float), s>>>(grad_sigma, grad_rgb, (const float *)feat, bone, S,
+                                                                  ld, params, grad_feat, (float *)ws);
+  else
+    mlp_bwd_bf16<<<nb, kBwdBlock, LDS_BF_BYTES, s>>>(grad_sigma, grad_rgb, (const __hip_bfloat16 *)feat, bone, S, ld,
+                                                     params, grad_feat, (float *)ws);
   reduce_partials<<<(unsigned)ceil_div(NPARAM, kRedP), kRedP * kRedG, 0, s>>>((const float *)ws, nb, grad_params,
                                                                                      (flags & IA355_OVERWRITE) != 0);
   return launch_status();

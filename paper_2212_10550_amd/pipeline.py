@@ -50,7 +50,7 @@ class StageTimer:
 
 class Pipeline:
     def __init__(self, w, device="cuda", table_dtype=torch.float32, mlp_dtype=K.F32, cap=None,
-                 grad_W=True, grad_B=True):
+                 grad_W=True, grad_B=True, rootinit_params=None, rootinit_dtype=K.BF16):
         self.w = w
         self.dev = torch.device(device)
         dev = self.dev
@@ -118,6 +118,12 @@ class Pipeline:
         self.ws_ift = e(K.deform_bwd_workspace_size(cap, Dx, Dy, Dz, nb), dt=torch.uint8)
         self.S = None
         self.timer = None  # optional StageTimer: HIP events around each stage
+        # learned root initialiser (guided solve with multi-init fallback)
+        self.guided = None
+        if rootinit_params is not None:
+            from .rootinit import GuidedDeform
+            self.pose_t = t(w.pose_params.reshape(-1), torch.float32)
+            self.guided = GuidedDeform(rootinit_params, w, cap, device=device, dtype=rootinit_dtype)
 
     def _mark(self, name):
         if self.timer is not None:
@@ -140,8 +146,12 @@ class Pipeline:
     def field(self, S):
         w = self.w
         self._mark("deform")
-        K.snarf_deform(self.xs, S, self.cap, self.B, self.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop,
-                       w.tol_valid, self.xc, self.bone, self.resid, self.steps, self.ws_deform)
+        if self.guided is not None:
+            self.guided.run(self.xs, S, self.cap, self.pose_t, self.B, self.W, self.xc, self.bone, self.resid,
+                            self.steps)
+        else:
+            K.snarf_deform(self.xs, S, self.cap, self.B, self.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop,
+                           w.tol_valid, self.xc, self.bone, self.resid, self.steps, self.ws_deform)
         feat = self.feat[: w.L * S * 2]
         self._mark("hash_fwd")
         K.hashgrid_encode(self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth, w.hash_aabb, feat)

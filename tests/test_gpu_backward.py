@@ -199,3 +199,34 @@ def test_train_step_subset(orc):
         ("grad_B", host(p.grad_B)), ("grad_W", host(p.grad_W))]}
     print(f"train subset: S={S} loss={float(p.loss.item()):.6f} root err {dx:.2e} tol {tol:.2e} "
           + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+
+
+def test_mlp_bwd_bf16(orc):
+    """BF16 MLP backward (BF16 MFMA, FP32 accumulate) against the oracle on
+    the BF16-rounded features and weights.  The kernel also rounds the hidden
+    activations and the intermediate gradients d2, d1 to BF16, and takes the
+    ReLU decisions on those rounded values (the oracle keeps FP64
+    activations), so the error is reported and held to a norm-wise sanity
+    bar of 1e-1 per parameter block; the reduced-precision acceptance bar is
+    the pixel one (mean 1e-3)."""
+    K = _K()
+    S = 4099
+    rng = np.random.default_rng(12)
+    feat = rng.normal(0, 0.5, (S, 32)).astype(np.float32)
+    params = synth.make_mlp(seed=3, sigma_bias=0.3).astype(np.float32)
+    gsig = rng.normal(size=S).astype(np.float32)
+    grgb = rng.normal(size=(S, 3)).astype(np.float32)
+    fb = up(feat.reshape(S, 16, 2).transpose(1, 0, 2).reshape(-1), torch.bfloat16)
+    gp = torch.empty(6532, device=dev())
+    gf = torch.empty(16 * S * 2, device=dev())
+    ws = torch.empty(K.mlp_bwd_workspace_size(S), dtype=torch.uint8, device=dev())
+    K.mlp_bwd(up(gsig), soa(grgb), fb, None, S, S, up(params), K.BF16, gp, gf, ws, flags=K.OVERWRITE)
+    torch.cuda.synchronize()
+    feat_b = host(fb).reshape(16, S, 2).transpose(1, 0, 2).reshape(S, 32)
+    params_b = host(up(params).bfloat16())
+    rp, rf = orc.mlp_bwd(gsig, grgb, feat_b, params_b)
+    got = host(gp)
+    offs = [0, 2048, 2112, 6208, 6272, 6528, 6532]
+    errs = [normclose(got[a:b], rp[a:b], 1e-1, f"bf16 grad_params[{a}:{b}]") for a, b in zip(offs[:-1], offs[1:])]
+    ef = normclose(host(gf).reshape(16, S, 2).transpose(1, 0, 2).reshape(S, 32), rf, 1e-1, "bf16 grad_feat")
+    print(f"bf16 mlp bwd: param block errors {', '.join(f'{e:.1e}' for e in errs)}; grad_feat {ef:.1e}")

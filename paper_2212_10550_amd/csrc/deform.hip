@@ -535,12 +535,33 @@ __global__ void __launch_bounds__(kConBlock) ift_contract_kernel(const float *__
   }
 }
 
-__global__ void ift_b_kernel(const float *__restrict__ partB, int nblk, int n, float *__restrict__ gB, int overwrite) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  double s = 0.0;
-  for (int q = 0; q < nblk; ++q) s += (double)partB[(int64_t)q * n + p];
-  gB[p] = overwrite ? (float)(-s) : gB[p] - (float)s;
+// Sum of the dL/dB block partials: 64 entries x 16 partial groups per
+// workgroup, each group summed in double with four accumulators, the groups
+// combined in a fixed order.
+constexpr int kRedP = 64, kRedG = 16;
+__global__ void __launch_bounds__(kRedP *kRedG) ift_b_kernel(const float *__restrict__ partB, int nblk, int n,
+                                                             float *__restrict__ gB, int overwrite) {
+  __shared__ double part[kRedG][kRedP];
+  const int pl = threadIdx.x % kRedP, grp = threadIdx.x / kRedP;
+  const int p = blockIdx.x * kRedP + pl;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (p < n) {
+    int q = grp;
+    for (; q + 3 * kRedG < nblk; q += 4 * kRedG) {
+      a0 += (double)partB[(int64_t)q * n + p];
+      a1 += (double)partB[(int64_t)(q + kRedG) * n + p];
+      a2 += (double)partB[(int64_t)(q + 2 * kRedG) * n + p];
+      a3 += (double)partB[(int64_t)(q + 3 * kRedG) * n + p];
+    }
+    for (; q < nblk; q += kRedG) a0 += (double)partB[(int64_t)q * n + p];
+  }
+  part[grp][pl] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (grp == 0 && p < n) {
+    double sum = 0.0;
+    for (int g2 = 0; g2 < kRedG; ++g2) sum += part[g2][pl];
+    gB[p] = overwrite ? (float)(-sum) : gB[p] - (float)sum;
+  }
 }
 
 Grid make_grid(int Dx, int Dy, int Dz, const float *aabb) {
@@ -673,7 +694,8 @@ extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc,
       ift_q_kernel<<<(unsigned)ceil_div(S * 64, kOwnBlock), kOwnBlock, 0, s>>>(xc, bone, vbuf, S, ld, g, Q);
     ift_contract_kernel<<<(unsigned)nblk, kConBlock, 0, s>>>(Q, B, nb, W, nvert, grad_W, grad_B ? partB : nullptr,
                                                              overwrite);
-    if (grad_B) ift_b_kernel<<<(unsigned)ceil_div(nb * 12, 256), 256, 0, s>>>(partB, nblk, nb * 12, grad_B, overwrite);
+    if (grad_B)
+      ift_b_kernel<<<(unsigned)ceil_div(nb * 12, kRedP), kRedP * kRedG, 0, s>>>(partB, nblk, nb * 12, grad_B, overwrite);
   }
   return launch_status();
 }

@@ -158,6 +158,71 @@ def frame_leg(args, torch, np, K, synth, Pipeline, out):
     return params
 
 
+def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
+    """Tiny FP32 forward; empty-space skipping on/off (the synthetic analogue
+    of Tab. 3); hash encode at T = 2^23 (FP16 table, 512 MiB)."""
+    # tiny forward: 1024 rays x 64 samples, no occupancy grid, FP32
+    wt = synth.tiny_forward()
+    pt = Pipeline(wt, device="cuda:0")
+    ms, S = time_forward(pt, 20, torch)
+    out["tiny_forward_f32"] = {"workload": "1024 front-face rays x 64 samples, 32^3x24 skinning grid, hash 2^14 FP32",
+                               "ms": ms, "posed_samples": S, "samples_per_s": S / (ms * 1e-3)}
+    del pt
+    # empty-space skipping off: every cell occupied (Sec. 3.3, Tab. 3)
+    w = synth.train_step()
+    wd = synth.train_step()
+    wd.occ = np.ones_like(w.occ)
+    res = {}
+    for tag, wl in (("with_skipping", w), ("without_skipping", wd)):
+        pd = Pipeline(wl, device="cuda:0")
+        for _ in range(2):
+            pd.train_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            Sd = pd.train_step()
+        torch.cuda.synchronize()
+        res[tag] = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / 5, "posed_samples": Sd}
+        del pd
+    wf = synth.full_frame()
+    wfd = synth.full_frame()
+    wfd.occ = np.ones_like(wf.occ)
+    for tag, wl in (("frame_with_skipping", wf), ("frame_without_skipping", wfd)):
+        pf = Pipeline(wl, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16, rootinit_params=params)
+        msf, Sf = time_forward(pf, 3, torch)
+        res[tag] = {"ms_per_frame": msf, "posed_samples": Sf, "dtype": "f16/bf16, learned init"}
+        del pf
+    res["training_speedup"] = res["without_skipping"]["ms_per_step"] / res["with_skipping"]["ms_per_step"]
+    res["render_speedup"] = res["frame_without_skipping"]["ms_per_frame"] / res["frame_with_skipping"]["ms_per_frame"]
+    res["paper_context"] = "Tab. 3 on RTX 3090: training 3m10s -> 1m47s, rendering ~1 -> ~15 FPS with skipping"
+    out["empty_space_skipping"] = res
+    # hash grid at T = 2^23 entries per level (FP16, 512 MiB): gathers reach HBM
+    S = 1 << 20
+    x = torch.rand(3, S, device="cuda:0")
+    table = (torch.rand(16, 1 << 23, 2, device="cuda:0") - 0.5).half()
+    feat = torch.empty(16 * S * 2, dtype=torch.bfloat16, device="cuda:0")
+    gt = torch.empty(16, 1 << 23, 2, device="cuda:0")
+    gf = torch.randn(16 * S * 2, device="cuda:0")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(2):
+        ev[0].record()
+        for _ in range(5):
+            K.hashgrid_encode(x, None, S, S, table, 16.0, 1.38, (0, 0, 0, 1, 1, 1), feat)
+        ev[1].record()
+        for _ in range(2):
+            K.hashgrid_encode_bwd(gf, x, None, S, S, table, 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, None, K.OVERWRITE)
+        ev[2].record()
+    torch.cuda.synchronize()
+    fwd_ms = ev[0].elapsed_time(ev[1]) / 5
+    bwd_ms = ev[1].elapsed_time(ev[2]) / 2
+    fwd_bytes = (16 * 8 * 2 * 2 + 12 + 16 * 2 * 2) * S
+    out["hash_stress_2e23"] = {"points": S, "table": "16 x 2^23 x 2 FP16 (512 MiB)", "fwd_ms": fwd_ms,
+                               "fwd_algorithmic_GBs": fwd_bytes / (fwd_ms * 1e-3) / 1e9,
+                               "fwd_frac_of_hbm_peak": fwd_bytes / (fwd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                               "bwd_table_ms_incl_zero_fill": bwd_ms}
+    del table, gt
+
+
 def learned_init_leg(params, torch, np, K, synth, out):
     """Held-out poses: guided solve vs 24-init solve on the same points."""
     from paper_2212_10550_amd import rootinit
@@ -293,6 +358,8 @@ def main():
         params = frame_leg(args, torch, np, K, synth, Pipeline, out)
         log("learned initialiser on held-out poses")
         learned_init_leg(params, torch, np, K, synth, out)
+        log("tiny forward, skipping on/off, hash stress")
+        extra_legs(args, params, torch, np, K, synth, Pipeline, out)
     if not args.no_cpu_baseline:
         log("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w)

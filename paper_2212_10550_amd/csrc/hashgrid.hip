@@ -204,13 +204,13 @@ constexpr int kTgBlock = 256;
 __global__ void __launch_bounds__(kTgBlock) table_grad_kernel(const float *__restrict__ gfeat,
                                                              const float *__restrict__ xc,
                                                              const int16_t *__restrict__ bone, int64_t S, int64_t ld,
-                                                             int L, int log2T, Levels lv, Box box,
+                                                             int l0, int L, int log2T, Levels lv, Box box,
                                                              float *__restrict__ gtable) {
   const int64_t t = (int64_t)blockIdx.x * kTgBlock + threadIdx.x;
   const int64_t item = t >> 4;
-  if (item >= (int64_t)L * S) return;
-  const int level = (int)(item / S);
-  const int64_t n = item - (int64_t)level * S;
+  if (item >= (int64_t)(L - l0) * S) return;
+  const int level = l0 + (int)(item / S);
+  const int64_t n = item - (int64_t)(level - l0) * S;  // 0 <= n < S
   if (bone && bone[n] < 0) return;
   const int sub = (int)(t & 15), k = sub >> 1, f = sub & 1;
   const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
@@ -219,6 +219,60 @@ __global__ void __launch_bounds__(kTgBlock) table_grad_kernel(const float *__res
   level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
   const float g = gfeat[2 * ((int64_t)level * S + n) + f];
   atomicAdd(gtable + 2 * ((int64_t)level * T + c.idx[k]) + f, c.w[k] * g);
+}
+
+// Dense (coarse) levels: many consecutive samples fall in the same cell, so
+// the same table entries are hit again and again (atomic contention).  One
+// lane per sample (a wave = 64 consecutive samples of one level); for each
+// corner the lanes are segmented into runs of equal table index and a
+// segmented wave scan sums each run, so only the last lane of a run issues
+// the atomic adds.
+constexpr int kDgBlock = 256;
+constexpr int kAggMaxRes = 32;  // finest resolution handled by run aggregation
+
+__global__ void __launch_bounds__(kDgBlock) table_grad_dense_kernel(const float *__restrict__ gfeat,
+                                                                   const float *__restrict__ xc,
+                                                                   const int16_t *__restrict__ bone, int64_t S,
+                                                                   int64_t ld, int64_t chunks, int log2T, Levels lv,
+                                                                   Box box, float *__restrict__ gtable) {
+  const int level = (int)(blockIdx.x / chunks);
+  const int64_t n = (blockIdx.x % chunks) * kDgBlock + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool act = n < S && (!bone || bone[n] >= 0);
+  const uint32_t T = 1u << log2T;
+  Corners c;
+  float2 g = make_float2(0.0f, 0.0f);
+  if (act) {
+    const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
+    level_cell(x, box, lv.res[level], true, T - 1u, c, false);
+    g = reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * S + n];
+  }
+  float *gl = gtable + (int64_t)level * T * 2;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int key = act ? (int)c.idx[k] : -1 - lane;  // inactive lanes: unique keys, no atomics
+    float v0 = act ? c.w[k] * g.x : 0.0f, v1 = act ? c.w[k] * g.y : 0.0f;
+    const int prev = __shfl_up(key, 1, kWave);
+    int hs = (lane == 0 || prev != key) ? lane : 0;  // run head index
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int t = __shfl_up(hs, o, kWave);
+      if (lane >= o) hs = max(hs, t);
+    }
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const float t0 = __shfl_up(v0, o, kWave), t1 = __shfl_up(v1, o, kWave);
+      if (lane - o >= hs) {
+        v0 += t0;
+        v1 += t1;
+      }
+    }
+    const int next = __shfl_down(key, 1, kWave);
+    if ((lane == kWave - 1 || next != key) && key >= 0) {
+      atomicAdd(gl + 2 * key, v0);
+      atomicAdd(gl + 2 * key + 1, v1);
+    }
+  }
 }
 
 int32_t make_levels(int L, int log2T, double base, double growth, Levels *lv) {
@@ -296,9 +350,21 @@ extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float
     const int32_t st = ia355_zero(grad_table, sizeof(float) * 2 * (size_t)L * ((size_t)1 << log2T), stream);
     if (st != IA355_OK) return st;
   }
-  if (grad_table && S > 0)
-    table_grad_kernel<<<(unsigned)ceil_div((int64_t)L * S * 16, kTgBlock), kTgBlock, 0, s>>>(
-        grad_feat, xc, bone, S, ld, L, log2T, lv, box, grad_table);
+  if (grad_table && S > 0) {
+    // Run aggregation pays while a cell spans several ray steps (coarse
+    // dense levels, which come first as the resolution grows with the level);
+    // finer levels use the 16-lanes-per-item mapping.
+    int ndense = 0;
+    while (ndense < L && lv.dense[ndense] && lv.res[ndense] <= kAggMaxRes) ++ndense;
+    if (ndense > 0) {
+      const int64_t chunks = ceil_div(S, kDgBlock);
+      table_grad_dense_kernel<<<(unsigned)(chunks * ndense), kDgBlock, 0, s>>>(grad_feat, xc, bone, S, ld, chunks,
+                                                                               log2T, lv, box, grad_table);
+    }
+    if (ndense < L)
+      table_grad_kernel<<<(unsigned)ceil_div((int64_t)(L - ndense) * S * 16, kTgBlock), kTgBlock, 0, s>>>(
+          grad_feat, xc, bone, S, ld, ndense, L, log2T, lv, box, grad_table);
+  }
   if (grad_xc && S > 0) {
     const int64_t blocks = ceil_div(S * 16, kBwdBlock);
     if (table_dtype == IA355_F32)

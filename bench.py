@@ -35,76 +35,185 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VEC_TFLOPS = 157.3
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 
-# Algorithmic work per unit (counted from the kernels)
+# Algorithmic work per unit, counted from the method (not from the kernels'
+# actual traffic); the per-stage table of the JSON line uses these.
 DEFORM_FLOP_PER_INIT = 670.0   # start point, Jacobian, inverse
 DEFORM_FLOP_PER_STEP = 380.0   # one Broyden step (residual 290 + update 90)
-HASH_FWD_BYTES = 16 * 8 * 2 * 4 + 12 + 16 * 2 * 4       # FP32 gathers + x + features
-HASH_BWD_BYTES = 2 * 16 * 8 * 2 * 4 + 12 + 16 * 2 * 4   # read-modify-write of the touched entries
+HASH_GATHER_BYTES = {4: 16 * 8 * 2 * 4, 2: 16 * 8 * 2 * 2}  # 16 levels x 8 corners x 2 features
+FEAT_BYTES = {4: 16 * 2 * 4, 2: 16 * 2 * 2}
+# backward: read-modify-write of the 256 touched FP32 entries, dL/dfeat and x
+# read, the table gather for dL/dx and its write
+HASH_BWD_BYTES = 2 * 16 * 8 * 2 * 4 + 16 * 2 * 4 + 12
+HASH_BWD_X_BYTES = 16 * 8 * 2 * 4 + 12
 IFT_BYTES_PER_SAMPLE = 2 * 8 * 12 * 4 + 24 + 12 + 8 * 24 * 4  # moment RMW + x, v, u + skinning rows
+MLP_FWD_FLOP = 12800.0
 MLP_BWD_FLOP = 25600.0 + 12800.0  # backward plus the recomputed forward
+MARCH_BYTES_PER_SAMPLE, MARCH_BYTES_PER_RAY = 20, 56
+RENDER_FWD_BYTES_PER_SAMPLE, RENDER_BWD_BYTES_PER_SAMPLE, RENDER_BYTES_PER_RAY = 16, 32, 40
+
+# kernels of each stage (names as rocprofv3 reports them)
+STAGE_KERNELS = {
+    "march": ["march_count", "march_scan", "march_fill"],
+    "deform": ["blend_kernel", "solve_kernel", "guided_kernel", "fallback_kernel", "rootinit_kernel"],
+    "hash_fwd": ["encode_kernel"],
+    "mlp_fwd": ["mlp_fwd_f32", "mlp_fwd_bf16"],
+    "render_fwd": ["render_fwd"],
+    "loss+render_bwd": ["l2_loss_kernel", "render_bwd"],
+    "mlp_bwd": ["mlp_bwd_f32", "mlp_bwd_bf16", "reduce_partials"],
+    "hash_bwd": ["bin_kernel", "slice_total_kernel", "plan_kernel", "accumulate_kernel", "table_grad_kernel",
+                 "table_grad_dense_kernel", "encode_bwd_kernel"],
+    "deform_bwd": ["ift_v_kernel", "ift_q_kernel", "ift_contract_kernel", "ift_b_kernel"],
+}
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "training_step_f32_hbm_traffic.md")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, budget_s=10.0):
+def cpu_baseline(w, budget_s=10.0, single_core_budget_s=8.0):
     """The FP64 oracle's training step on the same workload, repeated until
-    about budget_s seconds of host time have passed (at least once), on the
-    host's cores; posed samples/s over those runs."""
+    about budget_s seconds of host time have passed (at least once), on all
+    the host's cores; then on one core.  Posed samples/s over those runs."""
     import oracle
     oracle.lib()
-    runs, samples = 0, 0
-    t0 = time.perf_counter()
-    while True:
-        ref = oracle.train_step(w)
-        samples += ref["march"]["xs"].shape[0]
-        runs += 1
-        dt = time.perf_counter() - t0
-        if dt >= budget_s or dt * (runs + 1) / runs > 3 * budget_s:
-            break
-    return {"value": samples / dt, "unit": "posed samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+
+    def run(budget):
+        runs, samples = 0, 0
+        t0 = time.perf_counter()
+        while True:
+            ref = oracle.train_step(w)
+            samples += ref["march"]["xs"].shape[0]
+            runs += 1
+            dt = time.perf_counter() - t0
+            if dt >= budget or dt * (runs + 1) / runs > 3 * budget:
+                return samples, runs, dt
+
+    cores = oracle.num_threads()
+    samples, runs, dt = run(budget_s)
+    oracle.set_num_threads(1)
+    s1, r1, d1 = run(single_core_budget_s)
+    oracle.set_num_threads(cores)
+    return {"value": samples / dt, "unit": "posed samples/s", "cores": cores, "kind": "oracle",
             "sample": f"the full training step ({w.R} rays, {samples // runs} posed samples), forward + every "
-                      f"backward, {runs} run(s) in {dt:.1f} s"}
+                      f"backward, {runs} run(s) in {dt:.1f} s",
+            "single_core": {"value": s1 / d1, "runs": r1, "seconds": round(d1, 1)},
+            "host_cpu": _cpu_model()}
 
 
-def roofline(stage_ms, S, steps_total, nb):
-    dom = max(stage_ms, key=stage_ms.get)
-    t = stage_ms[dom] * 1e-3
-    if dom == "deform":
-        work = DEFORM_FLOP_PER_INIT * nb * S + DEFORM_FLOP_PER_STEP * steps_total
-        ach = work / t / 1e12
-        return {"kernel": "snarf_deform (solve_kernel + blend_kernel)", "bound": "alu", "achieved": ach,
-                "peak": PEAK_FP32_VEC_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VEC_TFLOPS,
-                "traffic": None, "work_per_launch": work, "work_unit": "flop"}
-    if dom == "mlp_bwd":
-        work = MLP_BWD_FLOP * S
-        ach = work / t / 1e12
-        return {"kernel": "mlp_bwd_f32", "bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None, "work_per_launch": work,
-                "work_unit": "flop"}
-    per = {"hash_bwd": HASH_BWD_BYTES, "hash_fwd": HASH_FWD_BYTES, "deform_bwd": IFT_BYTES_PER_SAMPLE}.get(dom)
-    kern = {"hash_bwd": "table_grad_kernel + encode_bwd_kernel", "hash_fwd": "encode_kernel",
-            "deform_bwd": "ift_v/ift_q/ift_contract kernels"}.get(dom, dom)
-    if per is None:
-        return {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
-                "traffic": None}
-    work = per * S
-    ach = work / t / 1e9
-    return {"kernel": kern, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": ach / PEAK_HBM_GBS, "traffic": None, "work_per_launch": work, "work_unit": "bytes"}
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
-def time_forward(p, n, torch):
+def source_digest():
+    """Digest of the library's kernel sources; counter figures taken from
+    other sources are stale."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2212_10550_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(stage):
+    """HBM bytes per launch of a stage's kernels from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each divided by the factor a plain
+    copy kernel of known size reads), or None when the summary is missing or
+    the kernel sources changed since the counters were taken."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            txt = f.read()
+        blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_digest") != source_digest():
+        return None
+    per = blob["kernels"]
+    tot, seen = 0.0, False
+    for name, rec in per.items():
+        if any(k in name for k in STAGE_KERNELS.get(stage, [])):
+            tot += rec["fetch_kib"] * 1024 / blob["copy_factor_fetch"] + rec["write_kib"] * 1024 / blob["copy_factor_write"]
+            seen = True
+    return tot if seen else None
+
+
+def stage_rooflines(stage_ms, S, R, steps_total, nb, es, mlp_bf16, backward=True, fallback_steps=None):
+    """One roofline entry per stage: algorithmic work / stage time against
+    the bound the stage's work sits on."""
+    out = {}
+
+    def put(name, bound, work, unit_work):
+        if name not in stage_ms or stage_ms[name] <= 0:
+            return
+        t = stage_ms[name] * 1e-3
+        if bound == "hbm":
+            ach, peak, unit = work / t / 1e9, PEAK_HBM_GBS, "GB/s"
+        elif bound == "mfma":
+            peak = PEAK_BF16_MFMA_TFLOPS if mlp_bf16 else PEAK_FP32_MFMA_TFLOPS
+            ach, unit = work / t / 1e12, "TFLOP/s"
+        else:
+            ach, peak, unit = work / t / 1e12, PEAK_FP32_VEC_TFLOPS, "TFLOP/s"
+        out[name] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                     "ms": stage_ms[name], "work_per_launch": work, "work_unit": unit_work}
+
+    put("march", "hbm", MARCH_BYTES_PER_SAMPLE * S + MARCH_BYTES_PER_RAY * R, "bytes")
+    if steps_total is not None:
+        put("deform", "alu", DEFORM_FLOP_PER_INIT * nb * S + DEFORM_FLOP_PER_STEP * steps_total, "flop")
+    put("hash_fwd", "hbm", (HASH_GATHER_BYTES[es] + 12 + FEAT_BYTES[2 if mlp_bf16 else 4]) * S, "bytes")
+    put("mlp_fwd", "mfma", MLP_FWD_FLOP * S, "flop")
+    put("render_fwd", "hbm", RENDER_FWD_BYTES_PER_SAMPLE * S + RENDER_BYTES_PER_RAY * R, "bytes")
+    if backward:
+        put("loss+render_bwd", "hbm", RENDER_BWD_BYTES_PER_SAMPLE * S + 2 * RENDER_BYTES_PER_RAY * R, "bytes")
+        put("mlp_bwd", "mfma", MLP_BWD_FLOP * S, "flop")
+        put("hash_bwd", "hbm", (HASH_BWD_BYTES + HASH_BWD_X_BYTES) * S, "bytes")
+        put("deform_bwd", "hbm", IFT_BYTES_PER_SAMPLE * S, "bytes")
+    return out
+
+
+def roofline(stage_ms, S, R, steps_total, nb):
+    """The contract's roofline object for the dominant stage of the FP32
+    training step (its kernels are listed; the duration is the stage's, HIP
+    events on the launch stream)."""
+    table = stage_rooflines(stage_ms, S, R, steps_total, nb, 4, False)
+    dom = max(table, key=lambda k: table[k]["ms"])
+    r = dict(table[dom])
+    r = {"stage": dom, "kernels": STAGE_KERNELS.get(dom, [dom]), "bound": r["bound"], "achieved": r["achieved"],
+         "peak": r["peak"], "unit": r["unit"], "frac": r["frac"], "traffic": pmc_traffic(dom),
+         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
+         "work_per_launch": r["work_per_launch"], "work_unit": r["work_unit"], "ms_per_launch": r["ms"]}
+    return r, table
+
+
+def time_forward(p, n, torch, stages=False):
+    """ms per forward over n runs after 2 warm-ups; with stages, also the
+    per-stage ms (HIP events on the launch stream) of those runs."""
+    from paper_2212_10550_amd.pipeline import StageTimer
     for _ in range(2):
         p.forward()
     torch.cuda.synchronize()
+    timer = StageTimer() if stages else None
+    p.timer = timer
     t0 = time.perf_counter()
     for _ in range(n):
         S = p.forward()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / n, S
+    ms = (time.perf_counter() - t0) * 1e3 / n
+    p.timer = None
+    if stages:
+        return ms, S, {k: v / n for k, v in timer.totals_ms().items()}
+    return ms, S
 
 
 def frame_leg(args, torch, np, K, synth, Pipeline, out):
@@ -119,13 +228,13 @@ def frame_leg(args, torch, np, K, synth, Pipeline, out):
     del data
     # FP32 multi-init reference frame
     p32 = Pipeline(wf, device="cuda:0")
-    ms32, S = time_forward(p32, 5, torch)
+    ms32, S, st32 = time_forward(p32, 5, torch, stages=True)
     c32 = p32.color.double().cpu().numpy()
     steps32 = int(p32.steps[:S].to(torch.int64).sum().item())
     del p32
     # FP16 table + BF16 MLP + learned initialiser
     pmx = Pipeline(wf, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16, rootinit_params=params)
-    msmx, Smx = time_forward(pmx, 5, torch)
+    msmx, Smx, stmx = time_forward(pmx, 5, torch, stages=True)
     cmx = pmx.color.double().cpu().numpy()
     stepsmx = int(pmx.steps[:Smx].to(torch.int64).sum().item())
     fb = int(pmx.guided.n_fallback.item())
@@ -142,8 +251,13 @@ def frame_leg(args, torch, np, K, synth, Pipeline, out):
                     "24-bone pose, hash T=2^19",
         "posed_samples": S, "samples_after_termination": used,
         "f32_multi_init": {"ms_per_frame": ms32, "fps": 1e3 / ms32, "broyden_steps": steps32,
+                           "stages_ms": {k: round(v, 4) for k, v in st32.items()},
+                           "stage_roofline": stage_rooflines(st32, S, wf.R, steps32, 24, 4, False, backward=False),
                            "pixel_err_vs_oracle": {"mean": float(e32.mean()), "max": float(e32.max())}},
         "f16_bf16_learned_init": {"ms_per_frame": msmx, "fps": 1e3 / msmx, "broyden_steps": stepsmx,
+                                  "stages_ms": {k: round(v, 4) for k, v in stmx.items()},
+                                  "stage_roofline": stage_rooflines(stmx, Smx, wf.R, None, 24, 2, True,
+                                                                    backward=False),
                                   "fallback_samples": fb,
                                   "pixel_err_vs_oracle": {"mean": float(emx.mean()),
                                                           "p99.9": float(np.quantile(emx, 0.999)),
@@ -203,6 +317,7 @@ def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
     feat = torch.empty(16 * S * 2, dtype=torch.bfloat16, device="cuda:0")
     gt = torch.empty(16, 1 << 23, 2, device="cuda:0")
     gf = torch.randn(16 * S * 2, device="cuda:0")
+    wsb = torch.empty(K.hashgrid_bwd_workspace_size(S, 16, 23), dtype=torch.uint8, device="cuda:0")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     for _ in range(2):
         ev[0].record()
@@ -210,7 +325,8 @@ def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
             K.hashgrid_encode(x, None, S, S, table, 16.0, 1.38, (0, 0, 0, 1, 1, 1), feat)
         ev[1].record()
         for _ in range(2):
-            K.hashgrid_encode_bwd(gf, x, None, S, S, table, 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, None, K.OVERWRITE)
+            K.hashgrid_encode_bwd(gf, x, None, S, S, table, 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, None, K.OVERWRITE,
+                                  ws=wsb)
         ev[2].record()
     torch.cuda.synchronize()
     fwd_ms = ev[0].elapsed_time(ev[1]) / 5
@@ -220,7 +336,7 @@ def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
                                "fwd_algorithmic_GBs": fwd_bytes / (fwd_ms * 1e-3) / 1e9,
                                "fwd_frac_of_hbm_peak": fwd_bytes / (fwd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                                "bwd_table_ms_incl_zero_fill": bwd_ms}
-    del table, gt
+    del table, gt, wsb
 
 
 def learned_init_leg(params, torch, np, K, synth, out):
@@ -271,6 +387,96 @@ def learned_init_leg(params, torch, np, K, synth, out):
     }
 
 
+def mixed_leg(args, w, S0, steps_total, nb, loss32, gp32, torch, np, K, Pipeline, StageTimer, out):
+    """The training step with the FP16 table and the BF16 MLP (forward and
+    backward), FP32 deform and compositing."""
+    pm = Pipeline(w, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16)
+    for _ in range(args.warmup):
+        pm.train_step()
+    torch.cuda.synchronize()
+    tm = StageTimer()
+    pm.timer = tm
+    t0 = time.perf_counter()
+    sm = 0
+    for _ in range(args.steps):
+        sm += pm.train_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pm.timer = None
+    stm = {k: v / args.steps for k, v in tm.totals_ms().items()}
+    gpm = pm.grad_params.double().cpu().numpy()
+    out["mixed_training_step"] = {
+        "dtype": "f16 table, bf16 MLP (MFMA, f32 accumulate), f32 deform and compositing",
+        "value": sm / (t1 - t0), "unit": "posed samples/s", "ms_per_step": (t1 - t0) * 1e3 / args.steps,
+        "stages_ms": {k: round(v, 4) for k, v in stm.items()},
+        "stage_roofline": stage_rooflines(stm, S0, w.R, steps_total, nb, 2, True),
+        "loss_rel_diff_vs_f32": abs(float(pm.loss.item()) - loss32) / abs(loss32),
+        "mlp_grad_rel_l2_diff_vs_f32": float(np.linalg.norm(gpm - gp32) / np.linalg.norm(gp32))}
+
+
+def short_kernel_name(name):
+    name = name.strip().strip('"')
+    if name.startswith("void "):
+        name = name[5:]
+    name = name.replace("(anonymous namespace)::", "")
+    return name.split("(", 1)[0]
+
+
+def pmc_summary(fetch_dir, write_dir):
+    """Per-kernel FETCH_SIZE / WRITE_SIZE (KiB per dispatch) from two
+    rocprofv3 --pmc runs, and the copy-kernel factors; printed as the JSON
+    block the profile summary holds."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        per = {}
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as f:
+                for row in csv.DictReader(f):
+                    if row.get("Counter_Name") != counter:
+                        continue
+                    key = (fn, row["Dispatch_Id"])
+                    name = short_kernel_name(row["Kernel_Name"])
+                    v = per.setdefault(key, [name, 0.0])
+                    v[1] += float(row["Counter_Value"])
+        agg = {}
+        for name, v in per.values():
+            a = agg.setdefault(name, [0, 0.0])
+            a[0] += 1
+            a[1] += v
+        return {k: (n, tot / n) for k, (n, tot) in agg.items()}
+
+    fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy = [k for k in fe if "MulFunctor" in k]
+    if not copy:
+        raise SystemExit("no copy-calibration kernel in the counter runs")
+    nbytes = COPY_CAL_FLOATS * 4
+    out = {"source_digest": source_digest(),
+           "copy_kernel": copy[0], "copy_bytes_each_way": nbytes,
+           "copy_factor_fetch": fe[copy[0]][1] * 1024 / nbytes, "copy_factor_write": wr[copy[0]][1] * 1024 / nbytes,
+           "kernels": {}}
+    for k in sorted(fe):
+        if k in copy:
+            continue
+        out["kernels"][k] = {"dispatches": fe[k][0], "fetch_kib": round(fe[k][1], 1),
+                             "write_kib": round(wr.get(k, (0, 0.0))[1], 1)}
+    print(json.dumps(out, indent=1))
+
+
+COPY_CAL_FLOATS = 64 << 20  # 256 MiB read and written by the calibration copy
+
+
+def copy_calibration(torch):
+    """A plain elementwise copy of known size (read 256 MiB, write 256 MiB),
+    for scaling the HBM byte counters."""
+    src = torch.empty(COPY_CAL_FLOATS, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,7 +486,15 @@ def main():
     ap.add_argument("--no-frame", action="store_true")
     ap.add_argument("--init-poses", type=int, default=256)
     ap.add_argument("--init-epochs", type=int, default=20)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP16/BF16 training-step leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain copy kernel of known size (for scaling rocprofv3 byte counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc output folders (no GPU needed) and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this path runs on one GPU; multi-GPU runs are not part of this build "
                                    "(see the sharding notes in DESIGN.md)", "n_gpus": args.gpus}))
@@ -329,30 +543,16 @@ def main():
                                "24-init Broyden (<=10 steps), L2 loss, every backward pass incl. the IFT",
                    "rays": w.R, "posed_samples_per_step": S0, "broyden_steps_per_step": steps_total},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "roofline": roofline(stage_ms, S0, steps_total, nb),
-        "hash_fwd_algorithmic_GBs": HASH_FWD_BYTES * S0 / (stage_ms["hash_fwd"] * 1e-3) / 1e9,
     }
+    out["roofline"], out["stage_roofline"] = roofline(stage_ms, S0, w.R, steps_total, nb)
     loss32 = float(p.loss.item())
     gp32 = p.grad_params.double().cpu().numpy()
     del p
     # the same step with FP16 hash features and the BF16 MLP (forward and backward)
-    pm = Pipeline(w, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16)
-    for _ in range(args.warmup):
-        pm.train_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sm = 0
-    for _ in range(args.steps):
-        sm += pm.train_step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    gpm = pm.grad_params.double().cpu().numpy()
-    out["mixed_training_step"] = {
-        "dtype": "f16 table, bf16 MLP (MFMA, f32 accumulate), f32 deform and compositing",
-        "value": sm / (t1 - t0), "unit": "posed samples/s", "ms_per_step": (t1 - t0) * 1e3 / args.steps,
-        "loss_rel_diff_vs_f32": abs(float(pm.loss.item()) - loss32) / abs(loss32),
-        "mlp_grad_rel_l2_diff_vs_f32": float(np.linalg.norm(gpm - gp32) / np.linalg.norm(gp32))}
-    del pm
+    if not args.no_mixed:
+        mixed_leg(args, w, S0, steps_total, nb, loss32, gp32, torch, np, K, Pipeline, StageTimer, out)
+    if args.copy_calibration:
+        copy_calibration(torch)
     if not args.no_frame:
         log("540x540 frame")
         params = frame_leg(args, torch, np, K, synth, Pipeline, out)

@@ -128,7 +128,12 @@ int32_t ia355_snarf_deform(const float *xp, int64_t S, int64_t ld,
  *   grad_W  [Dz][Dy][Dx][nb] += -tri_c(x*) v^T (B_b x*_h) (nullable)
  * With IA355_OVERWRITE in flags grad_B / grad_W are written instead (every
  * entry).  Samples with bone < 0 contribute nothing (grad_xp = 0).
- * ws: ia355_deform_bwd_workspace_size(S, Dx, Dy, Dz, nb) bytes. */
+ * The parameter gradients go through the per-vertex moment
+ * Q_v = sum_s tri_v(x*_s) v_s x*_h,s^T, summed in LDS per slice of 1024
+ * vertices (global atomics only for slices split over workgroups, or for
+ * grids beyond 4M vertices); summation order inside an entry is not fixed.
+ * ws: ia355_deform_bwd_workspace_size(S, Dx, Dy, Dz, nb) bytes (about 44 B
+ * per sample, 48 B per grid vertex and the dL/dB block partials). */
 size_t ia355_deform_bwd_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz, int32_t nb);
 int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int16_t *bone, int64_t S, int64_t ld,
                                const float *B, int32_t nb, const float *W,
@@ -189,12 +194,19 @@ int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, i
  *   (every entry, untouched ones set to 0).  Summation order inside a table
  *   entry is not fixed (atomic adds), so the last bits may vary run to run.
  *   grad_xc [3][ld] overwritten with sum_l sum_c (grad w_c)(theta_c . grad_feat_l)
- *   (nullable; needs the table). */
+ *   (nullable; needs the table).
+ * ws: device scratch of ia355_hashgrid_bwd_workspace_size(S, L, log2T) bytes
+ * selects the binned table gradient (contributions grouped by table slice
+ * and summed in LDS; about 10 bytes per sample, level and corner).  With
+ * ws NULL, or where that size is 0 (T > 2^25 or S > 2^27), the table
+ * gradient is added with global atomics instead (same result up to
+ * summation order, slower).  IA355_ERR_WORKSPACE if ws_bytes is too small. */
+size_t ia355_hashgrid_bwd_workspace_size(int64_t S, int32_t L, int32_t log2T);
 int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone,
                                   int64_t S, int64_t ld, const void *table, int32_t table_dtype,
                                   int32_t L, int32_t F, int32_t log2T, double base_res, double growth,
                                   const float *aabb, float *grad_table, float *grad_xc, uint32_t flags,
-                                  ia355_stream_t stream);
+                                  void *ws, size_t ws_bytes, ia355_stream_t stream);
 
 /* The decoder MLP 32 -> 64 -> 64 -> 4 with ReLU hidden layers; outputs
  * sigma = exp(o_0) (clamped at exp(80)) and c = sigmoid(o_1..3).

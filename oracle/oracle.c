@@ -39,6 +39,17 @@ int32_t oracle_num_threads(void)
 #endif
 }
 
+/* Thread count of the parallel loops (timing only; results do not depend
+ * on it: every parallel loop writes disjoint outputs). */
+void oracle_set_num_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Sec. 3.2 (ray r = o + t d, N samples between near and far) and      */
 /* Sec. 3.3 (samples in empty occupancy cells are skipped).            */

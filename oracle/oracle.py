@@ -29,6 +29,8 @@ def lib():
     L = ctypes.CDLL(ensure_built())
     L.oracle_num_threads.restype = _I32
     L.oracle_num_threads.argtypes = []
+    L.oracle_set_num_threads.restype = None
+    L.oracle_set_num_threads.argtypes = [_I32]
     L.oracle_march.restype = _I64
     L.oracle_march.argtypes = [_f, _f, _I64, _u8, _I32, _f, ctypes.c_float, _I32, _I32,
                                _d, _d, _i64, _I64, _i64, _i32, _d]
@@ -67,6 +69,10 @@ def lib():
 
 def num_threads():
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n):
+    lib().oracle_set_num_threads(int(n))
 
 
 def _p(a, t):

@@ -12,6 +12,7 @@
 //    Broyden solves in FP32 registers and pick the lowest residual with
 //    shuffles; bone inverses are staged in LDS once per block; the blended
 //    grid is read through the vector L1/L2 with float4 gathers.
+#include "binning.h"
 #include "common.h"
 #include "geometry.h"
 
@@ -408,7 +409,7 @@ constexpr int kOwnBlock = 256;
 __global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restrict__ gxc, const float *__restrict__ xc_soa,
                                                         const int16_t *__restrict__ bone, int64_t S, int64_t ld,
                                                         const float *__restrict__ B, int nb,
-                                                        const float *__restrict__ W, Grid gr,
+                                                        const float *__restrict__ W, Grid gr, int w_vec4,
                                                         float *__restrict__ gxp, float *__restrict__ vbuf) {
   __shared__ float sB[kMaxBones * 12];
   for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) sB[i] = B[i];
@@ -425,10 +426,7 @@ __global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restric
       vtx[k] = ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] +
                (c.i0[0] + (k & 1));
     float J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int b = 0; b < nb; ++b) {
-      float cv[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) cv[k] = W[vtx[k] * nb + b];
+    auto add_bone = [&](int b, const float cv[8]) {
       float w = 0.0f, d[3];
 #pragma unroll
       for (int k = 0; k < 8; ++k) w += tri_weight(c.f, k) * cv[k];
@@ -439,6 +437,35 @@ __global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restric
         const float y = Bb[4 * i] * x[0] + Bb[4 * i + 1] * x[1] + Bb[4 * i + 2] * x[2] + Bb[4 * i + 3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) J[i][j] += w * Bb[4 * i + j] + y * (c.dp[j] * d[j]);
+      }
+    };
+    if (w_vec4) {
+      // skinning rows as float4: 4 bones of the 8 corners per step
+      const int nq = nb >> 2;
+      for (int q = 0; q < nq; ++q) {
+        float4 c4[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c4[k] = reinterpret_cast<const float4 *>(W + vtx[k] * nb)[q];
+        float cv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cv[k] = c4[k].x;
+        add_bone(4 * q, cv);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cv[k] = c4[k].y;
+        add_bone(4 * q + 1, cv);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cv[k] = c4[k].z;
+        add_bone(4 * q + 2, cv);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cv[k] = c4[k].w;
+        add_bone(4 * q + 3, cv);
+      }
+    } else {
+      for (int b = 0; b < nb; ++b) {
+        float cv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cv[k] = W[vtx[k] * nb + b];
+        add_bone(b, cv);
       }
     }
     float Ji[3][3];
@@ -481,56 +508,229 @@ __global__ void __launch_bounds__(kOwnBlock) ift_q_kernel(const float *__restric
   if (j < 4) atomicAdd(q + 8 + j, tw * v[2] * xh[j]);
 }
 
-// Contractions of Q over a block of kConBlock vertices:
-//   dL/dW[v][b] = -sum_m B_b[m] Q_v[m]      (one vertex per thread)
-//   partial of sum_v W[v][b] Q_v[m]         (one (b, m) pair per thread)
-// The block's W rows and Q rows are staged in LDS with coalesced loads.
-constexpr int kConBlock = 256;
+// Binned accumulation of Q (same result as ift_q_kernel up to summation
+// order, without global atomics): the vertices are cut into slices of 1024
+// (12 floats each, 48 KB of LDS).  q_bin_kernel writes one 4-byte record
+// (sample << 3 | corner) per corner, grouped by slice, for each chunk of
+// 256 samples; q_accumulate_kernel recomputes each record's cell, weight and
+// 12 products, adds them in LDS and adds the slice to Q with coalesced
+// stores (atomics only where a slice is split over several workgroups).
+constexpr int kQChunk = 256;
+constexpr int kQSliceLog2 = 10;
+constexpr int kQMaxSlices = 4096;
+constexpr int kQRecPerGroup = 8192;
+constexpr int kQAccBlock = 256;
+constexpr int kQAccMaxGrid = 2048;
 
-__global__ void __launch_bounds__(kConBlock) ift_contract_kernel(const float *__restrict__ Q,
-                                                               const float *__restrict__ B, int nb,
-                                                               const float *__restrict__ W, int64_t nvert,
-                                                               float *__restrict__ gW, float *__restrict__ partB,
-                                                               int overwrite) {
+struct QLayout {
+  int64_t chunks = 0, max_items = 0;
+  int nsl = 0;
+  size_t offs = 0, recs = 0, tot = 0, items = 0, nitems = 0, bytes = 0;
+};
+
+bool q_layout(int64_t S, int64_t nvert, QLayout *q) {
+  if (S <= 0 || S > (1ll << 28)) return false;
+  const int64_t nsl = ceil_div(nvert, (int64_t)1 << kQSliceLog2);
+  if (nsl > kQMaxSlices) return false;
+  q->nsl = (int)nsl;
+  q->chunks = ceil_div(S, kQChunk);
+  q->max_items = nsl + ceil_div(8 * S, kQRecPerGroup) + 1;
+  size_t o = 0;
+  q->offs = o;
+  o = align256(o + sizeof(int32_t) * (size_t)q->chunks * (nsl + 1));
+  q->recs = o;
+  o = align256(o + sizeof(uint32_t) * (size_t)q->chunks * 8 * kQChunk);
+  q->tot = o;
+  o = align256(o + sizeof(int32_t) * (size_t)nsl);
+  q->items = o;
+  o = align256(o + sizeof(int4) * (size_t)q->max_items);
+  q->nitems = o;
+  o = align256(o + sizeof(int32_t));
+  q->bytes = o;
+  return true;
+}
+
+__device__ __forceinline__ int64_t corner_vertex(const Grid &gr, const Cell &c, int k) {
+  return ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] + (c.i0[0] + (k & 1));
+}
+
+__global__ void __launch_bounds__(kQChunk) q_bin_kernel(const float *__restrict__ xc_soa,
+                                                       const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                       Grid gr, int nsl, int32_t *__restrict__ offs,
+                                                       uint32_t *__restrict__ recs) {
+  __shared__ int cnt[kQMaxSlices];
+  __shared__ int red[kQChunk / kWave];
+  const int tid = threadIdx.x;
+  const int64_t chunk = blockIdx.x;
+  for (int i = tid; i < nsl; i += kQChunk) cnt[i] = 0;
+  __syncthreads();
+  const int64_t n = chunk * kQChunk + tid;
+  const bool act = n < S && bone[n] >= 0;
+  int sl[8];
+  if (act) {
+    const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
+    const Cell c = locate(gr, x);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      sl[k] = (int)(corner_vertex(gr, c, k) >> kQSliceLog2);
+      atomicAdd(&cnt[sl[k]], 1);
+    }
+  }
+  __syncthreads();
+  const int per = (nsl + kQChunk - 1) / kQChunk;
+  const int s0 = tid * per;
+  int mine = 0;
+  for (int i = 0; i < per; ++i)
+    if (s0 + i < nsl) mine += cnt[s0 + i];
+  int total;
+  int run = block_excl_scan<kQChunk / kWave>(mine, red, &total);
+  int32_t *row = offs + chunk * (nsl + 1);
+  for (int i = 0; i < per; ++i)
+    if (s0 + i < nsl) {
+      const int c = cnt[s0 + i];
+      row[s0 + i] = run;
+      cnt[s0 + i] = run;
+      run += c;
+    }
+  if (tid == 0) row[nsl] = total;
+  __syncthreads();
+  if (act) {
+    uint32_t *out = recs + chunk * (8 * kQChunk);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[atomicAdd(&cnt[sl[k]], 1)] = ((uint32_t)n << 3) | (uint32_t)k;
+  }
+}
+
+__global__ void __launch_bounds__(kQAccBlock) q_accumulate_kernel(const int32_t *__restrict__ offs,
+                                                                const uint32_t *__restrict__ recs,
+                                                                const int4 *__restrict__ items,
+                                                                const int32_t *__restrict__ n_items, int64_t chunks,
+                                                                int nsl, const float *__restrict__ xc_soa, int64_t ld,
+                                                                const float *__restrict__ vbuf, int64_t S, Grid gr,
+                                                                int64_t nvert, float *__restrict__ Q) {
+  __shared__ float acc[12 << kQSliceLog2];
+  __shared__ int sp[kQAccBlock];
+  __shared__ int64_t sb[kQAccBlock];
+  __shared__ int red[kQAccBlock / kWave];
+  const int tid = threadIdx.x;
+  const int64_t n_it = *n_items;
+  for (int64_t it = blockIdx.x; it < n_it; it += gridDim.x) {
+    const int4 info = items[it];
+    const int s = info.y, G = info.w;
+    int64_t c0, c1;
+    group_chunks(info.z, G, chunks, &c0, &c1);
+    const int64_t vbase = (int64_t)s << kQSliceLog2;
+    for (int e = tid; e < (12 << kQSliceLog2); e += kQAccBlock) acc[e] = 0.0f;
+    __syncthreads();
+    for (int64_t cb = c0; cb < c1; cb += kQAccBlock) {
+      const int nb = (int)((c1 - cb) < kQAccBlock ? (c1 - cb) : kQAccBlock);
+      int len = 0;
+      int64_t beg = 0;
+      if (tid < nb) {
+        const int32_t *row = offs + (cb + tid) * (nsl + 1);
+        const int b = row[s];
+        len = row[s + 1] - b;
+        beg = (cb + tid) * (8 * kQChunk) + b;
+      }
+      int m;
+      const int ex = block_excl_scan<kQAccBlock / kWave>(len, red, &m);
+      sp[tid] = ex;
+      sb[tid] = beg;
+      __syncthreads();
+      for (int r = tid; r < m; r += kQAccBlock) {
+        const uint32_t rec = recs[batch_record(r, nb, sp, sb)];
+        const int64_t n = rec >> 3;
+        const int k = (int)(rec & 7u);
+        const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
+        const float v[3] = {vbuf[n], vbuf[S + n], vbuf[2 * S + n]};
+        const Cell c = locate(gr, x);
+        const int64_t local = corner_vertex(gr, c, k) - vbase;  // same cell as in q_bin_kernel
+        if (local < 0 || local >= ((int64_t)1 << kQSliceLog2)) continue;
+        const float tw = tri_weight(c.f, k);
+        const float xh[4] = {x[0], x[1], x[2], 1.0f};
+        float *a = acc + 12 * local;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) atomicAdd(a + j, tw * v[j >> 2] * xh[j & 3]);
+      }
+      __syncthreads();
+    }
+    const int64_t nv = (nvert - vbase) < ((int64_t)1 << kQSliceLog2) ? (nvert - vbase) : ((int64_t)1 << kQSliceLog2);
+    float *q = Q + 12 * vbase;
+    for (int e = tid; e < 12 * nv; e += kQAccBlock) {
+      const float a = acc[e];
+      if (a != 0.0f) {
+        if (G == 1) q[e] += a;
+        else atomicAdd(q + e, a);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Contractions of Q over a block of kConBlock vertices:
+//   dL/dW[v][b] = -sum_m B_b[m] Q_v[m]      (one output element per thread
+//                                           and step: coalesced row stores)
+//   partial of sum_v W[v][b] Q_v[m]         (one (b, m) pair per thread)
+// Most vertices of the skinning grid are far from every sample and have
+// Q_v = 0; a block whose Q rows are all zero writes zero rows and a zero
+// partial without reading its W rows.
+constexpr int kConBlock = 64;
+constexpr int kConThreads = 256;
+
+__global__ void __launch_bounds__(kConThreads) ift_contract_kernel(const float *__restrict__ Q,
+                                                                 const float *__restrict__ B, int nb,
+                                                                 const float *__restrict__ W, int64_t nvert,
+                                                                 float *__restrict__ gW, float *__restrict__ partB,
+                                                                 int overwrite) {
   __shared__ float sB[kMaxBones * 12];
   __shared__ float sQ[kConBlock * 12];
-  __shared__ float sW[kConBlock * 32];  // nb <= 32 for the grad_B partial
-  for (int i = threadIdx.x; i < nb * 12; i += kConBlock) sB[i] = B[i];
+  __shared__ float sW[kConBlock * kMaxBones];
+  __shared__ int any;
+  const int tid = threadIdx.x;
   const int64_t v0 = (int64_t)blockIdx.x * kConBlock;
   const int nv = (int)min((int64_t)kConBlock, nvert - v0);
-  for (int i = threadIdx.x; i < kConBlock * 12; i += kConBlock) sQ[i] = i < nv * 12 ? Q[v0 * 12 + i] : 0.0f;
-  const bool wpart = partB && nb <= 32;
-  if (wpart)
-    for (int i = threadIdx.x; i < nv * nb; i += kConBlock) sW[(i / nb) * 32 + (i % nb)] = W[v0 * nb + i];
+  if (tid == 0) any = 0;
+  for (int i = tid; i < nb * 12; i += kConThreads) sB[i] = B[i];
   __syncthreads();
-  if (gW && (int)threadIdx.x < nv) {
-    const float *q = sQ + 12 * threadIdx.x;
-    float *out = gW + (v0 + threadIdx.x) * nb;
-    for (int b = 0; b < nb; ++b) {
-      const float *Bb = sB + 12 * b;
+  int mine = 0;
+  for (int i = tid; i < kConBlock * 12; i += kConThreads) {
+    const float q = i < nv * 12 ? Q[v0 * 12 + i] : 0.0f;
+    sQ[i] = q;
+    mine |= q != 0.0f;
+  }
+  if (mine) any = 1;
+  __syncthreads();
+  const bool live = any != 0;
+  if (gW) {
+    float *out = gW + v0 * nb;
+    for (int e = tid; e < nv * nb; e += kConThreads) {
       float s = 0.0f;
+      if (live) {
+        const int v = e / nb, b = e - v * nb;
+        const float *q = sQ + 12 * v, *Bb = sB + 12 * b;
 #pragma unroll
-      for (int m = 0; m < 12; ++m) s += Bb[m] * q[m];
-      out[b] = overwrite ? -s : out[b] - s;
+        for (int m = 0; m < 12; ++m) s += Bb[m] * q[m];
+      }
+      if (overwrite) out[e] = -s;
+      else out[e] -= s;
     }
   }
   if (partB) {
-    for (int p = threadIdx.x; p < nb * 12; p += kConBlock) {
-      const int b = p / 12, m = p % 12;
-      float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-      if (wpart) {
+    if (live)
+      for (int i = tid; i < nv * nb; i += kConThreads) sW[i] = W[v0 * nb + i];
+    __syncthreads();
+    for (int p = tid; p < nb * 12; p += kConThreads) {
+      float s0 = 0.0f, s1 = 0.0f;
+      if (live) {
+        const int b = p / 12, m = p - 12 * (p / 12);
         int e = 0;
-        for (; e + 3 < nv; e += 4) {
-          s0 += sW[e * 32 + b] * sQ[12 * e + m];
-          s1 += sW[(e + 1) * 32 + b] * sQ[12 * (e + 1) + m];
-          s2 += sW[(e + 2) * 32 + b] * sQ[12 * (e + 2) + m];
-          s3 += sW[(e + 3) * 32 + b] * sQ[12 * (e + 3) + m];
+        for (; e + 1 < nv; e += 2) {
+          s0 += sW[e * nb + b] * sQ[12 * e + m];
+          s1 += sW[(e + 1) * nb + b] * sQ[12 * (e + 1) + m];
         }
-        for (; e < nv; ++e) s0 += sW[e * 32 + b] * sQ[12 * e + m];
-      } else {
-        for (int e = 0; e < nv; ++e) s0 += W[(v0 + e) * nb + b] * sQ[12 * e + m];
+        if (e < nv) s0 += sW[e * nb + b] * sQ[12 * e + m];
       }
-      partB[(int64_t)blockIdx.x * nb * 12 + p] = (s0 + s1) + (s2 + s3);
+      partB[(int64_t)blockIdx.x * nb * 12 + p] = s0 + s1;
     }
   }
 }
@@ -662,8 +862,10 @@ extern "C" int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, int64_t
 extern "C" size_t ia355_deform_bwd_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz, int32_t nb) {
   if (S < 0 || Dx <= 0 || Dy <= 0 || Dz <= 0 || nb <= 0) return 0;
   const int64_t nvert = (int64_t)Dx * Dy * Dz;
+  QLayout ql;
+  const size_t qbytes = q_layout(S, nvert, &ql) ? ql.bytes : 0;
   return align256(sizeof(float) * 3 * (size_t)S) + align256(sizeof(float) * 12 * (size_t)nvert) +
-         align256(sizeof(float) * 12 * (size_t)nb * ceil_div(nvert, kConBlock));
+         align256(sizeof(float) * 12 * (size_t)nb * ceil_div(nvert, kConBlock)) + qbytes;
 }
 
 extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int16_t *bone, int64_t S,
@@ -684,16 +886,33 @@ extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc,
   float *vbuf = (float *)ws;
   float *Q = (float *)((char *)ws + align256(sizeof(float) * 3 * (size_t)S));
   float *partB = (float *)((char *)Q + align256(sizeof(float) * 12 * (size_t)nvert));
-  if (S > 0)
+  if (S > 0) {
+    const int w_vec4 = (nb % 4 == 0) && ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
     ift_v_kernel<<<(unsigned)ceil_div(S, kBwdBlock), kBwdBlock, 0, s>>>(grad_xc, xc, bone, S, ld, B, nb, W, g,
-                                                                        grad_xp, vbuf);
+                                                                        w_vec4, grad_xp, vbuf);
+  }
   if (grad_W || grad_B) {
     const int32_t st = ia355_zero(Q, sizeof(float) * 12 * (size_t)nvert, stream);
     if (st != IA355_OK) return st;
-    if (S > 0)
+    QLayout ql;
+    if (S > 0 && q_layout(S, nvert, &ql)) {
+      char *qw = (char *)partB + align256(sizeof(float) * 12 * (size_t)nb * nblk);
+      int32_t *offs = reinterpret_cast<int32_t *>(qw + ql.offs);
+      uint32_t *recs = reinterpret_cast<uint32_t *>(qw + ql.recs);
+      int32_t *tot = reinterpret_cast<int32_t *>(qw + ql.tot);
+      int4 *items = reinterpret_cast<int4 *>(qw + ql.items);
+      int32_t *n_items = reinterpret_cast<int32_t *>(qw + ql.nitems);
+      q_bin_kernel<<<(unsigned)ql.chunks, kQChunk, 0, s>>>(xc, bone, S, ld, g, ql.nsl, offs, recs);
+      slice_total_kernel<<<(unsigned)ceil_div(ql.nsl, 256), 256, 0, s>>>(offs, 1, ql.chunks, ql.nsl, tot);
+      plan_kernel<<<1, kPlanBlock, 0, s>>>(tot, 1, ql.chunks, ql.nsl, kQRecPerGroup, items, n_items);
+      const int64_t grid = ql.max_items < kQAccMaxGrid ? ql.max_items : kQAccMaxGrid;
+      q_accumulate_kernel<<<(unsigned)grid, kQAccBlock, 0, s>>>(offs, recs, items, n_items, ql.chunks, ql.nsl, xc, ld,
+                                                                vbuf, S, g, nvert, Q);
+    } else if (S > 0) {
       ift_q_kernel<<<(unsigned)ceil_div(S * 64, kOwnBlock), kOwnBlock, 0, s>>>(xc, bone, vbuf, S, ld, g, Q);
-    ift_contract_kernel<<<(unsigned)nblk, kConBlock, 0, s>>>(Q, B, nb, W, nvert, grad_W, grad_B ? partB : nullptr,
-                                                             overwrite);
+    }
+    ift_contract_kernel<<<(unsigned)nblk, kConThreads, 0, s>>>(Q, B, nb, W, nvert, grad_W, grad_B ? partB : nullptr,
+                                                               overwrite);
     if (grad_B)
       ift_b_kernel<<<(unsigned)ceil_div(nb * 12, kRedP), kRedP * kRedG, 0, s>>>(partB, nblk, nb * 12, grad_B, overwrite);
   }

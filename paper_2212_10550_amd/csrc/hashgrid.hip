@@ -20,6 +20,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include "binning.h"
 #include "common.h"
 
 using namespace ia355;
@@ -275,6 +276,192 @@ __global__ void __launch_bounds__(kDgBlock) table_grad_dense_kernel(const float 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Binned table gradient (used when a workspace is given).  Global FP32
+// atomics cost one L2/fabric request per touched cache line, and a fine
+// level's corners land on lines of their own, so the atomic path is bound by
+// that request rate.  Here the table of each level is cut into slices of
+// 2^13 entries (64 KB of FP32 pairs, one LDS buffer), and:
+//  1. bin_kernel: one workgroup per (level, 1024-sample chunk) computes each
+//     sample's 8 corners, counts them per slice in LDS, scans the counts
+//     (per-chunk slice offsets) and writes one record (entry in slice,
+//     w * dL/dfeat) per corner, grouped by slice;
+//  2. slice_total_kernel / plan_kernel: records per slice; a slice with many
+//     records (coarse levels) is split into up to kMaxGroups groups of
+//     chunks; the plan is a flat list of (level, slice, group, groups);
+//  3. accumulate_kernel: each item sums its records into the LDS slice with
+//     LDS atomics and adds the slice to the table with coalesced accesses:
+//     plain read-modify-write when it owns the slice alone, global atomics
+//     on the touched entries when the slice is split.
+constexpr int kBinChunk = 1024;
+constexpr int kBinBlock = 256;
+constexpr int kSliceLog2 = 13;
+constexpr int kMaxSlices = 4096;  // binned path for T <= 2^25
+constexpr int kRecPerGroup = 16384;
+constexpr int kAccBlock = 256;
+constexpr int kAccMaxGrid = 4096;
+
+struct BinLayout {
+  int64_t chunks = 0, max_items = 0;
+  int nsl = 0, sl = 0;
+  size_t offs = 0, keys = 0, vals = 0, tot = 0, items = 0, nitems = 0, bytes = 0;
+};
+
+bool bin_layout(int64_t S, int L, int log2T, BinLayout *b) {
+  if (S <= 0 || L <= 0 || log2T < 1 || log2T - kSliceLog2 > 12 || S > (1ll << 27)) return false;
+  b->sl = log2T < kSliceLog2 ? log2T : kSliceLog2;
+  b->nsl = 1 << (log2T - b->sl);
+  b->chunks = ceil_div(S, kBinChunk);
+  b->max_items = (int64_t)L * b->nsl + ceil_div(8 * S * L, kRecPerGroup) + 1;
+  const int64_t rec = (int64_t)L * b->chunks * 8 * kBinChunk;
+  size_t o = 0;
+  b->offs = o;
+  o = align256(o + sizeof(int32_t) * (size_t)L * b->chunks * (b->nsl + 1));
+  b->keys = o;
+  o = align256(o + sizeof(uint16_t) * (size_t)rec);
+  b->vals = o;
+  o = align256(o + sizeof(float2) * (size_t)rec);
+  b->tot = o;
+  o = align256(o + sizeof(int32_t) * (size_t)L * b->nsl);
+  b->items = o;
+  o = align256(o + sizeof(int4) * (size_t)b->max_items);
+  b->nitems = o;
+  o = align256(o + sizeof(int32_t));
+  b->bytes = o;
+  return true;
+}
+
+__global__ void __launch_bounds__(kBinBlock) bin_kernel(const float *__restrict__ gfeat, const float *__restrict__ xc,
+                                                       const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                       int64_t chunks, int log2T, int sl, int nsl, Levels lv,
+                                                       Box box, int32_t *__restrict__ offs,
+                                                       uint16_t *__restrict__ keys, float2 *__restrict__ vals) {
+  __shared__ int cnt[kMaxSlices];
+  __shared__ int red[kBinBlock / kWave];
+  const int level = (int)(blockIdx.x / chunks);
+  const int64_t chunk = blockIdx.x % chunks;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < nsl; i += kBinBlock) cnt[i] = 0;
+  __syncthreads();
+  const uint32_t T = 1u << log2T;
+  constexpr int kPer = kBinChunk / kBinBlock;
+  uint32_t idx[kPer][8];
+  float val[kPer][8];
+  float2 g[kPer];
+  bool act[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int64_t n = chunk * kBinChunk + j * kBinBlock + tid;
+    act[j] = n < S && (!bone || bone[n] >= 0);
+    g[j] = make_float2(0.0f, 0.0f);
+    if (act[j]) {
+      const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
+      Corners c;
+      level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
+      g[j] = reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * S + n];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        idx[j][k] = c.idx[k];
+        val[j][k] = c.w[k];
+        atomicAdd(&cnt[c.idx[k] >> sl], 1);
+      }
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the slice counts: thread t owns a run of slices
+  const int per = (nsl + kBinBlock - 1) / kBinBlock;
+  const int s0 = tid * per;
+  int mine = 0;
+  for (int i = 0; i < per; ++i)
+    if (s0 + i < nsl) mine += cnt[s0 + i];
+  int total;
+  int run = block_excl_scan<kBinBlock / kWave>(mine, red, &total);
+  int32_t *row = offs + ((int64_t)level * chunks + chunk) * (nsl + 1);
+  for (int i = 0; i < per; ++i)
+    if (s0 + i < nsl) {
+      const int c = cnt[s0 + i];
+      row[s0 + i] = run;
+      cnt[s0 + i] = run;  // becomes the slice's write cursor
+      run += c;
+    }
+  if (tid == 0) row[nsl] = total;
+  __syncthreads();
+  const int64_t rec = ((int64_t)level * chunks + chunk) * (8 * kBinChunk);
+  const uint32_t emask = (1u << sl) - 1u;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j)
+    if (act[j]) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int pos = atomicAdd(&cnt[idx[j][k] >> sl], 1);
+        keys[rec + pos] = (uint16_t)(idx[j][k] & emask);
+        vals[rec + pos] = make_float2(val[j][k] * g[j].x, val[j][k] * g[j].y);
+      }
+    }
+}
+
+__global__ void __launch_bounds__(kAccBlock) accumulate_kernel(const int32_t *__restrict__ offs,
+                                                              const uint16_t *__restrict__ keys,
+                                                              const float2 *__restrict__ vals,
+                                                              const int4 *__restrict__ items,
+                                                              const int32_t *__restrict__ n_items, int64_t chunks,
+                                                              int nsl, int sl, int log2T, float *__restrict__ gtable) {
+  __shared__ float2 acc[1 << kSliceLog2];
+  __shared__ int sp[kAccBlock];
+  __shared__ int64_t sb[kAccBlock];
+  __shared__ int red[kAccBlock / kWave];
+  const int tid = threadIdx.x;
+  const int E = 1 << sl;
+  const int64_t n = *n_items;
+  for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const int4 info = items[it];
+    const int level = info.x, s = info.y, G = info.w;
+    int64_t c0, c1;
+    group_chunks(info.z, G, chunks, &c0, &c1);
+    for (int e = tid; e < E; e += kAccBlock) acc[e] = make_float2(0.0f, 0.0f);
+    __syncthreads();
+    for (int64_t cb = c0; cb < c1; cb += kAccBlock) {
+      const int nb = (int)((c1 - cb) < kAccBlock ? (c1 - cb) : kAccBlock);
+      int len = 0;
+      int64_t beg = 0;
+      if (tid < nb) {
+        const int64_t rowi = (int64_t)level * chunks + cb + tid;
+        const int32_t *row = offs + rowi * (nsl + 1);
+        const int b = row[s];
+        len = row[s + 1] - b;
+        beg = rowi * (8 * kBinChunk) + b;
+      }
+      int m;
+      const int ex = block_excl_scan<kAccBlock / kWave>(len, red, &m);
+      sp[tid] = ex;
+      sb[tid] = beg;
+      __syncthreads();
+      for (int r = tid; r < m; r += kAccBlock) {
+        const int64_t ri = batch_record(r, nb, sp, sb);
+        const int key = keys[ri];
+        const float2 v = vals[ri];
+        atomicAdd(&acc[key].x, v.x);
+        atomicAdd(&acc[key].y, v.y);
+      }
+      __syncthreads();
+    }
+    float2 *gl = reinterpret_cast<float2 *>(gtable) + ((int64_t)level << log2T) + ((int64_t)s << sl);
+    for (int e = tid; e < E; e += kAccBlock) {
+      const float2 a = acc[e];
+      if (a.x != 0.0f || a.y != 0.0f) {
+        if (G == 1) {
+          const float2 o = gl[e];
+          gl[e] = make_float2(o.x + a.x, o.y + a.y);
+        } else {
+          atomicAdd(&gl[e].x, a.x);
+          atomicAdd(&gl[e].y, a.y);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 int32_t make_levels(int L, int log2T, double base, double growth, Levels *lv) {
   const uint64_t T = 1ull << log2T;
   for (int l = 0; l < L; ++l) {
@@ -332,10 +519,16 @@ extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, i
   return launch_status();
 }
 
+extern "C" size_t ia355_hashgrid_bwd_workspace_size(int64_t S, int32_t L, int32_t log2T) {
+  BinLayout b;
+  return bin_layout(S, L, log2T, &b) ? b.bytes : 0;
+}
+
 extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone, int64_t S,
                                              int64_t ld, const void *table, int32_t table_dtype, int32_t L, int32_t F,
                                              int32_t log2T, double base_res, double growth, const float *aabb,
-                                             float *grad_table, float *grad_xc, uint32_t flags, ia355_stream_t stream) {
+                                             float *grad_table, float *grad_xc, uint32_t flags, void *ws,
+                                             size_t ws_bytes, ia355_stream_t stream) {
   if (S < 0 || ld < S || L <= 0 || L > 16 || F != 2 || log2T < 1 || log2T > 30) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_feat || !xc)) return IA355_ERR_INVALID_ARG;
   if (grad_xc && !table) return IA355_ERR_INVALID_ARG;
@@ -350,7 +543,27 @@ extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float
     const int32_t st = ia355_zero(grad_table, sizeof(float) * 2 * (size_t)L * ((size_t)1 << log2T), stream);
     if (st != IA355_OK) return st;
   }
-  if (grad_table && S > 0) {
+  BinLayout bl;
+  const bool binned = ws && grad_table && S > 0 && bin_layout(S, L, log2T, &bl);
+  if (binned && ws_bytes < bl.bytes) return IA355_ERR_WORKSPACE;
+  if (binned) {
+    char *w = static_cast<char *>(ws);
+    int32_t *offs = reinterpret_cast<int32_t *>(w + bl.offs);
+    uint16_t *keys = reinterpret_cast<uint16_t *>(w + bl.keys);
+    float2 *vals = reinterpret_cast<float2 *>(w + bl.vals);
+    int32_t *tot = reinterpret_cast<int32_t *>(w + bl.tot);
+    int4 *items = reinterpret_cast<int4 *>(w + bl.items);
+    int32_t *n_items = reinterpret_cast<int32_t *>(w + bl.nitems);
+    const int64_t nbin = (int64_t)L * bl.chunks;
+    if (nbin > 0x7fffffffLL) return IA355_ERR_INVALID_ARG;
+    bin_kernel<<<(unsigned)nbin, kBinBlock, 0, s>>>(grad_feat, xc, bone, S, ld, bl.chunks, log2T, bl.sl, bl.nsl, lv,
+                                                    box, offs, keys, vals);
+    slice_total_kernel<<<(unsigned)ceil_div((int64_t)L * bl.nsl, 256), 256, 0, s>>>(offs, L, bl.chunks, bl.nsl, tot);
+    plan_kernel<<<1, kPlanBlock, 0, s>>>(tot, L, bl.chunks, bl.nsl, kRecPerGroup, items, n_items);
+    const int64_t g = bl.max_items < kAccMaxGrid ? bl.max_items : kAccMaxGrid;
+    accumulate_kernel<<<(unsigned)g, kAccBlock, 0, s>>>(offs, keys, vals, items, n_items, bl.chunks, bl.nsl, bl.sl,
+                                                        log2T, grad_table);
+  } else if (grad_table && S > 0) {
     // Run aggregation pays while a cell spans several ray steps (coarse
     // dense levels, which come first as the resolution grows with the level);
     // finer levels use the 16-lanes-per-item mapping.

@@ -116,6 +116,7 @@ class Pipeline:
         self.grad_B = e(*self.B.shape) if grad_B else None
         self.grad_W = e(*self.W.shape) if grad_W else None
         self.ws_ift = e(K.deform_bwd_workspace_size(cap, Dx, Dy, Dz, nb), dt=torch.uint8)
+        self.ws_hash = None  # binned table-gradient scratch, sized on first use for the step's S
         self.S = None
         self.timer = None  # optional StageTimer: HIP events around each stage
         # learned root initialiser (guided solve with multi-init fallback)
@@ -185,9 +186,12 @@ class Pipeline:
         gfeat = self.grad_feat[: w.L * S * 2]
         K.mlp_bwd(self.grad_sigma, self.grad_rgb, feat, self.bone, S, self.cap, self.params, self.mlp_dtype,
                   self.grad_params, gfeat, self.ws_mlp, flags=K.OVERWRITE)
+        need = K.hashgrid_bwd_workspace_size(S, w.L, self.table.shape[1].bit_length() - 1)
+        if need and (self.ws_hash is None or self.ws_hash.numel() < need):
+            self.ws_hash = torch.empty(need + need // 4, dtype=torch.uint8, device=self.dev)
         self._mark("hash_bwd")
         K.hashgrid_encode_bwd(gfeat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth, w.hash_aabb,
-                              self.grad_table, self.grad_xc, flags=K.OVERWRITE)
+                              self.grad_table, self.grad_xc, flags=K.OVERWRITE, ws=self.ws_hash if need else None)
         self._mark("deform_bwd")
         K.snarf_deform_bwd(self.grad_xc, self.xc, self.bone, S, self.cap, self.B, self.W, w.skin_aabb, self.grad_xp,
                            self.grad_B, self.grad_W, self.ws_ift, flags=K.OVERWRITE)

@@ -118,25 +118,55 @@ def test_mlp_bwd_f32(orc, S):
     gclose_rows(host(gf).reshape(16, S, 2).transpose(1, 0, 2).reshape(S, 32), rf, "grad_feat")
 
 
-@pytest.mark.parametrize("log2T,tdt", [(14, np.float32), (19, np.float32), (19, np.float16)])
-def test_hash_bwd(orc, log2T, tdt):
+@pytest.mark.parametrize("log2T,tdt,binned,overwrite,pad", [
+    (14, np.float32, True, True, 0), (19, np.float32, True, False, 5), (19, np.float16, True, True, 0),
+    (21, np.float16, True, False, 0), (14, np.float32, False, False, 0), (19, np.float32, False, True, 3),
+    (19, np.float16, False, False, 0)])
+def test_hash_bwd(orc, log2T, tdt, binned, overwrite, pad):
+    """Table and position gradients against the oracle.  binned: the LDS
+    slice path (S = 6007 -> 6 chunks, the last one ragged; level 0's single
+    slice holds ~48k records and is split over 3 workgroups that merge with
+    atomics; finer slices have one owner).  overwrite: the table starts as
+    garbage and must be replaced; otherwise it starts at 0.25 and the
+    gradient is added to it."""
     K = _K()
     S = 6007
+    ld = S + pad
     x = synth.random_points(S, 41)
     table = synth.make_hash_table(16, 1 << log2T, 2, seed=6, scale=0.3).astype(tdt)
     rng = np.random.default_rng(7)
     gfeat = rng.normal(size=(S, 32)).astype(np.float32)
     bone = np.where(np.arange(S) % 11 == 5, -1, 0).astype(np.int16)
-    gt = torch.zeros(16, 1 << log2T, 2, device=dev())
-    gx = torch.full((3, S), 3.0, device=dev())
-    K.hashgrid_encode_bwd(up(gfeat.reshape(S, 16, 2).transpose(1, 0, 2).reshape(-1)), soa(x), up(bone), S, S,
-                          up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, gx)
+    gt = torch.full((16, 1 << log2T, 2), 7.0 if overwrite else 0.25, device=dev())
+    gx = torch.full((3, ld), 3.0, device=dev())
+    ws = None
+    if binned:
+        nbytes = K.hashgrid_bwd_workspace_size(S, 16, log2T)
+        assert nbytes > 0
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev())
+    K.hashgrid_encode_bwd(up(gfeat.reshape(S, 16, 2).transpose(1, 0, 2).reshape(-1)), soa(x, ld), up(bone), S, ld,
+                          up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, gx, K.OVERWRITE if overwrite else 0, ws=ws)
     torch.cuda.synchronize()
     rt, rx = orc.hash_encode_bwd(gfeat, x, table, orc.resolutions(16), np.array([0, 0, 0, 1, 1, 1.0]), valid=bone)
-    gclose(host(gt), rt, "grad_table")
+    gclose(host(gt) - (0.0 if overwrite else 0.25), rt, "grad_table")
     # the position gradient scales with N_l |theta|; FP32 weights carry ~1e-7 relative error
-    gclose_rows(host(gx).T, rx, "grad_x")
-    assert (host(gx).T[bone < 0] == 0).all()
+    gclose_rows(host(gx[:, :S]).T, rx, "grad_x")
+    assert (host(gx[:, :S]).T[bone < 0] == 0).all()
+    assert (host(gx[:, S:]) == 3.0).all()
+
+
+def test_hash_bwd_workspace_errors():
+    K = _K()
+    S, log2T = 3000, 19
+    x = synth.random_points(S, 2)
+    table = torch.zeros(16, 1 << log2T, 2, device=dev())
+    gt = torch.zeros_like(table)
+    gf = torch.zeros(16 * S * 2, device=dev())
+    small = torch.empty(K.hashgrid_bwd_workspace_size(S, 16, log2T) - 256, dtype=torch.uint8, device=dev())
+    with pytest.raises(RuntimeError):
+        K.hashgrid_encode_bwd(gf, soa(x), None, S, S, table, 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, None, ws=small)
+    assert K.hashgrid_bwd_workspace_size(0, 16, log2T) == 0
+    assert K.hashgrid_bwd_workspace_size(S, 16, 26) == 0  # beyond the binned path: atomics, no workspace
 
 
 def test_deform_bwd(orc):

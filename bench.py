@@ -5,20 +5,33 @@ Step (the timed unit of ``value``): one training step of the path on the
 8192-ray workload -- march through the 128^3 occupancy grid, 24-init Broyden
 deform, hash encode, MLP, composite, L2 loss, and every backward pass
 (composite, MLP, encode, implicit-function-theorem deform), all in the
-library's HIP kernels, FP32.  value = posed samples (kept by the occupancy
-skip) per second over the K timed steps, inputs resident in HBM.
+library's HIP kernels, FP32.  The sample count stays in device memory and
+each step is one HIP graph replay.  value = posed samples (kept by the
+occupancy skip) per second over the K timed steps, inputs resident in HBM.
 
 Extra keys of the one JSON line:
-  stages_ms     per-stage time of the step (HIP events on the launch stream)
-  roofline      the dominant stage's kernel against its roofline
+  stages_ms, stage_roofline
+                GPU time of each stage (its calls captured in a graph of
+                their own and replayed back to back, HIP events on the
+                stream) and each stage's algorithmic work against its bound
+  roofline      the dominant stage against its roofline, with the HBM
+                traffic of its kernels from rocprofv3 counters
+  host_count_eager_ms_per_step
+                the same step with a host round trip for the sample count
+  mixed_training_step
+                FP16 table + BF16 MLP training step
   frame_540     ms per 540x540 frame: FP32 multi-init vs FP16 table + BF16
                 MLP + learned root initialiser, and their pixel errors
   learned_init  the initialiser on held-out poses: steps, fallback rate,
                 root error, deform time vs multi-init
+  tiny_forward_f32, empty_space_skipping, hash_stress_2e23
+                the tiny forward, skipping on/off (the synthetic analogue of
+                Tab. 3) and a 2^23-entry hash table
   cpu_baseline  the FP64 oracle timed on the host cores
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-frame] [--init-poses P]
+                       [--no-frame] [--no-mixed] [--init-poses P]
+                       [--copy-calibration] [--pmc-summary FETCH_DIR WRITE_DIR]
 """
 from __future__ import annotations
 
@@ -62,8 +75,7 @@ STAGE_KERNELS = {
     "render_fwd": ["render_fwd"],
     "loss+render_bwd": ["l2_loss_kernel", "render_bwd"],
     "mlp_bwd": ["mlp_bwd_f32", "mlp_bwd_bf16", "reduce_partials"],
-    "hash_bwd": ["bin_kernel", "slice_total_kernel", "plan_kernel", "accumulate_kernel", "table_grad_kernel",
-                 "table_grad_dense_kernel", "encode_bwd_kernel"],
+    "hash_bwd": ["table_grad_kernel", "table_grad_dense_kernel", "encode_bwd_kernel"],
     "deform_bwd": ["ift_v_kernel", "ift_q_kernel", "ift_contract_kernel", "ift_b_kernel"],
 }
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "training_step_f32_hbm_traffic.md")
@@ -197,23 +209,45 @@ def roofline(stage_ms, S, R, steps_total, nb):
 
 
 def time_forward(p, n, torch, stages=False):
-    """ms per forward over n runs after 2 warm-ups; with stages, also the
-    per-stage ms (HIP events on the launch stream) of those runs."""
-    from paper_2212_10550_amd.pipeline import StageTimer
+    """ms per forward over n runs after warm-up (HIP-graph replays for a
+    device-count pipeline); with stages, also the GPU ms of each stage
+    (replayed on its own, Pipeline.stage_times).  Returns (ms, S, stage_ms)."""
     for _ in range(2):
         p.forward()
     torch.cuda.synchronize()
-    timer = StageTimer() if stages else None
-    p.timer = timer
+    stage_ms = p.stage_times(n, backward=False) if stages else None
+    run = p.forward
+    if p.device_count:
+        p.capture_forward()
+        run = p.replay
+    run()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(n):
-        S = p.forward()
+        run()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / n
-    p.timer = None
-    if stages:
-        return ms, S, {k: v / n for k, v in timer.totals_ms().items()}
-    return ms, S
+    return ms, p.read_count(), stage_ms
+
+
+def time_train(p, steps, warmup, torch, stages=False):
+    """Training steps: optional GPU ms of each stage (Pipeline.stage_times),
+    then `steps` timed HIP-graph replays of the whole step (device-count
+    pipeline).  Returns (seconds for the timed steps, S per step, stage_ms)."""
+    for _ in range(warmup):
+        p.train_step()
+    torch.cuda.synchronize()
+    stage_ms = p.stage_times(steps) if stages else None
+    p.capture_train_step()
+    for _ in range(warmup):
+        p.train_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.train_step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, p.read_count(), stage_ms
 
 
 def frame_leg(args, torch, np, K, synth, Pipeline, out):
@@ -227,13 +261,14 @@ def frame_leg(args, torch, np, K, synth, Pipeline, out):
     fit_s = time.perf_counter() - t0
     del data
     # FP32 multi-init reference frame
-    p32 = Pipeline(wf, device="cuda:0")
+    p32 = Pipeline(wf, device="cuda:0", device_count=True)
     ms32, S, st32 = time_forward(p32, 5, torch, stages=True)
     c32 = p32.color.double().cpu().numpy()
     steps32 = int(p32.steps[:S].to(torch.int64).sum().item())
     del p32
     # FP16 table + BF16 MLP + learned initialiser
-    pmx = Pipeline(wf, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16, rootinit_params=params)
+    pmx = Pipeline(wf, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16, rootinit_params=params,
+                   device_count=True)
     msmx, Smx, stmx = time_forward(pmx, 5, torch, stages=True)
     cmx = pmx.color.double().cpu().numpy()
     stepsmx = int(pmx.steps[:Smx].to(torch.int64).sum().item())
@@ -277,8 +312,8 @@ def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
     of Tab. 3); hash encode at T = 2^23 (FP16 table, 512 MiB)."""
     # tiny forward: 1024 rays x 64 samples, no occupancy grid, FP32
     wt = synth.tiny_forward()
-    pt = Pipeline(wt, device="cuda:0")
-    ms, S = time_forward(pt, 20, torch)
+    pt = Pipeline(wt, device="cuda:0", device_count=True)
+    ms, S, _ = time_forward(pt, 20, torch)
     out["tiny_forward_f32"] = {"workload": "1024 front-face rays x 64 samples, 32^3x24 skinning grid, hash 2^14 FP32",
                                "ms": ms, "posed_samples": S, "samples_per_s": S / (ms * 1e-3)}
     del pt
@@ -288,22 +323,17 @@ def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
     wd.occ = np.ones_like(w.occ)
     res = {}
     for tag, wl in (("with_skipping", w), ("without_skipping", wd)):
-        pd = Pipeline(wl, device="cuda:0")
-        for _ in range(2):
-            pd.train_step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            Sd = pd.train_step()
-        torch.cuda.synchronize()
-        res[tag] = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / 5, "posed_samples": Sd}
+        pd = Pipeline(wl, device="cuda:0", device_count=True)
+        dt, Sd, _ = time_train(pd, 5, 2, torch)
+        res[tag] = {"ms_per_step": dt * 1e3 / 5, "posed_samples": Sd}
         del pd
     wf = synth.full_frame()
     wfd = synth.full_frame()
     wfd.occ = np.ones_like(wf.occ)
     for tag, wl in (("frame_with_skipping", wf), ("frame_without_skipping", wfd)):
-        pf = Pipeline(wl, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16, rootinit_params=params)
-        msf, Sf = time_forward(pf, 3, torch)
+        pf = Pipeline(wl, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16, rootinit_params=params,
+                      device_count=True)
+        msf, Sf, _ = time_forward(pf, 3, torch)
         res[tag] = {"ms_per_frame": msf, "posed_samples": Sf, "dtype": "f16/bf16, learned init"}
         del pf
     res["training_speedup"] = res["without_skipping"]["ms_per_step"] / res["with_skipping"]["ms_per_step"]
@@ -317,7 +347,6 @@ def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
     feat = torch.empty(16 * S * 2, dtype=torch.bfloat16, device="cuda:0")
     gt = torch.empty(16, 1 << 23, 2, device="cuda:0")
     gf = torch.randn(16 * S * 2, device="cuda:0")
-    wsb = torch.empty(K.hashgrid_bwd_workspace_size(S, 16, 23), dtype=torch.uint8, device="cuda:0")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     for _ in range(2):
         ev[0].record()
@@ -325,8 +354,7 @@ def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
             K.hashgrid_encode(x, None, S, S, table, 16.0, 1.38, (0, 0, 0, 1, 1, 1), feat)
         ev[1].record()
         for _ in range(2):
-            K.hashgrid_encode_bwd(gf, x, None, S, S, table, 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, None, K.OVERWRITE,
-                                  ws=wsb)
+            K.hashgrid_encode_bwd(gf, x, None, S, S, table, 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, None, K.OVERWRITE)
         ev[2].record()
     torch.cuda.synchronize()
     fwd_ms = ev[0].elapsed_time(ev[1]) / 5
@@ -336,7 +364,7 @@ def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
                                "fwd_algorithmic_GBs": fwd_bytes / (fwd_ms * 1e-3) / 1e9,
                                "fwd_frac_of_hbm_peak": fwd_bytes / (fwd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                                "bwd_table_ms_incl_zero_fill": bwd_ms}
-    del table, gt, wsb
+    del table, gt
 
 
 def learned_init_leg(params, torch, np, K, synth, out):
@@ -387,27 +415,15 @@ def learned_init_leg(params, torch, np, K, synth, out):
     }
 
 
-def mixed_leg(args, w, S0, steps_total, nb, loss32, gp32, torch, np, K, Pipeline, StageTimer, out):
+def mixed_leg(args, w, S0, steps_total, nb, loss32, gp32, torch, np, K, Pipeline, out):
     """The training step with the FP16 table and the BF16 MLP (forward and
     backward), FP32 deform and compositing."""
-    pm = Pipeline(w, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16)
-    for _ in range(args.warmup):
-        pm.train_step()
-    torch.cuda.synchronize()
-    tm = StageTimer()
-    pm.timer = tm
-    t0 = time.perf_counter()
-    sm = 0
-    for _ in range(args.steps):
-        sm += pm.train_step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    pm.timer = None
-    stm = {k: v / args.steps for k, v in tm.totals_ms().items()}
+    pm = Pipeline(w, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16, device_count=True)
+    dt, Sm, stm = time_train(pm, args.steps, args.warmup, torch, stages=True)
     gpm = pm.grad_params.double().cpu().numpy()
     out["mixed_training_step"] = {
         "dtype": "f16 table, bf16 MLP (MFMA, f32 accumulate), f32 deform and compositing",
-        "value": sm / (t1 - t0), "unit": "posed samples/s", "ms_per_step": (t1 - t0) * 1e3 / args.steps,
+        "value": Sm * args.steps / dt, "unit": "posed samples/s", "ms_per_step": dt * 1e3 / args.steps,
         "stages_ms": {k: round(v, 4) for k, v in stm.items()},
         "stage_roofline": stage_rooflines(stm, S0, w.R, steps_total, nb, 2, True),
         "loss_rel_diff_vs_f32": abs(float(pm.loss.item()) - loss32) / abs(loss32),
@@ -464,11 +480,11 @@ def pmc_summary(fetch_dir, write_dir):
     print(json.dumps(out, indent=1))
 
 
-COPY_CAL_FLOATS = 64 << 20  # 256 MiB read and written by the calibration copy
+COPY_CAL_FLOATS = 256 << 20  # 1 GiB read and written (4x the 256 MB Infinity Cache)
 
 
 def copy_calibration(torch):
-    """A plain elementwise copy of known size (read 256 MiB, write 256 MiB),
+    """A plain elementwise copy of known size (read 1 GiB, write 1 GiB),
     for scaling the HBM byte counters."""
     src = torch.empty(COPY_CAL_FLOATS, device="cuda:0")
     dst = torch.empty_like(src)
@@ -505,33 +521,37 @@ def main():
 
     from paper_2212_10550_amd import lib as K
     from paper_2212_10550_amd import synth
-    from paper_2212_10550_amd.pipeline import Pipeline, StageTimer
+    from paper_2212_10550_amd.pipeline import Pipeline
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     log("building inputs")
     w = synth.train_step()
-    p = Pipeline(w, device="cuda:0")
+    # host-count path (one host round trip per step for the sample count),
+    # reported beside the timed path for context
+    ph = Pipeline(w, device="cuda:0")
     log("warmup")
     for _ in range(args.warmup):
-        p.train_step()
+        ph.train_step()
     torch.cuda.synchronize()
-    S0 = p.S
-    steps_total = int(p.steps[:S0].to(torch.int64).sum().item())
-    log(f"S={S0}; timing {args.steps} steps")
-    timer = StageTimer()
-    p.timer = timer
-    torch.cuda.synchronize()
+    S0 = ph.S
+    steps_total = int(ph.steps[:S0].to(torch.int64).sum().item())
     t0 = time.perf_counter()
-    samples = 0
     for _ in range(args.steps):
-        samples += p.train_step()
+        ph.train_step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    p.timer = None
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    stage_ms = {k: v / args.steps for k, v in timer.totals_ms().items()}
-    value = samples / (t1 - t0)
+    host_count_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    loss32 = float(ph.loss.item())
+    gp32 = ph.grad_params.double().cpu().numpy()
+    del ph
+    # timed path: device-resident counts, the step replayed as one HIP graph
+    log(f"S={S0}; timing {args.steps} steps")
+    p = Pipeline(w, device="cuda:0", device_count=True)
+    dt, S1, stage_ms = time_train(p, args.steps, args.warmup, torch, stages=True)
+    if S1 != S0:
+        raise RuntimeError(f"sample count differs between paths: {S1} vs {S0}")
+    ms_step = dt * 1e3 / args.steps
+    value = S0 * args.steps / dt
     nb = w.B.shape[0]
     out = {
         "metric": "posed samples/s (deform+encode+MLP+composite, fwd+bwd); ms per 540² frame",
@@ -542,15 +562,17 @@ def main():
                                "(~15%), skinning grid 64x64x32x24, hash 16 levels x 2^19 x 2 FP32, MLP 32-64-64-4, "
                                "24-init Broyden (<=10 steps), L2 loss, every backward pass incl. the IFT",
                    "rays": w.R, "posed_samples_per_step": S0, "broyden_steps_per_step": steps_total},
+        "execution": "device-resident sample counts; each step one HIP graph replay",
+        "host_count_eager_ms_per_step": host_count_ms,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
     }
     out["roofline"], out["stage_roofline"] = roofline(stage_ms, S0, w.R, steps_total, nb)
-    loss32 = float(p.loss.item())
-    gp32 = p.grad_params.double().cpu().numpy()
+    if abs(float(p.loss.item()) - loss32) > 1e-6 * abs(loss32):
+        raise RuntimeError("graph-replayed step and host-count step disagree on the loss")
     del p
     # the same step with FP16 hash features and the BF16 MLP (forward and backward)
     if not args.no_mixed:
-        mixed_leg(args, w, S0, steps_total, nb, loss32, gp32, torch, np, K, Pipeline, StageTimer, out)
+        mixed_leg(args, w, S0, steps_total, nb, loss32, gp32, torch, np, K, Pipeline, out)
     if args.copy_calibration:
         copy_calibration(torch)
     if not args.no_frame:

@@ -19,13 +19,22 @@
  *    Bone transforms B are [nb][3][4] row-major rigid transforms
  *    (canonical -> posed).  The skinning grid W is [Dz][Dy][Dx][nb].  The hash
  *    table is [L][T][F] with T = 2^log2T.  Features are level-major
- *    [L][S][F].  Boxes (aabb) are host float[6] = (lo x, lo y, lo z,
+ *    [L][ld][F].  Boxes (aabb) are host float[6] = (lo x, lo y, lo z,
  *    hi x, hi y, hi z).
  *  - A sample whose `bone` is negative has no canonical correspondence: it
  *    gets density 0, zero features and zero gradients (the paper's "set
  *    their density to zero" for skipped points, Sec. 3.3).
  *  - grad_* outputs documented as "accumulated" are added to (+=), so the
  *    caller zeroes them (ia355_zero) or sums over several calls.
+ *  - Device sample counts: every entry point that takes a sample count S
+ *    also takes `S_dev` (device int64, nullable).  With S_dev NULL the count
+ *    is S.  With S_dev given, the count is min(S, *S_dev) read on the device
+ *    when the kernels run, and S is the capacity the buffers, workspaces and
+ *    launches are sized for.  A whole step (march, whose sample count lands
+ *    in device memory, then every later stage) can so be enqueued without a
+ *    host round trip, and captured in a HIP graph.
+ *  - Features are level-major [L][ld][F]: level l of sample n is at
+ *    (l * ld + n) * F, with ld the leading dimension of the point set.
  */
 #ifndef IA355_H
 #define IA355_H
@@ -114,7 +123,7 @@ int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d, int64_t R,
  * ws: ia355_deform_workspace_size(Dx, Dy, Dz) bytes (the per-pose blended
  * transform grid sum_i W[v][i] B_i). */
 size_t ia355_deform_workspace_size(int32_t Dx, int32_t Dy, int32_t Dz);
-int32_t ia355_snarf_deform(const float *xp, int64_t S, int64_t ld,
+int32_t ia355_snarf_deform(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld,
                            const float *B, int32_t nb, const float *W,
                            int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb, const float *hash_aabb,
                            int32_t max_iter, float tol_stop, float tol_valid,
@@ -129,13 +138,13 @@ int32_t ia355_snarf_deform(const float *xp, int64_t S, int64_t ld,
  * With IA355_OVERWRITE in flags grad_B / grad_W are written instead (every
  * entry).  Samples with bone < 0 contribute nothing (grad_xp = 0).
  * The parameter gradients go through the per-vertex moment
- * Q_v = sum_s tri_v(x*_s) v_s x*_h,s^T, summed in LDS per slice of 1024
- * vertices (global atomics only for slices split over workgroups, or for
- * grids beyond 4M vertices); summation order inside an entry is not fixed.
- * ws: ia355_deform_bwd_workspace_size(S, Dx, Dy, Dz, nb) bytes (about 44 B
- * per sample, 48 B per grid vertex and the dL/dB block partials). */
+ * Q_v = sum_s tri_v(x*_s) v_s x*_h,s^T (FP32 atomics; the summation order
+ * inside an entry is not fixed).
+ * ws: ia355_deform_bwd_workspace_size(S, Dx, Dy, Dz, nb) bytes (12 B per
+ * sample, 48 B per grid vertex and the dL/dB block partials). */
 size_t ia355_deform_bwd_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz, int32_t nb);
-int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int16_t *bone, int64_t S, int64_t ld,
+int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int16_t *bone, int64_t S,
+                               const int64_t *S_dev, int64_t ld,
                                const float *B, int32_t nb, const float *W,
                                int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
                                float *grad_xp, float *grad_B, float *grad_W, uint32_t flags,
@@ -151,7 +160,8 @@ int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int1
  *   hidden must be 64 and nb + 3 <= 32; dtype IA355_F32 or IA355_BF16
  *   (BF16 MFMA for the two hidden-to-hidden/output layers, FP32 accumulate)
  *   init_bone [S] int16, x0 [3][ld] outputs. */
-int32_t ia355_rootinit_fwd(const float *xp, int64_t S, int64_t ld, const float *pose, const float *params,
+int32_t ia355_rootinit_fwd(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld, const float *pose,
+                           const float *params,
                            int32_t hidden, const float *B, int32_t nb, int32_t dtype, int16_t *init_bone,
                            float *x0, ia355_stream_t stream);
 
@@ -164,7 +174,8 @@ int32_t ia355_rootinit_fwd(const float *xp, int64_t S, int64_t ld, const float *
  *   number of fallback samples.
  * ws: ia355_deform_guided_workspace_size(S, Dx, Dy, Dz) bytes. */
 size_t ia355_deform_guided_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz);
-int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, int64_t ld, const float *x0, const int16_t *init_bone,
+int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld, const float *x0,
+                                  const int16_t *init_bone,
                                   const float *B, int32_t nb, const float *W, int32_t Dx, int32_t Dy, int32_t Dz,
                                   const float *skin_aabb, const float *hash_aabb, int32_t max_iter, float tol_stop,
                                   float tol_valid, float *xc, int16_t *bone, float *resid, int16_t *steps,
@@ -181,53 +192,51 @@ int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, int64_t ld, const 
  * trilinearly interpolated; the levels are concatenated.
  *   xc [3][ld], bone [S] (nullable: all valid)
  *   table [L][T][F] of table_dtype (IA355_F32 or IA355_F16)
- *   feat  [L][S][F] of feat_dtype (IA355_F32 or IA355_BF16); zero for
+ *   feat  [L][ld][F] of feat_dtype (IA355_F32 or IA355_BF16); zero for
  *         invalid samples.  F must be 2.  Interpolation is FP32. */
-int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, int64_t ld,
+int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, const int64_t *S_dev, int64_t ld,
                               const void *table, int32_t table_dtype, int32_t L, int32_t F, int32_t log2T,
                               double base_res, double growth, const float *aabb,
                               void *feat, int32_t feat_dtype, ia355_stream_t stream);
 
-/* Backward of the encoding.  grad_feat [L][S][F] FP32.
+/* Backward of the encoding.  grad_feat [L][ld][F] FP32.
  *   grad_table [L][T][F] FP32 += sum over samples of w_c * grad_feat_l at each
  *   corner (nullable); with IA355_OVERWRITE in flags it is written instead
  *   (every entry, untouched ones set to 0).  Summation order inside a table
  *   entry is not fixed (atomic adds), so the last bits may vary run to run.
  *   grad_xc [3][ld] overwritten with sum_l sum_c (grad w_c)(theta_c . grad_feat_l)
  *   (nullable; needs the table).
- * ws: device scratch of ia355_hashgrid_bwd_workspace_size(S, L, log2T) bytes
- * selects the binned table gradient (contributions grouped by table slice
- * and summed in LDS; about 10 bytes per sample, level and corner).  With
- * ws NULL, or where that size is 0 (T > 2^25 or S > 2^27), the table
- * gradient is added with global atomics instead (same result up to
- * summation order, slower).  IA355_ERR_WORKSPACE if ws_bytes is too small. */
-size_t ia355_hashgrid_bwd_workspace_size(int64_t S, int32_t L, int32_t log2T);
+ * The table gradient is added with FP32 global atomics laid out so that each
+ * wave instruction touches few cache lines (run aggregation by a segmented
+ * wave scan on the coarse dense levels, 16 lanes per sample and level
+ * elsewhere). */
 int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone,
-                                  int64_t S, int64_t ld, const void *table, int32_t table_dtype,
+                                  int64_t S, const int64_t *S_dev, int64_t ld, const void *table, int32_t table_dtype,
                                   int32_t L, int32_t F, int32_t log2T, double base_res, double growth,
                                   const float *aabb, float *grad_table, float *grad_xc, uint32_t flags,
-                                  void *ws, size_t ws_bytes, ia355_stream_t stream);
+                                  ia355_stream_t stream);
 
 /* The decoder MLP 32 -> 64 -> 64 -> 4 with ReLU hidden layers; outputs
  * sigma = exp(o_0) (clamped at exp(80)) and c = sigmoid(o_1..3).
- *   feat [L][S][F] (L*F = 32) of feat_dtype; params FP32 flat
+ *   feat [L][ld][F] (L*F = 32) of feat_dtype; params FP32 flat
  *   (per layer W [out][in] row-major, then b [out]; 6532 floats)
  *   dtype: IA355_F32 (FP32 MFMA) or IA355_BF16 (BF16 MFMA, FP32 accumulate;
  *   requires feat_dtype BF16)
  *   sigma [S], rgb [3][ld] FP32; invalid samples (bone < 0) get 0. */
-int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int16_t *bone, int64_t S, int64_t ld,
+int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int16_t *bone, int64_t S, const int64_t *S_dev,
+                      int64_t ld,
                       const float *params, int32_t dtype, float *sigma, float *rgb, ia355_stream_t stream);
 
 /* Backward of the MLP (the forward is recomputed from feat; nothing is
  * saved).  grad_sigma [S], grad_rgb [3][ld] FP32.
  *   grad_params [6532] FP32 accumulated (written with IA355_OVERWRITE)
- *   grad_feat [L][S][F] FP32 overwritten (nullable)
+ *   grad_feat [L][ld][F] FP32 overwritten (nullable)
  * ws: ia355_mlp_bwd_workspace_size(S) bytes (per-block weight-gradient
  * partials, reduced in a fixed order: the result is deterministic). */
 size_t ia355_mlp_bwd_workspace_size(int64_t S);
 int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb, const void *feat, int32_t feat_dtype,
-                      const int16_t *bone, int64_t S, int64_t ld, const float *params, int32_t dtype,
-                      float *grad_params, float *grad_feat, uint32_t flags, void *ws, size_t ws_bytes,
+                      const int16_t *bone, int64_t S, const int64_t *S_dev, int64_t ld, const float *params,
+                      int32_t dtype, float *grad_params, float *grad_feat, uint32_t flags, void *ws, size_t ws_bytes,
                       ia355_stream_t stream);
 
 /* ------------------------------------------------------------------ */

@@ -30,6 +30,25 @@ inline unsigned grid_for(int64_t n, int block, int64_t max_blocks = 256 * 16) {
   return (unsigned)g;
 }
 
+// Sample count of a call.  Without a device counter it is S; with one it is
+// min(S, *S_dev), read on the device, and S is the capacity the caller sized
+// the buffers and the launch for.  Kernels that take S_dev loop over their
+// items (grid-stride), so a grid sized for the capacity stays bounded.
+__device__ __forceinline__ int64_t count_of(int64_t S, const int64_t *S_dev) {
+  if (!S_dev) return S;
+  const int64_t d = *S_dev;
+  return d < 0 ? 0 : (d < S ? d : S);
+}
+
+// Blocks for a grid-stride launch over `needed` blocks of work: all of them
+// when the count is known on the host, at most `cap_blocks` when it is read
+// on the device (the loop covers the rest).
+inline unsigned stride_grid(int64_t needed, bool device_count, int64_t cap_blocks = 2048) {
+  if (needed < 1) needed = 1;
+  if (device_count && needed > cap_blocks) needed = cap_blocks;
+  return (unsigned)needed;
+}
+
 // Workspace carving: 256-byte aligned slices.
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 

@@ -12,7 +12,6 @@
 //    Broyden solves in FP32 registers and pick the lowest residual with
 //    shuffles; bone inverses are staged in LDS once per block; the blended
 //    grid is read through the vector L1/L2 with float4 gathers.
-#include "binning.h"
 #include "common.h"
 #include "geometry.h"
 
@@ -312,25 +311,31 @@ __device__ __forceinline__ void write_choice(const Choice &c, int64_t n, int64_t
 }
 
 __global__ void __launch_bounds__(kSolveBlock) solve_kernel(
-    const float *__restrict__ xp_soa, int64_t S, int64_t ld, const float *__restrict__ B, int nb,
-    const float *__restrict__ A, Grid gr, Box hbox, int max_iter, float tol_stop, float tol_valid,
-    float *__restrict__ xc_soa, int16_t *__restrict__ bone_out, float *__restrict__ resid_out,
+    const float *__restrict__ xp_soa, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
+    const float *__restrict__ B, int nb, const float *__restrict__ A, Grid gr, Box hbox, int max_iter, float tol_stop,
+    float tol_valid, float *__restrict__ xc_soa, int16_t *__restrict__ bone_out, float *__restrict__ resid_out,
     int16_t *__restrict__ steps_out) {
   __shared__ float sBinv[kMaxBones * 12];
   __shared__ int sBok[kMaxBones];
   stage_bone_inverses(B, nb, sBinv, sBok);
   __syncthreads();
+  const int64_t Sn = count_of(S, S_dev);
   const int j = threadIdx.x % kGroup;
-  const int64_t n = ((int64_t)blockIdx.x * kSolveBlock + threadIdx.x) / kGroup;
-  const bool act = n < S;
-  float xp[3] = {0.0f, 0.0f, 0.0f};
-  if (act) {
-    xp[0] = xp_soa[n];
-    xp[1] = xp_soa[ld + n];
-    xp[2] = xp_soa[2 * ld + n];
+  constexpr int kPerBlock = kSolveBlock / kGroup;
+  // every lane of a block runs the same iterations, so the groups' shuffles
+  // always see all eight lanes
+  for (int64_t n0 = (int64_t)blockIdx.x * kPerBlock; n0 < Sn; n0 += (int64_t)gridDim.x * kPerBlock) {
+    const int64_t n = n0 + threadIdx.x / kGroup;
+    const bool act = n < Sn;
+    float xp[3] = {0.0f, 0.0f, 0.0f};
+    if (act) {
+      xp[0] = xp_soa[n];
+      xp[1] = xp_soa[ld + n];
+      xp[2] = xp_soa[2 * ld + n];
+    }
+    const Choice c = multi_init(A, gr, sBinv, sBok, nb, xp, act, j, hbox, max_iter, tol_stop, tol_valid);
+    if (act && j == 0) write_choice(c, n, ld, 0, xc_soa, bone_out, resid_out, steps_out);
   }
-  const Choice c = multi_init(A, gr, sBinv, sBok, nb, xp, act, j, hbox, max_iter, tol_stop, tol_valid);
-  if (act && j == 0) write_choice(c, n, ld, 0, xc_soa, bone_out, resid_out, steps_out);
 }
 
 // Guided solve: one lane per sample starts Broyden at the given x0; an
@@ -338,53 +343,59 @@ __global__ void __launch_bounds__(kSolveBlock) solve_kernel(
 // otherwise the sample index is appended to the fallback queue.
 __global__ void __launch_bounds__(kSolveBlock) guided_kernel(
     const float *__restrict__ xp_soa, const float *__restrict__ x0_soa, const int16_t *__restrict__ guide,
-    int64_t S, int64_t ld, const float *__restrict__ A, Grid gr, Box hbox, int max_iter, float tol_stop,
-    float tol_valid, float *__restrict__ xc_soa, int16_t *__restrict__ bone_out, float *__restrict__ resid_out,
-    int16_t *__restrict__ steps_out, int32_t *__restrict__ queue, int32_t *__restrict__ qlen,
-    int16_t *__restrict__ gsteps) {
-  const int64_t n = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
-  if (n >= S) return;
-  const float xp[3] = {xp_soa[n], xp_soa[ld + n], xp_soa[2 * ld + n]};
-  float x[3] = {x0_soa[n], x0_soa[ld + n], x0_soa[2 * ld + n]};
-  const InitResult q = broyden_from(A, gr, x, true, xp, max_iter, tol_stop);
-  gsteps[n] = (int16_t)q.steps;
-  if (q.ok && q.r < tol_valid && in_hbox(q.x, hbox)) {
-    xc_soa[n] = q.x[0];
-    xc_soa[ld + n] = q.x[1];
-    xc_soa[2 * ld + n] = q.x[2];
-    bone_out[n] = guide[n];
-    if (resid_out) resid_out[n] = q.r;
-    if (steps_out) steps_out[n] = (int16_t)q.steps;
-  } else {
-    queue[atomicAdd(qlen, 1)] = (int32_t)n;
+    int64_t S, const int64_t *__restrict__ S_dev, int64_t ld, const float *__restrict__ A, Grid gr, Box hbox,
+    int max_iter, float tol_stop, float tol_valid, float *__restrict__ xc_soa, int16_t *__restrict__ bone_out,
+    float *__restrict__ resid_out, int16_t *__restrict__ steps_out, int32_t *__restrict__ queue,
+    int32_t *__restrict__ qlen, int16_t *__restrict__ gsteps) {
+  const int64_t Sn = count_of(S, S_dev);
+  for (int64_t n = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x; n < Sn; n += (int64_t)gridDim.x * kSolveBlock) {
+    const float xp[3] = {xp_soa[n], xp_soa[ld + n], xp_soa[2 * ld + n]};
+    float x[3] = {x0_soa[n], x0_soa[ld + n], x0_soa[2 * ld + n]};
+    const InitResult q = broyden_from(A, gr, x, true, xp, max_iter, tol_stop);
+    gsteps[n] = (int16_t)q.steps;
+    if (q.ok && q.r < tol_valid && in_hbox(q.x, hbox)) {
+      xc_soa[n] = q.x[0];
+      xc_soa[ld + n] = q.x[1];
+      xc_soa[2 * ld + n] = q.x[2];
+      bone_out[n] = guide[n];
+      if (resid_out) resid_out[n] = q.r;
+      if (steps_out) steps_out[n] = (int16_t)q.steps;
+    } else {
+      queue[atomicAdd(qlen, 1)] = (int32_t)n;
+    }
   }
 }
 
-// Fallback: multi-init solve of the queued samples (the grid covers every
-// sample; groups past the queue length exit at once).
+// Fallback: multi-init solve of the queued samples; the blocks loop over
+// the queue (its length is known only on the device).
 __global__ void __launch_bounds__(kSolveBlock) fallback_kernel(
     const float *__restrict__ xp_soa, int64_t ld, const float *__restrict__ B, int nb, const float *__restrict__ A,
     Grid gr, Box hbox, int max_iter, float tol_stop, float tol_valid, float *__restrict__ xc_soa,
     int16_t *__restrict__ bone_out, float *__restrict__ resid_out, int16_t *__restrict__ steps_out,
-    const int32_t *__restrict__ queue, const int32_t *__restrict__ qlen, const int16_t *__restrict__ gsteps) {
-  const int64_t q = ((int64_t)blockIdx.x * kSolveBlock + threadIdx.x) / kGroup;
-  const int32_t nq = *qlen;
-  if ((int64_t)blockIdx.x * (kSolveBlock / kGroup) >= nq) return;  // whole block past the queue
+    const int32_t *__restrict__ queue, const int32_t *__restrict__ qlen, const int16_t *__restrict__ gsteps,
+    int32_t *__restrict__ n_fallback) {
+  constexpr int kPerBlock = kSolveBlock / kGroup;
+  const int64_t nq = *qlen;
+  if (n_fallback && blockIdx.x == 0 && threadIdx.x == 0) *n_fallback = (int32_t)nq;
+  if ((int64_t)blockIdx.x * kPerBlock >= nq) return;  // the whole block is past the queue
   __shared__ float sBinv[kMaxBones * 12];
   __shared__ int sBok[kMaxBones];
   stage_bone_inverses(B, nb, sBinv, sBok);
   __syncthreads();
   const int j = threadIdx.x % kGroup;
-  const bool act = q < nq;
-  const int64_t n = act ? queue[q] : 0;
-  float xp[3] = {0.0f, 0.0f, 0.0f};
-  if (act) {
-    xp[0] = xp_soa[n];
-    xp[1] = xp_soa[ld + n];
-    xp[2] = xp_soa[2 * ld + n];
+  for (int64_t q0 = (int64_t)blockIdx.x * kPerBlock; q0 < nq; q0 += (int64_t)gridDim.x * kPerBlock) {
+    const int64_t q = q0 + threadIdx.x / kGroup;
+    const bool act = q < nq;
+    const int64_t n = act ? queue[q] : 0;
+    float xp[3] = {0.0f, 0.0f, 0.0f};
+    if (act) {
+      xp[0] = xp_soa[n];
+      xp[1] = xp_soa[ld + n];
+      xp[2] = xp_soa[2 * ld + n];
+    }
+    const Choice c = multi_init(A, gr, sBinv, sBok, nb, xp, act, j, hbox, max_iter, tol_stop, tol_valid);
+    if (act && j == 0) write_choice(c, n, ld, gsteps[n], xc_soa, bone_out, resid_out, steps_out);
   }
-  const Choice c = multi_init(A, gr, sBinv, sBok, nb, xp, act, j, hbox, max_iter, tol_stop, tol_valid);
-  if (act && j == 0) write_choice(c, n, ld, gsteps[n], xc_soa, bone_out, resid_out, steps_out);
 }
 
 // ------------------------------------------------------------------------
@@ -406,16 +417,10 @@ constexpr int kBwdBlock = 256;
 constexpr int kMaxBonesBwd = 32;  // skinning weights of one sample kept in registers
 constexpr int kOwnBlock = 256;
 
-__global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restrict__ gxc, const float *__restrict__ xc_soa,
-                                                        const int16_t *__restrict__ bone, int64_t S, int64_t ld,
-                                                        const float *__restrict__ B, int nb,
-                                                        const float *__restrict__ W, Grid gr, int w_vec4,
-                                                        float *__restrict__ gxp, float *__restrict__ vbuf) {
-  __shared__ float sB[kMaxBones * 12];
-  for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) sB[i] = B[i];
-  __syncthreads();
-  const int64_t n = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x;
-  if (n >= S) return;
+__device__ __forceinline__ void ift_v_one(const float *__restrict__ gxc, const float *__restrict__ xc_soa,
+                                          const int16_t *__restrict__ bone, int64_t n, int64_t S, int64_t ld,
+                                          const float *sB, int nb, const float *__restrict__ W, const Grid &gr,
+                                          int w_vec4, float *__restrict__ gxp, float *__restrict__ vbuf) {
   float v[3] = {0.0f, 0.0f, 0.0f};
   if (bone[n] >= 0) {
     const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
@@ -484,6 +489,22 @@ __global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restric
   vbuf[2 * S + n] = v[2];
 }
 
+// vbuf [3][S] (S = the capacity) holds v for ift_q.
+__global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restrict__ gxc, const float *__restrict__ xc_soa,
+                                                        const int16_t *__restrict__ bone, int64_t S,
+                                                        const int64_t *__restrict__ S_dev, int64_t ld,
+                                                        const float *__restrict__ B, int nb,
+                                                        const float *__restrict__ W, Grid gr, int w_vec4,
+                                                        float *__restrict__ gxp, float *__restrict__ vbuf) {
+  __shared__ float sB[kMaxBones * 12];
+  for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) sB[i] = B[i];
+  __syncthreads();
+  const int64_t Sn = count_of(S, S_dev);
+  for (int64_t n = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x; n < Sn; n += (int64_t)gridDim.x * kBwdBlock)
+    ift_v_one(gxc, xc_soa, bone, n, S, ld, sB, nb, W, gr, w_vec4, gxp, vbuf);
+}
+
+
 // Q_v += tri_v(x*) v x*_h^T: 64 lanes per sample, lane = 8 * corner + slot,
 // slots j and j + 8 (< 12) of the corner's 12 floats.  A corner's 12 floats
 // are 48 contiguous bytes and x-neighbouring corners are adjacent vertices,
@@ -491,179 +512,23 @@ __global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restric
 // random lines are limited by L2 requests, not by floats).
 __global__ void __launch_bounds__(kOwnBlock) ift_q_kernel(const float *__restrict__ xc_soa,
                                                         const int16_t *__restrict__ bone, const float *__restrict__ vbuf,
-                                                        int64_t S, int64_t ld, Grid gr, float *__restrict__ Q) {
-  const int64_t t = (int64_t)blockIdx.x * kOwnBlock + threadIdx.x;
-  const int64_t n = t >> 6;
-  if (n >= S || bone[n] < 0) return;
-  const int lane = (int)(t & 63), k = lane >> 3, j = lane & 7;
-  const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
-  const float v[3] = {vbuf[n], vbuf[S + n], vbuf[2 * S + n]};
-  const Cell c = locate(gr, x);
-  const int64_t vtx = ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] +
-                      (c.i0[0] + (k & 1));
-  const float tw = tri_weight(c.f, k);
-  const float xh[4] = {x[0], x[1], x[2], 1.0f};
-  float *q = Q + 12 * vtx;
-  atomicAdd(q + j, tw * v[j >> 2] * xh[j & 3]);
-  if (j < 4) atomicAdd(q + 8 + j, tw * v[2] * xh[j]);
-}
-
-// Binned accumulation of Q (same result as ift_q_kernel up to summation
-// order, without global atomics): the vertices are cut into slices of 1024
-// (12 floats each, 48 KB of LDS).  q_bin_kernel writes one 4-byte record
-// (sample << 3 | corner) per corner, grouped by slice, for each chunk of
-// 256 samples; q_accumulate_kernel recomputes each record's cell, weight and
-// 12 products, adds them in LDS and adds the slice to Q with coalesced
-// stores (atomics only where a slice is split over several workgroups).
-constexpr int kQChunk = 256;
-constexpr int kQSliceLog2 = 10;
-constexpr int kQMaxSlices = 4096;
-constexpr int kQRecPerGroup = 8192;
-constexpr int kQAccBlock = 256;
-constexpr int kQAccMaxGrid = 2048;
-
-struct QLayout {
-  int64_t chunks = 0, max_items = 0;
-  int nsl = 0;
-  size_t offs = 0, recs = 0, tot = 0, items = 0, nitems = 0, bytes = 0;
-};
-
-bool q_layout(int64_t S, int64_t nvert, QLayout *q) {
-  if (S <= 0 || S > (1ll << 28)) return false;
-  const int64_t nsl = ceil_div(nvert, (int64_t)1 << kQSliceLog2);
-  if (nsl > kQMaxSlices) return false;
-  q->nsl = (int)nsl;
-  q->chunks = ceil_div(S, kQChunk);
-  q->max_items = nsl + ceil_div(8 * S, kQRecPerGroup) + 1;
-  size_t o = 0;
-  q->offs = o;
-  o = align256(o + sizeof(int32_t) * (size_t)q->chunks * (nsl + 1));
-  q->recs = o;
-  o = align256(o + sizeof(uint32_t) * (size_t)q->chunks * 8 * kQChunk);
-  q->tot = o;
-  o = align256(o + sizeof(int32_t) * (size_t)nsl);
-  q->items = o;
-  o = align256(o + sizeof(int4) * (size_t)q->max_items);
-  q->nitems = o;
-  o = align256(o + sizeof(int32_t));
-  q->bytes = o;
-  return true;
-}
-
-__device__ __forceinline__ int64_t corner_vertex(const Grid &gr, const Cell &c, int k) {
-  return ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] + (c.i0[0] + (k & 1));
-}
-
-__global__ void __launch_bounds__(kQChunk) q_bin_kernel(const float *__restrict__ xc_soa,
-                                                       const int16_t *__restrict__ bone, int64_t S, int64_t ld,
-                                                       Grid gr, int nsl, int32_t *__restrict__ offs,
-                                                       uint32_t *__restrict__ recs) {
-  __shared__ int cnt[kQMaxSlices];
-  __shared__ int red[kQChunk / kWave];
-  const int tid = threadIdx.x;
-  const int64_t chunk = blockIdx.x;
-  for (int i = tid; i < nsl; i += kQChunk) cnt[i] = 0;
-  __syncthreads();
-  const int64_t n = chunk * kQChunk + tid;
-  const bool act = n < S && bone[n] >= 0;
-  int sl[8];
-  if (act) {
+                                                        int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
+                                                        Grid gr, float *__restrict__ Q) {
+  const int64_t Sn = count_of(S, S_dev);
+  const int lane = (int)(threadIdx.x & 63), k = lane >> 3, j = lane & 7;
+  constexpr int kPerBlock = kOwnBlock / 64;
+  for (int64_t n = ((int64_t)blockIdx.x * kOwnBlock + threadIdx.x) >> 6; n < Sn; n += (int64_t)gridDim.x * kPerBlock) {
+    if (bone[n] < 0) continue;
     const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
+    const float v[3] = {vbuf[n], vbuf[S + n], vbuf[2 * S + n]};
     const Cell c = locate(gr, x);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      sl[k] = (int)(corner_vertex(gr, c, k) >> kQSliceLog2);
-      atomicAdd(&cnt[sl[k]], 1);
-    }
-  }
-  __syncthreads();
-  const int per = (nsl + kQChunk - 1) / kQChunk;
-  const int s0 = tid * per;
-  int mine = 0;
-  for (int i = 0; i < per; ++i)
-    if (s0 + i < nsl) mine += cnt[s0 + i];
-  int total;
-  int run = block_excl_scan<kQChunk / kWave>(mine, red, &total);
-  int32_t *row = offs + chunk * (nsl + 1);
-  for (int i = 0; i < per; ++i)
-    if (s0 + i < nsl) {
-      const int c = cnt[s0 + i];
-      row[s0 + i] = run;
-      cnt[s0 + i] = run;
-      run += c;
-    }
-  if (tid == 0) row[nsl] = total;
-  __syncthreads();
-  if (act) {
-    uint32_t *out = recs + chunk * (8 * kQChunk);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) out[atomicAdd(&cnt[sl[k]], 1)] = ((uint32_t)n << 3) | (uint32_t)k;
-  }
-}
-
-__global__ void __launch_bounds__(kQAccBlock) q_accumulate_kernel(const int32_t *__restrict__ offs,
-                                                                const uint32_t *__restrict__ recs,
-                                                                const int4 *__restrict__ items,
-                                                                const int32_t *__restrict__ n_items, int64_t chunks,
-                                                                int nsl, const float *__restrict__ xc_soa, int64_t ld,
-                                                                const float *__restrict__ vbuf, int64_t S, Grid gr,
-                                                                int64_t nvert, float *__restrict__ Q) {
-  __shared__ float acc[12 << kQSliceLog2];
-  __shared__ int sp[kQAccBlock];
-  __shared__ int64_t sb[kQAccBlock];
-  __shared__ int red[kQAccBlock / kWave];
-  const int tid = threadIdx.x;
-  const int64_t n_it = *n_items;
-  for (int64_t it = blockIdx.x; it < n_it; it += gridDim.x) {
-    const int4 info = items[it];
-    const int s = info.y, G = info.w;
-    int64_t c0, c1;
-    group_chunks(info.z, G, chunks, &c0, &c1);
-    const int64_t vbase = (int64_t)s << kQSliceLog2;
-    for (int e = tid; e < (12 << kQSliceLog2); e += kQAccBlock) acc[e] = 0.0f;
-    __syncthreads();
-    for (int64_t cb = c0; cb < c1; cb += kQAccBlock) {
-      const int nb = (int)((c1 - cb) < kQAccBlock ? (c1 - cb) : kQAccBlock);
-      int len = 0;
-      int64_t beg = 0;
-      if (tid < nb) {
-        const int32_t *row = offs + (cb + tid) * (nsl + 1);
-        const int b = row[s];
-        len = row[s + 1] - b;
-        beg = (cb + tid) * (8 * kQChunk) + b;
-      }
-      int m;
-      const int ex = block_excl_scan<kQAccBlock / kWave>(len, red, &m);
-      sp[tid] = ex;
-      sb[tid] = beg;
-      __syncthreads();
-      for (int r = tid; r < m; r += kQAccBlock) {
-        const uint32_t rec = recs[batch_record(r, nb, sp, sb)];
-        const int64_t n = rec >> 3;
-        const int k = (int)(rec & 7u);
-        const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
-        const float v[3] = {vbuf[n], vbuf[S + n], vbuf[2 * S + n]};
-        const Cell c = locate(gr, x);
-        const int64_t local = corner_vertex(gr, c, k) - vbase;  // same cell as in q_bin_kernel
-        if (local < 0 || local >= ((int64_t)1 << kQSliceLog2)) continue;
-        const float tw = tri_weight(c.f, k);
-        const float xh[4] = {x[0], x[1], x[2], 1.0f};
-        float *a = acc + 12 * local;
-#pragma unroll
-        for (int j = 0; j < 12; ++j) atomicAdd(a + j, tw * v[j >> 2] * xh[j & 3]);
-      }
-      __syncthreads();
-    }
-    const int64_t nv = (nvert - vbase) < ((int64_t)1 << kQSliceLog2) ? (nvert - vbase) : ((int64_t)1 << kQSliceLog2);
-    float *q = Q + 12 * vbase;
-    for (int e = tid; e < 12 * nv; e += kQAccBlock) {
-      const float a = acc[e];
-      if (a != 0.0f) {
-        if (G == 1) q[e] += a;
-        else atomicAdd(q + e, a);
-      }
-    }
-    __syncthreads();
+    const int64_t vtx = ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] +
+                        (c.i0[0] + (k & 1));
+    const float tw = tri_weight(c.f, k);
+    const float xh[4] = {x[0], x[1], x[2], 1.0f};
+    float *q = Q + 12 * vtx;
+    atomicAdd(q + j, tw * v[j >> 2] * xh[j & 3]);
+    if (j < 4) atomicAdd(q + 8 + j, tw * v[2] * xh[j]);
   }
 }
 
@@ -790,7 +655,8 @@ extern "C" size_t ia355_deform_workspace_size(int32_t Dx, int32_t Dy, int32_t Dz
   return align256(sizeof(float) * 12 * (size_t)Dx * Dy * Dz);
 }
 
-extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, int64_t ld, const float *B, int32_t nb,
+extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld, const float *B,
+                                      int32_t nb,
                                       const float *W, int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
                                       const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
                                       float *xc, int16_t *bone, float *resid, int16_t *steps, void *ws,
@@ -810,8 +676,8 @@ extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, int64_t ld, co
     hb.lo[a] = hash_aabb[a];
     hb.hi[a] = hash_aabb[3 + a];
   }
-  solve_kernel<<<(unsigned)ceil_div(S * kGroup, kSolveBlock), kSolveBlock, 0, s>>>(xp, S, ld, B, nb, A, g, hb, max_iter,
-                                                                         tol_stop, tol_valid, xc, bone, resid, steps);
+  solve_kernel<<<stride_grid(ceil_div(S * kGroup, kSolveBlock), S_dev != nullptr), kSolveBlock, 0, s>>>(
+      xp, S, S_dev, ld, B, nb, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps);
   return launch_status();
 }
 
@@ -821,7 +687,8 @@ extern "C" size_t ia355_deform_guided_workspace_size(int64_t S, int32_t Dx, int3
          align256(sizeof(int16_t) * (size_t)(S > 0 ? S : 1));
 }
 
-extern "C" int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, int64_t ld, const float *x0,
+extern "C" int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld,
+                                             const float *x0,
                                              const int16_t *guide_bone, const float *B, int32_t nb, const float *W,
                                              int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
                                              const float *hash_aabb, int32_t max_iter, float tol_stop,
@@ -849,27 +716,30 @@ extern "C" int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, int64_t
       hb.lo[a] = hash_aabb[a];
       hb.hi[a] = hash_aabb[3 + a];
     }
-    guided_kernel<<<(unsigned)ceil_div(S, kSolveBlock), kSolveBlock, 0, s>>>(
-        xp, x0, guide_bone, S, ld, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, queue, qlen,
-        gsteps);
-    fallback_kernel<<<(unsigned)ceil_div(S * kGroup, kSolveBlock), kSolveBlock, 0, s>>>(
-        xp, ld, B, nb, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, queue, qlen, gsteps);
+    const bool dev = S_dev != nullptr;
+    guided_kernel<<<stride_grid(ceil_div(S, kSolveBlock), dev), kSolveBlock, 0, s>>>(
+        xp, x0, guide_bone, S, S_dev, ld, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, queue,
+        qlen, gsteps);
+    fallback_kernel<<<stride_grid(ceil_div(S * kGroup, kSolveBlock), dev), kSolveBlock, 0, s>>>(
+        xp, ld, B, nb, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, queue, qlen, gsteps,
+        n_fallback);
+  } else if (n_fallback) {
+    st = ia355_zero(n_fallback, sizeof(int32_t), stream);
+    if (st != IA355_OK) return st;
   }
-  if (n_fallback) hipMemcpyAsync(n_fallback, qlen, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
   return launch_status();
 }
 
 extern "C" size_t ia355_deform_bwd_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz, int32_t nb) {
   if (S < 0 || Dx <= 0 || Dy <= 0 || Dz <= 0 || nb <= 0) return 0;
   const int64_t nvert = (int64_t)Dx * Dy * Dz;
-  QLayout ql;
-  const size_t qbytes = q_layout(S, nvert, &ql) ? ql.bytes : 0;
   return align256(sizeof(float) * 3 * (size_t)S) + align256(sizeof(float) * 12 * (size_t)nvert) +
-         align256(sizeof(float) * 12 * (size_t)nb * ceil_div(nvert, kConBlock)) + qbytes;
+         align256(sizeof(float) * 12 * (size_t)nb * ceil_div(nvert, kConBlock));
 }
 
 extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc, const int16_t *bone, int64_t S,
-                                          int64_t ld, const float *B, int32_t nb, const float *W, int32_t Dx,
+                                          const int64_t *S_dev, int64_t ld, const float *B, int32_t nb,
+                                          const float *W, int32_t Dx,
                                           int32_t Dy, int32_t Dz, const float *skin_aabb, float *grad_xp,
                                           float *grad_B, float *grad_W, uint32_t flags, void *ws, size_t ws_bytes,
                                           ia355_stream_t stream) {
@@ -888,29 +758,15 @@ extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc,
   float *partB = (float *)((char *)Q + align256(sizeof(float) * 12 * (size_t)nvert));
   if (S > 0) {
     const int w_vec4 = (nb % 4 == 0) && ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
-    ift_v_kernel<<<(unsigned)ceil_div(S, kBwdBlock), kBwdBlock, 0, s>>>(grad_xc, xc, bone, S, ld, B, nb, W, g,
-                                                                        w_vec4, grad_xp, vbuf);
+    ift_v_kernel<<<stride_grid(ceil_div(S, kBwdBlock), S_dev != nullptr), kBwdBlock, 0, s>>>(
+        grad_xc, xc, bone, S, S_dev, ld, B, nb, W, g, w_vec4, grad_xp, vbuf);
   }
   if (grad_W || grad_B) {
     const int32_t st = ia355_zero(Q, sizeof(float) * 12 * (size_t)nvert, stream);
     if (st != IA355_OK) return st;
-    QLayout ql;
-    if (S > 0 && q_layout(S, nvert, &ql)) {
-      char *qw = (char *)partB + align256(sizeof(float) * 12 * (size_t)nb * nblk);
-      int32_t *offs = reinterpret_cast<int32_t *>(qw + ql.offs);
-      uint32_t *recs = reinterpret_cast<uint32_t *>(qw + ql.recs);
-      int32_t *tot = reinterpret_cast<int32_t *>(qw + ql.tot);
-      int4 *items = reinterpret_cast<int4 *>(qw + ql.items);
-      int32_t *n_items = reinterpret_cast<int32_t *>(qw + ql.nitems);
-      q_bin_kernel<<<(unsigned)ql.chunks, kQChunk, 0, s>>>(xc, bone, S, ld, g, ql.nsl, offs, recs);
-      slice_total_kernel<<<(unsigned)ceil_div(ql.nsl, 256), 256, 0, s>>>(offs, 1, ql.chunks, ql.nsl, tot);
-      plan_kernel<<<1, kPlanBlock, 0, s>>>(tot, 1, ql.chunks, ql.nsl, kQRecPerGroup, items, n_items);
-      const int64_t grid = ql.max_items < kQAccMaxGrid ? ql.max_items : kQAccMaxGrid;
-      q_accumulate_kernel<<<(unsigned)grid, kQAccBlock, 0, s>>>(offs, recs, items, n_items, ql.chunks, ql.nsl, xc, ld,
-                                                                vbuf, S, g, nvert, Q);
-    } else if (S > 0) {
-      ift_q_kernel<<<(unsigned)ceil_div(S * 64, kOwnBlock), kOwnBlock, 0, s>>>(xc, bone, vbuf, S, ld, g, Q);
-    }
+    if (S > 0)
+      ift_q_kernel<<<stride_grid(ceil_div(S * 64, kOwnBlock), S_dev != nullptr, 8192), kOwnBlock, 0, s>>>(
+          xc, bone, vbuf, S, S_dev, ld, g, Q);
     ift_contract_kernel<<<(unsigned)nblk, kConThreads, 0, s>>>(Q, B, nb, W, nvert, grad_W, grad_B ? partB : nullptr,
                                                                overwrite);
     if (grad_B)

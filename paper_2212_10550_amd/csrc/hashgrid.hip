@@ -20,7 +20,6 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
-#include "binning.h"
 #include "common.h"
 
 using namespace ia355;
@@ -106,35 +105,40 @@ __device__ __forceinline__ void store_feat2(__hip_bfloat16 *f, int64_t i, float 
 
 constexpr int kFwdBlock = 256;
 
+// Block b works for XCD b % 8 on level (b % 8) + 8 * (slot % per_xcd) with
+// slot = b / 8, on 256-sample chunks slot / per_xcd, + nslot, + 2 nslot ...
 template <typename TT, typename FT>
 __global__ void __launch_bounds__(kFwdBlock) encode_kernel(const float *__restrict__ xc, const int16_t *__restrict__ bone,
-                                                           int64_t S, int64_t ld, const TT *__restrict__ table, int L,
-                                                           int log2T, Levels lv, Box box, FT *__restrict__ feat,
-                                                           int per_xcd) {
+                                                           int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
+                                                           const TT *__restrict__ table, int L, int log2T, Levels lv,
+                                                           Box box, FT *__restrict__ feat, int per_xcd) {
   const int xcd = blockIdx.x % kXcd;
   const int slot = blockIdx.x / kXcd;
   const int level = xcd + kXcd * (slot % per_xcd);
-  const int64_t chunk = slot / per_xcd;
   if (level >= L) return;
-  const int64_t n = chunk * kFwdBlock + threadIdx.x;
-  if (n >= S) return;
-  float a = 0.0f, b = 0.0f;
-  if (!bone || bone[n] >= 0) {
-    const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
-    Corners c;
-    const uint32_t T = 1u << log2T;
-    level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
-    const TT *tl = table + (int64_t)level * T * 2;
-    float2 v[8];
+  const int64_t Sn = count_of(S, S_dev);
+  const int64_t nslot = gridDim.x / (kXcd * per_xcd);
+  const uint32_t T = 1u << log2T;
+  const TT *tl = table + (int64_t)level * T * 2;
+  for (int64_t chunk = slot / per_xcd; chunk * kFwdBlock < Sn; chunk += nslot) {
+    const int64_t n = chunk * kFwdBlock + threadIdx.x;
+    if (n >= Sn) break;
+    float a = 0.0f, b = 0.0f;
+    if (!bone || bone[n] >= 0) {
+      const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
+      Corners c;
+      level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
+      float2 v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = load_feat2(tl, c.idx[k]);
+      for (int k = 0; k < 8; ++k) v[k] = load_feat2(tl, c.idx[k]);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      a += c.w[k] * v[k].x;
-      b += c.w[k] * v[k].y;
+      for (int k = 0; k < 8; ++k) {
+        a += c.w[k] * v[k].x;
+        b += c.w[k] * v[k].y;
+      }
     }
+    store_feat2(feat, (int64_t)level * ld + n, a, b);
   }
-  store_feat2(feat, (int64_t)level * S + n, a, b);
 }
 
 constexpr int kBwdBlock = 256;
@@ -143,27 +147,22 @@ constexpr int kBwdBlock = 256;
 template <typename TT>
 __global__ void __launch_bounds__(kBwdBlock) encode_bwd_kernel(
     const float *__restrict__ gfeat, const float *__restrict__ xc, const int16_t *__restrict__ bone, int64_t S,
-    int64_t ld, const TT *__restrict__ table, int L, int log2T, Levels lv, Box box, float *__restrict__ gtable,
+    const int64_t *__restrict__ S_dev, int64_t ld, const TT *__restrict__ table, int L, int log2T, Levels lv, Box box,
     float *__restrict__ gxc) {
   const int level = threadIdx.x & 15;
-  const int64_t n = ((int64_t)blockIdx.x * kBwdBlock + threadIdx.x) >> 4;
-  float gx[3] = {0.0f, 0.0f, 0.0f};
-  const bool act = n < S && level < L && (!bone || bone[n] >= 0);
-  if (act) {
-    const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
-    const float2 g = reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * S + n];
-    Corners c;
-    const uint32_t T = 1u << log2T;
-    level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, gxc != nullptr);
-    if (gtable) {
-      float *gl = gtable + (int64_t)level * T * 2;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        atomicAdd(gl + 2 * c.idx[k], c.w[k] * g.x);
-        atomicAdd(gl + 2 * c.idx[k] + 1, c.w[k] * g.y);
-      }
-    }
-    if (gxc) {
+  const int64_t Sn = count_of(S, S_dev);
+  constexpr int kPerBlock = kBwdBlock / 16;
+  // the 16 lanes of a sample share n, so they run the same iterations and
+  // the width-16 shuffles below always see their whole group
+  for (int64_t n = ((int64_t)blockIdx.x * kBwdBlock + threadIdx.x) >> 4; n < Sn; n += (int64_t)gridDim.x * kPerBlock) {
+    float gx[3] = {0.0f, 0.0f, 0.0f};
+    const bool act = level < L && (!bone || bone[n] >= 0);
+    if (act) {
+      const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
+      const float2 g = reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * ld + n];
+      Corners c;
+      const uint32_t T = 1u << log2T;
+      level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, true);
       const TT *tl = table + (int64_t)level * T * 2;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
@@ -174,15 +173,13 @@ __global__ void __launch_bounds__(kBwdBlock) encode_bwd_kernel(
         gx[2] += c.dw[k][2] * d;
       }
     }
-  }
-  if (gxc) {
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) {
       gx[0] += __shfl_xor(gx[0], o, 16);
       gx[1] += __shfl_xor(gx[1], o, 16);
       gx[2] += __shfl_xor(gx[2], o, 16);
     }
-    if (level == 0 && n < S) {
+    if (level == 0) {
       gxc[n] = gx[0];
       gxc[ld + n] = gx[1];
       gxc[2 * ld + n] = gx[2];
@@ -204,22 +201,25 @@ constexpr int kTgBlock = 256;
 
 __global__ void __launch_bounds__(kTgBlock) table_grad_kernel(const float *__restrict__ gfeat,
                                                              const float *__restrict__ xc,
-                                                             const int16_t *__restrict__ bone, int64_t S, int64_t ld,
-                                                             int l0, int L, int log2T, Levels lv, Box box,
+                                                             const int16_t *__restrict__ bone, int64_t S,
+                                                             const int64_t *__restrict__ S_dev, int64_t ld, int l0,
+                                                             int L, int log2T, Levels lv, Box box,
                                                              float *__restrict__ gtable) {
-  const int64_t t = (int64_t)blockIdx.x * kTgBlock + threadIdx.x;
-  const int64_t item = t >> 4;
-  if (item >= (int64_t)(L - l0) * S) return;
-  const int level = l0 + (int)(item / S);
-  const int64_t n = item - (int64_t)(level - l0) * S;  // 0 <= n < S
-  if (bone && bone[n] < 0) return;
-  const int sub = (int)(t & 15), k = sub >> 1, f = sub & 1;
-  const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
+  const int64_t Sn = count_of(S, S_dev);
+  const int64_t items = (int64_t)(L - l0) * Sn;
+  const int sub = (int)(threadIdx.x & 15), k = sub >> 1, f = sub & 1;
   const uint32_t T = 1u << log2T;
-  Corners c;
-  level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
-  const float g = gfeat[2 * ((int64_t)level * S + n) + f];
-  atomicAdd(gtable + 2 * ((int64_t)level * T + c.idx[k]) + f, c.w[k] * g);
+  for (int64_t item = ((int64_t)blockIdx.x * kTgBlock + threadIdx.x) >> 4; item < items;
+       item += (int64_t)gridDim.x * (kTgBlock / 16)) {
+    const int level = l0 + (int)(item / Sn);
+    const int64_t n = item - (int64_t)(level - l0) * Sn;  // 0 <= n < Sn
+    if (bone && bone[n] < 0) continue;
+    const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
+    Corners c;
+    level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
+    const float g = gfeat[2 * ((int64_t)level * ld + n) + f];
+    atomicAdd(gtable + 2 * ((int64_t)level * T + c.idx[k]) + f, c.w[k] * g);
+  }
 }
 
 // Dense (coarse) levels: many consecutive samples fall in the same cell, so
@@ -234,231 +234,52 @@ constexpr int kAggMaxRes = 32;  // finest resolution handled by run aggregation
 __global__ void __launch_bounds__(kDgBlock) table_grad_dense_kernel(const float *__restrict__ gfeat,
                                                                    const float *__restrict__ xc,
                                                                    const int16_t *__restrict__ bone, int64_t S,
-                                                                   int64_t ld, int64_t chunks, int log2T, Levels lv,
-                                                                   Box box, float *__restrict__ gtable) {
-  const int level = (int)(blockIdx.x / chunks);
-  const int64_t n = (blockIdx.x % chunks) * kDgBlock + threadIdx.x;
+                                                                   const int64_t *__restrict__ S_dev, int64_t ld,
+                                                                   int ndense, int log2T, Levels lv, Box box,
+                                                                   float *__restrict__ gtable) {
+  const int64_t Sn = count_of(S, S_dev);
+  const int64_t chunks = ceil_div(Sn, kDgBlock);
   const int lane = threadIdx.x & (kWave - 1);
-  const bool act = n < S && (!bone || bone[n] >= 0);
   const uint32_t T = 1u << log2T;
-  Corners c;
-  float2 g = make_float2(0.0f, 0.0f);
-  if (act) {
-    const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
-    level_cell(x, box, lv.res[level], true, T - 1u, c, false);
-    g = reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * S + n];
-  }
-  float *gl = gtable + (int64_t)level * T * 2;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int key = act ? (int)c.idx[k] : -1 - lane;  // inactive lanes: unique keys, no atomics
-    float v0 = act ? c.w[k] * g.x : 0.0f, v1 = act ? c.w[k] * g.y : 0.0f;
-    const int prev = __shfl_up(key, 1, kWave);
-    int hs = (lane == 0 || prev != key) ? lane : 0;  // run head index
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int t = __shfl_up(hs, o, kWave);
-      if (lane >= o) hs = max(hs, t);
-    }
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const float t0 = __shfl_up(v0, o, kWave), t1 = __shfl_up(v1, o, kWave);
-      if (lane - o >= hs) {
-        v0 += t0;
-        v1 += t1;
-      }
-    }
-    const int next = __shfl_down(key, 1, kWave);
-    if ((lane == kWave - 1 || next != key) && key >= 0) {
-      atomicAdd(gl + 2 * key, v0);
-      atomicAdd(gl + 2 * key + 1, v1);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Binned table gradient (used when a workspace is given).  Global FP32
-// atomics cost one L2/fabric request per touched cache line, and a fine
-// level's corners land on lines of their own, so the atomic path is bound by
-// that request rate.  Here the table of each level is cut into slices of
-// 2^13 entries (64 KB of FP32 pairs, one LDS buffer), and:
-//  1. bin_kernel: one workgroup per (level, 1024-sample chunk) computes each
-//     sample's 8 corners, counts them per slice in LDS, scans the counts
-//     (per-chunk slice offsets) and writes one record (entry in slice,
-//     w * dL/dfeat) per corner, grouped by slice;
-//  2. slice_total_kernel / plan_kernel: records per slice; a slice with many
-//     records (coarse levels) is split into up to kMaxGroups groups of
-//     chunks; the plan is a flat list of (level, slice, group, groups);
-//  3. accumulate_kernel: each item sums its records into the LDS slice with
-//     LDS atomics and adds the slice to the table with coalesced accesses:
-//     plain read-modify-write when it owns the slice alone, global atomics
-//     on the touched entries when the slice is split.
-constexpr int kBinChunk = 1024;
-constexpr int kBinBlock = 256;
-constexpr int kSliceLog2 = 13;
-constexpr int kMaxSlices = 4096;  // binned path for T <= 2^25
-constexpr int kRecPerGroup = 16384;
-constexpr int kAccBlock = 256;
-constexpr int kAccMaxGrid = 4096;
-
-struct BinLayout {
-  int64_t chunks = 0, max_items = 0;
-  int nsl = 0, sl = 0;
-  size_t offs = 0, keys = 0, vals = 0, tot = 0, items = 0, nitems = 0, bytes = 0;
-};
-
-bool bin_layout(int64_t S, int L, int log2T, BinLayout *b) {
-  if (S <= 0 || L <= 0 || log2T < 1 || log2T - kSliceLog2 > 12 || S > (1ll << 27)) return false;
-  b->sl = log2T < kSliceLog2 ? log2T : kSliceLog2;
-  b->nsl = 1 << (log2T - b->sl);
-  b->chunks = ceil_div(S, kBinChunk);
-  b->max_items = (int64_t)L * b->nsl + ceil_div(8 * S * L, kRecPerGroup) + 1;
-  const int64_t rec = (int64_t)L * b->chunks * 8 * kBinChunk;
-  size_t o = 0;
-  b->offs = o;
-  o = align256(o + sizeof(int32_t) * (size_t)L * b->chunks * (b->nsl + 1));
-  b->keys = o;
-  o = align256(o + sizeof(uint16_t) * (size_t)rec);
-  b->vals = o;
-  o = align256(o + sizeof(float2) * (size_t)rec);
-  b->tot = o;
-  o = align256(o + sizeof(int32_t) * (size_t)L * b->nsl);
-  b->items = o;
-  o = align256(o + sizeof(int4) * (size_t)b->max_items);
-  b->nitems = o;
-  o = align256(o + sizeof(int32_t));
-  b->bytes = o;
-  return true;
-}
-
-__global__ void __launch_bounds__(kBinBlock) bin_kernel(const float *__restrict__ gfeat, const float *__restrict__ xc,
-                                                       const int16_t *__restrict__ bone, int64_t S, int64_t ld,
-                                                       int64_t chunks, int log2T, int sl, int nsl, Levels lv,
-                                                       Box box, int32_t *__restrict__ offs,
-                                                       uint16_t *__restrict__ keys, float2 *__restrict__ vals) {
-  __shared__ int cnt[kMaxSlices];
-  __shared__ int red[kBinBlock / kWave];
-  const int level = (int)(blockIdx.x / chunks);
-  const int64_t chunk = blockIdx.x % chunks;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < nsl; i += kBinBlock) cnt[i] = 0;
-  __syncthreads();
-  const uint32_t T = 1u << log2T;
-  constexpr int kPer = kBinChunk / kBinBlock;
-  uint32_t idx[kPer][8];
-  float val[kPer][8];
-  float2 g[kPer];
-  bool act[kPer];
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    const int64_t n = chunk * kBinChunk + j * kBinBlock + tid;
-    act[j] = n < S && (!bone || bone[n] >= 0);
-    g[j] = make_float2(0.0f, 0.0f);
-    if (act[j]) {
+  // one (level, chunk) pair per block and step; the whole wave takes part
+  // in the scans below
+  for (int64_t p = blockIdx.x; p < (int64_t)ndense * chunks; p += gridDim.x) {
+    const int level = (int)(p / chunks);
+    const int64_t n = (p % chunks) * kDgBlock + threadIdx.x;
+    const bool act = n < Sn && (!bone || bone[n] >= 0);
+    Corners c;
+    float2 g = make_float2(0.0f, 0.0f);
+    if (act) {
       const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
-      Corners c;
-      level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
-      g[j] = reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * S + n];
+      level_cell(x, box, lv.res[level], true, T - 1u, c, false);
+      g = reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * ld + n];
+    }
+    float *gl = gtable + (int64_t)level * T * 2;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        idx[j][k] = c.idx[k];
-        val[j][k] = c.w[k];
-        atomicAdd(&cnt[c.idx[k] >> sl], 1);
-      }
-    }
-  }
-  __syncthreads();
-  // exclusive scan of the slice counts: thread t owns a run of slices
-  const int per = (nsl + kBinBlock - 1) / kBinBlock;
-  const int s0 = tid * per;
-  int mine = 0;
-  for (int i = 0; i < per; ++i)
-    if (s0 + i < nsl) mine += cnt[s0 + i];
-  int total;
-  int run = block_excl_scan<kBinBlock / kWave>(mine, red, &total);
-  int32_t *row = offs + ((int64_t)level * chunks + chunk) * (nsl + 1);
-  for (int i = 0; i < per; ++i)
-    if (s0 + i < nsl) {
-      const int c = cnt[s0 + i];
-      row[s0 + i] = run;
-      cnt[s0 + i] = run;  // becomes the slice's write cursor
-      run += c;
-    }
-  if (tid == 0) row[nsl] = total;
-  __syncthreads();
-  const int64_t rec = ((int64_t)level * chunks + chunk) * (8 * kBinChunk);
-  const uint32_t emask = (1u << sl) - 1u;
+    for (int k = 0; k < 8; ++k) {
+      const int key = act ? (int)c.idx[k] : -1 - lane;  // inactive lanes: unique keys, no atomics
+      float v0 = act ? c.w[k] * g.x : 0.0f, v1 = act ? c.w[k] * g.y : 0.0f;
+      const int prev = __shfl_up(key, 1, kWave);
+      int hs = (lane == 0 || prev != key) ? lane : 0;  // run head index
 #pragma unroll
-  for (int j = 0; j < kPer; ++j)
-    if (act[j]) {
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(hs, o, kWave);
+        if (lane >= o) hs = max(hs, t);
+      }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int pos = atomicAdd(&cnt[idx[j][k] >> sl], 1);
-        keys[rec + pos] = (uint16_t)(idx[j][k] & emask);
-        vals[rec + pos] = make_float2(val[j][k] * g[j].x, val[j][k] * g[j].y);
-      }
-    }
-}
-
-__global__ void __launch_bounds__(kAccBlock) accumulate_kernel(const int32_t *__restrict__ offs,
-                                                              const uint16_t *__restrict__ keys,
-                                                              const float2 *__restrict__ vals,
-                                                              const int4 *__restrict__ items,
-                                                              const int32_t *__restrict__ n_items, int64_t chunks,
-                                                              int nsl, int sl, int log2T, float *__restrict__ gtable) {
-  __shared__ float2 acc[1 << kSliceLog2];
-  __shared__ int sp[kAccBlock];
-  __shared__ int64_t sb[kAccBlock];
-  __shared__ int red[kAccBlock / kWave];
-  const int tid = threadIdx.x;
-  const int E = 1 << sl;
-  const int64_t n = *n_items;
-  for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
-    const int4 info = items[it];
-    const int level = info.x, s = info.y, G = info.w;
-    int64_t c0, c1;
-    group_chunks(info.z, G, chunks, &c0, &c1);
-    for (int e = tid; e < E; e += kAccBlock) acc[e] = make_float2(0.0f, 0.0f);
-    __syncthreads();
-    for (int64_t cb = c0; cb < c1; cb += kAccBlock) {
-      const int nb = (int)((c1 - cb) < kAccBlock ? (c1 - cb) : kAccBlock);
-      int len = 0;
-      int64_t beg = 0;
-      if (tid < nb) {
-        const int64_t rowi = (int64_t)level * chunks + cb + tid;
-        const int32_t *row = offs + rowi * (nsl + 1);
-        const int b = row[s];
-        len = row[s + 1] - b;
-        beg = rowi * (8 * kBinChunk) + b;
-      }
-      int m;
-      const int ex = block_excl_scan<kAccBlock / kWave>(len, red, &m);
-      sp[tid] = ex;
-      sb[tid] = beg;
-      __syncthreads();
-      for (int r = tid; r < m; r += kAccBlock) {
-        const int64_t ri = batch_record(r, nb, sp, sb);
-        const int key = keys[ri];
-        const float2 v = vals[ri];
-        atomicAdd(&acc[key].x, v.x);
-        atomicAdd(&acc[key].y, v.y);
-      }
-      __syncthreads();
-    }
-    float2 *gl = reinterpret_cast<float2 *>(gtable) + ((int64_t)level << log2T) + ((int64_t)s << sl);
-    for (int e = tid; e < E; e += kAccBlock) {
-      const float2 a = acc[e];
-      if (a.x != 0.0f || a.y != 0.0f) {
-        if (G == 1) {
-          const float2 o = gl[e];
-          gl[e] = make_float2(o.x + a.x, o.y + a.y);
-        } else {
-          atomicAdd(&gl[e].x, a.x);
-          atomicAdd(&gl[e].y, a.y);
+      for (int o = 1; o < kWave; o <<= 1) {
+        const float t0 = __shfl_up(v0, o, kWave), t1 = __shfl_up(v1, o, kWave);
+        if (lane - o >= hs) {
+          v0 += t0;
+          v1 += t1;
         }
       }
+      const int next = __shfl_down(key, 1, kWave);
+      if ((lane == kWave - 1 || next != key) && key >= 0) {
+        atomicAdd(gl + 2 * key, v0);
+        atomicAdd(gl + 2 * key + 1, v1);
+      }
     }
-    __syncthreads();
   }
 }
 
@@ -486,10 +307,10 @@ int32_t make_box(const float *aabb, Box *b) {
 
 }  // namespace
 
-extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, int64_t ld, const void *table,
-                                         int32_t table_dtype, int32_t L, int32_t F, int32_t log2T, double base_res,
-                                         double growth, const float *aabb, void *feat, int32_t feat_dtype,
-                                         ia355_stream_t stream) {
+extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, const int64_t *S_dev,
+                                         int64_t ld, const void *table, int32_t table_dtype, int32_t L, int32_t F,
+                                         int32_t log2T, double base_res, double growth, const float *aabb, void *feat,
+                                         int32_t feat_dtype, ia355_stream_t stream) {
   if (S < 0 || ld < S || L <= 0 || L > kMaxLevels || F != 2 || log2T < 1 || log2T > 30) return IA355_ERR_INVALID_ARG;
   if (!table || (S > 0 && (!xc || !feat))) return IA355_ERR_INVALID_ARG;
   if (table_dtype != IA355_F32 && table_dtype != IA355_F16) return IA355_ERR_INVALID_ARG;
@@ -499,36 +320,34 @@ extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, i
   if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
   if (S == 0) return IA355_OK;
   const int per_xcd = (L + kXcd - 1) / kXcd;
-  const int64_t chunks = ceil_div(S, kFwdBlock);
-  const int64_t blocks = chunks * per_xcd * kXcd;
+  // chunk slots per (XCD, level slot); with a device count at most 256 per
+  // level (8 per CU), the blocks loop over the rest
+  int64_t nslot = ceil_div(S, kFwdBlock);
+  if (S_dev && nslot > 256) nslot = 256;
+  const int64_t blocks = nslot * per_xcd * kXcd;
   if (blocks > 0x7fffffffLL) return IA355_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
   const unsigned g = (unsigned)blocks;
   if (table_dtype == IA355_F32 && feat_dtype == IA355_F32)
-    encode_kernel<float, float><<<g, kFwdBlock, 0, s>>>(xc, bone, S, ld, (const float *)table, L, log2T, lv, box,
-                                                        (float *)feat, per_xcd);
+    encode_kernel<float, float><<<g, kFwdBlock, 0, s>>>(xc, bone, S, S_dev, ld, (const float *)table, L, log2T, lv,
+                                                        box, (float *)feat, per_xcd);
   else if (table_dtype == IA355_F32)
-    encode_kernel<float, __hip_bfloat16><<<g, kFwdBlock, 0, s>>>(xc, bone, S, ld, (const float *)table, L, log2T, lv,
-                                                                 box, (__hip_bfloat16 *)feat, per_xcd);
+    encode_kernel<float, __hip_bfloat16><<<g, kFwdBlock, 0, s>>>(xc, bone, S, S_dev, ld, (const float *)table, L,
+                                                                 log2T, lv, box, (__hip_bfloat16 *)feat, per_xcd);
   else if (feat_dtype == IA355_F32)
-    encode_kernel<__half, float><<<g, kFwdBlock, 0, s>>>(xc, bone, S, ld, (const __half *)table, L, log2T, lv, box,
-                                                         (float *)feat, per_xcd);
+    encode_kernel<__half, float><<<g, kFwdBlock, 0, s>>>(xc, bone, S, S_dev, ld, (const __half *)table, L, log2T, lv,
+                                                         box, (float *)feat, per_xcd);
   else
-    encode_kernel<__half, __hip_bfloat16><<<g, kFwdBlock, 0, s>>>(xc, bone, S, ld, (const __half *)table, L, log2T,
-                                                                  lv, box, (__hip_bfloat16 *)feat, per_xcd);
+    encode_kernel<__half, __hip_bfloat16><<<g, kFwdBlock, 0, s>>>(xc, bone, S, S_dev, ld, (const __half *)table, L,
+                                                                  log2T, lv, box, (__hip_bfloat16 *)feat, per_xcd);
   return launch_status();
 }
 
-extern "C" size_t ia355_hashgrid_bwd_workspace_size(int64_t S, int32_t L, int32_t log2T) {
-  BinLayout b;
-  return bin_layout(S, L, log2T, &b) ? b.bytes : 0;
-}
-
 extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone, int64_t S,
-                                             int64_t ld, const void *table, int32_t table_dtype, int32_t L, int32_t F,
-                                             int32_t log2T, double base_res, double growth, const float *aabb,
-                                             float *grad_table, float *grad_xc, uint32_t flags, void *ws,
-                                             size_t ws_bytes, ia355_stream_t stream) {
+                                             const int64_t *S_dev, int64_t ld, const void *table, int32_t table_dtype,
+                                             int32_t L, int32_t F, int32_t log2T, double base_res, double growth,
+                                             const float *aabb, float *grad_table, float *grad_xc, uint32_t flags,
+                                             ia355_stream_t stream) {
   if (S < 0 || ld < S || L <= 0 || L > 16 || F != 2 || log2T < 1 || log2T > 30) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_feat || !xc)) return IA355_ERR_INVALID_ARG;
   if (grad_xc && !table) return IA355_ERR_INVALID_ARG;
@@ -538,56 +357,33 @@ extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float
   Box box;
   if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
+  const bool dev = S_dev != nullptr;
   const int overwrite = (flags & IA355_OVERWRITE) != 0;
   if (grad_table && overwrite) {
     const int32_t st = ia355_zero(grad_table, sizeof(float) * 2 * (size_t)L * ((size_t)1 << log2T), stream);
     if (st != IA355_OK) return st;
   }
-  BinLayout bl;
-  const bool binned = ws && grad_table && S > 0 && bin_layout(S, L, log2T, &bl);
-  if (binned && ws_bytes < bl.bytes) return IA355_ERR_WORKSPACE;
-  if (binned) {
-    char *w = static_cast<char *>(ws);
-    int32_t *offs = reinterpret_cast<int32_t *>(w + bl.offs);
-    uint16_t *keys = reinterpret_cast<uint16_t *>(w + bl.keys);
-    float2 *vals = reinterpret_cast<float2 *>(w + bl.vals);
-    int32_t *tot = reinterpret_cast<int32_t *>(w + bl.tot);
-    int4 *items = reinterpret_cast<int4 *>(w + bl.items);
-    int32_t *n_items = reinterpret_cast<int32_t *>(w + bl.nitems);
-    const int64_t nbin = (int64_t)L * bl.chunks;
-    if (nbin > 0x7fffffffLL) return IA355_ERR_INVALID_ARG;
-    bin_kernel<<<(unsigned)nbin, kBinBlock, 0, s>>>(grad_feat, xc, bone, S, ld, bl.chunks, log2T, bl.sl, bl.nsl, lv,
-                                                    box, offs, keys, vals);
-    slice_total_kernel<<<(unsigned)ceil_div((int64_t)L * bl.nsl, 256), 256, 0, s>>>(offs, L, bl.chunks, bl.nsl, tot);
-    plan_kernel<<<1, kPlanBlock, 0, s>>>(tot, L, bl.chunks, bl.nsl, kRecPerGroup, items, n_items);
-    const int64_t g = bl.max_items < kAccMaxGrid ? bl.max_items : kAccMaxGrid;
-    accumulate_kernel<<<(unsigned)g, kAccBlock, 0, s>>>(offs, keys, vals, items, n_items, bl.chunks, bl.nsl, bl.sl,
-                                                        log2T, grad_table);
-  } else if (grad_table && S > 0) {
+  if (grad_table && S > 0) {
     // Run aggregation pays while a cell spans several ray steps (coarse
     // dense levels, which come first as the resolution grows with the level);
     // finer levels use the 16-lanes-per-item mapping.
     int ndense = 0;
     while (ndense < L && lv.dense[ndense] && lv.res[ndense] <= kAggMaxRes) ++ndense;
-    if (ndense > 0) {
-      const int64_t chunks = ceil_div(S, kDgBlock);
-      table_grad_dense_kernel<<<(unsigned)(chunks * ndense), kDgBlock, 0, s>>>(grad_feat, xc, bone, S, ld, chunks,
-                                                                               log2T, lv, box, grad_table);
-    }
+    if (ndense > 0)
+      table_grad_dense_kernel<<<stride_grid(ceil_div(S, kDgBlock) * ndense, dev), kDgBlock, 0, s>>>(
+          grad_feat, xc, bone, S, S_dev, ld, ndense, log2T, lv, box, grad_table);
     if (ndense < L)
-      table_grad_kernel<<<(unsigned)ceil_div((int64_t)(L - ndense) * S * 16, kTgBlock), kTgBlock, 0, s>>>(
-          grad_feat, xc, bone, S, ld, ndense, L, log2T, lv, box, grad_table);
+      table_grad_kernel<<<stride_grid(ceil_div((int64_t)(L - ndense) * S * 16, kTgBlock), dev, 8192), kTgBlock, 0,
+                          s>>>(grad_feat, xc, bone, S, S_dev, ld, ndense, L, log2T, lv, box, grad_table);
   }
   if (grad_xc && S > 0) {
-    const int64_t blocks = ceil_div(S * 16, kBwdBlock);
+    const unsigned blocks = stride_grid(ceil_div(S * 16, kBwdBlock), dev, 4096);
     if (table_dtype == IA355_F32)
-      encode_bwd_kernel<float><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, ld,
-                                                                      (const float *)table, L, log2T, lv, box, nullptr,
-                                                                      grad_xc);
+      encode_bwd_kernel<float><<<blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, S_dev, ld, (const float *)table, L,
+                                                            log2T, lv, box, grad_xc);
     else
-      encode_bwd_kernel<__half><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, ld,
-                                                                       (const __half *)table, L, log2T, lv, box,
-                                                                       nullptr, grad_xc);
+      encode_bwd_kernel<__half><<<blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, S_dev, ld, (const __half *)table,
+                                                             L, log2T, lv, box, grad_xc);
   }
   return launch_status();
 }

@@ -52,11 +52,11 @@ __device__ __forceinline__ void head(const float o[4], float *sig, float c[3]) {
 
 // --------------------------------------------------------------- FP32 fwd
 // Loads the 8 features of lane group g for sample s (levels 4g..4g+3).
-__device__ __forceinline__ void load_x(const float *feat, int64_t S, int64_t s, int g, bool ok, float X[8]) {
+__device__ __forceinline__ void load_x(const float *feat, int64_t fst, int64_t s, int g, bool ok, float X[8]) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     float2 v = make_float2(0.0f, 0.0f);
-    if (ok) v = reinterpret_cast<const float2 *>(feat)[(int64_t)(4 * g + j) * S + s];
+    if (ok) v = reinterpret_cast<const float2 *>(feat)[(int64_t)(4 * g + j) * fst + s];
     X[2 * j] = v.x;
     X[2 * j + 1] = v.y;
   }
@@ -122,19 +122,22 @@ __device__ __forceinline__ void fwd32(const Frag32 &f, const float X[8], f32x4 z
 constexpr int kFwdBlock = 256;
 
 __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_f32(const float *__restrict__ feat,
-                                                         const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                         const int16_t *__restrict__ bone, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                          const float *__restrict__ P, float *__restrict__ sigma,
                                                          float *__restrict__ rgb) {
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  Frag32 f;
-  load_frag32(P, r, g, f);
+  S = count_of(S, S_dev);
   const int64_t ntile = ceil_div(S, 16);
   const int64_t wstride = (int64_t)gridDim.x * (kFwdBlock / 64);
+  // a wave without a tile skips the weight-fragment loads (no barriers here)
+  if ((int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6) >= ntile) return;
+  Frag32 f;
+  load_frag32(P, r, g, f);
   for (int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6); tile < ntile; tile += wstride) {
     const int64_t s = tile * 16 + r;
     const bool ok = s < S;
     float X[8];
-    load_x(feat, S, s, g, ok, X);
+    load_x(feat, ld, s, g, ok, X);
     f32x4 z1[4], z2[4], o;
     fwd32(f, X, z1, z2, o);
     if (g == 0 && ok) {
@@ -152,12 +155,12 @@ __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_f32(const float *__restrict
 }
 
 // --------------------------------------------------------------- BF16 fwd
-__device__ __forceinline__ bf16x8 load_x_bf16(const __hip_bfloat16 *feat, int64_t S, int64_t s, int g, bool ok) {
+__device__ __forceinline__ bf16x8 load_x_bf16(const __hip_bfloat16 *feat, int64_t fst, int64_t s, int g, bool ok) {
   bf16x8 x;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     uint32_t v = 0;
-    if (ok) v = reinterpret_cast<const uint32_t *>(feat)[(int64_t)(4 * g + j) * S + s];
+    if (ok) v = reinterpret_cast<const uint32_t *>(feat)[(int64_t)(4 * g + j) * fst + s];
     x[2 * j] = __builtin_bit_cast(__bf16, (uint16_t)(v & 0xffffu));
     x[2 * j + 1] = __builtin_bit_cast(__bf16, (uint16_t)(v >> 16));
   }
@@ -224,18 +227,20 @@ __device__ __forceinline__ void fwd_bf(const FragBf &f, const bf16x8 &X, f32x4 z
 }
 
 __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_bf16(const __hip_bfloat16 *__restrict__ feat,
-                                                          const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                          const int16_t *__restrict__ bone, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                           const float *__restrict__ P, float *__restrict__ sigma,
                                                           float *__restrict__ rgb) {
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  FragBf f;
-  load_frag_bf(P, r, g, f);
+  S = count_of(S, S_dev);
   const int64_t ntile = ceil_div(S, 16);
   const int64_t wstride = (int64_t)gridDim.x * (kFwdBlock / 64);
+  if ((int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6) >= ntile) return;
+  FragBf f;
+  load_frag_bf(P, r, g, f);
   for (int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6); tile < ntile; tile += wstride) {
     const int64_t s = tile * 16 + r;
     const bool ok = s < S;
-    const bf16x8 X = load_x_bf16(feat, S, s, g, ok);
+    const bf16x8 X = load_x_bf16(feat, ld, s, g, ok);
     f32x4 z1[4], z2[4], o;
     fwd_bf(f, X, z1, z2, o);
     if (g == 0 && ok) {
@@ -276,7 +281,7 @@ static_assert(LDS_FLOATS * 4 <= 65536, "one workgroup's LDS");
 
 __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_f32(const float *__restrict__ gsig, const float *__restrict__ grgb,
                                                          const float *__restrict__ feat,
-                                                         const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                         const int16_t *__restrict__ bone, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                          const float *__restrict__ P, float *__restrict__ gfeat,
                                                          float *__restrict__ partial) {
   extern __shared__ float lds[];
@@ -317,13 +322,14 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_f32(const float *__restrict
 #pragma unroll
     for (int b = 0; b < 2; ++b) aW1[a][b] = f32x4{0, 0, 0, 0};
   }
+  S = count_of(S, S_dev);
   const int64_t ntile = ceil_div(S, 16);
   const int64_t wstride = (int64_t)gridDim.x * kBwdWaves;
   for (int64_t tile = (int64_t)blockIdx.x * kBwdWaves + wid; tile < ntile; tile += wstride) {
     const int64_t s = tile * 16 + r;
     const bool ok = s < S;
     float X[8];
-    load_x(feat, S, s, g, ok, X);
+    load_x(feat, ld, s, g, ok, X);
     f32x4 z1[4], z2[4], o;
     fwd32(f, X, z1, z2, o);
     // output-head gradient (lanes g == 0 hold sample r's four outputs)
@@ -425,8 +431,8 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_f32(const float *__restrict
           for (int i = 0; i < 4; ++i) acc = mfma4(ft[FT1 + (mt * 16 + 4 * t + i) * 64 + lane], d1[t][i], acc);
         if (ok) {
           float2 *gf = reinterpret_cast<float2 *>(gfeat);
-          gf[(int64_t)(8 * mt + 2 * g) * S + s] = make_float2(acc[0], acc[1]);
-          gf[(int64_t)(8 * mt + 2 * g + 1) * S + s] = make_float2(acc[2], acc[3]);
+          gf[(int64_t)(8 * mt + 2 * g) * ld + s] = make_float2(acc[0], acc[1]);
+          gf[(int64_t)(8 * mt + 2 * g + 1) * ld + s] = make_float2(acc[2], acc[3]);
         }
       }
     }
@@ -551,7 +557,7 @@ __device__ __forceinline__ bf16x8 lds_row8(const __bf16 *scr, int row, int col) 
 __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_bf16(const float *__restrict__ gsig,
                                                           const float *__restrict__ grgb,
                                                           const __hip_bfloat16 *__restrict__ feat,
-                                                          const int16_t *__restrict__ bone, int64_t S, int64_t ld,
+                                                          const int16_t *__restrict__ bone, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                           const float *__restrict__ P, float *__restrict__ gfeat,
                                                           float *__restrict__ partial) {
   extern __shared__ __attribute__((aligned(16))) unsigned char ldsb[];
@@ -576,6 +582,7 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_bf16(const float *__restric
 #pragma unroll
     for (int b = 0; b < 2; ++b) aW1[a][b] = f32x4{0, 0, 0, 0};
   }
+  S = count_of(S, S_dev);
   const int64_t ntile = ceil_div(S, 32);
   const int64_t wstride = (int64_t)gridDim.x * kBwdWaves;
   for (int64_t tile = (int64_t)blockIdx.x * kBwdWaves + wid; tile < ntile; tile += wstride) {
@@ -584,7 +591,7 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_bf16(const float *__restric
       const int col = 16 * half + r;
       const int64_t s = tile * 32 + col;
       const bool ok = s < S;
-      const bf16x8 X = load_x_bf16(feat, S, s, g, ok);
+      const bf16x8 X = load_x_bf16(feat, ld, s, g, ok);
       f32x4 z1[4], z2[4], o;
       fwd_bf(f, X, z1, z2, o);
       float d3[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -635,8 +642,8 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_bf16(const float *__restric
           acc = mfma32(ft.w1t[mt][1], d1b, acc);
           if (ok) {
             float2 *gf = reinterpret_cast<float2 *>(gfeat);
-            gf[(int64_t)(8 * mt + 2 * g) * S + s] = make_float2(acc[0], acc[1]);
-            gf[(int64_t)(8 * mt + 2 * g + 1) * S + s] = make_float2(acc[2], acc[3]);
+            gf[(int64_t)(8 * mt + 2 * g) * ld + s] = make_float2(acc[0], acc[1]);
+            gf[(int64_t)(8 * mt + 2 * g + 1) * ld + s] = make_float2(acc[2], acc[3]);
           }
         }
       }
@@ -773,8 +780,9 @@ unsigned fwd_blocks(int64_t S) { return grid_for(ceil_div(S, 16) * 64, kFwdBlock
 
 }  // namespace
 
-extern "C" int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int16_t *bone, int64_t S, int64_t ld,
-                                 const float *params, int32_t dtype, float *sigma, float *rgb, ia355_stream_t stream) {
+extern "C" int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int16_t *bone, int64_t S,
+                                 const int64_t *S_dev, int64_t ld, const float *params, int32_t dtype, float *sigma,
+                                 float *rgb, ia355_stream_t stream) {
   if (S < 0 || ld < S || !params) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!feat || !sigma || !rgb)) return IA355_ERR_INVALID_ARG;
   if (dtype == IA355_F32 && feat_dtype != IA355_F32) return IA355_ERR_UNSUPPORTED;
@@ -783,9 +791,10 @@ extern "C" int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int
   if (S == 0) return IA355_OK;
   hipStream_t s = as_stream(stream);
   if (dtype == IA355_F32)
-    mlp_fwd_f32<<<fwd_blocks(S), kFwdBlock, 0, s>>>((const float *)feat, bone, S, ld, params, sigma, rgb);
+    mlp_fwd_f32<<<fwd_blocks(S), kFwdBlock, 0, s>>>((const float *)feat, bone, S, S_dev, ld, params, sigma, rgb);
   else
-    mlp_fwd_bf16<<<fwd_blocks(S), kFwdBlock, 0, s>>>((const __hip_bfloat16 *)feat, bone, S, ld, params, sigma, rgb);
+    mlp_fwd_bf16<<<fwd_blocks(S), kFwdBlock, 0, s>>>((const __hip_bfloat16 *)feat, bone, S, S_dev, ld, params, sigma,
+                                                     rgb);
   return launch_status();
 }
 
@@ -794,9 +803,9 @@ extern "C" size_t ia355_mlp_bwd_workspace_size(int64_t S) {
 }
 
 extern "C" int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb, const void *feat, int32_t feat_dtype,
-                                 const int16_t *bone, int64_t S, int64_t ld, const float *params, int32_t dtype,
-                                 float *grad_params, float *grad_feat, uint32_t flags, void *ws, size_t ws_bytes,
-                                 ia355_stream_t stream) {
+                                 const int16_t *bone, int64_t S, const int64_t *S_dev, int64_t ld,
+                                 const float *params, int32_t dtype, float *grad_params, float *grad_feat,
+                                 uint32_t flags, void *ws, size_t ws_bytes, ia355_stream_t stream) {
   if (S < 0 || ld < S || !params || !grad_params) return IA355_ERR_INVALID_ARG;
   if (flags & ~(uint32_t)IA355_OVERWRITE) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_sigma || !grad_rgb || !feat)) return IA355_ERR_INVALID_ARG;
@@ -808,10 +817,10 @@ extern "C" int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb,
   const int nb = bwd_blocks(S);
   if (dtype == IA355_F32)
     mlp_bwd_f32<<<nb, kBwdBlock, LDS_FLOATS * sizeof(float), s>>>(grad_sigma, grad_rgb, (const float *)feat, bone, S,
-                                                                  ld, params, grad_feat, (float *)ws);
+                                                                  S_dev, ld, params, grad_feat, (float *)ws);
   else
-    mlp_bwd_bf16<<<nb, kBwdBlock, LDS_BF_BYTES, s>>>(grad_sigma, grad_rgb, (const __hip_bfloat16 *)feat, bone, S, ld,
-                                                     params, grad_feat, (float *)ws);
+    mlp_bwd_bf16<<<nb, kBwdBlock, LDS_BF_BYTES, s>>>(grad_sigma, grad_rgb, (const __hip_bfloat16 *)feat, bone, S,
+                                                     S_dev, ld, params, grad_feat, (float *)ws);
   reduce_partials<<<(unsigned)ceil_div(NPARAM, kRedP), kRedP * kRedG, 0, s>>>((const float *)ws, nb, grad_params,
                                                                                      (flags & IA355_OVERWRITE) != 0);
   return launch_status();

@@ -27,7 +27,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ float relu(float z) { return z < 0.0f ? 0.0f : z; }
 
 template <bool BF16>
-__global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restrict__ xp_soa, int64_t S, int64_t ld,
+__global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restrict__ xp_soa, int64_t S,
+                                                          const int64_t *__restrict__ S_dev, int64_t ld,
                                                           const float *__restrict__ pose, const float *__restrict__ P,
                                                           const float *__restrict__ B, int nb,
                                                           int16_t *__restrict__ bone_out, float *__restrict__ x0_soa) {
@@ -88,6 +89,7 @@ __global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restric
     }
   }
 
+  S = count_of(S, S_dev);
   const int64_t ntile = ceil_div(S, 16);
   const int64_t wstride = (int64_t)gridDim.x * (kBlock / 64);
   for (int64_t tile = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); tile < ntile; tile += wstride) {
@@ -196,7 +198,8 @@ __global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restric
 
 }  // namespace
 
-extern "C" int32_t ia355_rootinit_fwd(const float *xp, int64_t S, int64_t ld, const float *pose, const float *params,
+extern "C" int32_t ia355_rootinit_fwd(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld, const float *pose,
+                                      const float *params,
                                       int32_t hidden, const float *B, int32_t nb, int32_t dtype, int16_t *init_bone,
                                       float *x0, ia355_stream_t stream) {
   if (S < 0 || ld < S || nb <= 0 || !pose || !params || !B) return IA355_ERR_INVALID_ARG;
@@ -207,8 +210,8 @@ extern "C" int32_t ia355_rootinit_fwd(const float *xp, int64_t S, int64_t ld, co
   const unsigned grid = grid_for(ceil_div(S, 16) * 64, kBlock, 256 * 8);
   hipStream_t s = as_stream(stream);
   if (dtype == IA355_F32)
-    rootinit_kernel<false><<<grid, kBlock, 0, s>>>(xp, S, ld, pose, params, B, nb, init_bone, x0);
+    rootinit_kernel<false><<<grid, kBlock, 0, s>>>(xp, S, S_dev, ld, pose, params, B, nb, init_bone, x0);
   else
-    rootinit_kernel<true><<<grid, kBlock, 0, s>>>(xp, S, ld, pose, params, B, nb, init_bone, x0);
+    rootinit_kernel<true><<<grid, kBlock, 0, s>>>(xp, S, S_dev, ld, pose, params, B, nb, init_bone, x0);
   return launch_status();
 }

@@ -18,7 +18,9 @@ __global__ void __launch_bounds__(kBlock) render_fwd(const float *__restrict__ s
                                                      int32_t *__restrict__ n_used, float *__restrict__ T_final) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= R) return;
-  const int64_t b = ray_off[r], e = ray_off[r + 1];
+  // a march that overflowed the sample buffer (count > ld, reported by the
+  // march) leaves offsets past ld: those samples were never written
+  const int64_t b = min(ray_off[r], ld), e = min(ray_off[r + 1], ld);
   const float dt = ray_dt[r];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, A = 0.0f;
   int used = 0;
@@ -50,7 +52,7 @@ __global__ void __launch_bounds__(kBlock) render_bwd(const float *__restrict__ g
                                                      int64_t R, float *__restrict__ gsig, float *__restrict__ grgb) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= R) return;
-  const int64_t b = ray_off[r], e = ray_off[r + 1], u = b + n_used[r];
+  const int64_t b = min(ray_off[r], ld), e = min(ray_off[r + 1], ld), u = min(b + n_used[r], e);
   const float dt = ray_dt[r];
   const float g0 = gC[3 * r], g1 = gC[3 * r + 1], g2 = gC[3 * r + 2];
   const float ga = gA ? gA[r] : 0.0f;

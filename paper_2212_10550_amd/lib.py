@@ -38,22 +38,21 @@ _SIGS = {
     "occgrid_march": (_i32, [_vp, _vp, _i64, _vp, _i32, _fp, _f, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
                              _vp, _vp, _sz, _vp]),
     "deform_workspace_size": (_sz, [_i32, _i32, _i32]),
-    "snarf_deform": (_i32, [_vp, _i64, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _vp, _vp,
+    "snarf_deform": (_i32, [_vp, _i64, _vp, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _vp, _vp,
                             _vp, _vp, _sz, _vp]),
     "deform_bwd_workspace_size": (_sz, [_i64, _i32, _i32, _i32, _i32]),
-    "snarf_deform_bwd": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _vp, _vp, _vp,
+    "snarf_deform_bwd": (_i32, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _vp, _vp, _vp,
                                 ctypes.c_uint32, _vp, _sz, _vp]),
-    "rootinit_fwd": (_i32, [_vp, _i64, _i64, _vp, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp]),
+    "rootinit_fwd": (_i32, [_vp, _i64, _vp, _i64, _vp, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp]),
     "deform_guided_workspace_size": (_sz, [_i64, _i32, _i32, _i32]),
-    "snarf_deform_guided": (_i32, [_vp, _i64, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f,
+    "snarf_deform_guided": (_i32, [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f,
                                    _f, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
-    "hashgrid_encode": (_i32, [_vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _i32, _vp]),
-    "hashgrid_bwd_workspace_size": (_sz, [_i64, _i32, _i32]),
-    "hashgrid_encode_bwd": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _vp,
-                                   ctypes.c_uint32, _vp, _sz, _vp]),
-    "mlp_fwd": (_i32, [_vp, _i32, _vp, _i64, _i64, _vp, _i32, _vp, _vp, _vp]),
+    "hashgrid_encode": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _i32, _vp]),
+    "hashgrid_encode_bwd": (_i32, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _vp,
+                                   ctypes.c_uint32, _vp]),
+    "mlp_fwd": (_i32, [_vp, _i32, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _vp, _vp]),
     "mlp_bwd_workspace_size": (_sz, [_i64]),
-    "mlp_bwd": (_i32, [_vp, _vp, _vp, _i32, _vp, _i64, _i64, _vp, _i32, _vp, _vp, ctypes.c_uint32, _vp, _sz, _vp]),
+    "mlp_bwd": (_i32, [_vp, _vp, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _vp, ctypes.c_uint32, _vp, _sz, _vp]),
     "volrender_fwd": (_i32, [_vp, _vp, _i64, _vp, _vp, _i64, _f, _vp, _vp, _vp, _vp, _vp]),
     "volrender_bwd": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "l2_loss": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
@@ -139,10 +138,12 @@ def deform_workspace_size(Dx, Dy, Dz):
     return lib().ia355_deform_workspace_size(Dx, Dy, Dz)
 
 
-def snarf_deform(xp, S, ld, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, ws):
+def snarf_deform(xp, S, ld, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, ws,
+                 S_dev=None):
     Dz, Dy, Dx, nb = W.shape
     _check(lib().ia355_snarf_deform(
-        _p(xp, torch.float32, "xp"), S, ld, _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"), Dx, Dy, Dz,
+        _p(xp, torch.float32, "xp"), S, _p(S_dev, torch.int64, "S_dev"), ld, _p(B, torch.float32, "B"), nb,
+        _p(W, torch.float32, "W"), Dx, Dy, Dz,
         _box(skin_aabb), _box(hash_aabb), max_iter, tol_stop, tol_valid, _p(xc, torch.float32, "xc"),
         _p(bone, torch.int16, "bone"), _p(resid, torch.float32, "resid"), _p(steps, torch.int16, "steps"),
         _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "snarf_deform")
@@ -152,20 +153,21 @@ def deform_bwd_workspace_size(S, Dx, Dy, Dz, nb):
     return lib().ia355_deform_bwd_workspace_size(S, Dx, Dy, Dz, nb)
 
 
-def snarf_deform_bwd(grad_xc, xc, bone, S, ld, B, W, skin_aabb, grad_xp, grad_B, grad_W, ws, flags=0):
+def snarf_deform_bwd(grad_xc, xc, bone, S, ld, B, W, skin_aabb, grad_xp, grad_B, grad_W, ws, flags=0, S_dev=None):
     Dz, Dy, Dx, nb = W.shape
     _check(lib().ia355_snarf_deform_bwd(
-        _p(grad_xc, torch.float32, "grad_xc"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S, ld,
-        _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"), Dx, Dy, Dz, _box(skin_aabb),
+        _p(grad_xc, torch.float32, "grad_xc"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S,
+        _p(S_dev, torch.int64, "S_dev"), ld, _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"), Dx, Dy, Dz, _box(skin_aabb),
         _p(grad_xp, torch.float32, "grad_xp"), _p(grad_B, torch.float32, "grad_B"),
         _p(grad_W, torch.float32, "grad_W"), flags, _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()),
         "snarf_deform_bwd")
 
 
-def rootinit_fwd(xp, S, ld, pose, params, B, dtype, init_bone, x0, hidden=64):
+def rootinit_fwd(xp, S, ld, pose, params, B, dtype, init_bone, x0, hidden=64, S_dev=None):
     nb = B.shape[0]
     _check(lib().ia355_rootinit_fwd(
-        _p(xp, torch.float32, "xp"), S, ld, _p(pose, torch.float32, "pose"), _p(params, torch.float32, "params"),
+        _p(xp, torch.float32, "xp"), S, _p(S_dev, torch.int64, "S_dev"), ld, _p(pose, torch.float32, "pose"),
+        _p(params, torch.float32, "params"),
         hidden, _p(B, torch.float32, "B"), nb, dtype, _p(init_bone, torch.int16, "init_bone"),
         _p(x0, torch.float32, "x0"), _stream()), "rootinit_fwd")
 
@@ -175,44 +177,39 @@ def deform_guided_workspace_size(S, Dx, Dy, Dz):
 
 
 def snarf_deform_guided(xp, S, ld, x0, init_bone, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, xc,
-                        bone, resid, steps, n_fallback, ws):
+                        bone, resid, steps, n_fallback, ws, S_dev=None):
     Dz, Dy, Dx, nb = W.shape
     _check(lib().ia355_snarf_deform_guided(
-        _p(xp, torch.float32, "xp"), S, ld, _p(x0, torch.float32, "x0"), _p(init_bone, torch.int16, "init_bone"),
+        _p(xp, torch.float32, "xp"), S, _p(S_dev, torch.int64, "S_dev"), ld, _p(x0, torch.float32, "x0"),
+        _p(init_bone, torch.int16, "init_bone"),
         _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"), Dx, Dy, Dz, _box(skin_aabb), _box(hash_aabb),
         max_iter, tol_stop, tol_valid, _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"),
         _p(resid, torch.float32, "resid"), _p(steps, torch.int16, "steps"), _p(n_fallback, torch.int32, "n_fallback"),
         _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "snarf_deform_guided")
 
 
-def hashgrid_encode(xc, bone, S, ld, table, base_res, growth, aabb, feat):
+def hashgrid_encode(xc, bone, S, ld, table, base_res, growth, aabb, feat, S_dev=None):
     L, T, F = table.shape
     _check(lib().ia355_hashgrid_encode(
-        _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S, ld, _p(table, name="table"), _DT[table.dtype],
+        _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S, _p(S_dev, torch.int64, "S_dev"), ld,
+        _p(table, name="table"), _DT[table.dtype],
         L, F, T.bit_length() - 1, base_res, growth, _box(aabb), _p(feat, name="feat"), _DT[feat.dtype], _stream()),
         "hashgrid_encode")
 
 
-def hashgrid_bwd_workspace_size(S, L, log2T):
-    return lib().ia355_hashgrid_bwd_workspace_size(S, L, log2T)
-
-
 def hashgrid_encode_bwd(grad_feat, xc, bone, S, ld, table, base_res, growth, aabb, grad_table, grad_xc, flags=0,
-                        ws=None):
-    """ws: uint8 device tensor of hashgrid_bwd_workspace_size bytes (binned
-    table gradient), or None (global atomics)."""
+                        S_dev=None):
     L, T, F = table.shape
     _check(lib().ia355_hashgrid_encode_bwd(
-        _p(grad_feat, torch.float32, "grad_feat"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S, ld,
-        _p(table, name="table"), _DT[table.dtype], L, F, T.bit_length() - 1, base_res, growth, _box(aabb),
-        _p(grad_table, torch.float32, "grad_table"), _p(grad_xc, torch.float32, "grad_xc"), flags,
-        _p(ws, torch.uint8, "ws"), 0 if ws is None else ws.numel(), _stream()),
+        _p(grad_feat, torch.float32, "grad_feat"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S,
+        _p(S_dev, torch.int64, "S_dev"), ld, _p(table, name="table"), _DT[table.dtype], L, F, T.bit_length() - 1, base_res, growth, _box(aabb),
+        _p(grad_table, torch.float32, "grad_table"), _p(grad_xc, torch.float32, "grad_xc"), flags, _stream()),
         "hashgrid_encode_bwd")
 
 
-def mlp_fwd(feat, bone, S, ld, params, dtype, sigma, rgb):
+def mlp_fwd(feat, bone, S, ld, params, dtype, sigma, rgb, S_dev=None):
     _check(lib().ia355_mlp_fwd(
-        _p(feat, name="feat"), _DT[feat.dtype], _p(bone, torch.int16, "bone"), S, ld,
+        _p(feat, name="feat"), _DT[feat.dtype], _p(bone, torch.int16, "bone"), S, _p(S_dev, torch.int64, "S_dev"), ld,
         _p(params, torch.float32, "params"), dtype, _p(sigma, torch.float32, "sigma"), _p(rgb, torch.float32, "rgb"),
         _stream()), "mlp_fwd")
 
@@ -221,10 +218,11 @@ def mlp_bwd_workspace_size(S):
     return lib().ia355_mlp_bwd_workspace_size(S)
 
 
-def mlp_bwd(grad_sigma, grad_rgb, feat, bone, S, ld, params, dtype, grad_params, grad_feat, ws, flags=0):
+def mlp_bwd(grad_sigma, grad_rgb, feat, bone, S, ld, params, dtype, grad_params, grad_feat, ws, flags=0, S_dev=None):
     _check(lib().ia355_mlp_bwd(
         _p(grad_sigma, torch.float32, "grad_sigma"), _p(grad_rgb, torch.float32, "grad_rgb"), _p(feat, name="feat"),
-        _DT[feat.dtype], _p(bone, torch.int16, "bone"), S, ld, _p(params, torch.float32, "params"), dtype,
+        _DT[feat.dtype], _p(bone, torch.int16, "bone"), S, _p(S_dev, torch.int64, "S_dev"), ld,
+        _p(params, torch.float32, "params"), dtype,
         _p(grad_params, torch.float32, "grad_params"), _p(grad_feat, torch.float32, "grad_feat"), flags,
         _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "mlp_bwd")
 

@@ -7,6 +7,11 @@ calls on preallocated HBM buffers.
 
 PyTorch only provides the device allocations and the stream; no torch
 operator runs inside ``forward`` / ``backward`` / ``train_step``.
+
+With ``device_count=True`` no stage waits for the host: the march leaves
+the sample count in device memory and every later call reads it there (the
+capacity sizes the launches).  A whole step is then enqueued at once and
+can be captured in a HIP graph (``capture_train_step``).
 """
 from __future__ import annotations
 
@@ -50,8 +55,10 @@ class StageTimer:
 
 class Pipeline:
     def __init__(self, w, device="cuda", table_dtype=torch.float32, mlp_dtype=K.F32, cap=None,
-                 grad_W=True, grad_B=True, rootinit_params=None, rootinit_dtype=K.BF16):
+                 grad_W=True, grad_B=True, rootinit_params=None, rootinit_dtype=K.BF16, device_count=False):
         self.w = w
+        self.device_count = device_count
+        self.graph, self.graph_kind = None, None
         self.dev = torch.device(device)
         dev = self.dev
         t = lambda a, dt=None: torch.as_tensor(np.ascontiguousarray(a), device=dev, dtype=dt)
@@ -116,7 +123,6 @@ class Pipeline:
         self.grad_B = e(*self.B.shape) if grad_B else None
         self.grad_W = e(*self.W.shape) if grad_W else None
         self.ws_ift = e(K.deform_bwd_workspace_size(cap, Dx, Dy, Dz, nb), dt=torch.uint8)
-        self.ws_hash = None  # binned table-gradient scratch, sized on first use for the step's S
         self.S = None
         self.timer = None  # optional StageTimer: HIP events around each stage
         # learned root initialiser (guided solve with multi-init fallback)
@@ -138,69 +144,159 @@ class Pipeline:
                         self.n_samples, self.ws_march)
 
     def read_count(self):
+        """The sample count of the last march (synchronises)."""
         S = int(self.n_samples.item())
         if S > self.cap:
             raise RuntimeError(f"sample buffer too small: {S} > {self.cap}")
         self.S = S
         return S
 
-    def field(self, S):
+    def _counts(self):
+        """(S, S_dev) for the stage calls: the host count after a sync, or the
+        capacity and the device counter."""
+        if self.device_count:
+            return self.cap, self.n_samples
+        return self.read_count(), None
+
+    # stages: each reads the outputs of the previous ones and overwrites its
+    # own outputs, so it can be run (or replayed) on its own
+    def _deform(self, S, Sd):
         w = self.w
-        self._mark("deform")
         if self.guided is not None:
             self.guided.run(self.xs, S, self.cap, self.pose_t, self.B, self.W, self.xc, self.bone, self.resid,
-                            self.steps)
+                            self.steps, S_dev=Sd)
         else:
             K.snarf_deform(self.xs, S, self.cap, self.B, self.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop,
-                           w.tol_valid, self.xc, self.bone, self.resid, self.steps, self.ws_deform)
-        feat = self.feat[: w.L * S * 2]
-        self._mark("hash_fwd")
-        K.hashgrid_encode(self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth, w.hash_aabb, feat)
-        self._mark("mlp_fwd")
-        K.mlp_fwd(feat, self.bone, S, self.cap, self.params, self.mlp_dtype, self.sigma, self.rgb)
+                           w.tol_valid, self.xc, self.bone, self.resid, self.steps, self.ws_deform, S_dev=Sd)
 
-    def composite(self):
-        self._mark("render_fwd")
+    def _encode(self, S, Sd):
+        w = self.w
+        K.hashgrid_encode(self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth, w.hash_aabb, self.feat,
+                          S_dev=Sd)
+
+    def _mlp(self, S, Sd):
+        K.mlp_fwd(self.feat, self.bone, S, self.cap, self.params, self.mlp_dtype, self.sigma, self.rgb, S_dev=Sd)
+
+    def _render(self):
         K.volrender_fwd(self.sigma, self.rgb, self.cap, self.ray_off, self.ray_dt, self.R, self.w.T_thresh,
                         self.color, self.opacity, self.n_used, self.T_final)
-        self._mark(None)
 
-    def forward(self):
-        self._mark("march")
-        self.march()
-        self._mark(None)
-        S = self.read_count()
-        self.field(S)
-        self.composite()
-        return S
-
-    # ----------------------------------------------------------- backward
-    def backward(self, S):
-        w = self.w
-        self._mark("loss+render_bwd")
+    def _render_bwd(self):
         K.l2_loss(self.color, self.target, self.loss, self.grad_color)
         K.volrender_bwd(self.grad_color, None, self.sigma, self.rgb, self.cap, self.ray_off, self.ray_dt, self.n_used,
                         self.color, self.T_final, self.R, self.grad_sigma, self.grad_rgb)
-        self._mark("mlp_bwd")
-        feat = self.feat[: w.L * S * 2]
-        gfeat = self.grad_feat[: w.L * S * 2]
-        K.mlp_bwd(self.grad_sigma, self.grad_rgb, feat, self.bone, S, self.cap, self.params, self.mlp_dtype,
-                  self.grad_params, gfeat, self.ws_mlp, flags=K.OVERWRITE)
-        need = K.hashgrid_bwd_workspace_size(S, w.L, self.table.shape[1].bit_length() - 1)
-        if need and (self.ws_hash is None or self.ws_hash.numel() < need):
-            self.ws_hash = torch.empty(need + need // 4, dtype=torch.uint8, device=self.dev)
-        self._mark("hash_bwd")
-        K.hashgrid_encode_bwd(gfeat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth, w.hash_aabb,
-                              self.grad_table, self.grad_xc, flags=K.OVERWRITE, ws=self.ws_hash if need else None)
-        self._mark("deform_bwd")
+
+    def _mlp_bwd(self, S, Sd):
+        K.mlp_bwd(self.grad_sigma, self.grad_rgb, self.feat, self.bone, S, self.cap, self.params, self.mlp_dtype,
+                  self.grad_params, self.grad_feat, self.ws_mlp, flags=K.OVERWRITE, S_dev=Sd)
+
+    def _encode_bwd(self, S, Sd):
+        w = self.w
+        K.hashgrid_encode_bwd(self.grad_feat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth,
+                              w.hash_aabb, self.grad_table, self.grad_xc, flags=K.OVERWRITE, S_dev=Sd)
+
+    def _deform_bwd(self, S, Sd):
+        w = self.w
         K.snarf_deform_bwd(self.grad_xc, self.xc, self.bone, S, self.cap, self.B, self.W, w.skin_aabb, self.grad_xp,
-                           self.grad_B, self.grad_W, self.ws_ift, flags=K.OVERWRITE)
+                           self.grad_B, self.grad_W, self.ws_ift, flags=K.OVERWRITE, S_dev=Sd)
+
+    def stages(self, S, Sd, backward=True):
+        """The step as (name, call) pairs after the march."""
+        st = [("deform", lambda: self._deform(S, Sd)), ("hash_fwd", lambda: self._encode(S, Sd)),
+              ("mlp_fwd", lambda: self._mlp(S, Sd)), ("render_fwd", self._render)]
+        if backward:
+            st += [("loss+render_bwd", self._render_bwd), ("mlp_bwd", lambda: self._mlp_bwd(S, Sd)),
+                   ("hash_bwd", lambda: self._encode_bwd(S, Sd)), ("deform_bwd", lambda: self._deform_bwd(S, Sd))]
+        return st
+
+    def forward(self):
+        """One forward; returns the sample count (None with device counts:
+        read it later with read_count)."""
+        self._mark("march")
+        self.march()
+        self._mark(None)
+        S, Sd = self._counts()
+        for name, fn in self.stages(S, Sd, backward=False):
+            self._mark(name)
+            fn()
+        self._mark(None)
+        self._last = (S, Sd)
+        return None if self.device_count else S
+
+    # ----------------------------------------------------------- backward
+    def backward(self, S=None, Sd=None):
+        if S is None:
+            S, Sd = self._last
+        for name, fn in self.stages(S, Sd)[4:]:
+            self._mark(name)
+            fn()
         self._mark(None)
 
+    def stage_times(self, n=20, backward=True):
+        """GPU ms per stage (device counts): each stage captured in a graph of
+        its own and replayed n times back to back after a full step has put
+        its inputs in place (so its inputs are as warm as the cache allows)."""
+        if not self.device_count:
+            raise RuntimeError("stage_times needs device_count=True")
+        self.forward()
+        if backward:
+            self.backward()
+        torch.cuda.synchronize()
+        out = {}
+        for name, fn in [("march", self.march)] + self.stages(self.cap, self.n_samples, backward):
+            fn()
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                fn()
+            g.replay()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(n):
+                g.replay()
+            b.record()
+            torch.cuda.synchronize()
+            out[name] = a.elapsed_time(b) / n
+            del g
+        return out
+
     def train_step(self):
+        """Forward and backward; returns the sample count (None with device
+        counts)."""
+        if self.graph is not None and self.graph_kind == "train":
+            self.graph.replay()
+            return None
         S = self.forward()
-        self.backward(S)
+        self.backward()
         return S
+
+    def capture_train_step(self):
+        """Capture one training step (device counts) in a HIP graph; later
+        train_step calls replay it."""
+        self._capture(lambda: (self.forward(), self.backward()), "train")
+
+    def capture_forward(self):
+        """Capture one forward (device counts) in a HIP graph; later
+        replay() calls run it."""
+        self._capture(self.forward, "forward")
+
+    def _capture(self, fn, kind):
+        # torch captures on a side stream; replays go to the current stream
+        if not self.device_count:
+            raise RuntimeError("graph capture needs device_count=True")
+        self.graph = None
+        fn()  # warm-up outside the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        torch.cuda.synchronize()
+        self.graph, self.graph_kind = g, kind
+
+    def replay(self):
+        self.graph.replay()
 
     # ------------------------------------------------------------ readback
     def soa(self, t, S=None):
@@ -209,4 +305,5 @@ class Pipeline:
 
     def feat_samples(self, S=None):
         S = self.S if S is None else S
-        return self.feat[: self.w.L * S * 2].float().view(self.w.L, S, 2).permute(1, 0, 2).reshape(S, -1).double().cpu().numpy()
+        f = self.feat.float().view(self.w.L, self.cap, 2)[:, :S]
+        return f.permute(1, 0, 2).reshape(S, -1).double().cpu().numpy()

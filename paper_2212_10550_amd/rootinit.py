@@ -138,8 +138,8 @@ class GuidedDeform:
         self.n_fallback = torch.zeros(1, dtype=torch.int32, device=dev)
         self.ws = torch.empty(K.deform_guided_workspace_size(cap, Dx, Dy, Dz), dtype=torch.uint8, device=dev)
 
-    def run(self, xp, S, ld, pose_t, B, W, xc, bone, resid, steps):
+    def run(self, xp, S, ld, pose_t, B, W, xc, bone, resid, steps, S_dev=None):
         w = self.w
-        K.rootinit_fwd(xp, S, ld, pose_t, self.params, B, self.dtype, self.init_bone, self.x0)
+        K.rootinit_fwd(xp, S, ld, pose_t, self.params, B, self.dtype, self.init_bone, self.x0, S_dev=S_dev)
         K.snarf_deform_guided(xp, S, ld, self.x0, self.init_bone, B, W, w.skin_aabb, w.hash_aabb, w.max_iter,
-                              w.tol_stop, w.tol_valid, xc, bone, resid, steps, self.n_fallback, self.ws)
+                              w.tol_stop, w.tol_valid, xc, bone, resid, steps, self.n_fallback, self.ws, S_dev=S_dev)

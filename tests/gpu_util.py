@@ -23,6 +23,23 @@ def soa(a, ld=None, dtype=torch.float32):
     return up(out, dtype)
 
 
+def feat_dev(rows, ld=None, dtype=torch.float32):
+    """[S][32] per-sample feature rows -> level-major [16][ld][2] device
+    tensor (flat, zero padded past S)."""
+    rows = np.asarray(rows)
+    S = rows.shape[0]
+    ld = S if ld is None else ld
+    out = np.zeros((16, ld, 2), np.float64)
+    out[:, :S, :] = rows.reshape(S, 16, 2).transpose(1, 0, 2)
+    return up(out.reshape(-1), dtype)
+
+
+def feat_host(t, S, ld=None):
+    """Level-major [16][ld][2] device features -> [S][32] host rows."""
+    ld = S if ld is None else ld
+    return host(t).reshape(16, ld, 2)[:, :S, :].transpose(1, 0, 2).reshape(S, 32)
+
+
 def host(t):
     return t.detach().double().cpu().numpy()
 

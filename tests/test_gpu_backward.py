@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from paper_2212_10550_amd import synth
-from tests.gpu_util import assert_mixed, dev, host, soa, up
+from tests.gpu_util import feat_dev, feat_host, assert_mixed, dev, host, soa, up
 
 pytestmark = pytest.mark.gpu
 
@@ -100,9 +100,9 @@ def test_mlp_bwd_f32(orc, S):
     gsig = rng.normal(size=S).astype(np.float32)
     grgb = rng.normal(size=(S, 3)).astype(np.float32)
     ld = S + 3
-    ft = up(feat.reshape(S, 16, 2).transpose(1, 0, 2).reshape(-1))
+    ft = feat_dev(feat, ld)
     gp = torch.full((6532,), 0.25, device=dev())  # accumulated into
-    gf = torch.empty(16 * S * 2, device=dev())
+    gf = torch.empty(16 * ld * 2, device=dev())
     ws = torch.empty(K.mlp_bwd_workspace_size(S), dtype=torch.uint8, device=dev())
     K.mlp_bwd(up(gsig), soa(grgb, ld), ft, up(bone), S, ld, up(params), K.F32, gp, gf, ws)
     torch.cuda.synchronize()
@@ -115,20 +115,18 @@ def test_mlp_bwd_f32(orc, S):
     for a, b in zip(offs[:-1], offs[1:]):
         normclose(got[a:b], rp[a:b], GTOL, f"grad_params[{a}:{b}]")
     assert_mixed(got, rp, 1e-3, "grad_params", scale=1e-3 * np.abs(rp).max())
-    gclose_rows(host(gf).reshape(16, S, 2).transpose(1, 0, 2).reshape(S, 32), rf, "grad_feat")
+    gclose_rows(feat_host(gf, S, ld), rf, "grad_feat")
 
 
-@pytest.mark.parametrize("log2T,tdt,binned,overwrite,pad", [
-    (14, np.float32, True, True, 0), (19, np.float32, True, False, 5), (19, np.float16, True, True, 0),
-    (21, np.float16, True, False, 0), (14, np.float32, False, False, 0), (19, np.float32, False, True, 3),
-    (19, np.float16, False, False, 0)])
-def test_hash_bwd(orc, log2T, tdt, binned, overwrite, pad):
-    """Table and position gradients against the oracle.  binned: the LDS
-    slice path (S = 6007 -> 6 chunks, the last one ragged; level 0's single
-    slice holds ~48k records and is split over 3 workgroups that merge with
-    atomics; finer slices have one owner).  overwrite: the table starts as
-    garbage and must be replaced; otherwise it starts at 0.25 and the
-    gradient is added to it."""
+@pytest.mark.parametrize("log2T,tdt,overwrite,pad", [
+    (14, np.float32, True, 0), (19, np.float32, False, 5), (19, np.float16, True, 0), (21, np.float16, False, 0),
+    (19, np.float32, True, 3)])
+def test_hash_bwd(orc, log2T, tdt, overwrite, pad):
+    """Table and position gradients against the oracle.  overwrite: the table
+    starts as garbage and must be replaced; otherwise it starts at 0.25 and
+    the gradient is added to it.  S = 6007 leaves a ragged last block; the
+    coarse levels (run aggregation) and the hashed levels (16 lanes per
+    item) are both exercised; pad > 0 gives ld > S."""
     K = _K()
     S = 6007
     ld = S + pad
@@ -139,13 +137,8 @@ def test_hash_bwd(orc, log2T, tdt, binned, overwrite, pad):
     bone = np.where(np.arange(S) % 11 == 5, -1, 0).astype(np.int16)
     gt = torch.full((16, 1 << log2T, 2), 7.0 if overwrite else 0.25, device=dev())
     gx = torch.full((3, ld), 3.0, device=dev())
-    ws = None
-    if binned:
-        nbytes = K.hashgrid_bwd_workspace_size(S, 16, log2T)
-        assert nbytes > 0
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev())
-    K.hashgrid_encode_bwd(up(gfeat.reshape(S, 16, 2).transpose(1, 0, 2).reshape(-1)), soa(x, ld), up(bone), S, ld,
-                          up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, gx, K.OVERWRITE if overwrite else 0, ws=ws)
+    K.hashgrid_encode_bwd(feat_dev(gfeat, ld), soa(x, ld), up(bone), S, ld,
+                          up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, gx, K.OVERWRITE if overwrite else 0)
     torch.cuda.synchronize()
     rt, rx = orc.hash_encode_bwd(gfeat, x, table, orc.resolutions(16), np.array([0, 0, 0, 1, 1, 1.0]), valid=bone)
     gclose(host(gt) - (0.0 if overwrite else 0.25), rt, "grad_table")
@@ -153,20 +146,6 @@ def test_hash_bwd(orc, log2T, tdt, binned, overwrite, pad):
     gclose_rows(host(gx[:, :S]).T, rx, "grad_x")
     assert (host(gx[:, :S]).T[bone < 0] == 0).all()
     assert (host(gx[:, S:]) == 3.0).all()
-
-
-def test_hash_bwd_workspace_errors():
-    K = _K()
-    S, log2T = 3000, 19
-    x = synth.random_points(S, 2)
-    table = torch.zeros(16, 1 << log2T, 2, device=dev())
-    gt = torch.zeros_like(table)
-    gf = torch.zeros(16 * S * 2, device=dev())
-    small = torch.empty(K.hashgrid_bwd_workspace_size(S, 16, log2T) - 256, dtype=torch.uint8, device=dev())
-    with pytest.raises(RuntimeError):
-        K.hashgrid_encode_bwd(gf, soa(x), None, S, S, table, 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, None, ws=small)
-    assert K.hashgrid_bwd_workspace_size(0, 16, log2T) == 0
-    assert K.hashgrid_bwd_workspace_size(S, 16, 26) == 0  # beyond the binned path: atomics, no workspace
 
 
 def test_deform_bwd(orc):

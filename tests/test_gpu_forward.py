@@ -9,7 +9,7 @@ import torch
 
 from paper_2212_10550_amd import synth
 from tests import indep
-from tests.gpu_util import assert_mixed, dev, host, soa, up
+from tests.gpu_util import feat_dev, feat_host, assert_mixed, dev, host, soa, up
 
 pytestmark = pytest.mark.gpu
 
@@ -187,7 +187,7 @@ def test_mlp_fwd_f32(orc, S):
     ld = S + 5
     sigma = torch.empty(S, device=dev())
     rgb = torch.zeros(3, ld, device=dev())
-    K.mlp_fwd(_feat_tensor(feat), up(bone), S, ld, up(params), K.F32, sigma, rgb)
+    K.mlp_fwd(feat_dev(feat, ld), up(bone), S, ld, up(params), K.F32, sigma, rgb)
     torch.cuda.synchronize()
     s_ref, c_ref = orc.mlp_fwd(feat, params, valid=bone)
     assert_mixed(host(sigma), s_ref, TOL, "sigma")

@@ -44,19 +44,24 @@ struct Corners {
   float dw[8][3];
 };
 
-__device__ __forceinline__ void level_cell(const float x[3], const Box &box, int N, bool dense, uint32_t Tmask,
-                                           Corners &c, bool want_grad) {
+// Cell of x on a level of resolution N: base vertex v0, fraction f and the
+// scale dN x / dx (0 along a clamped axis).
+struct CellPos {
+  int v0[3];
+  float f[3], sc[3];
+};
+
+__device__ __forceinline__ CellPos level_pos(const float x[3], const Box &box, int N) {
   // no contraction: (uh - i) must stay a separately rounded difference, or
   // the compiler folds the product back in and the remainder counts twice
 #pragma clang fp contract(off)
-  int v0[3];
-  float f[3], sc[3];
+  CellPos p;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float xn = (x[a] - box.lo[a]) * box.inv[a];
-    sc[a] = (float)N * box.inv[a];
-    if (!(xn >= 0.0f)) { xn = 0.0f; sc[a] = 0.0f; }  // also catches NaN
-    if (xn > 1.0f) { xn = 1.0f; sc[a] = 0.0f; }
+    p.sc[a] = (float)N * box.inv[a];
+    if (!(xn >= 0.0f)) { xn = 0.0f; p.sc[a] = 0.0f; }  // also catches NaN
+    if (xn > 1.0f) { xn = 1.0f; p.sc[a] = 0.0f; }
     const float uh = xn * (float)N;
     const float ul = fmaf(xn, (float)N, -uh);  // exact remainder of the product
     int i = (int)floorf(uh);
@@ -64,24 +69,42 @@ __device__ __forceinline__ void level_cell(const float x[3], const Box &box, int
     if (fr < 0.0f && i > 0) { i -= 1; fr += 1.0f; }
     if (i > N - 1) { fr += (float)(i - (N - 1)); i = N - 1; }
     if (i < 0) { i = 0; }
-    v0[a] = i;
-    f[a] = fr;
+    p.v0[a] = i;
+    p.f[a] = fr;
   }
+  return p;
+}
+
+// Table index and trilinear weight of corner k (k = cx + 2 cy + 4 cz).
+__device__ __forceinline__ uint32_t corner_index(const CellPos &p, int k, int N, bool dense, uint32_t Tmask) {
+  const uint32_t vx = (uint32_t)(p.v0[0] + (k & 1));
+  const uint32_t vy = (uint32_t)(p.v0[1] + ((k >> 1) & 1));
+  const uint32_t vz = (uint32_t)(p.v0[2] + ((k >> 2) & 1));
   const uint32_t side = (uint32_t)N + 1u;
+  return dense ? vx + side * (vy + side * vz) : ((vx * 1u) ^ (vy * 2654435761u) ^ (vz * 805459861u)) & Tmask;
+}
+
+__device__ __forceinline__ float corner_weight(const CellPos &p, int k) {
+  const float wx = (k & 1) ? p.f[0] : 1.0f - p.f[0];
+  const float wy = (k & 2) ? p.f[1] : 1.0f - p.f[1];
+  const float wz = (k & 4) ? p.f[2] : 1.0f - p.f[2];
+  return wx * wy * wz;
+}
+
+__device__ __forceinline__ void level_cell(const float x[3], const Box &box, int N, bool dense, uint32_t Tmask,
+                                           Corners &c, bool want_grad) {
+  const CellPos p = level_pos(x, box, N);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const uint32_t vx = (uint32_t)(v0[0] + (k & 1));
-    const uint32_t vy = (uint32_t)(v0[1] + ((k >> 1) & 1));
-    const uint32_t vz = (uint32_t)(v0[2] + ((k >> 2) & 1));
-    c.idx[k] = dense ? vx + side * (vy + side * vz) : ((vx * 1u) ^ (vy * 2654435761u) ^ (vz * 805459861u)) & Tmask;
-    const float wx = (k & 1) ? f[0] : 1.0f - f[0];
-    const float wy = (k & 2) ? f[1] : 1.0f - f[1];
-    const float wz = (k & 4) ? f[2] : 1.0f - f[2];
-    c.w[k] = wx * wy * wz;
+    c.idx[k] = corner_index(p, k, N, dense, Tmask);
+    c.w[k] = corner_weight(p, k);
     if (want_grad) {
-      c.dw[k][0] = ((k & 1) ? sc[0] : -sc[0]) * wy * wz;
-      c.dw[k][1] = wx * ((k & 2) ? sc[1] : -sc[1]) * wz;
-      c.dw[k][2] = wx * wy * ((k & 4) ? sc[2] : -sc[2]);
+      const float wx = (k & 1) ? p.f[0] : 1.0f - p.f[0];
+      const float wy = (k & 2) ? p.f[1] : 1.0f - p.f[1];
+      const float wz = (k & 4) ? p.f[2] : 1.0f - p.f[2];
+      c.dw[k][0] = ((k & 1) ? p.sc[0] : -p.sc[0]) * wy * wz;
+      c.dw[k][1] = wx * ((k & 2) ? p.sc[1] : -p.sc[1]) * wz;
+      c.dw[k][2] = wx * wy * ((k & 4) ? p.sc[2] : -p.sc[2]);
     }
   }
 }
@@ -91,6 +114,50 @@ __device__ __forceinline__ float2 load_feat2(const float *t, uint32_t i) {
 }
 __device__ __forceinline__ float2 load_feat2(const __half *t, uint32_t i) {
   return __half22float2(reinterpret_cast<const __half2 *>(t)[i]);
+}
+
+// The two x-neighbouring corners (k, k + 1) of a cell usually sit in one
+// aligned block of the table: adjacent entries on dense levels, and on hashed
+// levels x + 1 flips only the low bits of x when x mod 4 != 3 (the x prime is
+// 1).  One vector load of the aligned block then serves both corners, and a
+// second load runs only for the lanes whose partner lies outside it; the L1
+// cost of a gather is one cache-line access per lane, so this cuts the
+// accesses per (sample, level) from 8 to about 5.  Values are unchanged.
+__device__ __forceinline__ uint32_t pick4(const uint4 &b, uint32_t j) {
+  return j == 0 ? b.x : (j == 1 ? b.y : (j == 2 ? b.z : b.w));
+}
+
+// FP16 table (4-byte entries): aligned 4-entry block, 16 B.
+__device__ __forceinline__ void gather_pair(const __half *t, uint32_t i0, uint32_t i1, float2 &v0, float2 &v1) {
+  const uint32_t q = i0 & ~3u;
+  const uint4 blk = reinterpret_cast<const uint4 *>(t)[q >> 2];
+  const uint32_t a = pick4(blk, i0 & 3u);
+  v0 = __half22float2(__builtin_bit_cast(__half2, a));
+  if ((i1 & ~3u) == q) {
+    v1 = __half22float2(__builtin_bit_cast(__half2, pick4(blk, i1 & 3u)));
+  } else {
+    v1 = load_feat2(t, i1);
+  }
+}
+
+// FP32 table (8-byte entries): aligned 2-entry block, 16 B.
+__device__ __forceinline__ void gather_pair(const float *t, uint32_t i0, uint32_t i1, float2 &v0, float2 &v1) {
+  const uint32_t q = i0 & ~1u;
+  const float4 blk = reinterpret_cast<const float4 *>(t)[q >> 1];
+  v0 = (i0 & 1u) ? make_float2(blk.z, blk.w) : make_float2(blk.x, blk.y);
+  if ((i1 & ~1u) == q) {
+    v1 = (i1 & 1u) ? make_float2(blk.z, blk.w) : make_float2(blk.x, blk.y);
+  } else {
+    v1 = load_feat2(t, i1);
+  }
+}
+
+// The eight corner values of a cell (table of one level, 16-byte aligned,
+// T a multiple of 4).
+template <typename TT>
+__device__ __forceinline__ void gather8(const TT *tl, const Corners &c, float2 v[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) gather_pair(tl, c.idx[k], c.idx[k + 1], v[k], v[k + 1]);
 }
 
 __device__ __forceinline__ void store_feat2(float *f, int64_t i, float a, float b) {
@@ -129,8 +196,7 @@ __global__ void __launch_bounds__(kFwdBlock) encode_kernel(const float *__restri
       Corners c;
       level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
       float2 v[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = load_feat2(tl, c.idx[k]);
+      gather8(tl, c, v);
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         a += c.w[k] * v[k].x;
@@ -164,9 +230,11 @@ __global__ void __launch_bounds__(kBwdBlock) encode_bwd_kernel(
       const uint32_t T = 1u << log2T;
       level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, true);
       const TT *tl = table + (int64_t)level * T * 2;
+      float2 vv[8];
+      gather8(tl, c, vv);
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const float2 v = load_feat2(tl, c.idx[k]);
+        const float2 v = vv[k];
         const float d = v.x * g.x + v.y * g.y;
         gx[0] += c.dw[k][0] * d;
         gx[1] += c.dw[k][1] * d;
@@ -215,10 +283,13 @@ __global__ void __launch_bounds__(kTgBlock) table_grad_kernel(const float *__res
     const int64_t n = item - (int64_t)(level - l0) * Sn;  // 0 <= n < Sn
     if (bone && bone[n] < 0) continue;
     const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
-    Corners c;
-    level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, false);
+    // this lane's corner only (a runtime-indexed corner array would live in
+    // scratch memory)
+    const int N = lv.res[level];
+    const CellPos cp = level_pos(x, box, N);
+    const uint32_t idx = corner_index(cp, k, N, lv.dense[level] != 0, T - 1u);
     const float g = gfeat[2 * ((int64_t)level * ld + n) + f];
-    atomicAdd(gtable + 2 * ((int64_t)level * T + c.idx[k]) + f, c.w[k] * g);
+    atomicAdd(gtable + 2 * ((int64_t)level * T + idx) + f, corner_weight(cp, k) * g);
   }
 }
 
@@ -313,6 +384,7 @@ extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, i
                                          int32_t feat_dtype, ia355_stream_t stream) {
   if (S < 0 || ld < S || L <= 0 || L > kMaxLevels || F != 2 || log2T < 1 || log2T > 30) return IA355_ERR_INVALID_ARG;
   if (!table || (S > 0 && (!xc || !feat))) return IA355_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(table) & 15) != 0 || log2T < 2) return IA355_ERR_INVALID_ARG;  // block gathers
   if (table_dtype != IA355_F32 && table_dtype != IA355_F16) return IA355_ERR_INVALID_ARG;
   if (feat_dtype != IA355_F32 && feat_dtype != IA355_BF16) return IA355_ERR_INVALID_ARG;
   Levels lv;
@@ -320,10 +392,10 @@ extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, i
   if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
   if (S == 0) return IA355_OK;
   const int per_xcd = (L + kXcd - 1) / kXcd;
-  // chunk slots per (XCD, level slot); with a device count at most 256 per
-  // level (8 per CU), the blocks loop over the rest
+  // chunk slots per (XCD, level slot); with a device count at most 1024 per
+  // level, the blocks loop over the rest (blocks past the count exit at once)
   int64_t nslot = ceil_div(S, kFwdBlock);
-  if (S_dev && nslot > 256) nslot = 256;
+  if (S_dev && nslot > 1024) nslot = 1024;
   const int64_t blocks = nslot * per_xcd * kXcd;
   if (blocks > 0x7fffffffLL) return IA355_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
@@ -351,6 +423,7 @@ extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float
   if (S < 0 || ld < S || L <= 0 || L > 16 || F != 2 || log2T < 1 || log2T > 30) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_feat || !xc)) return IA355_ERR_INVALID_ARG;
   if (grad_xc && !table) return IA355_ERR_INVALID_ARG;
+  if (grad_xc && ((reinterpret_cast<uintptr_t>(table) & 15) != 0 || log2T < 2)) return IA355_ERR_INVALID_ARG;
   if (table_dtype != IA355_F32 && table_dtype != IA355_F16) return IA355_ERR_INVALID_ARG;
   if (flags & ~(uint32_t)IA355_OVERWRITE) return IA355_ERR_INVALID_ARG;
   Levels lv;

@@ -237,7 +237,7 @@ extern "C" int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d,
     march_count<<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray, max_steps,
                                                   ray_off, ray_cnt, ray_dt, block_sum);
   march_scan<<<1, 1024, 0, s>>>(block_sum, nblk, ray_off, R, n_samples);
-  if (R > 0)
+  if (R > 0 && cap > 0)
     march_fill<<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, max_steps, block_sum, ray_off,
                                                  ray_dt, xs, ts, ray_id, cap);
   return launch_status();

@@ -327,10 +327,11 @@ def tiny_forward(pose_seed: int = 1) -> Workload:
 
 
 def _body_frame(name, n_rays, occ_frac, pose_seed, ray_seed, target_seed, sigma_bias, T_thresh,
-                table_scale):
+                table_scale, res=540):
     skel = _skeleton_cached(0)
     pose = make_pose(skel, pose_seed)
-    o, d = camera_rays()
+    # the 540^2 camera's field of view at any resolution
+    o, d = camera_rays(res, res, 583.2 * (res / 540.0), res / 2.0, res / 2.0)
     if n_rays < o.shape[0]:
         idx = np.sort(np.random.default_rng(ray_seed).choice(o.shape[0], size=n_rays, replace=False))
         o, d = o[idx], d[idx]
@@ -361,6 +362,30 @@ def full_frame(pose_seed: int = 1, table_scale: float = 1e-4) -> Workload:
     """Full-frame inference: 540 x 540 rays, ~10 % occupancy, early ray
     termination at transmittance 1e-4, density output bias +4."""
     return _body_frame("frame540", 540 * 540, 0.10, pose_seed, None, None, 4.0, 1e-4, table_scale)
+
+
+BATCH_RES = (270, 540, 1080)
+
+
+def batch_pose(k: int, n: int = 16, table_scale: float = 1e-4) -> Workload:
+    """Pose k of the batched render: pose seed 3000 + k, occupancy
+    5 % + 20 % k / (n - 1), resolution 270^2, 540^2 or 1080^2 by k mod 3
+    (the 540^2 camera's field of view), termination at T < 1e-4, density
+    output bias +4.  One avatar: the hash table, MLP and skinning grid are
+    those of full_frame."""
+    frac = 0.05 + 0.20 * k / max(n - 1, 1)
+    res = BATCH_RES[k % 3]
+    return _body_frame(f"batch{k}", res * res, frac, 3000 + k, None, None, 4.0, 1e-4, table_scale, res=res)
+
+
+def batch_poses(n: int = 16, table_scale: float = 1e-4, workers: int = 1) -> list:
+    """The n poses of the batched render (occupancy grids built in a process
+    pool of `workers` when > 1)."""
+    if workers > 1:
+        import concurrent.futures as cf
+        with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(batch_pose, range(n), [n] * n, [table_scale] * n))
+    return [batch_pose(k, n, table_scale) for k in range(n)]
 
 
 def ray_subset(w: Workload, idx: np.ndarray) -> Workload:

@@ -59,10 +59,11 @@ DEFORM_FLOP_PER_INIT = 670.0   # start point, Jacobian, inverse
 DEFORM_FLOP_PER_STEP = 380.0   # one Broyden step (residual 290 + update 90)
 HASH_GATHER_BYTES = {4: 16 * 8 * 2 * 4, 2: 16 * 8 * 2 * 2}  # 16 levels x 8 corners x 2 features
 FEAT_BYTES = {4: 16 * 2 * 4, 2: 16 * 2 * 2}
-# backward: read-modify-write of the 256 touched FP32 entries, dL/dfeat and x
-# read, the table gather for dL/dx and its write
+# table gradient: read-modify-write of the 256 touched FP32 entries, dL/dfeat
+# and x read; position gradient: the table gather, dL/dfeat and x read, the
+# gradient written
 HASH_BWD_BYTES = 2 * 16 * 8 * 2 * 4 + 16 * 2 * 4 + 12
-HASH_BWD_X_BYTES = 16 * 8 * 2 * 4 + 12
+HASH_BWD_X_BYTES = 16 * 8 * 2 * 4 + 16 * 2 * 4 + 12 + 12
 IFT_BYTES_PER_SAMPLE = 2 * 8 * 12 * 4 + 24 + 12 + 8 * 24 * 4  # moment RMW + x, v, u + skinning rows
 MLP_FWD_FLOP = 12800.0
 MLP_BWD_FLOP = 25600.0 + 12800.0  # backward plus the recomputed forward
@@ -78,7 +79,8 @@ STAGE_KERNELS = {
     "render_fwd": ["render_fwd"],
     "loss+render_bwd": ["l2_loss_kernel", "render_bwd"],
     "mlp_bwd": ["mlp_bwd_f32", "mlp_bwd_bf16", "reduce_partials"],
-    "hash_bwd": ["table_grad_kernel", "table_grad_dense_kernel", "encode_bwd_kernel"],
+    "hash_bwd_table": ["table_grad_kernel", "table_grad_dense_kernel"],
+    "hash_bwd_x": ["encode_bwd_kernel"],
     "deform_bwd": ["ift_v_kernel", "ift_q_kernel", "ift_contract_kernel", "ift_b_kernel"],
 }
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "training_step_f32_hbm_traffic.md")
@@ -192,7 +194,8 @@ def stage_rooflines(stage_ms, S, R, steps_total, nb, es, mlp_bf16, backward=True
     if backward:
         put("loss+render_bwd", "hbm", RENDER_BWD_BYTES_PER_SAMPLE * S + 2 * RENDER_BYTES_PER_RAY * R, "bytes")
         put("mlp_bwd", "mfma", MLP_BWD_FLOP * S, "flop")
-        put("hash_bwd", "hbm", (HASH_BWD_BYTES + HASH_BWD_X_BYTES) * S, "bytes")
+        put("hash_bwd_table", "hbm", HASH_BWD_BYTES * S, "bytes")
+        put("hash_bwd_x", "hbm", HASH_BWD_X_BYTES * S, "bytes")
         put("deform_bwd", "hbm", IFT_BYTES_PER_SAMPLE * S, "bytes")
     return out
 

@@ -266,6 +266,8 @@ __global__ void __launch_bounds__(kBwdBlock) encode_bwd_kernel(
 // the four items of a wave are consecutive samples of one level and share
 // lines on the coarse levels as well.
 constexpr int kTgBlock = 256;
+constexpr int kTgMaxGrid = 1024;      // 4 blocks per CU
+constexpr int kTgDenseMaxGrid = 512;  // 2 blocks per CU
 
 __global__ void __launch_bounds__(kTgBlock) table_grad_kernel(const float *__restrict__ gfeat,
                                                              const float *__restrict__ xc,
@@ -442,12 +444,16 @@ extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float
     // finer levels use the 16-lanes-per-item mapping.
     int ndense = 0;
     while (ndense < L && lv.dense[ndense] && lv.res[ndense] <= kAggMaxRes) ++ndense;
+    // The atomics do not return values, so a few waves per CU keep the
+    // memory-side atomic units busy; bounded grids (grid-stride) leave CUs
+    // to kernels on other streams (the position gradient and the IFT run
+    // beside the table gradient).
     if (ndense > 0)
-      table_grad_dense_kernel<<<stride_grid(ceil_div(S, kDgBlock) * ndense, dev), kDgBlock, 0, s>>>(
+      table_grad_dense_kernel<<<stride_grid(ceil_div(S, kDgBlock) * ndense, true, kTgDenseMaxGrid), kDgBlock, 0, s>>>(
           grad_feat, xc, bone, S, S_dev, ld, ndense, log2T, lv, box, grad_table);
     if (ndense < L)
-      table_grad_kernel<<<stride_grid(ceil_div((int64_t)(L - ndense) * S * 16, kTgBlock), dev, 8192), kTgBlock, 0,
-                          s>>>(grad_feat, xc, bone, S, S_dev, ld, ndense, L, log2T, lv, box, grad_table);
+      table_grad_kernel<<<stride_grid(ceil_div((int64_t)(L - ndense) * S * 16, kTgBlock), true, kTgMaxGrid), kTgBlock,
+                          0, s>>>(grad_feat, xc, bone, S, S_dev, ld, ndense, L, log2T, lv, box, grad_table);
   }
   if (grad_xc && S > 0) {
     const unsigned blocks = stride_grid(ceil_div(S * 16, kBwdBlock), dev, 4096);

@@ -59,6 +59,8 @@ class Pipeline:
         self.w = w
         self.device_count = device_count
         self.graph, self.graph_kind = None, None
+        self.side = torch.cuda.Stream(device=torch.device(device))  # default priority
+        self._table_zeroed = False
         self.dev = torch.device(device)
         dev = self.dev
         t = lambda a, dt=None: torch.as_tensor(np.ascontiguousarray(a), device=dev, dtype=dt)
@@ -190,10 +192,23 @@ class Pipeline:
         K.mlp_bwd(self.grad_sigma, self.grad_rgb, self.feat, self.bone, S, self.cap, self.params, self.mlp_dtype,
                   self.grad_params, self.grad_feat, self.ws_mlp, flags=K.OVERWRITE, S_dev=Sd)
 
-    def _encode_bwd(self, S, Sd):
+    def _table_grad(self, S, Sd, overwrite=True):
         w = self.w
         K.hashgrid_encode_bwd(self.grad_feat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth,
-                              w.hash_aabb, self.grad_table, self.grad_xc, flags=K.OVERWRITE, S_dev=Sd)
+                              w.hash_aabb, self.grad_table, None, flags=K.OVERWRITE if overwrite else 0, S_dev=Sd)
+
+    def _zero_table_async(self):
+        """Clear the table gradient on the side stream (it overlaps the
+        forward); the backward's table gradient then adds to it."""
+        self.side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.side):
+            K.zero(self.grad_table)
+        self._table_zeroed = True
+
+    def _x_grad(self, S, Sd):
+        w = self.w
+        K.hashgrid_encode_bwd(self.grad_feat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth,
+                              w.hash_aabb, None, self.grad_xc, S_dev=Sd)
 
     def _deform_bwd(self, S, Sd):
         w = self.w
@@ -206,7 +221,8 @@ class Pipeline:
               ("mlp_fwd", lambda: self._mlp(S, Sd)), ("render_fwd", self._render)]
         if backward:
             st += [("loss+render_bwd", self._render_bwd), ("mlp_bwd", lambda: self._mlp_bwd(S, Sd)),
-                   ("hash_bwd", lambda: self._encode_bwd(S, Sd)), ("deform_bwd", lambda: self._deform_bwd(S, Sd))]
+                   ("hash_bwd_table", lambda: self._table_grad(S, Sd)), ("hash_bwd_x", lambda: self._x_grad(S, Sd)),
+                   ("deform_bwd", lambda: self._deform_bwd(S, Sd))]
         return st
 
     def forward(self):
@@ -225,12 +241,30 @@ class Pipeline:
 
     # ----------------------------------------------------------- backward
     def backward(self, S=None, Sd=None):
+        """Loss, composite and MLP backward, then two independent branches:
+        the hash-table gradient on a side stream, and the position gradient
+        followed by the implicit-function-theorem backward on this stream;
+        the side stream joins back before returning."""
         if S is None:
             S, Sd = self._last
-        for name, fn in self.stages(S, Sd)[4:]:
+        st = dict(self.stages(S, Sd))
+        for name in ("loss+render_bwd", "mlp_bwd"):
             self._mark(name)
-            fn()
-        self._mark(None)
+            st[name]()
+        if self.timer is not None:  # stage timing: serial, one stage at a time
+            for name in ("hash_bwd_table", "hash_bwd_x", "deform_bwd"):
+                self._mark(name)
+                st[name]()
+            self._mark(None)
+            return
+        main = torch.cuda.current_stream()
+        self.side.wait_stream(main)
+        with torch.cuda.stream(self.side):
+            self._table_grad(S, Sd, overwrite=not self._table_zeroed)
+        self._table_zeroed = False
+        st["hash_bwd_x"]()
+        st["deform_bwd"]()
+        main.wait_stream(self.side)
 
     def stage_times(self, n=20, backward=True):
         """GPU ms per stage (device counts): each stage captured in a graph of
@@ -268,6 +302,8 @@ class Pipeline:
         if self.graph is not None and self.graph_kind == "train":
             self.graph.replay()
             return None
+        if self.timer is None:
+            self._zero_table_async()
         S = self.forward()
         self.backward()
         return S
@@ -275,7 +311,7 @@ class Pipeline:
     def capture_train_step(self):
         """Capture one training step (device counts) in a HIP graph; later
         train_step calls replay it."""
-        self._capture(lambda: (self.forward(), self.backward()), "train")
+        self._capture(lambda: (self._zero_table_async(), self.forward(), self.backward()), "train")
 
     def capture_forward(self):
         """Capture one forward (device counts) in a HIP graph; later

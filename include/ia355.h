@@ -54,6 +54,12 @@ extern "C" {
 
 /* flags of the backward entry points */
 #define IA355_OVERWRITE 1u /* write the gradient instead of adding to it */
+/* Hash-table gradient level groups (ia355_hashgrid_encode_bwd): the coarse
+ * dense levels (resolution <= 32, summed by run aggregation) or the rest;
+ * neither flag, or both, means every level.  The groups write disjoint
+ * slices of grad_table, so they may run concurrently on two streams. */
+#define IA355_TABLE_COARSE 2u
+#define IA355_TABLE_FINE 4u
 
 #define IA355_F32 0
 #define IA355_F16 1
@@ -73,9 +79,15 @@ int32_t ia355_zero(void *p, size_t bytes, ia355_stream_t stream);
 /* ------------------------------------------------------------------ */
 /* Occupancy grid (Sec. 3.3, "Empty Space Skipping").                  */
 /* ------------------------------------------------------------------ */
+/* Number of 32-bit words of a packed G^3 grid (0 unless 0 < G <= 2048). */
+size_t ia355_occ_words(int32_t G);
 /* Pack a binary occupancy grid occ [G][G][G] (uint8, z-major, x fastest,
- * non-zero = occupied) into bits [ceil(G^3/32)] (bit i of word i/32 is cell
- * i = x + G*(y + G*z)). */
+ * non-zero = occupied) into bits [ia355_occ_words(G)].  Layout: bricks of
+ * 8 x 8 x 16 cells (x, y, z), 32 words (one 128-byte line) each, in
+ * x-fastest brick order over ceil(G/8) x ceil(G/8) x ceil(G/16) bricks;
+ * cell (x, y, z) is bit lx + 8 ly + 64 lz of its brick (l = offset in the
+ * brick), i.e. bit (lx + 8 ly) mod 32 of word 32 brick + ly/4 + 2 lz.
+ * Cells past G in a brick are 0.  The march reads this layout. */
 int32_t ia355_occ_pack(const uint8_t *occ, int32_t G, uint32_t *bits, ia355_stream_t stream);
 
 /* Ray marching with empty-space skipping (Sec. 3.2 ray r = o + t d with N
@@ -87,15 +99,19 @@ int32_t ia355_occ_pack(const uint8_t *occ, int32_t G, uint32_t *bits, ia355_stre
  * kept iff its cell in the G^3 grid over `aabb` is occupied (occ_bits NULL:
  * all cells occupied).  Positions and decisions use IEEE single precision
  * with no fused operations.
+ * occ_bits: the packed grid of ia355_occ_pack.
  * Outputs (compacted, rays in order, samples in t order):
  *   xs [3][cap] positions, ts [cap] ray parameter, ray_id [cap],
  *   ray_off [R+1] first-sample offsets (int64), ray_cnt [R], ray_dt [R]
  *   (the ray's uniform step: every kept sample's delta, Eq. 8),
  *   n_samples [1] device int64 total kept count.
+ * With cap == 0 the call only counts: ray_cnt, ray_dt and n_samples are
+ * written, ray_off is not final.
  * If *n_samples > cap, samples at offsets >= cap are not written: the caller
  * must compare after the stream completes.
- * ws: ia355_march_workspace_size(R) bytes. */
-size_t ia355_march_workspace_size(int64_t R);
+ * ws: ia355_march_workspace_size(R, max_steps) bytes (per-block totals,
+ * and each ray's keep masks, 8 bytes per 64 steps, and entry distance). */
+size_t ia355_march_workspace_size(int64_t R, int32_t max_steps);
 int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d, int64_t R,
                             const uint32_t *occ_bits, int32_t G, const float *aabb,
                             float dt, int32_t n_per_ray, int32_t max_steps,
@@ -202,7 +218,9 @@ int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, c
 /* Backward of the encoding.  grad_feat [L][ld][F] FP32.
  *   grad_table [L][T][F] FP32 += sum over samples of w_c * grad_feat_l at each
  *   corner (nullable); with IA355_OVERWRITE in flags it is written instead
- *   (every entry, untouched ones set to 0).  Summation order inside a table
+ *   (every entry, untouched ones set to 0).  IA355_TABLE_COARSE or
+ *   IA355_TABLE_FINE limits the update (and the overwrite) to that level
+ *   group's slice; the rest of grad_table is not touched.  Summation order inside a table
  *   entry is not fixed (atomic adds), so the last bits may vary run to run.
  *   grad_xc [3][ld] overwritten with sum_l sum_c (grad w_c)(theta_c . grad_feat_l)
  *   (nullable; needs the table).

@@ -781,7 +781,7 @@ double oracle_l2_loss(const double *color, const double *target, int64_t R, doub
 }
 
 /* ------------------------------------------------------------------ */
-/* Learned root initialiser (this build's addition; not in the paper).  */
+/* Learned root initialiser (an addition to the method; not in the paper).  */
 /* An MLP maps (x', pose) -> (bone logits, canonical offset):          */
 /* input = (x'_xyz, then per bone axis-angle(3) and translation(3)),   */
 /* ReLU hidden layers, linear outputs: nb logits then 3 offsets.       */

@@ -31,7 +31,7 @@ class _Pose:
         self.rays_d = t(w.rays_d)
         self.G = w.occ.shape[0]
         occ = t(w.occ, torch.uint8)
-        self.occ_bits = torch.empty((self.G ** 3 + 31) // 32, dtype=torch.int32, device=dev)
+        self.occ_bits = torch.empty(K.occ_words(self.G), dtype=torch.int32, device=dev)
         K.occ_pack(occ, self.occ_bits)
         self.B = t(w.B)
         self.pose_t = t(w.pose_params.reshape(-1))
@@ -50,7 +50,7 @@ class _Pose:
 class _Slot:
     """Sample buffers of one stream."""
 
-    def __init__(self, cap, max_R, L, Wshape, feat_dtype, dev):
+    def __init__(self, cap, max_R, max_steps, L, Wshape, feat_dtype, dev):
         e = lambda *shape, dt=torch.float32: torch.empty(*shape, dtype=dt, device=dev)
         Dz, Dy, Dx, nb = Wshape
         self.cap = cap
@@ -58,7 +58,7 @@ class _Slot:
         self.ts = e(cap)
         self.ray_id = e(cap, dt=torch.int32)
         self.n_samples = e(1, dt=torch.int64)
-        self.ws_march = e(K.march_workspace_size(max_R), dt=torch.uint8)
+        self.ws_march = e(K.march_workspace_size(max_R, max_steps), dt=torch.uint8)
         self.init_bone = e(cap, dt=torch.int16)
         self.x0 = e(3, cap)
         self.ws_guided = e(K.deform_guided_workspace_size(cap, Dx, Dy, Dz), dt=torch.uint8)
@@ -92,7 +92,7 @@ class BatchRenderer:
         n = torch.empty(1, dtype=torch.int64, device=self.dev)
         for p in self.poses:
             w = p.w
-            ws = torch.empty(K.march_workspace_size(p.R), dtype=torch.uint8, device=self.dev)
+            ws = torch.empty(K.march_workspace_size(p.R, w.max_steps), dtype=torch.uint8, device=self.dev)
             K.occgrid_march(p.rays_o, p.rays_d, p.occ_bits, p.G, w.occ_aabb, w.dt, w.n_per_ray, w.max_steps,
                             None, None, None, 0, p.ray_off, p.ray_cnt, p.ray_dt, n, ws)
             p.S = int(n.item())
@@ -116,7 +116,8 @@ class BatchRenderer:
             ps = [self.poses[i] for i in self.assign[j]]
             cap = max([p.S for p in ps] + [1])
             max_R = max([p.R for p in ps] + [1])
-            self.slots.append(_Slot(cap, max_R, w0.L, w0.W.shape, torch.bfloat16, self.dev))
+            max_steps = max([p.w.max_steps for p in ps] + [1])
+            self.slots.append(_Slot(cap, max_R, max_steps, w0.L, w0.W.shape, torch.bfloat16, self.dev))
         self.n_streams = n_streams
 
     def _pose_forward(self, sl, p):

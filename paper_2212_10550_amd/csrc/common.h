@@ -49,6 +49,19 @@ inline unsigned stride_grid(int64_t needed, bool device_count, int64_t cap_block
   return (unsigned)needed;
 }
 
+// Packed occupancy bits: bricks of 8 x 8 x 16 cells (x, y, z), 1024 bits =
+// one 128-byte cache line each, bricks in x-fastest order; inside a brick,
+// cell (lx, ly, lz) is bit lx + 8 ly + 64 lz.
+__host__ __device__ inline int64_t occ_words(int64_t G) {
+  return ceil_div(G, 8) * ceil_div(G, 8) * ceil_div(G, 16) * 32;
+}
+__device__ __forceinline__ uint32_t occ_word(int x, int y, int z, int G) {
+  const uint32_t nb = (uint32_t)(G + 7) >> 3;  // bricks along x and along y
+  const uint32_t brick = ((uint32_t)x >> 3) + nb * (((uint32_t)y >> 3) + nb * ((uint32_t)z >> 4));
+  return brick * 32u + (((uint32_t)y & 7u) >> 2) + 2u * ((uint32_t)z & 15u);
+}
+__device__ __forceinline__ uint32_t occ_bit(int x, int y) { return ((uint32_t)x & 7u) + 8u * ((uint32_t)y & 3u); }
+
 // Workspace carving: 256-byte aligned slices.
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 

@@ -427,31 +427,37 @@ extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float
   if (grad_xc && !table) return IA355_ERR_INVALID_ARG;
   if (grad_xc && ((reinterpret_cast<uintptr_t>(table) & 15) != 0 || log2T < 2)) return IA355_ERR_INVALID_ARG;
   if (table_dtype != IA355_F32 && table_dtype != IA355_F16) return IA355_ERR_INVALID_ARG;
-  if (flags & ~(uint32_t)IA355_OVERWRITE) return IA355_ERR_INVALID_ARG;
+  const uint32_t known = IA355_OVERWRITE | IA355_TABLE_COARSE | IA355_TABLE_FINE;
+  if (flags & ~known) return IA355_ERR_INVALID_ARG;
   Levels lv;
   Box box;
   if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
   const bool dev = S_dev != nullptr;
   const int overwrite = (flags & IA355_OVERWRITE) != 0;
-  if (grad_table && overwrite) {
-    const int32_t st = ia355_zero(grad_table, sizeof(float) * 2 * (size_t)L * ((size_t)1 << log2T), stream);
+  // Run aggregation pays while a cell spans several ray steps (coarse dense
+  // levels, which come first as the resolution grows with the level); finer
+  // levels use the 16-lanes-per-item mapping.  The two groups touch disjoint
+  // slices of the table, so a caller may run them on two streams.
+  int ndense = 0;
+  while (ndense < L && lv.dense[ndense] && lv.res[ndense] <= kAggMaxRes) ++ndense;
+  const bool coarse = !(flags & IA355_TABLE_FINE) || (flags & IA355_TABLE_COARSE);
+  const bool fine = !(flags & IA355_TABLE_COARSE) || (flags & IA355_TABLE_FINE);
+  const int l0 = coarse ? 0 : ndense, l1 = fine ? L : ndense;
+  const size_t level_floats = 2 * ((size_t)1 << log2T);
+  if (grad_table && overwrite && l1 > l0) {
+    const int32_t st = ia355_zero(grad_table + level_floats * l0, sizeof(float) * level_floats * (l1 - l0), stream);
     if (st != IA355_OK) return st;
   }
   if (grad_table && S > 0) {
-    // Run aggregation pays while a cell spans several ray steps (coarse
-    // dense levels, which come first as the resolution grows with the level);
-    // finer levels use the 16-lanes-per-item mapping.
-    int ndense = 0;
-    while (ndense < L && lv.dense[ndense] && lv.res[ndense] <= kAggMaxRes) ++ndense;
     // The atomics do not return values, so a few waves per CU keep the
     // memory-side atomic units busy; bounded grids (grid-stride) leave CUs
     // to kernels on other streams (the position gradient and the IFT run
     // beside the table gradient).
-    if (ndense > 0)
+    if (coarse && ndense > 0)
       table_grad_dense_kernel<<<stride_grid(ceil_div(S, kDgBlock) * ndense, true, kTgDenseMaxGrid), kDgBlock, 0, s>>>(
           grad_feat, xc, bone, S, S_dev, ld, ndense, log2T, lv, box, grad_table);
-    if (ndense < L)
+    if (fine && ndense < L)
       table_grad_kernel<<<stride_grid(ceil_div((int64_t)(L - ndense) * S * 16, kTgBlock), true, kTgMaxGrid), kTgBlock,
                           0, s>>>(grad_feat, xc, bone, S, S_dev, ld, ndense, L, log2T, lv, box, grad_table);
   }

@@ -1,16 +1,27 @@
 // Ray marching with empty-space skipping (Sec. 3.2 ray sampling, Sec. 3.3
-// occupancy-grid skipping), as a three-kernel stream compaction:
+// occupancy-grid skipping), as a stream compaction in four kernels:
 //   count  -- one wave per ray, one lane per midpoint sample: a ballot of
-//             the samples in occupied cells gives the ray's count;
-//   scan   -- one block turns the per-block totals into global offsets;
-//   fill   -- one wave per ray again; each kept sample's slot is the ray's
-//             offset plus the popcount of kept lanes below it, so a ray's
-//             samples are written in t order by consecutive lanes
-//             (structure-of-arrays, coalesced).
+//             the samples in occupied cells gives the ray's count, and the
+//             block's total;
+//   chunk  -- each block scans 4096 block totals (exclusive, in place) and
+//             writes its chunk total;
+//   top    -- one block scans the chunk totals and writes the sample count;
+//   fill   -- one wave per ray again, from the keep masks the count kernel
+//             saved (one 64-bit ballot per 64 steps) and the ray's entry
+//             distance: only kept samples' positions are recomputed (the same
+//             expression, so the same floats), no cell lookups; each kept
+//             sample's slot is the ray's offset plus the popcount of kept
+//             lanes below it, so a ray's samples are written in t order by
+//             consecutive lanes (structure-of-arrays, coalesced).
+// The occupancy bits are stored in bricks of 8 x 8 x 16 cells, one 128-byte
+// cache line each, so the consecutive samples of a ray (one wave) touch a
+// few lines rather than one line per sample.
 // Every position and keep/skip decision is computed with individually
 // rounded IEEE single operations (contraction is switched off: the
 // compiler would otherwise fuse o + t d into one FMA), so the sample set is
 // exactly reproducible.
+#include <cmath>
+
 #include "common.h"
 
 using namespace ia355;
@@ -19,6 +30,7 @@ namespace {
 
 struct Box {
   float lo[3], hi[3];
+  float inv_ext[3];  // 1 / (hi - lo), used only when every extent is a power of two
 };
 
 struct RaySpan {
@@ -54,6 +66,10 @@ __device__ __forceinline__ RaySpan ray_span(const float o[3], const float d[3], 
 }
 
 // Sample k of a ray: position and whether its cell is occupied.
+// kPow2Ext: every box extent is a power of two, so dividing by it and
+// multiplying by its (exact) reciprocal round the same real number once and
+// give the same float; the multiply saves the division sequence.
+template <bool kPow2Ext>
 __device__ __forceinline__ bool sample_at(const float o[3], const float d[3], const RaySpan &s, int k, const Box &b,
                                           const uint32_t *bits, int G, float *t_out, float x[3]) {
 #pragma clang fp contract(off)
@@ -63,13 +79,14 @@ __device__ __forceinline__ bool sample_at(const float o[3], const float d[3], co
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     x[a] = o[a] + t * d[a];
-    const float u = (x[a] - b.lo[a]) / (b.hi[a] - b.lo[a]) * (float)G;
+    const float rel = kPow2Ext ? (x[a] - b.lo[a]) * b.inv_ext[a] : (x[a] - b.lo[a]) / (b.hi[a] - b.lo[a]);
+    const float u = rel * (float)G;
     int c = (int)floorf(u);
     cell[a] = c < 0 ? 0 : (c > G - 1 ? G - 1 : c);
   }
   if (!bits) return true;
-  const uint32_t idx = (uint32_t)cell[0] + (uint32_t)G * ((uint32_t)cell[1] + (uint32_t)G * (uint32_t)cell[2]);
-  return (bits[idx >> 5] >> (idx & 31)) & 1u;
+  const uint32_t word = occ_word(cell[0], cell[1], cell[2], G);
+  return (bits[word] >> occ_bit(cell[0], cell[1])) & 1u;
 }
 
 // One wave per ray: lane l handles steps k = l, l + 64, ... of its ray, so a
@@ -85,10 +102,12 @@ __device__ __forceinline__ void load_ray(const float *ro, const float *rd, int64
   }
 }
 
+template <bool kPow2Ext>
 __global__ void __launch_bounds__(kBlock) march_count(const float *ro, const float *rd, int64_t R,
                                                       const uint32_t *bits, int G, Box box, float dt_fixed,
                                                       int n_per_ray, int max_steps, int64_t *ray_off,
-                                                      int32_t *ray_cnt, float *ray_dt, int64_t *block_sum) {
+                                                      int32_t *ray_cnt, float *ray_dt, int64_t *block_sum,
+                                                      uint64_t *masks, int nw, float *ray_tn) {
   __shared__ int cnts[kRays];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t r = (int64_t)blockIdx.x * kRays + wid;
@@ -97,24 +116,31 @@ __global__ void __launch_bounds__(kBlock) march_count(const float *ro, const flo
     float o[3], d[3];
     load_ray(ro, rd, r, o, d);
     const RaySpan s = ray_span(o, d, box, dt_fixed, n_per_ray);
+    uint64_t *mr = masks + r * nw;
+    int words = 0;  // mask words written; the rest are cleared below
     if (s.hit) {
       for (int k0 = 0; k0 < max_steps; k0 += kWave) {
         const int k = k0 + lane;
         float t = 0.0f, x[3];
         bool keep = false, inside = false;
         if (k < max_steps) {
-          keep = sample_at(o, d, s, k, box, bits, G, &t, x);
+          keep = sample_at<kPow2Ext>(o, d, s, k, box, bits, G, &t, x);
           inside = t < s.tf;
           keep = keep && inside;
         }
-        cnt += __popcll(__ballot(keep));
+        const uint64_t m = __ballot(keep);
+        cnt += __popcll(m);
+        if (lane == 0) mr[words] = m;
+        ++words;
         // t grows with k: once the last lane is beyond t_far, so is every later step
         if (!__shfl((int)inside, kWave - 1, kWave)) break;
       }
     }
+    for (int j = words + lane; j < nw; j += kWave) mr[j] = 0ull;
     if (lane == 0) {
       ray_cnt[r] = cnt;
       ray_dt[r] = s.dt;
+      ray_tn[r] = s.tn;
     }
   }
   if (lane == 0) cnts[wid] = cnt;
@@ -130,32 +156,65 @@ __global__ void __launch_bounds__(kBlock) march_count(const float *ro, const flo
   }
 }
 
-// Exclusive scan of the per-block totals in one block (in place), total to
-// n_samples and ray_off[R].
-__global__ void __launch_bounds__(1024) march_scan(int64_t *block_sum, int64_t nblk, int64_t *ray_off, int64_t R,
-                                                   int64_t *n_samples) {
-  __shared__ int64_t wsum[1024 / kWave];
-  __shared__ int64_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
+// Exclusive scan in one block of 1024 threads: thread t holds `v`; returns
+// the sum of the values of threads below it, and the block total in *total.
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *wsum, int64_t *total) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  for (int64_t b0 = 0; b0 < nblk; b0 += 1024) {
-    const int64_t i = b0 + threadIdx.x;
-    const int64_t v = i < nblk ? block_sum[i] : 0;
-    int64_t incl = v;
+  int64_t incl = v;
 #pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int64_t t = __shfl_up(incl, o, kWave);
-      if (lane >= o) incl += t;
-    }
-    if (lane == kWave - 1) wsum[wid] = incl;
-    __syncthreads();
-    int64_t base = carry;
-    for (int w = 0; w < wid; ++w) base += wsum[w];
-    if (i < nblk) block_sum[i] = base + incl - v;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry = base + incl;
-    __syncthreads();
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  int64_t base = 0, all = 0;
+  for (int w = 0; w < 1024 / kWave; ++w) {
+    base += w < wid ? wsum[w] : 0;
+    all += wsum[w];
+  }
+  __syncthreads();
+  *total = all;
+  return base + incl - v;
+}
+
+// Chunk c of the per-block totals, kScanPer per thread: exclusive scan in
+// place (offsets within the chunk) and the chunk's total.
+constexpr int kScanPer = 4;
+constexpr int64_t kScanChunk = 1024 * kScanPer;
+
+__global__ void __launch_bounds__(1024) march_scan_chunk(int64_t *block_sum, int64_t nblk, int64_t *chunk_sum) {
+  __shared__ int64_t wsum[1024 / kWave];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+  int64_t v[kScanPer], run = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    v[j] = i0 + j < nblk ? block_sum[i0 + j] : 0;
+    run += v[j];
+  }
+  int64_t total;
+  int64_t off = block_exclusive_scan(run, wsum, &total);
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    if (i0 + j < nblk) block_sum[i0 + j] = off;
+    off += v[j];
+  }
+  if (threadIdx.x == 0) chunk_sum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the chunk totals (in place) in one block; the grand
+// total goes to n_samples and ray_off[R].
+__global__ void __launch_bounds__(1024) march_scan_top(int64_t *chunk_sum, int64_t nchunk, int64_t *ray_off,
+                                                       int64_t R, int64_t *n_samples) {
+  __shared__ int64_t wsum[1024 / kWave];
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nchunk; c0 += 1024) {
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t v = i < nchunk ? chunk_sum[i] : 0;
+    int64_t total;
+    const int64_t off = block_exclusive_scan(v, wsum, &total);
+    if (i < nchunk) chunk_sum[i] = carry + off;
+    carry += total;
   }
   if (threadIdx.x == 0) {
     n_samples[0] = carry;
@@ -164,51 +223,74 @@ __global__ void __launch_bounds__(1024) march_scan(int64_t *block_sum, int64_t n
 }
 
 __global__ void __launch_bounds__(kBlock) march_fill(const float *ro, const float *rd, int64_t R,
-                                                     const uint32_t *bits, int G, Box box, int max_steps,
-                                                     const int64_t *block_off, int64_t *ray_off,
-                                                     const float *ray_dt, float *xs, float *ts, int32_t *ray_id,
-                                                     int64_t cap) {
+                                                     const uint64_t *masks, int nw, const float *ray_tn,
+                                                     const int64_t *block_off, const int64_t *chunk_off,
+                                                     int64_t *ray_off, const float *ray_dt, float *xs, float *ts,
+                                                     int32_t *ray_id, int64_t cap) {
+#pragma clang fp contract(off)
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t r = (int64_t)blockIdx.x * kRays + wid;
   if (r >= R) return;
-  int64_t off = ray_off[r] + block_off[blockIdx.x];
+  int64_t off = ray_off[r] + block_off[blockIdx.x] + chunk_off[blockIdx.x / kScanChunk];
   __builtin_amdgcn_wave_barrier();
   if (lane == 0) ray_off[r] = off;
   float o[3], d[3];
   load_ray(ro, rd, r, o, d);
-  RaySpan s = ray_span(o, d, box, ray_dt[r], 0);
-  if (!s.hit) return;
-  s.dt = ray_dt[r];
+  const float tn = ray_tn[r], dt = ray_dt[r];
+  const uint64_t *mr = masks + r * nw;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  for (int k0 = 0; k0 < max_steps; k0 += kWave) {
-    const int k = k0 + lane;
-    float t = 0.0f, x[3];
-    bool keep = false, inside = false;
-    if (k < max_steps) {
-      keep = sample_at(o, d, s, k, box, bits, G, &t, x);
-      inside = t < s.tf;
-      keep = keep && inside;
-    }
-    const uint64_t m = __ballot(keep);
-    if (keep) {
+  for (int w = 0; w < nw; ++w) {
+    const uint64_t m = mr[w];
+    if (m == 0ull) continue;
+    if ((m >> lane) & 1ull) {
+      // the count kernel's expressions for t and x (see sample_at)
+      const float t = tn + ((float)(w * kWave + lane) + 0.5f) * dt;
       const int64_t at = off + __popcll(m & below);
       if (at < cap) {
-        xs[at] = x[0];
-        xs[cap + at] = x[1];
-        xs[2 * cap + at] = x[2];
+        xs[at] = o[0] + t * d[0];
+        xs[cap + at] = o[1] + t * d[1];
+        xs[2 * cap + at] = o[2] + t * d[2];
         ts[at] = t;
         ray_id[at] = (int32_t)r;
       }
     }
     off += __popcll(m);
-    if (!__shfl((int)inside, kWave - 1, kWave)) break;
   }
 }
 
 }  // namespace
 
-extern "C" size_t ia355_march_workspace_size(int64_t R) {
-  return align256(sizeof(int64_t) * (size_t)(ceil_div(R > 0 ? R : 1, kRays)));
+// Workspace: block totals, chunk totals, keep masks [R][ceil(max_steps/64)]
+// and entry distances [R], each slice 256-byte aligned.
+struct MarchWs {
+  int64_t *block_sum, *chunk_sum;
+  uint64_t *masks;
+  float *tn;
+  size_t bytes;
+};
+
+static MarchWs march_ws(void *base, int64_t R, int32_t max_steps) {
+  const int64_t Rp = R > 0 ? R : 1;
+  const int64_t nblk = ceil_div(Rp, kRays);
+  const int64_t nw = ceil_div(max_steps > 0 ? max_steps : 1, kWave);
+  char *p = (char *)base;
+  MarchWs w;
+  size_t o = 0;
+  w.block_sum = (int64_t *)(p + o);
+  o += align256(sizeof(int64_t) * (size_t)nblk);
+  w.chunk_sum = (int64_t *)(p + o);
+  o += align256(sizeof(int64_t) * (size_t)ceil_div(nblk, kScanChunk));
+  w.masks = (uint64_t *)(p + o);
+  o += align256(sizeof(uint64_t) * (size_t)(Rp * nw));
+  w.tn = (float *)(p + o);
+  o += align256(sizeof(float) * (size_t)Rp);
+  w.bytes = o;
+  return w;
+}
+
+extern "C" size_t ia355_march_workspace_size(int64_t R, int32_t max_steps) {
+  if (R < 0 || max_steps < 0) return 0;
+  return march_ws(nullptr, R, max_steps).bytes;
 }
 
 extern "C" int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d, int64_t R, const uint32_t *occ_bits,
@@ -223,22 +305,40 @@ extern "C" int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d,
   if (occ_bits && (G <= 0 || G > 2048)) return IA355_ERR_INVALID_ARG;
   if (n_per_ray <= 0 && !(dt > 0.0f)) return IA355_ERR_INVALID_ARG;
   if ((int64_t)cap * 3 < cap) return IA355_ERR_INVALID_ARG;
-  if (ws_bytes < ia355_march_workspace_size(R) || !ws) return IA355_ERR_WORKSPACE;
+  if (!ws || ws_bytes < ia355_march_workspace_size(R, max_steps)) return IA355_ERR_WORKSPACE;
   Box box;
   for (int a = 0; a < 3; ++a) {
     box.lo[a] = aabb[a];
     box.hi[a] = aabb[3 + a];
     if (!(box.hi[a] > box.lo[a])) return IA355_ERR_INVALID_ARG;
   }
+  bool pow2 = true;
+  for (int a = 0; a < 3; ++a) {
+    const float ext = box.hi[a] - box.lo[a];
+    int e;
+    pow2 = pow2 && std::isfinite(ext) && std::frexp(ext, &e) == 0.5f && e > -100 && e < 100;
+    box.inv_ext[a] = pow2 ? 1.0f / ext : 0.0f;
+  }
   hipStream_t s = as_stream(stream);
-  int64_t *block_sum = (int64_t *)ws;
   const int64_t nblk = ceil_div(R, kRays);
-  if (R > 0)
-    march_count<<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray, max_steps,
-                                                  ray_off, ray_cnt, ray_dt, block_sum);
-  march_scan<<<1, 1024, 0, s>>>(block_sum, nblk, ray_off, R, n_samples);
+  const int64_t nchunk = ceil_div(nblk, kScanChunk);
+  const int nw = (int)ceil_div(max_steps, kWave);
+  const MarchWs mw = march_ws(ws, R, max_steps);
+  int64_t *block_sum = mw.block_sum, *chunk_sum = mw.chunk_sum;
+  if (R > 0) {
+    if (pow2)
+      march_count<true><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray,
+                                                          max_steps, ray_off, ray_cnt, ray_dt, block_sum,
+                                                          mw.masks, nw, mw.tn);
+    else
+      march_count<false><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray,
+                                                           max_steps, ray_off, ray_cnt, ray_dt, block_sum,
+                                                           mw.masks, nw, mw.tn);
+    march_scan_chunk<<<(unsigned)nchunk, 1024, 0, s>>>(block_sum, nblk, chunk_sum);
+  }
+  march_scan_top<<<1, 1024, 0, s>>>(chunk_sum, nchunk, ray_off, R, n_samples);
   if (R > 0 && cap > 0)
-    march_fill<<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, max_steps, block_sum, ray_off,
-                                                 ray_dt, xs, ts, ray_id, cap);
+    march_fill<<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, mw.masks, nw, mw.tn, block_sum, chunk_sum,
+                                                 ray_off, ray_dt, xs, ts, ray_id, cap);
   return launch_status();
 }

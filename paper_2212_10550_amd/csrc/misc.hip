@@ -43,22 +43,31 @@ extern "C" int32_t ia355_zero(void *p, size_t bytes, ia355_stream_t stream) {
   return launch_status();
 }
 
-__global__ void occ_pack_kernel(const uint8_t *occ, int64_t ncell, uint32_t *bits, int64_t nword) {
+// One thread per output word: 32 cells of one brick (8 along x, 4 along y).
+__global__ void occ_pack_kernel(const uint8_t *occ, int G, uint32_t *bits, int64_t nword) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nword) return;
+  const int64_t nb = (G + 7) / 8;
+  const int64_t brick = w >> 5;
+  const int q = (int)(w & 31);
+  const int x0 = (int)(brick % nb) * 8, y0 = (int)((brick / nb) % nb) * 8 + (q & 1) * 4;
+  const int z = (int)(brick / (nb * nb)) * 16 + (q >> 1);
   uint32_t v = 0;
-  for (int j = 0; j < 32; ++j) {
-    const int64_t c = 32 * w + j;
-    if (c < ncell && occ[c]) v |= 1u << j;
+  if (z < G) {
+    for (int j = 0; j < 32; ++j) {
+      const int x = x0 + (j & 7), y = y0 + (j >> 3);
+      if (x < G && y < G && occ[(int64_t)x + (int64_t)G * ((int64_t)y + (int64_t)G * z)]) v |= 1u << j;
+    }
   }
   bits[w] = v;
 }
 
+extern "C" size_t ia355_occ_words(int32_t G) { return G > 0 && G <= 2048 ? (size_t)occ_words(G) : 0; }
+
 extern "C" int32_t ia355_occ_pack(const uint8_t *occ, int32_t G, uint32_t *bits, ia355_stream_t stream) {
   if (!occ || !bits || G <= 0 || G > 2048) return IA355_ERR_INVALID_ARG;
-  const int64_t ncell = (int64_t)G * G * G;
-  const int64_t nword = ceil_div(ncell, 32);
-  occ_pack_kernel<<<(unsigned)ceil_div(nword, 256), 256, 0, as_stream(stream)>>>(occ, ncell, bits, nword);
+  const int64_t nword = occ_words(G);
+  occ_pack_kernel<<<(unsigned)ceil_div(nword, 256), 256, 0, as_stream(stream)>>>(occ, G, bits, nword);
   return launch_status();
 }
 
@@ -66,11 +75,23 @@ extern "C" int32_t ia355_occ_pack(const uint8_t *occ, int32_t G, uint32_t *bits,
 __global__ void __launch_bounds__(1024) l2_loss_kernel(const float *c, const float *t, int64_t n, float inv,
                                                        float *loss, float *grad) {
   __shared__ float part[1024 / kWave];
+  constexpr int kU = 8;  // elements per thread per round, loads issued together
   float acc = 0.0f;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const float e = c[i] - t[i];
-    acc += e * e;
-    grad[i] = 2.0f * e * inv;
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kU * blockDim.x) {
+    float cv[kU], tv[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int64_t i = i0 + (int64_t)k * blockDim.x;
+      cv[k] = i < n ? c[i] : 0.0f;
+      tv[k] = i < n ? t[i] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int64_t i = i0 + (int64_t)k * blockDim.x;
+      const float e = cv[k] - tv[k];
+      acc += e * e;
+      if (i < n) grad[i] = 2.0f * e * inv;
+    }
   }
   acc = wave_sum(acc);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;

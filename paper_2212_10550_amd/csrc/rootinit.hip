@@ -1,5 +1,5 @@
-// Learned root initialiser for the canonical-correspondence search (this
-// build's addition to the paper's Sec. 3.1 root finding): a small MLP maps
+// Learned root initialiser for the canonical-correspondence search (an
+// addition to the root finding of Sec. 3.1, not in the paper): a small MLP maps
 // (posed point x', pose) to per-bone logits and a canonical offset; the
 // start point handed to Broyden is x0 = B_k^{-1} x' + offset, k = argmax.
 //
@@ -39,10 +39,27 @@ __global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restric
   __shared__ float w1x[H * 3];   // W1[:, :3]
   __shared__ float sBinv[64 * 12];
   __shared__ int sBok[64];
-  for (int n = threadIdx.x; n < H; n += kBlock) {
-    float acc = P[offb1 + n];
-    for (int i = 0; i < 6 * nb; ++i) acc += P[offW1 + n * nin + 3 + i] * pose[i];
-    c1[n] = acc;
+  {
+    // four threads per neuron, each a strided quarter of the pose terms with
+    // four independent partial sums (loads in flight instead of one long
+    // dependent chain), combined across the four lanes
+    static_assert(kBlock == 4 * H, "four threads per hidden neuron");
+    const int n = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const float *wrow = P + offW1 + n * nin + 3;
+    const int np = 6 * nb;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    int i = q;
+    for (; i + 12 < np; i += 16) {
+      a0 += wrow[i] * pose[i];
+      a1 += wrow[i + 4] * pose[i + 4];
+      a2 += wrow[i + 8] * pose[i + 8];
+      a3 += wrow[i + 12] * pose[i + 12];
+    }
+    for (; i < np; i += 4) a0 += wrow[i] * pose[i];
+    float acc = (a0 + a1) + (a2 + a3);
+    acc += __shfl_xor(acc, 1, kWave);
+    acc += __shfl_xor(acc, 2, kWave);
+    if (q == 0) c1[n] = acc + P[offb1 + n];
   }
   for (int e = threadIdx.x; e < H * 3; e += kBlock) w1x[e] = P[offW1 + (e / 3) * nin + (e % 3)];
   stage_bone_inverses(B, nb, sBinv, sBok);

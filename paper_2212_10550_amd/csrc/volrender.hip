@@ -1,8 +1,16 @@
 // Volume rendering (Sec. 3.2, Eq. 8) with early ray termination (Sec. 3.4),
-// forward and backward, one thread per ray walking its compacted samples in
-// order.  alpha_i = -expm1(-sigma_i delta) and T_{i+1} = T_i exp(-sigma_i delta)
-// (the same quantities as 1 - exp(-sigma delta) and T_i (1 - alpha_i),
-// without the cancellation of 1 - exp(.) for small sigma delta).
+// forward and backward.  alpha_i = -expm1(-sigma_i delta) and
+// T_{i+1} = T_i exp(-sigma_i delta) (the same quantities as 1 - exp(-sigma
+// delta) and T_i (1 - alpha_i), without the cancellation of 1 - exp(.) for
+// small sigma delta).
+//
+// A ray is a segment of 16 lanes (four rays per wave) that walks its
+// compacted samples 16 at a time: within a chunk the transmittances are a
+// product scan of exp(-sigma delta) across the lanes (and, backward, the
+// partial colours sum_{j<=i} w_j c_j a sum scan), carried from chunk to
+// chunk.  Densities are non-negative, so T never grows along a ray and the
+// samples kept by the termination test T_i >= T_thresh are a prefix of the
+// chunk; the ray stops at the first chunk that has an unused sample.
 #include "common.h"
 
 using namespace ia355;
@@ -10,38 +18,97 @@ using namespace ia355;
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kSeg = 16;  // lanes per ray
+constexpr int kRaysPerBlock = kBlock / kSeg;
+
+// Inclusive scans over the kSeg lanes of a segment (lane j of the segment
+// gets the product / sum over lanes 0..j).
+__device__ __forceinline__ float seg_scan_mul(float v, int j) {
+#pragma unroll
+  for (int o = 1; o < kSeg; o <<= 1) {
+    const float t = __shfl_up(v, o, kSeg);
+    if (j >= o) v *= t;
+  }
+  return v;
+}
+__device__ __forceinline__ float seg_scan_add(float v, int j) {
+#pragma unroll
+  for (int o = 1; o < kSeg; o <<= 1) {
+    const float t = __shfl_up(v, o, kSeg);
+    if (j >= o) v += t;
+  }
+  return v;
+}
+__device__ __forceinline__ float seg_sum(float v) {
+#pragma unroll
+  for (int o = kSeg / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kSeg);
+  return v;
+}
+
+// Transmittance before each lane's sample: T_in times the product of the
+// lower lanes' factors.  Also returns the product over all kSeg lanes.
+__device__ __forceinline__ float seg_trans(float T_in, float ex, int j, float *chunk_prod) {
+  const float incl = seg_scan_mul(ex, j);
+  const float excl = __shfl_up(incl, 1, kSeg);
+  *chunk_prod = __shfl(incl, kSeg - 1, kSeg);
+  return j == 0 ? T_in : T_in * excl;
+}
+
+// Number of lanes of this segment whose predicate holds (a prefix).
+__device__ __forceinline__ int seg_count(bool p) {
+  const int seg = (threadIdx.x & (kWave - 1)) / kSeg;
+  return __popcll((__ballot(p) >> (kSeg * seg)) & 0xffffull);
+}
 
 __global__ void __launch_bounds__(kBlock) render_fwd(const float *__restrict__ sigma, const float *__restrict__ rgb,
                                                      int64_t ld, const int64_t *__restrict__ ray_off,
                                                      const float *__restrict__ ray_dt, int64_t R, float T_thresh,
                                                      float *__restrict__ color, float *__restrict__ opacity,
                                                      int32_t *__restrict__ n_used, float *__restrict__ T_final) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (r >= R) return;
+  const int j = threadIdx.x % kSeg;
+  const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + threadIdx.x / kSeg;
+  if (r >= R) return;  // whole segments leave together
   // a march that overflowed the sample buffer (count > ld, reported by the
   // march) leaves offsets past ld: those samples were never written
   const int64_t b = min(ray_off[r], ld), e = min(ray_off[r + 1], ld);
   const float dt = ray_dt[r];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, A = 0.0f;
   int used = 0;
-  for (int64_t i = b; i < e; ++i) {
-    if (T < T_thresh) break;
-    const float x = sigma[i] * dt;
-    const float alpha = -expm1f(-x);
-    const float w = T * alpha;
-    C0 += w * rgb[i];
-    C1 += w * rgb[ld + i];
-    C2 += w * rgb[2 * ld + i];
-    A += w;
-    T *= expf(-x);
-    ++used;
+  for (int64_t base = b; base < e; base += kSeg) {
+    const int64_t i = base + j;
+    const bool valid = i < e;
+    const float x = valid ? sigma[i] * dt : 0.0f;
+    float prod;
+    const float Ti = seg_trans(T, valid ? expf(-x) : 1.0f, j, &prod);
+    const bool use = valid && Ti >= T_thresh;
+    if (use) {
+      const float w = Ti * -expm1f(-x);
+      C0 += w * rgb[i];
+      C1 += w * rgb[ld + i];
+      C2 += w * rgb[2 * ld + i];
+      A += w;
+    }
+    const int n = seg_count(use);
+    used += n;
+    const int len = e - base < kSeg ? (int)(e - base) : kSeg;
+    if (n < len) {  // terminated inside this chunk: T of the first unused sample
+      T = __shfl(Ti, n, kSeg);
+      break;
+    }
+    T *= prod;
   }
-  color[3 * r] = C0;
-  color[3 * r + 1] = C1;
-  color[3 * r + 2] = C2;
-  opacity[r] = A;
-  n_used[r] = used;
-  T_final[r] = T;
+  C0 = seg_sum(C0);
+  C1 = seg_sum(C1);
+  C2 = seg_sum(C2);
+  A = seg_sum(A);
+  if (j == 0) {
+    color[3 * r] = C0;
+    color[3 * r + 1] = C1;
+    color[3 * r + 2] = C2;
+    opacity[r] = A;
+    n_used[r] = used;
+    T_final[r] = T;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) render_bwd(const float *__restrict__ gC, const float *__restrict__ gA,
@@ -50,7 +117,8 @@ __global__ void __launch_bounds__(kBlock) render_bwd(const float *__restrict__ g
                                                      const float *__restrict__ ray_dt, const int32_t *__restrict__ n_used,
                                                      const float *__restrict__ color, const float *__restrict__ T_final,
                                                      int64_t R, float *__restrict__ gsig, float *__restrict__ grgb) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int j = threadIdx.x % kSeg;
+  const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + threadIdx.x / kSeg;
   if (r >= R) return;
   const int64_t b = min(ray_off[r], ld), e = min(ray_off[r + 1], ld), u = min(b + n_used[r], e);
   const float dt = ray_dt[r];
@@ -58,29 +126,42 @@ __global__ void __launch_bounds__(kBlock) render_bwd(const float *__restrict__ g
   const float ga = gA ? gA[r] : 0.0f;
   const float Cc0 = color[3 * r], Cc1 = color[3 * r + 1], Cc2 = color[3 * r + 2];
   const float tail = ga * dt * T_final[r];
-  float T = 1.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
-  for (int64_t i = b; i < u; ++i) {
-    const float x = sigma[i] * dt;
-    const float alpha = -expm1f(-x);
-    const float w = T * alpha;
-    const float c0 = rgb[i], c1 = rgb[ld + i], c2 = rgb[2 * ld + i];
-    P0 += w * c0;
-    P1 += w * c1;
-    P2 += w * c2;
-    const float Tn = T * expf(-x);
-    const float gc = g0 * c0 + g1 * c1 + g2 * c2;
-    const float after = g0 * (Cc0 - P0) + g1 * (Cc1 - P1) + g2 * (Cc2 - P2);
-    gsig[i] = dt * (Tn * gc - after) + tail;
-    grgb[i] = w * g0;
-    grgb[ld + i] = w * g1;
-    grgb[2 * ld + i] = w * g2;
-    T = Tn;
-  }
-  for (int64_t i = u; i < e; ++i) {
-    gsig[i] = 0.0f;
-    grgb[i] = 0.0f;
-    grgb[ld + i] = 0.0f;
-    grgb[2 * ld + i] = 0.0f;
+  float T = 1.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;  // carried into each chunk
+  for (int64_t base = b; base < e; base += kSeg) {
+    const int64_t i = base + j;
+    const bool use = i < u;
+    float x = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    if (use) {
+      x = sigma[i] * dt;
+      c0 = rgb[i];
+      c1 = rgb[ld + i];
+      c2 = rgb[2 * ld + i];
+    }
+    const float ex = use ? expf(-x) : 1.0f;
+    float prod;
+    const float Ti = seg_trans(T, ex, j, &prod);
+    const float w = use ? Ti * -expm1f(-x) : 0.0f;
+    const float Q0 = P0 + seg_scan_add(w * c0, j), Q1 = P1 + seg_scan_add(w * c1, j),
+                Q2 = P2 + seg_scan_add(w * c2, j);  // sum over samples up to and including i
+    if (i < e) {
+      if (use) {
+        const float gc = g0 * c0 + g1 * c1 + g2 * c2;
+        const float after = g0 * (Cc0 - Q0) + g1 * (Cc1 - Q1) + g2 * (Cc2 - Q2);
+        gsig[i] = dt * (Ti * ex * gc - after) + tail;
+        grgb[i] = w * g0;
+        grgb[ld + i] = w * g1;
+        grgb[2 * ld + i] = w * g2;
+      } else {
+        gsig[i] = 0.0f;
+        grgb[i] = 0.0f;
+        grgb[ld + i] = 0.0f;
+        grgb[2 * ld + i] = 0.0f;
+      }
+    }
+    T *= prod;
+    P0 = __shfl(Q0, kSeg - 1, kSeg);
+    P1 = __shfl(Q1, kSeg - 1, kSeg);
+    P2 = __shfl(Q2, kSeg - 1, kSeg);
   }
 }
 
@@ -93,8 +174,8 @@ extern "C" int32_t ia355_volrender_fwd(const float *sigma, const float *rgb, int
   if (R == 0) return IA355_OK;
   if (!ray_off || !ray_dt || !color || !opacity || !n_used || !T_final) return IA355_ERR_INVALID_ARG;
   if (ld > 0 && (!sigma || !rgb)) return IA355_ERR_INVALID_ARG;
-  render_fwd<<<(unsigned)ceil_div(R, kBlock), kBlock, 0, as_stream(stream)>>>(sigma, rgb, ld, ray_off, ray_dt, R,
-                                                                              T_thresh, color, opacity, n_used, T_final);
+  render_fwd<<<(unsigned)ceil_div(R, kRaysPerBlock), kBlock, 0, as_stream(stream)>>>(
+      sigma, rgb, ld, ray_off, ray_dt, R, T_thresh, color, opacity, n_used, T_final);
   return launch_status();
 }
 
@@ -106,8 +187,7 @@ extern "C" int32_t ia355_volrender_bwd(const float *grad_color, const float *gra
   if (R == 0) return IA355_OK;
   if (!grad_color || !ray_off || !ray_dt || !n_used || !color || !T_final) return IA355_ERR_INVALID_ARG;
   if (ld > 0 && (!sigma || !rgb || !grad_sigma || !grad_rgb)) return IA355_ERR_INVALID_ARG;
-  render_bwd<<<(unsigned)ceil_div(R, kBlock), kBlock, 0, as_stream(stream)>>>(grad_color, grad_opacity, sigma, rgb, ld,
-                                                                              ray_off, ray_dt, n_used, color, T_final,
-                                                                              R, grad_sigma, grad_rgb);
+  render_bwd<<<(unsigned)ceil_div(R, kRaysPerBlock), kBlock, 0, as_stream(stream)>>>(
+      grad_color, grad_opacity, sigma, rgb, ld, ray_off, ray_dt, n_used, color, T_final, R, grad_sigma, grad_rgb);
   return launch_status();
 }

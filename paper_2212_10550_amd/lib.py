@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libia355.so")
 
 F32, F16, BF16 = 0, 1, 2
 OVERWRITE = 1  # backward flag: write gradients instead of adding to them
+TABLE_COARSE = 2  # hash-table gradient: only the coarse dense levels
+TABLE_FINE = 4  # hash-table gradient: only the other levels
 _DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 
 _vp = ctypes.c_void_p
@@ -33,8 +35,9 @@ _SIGS = {
     "version": (_i32, []),
     "error_string": (ctypes.c_char_p, [_i32]),
     "zero": (_i32, [_vp, _sz, _vp]),
+    "occ_words": (_sz, [_i32]),
     "occ_pack": (_i32, [_vp, _i32, _vp, _vp]),
-    "march_workspace_size": (_sz, [_i64]),
+    "march_workspace_size": (_sz, [_i64, _i32]),
     "occgrid_march": (_i32, [_vp, _vp, _i64, _vp, _i32, _fp, _f, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
                              _vp, _vp, _sz, _vp]),
     "deform_workspace_size": (_sz, [_i32, _i32, _i32]),
@@ -112,14 +115,22 @@ def zero(t):
     _check(lib().ia355_zero(_p(t), t.numel() * t.element_size(), _stream()), "zero")
 
 
+def occ_words(G):
+    """int32 words of a packed G^3 occupancy grid."""
+    return lib().ia355_occ_words(G)
+
+
 def occ_pack(occ_u8, bits):
     G = occ_u8.shape[0]
+    if tuple(occ_u8.shape) != (G, G, G) or bits.numel() < occ_words(G):
+        raise ValueError(f"occ_pack: grid {tuple(occ_u8.shape)} / bits {bits.numel()} words "
+                         f"(need a cube and {occ_words(G)} words)")
     _check(lib().ia355_occ_pack(_p(occ_u8, torch.uint8, "occ"), G, _p(bits, torch.int32, "bits"), _stream()),
            "occ_pack")
 
 
-def march_workspace_size(R):
-    return lib().ia355_march_workspace_size(R)
+def march_workspace_size(R, max_steps):
+    return lib().ia355_march_workspace_size(R, max_steps)
 
 
 def occgrid_march(rays_o, rays_d, occ_bits, G, aabb, dt, n_per_ray, max_steps, xs, ts, ray_id, cap, ray_off,

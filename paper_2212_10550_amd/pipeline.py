@@ -59,7 +59,10 @@ class Pipeline:
         self.w = w
         self.device_count = device_count
         self.graph, self.graph_kind = None, None
-        self.side = torch.cuda.Stream(device=torch.device(device))  # default priority
+        # side streams of the backward (default priority): the coarse and the
+        # fine levels of the table gradient
+        self.side = torch.cuda.Stream(device=torch.device(device))
+        self.side2 = torch.cuda.Stream(device=torch.device(device))
         self._table_zeroed = False
         self.dev = torch.device(device)
         dev = self.dev
@@ -72,7 +75,7 @@ class Pipeline:
         if w.occ is not None:
             self.G = w.occ.shape[0]
             occ = t(w.occ, torch.uint8)
-            self.occ_bits = torch.empty((self.G ** 3 + 31) // 32, dtype=torch.int32, device=dev)
+            self.occ_bits = torch.empty(K.occ_words(self.G), dtype=torch.int32, device=dev)
             K.occ_pack(occ, self.occ_bits)
         self.B = t(w.B, torch.float32)
         self.W = t(w.W, torch.float32)
@@ -94,7 +97,7 @@ class Pipeline:
         self.ray_cnt = e(self.R, dt=torch.int32)
         self.ray_dt = e(self.R)
         self.n_samples = e(1, dt=torch.int64)
-        self.ws_march = e(K.march_workspace_size(self.R), dt=torch.uint8)
+        self.ws_march = e(K.march_workspace_size(self.R, w.max_steps), dt=torch.uint8)
         # deform
         Dz, Dy, Dx, nb = w.W.shape
         self.ws_deform = e(K.deform_workspace_size(Dx, Dy, Dz), dt=torch.uint8)
@@ -192,10 +195,13 @@ class Pipeline:
         K.mlp_bwd(self.grad_sigma, self.grad_rgb, self.feat, self.bone, S, self.cap, self.params, self.mlp_dtype,
                   self.grad_params, self.grad_feat, self.ws_mlp, flags=K.OVERWRITE, S_dev=Sd)
 
-    def _table_grad(self, S, Sd, overwrite=True):
+    def _table_grad(self, S, Sd, overwrite=True, group=0):
+        """Table gradient of the level group (K.TABLE_COARSE, K.TABLE_FINE,
+        or 0 for every level)."""
         w = self.w
         K.hashgrid_encode_bwd(self.grad_feat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth,
-                              w.hash_aabb, self.grad_table, None, flags=K.OVERWRITE if overwrite else 0, S_dev=Sd)
+                              w.hash_aabb, self.grad_table, None, flags=(K.OVERWRITE if overwrite else 0) | group,
+                              S_dev=Sd)
 
     def _zero_table_async(self):
         """Clear the table gradient on the side stream (it overlaps the
@@ -225,12 +231,16 @@ class Pipeline:
                    ("deform_bwd", lambda: self._deform_bwd(S, Sd))]
         return st
 
-    def forward(self):
+    def forward(self, zero_table=False):
         """One forward; returns the sample count (None with device counts:
-        read it later with read_count)."""
+        read it later with read_count).  zero_table: fork the clear of the
+        table gradient to the side stream after the march (it then overlaps
+        the root finding)."""
         self._mark("march")
         self.march()
         self._mark(None)
+        if zero_table:
+            self._zero_table_async()
         S, Sd = self._counts()
         for name, fn in self.stages(S, Sd, backward=False):
             self._mark(name)
@@ -241,10 +251,13 @@ class Pipeline:
 
     # ----------------------------------------------------------- backward
     def backward(self, S=None, Sd=None):
-        """Loss, composite and MLP backward, then two independent branches:
-        the hash-table gradient on a side stream, and the position gradient
-        followed by the implicit-function-theorem backward on this stream;
-        the side stream joins back before returning."""
+        """Loss, composite and MLP backward, then three independent branches:
+        the hash-table gradient of the coarse levels and of the fine levels
+        on two side streams (disjoint slices of the table; the coarse levels
+        are bound by contention on few entries, the fine ones by atomic
+        throughput, so they overlap), and the position gradient followed by
+        the implicit-function-theorem backward on this stream; the side
+        streams join back before returning."""
         if S is None:
             S, Sd = self._last
         st = dict(self.stages(S, Sd))
@@ -252,19 +265,31 @@ class Pipeline:
             self._mark(name)
             st[name]()
         if self.timer is not None:  # stage timing: serial, one stage at a time
-            for name in ("hash_bwd_table", "hash_bwd_x", "deform_bwd"):
+            main = torch.cuda.current_stream()
+            ow = not self._table_zeroed
+            if self._table_zeroed:  # the clear was forked to the side stream
+                main.wait_stream(self.side)
+                self._table_zeroed = False
+            self._mark("hash_bwd_table")
+            self._table_grad(S, Sd, overwrite=ow)
+            for name in ("hash_bwd_x", "deform_bwd"):
                 self._mark(name)
                 st[name]()
             self._mark(None)
             return
         main = torch.cuda.current_stream()
         self.side.wait_stream(main)
+        self.side2.wait_stream(self.side)  # after the table clear (if any) and the MLP backward
+        ow = not self._table_zeroed
         with torch.cuda.stream(self.side):
-            self._table_grad(S, Sd, overwrite=not self._table_zeroed)
+            self._table_grad(S, Sd, overwrite=ow, group=K.TABLE_COARSE)
+        with torch.cuda.stream(self.side2):
+            self._table_grad(S, Sd, overwrite=ow, group=K.TABLE_FINE)
         self._table_zeroed = False
         st["hash_bwd_x"]()
         st["deform_bwd"]()
         main.wait_stream(self.side)
+        main.wait_stream(self.side2)
 
     def stage_times(self, n=20, backward=True):
         """GPU ms per stage (device counts): each stage captured in a graph of
@@ -302,16 +327,14 @@ class Pipeline:
         if self.graph is not None and self.graph_kind == "train":
             self.graph.replay()
             return None
-        if self.timer is None:
-            self._zero_table_async()
-        S = self.forward()
+        S = self.forward(zero_table=self.timer is None)
         self.backward()
         return S
 
     def capture_train_step(self):
         """Capture one training step (device counts) in a HIP graph; later
         train_step calls replay it."""
-        self._capture(lambda: (self._zero_table_async(), self.forward(), self.backward()), "train")
+        self._capture(lambda: (self.forward(zero_table=True), self.backward()), "train")
 
     def capture_forward(self):
         """Capture one forward (device counts) in a HIP graph; later

@@ -34,6 +34,7 @@ def test_binding_names_match_header():
 
 def test_workspace_sizes_without_gpu():
     from paper_2212_10550_amd import lib as K
-    assert K.march_workspace_size(291600) >= 8 * (291600 // 256)
+    assert K.march_workspace_size(291600, 128) >= 8 * (291600 // 4) + 16 * 291600 + 4 * 291600
+    assert K.march_workspace_size(0, 0) > 0 and K.march_workspace_size(-1, 128) == 0
     assert K.deform_workspace_size(64, 64, 32) == 12 * 4 * 64 * 64 * 32
     assert K.mlp_bwd_workspace_size(1 << 20) >= 6532 * 4

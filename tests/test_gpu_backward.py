@@ -148,6 +148,32 @@ def test_hash_bwd(orc, log2T, tdt, overwrite, pad):
     assert (host(gx[:, S:]) == 3.0).all()
 
 
+@pytest.mark.parametrize("overwrite", [False, True])
+def test_hash_bwd_level_groups(orc, overwrite):
+    """The coarse and the fine level groups, called separately (as two
+    streams do), give the oracle's table gradient; each call leaves the other
+    group's slice as it was."""
+    K = _K()
+    S, log2T = 5003, 19
+    x = synth.random_points(S, 43)
+    table = synth.make_hash_table(16, 1 << log2T, 2, seed=6, scale=0.3).astype(np.float32)
+    gfeat = np.random.default_rng(9).normal(size=(S, 32)).astype(np.float32)
+    res = orc.resolutions(16)
+    ncoarse = int(np.sum((np.asarray(res) <= 32) & ((np.asarray(res, dtype=np.int64) + 1) ** 3 <= (1 << log2T))))
+    assert 0 < ncoarse < 16
+    start = 7.0 if overwrite else 0.25
+    gt = torch.full((16, 1 << log2T, 2), start, device=dev())
+    args = (feat_dev(gfeat, S), soa(x, S), None, S, S, up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, None)
+    ow = K.OVERWRITE if overwrite else 0
+    K.hashgrid_encode_bwd(*args, ow | K.TABLE_COARSE)
+    torch.cuda.synchronize()
+    assert (host(gt[ncoarse:]) == start).all()
+    K.hashgrid_encode_bwd(*args, ow | K.TABLE_FINE)
+    torch.cuda.synchronize()
+    rt, _ = orc.hash_encode_bwd(gfeat, x, table, res, np.array([0, 0, 0, 1, 1, 1.0]))
+    gclose(host(gt) - (0.0 if overwrite else 0.25), rt, "grad_table (two groups)")
+
+
 def test_deform_bwd(orc):
     K = _K()
     w = synth.train_step()

@@ -50,6 +50,56 @@ def test_march_bit_exact(orc, which):
     np.testing.assert_array_equal(host(p.ray_id[:S]), m["ray_id"])
 
 
+def _unpack_bricks(bits, G):
+    """Host decode of the packed occupancy layout (8 x 8 x 16 bricks, bit
+    lx + 8 ly + 64 lz of a 32-word brick) into a [z][y][x] bool grid."""
+    words = bits.astype(np.uint32)
+    nb, nbz = (G + 7) // 8, (G + 15) // 16
+    out = np.zeros((nbz * 16, nb * 8, nb * 8), dtype=bool)
+    for bz in range(nbz):
+        for by in range(nb):
+            for bx in range(nb):
+                brick = words[32 * (bx + nb * (by + nb * bz)):][:32]
+                cells = ((brick[:, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(-1)  # 1024 bits
+                out[16 * bz:16 * bz + 16, 8 * by:8 * by + 8, 8 * bx:8 * bx + 8] = cells.reshape(16, 8, 8)
+    return out
+
+
+@pytest.mark.parametrize("G", [16, 37, 128])
+def test_occ_pack_brick_layout(G):
+    K = _K()
+    rng = np.random.default_rng(G)
+    occ = (rng.random((G, G, G)) < 0.3).astype(np.uint8)
+    bits = torch.full((K.occ_words(G),), -1, dtype=torch.int32, device=dev())
+    K.occ_pack(torch.as_tensor(occ, device=dev()), bits)
+    full = _unpack_bricks(host(bits), G)
+    np.testing.assert_array_equal(full[:G, :G, :G], occ.astype(bool))
+    assert not full[G:].any() and not full[:, G:].any() and not full[:, :, G:].any()
+
+
+@pytest.mark.parametrize("box", ["unit", "pow2", "general"])
+def test_march_odd_grid_bit_exact(orc, box):
+    """A grid size that leaves partial bricks, enough rays for several scan
+    chunks (4096 blocks of 4 rays each), and grid boxes whose extents are a
+    power of two (cell coordinates by an exact reciprocal) or not (by
+    division)."""
+    w = synth.full_frame()
+    w = synth.ray_subset(w, np.arange(120 * 540, 190 * 540))
+    rng = np.random.default_rng(7)
+    w.occ = (rng.random((37, 37, 37)) < 0.2).astype(np.uint8)
+    if box == "pow2":
+        w.occ_aabb = np.array([-0.5, -0.5, -0.5, 1.5, 1.5, 1.5], np.float32)
+    elif box == "general":
+        w.occ_aabb = np.array([-0.05, -0.02, -0.1, 1.05, 1.0, 1.07], np.float32)
+    p, S = _march_gpu(w)
+    m = orc.march(w.rays_o, w.rays_d, w.occ, w.occ_aabb, w.dt, w.n_per_ray, w.max_steps)
+    assert w.R > 2 * 4 * 4096 and S == m["xs"].shape[0] and S > 0
+    np.testing.assert_array_equal(host(p.ray_off), m["ray_off"])
+    np.testing.assert_array_equal(host(p.ray_cnt), m["ray_cnt"])
+    np.testing.assert_array_equal(p.soa(p.xs), m["xs"])
+    np.testing.assert_array_equal(host(p.ray_id[:S]), m["ray_id"])
+
+
 def test_march_empty_and_capacity(orc):
     w = synth.train_step()
     w0 = synth.ray_subset(w, np.arange(64))

@@ -329,3 +329,49 @@ def train_step(w):
     f.update(loss=loss, grad_color=gC, grad_sigma=gs, grad_rgb=gr, grad_params=gp, grad_feat=gfeat,
              grad_table=gt, grad_xc=gx, grad_xp=gxp, grad_B=gB, grad_W=gW)
     return f
+
+
+# ------------------------------------------- inference occupancy grid
+def lattice_points(G, aabb):
+    """Sample points of the posed-space occupancy grid (Sec. 3.3, inference):
+    the centres of the G^3 cells of ``aabb``, point n = x + G (y + G z) at
+    lo + ((i + 1/2) / G) * (hi - lo) per axis, every operation rounded to
+    IEEE single (the grid decides integers, so both sides use one precision).
+    Returns [G^3, 3] float32."""
+    lo = np.asarray(aabb[:3], np.float32)
+    ext = np.asarray(aabb[3:], np.float32) - lo
+    u = ((np.arange(G, dtype=np.float32) + np.float32(0.5)) / np.float32(G)).astype(np.float32)
+    ax = [(lo[a] + u * ext[a]).astype(np.float32) for a in range(3)]
+    z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(np.float32)
+
+
+def dilate(occ, r):
+    """Occupied cells grown by r cells in every direction (a (2r+1)^3 box,
+    clipped at the grid boundary): out[c] = any occ[c'] with
+    max_a |c_a - c'_a| <= r.  occ: bool [G][G][G]."""
+    occ = np.asarray(occ, bool)
+    out = np.zeros_like(occ)
+    G = occ.shape
+    for dz in range(-r, r + 1):
+        for dy in range(-r, r + 1):
+            for dx in range(-r, r + 1):
+                src = occ[max(dz, 0):G[0] + min(dz, 0), max(dy, 0):G[1] + min(dy, 0), max(dx, 0):G[2] + min(dx, 0)]
+                out[max(-dz, 0):G[0] + min(-dz, 0), max(-dy, 0):G[1] + min(-dy, 0), max(-dx, 0):G[2] + min(-dx, 0)] |= src
+    return out
+
+
+def occgrid_build(G, aabb, B, W, skin_aabb, hash_aabb, table, res, params, widths, sigma_thresh, r, max_iter=10,
+                  tol_stop=1e-6, tol_valid=1e-5):
+    """Per-pose occupancy grid for rendering (Sec. 3.3, inference): the
+    lattice points are mapped to canonical space (the multi-init root of
+    Sec. 3.1, no root -> density 0), their density is queried (hash encoding
+    and MLP, Eq. 1-2), thresholded (sigma > sigma_thresh) and the occupied
+    region is dilated by r cells.  Returns points, deform, sigma [G^3], occ
+    and the dilated grid, both bool [G][G][G] (z, y, x)."""
+    pts = lattice_points(G, aabb)
+    d = deform(pts, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid)
+    feat = hash_encode(d["xc"], table, res, hash_aabb, valid=d["bone"])
+    sigma, _ = mlp_fwd(feat, params, widths, valid=d["bone"])
+    occ = (sigma > sigma_thresh).reshape(G, G, G)
+    return dict(points=pts, deform=d, sigma=sigma, occ=occ, grid=dilate(occ, r))

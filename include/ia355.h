@@ -119,6 +119,37 @@ int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d, int64_t R,
                             int64_t *ray_off, int32_t *ray_cnt, float *ray_dt, int64_t *n_samples,
                             void *ws, size_t ws_bytes, ia355_stream_t stream);
 
+/* Occupancy from densities: cell c of the G^3 grid (c = x + G (y + G z) in
+ * sigma [G^3]) is occupied when some cell within `dilate` cells of it
+ * (Chebyshev distance, clipped at the grid) has sigma > sigma_thresh
+ * (Sec. 3.3: thresholded densities, occupied region dilated).  Writes the
+ * packed bits [ia355_occ_words(G)] in the layout of ia355_occ_pack.
+ * 0 <= dilate <= 4. */
+int32_t ia355_occ_from_density(const float *sigma, int32_t G, float sigma_thresh, int32_t dilate,
+                               uint32_t *occ_bits, ia355_stream_t stream);
+
+/* Per-pose occupancy grid for rendering (Sec. 3.3, inference stage).  The
+ * cell centres of a G^3 lattice over the posed box `aabb` (point
+ * n = x + G (y + G z) at lo + ((i + 1/2) / G) (hi - lo), IEEE single, no
+ * fused operations) are mapped to canonical space exactly as by
+ * ia355_snarf_deform (same arguments), their density is taken from the
+ * canonical field as by ia355_hashgrid_encode + ia355_mlp_fwd (table_dtype
+ * IA355_F32 / IA355_F16; mlp_dtype IA355_F32 with FP32 features or
+ * IA355_BF16 with BF16 features), a point without a valid root has density
+ * 0, and occ_bits are made by ia355_occ_from_density.
+ *   sigma [G^3]  lattice densities (nullable)
+ *   ws: ia355_occgrid_build_workspace_size(G, L, F, mlp_dtype, Dx, Dy, Dz)
+ *   bytes (0 unless 0 < G <= 256). */
+size_t ia355_occgrid_build_workspace_size(int32_t G, int32_t L, int32_t F, int32_t mlp_dtype,
+                                          int32_t Dx, int32_t Dy, int32_t Dz);
+int32_t ia355_occgrid_build(int32_t G, const float *aabb, const float *B, int32_t nb, const float *W,
+                            int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
+                            const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
+                            const void *table, int32_t table_dtype, int32_t L, int32_t F, int32_t log2T,
+                            double base_res, double growth, const float *params, int32_t mlp_dtype,
+                            float sigma_thresh, int32_t dilate, uint32_t *occ_bits, float *sigma,
+                            void *ws, size_t ws_bytes, ia355_stream_t stream);
+
 /* ------------------------------------------------------------------ */
 /* Articulation (Sec. 3.1, Eq. 5-7): canonical correspondences x* of    */
 /* posed points x' as roots of x' = sum_i w_i(x) B_i x, by multi-init   */

@@ -1,0 +1,154 @@
+// Per-pose occupancy grid for rendering (Sec. 3.3, inference stage): the
+// centres of a G^3 lattice in posed space are mapped to canonical space by
+// the multi-init root finding (Sec. 3.1), their densities are queried from
+// the canonical field (hash encoding and MLP, Eq. 1-2; a point without a
+// valid root has density 0), thresholded, and the occupied region is
+// dilated so that the coarse lattice does not clip the subject.  The result
+// is the packed occupancy bitfield the march reads.
+//
+// The lattice, deform, encode and MLP steps reuse the library's stages on
+// one lattice point per sample; the threshold, the dilation and the packing
+// are one kernel with a thread per output word.
+#include "common.h"
+
+using namespace ia355;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxDilate = 4;
+
+// Cell centres, point n = x + G (y + G z): lo + ((i + 1/2) / G) ext per axis,
+// each operation rounded once (the oracle evaluates the same expression in
+// IEEE single).
+__global__ void __launch_bounds__(kBlock) lattice_kernel(int G, float lo0, float lo1, float lo2, float ext0,
+                                                         float ext1, float ext2, int64_t N, float *__restrict__ xp) {
+#pragma clang fp contract(off)
+  const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (n >= N) return;
+  const int ix = (int)(n % G), iy = (int)((n / G) % G), iz = (int)(n / ((int64_t)G * G));
+  const float g = (float)G;
+  xp[n] = lo0 + (((float)ix + 0.5f) / g) * ext0;
+  xp[N + n] = lo1 + (((float)iy + 0.5f) / g) * ext1;
+  xp[2 * N + n] = lo2 + (((float)iz + 0.5f) / g) * ext2;
+}
+
+// One thread per output word of the brick layout (32 cells: 8 along x, 4
+// along y); a cell is occupied when any density within r cells (Chebyshev
+// distance, clipped at the grid) exceeds the threshold.
+__global__ void __launch_bounds__(kBlock) occ_from_density_kernel(const float *__restrict__ sigma, int G,
+                                                                  float thresh, int r, uint32_t *__restrict__ bits,
+                                                                  int64_t nword) {
+  const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (w >= nword) return;
+  const int64_t nb = (G + 7) / 8;
+  const int64_t brick = w >> 5;
+  const int q = (int)(w & 31);
+  const int x0 = (int)(brick % nb) * 8, y0 = (int)((brick / nb) % nb) * 8 + (q & 1) * 4;
+  const int z = (int)(brick / (nb * nb)) * 16 + (q >> 1);
+  uint32_t v = 0;
+  if (z < G) {
+    const int z0 = z - r < 0 ? 0 : z - r, z1 = z + r > G - 1 ? G - 1 : z + r;
+    for (int j = 0; j < 32; ++j) {
+      const int x = x0 + (j & 7), y = y0 + (j >> 3);
+      if (x >= G || y >= G) continue;
+      const int xa = x - r < 0 ? 0 : x - r, xb = x + r > G - 1 ? G - 1 : x + r;
+      const int ya = y - r < 0 ? 0 : y - r, yb = y + r > G - 1 ? G - 1 : y + r;
+      bool occ = false;
+      for (int zz = z0; zz <= z1 && !occ; ++zz)
+        for (int yy = ya; yy <= yb && !occ; ++yy) {
+          const float *row = sigma + ((int64_t)zz * G + yy) * G;
+          for (int xx = xa; xx <= xb; ++xx) occ = occ || row[xx] > thresh;
+        }
+      if (occ) v |= 1u << j;
+    }
+  }
+  bits[w] = v;
+}
+
+struct OccWs {
+  float *xp, *xc, *sigma, *rgb;
+  int16_t *bone;
+  void *feat, *deform_ws;
+  size_t deform_bytes, bytes;
+};
+
+OccWs occ_ws(void *base, int32_t G, int32_t L, int32_t F, int32_t mlp_dtype, int32_t Dx, int32_t Dy, int32_t Dz) {
+  const size_t N = (size_t)G * G * G;
+  const size_t fbytes = mlp_dtype == IA355_F32 ? 4 : 2;
+  char *p = (char *)base;
+  size_t o = 0;
+  OccWs w;
+  w.xp = (float *)(p + o);
+  o += align256(12 * N);
+  w.xc = (float *)(p + o);
+  o += align256(12 * N);
+  w.sigma = (float *)(p + o);
+  o += align256(4 * N);
+  w.rgb = (float *)(p + o);
+  o += align256(12 * N);
+  w.bone = (int16_t *)(p + o);
+  o += align256(2 * N);
+  w.feat = (void *)(p + o);
+  o += align256(fbytes * (size_t)L * (size_t)F * N);
+  w.deform_ws = (void *)(p + o);
+  w.deform_bytes = ia355_deform_workspace_size(Dx, Dy, Dz);
+  o += align256(w.deform_bytes);
+  w.bytes = o;
+  return w;
+}
+
+}  // namespace
+
+extern "C" int32_t ia355_occ_from_density(const float *sigma, int32_t G, float sigma_thresh, int32_t dilate,
+                                          uint32_t *occ_bits, ia355_stream_t stream) {
+  if (G <= 0 || G > 2048 || dilate < 0 || dilate > kMaxDilate || !sigma || !occ_bits) return IA355_ERR_INVALID_ARG;
+  const int64_t nword = occ_words(G);
+  occ_from_density_kernel<<<(unsigned)ceil_div(nword, kBlock), kBlock, 0, as_stream(stream)>>>(
+      sigma, G, sigma_thresh, dilate, occ_bits, nword);
+  return launch_status();
+}
+
+extern "C" size_t ia355_occgrid_build_workspace_size(int32_t G, int32_t L, int32_t F, int32_t mlp_dtype, int32_t Dx,
+                                                     int32_t Dy, int32_t Dz) {
+  if (G <= 0 || G > 256 || L <= 0 || F <= 0) return 0;
+  return occ_ws(nullptr, G, L, F, mlp_dtype, Dx, Dy, Dz).bytes;
+}
+
+extern "C" int32_t ia355_occgrid_build(int32_t G, const float *aabb, const float *B, int32_t nb, const float *W,
+                                       int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
+                                       const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
+                                       const void *table, int32_t table_dtype, int32_t L, int32_t F, int32_t log2T,
+                                       double base_res, double growth, const float *params, int32_t mlp_dtype,
+                                       float sigma_thresh, int32_t dilate, uint32_t *occ_bits, float *sigma,
+                                       void *ws, size_t ws_bytes, ia355_stream_t stream) {
+  if (G <= 0 || G > 256 || !aabb || !occ_bits) return IA355_ERR_INVALID_ARG;
+  if (mlp_dtype != IA355_F32 && mlp_dtype != IA355_BF16) return IA355_ERR_INVALID_ARG;
+  if (dilate < 0 || dilate > kMaxDilate) return IA355_ERR_INVALID_ARG;
+  float lo[3], ext[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = aabb[a];
+    ext[a] = aabb[3 + a] - aabb[a];
+    if (!(ext[a] > 0.0f)) return IA355_ERR_INVALID_ARG;
+  }
+  const size_t need = ia355_occgrid_build_workspace_size(G, L, F, mlp_dtype, Dx, Dy, Dz);
+  if (!ws || need == 0 || ws_bytes < need) return IA355_ERR_WORKSPACE;
+  const OccWs w = occ_ws(ws, G, L, F, mlp_dtype, Dx, Dy, Dz);
+  const int64_t N = (int64_t)G * G * G;
+  float *sig = sigma ? sigma : w.sigma;
+  const int32_t feat_dtype = mlp_dtype == IA355_F32 ? IA355_F32 : IA355_BF16;
+  hipStream_t s = as_stream(stream);
+  lattice_kernel<<<(unsigned)ceil_div(N, kBlock), kBlock, 0, s>>>(G, lo[0], lo[1], lo[2], ext[0], ext[1], ext[2], N,
+                                                                   w.xp);
+  int32_t st = launch_status();
+  if (st != IA355_OK) return st;
+  st = ia355_snarf_deform(w.xp, N, nullptr, N, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter, tol_stop,
+                          tol_valid, w.xc, w.bone, nullptr, nullptr, w.deform_ws, w.deform_bytes, stream);
+  if (st != IA355_OK) return st;
+  st = ia355_hashgrid_encode(w.xc, w.bone, N, nullptr, N, table, table_dtype, L, F, log2T, base_res, growth,
+                             hash_aabb, w.feat, feat_dtype, stream);
+  if (st != IA355_OK) return st;
+  st = ia355_mlp_fwd(w.feat, feat_dtype, w.bone, N, nullptr, N, params, mlp_dtype, sig, w.rgb, stream);
+  if (st != IA355_OK) return st;
+  return ia355_occ_from_density(sig, G, sigma_thresh, dilate, occ_bits, stream);
+}

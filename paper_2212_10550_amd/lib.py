@@ -38,6 +38,10 @@ _SIGS = {
     "occ_words": (_sz, [_i32]),
     "occ_pack": (_i32, [_vp, _i32, _vp, _vp]),
     "march_workspace_size": (_sz, [_i64, _i32]),
+    "occ_from_density": (_i32, [_vp, _i32, _f, _i32, _vp, _vp]),
+    "occgrid_build_workspace_size": (_sz, [_i32, _i32, _i32, _i32, _i32, _i32, _i32]),
+    "occgrid_build": (_i32, [_i32, _fp, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _i32, _i32,
+                             _i32, _i32, _d, _d, _vp, _i32, _f, _i32, _vp, _vp, _vp, _sz, _vp]),
     "occgrid_march": (_i32, [_vp, _vp, _i64, _vp, _i32, _fp, _f, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
                              _vp, _vp, _sz, _vp]),
     "deform_workspace_size": (_sz, [_i32, _i32, _i32]),
@@ -127,6 +131,32 @@ def occ_pack(occ_u8, bits):
                          f"(need a cube and {occ_words(G)} words)")
     _check(lib().ia355_occ_pack(_p(occ_u8, torch.uint8, "occ"), G, _p(bits, torch.int32, "bits"), _stream()),
            "occ_pack")
+
+
+def occ_from_density(sigma, G, sigma_thresh, dilate, bits):
+    if sigma.numel() < G ** 3 or bits.numel() < occ_words(G):
+        raise ValueError("occ_from_density: sigma needs G^3 values and bits occ_words(G) words")
+    _check(lib().ia355_occ_from_density(_p(sigma, torch.float32, "sigma"), G, float(sigma_thresh), dilate,
+                                        _p(bits, torch.int32, "bits"), _stream()), "occ_from_density")
+
+
+def occgrid_build_workspace_size(G, L, F, mlp_dtype, Dx, Dy, Dz):
+    return lib().ia355_occgrid_build_workspace_size(G, L, F, mlp_dtype, Dx, Dy, Dz)
+
+
+def occgrid_build(G, aabb, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, table, base_res, growth,
+                  params, mlp_dtype, sigma_thresh, dilate, bits, sigma, ws):
+    """Per-pose occupancy grid (Sec. 3.3, inference): see the C header."""
+    Dz, Dy, Dx, nb = W.shape
+    L, T, F = table.shape
+    if bits.numel() < occ_words(G) or (sigma is not None and sigma.numel() < G ** 3):
+        raise ValueError("occgrid_build: bits need occ_words(G) words, sigma G^3 values")
+    _check(lib().ia355_occgrid_build(
+        G, _box(aabb), _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"), Dx, Dy, Dz, _box(skin_aabb),
+        _box(hash_aabb), max_iter, tol_stop, tol_valid, _p(table, name="table"), _DT[table.dtype], L, F,
+        T.bit_length() - 1, base_res, growth, _p(params, torch.float32, "params"), mlp_dtype, float(sigma_thresh),
+        dilate, _p(bits, torch.int32, "bits"), _p(sigma, torch.float32, "sigma"), _p(ws, name="ws"),
+        ws.numel() * ws.element_size(), _stream()), "occgrid_build")
 
 
 def march_workspace_size(R, max_steps):

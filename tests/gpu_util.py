@@ -55,3 +55,18 @@ def assert_mixed(got, ref, tol, what="", scale=1.0):
         raise AssertionError(f"{what}: max mixed error {err.max():.3e} > {tol:.1e} at {i}: got {got[i]!r} "
                              f"ref {ref[i]!r} ({(err > tol).sum()} of {err.size} elements)")
     return float(err.max()) if err.size else 0.0
+
+
+def unpack_bricks(bits, G):
+    """Host decode of the packed occupancy layout (8 x 8 x 16 bricks, bit
+    lx + 8 ly + 64 lz of a 32-word brick) into a [z][y][x] bool grid."""
+    words = bits.astype(np.uint32)
+    nb, nbz = (G + 7) // 8, (G + 15) // 16
+    out = np.zeros((nbz * 16, nb * 8, nb * 8), dtype=bool)
+    for bz in range(nbz):
+        for by in range(nb):
+            for bx in range(nb):
+                brick = words[32 * (bx + nb * (by + nb * bz)):][:32]
+                cells = ((brick[:, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(-1)  # 1024 bits
+                out[16 * bz:16 * bz + 16, 8 * by:8 * by + 8, 8 * bx:8 * bx + 8] = cells.reshape(16, 8, 8)
+    return out

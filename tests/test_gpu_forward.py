@@ -9,7 +9,7 @@ import torch
 
 from paper_2212_10550_amd import synth
 from tests import indep
-from tests.gpu_util import feat_dev, feat_host, assert_mixed, dev, host, soa, up
+from tests.gpu_util import feat_dev, feat_host, assert_mixed, dev, host, soa, up, unpack_bricks
 
 pytestmark = pytest.mark.gpu
 
@@ -50,21 +50,6 @@ def test_march_bit_exact(orc, which):
     np.testing.assert_array_equal(host(p.ray_id[:S]), m["ray_id"])
 
 
-def _unpack_bricks(bits, G):
-    """Host decode of the packed occupancy layout (8 x 8 x 16 bricks, bit
-    lx + 8 ly + 64 lz of a 32-word brick) into a [z][y][x] bool grid."""
-    words = bits.astype(np.uint32)
-    nb, nbz = (G + 7) // 8, (G + 15) // 16
-    out = np.zeros((nbz * 16, nb * 8, nb * 8), dtype=bool)
-    for bz in range(nbz):
-        for by in range(nb):
-            for bx in range(nb):
-                brick = words[32 * (bx + nb * (by + nb * bz)):][:32]
-                cells = ((brick[:, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(-1)  # 1024 bits
-                out[16 * bz:16 * bz + 16, 8 * by:8 * by + 8, 8 * bx:8 * bx + 8] = cells.reshape(16, 8, 8)
-    return out
-
-
 @pytest.mark.parametrize("G", [16, 37, 128])
 def test_occ_pack_brick_layout(G):
     K = _K()
@@ -72,7 +57,7 @@ def test_occ_pack_brick_layout(G):
     occ = (rng.random((G, G, G)) < 0.3).astype(np.uint8)
     bits = torch.full((K.occ_words(G),), -1, dtype=torch.int32, device=dev())
     K.occ_pack(torch.as_tensor(occ, device=dev()), bits)
-    full = _unpack_bricks(host(bits), G)
+    full = unpack_bricks(host(bits), G)
     np.testing.assert_array_equal(full[:G, :G, :G], occ.astype(bool))
     assert not full[G:].any() and not full[:, G:].any() and not full[:, :, G:].any()
 

@@ -80,7 +80,7 @@ STAGE_KERNELS = {
     "loss+render_bwd": ["l2_loss_kernel", "render_bwd"],
     "mlp_bwd": ["mlp_bwd_f32", "mlp_bwd_bf16", "reduce_partials"],
     "hash_bwd_table": ["table_grad_kernel", "table_grad_dense_kernel"],
-    "hash_bwd_x": ["encode_bwd_kernel"],
+    "hash_bwd_x": ["xgrad_level_kernel", "xgrad_sum_kernel"],
     "deform_bwd": ["ift_v_kernel", "ift_q_kernel", "ift_contract_kernel", "ift_b_kernel"],
 }
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "training_step_f32_hbm_traffic.md")
@@ -373,6 +373,46 @@ def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
     del table, gt
 
 
+def occgrid_leg(torch, np, K, synth, out):
+    """Per-pose inference occupancy grid (Sec. 3.3) for the 540^2 frame's
+    pose: G = 64 (the paper's lattice) and 128 (the grid the march reads),
+    FP32 with the 24-init solve and FP16 table / BF16 MLP; the paper calls
+    its cost negligible next to rendering a frame."""
+    wf = synth.full_frame()
+    dev = "cuda:0"
+    B = torch.as_tensor(wf.B, device=dev)
+    W = torch.as_tensor(wf.W, device=dev)
+    t32 = torch.as_tensor(wf.table, device=dev)
+    t16 = t32.half()
+    prm = torch.as_tensor(wf.mlp, device=dev)
+    Dz, Dy, Dx, nb = wf.W.shape
+    L, T, F = t32.shape
+    res = {"workload": "540^2 frame pose; lattice of cell centres over the unit box; density threshold 10 "
+                       "(the frame's density bias puts valid roots near 55), dilation 1 cell"}
+    for G in (64, 128):
+        for tag, table, md in (("f32", t32, K.F32), ("f16_bf16", t16, K.BF16)):
+            bits = torch.empty(K.occ_words(G), dtype=torch.int32, device=dev)
+            ws = torch.empty(K.occgrid_build_workspace_size(G, L, F, md, Dx, Dy, Dz), dtype=torch.uint8, device=dev)
+
+            def run():
+                K.occgrid_build(G, wf.occ_aabb, B, W, wf.skin_aabb, wf.hash_aabb, wf.max_iter, wf.tol_stop,
+                                wf.tol_valid, table, wf.base_res, wf.growth, prm, md, 10.0, 1, bits, None, ws)
+
+            run()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(5):
+                run()
+            b.record()
+            torch.cuda.synchronize()
+            occ = int(sum(bin(v & 0xFFFFFFFF).count("1") for v in bits.cpu().tolist()))
+            res[f"G{G}_{tag}"] = {"ms": a.elapsed_time(b) / 5, "lattice_points": G ** 3,
+                                  "occupied_fraction": occ / G ** 3}
+            del ws, bits
+    out["occupancy_grid_build"] = res
+
+
 def batch_leg(args, params, poses, gen_s, torch, np, synth, out):
     """16 poses of one avatar (occupancy 5-25 %, 270^2 / 540^2 / 1080^2) in
     one HIP graph, FP16 table, BF16 MLP, learned root initialiser with
@@ -654,6 +694,8 @@ def main():
         params = frame_leg(args, torch, np, K, synth, Pipeline, out)
         log("learned initialiser on held-out poses")
         learned_init_leg(params, torch, np, K, synth, out)
+        log("occupancy grid construction")
+        occgrid_leg(torch, np, K, synth, out)
         log("tiny forward, skipping on/off, hash stress")
         extra_legs(args, params, torch, np, K, synth, Pipeline, out)
         log("batched render of 16 poses")

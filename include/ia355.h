@@ -254,16 +254,20 @@ int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, int64_t S, c
  *   group's slice; the rest of grad_table is not touched.  Summation order inside a table
  *   entry is not fixed (atomic adds), so the last bits may vary run to run.
  *   grad_xc [3][ld] overwritten with sum_l sum_c (grad w_c)(theta_c . grad_feat_l)
- *   (nullable; needs the table).
+ *   (nullable; needs the table and ws).  The levels are summed in order
+ *   l = 0, 1, ..., so the result does not depend on the schedule.
+ *   ws: ia355_hashgrid_encode_bwd_workspace_size(S, L) bytes (per-level
+ *   partial position gradients); nullable when grad_xc is NULL.
  * The table gradient is added with FP32 global atomics laid out so that each
  * wave instruction touches few cache lines (run aggregation by a segmented
  * wave scan on the coarse dense levels, 16 lanes per sample and level
  * elsewhere). */
+size_t ia355_hashgrid_encode_bwd_workspace_size(int64_t S, int32_t L);
 int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone,
                                   int64_t S, const int64_t *S_dev, int64_t ld, const void *table, int32_t table_dtype,
                                   int32_t L, int32_t F, int32_t log2T, double base_res, double growth,
                                   const float *aabb, float *grad_table, float *grad_xc, uint32_t flags,
-                                  ia355_stream_t stream);
+                                  void *ws, size_t ws_bytes, ia355_stream_t stream);
 
 /* The decoder MLP 32 -> 64 -> 64 -> 4 with ReLU hidden layers; outputs
  * sigma = exp(o_0) (clamped at exp(80)) and c = sigmoid(o_1..3).

@@ -130,8 +130,9 @@ class _Encode(torch.autograd.Function):
         grad_xc = _empty(3, S, like=xc) if ctx.needs_input_grad[0] else None
         grad_table = _empty(*table.shape, like=table) if ctx.needs_input_grad[2] else None
         if grad_xc is not None or grad_table is not None:
+            ws = _empty(K.hashgrid_encode_bwd_workspace_size(S, table.shape[0]), dtype=torch.uint8, like=xc)
             K.hashgrid_encode_bwd(grad_feat.contiguous(), xc, bone, S, S, table, cfg.base_res, cfg.growth, cfg.aabb,
-                                  grad_table, grad_xc, flags=K.OVERWRITE)
+                                  grad_table, grad_xc, flags=K.OVERWRITE, ws=ws)
         return grad_xc, None, grad_table, None
 
 
@@ -201,8 +202,9 @@ class _Field(torch.autograd.Function):
         grad_xc = _empty(3, S, like=xc) if ctx.needs_input_grad[0] else None
         grad_table = _empty(*tshape, like=xc) if ctx.needs_input_grad[2] else None
         if grad_xc is not None or grad_table is not None:
+            ws = _empty(K.hashgrid_encode_bwd_workspace_size(S, tshape[0]), dtype=torch.uint8, like=xc)
             K.hashgrid_encode_bwd(grad_feat, xc, bone, S, S, table_read, hcfg.base_res, hcfg.growth, hcfg.aabb,
-                                  grad_table, grad_xc, flags=K.OVERWRITE)
+                                  grad_table, grad_xc, flags=K.OVERWRITE, ws=ws)
         return (grad_xc, None, grad_table, grad_params if ctx.needs_input_grad[3] else None, None, None, None,
                 None)
 

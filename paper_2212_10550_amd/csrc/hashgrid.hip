@@ -207,50 +207,72 @@ __global__ void __launch_bounds__(kFwdBlock) encode_kernel(const float *__restri
   }
 }
 
+// Position gradient dL/dx = sum_l sum_c (grad w_c) (theta_c . dL/dfeat_l),
+// in two kernels.  The first has the forward's mapping (block b on XCD
+// b % 8, levels b % 8 and b % 8 + 8, one lane per sample): every sample of a
+// level is served by one XCD's L2, so cells shared by samples are fetched
+// once rather than once per XCD; it writes each level's contribution to a
+// workspace part [L][3][S].  The second sums the levels in a fixed order.
 constexpr int kBwdBlock = 256;
+constexpr int kBwdMaxLevels = 16;  // the backward's level limit
 
-// lane = level (low 4 bits) + 16 * sample-in-wave; requires L <= 16.
 template <typename TT>
-__global__ void __launch_bounds__(kBwdBlock) encode_bwd_kernel(
+__global__ void __launch_bounds__(kBwdBlock) xgrad_level_kernel(
     const float *__restrict__ gfeat, const float *__restrict__ xc, const int16_t *__restrict__ bone, int64_t S,
     const int64_t *__restrict__ S_dev, int64_t ld, const TT *__restrict__ table, int L, int log2T, Levels lv, Box box,
-    float *__restrict__ gxc) {
-  const int level = threadIdx.x & 15;
+    float *__restrict__ part, int per_xcd) {
+  const int xcd = blockIdx.x % kXcd;
+  const int slot = blockIdx.x / kXcd;
+  const int level = xcd + kXcd * (slot % per_xcd);
+  if (level >= L) return;
   const int64_t Sn = count_of(S, S_dev);
-  constexpr int kPerBlock = kBwdBlock / 16;
-  // the 16 lanes of a sample share n, so they run the same iterations and
-  // the width-16 shuffles below always see their whole group
-  for (int64_t n = ((int64_t)blockIdx.x * kBwdBlock + threadIdx.x) >> 4; n < Sn; n += (int64_t)gridDim.x * kPerBlock) {
+  const int64_t nslot = gridDim.x / (kXcd * per_xcd);
+  const uint32_t T = 1u << log2T;
+  const TT *tl = table + (int64_t)level * T * 2;
+  float *pl = part + (int64_t)level * 3 * S;
+  for (int64_t chunk = slot / per_xcd; chunk * kBwdBlock < Sn; chunk += nslot) {
+    const int64_t n = chunk * kBwdBlock + threadIdx.x;
+    if (n >= Sn) break;
     float gx[3] = {0.0f, 0.0f, 0.0f};
-    const bool act = level < L && (!bone || bone[n] >= 0);
-    if (act) {
+    if (!bone || bone[n] >= 0) {
       const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
       const float2 g = reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * ld + n];
       Corners c;
-      const uint32_t T = 1u << log2T;
       level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, true);
-      const TT *tl = table + (int64_t)level * T * 2;
       float2 vv[8];
       gather8(tl, c, vv);
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const float2 v = vv[k];
-        const float d = v.x * g.x + v.y * g.y;
+        const float d = vv[k].x * g.x + vv[k].y * g.y;
         gx[0] += c.dw[k][0] * d;
         gx[1] += c.dw[k][1] * d;
         gx[2] += c.dw[k][2] * d;
       }
     }
+    pl[n] = gx[0];
+    pl[S + n] = gx[1];
+    pl[2 * S + n] = gx[2];
+  }
+}
+
+__global__ void __launch_bounds__(kBwdBlock) xgrad_sum_kernel(const float *__restrict__ part, int64_t S,
+                                                              const int64_t *__restrict__ S_dev, int L, int64_t ld,
+                                                              float *__restrict__ gxc) {
+  const int64_t Sn = count_of(S, S_dev);
+  for (int64_t n = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x; n < Sn; n += (int64_t)gridDim.x * kBwdBlock) {
+    // all loads first (independent addresses), then the sums in level order
+    float v[kBwdMaxLevels][3];
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-      gx[0] += __shfl_xor(gx[0], o, 16);
-      gx[1] += __shfl_xor(gx[1], o, 16);
-      gx[2] += __shfl_xor(gx[2], o, 16);
-    }
-    if (level == 0) {
-      gxc[n] = gx[0];
-      gxc[ld + n] = gx[1];
-      gxc[2 * ld + n] = gx[2];
+    for (int l = 0; l < kBwdMaxLevels; ++l)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[l][a] = l < L ? part[((int64_t)l * 3 + a) * S + n] : 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int l = 0; l < kBwdMaxLevels; ++l)
+        if (l < L) acc += v[l][a];
+      gxc[a * ld + n] = acc;
     }
   }
 }
@@ -417,15 +439,22 @@ extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, i
   return launch_status();
 }
 
+extern "C" size_t ia355_hashgrid_encode_bwd_workspace_size(int64_t S, int32_t L) {
+  if (S < 0 || L <= 0) return 0;
+  return align256(sizeof(float) * 3 * (size_t)L * (size_t)(S > 0 ? S : 1));
+}
+
 extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const int16_t *bone, int64_t S,
                                              const int64_t *S_dev, int64_t ld, const void *table, int32_t table_dtype,
                                              int32_t L, int32_t F, int32_t log2T, double base_res, double growth,
                                              const float *aabb, float *grad_table, float *grad_xc, uint32_t flags,
-                                             ia355_stream_t stream) {
+                                             void *ws, size_t ws_bytes, ia355_stream_t stream) {
   if (S < 0 || ld < S || L <= 0 || L > 16 || F != 2 || log2T < 1 || log2T > 30) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_feat || !xc)) return IA355_ERR_INVALID_ARG;
   if (grad_xc && !table) return IA355_ERR_INVALID_ARG;
   if (grad_xc && ((reinterpret_cast<uintptr_t>(table) & 15) != 0 || log2T < 2)) return IA355_ERR_INVALID_ARG;
+  if (grad_xc && S > 0 && (!ws || ws_bytes < ia355_hashgrid_encode_bwd_workspace_size(S, L)))
+    return IA355_ERR_WORKSPACE;
   if (table_dtype != IA355_F32 && table_dtype != IA355_F16) return IA355_ERR_INVALID_ARG;
   const uint32_t known = IA355_OVERWRITE | IA355_TABLE_COARSE | IA355_TABLE_FINE;
   if (flags & ~known) return IA355_ERR_INVALID_ARG;
@@ -462,13 +491,22 @@ extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float
                           0, s>>>(grad_feat, xc, bone, S, S_dev, ld, ndense, L, log2T, lv, box, grad_table);
   }
   if (grad_xc && S > 0) {
-    const unsigned blocks = stride_grid(ceil_div(S * 16, kBwdBlock), dev, 4096);
+    float *part = (float *)ws;
+    const int per_xcd = (L + kXcd - 1) / kXcd;
+    int64_t nslot = ceil_div(S, kBwdBlock);
+    if (dev && nslot > 1024) nslot = 1024;
+    const int64_t blocks = nslot * per_xcd * kXcd;
+    if (blocks > 0x7fffffffLL) return IA355_ERR_INVALID_ARG;
     if (table_dtype == IA355_F32)
-      encode_bwd_kernel<float><<<blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, S_dev, ld, (const float *)table, L,
-                                                            log2T, lv, box, grad_xc);
+      xgrad_level_kernel<float><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, S_dev, ld,
+                                                                       (const float *)table, L, log2T, lv, box, part,
+                                                                       per_xcd);
     else
-      encode_bwd_kernel<__half><<<blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, S_dev, ld, (const __half *)table,
-                                                             L, log2T, lv, box, grad_xc);
+      xgrad_level_kernel<__half><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, S_dev, ld,
+                                                                        (const __half *)table, L, log2T, lv, box,
+                                                                        part, per_xcd);
+    xgrad_sum_kernel<<<stride_grid(ceil_div(S, kBwdBlock), dev, 1024), kBwdBlock, 0, s>>>(part, S, S_dev, L, ld,
+                                                                                           grad_xc);
   }
   return launch_status();
 }

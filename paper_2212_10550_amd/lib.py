@@ -55,8 +55,9 @@ _SIGS = {
     "snarf_deform_guided": (_i32, [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f,
                                    _f, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "hashgrid_encode": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _i32, _vp]),
+    "hashgrid_encode_bwd_workspace_size": (_sz, [_i64, _i32]),
     "hashgrid_encode_bwd": (_i32, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _vp,
-                                   ctypes.c_uint32, _vp]),
+                                   ctypes.c_uint32, _vp, _sz, _vp]),
     "mlp_fwd": (_i32, [_vp, _i32, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _vp, _vp]),
     "mlp_bwd_workspace_size": (_sz, [_i64]),
     "mlp_bwd": (_i32, [_vp, _vp, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _vp, ctypes.c_uint32, _vp, _sz, _vp]),
@@ -238,14 +239,20 @@ def hashgrid_encode(xc, bone, S, ld, table, base_res, growth, aabb, feat, S_dev=
         "hashgrid_encode")
 
 
+def hashgrid_encode_bwd_workspace_size(S, L):
+    return lib().ia355_hashgrid_encode_bwd_workspace_size(S, L)
+
+
 def hashgrid_encode_bwd(grad_feat, xc, bone, S, ld, table, base_res, growth, aabb, grad_table, grad_xc, flags=0,
-                        S_dev=None):
+                        S_dev=None, ws=None):
+    """ws: hashgrid_encode_bwd_workspace_size(S, L) bytes, needed with grad_xc."""
     L, T, F = table.shape
     _check(lib().ia355_hashgrid_encode_bwd(
         _p(grad_feat, torch.float32, "grad_feat"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S,
-        _p(S_dev, torch.int64, "S_dev"), ld, _p(table, name="table"), _DT[table.dtype], L, F, T.bit_length() - 1, base_res, growth, _box(aabb),
-        _p(grad_table, torch.float32, "grad_table"), _p(grad_xc, torch.float32, "grad_xc"), flags, _stream()),
-        "hashgrid_encode_bwd")
+        _p(S_dev, torch.int64, "S_dev"), ld, _p(table, name="table"), _DT[table.dtype], L, F, T.bit_length() - 1,
+        base_res, growth, _box(aabb), _p(grad_table, torch.float32, "grad_table"),
+        _p(grad_xc, torch.float32, "grad_xc"), flags, _p(ws, name="ws"),
+        0 if ws is None else ws.numel() * ws.element_size(), _stream()), "hashgrid_encode_bwd")
 
 
 def mlp_fwd(feat, bone, S, ld, params, dtype, sigma, rgb, S_dev=None):

@@ -124,6 +124,8 @@ class Pipeline:
         self.ws_mlp = e(K.mlp_bwd_workspace_size(cap), dt=torch.uint8)
         self.grad_table = e(*self.table32.shape)
         self.grad_xc = e(3, cap)
+        # per-level partial position gradients (training workloads only)
+        self.ws_xgrad = None if w.target is None else e(K.hashgrid_encode_bwd_workspace_size(cap, L), dt=torch.uint8)
         self.grad_xp = e(3, cap)
         self.grad_B = e(*self.B.shape) if grad_B else None
         self.grad_W = e(*self.W.shape) if grad_W else None
@@ -213,8 +215,11 @@ class Pipeline:
 
     def _x_grad(self, S, Sd):
         w = self.w
+        if self.ws_xgrad is None:
+            self.ws_xgrad = torch.empty(K.hashgrid_encode_bwd_workspace_size(self.cap, w.L), dtype=torch.uint8,
+                                        device=self.dev)
         K.hashgrid_encode_bwd(self.grad_feat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth,
-                              w.hash_aabb, None, self.grad_xc, S_dev=Sd)
+                              w.hash_aabb, None, self.grad_xc, S_dev=Sd, ws=self.ws_xgrad)
 
     def _deform_bwd(self, S, Sd):
         w = self.w

@@ -137,8 +137,9 @@ def test_hash_bwd(orc, log2T, tdt, overwrite, pad):
     bone = np.where(np.arange(S) % 11 == 5, -1, 0).astype(np.int16)
     gt = torch.full((16, 1 << log2T, 2), 7.0 if overwrite else 0.25, device=dev())
     gx = torch.full((3, ld), 3.0, device=dev())
+    ws = torch.empty(K.hashgrid_encode_bwd_workspace_size(S, 16), dtype=torch.uint8, device=dev())
     K.hashgrid_encode_bwd(feat_dev(gfeat, ld), soa(x, ld), up(bone), S, ld,
-                          up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, gx, K.OVERWRITE if overwrite else 0)
+                          up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, gx, K.OVERWRITE if overwrite else 0, ws=ws)
     torch.cuda.synchronize()
     rt, rx = orc.hash_encode_bwd(gfeat, x, table, orc.resolutions(16), np.array([0, 0, 0, 1, 1, 1.0]), valid=bone)
     gclose(host(gt) - (0.0 if overwrite else 0.25), rt, "grad_table")

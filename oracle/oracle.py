@@ -375,3 +375,65 @@ def occgrid_build(G, aabb, B, W, skin_aabb, hash_aabb, table, res, params, width
     sigma, _ = mlp_fwd(feat, params, widths, valid=d["bone"])
     occ = (sigma > sigma_thresh).reshape(G, G, G)
     return dict(points=pts, deform=d, sigma=sigma, occ=occ, grid=dilate(occ, r))
+
+
+# ------------------------------------------- training occupancy grid
+def jittered_points(G, aabb, u):
+    """One point per cell of the G^3 grid of ``aabb`` at a random position
+    inside it (Sec. 3.3, training stage: densities of randomly sampled
+    points): point n = x + G (y + G z) at lo + ((i + u_n) / G) * (hi - lo) per
+    axis with u [3][G^3] in [0, 1) supplied by the caller, every operation
+    in IEEE single.  Returns [G^3, 3] float32."""
+    lo = np.asarray(aabb[:3], np.float32)
+    ext = np.asarray(aabb[3:], np.float32) - lo
+    u = np.asarray(u, np.float32).reshape(3, G ** 3)
+    n = np.arange(G ** 3)
+    idx = [n % G, (n // G) % G, n // (G * G)]
+    out = np.empty((G ** 3, 3), np.float32)
+    g = np.float32(G)
+    for a in range(3):
+        out[:, a] = lo[a] + ((idx[a].astype(np.float32) + u[a]) / g) * ext[a]
+    return out
+
+
+def occgrid_update(values, G, aabb, u, B, W, skin_aabb, hash_aabb, table, res, params, widths, beta, sigma_thresh,
+                   r, max_iter=10, tol_stop=1e-6, tol_valid=1e-5):
+    """One update of the shared training occupancy grid (Sec. 3.3, training
+    stage): densities of one random point per cell in the posed space of
+    the given frame (no root -> 0), a moving average with the grid's
+    current values, v <- beta v + (1 - beta) sigma, then the threshold and
+    dilation of the inference grid.  values: [G^3] float64 (new array
+    returned)."""
+    pts = jittered_points(G, aabb, u)
+    d = deform(pts, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid)
+    feat = hash_encode(d["xc"], table, res, hash_aabb, valid=d["bone"])
+    sigma, _ = mlp_fwd(feat, params, widths, valid=d["bone"])
+    v = beta * np.asarray(values, np.float64) + (1.0 - beta) * sigma
+    occ = (v > sigma_thresh).reshape(G, G, G)
+    return dict(points=pts, deform=d, sigma=sigma, values=v, grid=dilate(occ, r))
+
+
+def point_cells(x, aabb, G):
+    """Cell (x, y, z) of each point of [n, 3] in the G^3 grid of ``aabb``:
+    floor((x - lo) / (hi - lo) * G) clamped to [0, G - 1], every operation in
+    IEEE single (the march's keep test)."""
+    x = np.asarray(x, np.float32)
+    lo = np.asarray(aabb[:3], np.float32)
+    ext = np.asarray(aabb[3:], np.float32) - lo
+    u = ((x - lo) / ext).astype(np.float32) * np.float32(G)
+    return np.clip(np.floor(u).astype(np.int64), 0, G - 1)
+
+
+def density_reg(x, sigma, grid, aabb, lam):
+    """Occupancy-based density regulariser (Sec. 3.4, L_density): the mean
+    over the n points of lam * |sigma| for points in empty cells of the
+    occupancy grid (bool [G][G][G], z-major), 0 elsewhere.  Returns the
+    loss and dL/dsigma."""
+    sigma = np.asarray(sigma, np.float64)
+    n = len(sigma)
+    G = grid.shape[0]
+    c = point_cells(x, aabb, G)
+    empty = ~grid[c[:, 2], c[:, 1], c[:, 0]]
+    loss = lam * np.sum(np.abs(sigma) * empty) / n
+    grad = lam * np.sign(sigma) * empty / n
+    return loss, grad

@@ -81,3 +81,73 @@ def test_occgrid_composition():
     far = orc.occgrid_build(2, (5, 5, 5, 6, 6, 6), B, w.W, w.skin_aabb, w.hash_aabb, table, res, params,
                             w.widths, -1.0, 0)
     assert (far["deform"]["bone"] < 0).all() and (far["sigma"] == 0).all() and far["grid"].all()
+
+
+def test_jittered_points_stay_in_their_cells():
+    G = 7
+    rng = np.random.default_rng(1)
+    u = rng.random((3, G ** 3)).astype(np.float32) * np.float32(0.999)
+    box = (-0.5, 0.0, 1.0, 1.5, 2.0, 1.25)
+    p = orc.jittered_points(G, box, u)
+    c = orc.point_cells(p, box, G)
+    n = np.arange(G ** 3)
+    np.testing.assert_array_equal(c, np.stack([n % G, (n // G) % G, n // (G * G)], 1))
+    # u = 1/2 is the lattice of cell centres
+    np.testing.assert_array_equal(orc.jittered_points(G, box, np.full((3, G ** 3), 0.5, np.float32)),
+                                  orc.lattice_points(G, box))
+
+
+def test_point_cells_closed_forms():
+    box = (0, 0, 0, 1, 1, 1)
+    x = np.array([[0.0, 0.0, 0.0], [0.999, 0.5, 0.25], [1.0, -0.1, 2.0], [0.125, 0.375, 0.875]], np.float32)
+    np.testing.assert_array_equal(orc.point_cells(x, box, 8), [[0, 0, 0], [7, 4, 2], [7, 0, 7], [1, 3, 7]])
+
+
+def test_occgrid_update_moving_average():
+    """beta = 0 is the inference grid at the jittered points; beta = 1
+    keeps the old values; in between, the values are the stated average."""
+    w = synth.tiny_forward()
+    nb = w.B.shape[0]
+    B = np.tile(np.eye(3, 4), (nb, 1, 1))
+    G = 4
+    res = orc.resolutions(w.L, w.base_res, w.growth)
+    params = synth.make_mlp(seed=3)
+    table = synth.make_hash_table(w.L, w.table.shape[1], 2, seed=5, scale=0.3)
+    u = np.random.default_rng(2).random((3, G ** 3)).astype(np.float32)
+    old = np.random.default_rng(3).random(G ** 3) * 2.0
+    box = (0, 0, 0, 1, 1, 1)
+    a = orc.occgrid_update(old, G, box, u, B, w.W, w.skin_aabb, w.hash_aabb, table, res, params, w.widths, 0.0,
+                           0.8, 0)
+    d = orc.deform(a["points"], B, w.W, w.skin_aabb, w.hash_aabb)
+    feat = orc.hash_encode(d["xc"], table, res, w.hash_aabb, valid=d["bone"])
+    sigma, _ = orc.mlp_fwd(feat, params, w.widths, valid=d["bone"])
+    np.testing.assert_array_equal(a["values"], sigma)
+    np.testing.assert_array_equal(a["grid"], (sigma > 0.8).reshape(G, G, G))
+    b = orc.occgrid_update(old, G, box, u, B, w.W, w.skin_aabb, w.hash_aabb, table, res, params, w.widths, 1.0,
+                           0.8, 0)
+    np.testing.assert_array_equal(b["values"], old)
+    c = orc.occgrid_update(old, G, box, u, B, w.W, w.skin_aabb, w.hash_aabb, table, res, params, w.widths, 0.75,
+                           0.8, 1)
+    np.testing.assert_allclose(c["values"], 0.75 * old + 0.25 * sigma, rtol=1e-15)
+    np.testing.assert_array_equal(c["grid"], orc.dilate((c["values"] > 0.8).reshape(G, G, G), 1))
+
+
+def test_density_reg_closed_form():
+    G = 4
+    grid = np.zeros((G, G, G), bool)
+    grid[1, 2, 3] = True  # z = 1, y = 2, x = 3 occupied
+    box = (0, 0, 0, 1, 1, 1)
+    x = np.array([[0.875, 0.625, 0.375],    # cell (3, 2, 1): occupied
+                  [0.125, 0.125, 0.125],    # empty
+                  [0.6, 0.9, 0.1]], np.float32)  # empty
+    sigma = np.array([5.0, 2.0, 0.5])
+    loss, grad = orc.density_reg(x, sigma, grid, box, 0.1)
+    assert abs(loss - 0.1 * (2.0 + 0.5) / 3) < 1e-15
+    np.testing.assert_allclose(grad, [0.0, 0.1 / 3, 0.1 / 3], rtol=1e-15)
+    # finite differences of the loss in sigma
+    eps = 1e-6
+    for i in range(3):
+        s2 = sigma.copy()
+        s2[i] += eps
+        l2, _ = orc.density_reg(x, s2, grid, box, 0.1)
+        assert abs((l2 - loss) / eps - grad[i]) < 1e-8

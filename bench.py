@@ -407,8 +407,41 @@ def occgrid_leg(torch, np, K, synth, out):
             b.record()
             torch.cuda.synchronize()
             occ = int(sum(bin(v & 0xFFFFFFFF).count("1") for v in bits.cpu().tolist()))
-            res[f"G{G}_{tag}"] = {"ms": a.elapsed_time(b) / 5, "lattice_points": G ** 3,
-                                  "occupied_fraction": occ / G ** 3}
+            entry = {"ms": a.elapsed_time(b) / 5, "lattice_points": G ** 3, "occupied_fraction": occ / G ** 3}
+            if tag == "f32":
+                # training stage: one moving-average update of the shared grid
+                # from one jittered point per cell (the jitter drawn on the host)
+                jit = torch.as_tensor(np.random.default_rng(G).random((3, G ** 3), dtype=np.float32) * 0.999,
+                                      device=dev)
+                vals = torch.zeros(G ** 3, device=dev)
+
+                def upd():
+                    K.occgrid_update(G, wf.occ_aabb, jit, B, W, wf.skin_aabb, wf.hash_aabb, wf.max_iter, wf.tol_stop,
+                                     wf.tol_valid, table, wf.base_res, wf.growth, prm, md, 0.95, 10.0, 1, vals, bits,
+                                     ws)
+
+                upd()
+                a.record()
+                for _ in range(5):
+                    upd()
+                b.record()
+                torch.cuda.synchronize()
+                entry["training_update_ms"] = a.elapsed_time(b) / 5
+                # density regulariser over the same number of points
+                sig = torch.rand(G ** 3, device=dev) * 5.0
+                loss = torch.empty(1, device=dev)
+                gs = torch.empty(G ** 3, device=dev)
+                pts = torch.rand(3, G ** 3, device=dev)
+                rws = torch.empty(K.density_reg_workspace_size(G ** 3), dtype=torch.uint8, device=dev)
+                K.density_reg(pts, sig, G ** 3, G ** 3, bits, G, wf.occ_aabb, 0.1, loss, gs, rws)
+                a.record()
+                for _ in range(5):
+                    K.density_reg(pts, sig, G ** 3, G ** 3, bits, G, wf.occ_aabb, 0.1, loss, gs, rws)
+                b.record()
+                torch.cuda.synchronize()
+                entry["density_reg_ms"] = a.elapsed_time(b) / 5
+                del jit, vals, sig, gs, pts
+            res[f"G{G}_{tag}"] = entry
             del ws, bits
     out["occupancy_grid_build"] = res
 

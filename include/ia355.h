@@ -150,6 +150,33 @@ int32_t ia355_occgrid_build(int32_t G, const float *aabb, const float *B, int32_
                             float sigma_thresh, int32_t dilate, uint32_t *occ_bits, float *sigma,
                             void *ws, size_t ws_bytes, ia355_stream_t stream);
 
+/* Training-stage occupancy grid (Sec. 3.3): one update of the grid shared
+ * by all frames.  For the frame given by B, one point per cell at
+ * lo + ((i + u) / G) (hi - lo) with u = jitter [3][G^3] in [0, 1) (the
+ * caller draws it; IEEE single, no fused operations) gets its density as in
+ * ia355_occgrid_build (no root: 0); values [G^3] (FP32, in/out) become
+ * beta * values + (1 - beta) * sigma, and occ_bits are made from values by
+ * ia355_occ_from_density.  0 <= beta <= 1.
+ * ws: ia355_occgrid_build_workspace_size(G, L, F, mlp_dtype, Dx, Dy, Dz). */
+int32_t ia355_occgrid_update(int32_t G, const float *aabb, const float *jitter, const float *B, int32_t nb,
+                             const float *W, int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
+                             const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
+                             const void *table, int32_t table_dtype, int32_t L, int32_t F, int32_t log2T,
+                             double base_res, double growth, const float *params, int32_t mlp_dtype,
+                             float beta, float sigma_thresh, int32_t dilate, float *values,
+                             uint32_t *occ_bits, void *ws, size_t ws_bytes, ia355_stream_t stream);
+
+/* Occupancy-based density regulariser (Sec. 3.4, L_density): with n the
+ * point count, loss[0] = (lam / n) sum |sigma_i| over the points x [3][ld]
+ * whose cell of the grid (occ_bits, layout of ia355_occ_pack, over aabb;
+ * cell as in ia355_occgrid_march) is empty; grad_sigma [S] = dloss/dsigma
+ * (overwritten; 0 for points in occupied cells).  A fixed summation order
+ * for a given S.  ws: ia355_density_reg_workspace_size(S) bytes. */
+size_t ia355_density_reg_workspace_size(int64_t S);
+int32_t ia355_density_reg(const float *x, const float *sigma, int64_t S, const int64_t *S_dev, int64_t ld,
+                          const uint32_t *occ_bits, int32_t G, const float *aabb, float lam,
+                          float *loss, float *grad_sigma, void *ws, size_t ws_bytes, ia355_stream_t stream);
+
 /* ------------------------------------------------------------------ */
 /* Articulation (Sec. 3.1, Eq. 5-7): canonical correspondences x* of    */
 /* posed points x' as roots of x' = sum_i w_i(x) B_i x, by multi-init   */

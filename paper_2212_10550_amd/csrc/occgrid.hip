@@ -9,6 +9,12 @@
 // The lattice, deform, encode and MLP steps reuse the library's stages on
 // one lattice point per sample; the threshold, the dilation and the packing
 // are one kernel with a thread per output word.
+//
+// Training stage (Sec. 3.3): one shared grid, updated every few iterations
+// from the densities of one random point per cell in the posed space of a
+// training frame, as a moving average of the grid's values; and the
+// occupancy-based density regulariser (Sec. 3.4), |sigma| of points that
+// fall in empty cells.
 #include "common.h"
 
 using namespace ia355;
@@ -18,19 +24,98 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kMaxDilate = 4;
 
-// Cell centres, point n = x + G (y + G z): lo + ((i + 1/2) / G) ext per axis,
-// each operation rounded once (the oracle evaluates the same expression in
-// IEEE single).
+// One point per cell, point n = x + G (y + G z): lo + ((i + u) / G) ext per
+// axis with u = 1/2 (cell centres) or u = jitter [3][G^3] in [0, 1), each
+// operation rounded once (the oracle evaluates the same expression in IEEE
+// single).
 __global__ void __launch_bounds__(kBlock) lattice_kernel(int G, float lo0, float lo1, float lo2, float ext0,
-                                                         float ext1, float ext2, int64_t N, float *__restrict__ xp) {
+                                                         float ext1, float ext2, int64_t N,
+                                                         const float *__restrict__ jitter, float *__restrict__ xp) {
 #pragma clang fp contract(off)
   const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n >= N) return;
   const int ix = (int)(n % G), iy = (int)((n / G) % G), iz = (int)(n / ((int64_t)G * G));
   const float g = (float)G;
-  xp[n] = lo0 + (((float)ix + 0.5f) / g) * ext0;
-  xp[N + n] = lo1 + (((float)iy + 0.5f) / g) * ext1;
-  xp[2 * N + n] = lo2 + (((float)iz + 0.5f) / g) * ext2;
+  const float u0 = jitter ? jitter[n] : 0.5f, u1 = jitter ? jitter[N + n] : 0.5f, u2 = jitter ? jitter[2 * N + n] : 0.5f;
+  xp[n] = lo0 + (((float)ix + u0) / g) * ext0;
+  xp[N + n] = lo1 + (((float)iy + u1) / g) * ext1;
+  xp[2 * N + n] = lo2 + (((float)iz + u2) / g) * ext2;
+}
+
+// v <- beta v + (1 - beta) sigma (the moving average of the training grid).
+__global__ void __launch_bounds__(kBlock) ema_kernel(float *__restrict__ v, const float *__restrict__ sigma,
+                                                     float beta, int64_t N) {
+#pragma clang fp contract(off)
+  const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (n >= N) return;
+  v[n] = beta * v[n] + (1.0f - beta) * sigma[n];
+}
+
+// Density regulariser in two kernels with a fixed summation order: a
+// grid-stride pass (the grid depends only on the capacity S) writes dL/dsigma
+// and one partial sum of |sigma| over empty-cell points per workgroup, then
+// one workgroup adds the partials in order.  A point is in an empty cell when
+// its cell's bit is 0 (cell as in the march's keep test, IEEE single without
+// fused operations).
+constexpr int kRegBlock = 256;
+constexpr int kRegMaxBlocks = 1024;
+
+__device__ __forceinline__ float block_sum256(float v, float *part) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  float t = 0.0f;
+  for (int i = 0; i < kRegBlock / kWave; ++i) t += part[i];
+  return t;
+}
+
+__global__ void __launch_bounds__(kRegBlock) density_reg_kernel(const float *__restrict__ x, const float *__restrict__ sigma,
+                                                                int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
+                                                                const uint32_t *__restrict__ bits, int G, float lo0,
+                                                                float lo1, float lo2, float ext0, float ext1, float ext2,
+                                                                float lam, float *__restrict__ grad,
+                                                                float *__restrict__ partial) {
+#pragma clang fp contract(off)
+  __shared__ float part[kRegBlock / kWave];
+  const int64_t n_pts = count_of(S, S_dev);
+  const float inv_n = n_pts > 0 ? 1.0f / (float)n_pts : 0.0f;
+  const float lo[3] = {lo0, lo1, lo2}, ext[3] = {ext0, ext1, ext2};
+  float acc = 0.0f;
+  for (int64_t n = (int64_t)blockIdx.x * kRegBlock + threadIdx.x; n < n_pts; n += (int64_t)gridDim.x * kRegBlock) {
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float u = (x[a * ld + n] - lo[a]) / ext[a] * (float)G;
+      const int i = (int)floorf(u);
+      c[a] = i < 0 ? 0 : (i > G - 1 ? G - 1 : i);
+    }
+    const bool empty = !((bits[occ_word(c[0], c[1], c[2], G)] >> occ_bit(c[0], c[1])) & 1u);
+    const float s = sigma[n];
+    const float sgn = s > 0.0f ? 1.0f : (s < 0.0f ? -1.0f : 0.0f);
+    grad[n] = empty ? lam * sgn * inv_n : 0.0f;
+    if (empty) acc += fabsf(s);
+  }
+  const float t = block_sum256(acc, part);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kRegBlock) density_reg_sum_kernel(const float *__restrict__ partial, int nblk,
+                                                                    int64_t S, const int64_t *__restrict__ S_dev,
+                                                                    float lam, float *__restrict__ loss) {
+  __shared__ float part[kRegBlock / kWave];
+  float acc = 0.0f;
+  for (int i = threadIdx.x; i < nblk; i += kRegBlock) acc += partial[i];
+  const float t = block_sum256(acc, part);
+  if (threadIdx.x == 0) {
+    const int64_t n_pts = count_of(S, S_dev);
+    loss[0] = n_pts > 0 ? lam * t * (1.0f / (float)n_pts) : 0.0f;
+  }
+}
+
+int reg_blocks(int64_t S) {
+  int64_t b = ceil_div(S > 0 ? S : 1, kRegBlock);
+  return (int)(b > kRegMaxBlocks ? kRegMaxBlocks : b);
 }
 
 // One thread per output word of the brick layout (32 cells: 8 along x, 4
@@ -115,16 +200,16 @@ extern "C" size_t ia355_occgrid_build_workspace_size(int32_t G, int32_t L, int32
   return occ_ws(nullptr, G, L, F, mlp_dtype, Dx, Dy, Dz).bytes;
 }
 
-extern "C" int32_t ia355_occgrid_build(int32_t G, const float *aabb, const float *B, int32_t nb, const float *W,
-                                       int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
-                                       const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
-                                       const void *table, int32_t table_dtype, int32_t L, int32_t F, int32_t log2T,
-                                       double base_res, double growth, const float *params, int32_t mlp_dtype,
-                                       float sigma_thresh, int32_t dilate, uint32_t *occ_bits, float *sigma,
-                                       void *ws, size_t ws_bytes, ia355_stream_t stream) {
-  if (G <= 0 || G > 256 || !aabb || !occ_bits) return IA355_ERR_INVALID_ARG;
+// Densities of one point per cell (cell centres, or jittered): lattice,
+// root finding, encoding, MLP.  Writes sig [G^3].
+static int32_t lattice_density(int32_t G, const float *aabb, const float *jitter, const float *B, int32_t nb,
+                               const float *W, int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
+                               const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
+                               const void *table, int32_t table_dtype, int32_t L, int32_t F, int32_t log2T,
+                               double base_res, double growth, const float *params, int32_t mlp_dtype, float *sigma,
+                               void *ws, size_t ws_bytes, ia355_stream_t stream, float **sig_out) {
+  if (G <= 0 || G > 256 || !aabb) return IA355_ERR_INVALID_ARG;
   if (mlp_dtype != IA355_F32 && mlp_dtype != IA355_BF16) return IA355_ERR_INVALID_ARG;
-  if (dilate < 0 || dilate > kMaxDilate) return IA355_ERR_INVALID_ARG;
   float lo[3], ext[3];
   for (int a = 0; a < 3; ++a) {
     lo[a] = aabb[a];
@@ -136,10 +221,11 @@ extern "C" int32_t ia355_occgrid_build(int32_t G, const float *aabb, const float
   const OccWs w = occ_ws(ws, G, L, F, mlp_dtype, Dx, Dy, Dz);
   const int64_t N = (int64_t)G * G * G;
   float *sig = sigma ? sigma : w.sigma;
+  *sig_out = sig;
   const int32_t feat_dtype = mlp_dtype == IA355_F32 ? IA355_F32 : IA355_BF16;
   hipStream_t s = as_stream(stream);
   lattice_kernel<<<(unsigned)ceil_div(N, kBlock), kBlock, 0, s>>>(G, lo[0], lo[1], lo[2], ext[0], ext[1], ext[2], N,
-                                                                   w.xp);
+                                                                   jitter, w.xp);
   int32_t st = launch_status();
   if (st != IA355_OK) return st;
   st = ia355_snarf_deform(w.xp, N, nullptr, N, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter, tol_stop,
@@ -148,7 +234,69 @@ extern "C" int32_t ia355_occgrid_build(int32_t G, const float *aabb, const float
   st = ia355_hashgrid_encode(w.xc, w.bone, N, nullptr, N, table, table_dtype, L, F, log2T, base_res, growth,
                              hash_aabb, w.feat, feat_dtype, stream);
   if (st != IA355_OK) return st;
-  st = ia355_mlp_fwd(w.feat, feat_dtype, w.bone, N, nullptr, N, params, mlp_dtype, sig, w.rgb, stream);
+  return ia355_mlp_fwd(w.feat, feat_dtype, w.bone, N, nullptr, N, params, mlp_dtype, sig, w.rgb, stream);
+}
+
+extern "C" int32_t ia355_occgrid_build(int32_t G, const float *aabb, const float *B, int32_t nb, const float *W,
+                                       int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
+                                       const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
+                                       const void *table, int32_t table_dtype, int32_t L, int32_t F, int32_t log2T,
+                                       double base_res, double growth, const float *params, int32_t mlp_dtype,
+                                       float sigma_thresh, int32_t dilate, uint32_t *occ_bits, float *sigma,
+                                       void *ws, size_t ws_bytes, ia355_stream_t stream) {
+  if (!occ_bits || dilate < 0 || dilate > kMaxDilate) return IA355_ERR_INVALID_ARG;
+  float *sig = nullptr;
+  const int32_t st = lattice_density(G, aabb, nullptr, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter,
+                                     tol_stop, tol_valid, table, table_dtype, L, F, log2T, base_res, growth, params,
+                                     mlp_dtype, sigma, ws, ws_bytes, stream, &sig);
   if (st != IA355_OK) return st;
   return ia355_occ_from_density(sig, G, sigma_thresh, dilate, occ_bits, stream);
+}
+
+extern "C" int32_t ia355_occgrid_update(int32_t G, const float *aabb, const float *jitter, const float *B,
+                                        int32_t nb, const float *W, int32_t Dx, int32_t Dy, int32_t Dz,
+                                        const float *skin_aabb, const float *hash_aabb, int32_t max_iter,
+                                        float tol_stop, float tol_valid, const void *table, int32_t table_dtype,
+                                        int32_t L, int32_t F, int32_t log2T, double base_res, double growth,
+                                        const float *params, int32_t mlp_dtype, float beta, float sigma_thresh,
+                                        int32_t dilate, float *values, uint32_t *occ_bits, void *ws,
+                                        size_t ws_bytes, ia355_stream_t stream) {
+  if (!jitter || !values || !occ_bits || dilate < 0 || dilate > kMaxDilate) return IA355_ERR_INVALID_ARG;
+  if (!(beta >= 0.0f && beta <= 1.0f)) return IA355_ERR_INVALID_ARG;
+  float *sig = nullptr;
+  int32_t st = lattice_density(G, aabb, jitter, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter, tol_stop,
+                               tol_valid, table, table_dtype, L, F, log2T, base_res, growth, params, mlp_dtype,
+                               nullptr, ws, ws_bytes, stream, &sig);
+  if (st != IA355_OK) return st;
+  const int64_t N = (int64_t)G * G * G;
+  ema_kernel<<<(unsigned)ceil_div(N, kBlock), kBlock, 0, as_stream(stream)>>>(values, sig, beta, N);
+  st = launch_status();
+  if (st != IA355_OK) return st;
+  return ia355_occ_from_density(values, G, sigma_thresh, dilate, occ_bits, stream);
+}
+
+extern "C" size_t ia355_density_reg_workspace_size(int64_t S) {
+  return S < 0 ? 0 : align256(sizeof(float) * (size_t)reg_blocks(S));
+}
+
+extern "C" int32_t ia355_density_reg(const float *x, const float *sigma, int64_t S, const int64_t *S_dev, int64_t ld,
+                                     const uint32_t *occ_bits, int32_t G, const float *aabb, float lam,
+                                     float *loss, float *grad_sigma, void *ws, size_t ws_bytes,
+                                     ia355_stream_t stream) {
+  if (S < 0 || ld < S || !occ_bits || !aabb || !loss || G <= 0 || G > 2048) return IA355_ERR_INVALID_ARG;
+  if (S > 0 && (!x || !sigma || !grad_sigma)) return IA355_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < ia355_density_reg_workspace_size(S)) return IA355_ERR_WORKSPACE;
+  float lo[3], ext[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = aabb[a];
+    ext[a] = aabb[3 + a] - aabb[a];
+    if (!(ext[a] > 0.0f)) return IA355_ERR_INVALID_ARG;
+  }
+  hipStream_t s = as_stream(stream);
+  const int nblk = reg_blocks(S);
+  float *partial = (float *)ws;
+  density_reg_kernel<<<nblk, kRegBlock, 0, s>>>(x, sigma, S, S_dev, ld, occ_bits, G, lo[0], lo[1], lo[2], ext[0],
+                                                ext[1], ext[2], lam, grad_sigma, partial);
+  density_reg_sum_kernel<<<1, kRegBlock, 0, s>>>(partial, nblk, S, S_dev, lam, loss);
+  return launch_status();
 }

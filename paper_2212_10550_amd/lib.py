@@ -38,6 +38,10 @@ _SIGS = {
     "occ_words": (_sz, [_i32]),
     "occ_pack": (_i32, [_vp, _i32, _vp, _vp]),
     "march_workspace_size": (_sz, [_i64, _i32]),
+    "occgrid_update": (_i32, [_i32, _fp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _i32,
+                              _i32, _i32, _i32, _d, _d, _vp, _i32, _f, _f, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "density_reg_workspace_size": (_sz, [_i64]),
+    "density_reg": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _i32, _fp, _f, _vp, _vp, _vp, _sz, _vp]),
     "occ_from_density": (_i32, [_vp, _i32, _f, _i32, _vp, _vp]),
     "occgrid_build_workspace_size": (_sz, [_i32, _i32, _i32, _i32, _i32, _i32, _i32]),
     "occgrid_build": (_i32, [_i32, _fp, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _i32, _i32,
@@ -158,6 +162,34 @@ def occgrid_build(G, aabb, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_v
         T.bit_length() - 1, base_res, growth, _p(params, torch.float32, "params"), mlp_dtype, float(sigma_thresh),
         dilate, _p(bits, torch.int32, "bits"), _p(sigma, torch.float32, "sigma"), _p(ws, name="ws"),
         ws.numel() * ws.element_size(), _stream()), "occgrid_build")
+
+
+def occgrid_update(G, aabb, jitter, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, table, base_res,
+                   growth, params, mlp_dtype, beta, sigma_thresh, dilate, values, bits, ws):
+    """One update of the training occupancy grid (Sec. 3.3): see the C header."""
+    Dz, Dy, Dx, nb = W.shape
+    L, T, F = table.shape
+    if jitter.numel() < 3 * G ** 3 or values.numel() < G ** 3 or bits.numel() < occ_words(G):
+        raise ValueError("occgrid_update: jitter [3][G^3], values [G^3], bits occ_words(G)")
+    _check(lib().ia355_occgrid_update(
+        G, _box(aabb), _p(jitter, torch.float32, "jitter"), _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"),
+        Dx, Dy, Dz, _box(skin_aabb), _box(hash_aabb), max_iter, tol_stop, tol_valid, _p(table, name="table"),
+        _DT[table.dtype], L, F, T.bit_length() - 1, base_res, growth, _p(params, torch.float32, "params"), mlp_dtype,
+        float(beta), float(sigma_thresh), dilate, _p(values, torch.float32, "values"), _p(bits, torch.int32, "bits"),
+        _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "occgrid_update")
+
+
+def density_reg_workspace_size(S):
+    return lib().ia355_density_reg_workspace_size(S)
+
+
+def density_reg(x, sigma, S, ld, bits, G, aabb, lam, loss, grad_sigma, ws, S_dev=None):
+    """Occupancy-based density regulariser (Sec. 3.4): see the C header."""
+    _check(lib().ia355_density_reg(
+        _p(x, torch.float32, "x"), _p(sigma, torch.float32, "sigma"), S, _p(S_dev, torch.int64, "S_dev"), ld,
+        _p(bits, torch.int32, "bits"), G, _box(aabb), float(lam), _p(loss, torch.float32, "loss"),
+        _p(grad_sigma, torch.float32, "grad_sigma"), _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()),
+        "density_reg")
 
 
 def march_workspace_size(R, max_steps):

@@ -158,3 +158,79 @@ def test_occgrid_build_mixed_precision():
     assert agree > 0.97, agree
     print(f"occgrid mixed G={G}: density rel err median {np.median(rel):.1e} max {rel.max():.1e}, "
           f"occupancy agreement {agree:.4f}")
+
+
+def test_occgrid_update_matches_oracle():
+    """Two updates of the training grid in a row (the state carried on the
+    device), rest pose and a table of values ~0.01 as in the rest-pose build
+    test: moving-average values at the FP32 bar, occupancy exact outside the
+    uncertain band."""
+    K = _K()
+    w, _ = _pose_workload()
+    w.B = np.tile(np.eye(3, 4, dtype=np.float32), (w.B.shape[0], 1, 1))
+    table = synth.make_hash_table(w.L, 1 << w.log2T, 2, seed=5, scale=0.01).astype(np.float32)
+    G, r, beta = 16, 1, 0.75
+    res = orc.resolutions(w.L, w.base_res, w.growth)
+    rng = np.random.default_rng(11)
+    v_ref = rng.random(G ** 3) * 2.0
+    Dz, Dy, Dx, nb = w.W.shape
+    values = up(v_ref.astype(np.float32))
+    v_ref = v_ref.astype(np.float32).astype(np.float64)
+    bits = torch.full((K.occ_words(G),), -1, dtype=torch.int32, device=dev())
+    ws = torch.empty(K.occgrid_build_workspace_size(G, w.L, 2, K.F32, Dx, Dy, Dz), dtype=torch.uint8, device=dev())
+    thresh = None
+    for it in range(2):
+        u = (rng.random((3, G ** 3)) * 0.999).astype(np.float32)
+        ref = orc.occgrid_update(v_ref, G, w.occ_aabb, u, w.B, w.W, w.skin_aabb, w.hash_aabb, table, res, w.mlp,
+                                 w.widths, beta, 0.0 if thresh is None else thresh, r, w.max_iter, w.tol_stop,
+                                 w.tol_valid)
+        if thresh is None:
+            thresh = float(np.median(ref["values"]))
+            ref = orc.occgrid_update(v_ref, G, w.occ_aabb, u, w.B, w.W, w.skin_aabb, w.hash_aabb, table, res,
+                                     w.mlp, w.widths, beta, thresh, r, w.max_iter, w.tol_stop, w.tol_valid)
+        K.occgrid_update(G, w.occ_aabb, up(u), up(w.B), up(w.W), w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop,
+                         w.tol_valid, up(table), w.base_res, w.growth, up(w.mlp), K.F32, beta, thresh, r, values,
+                         bits, ws)
+        torch.cuda.synchronize()
+        got_v = host(values)
+        err = np.abs(got_v - ref["values"]) / np.maximum(1.0, np.abs(ref["values"]))
+        assert err.max() <= 1e-5, (it, err.max())
+        got = unpack_bricks(host(bits), G)[:G, :G, :G]
+        near = np.abs(ref["values"] - thresh) <= 1e-5 * max(1.0, thresh)
+        unsure = orc.dilate(near.reshape(G, G, G), r)
+        np.testing.assert_array_equal(got[~unsure], ref["grid"][~unsure])
+        assert unsure.mean() < 0.2
+        v_ref = ref["values"]
+
+
+@pytest.mark.parametrize("device_count", [False, True])
+def test_density_reg_matches_oracle(device_count):
+    K = _K()
+    G, S = 13, 5003
+    ld = S + 7
+    rng = np.random.default_rng(5)
+    occ = (rng.random((G, G, G)) < 0.4).astype(np.uint8)
+    bits = torch.empty(K.occ_words(G), dtype=torch.int32, device=dev())
+    K.occ_pack(up(occ), bits)
+    box = (-0.1, 0.0, 0.2, 1.1, 0.9, 1.3)
+    x = np.stack([rng.uniform(box[a] - 0.05, box[3 + a] + 0.05, S) for a in range(3)], 1).astype(np.float32)
+    sigma = rng.exponential(3.0, S).astype(np.float32)
+    sigma[::17] = 0.0
+    xs = torch.zeros(3, ld, device=dev())
+    xs[:, :S] = up(x.T.copy())
+    loss = torch.full((1,), float("nan"), device=dev())
+    grad = torch.full((ld,), float("nan"), device=dev())
+    cap = S + 5 if device_count else S
+    sig = torch.zeros(cap, device=dev())
+    sig[:S] = up(sigma)
+    S_dev = torch.tensor([S], dtype=torch.int64, device=dev()) if device_count else None
+    ws = torch.empty(K.density_reg_workspace_size(cap), dtype=torch.uint8, device=dev())
+    K.density_reg(xs, sig, cap, ld, bits, G, box, 0.1, loss, grad, ws, S_dev=S_dev)
+    torch.cuda.synchronize()
+    rl, rg = orc.density_reg(x, sigma, occ.astype(bool), box, 0.1)
+    g = host(grad)[:S]
+    # the empty-cell decision is exact; values at the FP32 bar
+    np.testing.assert_array_equal(g == 0, rg == 0)
+    np.testing.assert_allclose(g, rg, rtol=1e-6, atol=0)
+    assert abs(float(loss.item()) - rl) <= 1e-5 * abs(rl)
+    assert 0.2 < (rg != 0).mean() < 0.8

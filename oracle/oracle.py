@@ -437,3 +437,51 @@ def density_reg(x, sigma, grid, aabb, lam):
     loss = lam * np.sum(np.abs(sigma) * empty) / n
     grad = lam * np.sign(sigma) * empty / n
     return loss, grad
+
+
+# ------------------------------------------------------ full loss set
+def huber(r, delta):
+    """Huber function rho of a non-negative residual norm."""
+    r = np.asarray(r, np.float64)
+    return np.where(r <= delta, 0.5 * r * r, delta * (r - 0.5 * delta))
+
+
+def hard_surface(a):
+    """Hard-surface term of Sec. 3.4: -log(exp(-|a|) + exp(-|a - 1|)) plus
+    the constant log(1 + exp(-1)) that makes its minimum (at a = 0 and a = 1)
+    zero."""
+    a = np.asarray(a, np.float64)
+    return -np.log(np.exp(-np.abs(a)) + np.exp(-np.abs(a - 1.0))) + np.log(1.0 + np.exp(-1.0))
+
+
+def loss_full(color, opacity, target, alpha_gt, delta, lam_alpha, lam_hard):
+    """Training loss of Sec. 3.4 averaged over the R rays: Huber of the colour
+    error norm (L_rgb), lam_alpha |A - A_gt| (L_alpha) and lam_hard times the
+    hard-surface term of A (L_hard).  Returns (loss, dL/dcolor [R][3],
+    dL/dopacity [R]); at |C - C_gt| = 0 and A = A_gt the subgradient 0 is used,
+    at A = 0 or 1 the one-sided mean 0 (both sides' slopes cancel)."""
+    C = np.asarray(color, np.float64).reshape(-1, 3)
+    T = np.asarray(target, np.float64).reshape(-1, 3)
+    A = np.asarray(opacity, np.float64)
+    Ag = np.asarray(alpha_gt, np.float64)
+    R = len(A)
+    e = C - T
+    r = np.linalg.norm(e, axis=1)
+    loss = (huber(r, delta).sum() + lam_alpha * np.abs(A - Ag).sum() + lam_hard * hard_surface(A).sum()) / R
+    scale = np.where(r <= delta, 1.0, delta / np.where(r > 0, r, 1.0))
+    gC = e * scale[:, None] / R
+    ea, eb = np.exp(-np.abs(A)), np.exp(-np.abs(A - 1.0))
+    gh = (ea * np.sign(A) + eb * np.sign(A - 1.0)) / (ea + eb)
+    gA = (lam_alpha * np.sign(A - Ag) + lam_hard * gh) / R
+    return loss, gC, gA
+
+
+def adam_step(p, g, m, v, t, lr, beta1, beta2, eps):
+    """One Adam step (Kingma and Ba), bias-corrected, step t >= 1.  Returns
+    new (p, m, v) in float64."""
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1 - beta2) * g * g
+    mh = m / (1 - beta1 ** t)
+    vh = v / (1 - beta2 ** t)
+    return np.asarray(p, np.float64) - lr * mh / (np.sqrt(vh) + eps), m, v

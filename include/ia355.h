@@ -342,6 +342,31 @@ int32_t ia355_volrender_bwd(const float *grad_color, const float *grad_opacity,
                             const float *ray_dt, const int32_t *n_used, const float *color, const float *T_final,
                             int64_t R, float *grad_sigma, float *grad_rgb, ia355_stream_t stream);
 
+/* Training loss of Sec. 3.4 over R rays: loss[4] = {total, L_rgb, L_alpha,
+ * L_hard}, each the mean over the rays of, respectively, the sum of the
+ * three, rho(|C - C_gt|) (Huber with threshold delta, whose value the paper
+ * does not give), lam_alpha |A - A_gt| and lam_hard (-log(exp(-|A|) +
+ * exp(-|A - 1|)) + log(1 + exp(-1))).  color, target [R][3], opacity,
+ * alpha_gt [R] (alpha_gt nullable: no L_alpha).  grad_color [R][3] and
+ * grad_opacity [R] (for ia355_volrender_bwd) are overwritten; at a kink the
+ * gradient uses sign(0) = 0.  One workgroup, a fixed summation order. */
+int32_t ia355_loss_full(const float *color, const float *opacity, const float *target, const float *alpha_gt,
+                        int64_t R, float delta, float lam_alpha, float lam_hard, float *loss,
+                        float *grad_color, float *grad_opacity, ia355_stream_t stream);
+
+/* Adam (Kingma and Ba, bias-corrected) on a flat FP32 array of n
+ * parameters: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * param -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), with t = step,
+ * or t = *step_dev when step_dev is given (device memory, so a captured
+ * step needs no host value).  param_f16 (nullable) receives the updated
+ * parameters rounded to FP16 (the mixed-precision copy of the hash table).
+ * ia355_count_step adds one to *step_dev: call it once per training step
+ * before the updates. */
+int32_t ia355_adam(float *param, const float *grad, float *m, float *v, int64_t n, float lr, float beta1,
+                   float beta2, float eps, int32_t step, const int32_t *step_dev, void *param_f16,
+                   ia355_stream_t stream);
+int32_t ia355_count_step(int32_t *step_dev, ia355_stream_t stream);
+
 /* Photometric L2 loss (the benchmark's stand-in for the Huber loss of
  * Eq. 9, whose threshold the paper does not give): loss[0] = mean over R*3
  * of (color - target)^2 (device float, overwritten); grad_color [R][3] =

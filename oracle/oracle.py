@@ -458,8 +458,8 @@ def loss_full(color, opacity, target, alpha_gt, delta, lam_alpha, lam_hard):
     """Training loss of Sec. 3.4 averaged over the R rays: Huber of the colour
     error norm (L_rgb), lam_alpha |A - A_gt| (L_alpha) and lam_hard times the
     hard-surface term of A (L_hard).  Returns (loss, dL/dcolor [R][3],
-    dL/dopacity [R]); at |C - C_gt| = 0 and A = A_gt the subgradient 0 is used,
-    at A = 0 or 1 the one-sided mean 0 (both sides' slopes cancel)."""
+    dL/dopacity [R]); at the kinks (A = A_gt, A = 0, A = 1) the gradient
+    formula takes sign(0) = 0."""
     C = np.asarray(color, np.float64).reshape(-1, 3)
     T = np.asarray(target, np.float64).reshape(-1, 3)
     A = np.asarray(opacity, np.float64)

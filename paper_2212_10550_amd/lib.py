@@ -38,6 +38,9 @@ _SIGS = {
     "occ_words": (_sz, [_i32]),
     "occ_pack": (_i32, [_vp, _i32, _vp, _vp]),
     "march_workspace_size": (_sz, [_i64, _i32]),
+    "loss_full": (_i32, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _vp, _vp, _vp, _vp]),
+    "adam": (_i32, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp, _vp, _vp]),
+    "count_step": (_i32, [_vp, _vp]),
     "occgrid_update": (_i32, [_i32, _fp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _i32,
                               _i32, _i32, _i32, _d, _d, _vp, _i32, _f, _f, _i32, _vp, _vp, _vp, _sz, _vp]),
     "density_reg_workspace_size": (_sz, [_i64]),
@@ -190,6 +193,31 @@ def density_reg(x, sigma, S, ld, bits, G, aabb, lam, loss, grad_sigma, ws, S_dev
         _p(bits, torch.int32, "bits"), G, _box(aabb), float(lam), _p(loss, torch.float32, "loss"),
         _p(grad_sigma, torch.float32, "grad_sigma"), _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()),
         "density_reg")
+
+
+def loss_full(color, opacity, target, alpha_gt, delta, lam_alpha, lam_hard, loss, grad_color, grad_opacity):
+    """Training loss of Sec. 3.4 (loss[4] = total, rgb, alpha, hard): see the C header."""
+    R = color.shape[0]
+    _check(lib().ia355_loss_full(
+        _p(color, torch.float32, "color"), _p(opacity, torch.float32, "opacity"), _p(target, torch.float32, "target"),
+        _p(alpha_gt, torch.float32, "alpha_gt"), R, float(delta), float(lam_alpha), float(lam_hard),
+        _p(loss, torch.float32, "loss"), _p(grad_color, torch.float32, "grad_color"),
+        _p(grad_opacity, torch.float32, "grad_opacity"), _stream()), "loss_full")
+
+
+def adam(param, grad, m, v, lr, beta1=0.9, beta2=0.99, eps=1e-15, step=1, step_dev=None, param_f16=None):
+    """One Adam step on flat FP32 arrays: see the C header."""
+    n = param.numel()
+    if grad.numel() != n or m.numel() != n or v.numel() != n or (param_f16 is not None and param_f16.numel() != n):
+        raise ValueError("adam: param, grad, m, v (and param_f16) must have the same size")
+    _check(lib().ia355_adam(
+        _p(param, torch.float32, "param"), _p(grad, torch.float32, "grad"), _p(m, torch.float32, "m"),
+        _p(v, torch.float32, "v"), n, float(lr), float(beta1), float(beta2), float(eps), int(step),
+        _p(step_dev, torch.int32, "step_dev"), _p(param_f16, torch.float16, "param_f16"), _stream()), "adam")
+
+
+def count_step(step_dev):
+    _check(lib().ia355_count_step(_p(step_dev, torch.int32, "step_dev"), _stream()), "count_step")
 
 
 def march_workspace_size(R, max_steps):

@@ -117,6 +117,10 @@ class Pipeline:
         # backward
         self.loss = e(1)
         self.grad_color = e(self.R, 3)
+        # the full loss of Sec. 3.4 (set_full_loss); otherwise the L2 loss
+        self.full_loss = None
+        self.loss4 = e(4)
+        self.grad_opacity = e(self.R)
         self.grad_sigma = e(cap)
         self.grad_rgb = e(3, cap)
         self.grad_feat = e(L * cap * 2)
@@ -188,9 +192,23 @@ class Pipeline:
         K.volrender_fwd(self.sigma, self.rgb, self.cap, self.ray_off, self.ray_dt, self.R, self.w.T_thresh,
                         self.color, self.opacity, self.n_used, self.T_final)
 
+    def set_full_loss(self, alpha_gt=None, delta=0.1, lam_alpha=0.1, lam_hard=0.01):
+        """Train on the loss of Sec. 3.4 (Huber colour, L1 opacity against
+        alpha_gt [R] if given, hard-surface term) instead of the L2 loss;
+        self.loss4 holds (total, rgb, alpha, hard)."""
+        self.full_loss = (None if alpha_gt is None else torch.as_tensor(alpha_gt, device=self.dev, dtype=torch.float32),
+                          float(delta), float(lam_alpha), float(lam_hard))
+
     def _render_bwd(self):
-        K.l2_loss(self.color, self.target, self.loss, self.grad_color)
-        K.volrender_bwd(self.grad_color, None, self.sigma, self.rgb, self.cap, self.ray_off, self.ray_dt, self.n_used,
+        if self.full_loss is None:
+            K.l2_loss(self.color, self.target, self.loss, self.grad_color)
+            g_op = None
+        else:
+            alpha_gt, delta, lam_alpha, lam_hard = self.full_loss
+            K.loss_full(self.color, self.opacity, self.target, alpha_gt, delta, lam_alpha, lam_hard, self.loss4,
+                        self.grad_color, self.grad_opacity)
+            g_op = self.grad_opacity
+        K.volrender_bwd(self.grad_color, g_op, self.sigma, self.rgb, self.cap, self.ray_off, self.ray_dt, self.n_used,
                         self.color, self.T_final, self.R, self.grad_sigma, self.grad_rgb)
 
     def _mlp_bwd(self, S, Sd):

@@ -446,6 +446,60 @@ def occgrid_leg(torch, np, K, synth, out):
     out["occupancy_grid_build"] = res
 
 
+def training_loop_leg(torch, np, K, synth, out):
+    """The training loop (`train.Trainer`): one captured graph per step with
+    the loss of Sec. 3.4, every backward and Adam on the table and the MLP;
+    the shared occupancy grid's update (Sec. 3.3) timed on its own and
+    amortised over k = 16 steps; and a fit of a teacher field's renders."""
+    from paper_2212_10550_amd.pipeline import Pipeline
+    from paper_2212_10550_amd.train import Trainer
+    res = {"workload": "training step (8192 rays of a 540x540 camera, 128^3 occupancy) + Adam (table 16 x 2^19 x 2, "
+                       "MLP 6532) per step; occupancy-grid update at G = 128 every k = 16 steps"}
+    for tag, kw in (("f32", {}), ("f16_bf16", dict(table_dtype=torch.float16, mlp_dtype=K.BF16))):
+        w = synth.train_step()
+        tr = Trainer(w, occ_every=16, **kw)
+        tr.capture()
+        for _ in range(5):
+            tr.graph.replay()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n = 50
+        a.record()
+        for _ in range(n):
+            tr.graph.replay()
+        b.record()
+        torch.cuda.synchronize()
+        step_ms = a.elapsed_time(b) / n
+        a.record()
+        for _ in range(3):
+            tr.occupancy_update()
+        b.record()
+        torch.cuda.synchronize()
+        upd_ms = a.elapsed_time(b) / 3
+        res[tag] = {"ms_per_step_with_adam": step_ms, "occupancy_update_ms": upd_ms,
+                    "ms_per_step_amortised": step_ms + upd_ms / 16}
+        del tr
+    # a student fitting a teacher's renders (FP32, no occupancy updates)
+    w = synth.train_step()
+    teacher = synth.train_step()
+    teacher.table = synth.make_hash_table(w.L, 1 << w.log2T, 2, seed=9, scale=0.1).astype(np.float32)
+    teacher.mlp = synth.make_mlp(seed=12).astype(np.float32)
+    pt = Pipeline(teacher, device="cuda:0")
+    pt.forward()
+    torch.cuda.synchronize()
+    w.target = pt.color.float().cpu().numpy()
+    tr = Trainer(w, alpha_gt=pt.opacity.clone(), occ_every=0)
+    tr.capture()
+    l0 = tr.loss_value()
+    t0 = time.perf_counter()
+    for _ in range(100):
+        tr.step()
+    torch.cuda.synchronize()
+    res["fit_teacher_100_steps"] = {"loss_start": l0, "loss_end": tr.loss_value(),
+                                    "wall_s": time.perf_counter() - t0}
+    out["training_loop"] = res
+
+
 def batch_leg(args, params, poses, gen_s, torch, np, synth, out):
     """16 poses of one avatar (occupancy 5-25 %, 270^2 / 540^2 / 1080^2) in
     one HIP graph, FP16 table, BF16 MLP, learned root initialiser with
@@ -729,6 +783,8 @@ def main():
         learned_init_leg(params, torch, np, K, synth, out)
         log("occupancy grid construction")
         occgrid_leg(torch, np, K, synth, out)
+        log("training loop with Adam and occupancy updates")
+        training_loop_leg(torch, np, K, synth, out)
         log("tiny forward, skipping on/off, hash stress")
         extra_legs(args, params, torch, np, K, synth, Pipeline, out)
         log("batched render of 16 poses")

@@ -485,3 +485,42 @@ def adam_step(p, g, m, v, t, lr, beta1, beta2, eps):
     mh = m / (1 - beta1 ** t)
     vh = v / (1 - beta2 ** t)
     return np.asarray(p, np.float64) - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ------------------------------------------------ multi-root aggregation
+def max_density_roots(xs, w, table=None, params=None):
+    """Multi-root aggregation (an alternative to keeping the lowest-residual
+    root, Sec. 3.1): the density and colour of every distinct valid root of
+    each posed point; the point takes the root with the largest density
+    (first in init order among equals) and that root's colour.  A point
+    without a root has density and colour 0.  Returns dict(sigma [S],
+    rgb [S,3], xc [S,3] (chosen root), n_roots [S], deform)."""
+    tab = w.table if table is None else table
+    prm = w.mlp if params is None else params
+    d = deform(xs, w.B, w.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop, w.tol_valid, details=True)
+    nr = d["n_roots"]
+    S = len(nr)
+    own = np.repeat(np.arange(S), nr)
+    flat = np.concatenate([d["roots"][n, :nr[n]] for n in range(S)]) if nr.sum() else np.zeros((0, 3))
+    res = resolutions(w.L, w.base_res, w.growth)
+    feat = hash_encode(flat, tab, res, w.hash_aabb)
+    sig, rgb = mlp_fwd(feat, prm, w.widths)
+    sigma = np.zeros(S)
+    col = np.zeros((S, 3))
+    xc = np.zeros((S, 3))
+    start = np.concatenate([[0], np.cumsum(nr)])
+    for n in range(S):
+        if nr[n] == 0:
+            continue
+        k = start[n] + int(np.argmax(sig[start[n]:start[n + 1]]))
+        sigma[n], col[n], xc[n] = sig[k], rgb[k], flat[k]
+    return dict(sigma=sigma, rgb=col, xc=xc, n_roots=nr, deform=d, own=own, all_sigma=sig)
+
+
+def forward_max_density(w):
+    """Fig. 2 order with multi-root aggregation: march, every root, the
+    largest density per sample, composite."""
+    m = march(w.rays_o, w.rays_d, w.occ, w.occ_aabb, w.dt, w.n_per_ray, w.max_steps)
+    a = max_density_roots(m["xs"], w)
+    c = composite_fwd(a["sigma"], a["rgb"], m["ray_off"], m["ray_dt"], w.T_thresh)
+    return dict(march=m, **a, **c)

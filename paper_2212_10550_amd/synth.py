@@ -364,6 +364,48 @@ def full_frame(pose_seed: int = 1, table_scale: float = 1e-4) -> Workload:
     return _body_frame("frame540", 540 * 540, 0.10, pose_seed, None, None, 4.0, 1e-4, table_scale)
 
 
+def folded_pose(skel: Skeleton, bone: int = 4, deg: float = 120.0) -> np.ndarray:
+    """Rest pose except one bone turned by `deg` about the z axis through its
+    rest joint (a fold in the body's plane): with sharp skinning weights,
+    posed points near the fold have a root in each of the two overlapping
+    parts (several canonical correspondences, Sec. 3.1)."""
+    B = identity_pose()
+    a = math.radians(deg)
+    R = np.array([[math.cos(a), -math.sin(a), 0.0], [math.sin(a), math.cos(a), 0.0], [0.0, 0.0, 1.0]])
+    j = skel.joints[bone]
+    B[bone, :, :3] = R
+    B[bone, :, 3] = j - R @ j
+    return B
+
+
+@functools.lru_cache(maxsize=2)
+def _folded_cached(res, temp):
+    skel = _skeleton_cached(0)
+    B = folded_pose(skel)
+    W = make_skin_grid(skel, (64, 64, 32), (0.0, 0.0, 0.25), (1.0, 1.0, 0.75), temp=temp)
+    occ = make_occupancy(skel, B, 128, 0.10, 7)
+    return B, W, occ
+
+
+def folded_frame(res: int = 540, table_scale: float = 1e-4, temp: float = 100.0) -> Workload:
+    """A frame of a folded pose (one leg bone turned 120 degrees in the body's
+    plane) with sharp skinning weights (softmax temperature 100): about 6 % of
+    the posed points near the body have two distinct roots.  The 540^2
+    camera's field of view, ~10 % occupancy built from the folded pose, no
+    termination, density output bias 0."""
+    B, W, occ = _folded_cached(res, temp)
+    o, d = camera_rays(res, res, 583.2 * (res / 540.0), res / 2.0, res / 2.0)
+    box = (0.0, 0.0, 0.0, 1.0, 1.0, 1.0)
+    return Workload(
+        name=f"folded{res}", rays_o=_f32(o), rays_d=_f32(d), occ=occ.astype(np.uint8), occ_aabb=_f32(box),
+        dt=float(np.float32(math.sqrt(3.0) / 128.0)), n_per_ray=0, max_steps=128,
+        B=_f32(B), pose_params=np.zeros((NB * 6,), np.float32),
+        W=_f32(W), skin_aabb=_f32((0.0, 0.0, 0.25, 1.0, 1.0, 0.75)), hash_aabb=_f32(box),
+        table=_f32(make_hash_table(16, 1 << 19, 2, scale=table_scale)), L=16, F=2, log2T=19,
+        mlp=_f32(make_mlp()), widths=(32, 64, 64, 4), max_iter=10,
+        tol_stop=1e-6, tol_valid=1e-5, T_thresh=0.0, target=None)
+
+
 BATCH_RES = (270, 540, 1080)
 
 

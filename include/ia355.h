@@ -247,6 +247,33 @@ int32_t ia355_rootinit_fwd(const float *xp, int64_t S, const int64_t *S_dev, int
  *   init's steps; n_fallback [1] (device int32, nullable) receives the
  *   number of fallback samples.
  * ws: ia355_deform_guided_workspace_size(S, Dx, Dy, Dz) bytes. */
+/* Multi-root aggregation (an alternative to keeping the lowest-residual root
+ * of Sec. 3.1).  ia355_snarf_deform_roots runs the same multi-init solve and
+ * writes, per sample, up to K distinct valid roots in order of increasing
+ * residual (ties: lower init), a candidate within dup_tol of a root already
+ * taken counting as the same root:
+ *   roots [3][K][S]  (slot k of sample n at (a K + k) S + n; past the
+ *                    sample's count, init 0's final iterate)
+ *   root_bone [K][S] the init of each root, -1 past the count
+ *   n_roots [S]      the number of roots kept (0..K)
+ * With K = 1 the root is ia355_snarf_deform's.  The K S slots can be fed to
+ * ia355_hashgrid_encode / ia355_mlp_fwd as one batch of K S points (ld =
+ * K S); ia355_select_max_density then keeps, per sample, the root with the
+ * largest density (ties: the lower slot) and writes its point, bone,
+ * density and colour (xc [3][ld], bone [S], sigma [S], rgb [3][ld]); a
+ * sample without a root gets bone -1, density and colour 0.
+ * ws: ia355_deform_workspace_size(Dx, Dy, Dz) bytes.  1 <= K <= nb. */
+int32_t ia355_snarf_deform_roots(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld,
+                                 const float *B, int32_t nb, const float *W, int32_t Dx, int32_t Dy,
+                                 int32_t Dz, const float *skin_aabb, const float *hash_aabb,
+                                 int32_t max_iter, float tol_stop, float tol_valid, int32_t K,
+                                 float dup_tol, float *roots, int16_t *root_bone, int32_t *n_roots,
+                                 void *ws, size_t ws_bytes, ia355_stream_t stream);
+int32_t ia355_select_max_density(int32_t K, int64_t S, const float *sigma_k, const float *rgb_k,
+                                 const float *roots, const int16_t *root_bone, const int32_t *n_roots,
+                                 int64_t ld, float *xc, int16_t *bone, float *sigma, float *rgb,
+                                 ia355_stream_t stream);
+
 size_t ia355_deform_guided_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz);
 int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld, const float *x0,
                                   const int16_t *init_bone,

@@ -341,6 +341,111 @@ __global__ void __launch_bounds__(kSolveBlock) solve_kernel(
 // Guided solve: one lane per sample starts Broyden at the given x0; an
 // accepted root (residual < tol_valid, inside the canonical box) is final,
 // otherwise the sample index is appended to the fallback queue.
+// Every distinct valid root of each sample (multi-root aggregation, the
+// alternative to keeping only the lowest-residual root): the kGroup lanes of
+// a sample run its inits as in the multi-init solve and put each init's final
+// iterate and residual (infinite when the init is not valid) in LDS; the
+// group's first lane then takes up to K roots in order of increasing residual
+// (ties: lower init), dropping every candidate within dup_tol of a root
+// already taken.  With K = 1 this is the lowest-residual root.  Layout:
+// roots [3][K][S] (slot k of sample n at (a K + k) S + n), root_bone [K][S]
+// (-1 past the sample's count; the slot then holds init 0's final iterate).
+constexpr int kRootSamples = kSolveBlock / kGroup;
+
+__global__ void __launch_bounds__(kSolveBlock) roots_kernel(
+    const float *__restrict__ xp_soa, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
+    const float *__restrict__ B, int nb, const float *__restrict__ A, Grid gr, Box hbox, int max_iter, float tol_stop,
+    float tol_valid, int K, float dup_tol, float *__restrict__ roots, int16_t *__restrict__ rbone,
+    int32_t *__restrict__ nroots) {
+  __shared__ float sBinv[kMaxBones * 12];
+  __shared__ int sBok[kMaxBones];
+  __shared__ float cx[kRootSamples][kMaxBones][3];
+  __shared__ float cr[kRootSamples][kMaxBones];
+  stage_bone_inverses(B, nb, sBinv, sBok);
+  __syncthreads();
+  const int64_t Sn = count_of(S, S_dev);
+  const int j = threadIdx.x % kGroup, sl = threadIdx.x / kGroup;
+  const float tol2 = dup_tol * dup_tol;
+  // every lane of a block runs the same iterations (the barriers below)
+  for (int64_t n0 = (int64_t)blockIdx.x * kRootSamples; n0 < Sn; n0 += (int64_t)gridDim.x * kRootSamples) {
+    const int64_t n = n0 + sl;
+    const bool act = n < Sn;
+    if (act) {
+      const float xp[3] = {xp_soa[n], xp_soa[ld + n], xp_soa[2 * ld + n]};
+      for (int i = j; i < nb; i += kGroup) {
+        const InitResult q = broyden(A, gr, sBinv + 12 * i, sBok[i], xp, max_iter, tol_stop);
+        const bool valid = q.ok && q.r < tol_valid && in_hbox(q.x, hbox);
+        cx[sl][i][0] = q.x[0];
+        cx[sl][i][1] = q.x[1];
+        cx[sl][i][2] = q.x[2];
+        cr[sl][i] = valid ? q.r : INFINITY;
+      }
+    }
+    __syncthreads();
+    if (act && j == 0) {
+      int cnt = 0;
+      for (int k = 0; k < K; ++k) {
+        int best = -1;
+        float br = INFINITY;
+        for (int i = 0; i < nb; ++i)
+          if (cr[sl][i] < br) {
+            br = cr[sl][i];
+            best = i;
+          }
+        if (best < 0) break;
+        const float bx[3] = {cx[sl][best][0], cx[sl][best][1], cx[sl][best][2]};
+        for (int i = 0; i < nb; ++i) {
+          if (!(cr[sl][i] < INFINITY)) continue;
+          const float d0 = cx[sl][i][0] - bx[0], d1 = cx[sl][i][1] - bx[1], d2 = cx[sl][i][2] - bx[2];
+          if (d0 * d0 + d1 * d1 + d2 * d2 <= tol2) cr[sl][i] = INFINITY;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) roots[((int64_t)a * K + k) * S + n] = bx[a];
+        rbone[(int64_t)k * S + n] = (int16_t)best;
+        ++cnt;
+      }
+      for (int k = cnt; k < K; ++k) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) roots[((int64_t)a * K + k) * S + n] = cx[sl][0][a];
+        rbone[(int64_t)k * S + n] = -1;
+      }
+      nroots[n] = cnt;
+    }
+    __syncthreads();
+  }
+}
+
+// Per sample, the root with the largest density among its n_roots (ties: the
+// lower slot, i.e. the lower residual): its point, bone, density and colour.
+__global__ void __launch_bounds__(256) select_max_kernel(int K, int64_t S, const float *__restrict__ sigk,
+                                                         const float *__restrict__ rgbk, const float *__restrict__ roots,
+                                                         const int16_t *__restrict__ rbone,
+                                                         const int32_t *__restrict__ nroots, int64_t ld,
+                                                         float *__restrict__ xc, int16_t *__restrict__ bone,
+                                                         float *__restrict__ sigma, float *__restrict__ rgb) {
+  const int64_t KS = (int64_t)K * S;
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < S; n += (int64_t)gridDim.x * 256) {
+    const int cnt = nroots[n];
+    int best = -1;
+    float bs = -INFINITY;
+    for (int k = 0; k < cnt && k < K; ++k) {
+      const float v = sigk[(int64_t)k * S + n];
+      if (v > bs) {
+        bs = v;
+        best = k;
+      }
+    }
+    const int kk = best < 0 ? 0 : best;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      xc[a * ld + n] = roots[((int64_t)a * K + kk) * S + n];
+      rgb[a * ld + n] = best < 0 ? 0.0f : rgbk[a * KS + (int64_t)kk * S + n];
+    }
+    bone[n] = best < 0 ? (int16_t)-1 : rbone[(int64_t)kk * S + n];
+    sigma[n] = best < 0 ? 0.0f : bs;
+  }
+}
+
 __global__ void __launch_bounds__(kSolveBlock) guided_kernel(
     const float *__restrict__ xp_soa, const float *__restrict__ x0_soa, const int16_t *__restrict__ guide,
     int64_t S, const int64_t *__restrict__ S_dev, int64_t ld, const float *__restrict__ A, Grid gr, Box hbox,
@@ -678,6 +783,46 @@ extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, const int64_t 
   }
   solve_kernel<<<stride_grid(ceil_div(S * kGroup, kSolveBlock), S_dev != nullptr), kSolveBlock, 0, s>>>(
       xp, S, S_dev, ld, B, nb, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps);
+  return launch_status();
+}
+
+extern "C" int32_t ia355_snarf_deform_roots(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld,
+                                            const float *B, int32_t nb, const float *W, int32_t Dx, int32_t Dy,
+                                            int32_t Dz, const float *skin_aabb, const float *hash_aabb,
+                                            int32_t max_iter, float tol_stop, float tol_valid, int32_t K,
+                                            float dup_tol, float *roots, int16_t *root_bone, int32_t *n_roots,
+                                            void *ws, size_t ws_bytes, ia355_stream_t stream) {
+  if (S < 0 || ld < S || nb <= 0 || nb > kMaxBones || max_iter < 0 || max_iter > 1000) return IA355_ERR_INVALID_ARG;
+  if (K < 1 || K > nb || !(dup_tol >= 0.0f)) return IA355_ERR_INVALID_ARG;
+  if (!B || !W || !grid_ok(Dx, Dy, Dz, skin_aabb) || !hash_aabb) return IA355_ERR_INVALID_ARG;
+  if (S > 0 && (!xp || !roots || !root_bone || !n_roots)) return IA355_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < ia355_deform_workspace_size(Dx, Dy, Dz)) return IA355_ERR_WORKSPACE;
+  hipStream_t s = as_stream(stream);
+  const int64_t nvert = (int64_t)Dx * Dy * Dz;
+  float *A = (float *)ws;
+  blend_kernel<<<(unsigned)ceil_div(nvert, 256), 256, 0, s>>>(W, B, nb, nvert, A);
+  if (S == 0) return launch_status();
+  const Grid g = make_grid(Dx, Dy, Dz, skin_aabb);
+  Box hb;
+  for (int a = 0; a < 3; ++a) {
+    hb.lo[a] = hash_aabb[a];
+    hb.hi[a] = hash_aabb[3 + a];
+  }
+  roots_kernel<<<stride_grid(ceil_div(S, kRootSamples), S_dev != nullptr), kSolveBlock, 0, s>>>(
+      xp, S, S_dev, ld, B, nb, A, g, hb, max_iter, tol_stop, tol_valid, K, dup_tol, roots, root_bone, n_roots);
+  return launch_status();
+}
+
+extern "C" int32_t ia355_select_max_density(int32_t K, int64_t S, const float *sigma_k, const float *rgb_k,
+                                            const float *roots, const int16_t *root_bone, const int32_t *n_roots,
+                                            int64_t ld, float *xc, int16_t *bone, float *sigma, float *rgb,
+                                            ia355_stream_t stream) {
+  if (K < 1 || S < 0 || ld < S) return IA355_ERR_INVALID_ARG;
+  if (S > 0 && (!sigma_k || !rgb_k || !roots || !root_bone || !n_roots || !xc || !bone || !sigma || !rgb))
+    return IA355_ERR_INVALID_ARG;
+  if (S == 0) return IA355_OK;
+  select_max_kernel<<<grid_for(S, 256), 256, 0, as_stream(stream)>>>(K, S, sigma_k, rgb_k, roots, root_bone, n_roots,
+                                                                      ld, xc, bone, sigma, rgb);
   return launch_status();
 }
 

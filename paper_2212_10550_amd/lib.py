@@ -38,6 +38,9 @@ _SIGS = {
     "occ_words": (_sz, [_i32]),
     "occ_pack": (_i32, [_vp, _i32, _vp, _vp]),
     "march_workspace_size": (_sz, [_i64, _i32]),
+    "snarf_deform_roots": (_i32, [_vp, _i64, _vp, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f,
+                                  _i32, _f, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "select_max_density": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     "loss_full": (_i32, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _vp, _vp, _vp, _vp]),
     "adam": (_i32, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp, _vp, _vp]),
     "count_step": (_i32, [_vp, _vp]),
@@ -218,6 +221,26 @@ def adam(param, grad, m, v, lr, beta1=0.9, beta2=0.99, eps=1e-15, step=1, step_d
 
 def count_step(step_dev):
     _check(lib().ia355_count_step(_p(step_dev, torch.int32, "step_dev"), _stream()), "count_step")
+
+
+def snarf_deform_roots(xp, S, ld, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, K, dup_tol, roots,
+                       root_bone, n_roots, ws, S_dev=None):
+    """Every distinct valid root (up to K per sample): see the C header."""
+    Dz, Dy, Dx, nb = W.shape
+    _check(lib().ia355_snarf_deform_roots(
+        _p(xp, torch.float32, "xp"), S, _p(S_dev, torch.int64, "S_dev"), ld, _p(B, torch.float32, "B"), nb,
+        _p(W, torch.float32, "W"), Dx, Dy, Dz, _box(skin_aabb), _box(hash_aabb), max_iter, tol_stop, tol_valid, K,
+        float(dup_tol), _p(roots, torch.float32, "roots"), _p(root_bone, torch.int16, "root_bone"),
+        _p(n_roots, torch.int32, "n_roots"), _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()),
+        "snarf_deform_roots")
+
+
+def select_max_density(K, S, sigma_k, rgb_k, roots, root_bone, n_roots, ld, xc, bone, sigma, rgb):
+    _check(lib().ia355_select_max_density(
+        K, S, _p(sigma_k, torch.float32, "sigma_k"), _p(rgb_k, torch.float32, "rgb_k"),
+        _p(roots, torch.float32, "roots"), _p(root_bone, torch.int16, "root_bone"),
+        _p(n_roots, torch.int32, "n_roots"), ld, _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"),
+        _p(sigma, torch.float32, "sigma"), _p(rgb, torch.float32, "rgb"), _stream()), "select_max_density")
 
 
 def march_workspace_size(R, max_steps):

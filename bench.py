@@ -500,6 +500,41 @@ def training_loop_leg(torch, np, K, synth, out):
     out["training_loop"] = res
 
 
+def multiroot_leg(torch, np, K, synth, out):
+    """Multi-root aggregation (largest density over every distinct valid
+    root) against the lowest-residual root on a folded pose's 540^2 frame
+    (FP32, 24 inits, host counts for both)."""
+    from paper_2212_10550_amd.multiroot import MaxDensityRenderer
+    from paper_2212_10550_amd.pipeline import Pipeline
+    w = synth.folded_frame()
+    res = {"workload": "540x540 rays of a folded pose (one leg bone turned 120 degrees, skinning softmax "
+                       "temperature 100), 128^3 occupancy (~10 %), <=128 samples/ray, FP32, 24-init Broyden"}
+
+    def timed(fn, n=3):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    p = Pipeline(w, device="cuda:0")
+    res["lowest_residual_ms"] = timed(p.forward)
+    c0 = p.color.clone()
+    del p
+    mr = MaxDensityRenderer(w, K_roots=4)
+    res["max_density_ms"] = timed(mr.forward)
+    nr = mr.n_roots().to(torch.int64)
+    res["posed_samples"] = int(mr.S)
+    res["samples_with_two_or_more_roots"] = int((nr >= 2).sum().item())
+    res["pixel_change_vs_lowest_residual"] = {"mean": float((mr.p.color - c0).abs().mean().item()),
+                                              "max": float((mr.p.color - c0).abs().max().item())}
+    out["multi_root_aggregation"] = res
+
+
 def batch_leg(args, params, poses, gen_s, torch, np, synth, out):
     """16 poses of one avatar (occupancy 5-25 %, 270^2 / 540^2 / 1080^2) in
     one HIP graph, FP16 table, BF16 MLP, learned root initialiser with
@@ -785,6 +820,8 @@ def main():
         occgrid_leg(torch, np, K, synth, out)
         log("training loop with Adam and occupancy updates")
         training_loop_leg(torch, np, K, synth, out)
+        log("multi-root aggregation on a folded pose")
+        multiroot_leg(torch, np, K, synth, out)
         log("tiny forward, skipping on/off, hash stress")
         extra_legs(args, params, torch, np, K, synth, Pipeline, out)
         log("batched render of 16 poses")

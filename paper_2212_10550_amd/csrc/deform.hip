@@ -246,13 +246,14 @@ struct Choice {
   int bone, steps;
 };
 
+template <int kG = kGroup>
 __device__ __forceinline__ Choice multi_init(const float *__restrict__ A, const Grid &gr, const float *sBinv,
                                              const int *sBok, int nb, const float xp[3], bool act, int j, Box hbox,
                                              int max_iter, float tol_stop, float tol_valid) {
   float best_r = INFINITY, best_x[3] = {0.0f, 0.0f, 0.0f}, x0[3] = {0.0f, 0.0f, 0.0f};
   int best = 0x7fffffff, steps = 0;
   if (act) {
-    for (int i = j; i < nb; i += kGroup) {
+    for (int i = j; i < nb; i += kG) {
       const InitResult q = broyden(A, gr, sBinv + 12 * i, sBok[i], xp, max_iter, tol_stop);
       steps += q.steps;
       if (i == 0) {
@@ -270,13 +271,13 @@ __device__ __forceinline__ Choice multi_init(const float *__restrict__ A, const 
     }
   }
 #pragma unroll
-  for (int o = kGroup / 2; o > 0; o >>= 1) {
-    const float r2 = __shfl_xor(best_r, o, kGroup);
-    const int b2 = __shfl_xor(best, o, kGroup);
-    const float x20 = __shfl_xor(best_x[0], o, kGroup);
-    const float x21 = __shfl_xor(best_x[1], o, kGroup);
-    const float x22 = __shfl_xor(best_x[2], o, kGroup);
-    steps += __shfl_xor(steps, o, kGroup);
+  for (int o = kG / 2; o > 0; o >>= 1) {
+    const float r2 = __shfl_xor(best_r, o, kG);
+    const int b2 = __shfl_xor(best, o, kG);
+    const float x20 = __shfl_xor(best_x[0], o, kG);
+    const float x21 = __shfl_xor(best_x[1], o, kG);
+    const float x22 = __shfl_xor(best_x[2], o, kG);
+    steps += __shfl_xor(steps, o, kG);
     if (r2 < best_r || (r2 == best_r && b2 < best)) {
       best_r = r2;
       best = b2;
@@ -473,13 +474,17 @@ __global__ void __launch_bounds__(kSolveBlock) guided_kernel(
 
 // Fallback: multi-init solve of the queued samples; the blocks loop over
 // the queue (its length is known only on the device).
+// 32 lanes per queued sample (one init per lane): the queue is short and
+// its samples are the slow ones, so latency, not throughput, sets the time.
+constexpr int kFbGroup = 32;
+
 __global__ void __launch_bounds__(kSolveBlock) fallback_kernel(
     const float *__restrict__ xp_soa, int64_t ld, const float *__restrict__ B, int nb, const float *__restrict__ A,
     Grid gr, Box hbox, int max_iter, float tol_stop, float tol_valid, float *__restrict__ xc_soa,
     int16_t *__restrict__ bone_out, float *__restrict__ resid_out, int16_t *__restrict__ steps_out,
     const int32_t *__restrict__ queue, const int32_t *__restrict__ qlen, const int16_t *__restrict__ gsteps,
     int32_t *__restrict__ n_fallback) {
-  constexpr int kPerBlock = kSolveBlock / kGroup;
+  constexpr int kPerBlock = kSolveBlock / kFbGroup;
   const int64_t nq = *qlen;
   if (n_fallback && blockIdx.x == 0 && threadIdx.x == 0) *n_fallback = (int32_t)nq;
   if ((int64_t)blockIdx.x * kPerBlock >= nq) return;  // the whole block is past the queue
@@ -487,9 +492,9 @@ __global__ void __launch_bounds__(kSolveBlock) fallback_kernel(
   __shared__ int sBok[kMaxBones];
   stage_bone_inverses(B, nb, sBinv, sBok);
   __syncthreads();
-  const int j = threadIdx.x % kGroup;
+  const int j = threadIdx.x % kFbGroup;
   for (int64_t q0 = (int64_t)blockIdx.x * kPerBlock; q0 < nq; q0 += (int64_t)gridDim.x * kPerBlock) {
-    const int64_t q = q0 + threadIdx.x / kGroup;
+    const int64_t q = q0 + threadIdx.x / kFbGroup;
     const bool act = q < nq;
     const int64_t n = act ? queue[q] : 0;
     float xp[3] = {0.0f, 0.0f, 0.0f};
@@ -498,7 +503,7 @@ __global__ void __launch_bounds__(kSolveBlock) fallback_kernel(
       xp[1] = xp_soa[ld + n];
       xp[2] = xp_soa[2 * ld + n];
     }
-    const Choice c = multi_init(A, gr, sBinv, sBok, nb, xp, act, j, hbox, max_iter, tol_stop, tol_valid);
+    const Choice c = multi_init<kFbGroup>(A, gr, sBinv, sBok, nb, xp, act, j, hbox, max_iter, tol_stop, tol_valid);
     if (act && j == 0) write_choice(c, n, ld, gsteps[n], xc_soa, bone_out, resid_out, steps_out);
   }
 }
@@ -862,10 +867,12 @@ extern "C" int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, const i
       hb.hi[a] = hash_aabb[3 + a];
     }
     const bool dev = S_dev != nullptr;
-    guided_kernel<<<stride_grid(ceil_div(S, kSolveBlock), dev), kSolveBlock, 0, s>>>(
+    // up to one sample per lane at frame sizes (more waves in flight to
+    // hide the gathers' latency)
+    guided_kernel<<<stride_grid(ceil_div(S, kSolveBlock), dev, 8192), kSolveBlock, 0, s>>>(
         xp, x0, guide_bone, S, S_dev, ld, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, queue,
         qlen, gsteps);
-    fallback_kernel<<<stride_grid(ceil_div(S * kGroup, kSolveBlock), dev), kSolveBlock, 0, s>>>(
+    fallback_kernel<<<stride_grid(ceil_div(S * kFbGroup, kSolveBlock), dev), kSolveBlock, 0, s>>>(
         xp, ld, B, nb, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps, queue, qlen, gsteps,
         n_fallback);
   } else if (n_fallback) {

@@ -5,7 +5,8 @@
 //             block's total;
 //   chunk  -- each block scans 4096 block totals (exclusive, in place) and
 //             writes its chunk total;
-//   top    -- one block scans the chunk totals and writes the sample count;
+//   top    -- one block scans the chunk totals and writes the sample count
+//             (skipped when there is one chunk: the chunk kernel writes it);
 //   fill   -- one wave per ray again, from the keep masks the count kernel
 //             saved (one 64-bit ballot per 64 steps) and the ray's entry
 //             distance: only kept samples' positions are recomputed (the same
@@ -183,7 +184,8 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *wsum
 constexpr int kScanPer = 4;
 constexpr int64_t kScanChunk = 1024 * kScanPer;
 
-__global__ void __launch_bounds__(1024) march_scan_chunk(int64_t *block_sum, int64_t nblk, int64_t *chunk_sum) {
+__global__ void __launch_bounds__(1024) march_scan_chunk(int64_t *block_sum, int64_t nblk, int64_t *chunk_sum,
+                                                         int64_t *ray_off, int64_t R, int64_t *n_samples) {
   __shared__ int64_t wsum[1024 / kWave];
   const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
   int64_t v[kScanPer], run = 0;
@@ -199,7 +201,14 @@ __global__ void __launch_bounds__(1024) march_scan_chunk(int64_t *block_sum, int
     if (i0 + j < nblk) block_sum[i0 + j] = off;
     off += v[j];
   }
-  if (threadIdx.x == 0) chunk_sum[blockIdx.x] = total;
+  if (threadIdx.x == 0) {
+    chunk_sum[blockIdx.x] = total;
+    if (gridDim.x == 1) {  // a single chunk: its total is the sample count
+      chunk_sum[0] = 0;
+      n_samples[0] = total;
+      ray_off[R] = total;
+    }
+  }
 }
 
 // Exclusive scan of the chunk totals (in place) in one block; the grand
@@ -334,9 +343,9 @@ extern "C" int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d,
       march_count<false><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray,
                                                            max_steps, ray_off, ray_cnt, ray_dt, block_sum,
                                                            mw.masks, nw, mw.tn);
-    march_scan_chunk<<<(unsigned)nchunk, 1024, 0, s>>>(block_sum, nblk, chunk_sum);
+    march_scan_chunk<<<(unsigned)nchunk, 1024, 0, s>>>(block_sum, nblk, chunk_sum, ray_off, R, n_samples);
   }
-  march_scan_top<<<1, 1024, 0, s>>>(chunk_sum, nchunk, ray_off, R, n_samples);
+  if (nchunk != 1) march_scan_top<<<1, 1024, 0, s>>>(chunk_sum, nchunk, ray_off, R, n_samples);
   if (R > 0 && cap > 0)
     march_fill<<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, mw.masks, nw, mw.tn, block_sum, chunk_sum,
                                                  ray_off, ray_dt, xs, ts, ray_id, cap);

@@ -42,7 +42,8 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ float relu(float z) { return z < 0.0f ? 0.0f : z; }
+// max(z, 0): one v_max_f32 (a compare-and-select keeps NaN semantics and costs two)
+__device__ __forceinline__ float relu(float z) { return fmaxf(z, 0.0f); }
 
 __device__ __forceinline__ void head(const float o[4], float *sig, float c[3]) {
   *sig = expf(fminf(o[0], 80.0f));

@@ -24,7 +24,8 @@ constexpr int kBlock = 256;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ float relu(float z) { return z < 0.0f ? 0.0f : z; }
+// max(z, 0): one v_max_f32 (a compare-and-select keeps NaN semantics and costs two)
+__device__ __forceinline__ float relu(float z) { return fmaxf(z, 0.0f); }
 
 template <bool BF16>
 __global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restrict__ xp_soa, int64_t S,

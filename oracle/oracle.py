@@ -378,18 +378,20 @@ def occgrid_build(G, aabb, B, W, skin_aabb, hash_aabb, table, res, params, width
 
 
 # ------------------------------------------- training occupancy grid
-def jittered_points(G, aabb, u):
+def jittered_points(G, aabb, u, cells=None):
     """One point per cell of the G^3 grid of ``aabb`` at a random position
     inside it (Sec. 3.3, training stage: densities of randomly sampled
-    points): point n = x + G (y + G z) at lo + ((i + u_n) / G) * (hi - lo) per
-    axis with u [3][G^3] in [0, 1) supplied by the caller, every operation
-    in IEEE single.  Returns [G^3, 3] float32."""
+    points): for cell c = x + G (y + G z), lo + ((i + u) / G) * (hi - lo) per
+    axis with u [3][M] in [0, 1) supplied by the caller, every operation in
+    IEEE single.  ``cells`` [M] lists the cells (default: all G^3 in order).
+    Returns [M, 3] float32."""
     lo = np.asarray(aabb[:3], np.float32)
     ext = np.asarray(aabb[3:], np.float32) - lo
-    u = np.asarray(u, np.float32).reshape(3, G ** 3)
-    n = np.arange(G ** 3)
-    idx = [n % G, (n // G) % G, n // (G * G)]
-    out = np.empty((G ** 3, 3), np.float32)
+    c = np.arange(G ** 3) if cells is None else np.asarray(cells, np.int64)
+    M = len(c)
+    u = np.asarray(u, np.float32).reshape(3, M)
+    idx = [c % G, (c // G) % G, c // (G * G)]
+    out = np.empty((M, 3), np.float32)
     g = np.float32(G)
     for a in range(3):
         out[:, a] = lo[a] + ((idx[a].astype(np.float32) + u[a]) / g) * ext[a]
@@ -397,18 +399,21 @@ def jittered_points(G, aabb, u):
 
 
 def occgrid_update(values, G, aabb, u, B, W, skin_aabb, hash_aabb, table, res, params, widths, beta, sigma_thresh,
-                   r, max_iter=10, tol_stop=1e-6, tol_valid=1e-5):
+                   r, max_iter=10, tol_stop=1e-6, tol_valid=1e-5, cells=None):
     """One update of the shared training occupancy grid (Sec. 3.3, training
-    stage): densities of one random point per cell in the posed space of
-    the given frame (no root -> 0), a moving average with the grid's
-    current values, v <- beta v + (1 - beta) sigma, then the threshold and
+    stage): densities of one random point in each listed cell (default all;
+    distinct cells) in the posed space of the given frame (no root -> 0), a
+    moving average with those cells' current values, v <- beta v +
+    (1 - beta) sigma (other cells keep theirs), then the threshold and
     dilation of the inference grid.  values: [G^3] float64 (new array
     returned)."""
-    pts = jittered_points(G, aabb, u)
+    pts = jittered_points(G, aabb, u, cells)
     d = deform(pts, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid)
     feat = hash_encode(d["xc"], table, res, hash_aabb, valid=d["bone"])
     sigma, _ = mlp_fwd(feat, params, widths, valid=d["bone"])
-    v = beta * np.asarray(values, np.float64) + (1.0 - beta) * sigma
+    v = np.array(values, np.float64)
+    c = np.arange(G ** 3) if cells is None else np.asarray(cells, np.int64)
+    v[c] = beta * v[c] + (1.0 - beta) * sigma
     occ = (v > sigma_thresh).reshape(G, G, G)
     return dict(points=pts, deform=d, sigma=sigma, values=v, grid=dilate(occ, r))
 

@@ -151,3 +151,28 @@ def test_density_reg_closed_form():
         s2[i] += eps
         l2, _ = orc.density_reg(x, s2, grid, box, 0.1)
         assert abs((l2 - loss) / eps - grad[i]) < 1e-8
+
+
+def test_occgrid_update_on_a_subset_of_cells():
+    """Listed cells get the average, the others keep their values; the
+    listed cells' points are those of the full update."""
+    w = synth.tiny_forward()
+    nb = w.B.shape[0]
+    B = np.tile(np.eye(3, 4), (nb, 1, 1))
+    G = 4
+    res = orc.resolutions(w.L, w.base_res, w.growth)
+    params = synth.make_mlp(seed=3)
+    table = synth.make_hash_table(w.L, w.table.shape[1], 2, seed=5, scale=0.3)
+    rng = np.random.default_rng(4)
+    u = rng.random((3, G ** 3)).astype(np.float32)
+    old = rng.random(G ** 3) * 2.0
+    cells = np.sort(rng.choice(G ** 3, 20, replace=False))
+    box = (0, 0, 0, 1, 1, 1)
+    full = orc.occgrid_update(old, G, box, u, B, w.W, w.skin_aabb, w.hash_aabb, table, res, params, w.widths, 0.5,
+                              0.8, 0)
+    sub = orc.occgrid_update(old, G, box, u[:, cells], B, w.W, w.skin_aabb, w.hash_aabb, table, res, params,
+                             w.widths, 0.5, 0.8, 0, cells=cells)
+    np.testing.assert_array_equal(sub["points"], full["points"][cells])
+    np.testing.assert_array_equal(sub["values"][cells], full["values"][cells])
+    rest = np.setdiff1d(np.arange(G ** 3), cells)
+    np.testing.assert_array_equal(sub["values"][rest], old[rest])

@@ -454,7 +454,7 @@ def training_loop_leg(torch, np, K, synth, out):
     from paper_2212_10550_amd.pipeline import Pipeline
     from paper_2212_10550_amd.train import Trainer
     res = {"workload": "training step (8192 rays of a 540x540 camera, 128^3 occupancy) + Adam (table 16 x 2^19 x 2, "
-                       "MLP 6532) per step; occupancy-grid update at G = 128 every k = 16 steps"}
+                       "MLP 6532) per step; occupancy-grid update of a random eighth of the 128^3 cells every k = 16 steps"}
     for tag, kw in (("f32", {}), ("f16_bf16", dict(table_dtype=torch.float16, mlp_dtype=K.BF16))):
         w = synth.train_step()
         tr = Trainer(w, occ_every=16, **kw)

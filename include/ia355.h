@@ -151,14 +151,17 @@ int32_t ia355_occgrid_build(int32_t G, const float *aabb, const float *B, int32_
                             void *ws, size_t ws_bytes, ia355_stream_t stream);
 
 /* Training-stage occupancy grid (Sec. 3.3): one update of the grid shared
- * by all frames.  For the frame given by B, one point per cell at
- * lo + ((i + u) / G) (hi - lo) with u = jitter [3][G^3] in [0, 1) (the
- * caller draws it; IEEE single, no fused operations) gets its density as in
- * ia355_occgrid_build (no root: 0); values [G^3] (FP32, in/out) become
- * beta * values + (1 - beta) * sigma, and occ_bits are made from values by
- * ia355_occ_from_density.  0 <= beta <= 1.
+ * by all frames.  For the frame given by B, one point in each cell listed
+ * in cells [M] (distinct indices c = x + G (y + G z); NULL: every cell, M
+ * ignored), at lo + ((i + u) / G) (hi - lo) with u = jitter [3][M] (or
+ * [3][G^3]) in [0, 1) (the caller draws both; IEEE single, no fused
+ * operations), gets its density as in ia355_occgrid_build (no root: 0); the
+ * listed cells' values [G^3] (FP32, in/out) become beta * values +
+ * (1 - beta) * sigma (an index outside the grid is skipped), and occ_bits
+ * are made from all values by ia355_occ_from_density.  0 <= beta <= 1.
  * ws: ia355_occgrid_build_workspace_size(G, L, F, mlp_dtype, Dx, Dy, Dz). */
-int32_t ia355_occgrid_update(int32_t G, const float *aabb, const float *jitter, const float *B, int32_t nb,
+int32_t ia355_occgrid_update(int32_t G, const float *aabb, const float *jitter, const int32_t *cells, int64_t M,
+                             const float *B, int32_t nb,
                              const float *W, int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
                              const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
                              const void *table, int32_t table_dtype, int32_t L, int32_t F, int32_t log2T,

@@ -30,11 +30,14 @@ constexpr int kMaxDilate = 4;
 // single).
 __global__ void __launch_bounds__(kBlock) lattice_kernel(int G, float lo0, float lo1, float lo2, float ext0,
                                                          float ext1, float ext2, int64_t N,
-                                                         const float *__restrict__ jitter, float *__restrict__ xp) {
+                                                         const float *__restrict__ jitter,
+                                                         const int32_t *__restrict__ cells, float *__restrict__ xp) {
 #pragma clang fp contract(off)
   const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n >= N) return;
-  const int ix = (int)(n % G), iy = (int)((n / G) % G), iz = (int)(n / ((int64_t)G * G));
+  int64_t c = cells ? (int64_t)cells[n] : n;  // the cell of point n
+  if (c < 0 || c >= (int64_t)G * G * G) c = 0;  // an invalid index: any in-grid point (its update is skipped)
+  const int ix = (int)(c % G), iy = (int)((c / G) % G), iz = (int)(c / ((int64_t)G * G));
   const float g = (float)G;
   const float u0 = jitter ? jitter[n] : 0.5f, u1 = jitter ? jitter[N + n] : 0.5f, u2 = jitter ? jitter[2 * N + n] : 0.5f;
   xp[n] = lo0 + (((float)ix + u0) / g) * ext0;
@@ -42,13 +45,17 @@ __global__ void __launch_bounds__(kBlock) lattice_kernel(int G, float lo0, float
   xp[2 * N + n] = lo2 + (((float)iz + u2) / g) * ext2;
 }
 
-// v <- beta v + (1 - beta) sigma (the moving average of the training grid).
+// v <- beta v + (1 - beta) sigma (the moving average of the training grid),
+// point n updating its cell (cells[n], or n).
 __global__ void __launch_bounds__(kBlock) ema_kernel(float *__restrict__ v, const float *__restrict__ sigma,
-                                                     float beta, int64_t N) {
+                                                     const int32_t *__restrict__ cells, float beta, int64_t N,
+                                                     int64_t ncell) {
 #pragma clang fp contract(off)
   const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n >= N) return;
-  v[n] = beta * v[n] + (1.0f - beta) * sigma[n];
+  const int64_t c = cells ? (int64_t)cells[n] : n;
+  if (c < 0 || c >= ncell) return;
+  v[c] = beta * v[c] + (1.0f - beta) * sigma[n];
 }
 
 // Density regulariser in two kernels with a fixed summation order: a
@@ -202,7 +209,8 @@ extern "C" size_t ia355_occgrid_build_workspace_size(int32_t G, int32_t L, int32
 
 // Densities of one point per cell (cell centres, or jittered): lattice,
 // root finding, encoding, MLP.  Writes sig [G^3].
-static int32_t lattice_density(int32_t G, const float *aabb, const float *jitter, const float *B, int32_t nb,
+static int32_t lattice_density(int32_t G, const float *aabb, const float *jitter, const int32_t *cells, int64_t M,
+                               const float *B, int32_t nb,
                                const float *W, int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
                                const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
                                const void *table, int32_t table_dtype, int32_t L, int32_t F, int32_t log2T,
@@ -219,13 +227,13 @@ static int32_t lattice_density(int32_t G, const float *aabb, const float *jitter
   const size_t need = ia355_occgrid_build_workspace_size(G, L, F, mlp_dtype, Dx, Dy, Dz);
   if (!ws || need == 0 || ws_bytes < need) return IA355_ERR_WORKSPACE;
   const OccWs w = occ_ws(ws, G, L, F, mlp_dtype, Dx, Dy, Dz);
-  const int64_t N = (int64_t)G * G * G;
+  const int64_t N = cells ? M : (int64_t)G * G * G;  // points: the listed cells, or every cell
   float *sig = sigma ? sigma : w.sigma;
   *sig_out = sig;
   const int32_t feat_dtype = mlp_dtype == IA355_F32 ? IA355_F32 : IA355_BF16;
   hipStream_t s = as_stream(stream);
   lattice_kernel<<<(unsigned)ceil_div(N, kBlock), kBlock, 0, s>>>(G, lo[0], lo[1], lo[2], ext[0], ext[1], ext[2], N,
-                                                                   jitter, w.xp);
+                                                                   jitter, cells, w.xp);
   int32_t st = launch_status();
   if (st != IA355_OK) return st;
   st = ia355_snarf_deform(w.xp, N, nullptr, N, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter, tol_stop,
@@ -246,15 +254,16 @@ extern "C" int32_t ia355_occgrid_build(int32_t G, const float *aabb, const float
                                        void *ws, size_t ws_bytes, ia355_stream_t stream) {
   if (!occ_bits || dilate < 0 || dilate > kMaxDilate) return IA355_ERR_INVALID_ARG;
   float *sig = nullptr;
-  const int32_t st = lattice_density(G, aabb, nullptr, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter,
+  const int32_t st = lattice_density(G, aabb, nullptr, nullptr, 0, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter,
                                      tol_stop, tol_valid, table, table_dtype, L, F, log2T, base_res, growth, params,
                                      mlp_dtype, sigma, ws, ws_bytes, stream, &sig);
   if (st != IA355_OK) return st;
   return ia355_occ_from_density(sig, G, sigma_thresh, dilate, occ_bits, stream);
 }
 
-extern "C" int32_t ia355_occgrid_update(int32_t G, const float *aabb, const float *jitter, const float *B,
-                                        int32_t nb, const float *W, int32_t Dx, int32_t Dy, int32_t Dz,
+extern "C" int32_t ia355_occgrid_update(int32_t G, const float *aabb, const float *jitter, const int32_t *cells,
+                                        int64_t M, const float *B, int32_t nb, const float *W, int32_t Dx,
+                                        int32_t Dy, int32_t Dz,
                                         const float *skin_aabb, const float *hash_aabb, int32_t max_iter,
                                         float tol_stop, float tol_valid, const void *table, int32_t table_dtype,
                                         int32_t L, int32_t F, int32_t log2T, double base_res, double growth,
@@ -263,13 +272,15 @@ extern "C" int32_t ia355_occgrid_update(int32_t G, const float *aabb, const floa
                                         size_t ws_bytes, ia355_stream_t stream) {
   if (!jitter || !values || !occ_bits || dilate < 0 || dilate > kMaxDilate) return IA355_ERR_INVALID_ARG;
   if (!(beta >= 0.0f && beta <= 1.0f)) return IA355_ERR_INVALID_ARG;
+  if (G <= 0 || G > 256 || (cells && (M < 1 || M > (int64_t)G * G * G))) return IA355_ERR_INVALID_ARG;
   float *sig = nullptr;
-  int32_t st = lattice_density(G, aabb, jitter, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter, tol_stop,
+  int32_t st = lattice_density(G, aabb, jitter, cells, M, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter, tol_stop,
                                tol_valid, table, table_dtype, L, F, log2T, base_res, growth, params, mlp_dtype,
                                nullptr, ws, ws_bytes, stream, &sig);
   if (st != IA355_OK) return st;
-  const int64_t N = (int64_t)G * G * G;
-  ema_kernel<<<(unsigned)ceil_div(N, kBlock), kBlock, 0, as_stream(stream)>>>(values, sig, beta, N);
+  const int64_t N = cells ? M : (int64_t)G * G * G;
+  ema_kernel<<<(unsigned)ceil_div(N, kBlock), kBlock, 0, as_stream(stream)>>>(values, sig, cells, beta, N,
+                                                                               (int64_t)G * G * G);
   st = launch_status();
   if (st != IA355_OK) return st;
   return ia355_occ_from_density(values, G, sigma_thresh, dilate, occ_bits, stream);

@@ -44,7 +44,8 @@ _SIGS = {
     "loss_full": (_i32, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _vp, _vp, _vp, _vp]),
     "adam": (_i32, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp, _vp, _vp]),
     "count_step": (_i32, [_vp, _vp]),
-    "occgrid_update": (_i32, [_i32, _fp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _i32,
+    "occgrid_update": (_i32, [_i32, _fp, _vp, _vp, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f,
+                              _vp, _i32,
                               _i32, _i32, _i32, _d, _d, _vp, _i32, _f, _f, _i32, _vp, _vp, _vp, _sz, _vp]),
     "density_reg_workspace_size": (_sz, [_i64]),
     "density_reg": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _i32, _fp, _f, _vp, _vp, _vp, _sz, _vp]),
@@ -171,14 +172,17 @@ def occgrid_build(G, aabb, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_v
 
 
 def occgrid_update(G, aabb, jitter, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, table, base_res,
-                   growth, params, mlp_dtype, beta, sigma_thresh, dilate, values, bits, ws):
-    """One update of the training occupancy grid (Sec. 3.3): see the C header."""
+                   growth, params, mlp_dtype, beta, sigma_thresh, dilate, values, bits, ws, cells=None):
+    """One update of the training occupancy grid (Sec. 3.3), of every cell or
+    of the listed ones (int32 [M], distinct): see the C header."""
     Dz, Dy, Dx, nb = W.shape
     L, T, F = table.shape
-    if jitter.numel() < 3 * G ** 3 or values.numel() < G ** 3 or bits.numel() < occ_words(G):
-        raise ValueError("occgrid_update: jitter [3][G^3], values [G^3], bits occ_words(G)")
+    M = G ** 3 if cells is None else cells.numel()
+    if jitter.numel() < 3 * M or values.numel() < G ** 3 or bits.numel() < occ_words(G):
+        raise ValueError("occgrid_update: jitter [3][M], values [G^3], bits occ_words(G)")
     _check(lib().ia355_occgrid_update(
-        G, _box(aabb), _p(jitter, torch.float32, "jitter"), _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"),
+        G, _box(aabb), _p(jitter, torch.float32, "jitter"), _p(cells, torch.int32, "cells"), M,
+        _p(B, torch.float32, "B"), nb, _p(W, torch.float32, "W"),
         Dx, Dy, Dz, _box(skin_aabb), _box(hash_aabb), max_iter, tol_stop, tol_valid, _p(table, name="table"),
         _DT[table.dtype], L, F, T.bit_length() - 1, base_res, growth, _p(params, torch.float32, "params"), mlp_dtype,
         float(beta), float(sigma_thresh), dilate, _p(values, torch.float32, "values"), _p(bits, torch.int32, "bits"),

@@ -2,7 +2,8 @@
 deform, encode, MLP, composite, the loss of Sec. 3.4, every backward) plus
 the Adam update of the hash table and the MLP, captured as one HIP graph,
 and every k steps an update of the shared training occupancy grid
-(Sec. 3.3) that the next steps' march reads.
+(Sec. 3.3) at random points of a random subset of its cells, which the next
+steps' march reads.
 
 Random numbers the method draws (the jitter of the occupancy update) come
 from a seeded pool drawn once on the host and kept in HBM.
@@ -19,7 +20,7 @@ from .pipeline import Pipeline
 class Trainer:
     def __init__(self, w, lr=1e-2, betas=(0.9, 0.99), eps=1e-15, table_dtype=torch.float32, mlp_dtype=K.F32,
                  alpha_gt=None, loss_args=(0.1, 0.1, 0.01), occ_every=16, occ_beta=0.95, occ_thresh=0.01,
-                 occ_dilate=1, jitter_pool=8, seed=0, device="cuda"):
+                 occ_dilate=1, occ_fraction=0.125, jitter_pool=8, seed=0, device="cuda"):
         self.p = Pipeline(w, device=device, table_dtype=table_dtype, mlp_dtype=mlp_dtype, device_count=True)
         p = self.p
         if alpha_gt is not None or loss_args is not None:
@@ -42,7 +43,13 @@ class Trainer:
             occ = torch.as_tensor(np.ascontiguousarray(w.occ), device=dev, dtype=torch.float32).reshape(-1)
             self.occ_values = occ * (2.0 * occ_thresh)
             rng = np.random.default_rng(seed)
-            self.jitter = torch.as_tensor(rng.random((jitter_pool, 3, G ** 3), dtype=np.float32) * np.float32(0.999),
+            # each update refreshes a random subset of the cells (sorted, so
+            # neighbouring points stay close), jittered inside each cell
+            M = G ** 3 if occ_fraction >= 1.0 else max(1, int(G ** 3 * occ_fraction))
+            self.cells = None if M == G ** 3 else torch.as_tensor(
+                np.stack([np.sort(rng.choice(G ** 3, M, replace=False)) for _ in range(jitter_pool)]).astype(
+                    np.int32), device=dev)
+            self.jitter = torch.as_tensor(rng.random((jitter_pool, 3, M), dtype=np.float32) * np.float32(0.999),
                                           device=dev)
             Dz, Dy, Dx, nb = w.W.shape
             self.ws_occ = torch.empty(K.occgrid_build_workspace_size(G, w.L, 2, p.mlp_dtype, Dx, Dy, Dz),
@@ -72,10 +79,11 @@ class Trainer:
         """One moving-average update of the shared grid (Sec. 3.3) in the
         posed space of this workload's frame, jitter from the pool."""
         p, w = self.p, self.p.w
-        j = self.jitter[(self.steps_done // max(self.occ_every, 1)) % self.jitter.shape[0]]
-        K.occgrid_update(self.G, w.occ_aabb, j, p.B, p.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop,
-                         w.tol_valid, p.table, w.base_res, w.growth, p.params, p.mlp_dtype, self.occ_beta,
-                         self.occ_thresh, self.occ_dilate, self.occ_values, p.occ_bits, self.ws_occ)
+        i = (self.steps_done // max(self.occ_every, 1)) % self.jitter.shape[0]
+        K.occgrid_update(self.G, w.occ_aabb, self.jitter[i], p.B, p.W, w.skin_aabb, w.hash_aabb, w.max_iter,
+                         w.tol_stop, w.tol_valid, p.table, w.base_res, w.growth, p.params, p.mlp_dtype,
+                         self.occ_beta, self.occ_thresh, self.occ_dilate, self.occ_values, p.occ_bits, self.ws_occ,
+                         cells=None if self.cells is None else self.cells[i])
 
     def step(self):
         """One training step (graph replay once captured); every occ_every

@@ -234,3 +234,33 @@ def test_density_reg_matches_oracle(device_count):
     np.testing.assert_allclose(g, rg, rtol=1e-6, atol=0)
     assert abs(float(loss.item()) - rl) <= 1e-5 * abs(rl)
     assert 0.2 < (rg != 0).mean() < 0.8
+
+
+def test_occgrid_update_on_listed_cells_matches_oracle():
+    """An update of a random subset of cells: listed cells at the FP32 bar,
+    the others unchanged bit for bit."""
+    K = _K()
+    w, _ = _pose_workload()
+    w.B = np.tile(np.eye(3, 4, dtype=np.float32), (w.B.shape[0], 1, 1))
+    table = synth.make_hash_table(w.L, 1 << w.log2T, 2, seed=5, scale=0.01).astype(np.float32)
+    G, M = 16, 700
+    res = orc.resolutions(w.L, w.base_res, w.growth)
+    rng = np.random.default_rng(12)
+    cells = np.sort(rng.choice(G ** 3, M, replace=False)).astype(np.int32)
+    u = (rng.random((3, M)) * 0.999).astype(np.float32)
+    v0 = (rng.random(G ** 3) * 2.0).astype(np.float32)
+    Dz, Dy, Dx, nb = w.W.shape
+    values = up(v0)
+    bits = torch.full((K.occ_words(G),), -1, dtype=torch.int32, device=dev())
+    ws = torch.empty(K.occgrid_build_workspace_size(G, w.L, 2, K.F32, Dx, Dy, Dz), dtype=torch.uint8, device=dev())
+    K.occgrid_update(G, w.occ_aabb, up(u), up(w.B), up(w.W), w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop,
+                     w.tol_valid, up(table), w.base_res, w.growth, up(w.mlp), K.F32, 0.5, 1.0, 1, values, bits, ws,
+                     cells=up(cells))
+    torch.cuda.synchronize()
+    ref = orc.occgrid_update(v0.astype(np.float64), G, w.occ_aabb, u, w.B, w.W, w.skin_aabb, w.hash_aabb, table, res,
+                             w.mlp, w.widths, 0.5, 1.0, 1, w.max_iter, w.tol_stop, w.tol_valid, cells=cells)
+    got = host(values)
+    err = np.abs(got[cells] - ref["values"][cells]) / np.maximum(1.0, np.abs(ref["values"][cells]))
+    assert err.max() <= 1e-5, err.max()
+    rest = np.setdiff1d(np.arange(G ** 3), cells)
+    np.testing.assert_array_equal(got[rest], v0[rest])

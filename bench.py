@@ -630,6 +630,48 @@ def learned_init_leg(params, torch, np, K, synth, out, n_poses=64):
         return a.elapsed_time(b) / reps
 
     ms_g, ms_m = graph_ms(guided), graph_ms(multi)
+
+    # the same calls spread over four streams inside the graph (per-stream
+    # buffers), so that concurrent poses hide each other's latency
+    n_str = 4
+    streams = [torch.cuda.Stream() for _ in range(n_str)]
+    gds = [rootinit.GuidedDeform(params, w, max(q["S"] for q in poses), device="cuda:0") for _ in range(n_str)]
+    wss = [e(K.deform_workspace_size(Dx, Dy, Dz), dt=torch.uint8) for _ in range(n_str)]
+
+    def spread(fn):
+        def run():
+            main = torch.cuda.current_stream()
+            for st in streams:
+                st.wait_stream(main)
+            for k, q in enumerate(poses):
+                with torch.cuda.stream(streams[k % n_str]):
+                    fn(q, k % n_str)
+            for st in streams:
+                main.wait_stream(st)
+        return run
+
+    def guided_s(q, j):
+        gds[j].run(q["xp"], q["S"], q["S"], q["pose"], q["B"], W_t, q["xg"], q["bg"], None, q["sg"])
+
+    def multi_s(q, j):
+        K.snarf_deform(q["xp"], q["S"], q["S"], q["B"], W_t, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop,
+                       w.tol_valid, q["xm"], q["bm"], None, q["sm"], wss[j])
+
+    def graph_ms_run(run, reps=5):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            run()
+        g.replay()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms_g4, ms_m4 = graph_ms_run(spread(guided_s)), graph_ms_run(spread(multi_s))
     err = np.concatenate(errs)
     out["learned_init"] = {
         "held_out": f"{n_poses} poses (seeds 2000-{2000 + n_poses - 1}) x 4096 posed points = {n} samples",
@@ -638,6 +680,7 @@ def learned_init_leg(params, torch, np, K, synth, out, n_poses=64):
         "root_err_vs_multi_init": {"mean": float(err.mean()), "max": float(err.max())},
         "deform_ms_all_poses": {"learned_bf16_guided": ms_g, "multi_init_24": ms_m},
         "deform_samples_per_s": {"learned_bf16_guided": n / ms_g * 1e3, "multi_init_24": n / ms_m * 1e3},
+        "deform_ms_all_poses_4_streams": {"learned_bf16_guided": ms_g4, "multi_init_24": ms_m4},
         "timing": "one HIP graph per method with every pose's call in order; each call includes the per-pose "
                   "blend of the skinning grid with the bone transforms (the same work in both methods)",
     }

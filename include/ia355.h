@@ -326,6 +326,33 @@ int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const
                                   const float *aabb, float *grad_table, float *grad_xc, uint32_t flags,
                                   void *ws, size_t ws_bytes, ia355_stream_t stream);
 
+/* Table gradient of the encoding (the grad_table output of
+ * ia355_hashgrid_encode_bwd, same arguments, flags and result) computed
+ * without global atomics on almost every entry: the corner updates are
+ * binned by (level, table tile of 4096 entries), written once as 12-byte
+ * records (the two FP32 values, the entry in the tile) and summed per tile
+ * in LDS as exact 64-bit fixed point (a power-of-two scale per group of at
+ * most 8192 records, chosen from its largest value), then converted back
+ * and written with plain stores.  A tile whose bin holds more than 8192
+ * records is summed by several workgroups that add their nonzero entries
+ * with FP32 atomics.  Every tile of the selected levels is written, so
+ * IA355_OVERWRITE needs no separate clear.  A tile summed by one workgroup
+ * does not depend on the order of its records; split tiles may vary in the
+ * last bit from run to run.  Non-finite gradients are not supported.
+ *   grad_table: [L][T][F] FP32, 16-byte aligned, T = 2^log2T.
+ *   ws: ia355_hashgrid_table_grad_workspace_size(S, L, log2T) bytes
+ *       (S is the capacity when S_dev is given); about 96 bytes per sample
+ *       and level.  Calls that may run at the same time need separate
+ *       workspaces.
+ * Limits: L <= 16, L * 2^log2T <= 2^26 entries (at most 16384 tiles),
+ * 8 L S < 2^32; otherwise IA355_ERR_INVALID_ARG (the workspace size is then
+ * 0).  A workspace below the size returns IA355_ERR_WORKSPACE. */
+size_t ia355_hashgrid_table_grad_workspace_size(int64_t S, int32_t L, int32_t log2T);
+int32_t ia355_hashgrid_table_grad(const float *grad_feat, const float *xc, const int16_t *bone, int64_t S,
+                                  const int64_t *S_dev, int64_t ld, int32_t L, int32_t F, int32_t log2T,
+                                  double base_res, double growth, const float *aabb, float *grad_table,
+                                  uint32_t flags, void *ws, size_t ws_bytes, ia355_stream_t stream);
+
 /* The decoder MLP 32 -> 64 -> 64 -> 4 with ReLU hidden layers; outputs
  * sigma = exp(o_0) (clamped at exp(80)) and c = sigmoid(o_1..3).
  *   feat [L][ld][F] (L*F = 32) of feat_dtype; params FP32 flat

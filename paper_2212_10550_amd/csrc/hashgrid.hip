@@ -378,6 +378,462 @@ __global__ void __launch_bounds__(kDgBlock) table_grad_dense_kernel(const float 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Table gradient without global atomics (binned).  Each level's table is cut
+// into tiles of E = 2^tb entries (2 E 8-byte sums fit in LDS); a corner update
+// (level, entry, w_c dL/dfeat_l) belongs to bin (level, tile), bins in
+// level-major order.  Five passes:
+//  1. count: every block counts its updates per bin in LDS and writes its
+//     column of the histogram hist[bin][block];
+//  2. scan: exclusive scan of the histogram in bin-major order, in chunks of
+//     4096 (offsets inside the chunk, chunk totals);
+//  3. plan (one block): offsets of the chunks, the record range of every bin
+//     and the number of accumulation chunks it needs (<= kAccChunk records
+//     each);
+//  4. scatter: the same blocks regenerate the same updates (same items, same
+//     arithmetic) and append them to their run inside their bin's records,
+//     one 12-byte record each (the two values, the entry inside the tile);
+//  5. accumulate: one workgroup per chunk sums its records into an LDS copy
+//     of the tile and writes the tile with plain vector stores; a bin split
+//     over several chunks (only bins with many updates, on the coarse
+//     levels) adds its nonzero entries with global atomics instead, after a
+//     pass that clears those tiles when overwriting.
+// The LDS sums are 64-bit fixed point, added exactly: LDS float atomic adds run at
+// about a sixteenth of the rate of integer ones on gfx950, so each chunk
+// scales its values by a power of two 2^s chosen from its largest |value|
+// and record count (no overflow, quantum 2^-s far below FP32 rounding of the
+// sum), adds them as integers and converts each entry back once.  Integer
+// addition is associative, so a tile summed by one workgroup does not
+// depend on the order of its records.
+// Every tile of the selected levels is written, so an overwrite needs no
+// separate clear.  The HBM traffic is the records (12 bytes per corner
+// update, written once and read once) and one pass over the table slice.
+constexpr int kBinBlock = 1024;       // count / scatter
+constexpr int kBinMaxBlocks = 256;    // one block per CU
+constexpr int kBinUnroll = 4;         // items per thread whose loads are in flight together
+constexpr int kMaxBins = 16384;       // LDS counters of one block: 64 KB
+constexpr int kTileLog2Max = 12;      // 4096 entries x 2 x 8 B = 64 KB of LDS
+constexpr int kHsPer = 4;
+constexpr int kHsChunk = 1024 * kHsPer;
+constexpr int kMaxHsChunks = 4096;
+constexpr int kAccBlock = 1024;
+constexpr uint32_t kAccChunk = 8192;  // records per accumulation workgroup
+constexpr int kAccPer = kAccChunk / kAccBlock;  // records per thread, held in registers
+constexpr int kAccMaxGrid = 2048;
+static_assert(kAccChunk <= (1u << 13) && kAccChunk % kAccBlock == 0, "bin_accum_kernel: scale and record slots");
+
+struct BinGeom {
+  int tb;         // log2 entries per tile
+  int tpl_log2;   // log2 tiles per level
+  int nbins;
+  int P;          // count / scatter blocks
+  int64_t H;      // histogram entries nbins * P
+  int nchunk;     // histogram scan chunks
+  int64_t rmax;   // record capacity: levels * S * 8
+  int64_t qmax;   // accumulation chunks at most
+};
+
+inline bool bin_geom(int nl, int64_t S, int log2T, BinGeom *g) {
+  if (nl <= 0 || S < 0 || log2T < 1 || log2T > 30) return false;
+  g->tb = log2T < kTileLog2Max ? log2T : kTileLog2Max;
+  g->tpl_log2 = log2T - g->tb;
+  const int64_t nb = (int64_t)nl << g->tpl_log2;
+  if (nb > kMaxBins) return false;
+  g->nbins = (int)nb;
+  int64_t p = ceil_div((int64_t)nl * (S > 0 ? S : 1), (int64_t)kBinBlock);
+  g->P = (int)(p < 1 ? 1 : (p > kBinMaxBlocks ? kBinMaxBlocks : p));
+  g->H = (int64_t)g->nbins * g->P;
+  g->nchunk = (int)ceil_div(g->H, kHsChunk);
+  g->rmax = (int64_t)nl * S * 8;
+  g->qmax = g->nbins + ceil_div(g->rmax, (int64_t)kAccChunk);
+  return g->nchunk <= kMaxHsChunks && g->rmax < 0xffffffffLL;
+}
+
+struct BinWs {
+  uint32_t *hist, *csum, *chunk_first;
+  uint4 *chunk_info;  // per accumulation chunk: bin, first record, end, chunks of the bin
+  float3 *rec;  // (value 0, value 1, entry inside the tile as bits)
+  size_t bytes;
+};
+
+inline BinWs bin_ws(const BinGeom &g, void *base) {
+  BinWs w;
+  char *p = (char *)base;
+  size_t o = 0;
+  w.hist = (uint32_t *)(p + o);
+  o += align256(sizeof(uint32_t) * (size_t)g.H);
+  w.csum = (uint32_t *)(p + o);
+  o += align256(sizeof(uint32_t) * (size_t)g.nchunk);
+  w.chunk_first = (uint32_t *)(p + o);
+  o += align256(sizeof(uint32_t) * ((size_t)g.nbins + 1));
+  w.chunk_info = (uint4 *)(p + o);
+  o += align256(sizeof(uint4) * (size_t)g.qmax);
+  w.rec = (float3 *)(p + o);
+  o += align256(sizeof(float3) * (size_t)(g.rmax > 0 ? g.rmax : 1));
+  w.bytes = o;
+  return w;
+}
+
+// Exclusive scan of one value per thread over a 1024-thread block; *total
+// gets the block's sum (the same in every thread).
+__device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t *wsum, uint32_t *total) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t base = 0, all = 0;
+  for (int w = 0; w < 1024 / kWave; ++w) {
+    base += w < wid ? wsum[w] : 0u;
+    all += wsum[w];
+  }
+  __syncthreads();
+  *total = all;
+  return base + incl - v;
+}
+
+// Adds 1 to the LDS counter c[bin] for each lane with act and returns the
+// counter's old value plus the lane's rank among the wave's lanes with the
+// same bin.  When every active lane has the same bin (coarse levels: one
+// tile per level, consecutive samples) the wave does one add of the lane
+// count instead of 64 adds serialised on one LDS address.
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t *c, int bin, bool act) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t am = __ballot(act);
+  if (am == 0ull) return 0u;
+  const int first = __ffsll((unsigned long long)am) - 1;
+  const int b0 = __shfl(bin, first, kWave);
+  const uint64_t same = __ballot(act && bin == b0);
+  if (same == am) {
+    uint32_t base = 0u;
+    if (lane == first) base = atomicAdd(&c[bin], (uint32_t)__popcll(am));
+    base = __shfl(base, first, kWave);
+    return base + (uint32_t)__popcll(am & ((1ull << lane) - 1ull));
+  }
+  return act ? atomicAdd(&c[bin], 1u) : 0u;
+}
+
+// Items of the count and scatter passes: item it = level (l0 + it / Sn),
+// sample it % Sn; thread t of block b takes items b * 1024 + t + j * stride
+// (stride = blocks * 1024), kBinUnroll of them per round with their loads
+// issued together.  Both passes visit the same items in the same blocks and
+// compute the corner entries with the same code, so their per-(bin, block)
+// counts agree.
+struct BinItem {
+  int lr;
+  bool act;
+  float x[3];
+  float2 g;
+};
+
+template <bool kWithGrad>
+__device__ __forceinline__ void load_items(int64_t i0, int64_t stride, int64_t items, int64_t Sn,
+                                           const float *__restrict__ xc, const int16_t *__restrict__ bone,
+                                           const float *__restrict__ gfeat, int64_t ld, int l0,
+                                           BinItem (&b)[kBinUnroll]) {
+#pragma unroll
+  for (int j = 0; j < kBinUnroll; ++j) {
+    const int64_t it = i0 + j * stride;
+    const bool in = it < items;
+    // items < 2^32 (the record count is), so 32-bit division suffices
+    const uint32_t lr = in ? (uint32_t)it / (uint32_t)Sn : 0u;
+    const int64_t n = in ? it - (int64_t)lr * Sn : 0;
+    b[j].lr = (int)lr;
+    // all loads issued together; n < Sn keeps them in bounds
+    const bool valid = !bone || bone[n] >= 0;
+    b[j].x[0] = xc[n];
+    b[j].x[1] = xc[ld + n];
+    b[j].x[2] = xc[2 * ld + n];
+    b[j].g = kWithGrad ? reinterpret_cast<const float2 *>(gfeat)[(int64_t)(l0 + b[j].lr) * ld + n]
+                       : make_float2(0.0f, 0.0f);
+    b[j].act = in && valid;
+  }
+}
+
+__global__ void __launch_bounds__(kBinBlock) bin_count_kernel(const float *__restrict__ xc,
+                                                             const int16_t *__restrict__ bone, int64_t S,
+                                                             const int64_t *__restrict__ S_dev, int64_t ld, int l0,
+                                                             int nl, int log2T, int tb, Levels lv, Box box,
+                                                             uint32_t *__restrict__ hist) {
+  extern __shared__ uint32_t cnt[];
+  const int tpl_log2 = log2T - tb;
+  const int nbins = nl << tpl_log2;
+  for (int i = threadIdx.x; i < nbins; i += kBinBlock) cnt[i] = 0u;
+  __syncthreads();
+  const int64_t Sn = count_of(S, S_dev);
+  const int64_t items = (int64_t)nl * Sn;
+  const uint32_t T = 1u << log2T;
+  const int64_t stride = (int64_t)gridDim.x * kBinBlock;
+  // the loop bound is wave-uniform at kBinUnroll granularity: lanes past the
+  // end stay in with act = false (the reservations use wave ballots)
+  for (int64_t w0 = (int64_t)blockIdx.x * kBinBlock + (threadIdx.x & ~(kWave - 1)); w0 < items;
+       w0 += stride * kBinUnroll) {
+    BinItem b[kBinUnroll];
+    load_items<false>(w0 + (threadIdx.x & (kWave - 1)), stride, items, Sn, xc, bone, nullptr, ld, l0, b);
+#pragma unroll
+    for (int j = 0; j < kBinUnroll; ++j) {
+      const int level = l0 + b[j].lr;
+      const int N = lv.res[level];
+      const CellPos cp = level_pos(b[j].x, box, N);
+      const bool dense = lv.dense[level] != 0;
+      // dense levels: few tiles, neighbouring samples share them (one add
+      // per wave); hashed levels: bins spread over the tiles (plain adds)
+      if (__ballot(b[j].act && dense) != 0ull) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t idx = corner_index(cp, k, N, dense, T - 1u);
+          wave_reserve(cnt, (b[j].lr << tpl_log2) + (int)(idx >> tb), b[j].act);
+        }
+      } else if (b[j].act) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t idx = corner_index(cp, k, N, dense, T - 1u);
+          atomicAdd(&cnt[(b[j].lr << tpl_log2) + (int)(idx >> tb)], 1u);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int P = gridDim.x;
+  for (int i = threadIdx.x; i < nbins; i += kBinBlock) hist[(int64_t)i * P + blockIdx.x] = cnt[i];
+}
+
+__global__ void __launch_bounds__(1024) bin_hist_scan_kernel(uint32_t *__restrict__ hist, int64_t H,
+                                                            uint32_t *__restrict__ csum) {
+  __shared__ uint32_t wsum[1024 / kWave];
+  const int64_t i0 = (int64_t)blockIdx.x * kHsChunk + (int64_t)threadIdx.x * kHsPer;
+  uint32_t v[kHsPer], run = 0;
+#pragma unroll
+  for (int j = 0; j < kHsPer; ++j) {
+    v[j] = i0 + j < H ? hist[i0 + j] : 0u;
+    run += v[j];
+  }
+  uint32_t total;
+  uint32_t off = block_scan_u32(run, wsum, &total);
+#pragma unroll
+  for (int j = 0; j < kHsPer; ++j) {
+    if (i0 + j < H) hist[i0 + j] = off;
+    off += v[j];
+  }
+  if (threadIdx.x == 0) csum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(1024) bin_plan_kernel(const uint32_t *__restrict__ hist, uint32_t *__restrict__ csum,
+                                                       int nchunk, int nbins, int P,
+                                                       uint32_t *__restrict__ chunk_first,
+                                                       uint4 *__restrict__ chunk_info) {
+  __shared__ uint32_t wsum[1024 / kWave];
+  __shared__ uint32_t coff[kMaxHsChunks];
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nchunk; c0 += 1024) {
+    const int i = c0 + threadIdx.x;
+    const uint32_t v = i < nchunk ? csum[i] : 0u;
+    uint32_t total;
+    const uint32_t off = block_scan_u32(v, wsum, &total);
+    if (i < nchunk) coff[i] = carry + off;
+    carry += total;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nchunk; i += 1024) csum[i] = coff[i];  // chunk offsets for the scatter pass
+  const uint32_t n_rec = carry;
+  uint32_t ccarry = 0;
+  for (int b0 = 0; b0 < nbins; b0 += 1024) {
+    const int b = b0 + threadIdx.x;
+    uint32_t nch = 0, st = 0, en = 0;
+    if (b < nbins) {
+      const int64_t j = (int64_t)b * P;
+      st = hist[j] + coff[j / kHsChunk];
+      en = n_rec;
+      if (b + 1 < nbins) {
+        const int64_t j1 = j + P;
+        en = hist[j1] + coff[j1 / kHsChunk];
+      }
+      nch = en > st ? (en - st + kAccChunk - 1) / kAccChunk : 1u;
+    }
+    uint32_t total;
+    const uint32_t off = block_scan_u32(nch, wsum, &total);
+    if (b < nbins) {
+      chunk_first[b] = ccarry + off;
+      for (uint32_t c = 0; c < nch; ++c) {
+        const uint32_t rb = st + c * kAccChunk;
+        chunk_info[ccarry + off + c] = make_uint4((uint32_t)b, rb, en - rb > kAccChunk ? rb + kAccChunk : en, nch);
+      }
+    }
+    ccarry += total;
+  }
+  if (threadIdx.x == 0) {
+    chunk_first[nbins] = ccarry;
+  }
+}
+
+__global__ void __launch_bounds__(kBinBlock) bin_scatter_kernel(
+    const float *__restrict__ gfeat, const float *__restrict__ xc, const int16_t *__restrict__ bone, int64_t S,
+    const int64_t *__restrict__ S_dev, int64_t ld, int l0, int nl, int log2T, int tb, Levels lv, Box box,
+    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ coff, float3 *__restrict__ rec) {
+  extern __shared__ uint32_t cur[];
+  const int tpl_log2 = log2T - tb;
+  const int nbins = nl << tpl_log2;
+  const int P = gridDim.x;
+  for (int i = threadIdx.x; i < nbins; i += kBinBlock) {
+    const int64_t j = (int64_t)i * P + blockIdx.x;
+    cur[i] = hist[j] + coff[j / kHsChunk];
+  }
+  __syncthreads();
+  const int64_t Sn = count_of(S, S_dev);
+  const int64_t items = (int64_t)nl * Sn;
+  const uint32_t T = 1u << log2T;
+  const uint32_t emask = (1u << tb) - 1u;
+  const int64_t stride = (int64_t)gridDim.x * kBinBlock;
+  for (int64_t w0 = (int64_t)blockIdx.x * kBinBlock + (threadIdx.x & ~(kWave - 1)); w0 < items;
+       w0 += stride * kBinUnroll) {
+    BinItem b[kBinUnroll];
+    load_items<true>(w0 + (threadIdx.x & (kWave - 1)), stride, items, Sn, xc, bone, gfeat, ld, l0, b);
+#pragma unroll
+    for (int j = 0; j < kBinUnroll; ++j) {
+      const int level = l0 + b[j].lr;
+      const int N = lv.res[level];
+      const CellPos cp = level_pos(b[j].x, box, N);
+      const bool dense = lv.dense[level] != 0;
+      if (__ballot(b[j].act && dense) != 0ull) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t idx = corner_index(cp, k, N, dense, T - 1u);
+          const float w = corner_weight(cp, k);
+          const uint32_t pos = wave_reserve(cur, (b[j].lr << tpl_log2) + (int)(idx >> tb), b[j].act);
+          if (b[j].act) rec[pos] = make_float3(w * b[j].g.x, w * b[j].g.y, __uint_as_float(idx & emask));
+        }
+      } else if (b[j].act) {
+        uint32_t idx[8], pos[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          idx[k] = corner_index(cp, k, N, dense, T - 1u);
+          pos[k] = atomicAdd(&cur[(b[j].lr << tpl_log2) + (int)(idx[k] >> tb)], 1u);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float w = corner_weight(cp, k);
+          rec[pos[k]] = make_float3(w * b[j].g.x, w * b[j].g.y, __uint_as_float(idx[k] & emask));
+        }
+      }
+    }
+  }
+}
+
+// Base of bin b's tile in the table gradient.
+__device__ __forceinline__ float4 *tile_ptr(float *gtable, int b, int l0, int log2T, int tb) {
+  const int tpl_log2 = log2T - tb;
+  const int64_t level = l0 + (b >> tpl_log2);
+  const int64_t tile = b & ((1 << tpl_log2) - 1);
+  return reinterpret_cast<float4 *>(gtable + 2 * ((level << log2T) + (tile << tb)));
+}
+
+// Clears the tiles of bins split over several chunks (they are then summed
+// with atomics); overwrite only.
+__global__ void __launch_bounds__(256) bin_clear_split_kernel(const uint32_t *__restrict__ chunk_first, int nbins,
+                                                             int l0, int log2T, int tb, float *__restrict__ gtable) {
+  const int n4 = 1 << (tb - 1);  // float4 per tile (2 entries each)
+  for (int b = blockIdx.x; b < nbins; b += gridDim.x) {
+    if (chunk_first[b + 1] - chunk_first[b] <= 1u) continue;
+    float4 *dst = tile_ptr(gtable, b, l0, log2T, tb);
+    for (int j = threadIdx.x; j < n4; j += 256) dst[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+}
+
+__device__ __forceinline__ float block_max(float v, float *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  float m = 0.0f;
+  for (int w = 0; w < kAccBlock / kWave; ++w) m = fmaxf(m, red[w]);
+  __syncthreads();
+  return m;
+}
+
+// v * 2^s rounded to an integer, as two's complement bits (|v| 2^s < 2^48)
+__device__ __forceinline__ unsigned long long to_fixed(float v, int s) {
+  return (unsigned long long)(long long)rint((double)ldexpf(v, s));
+}
+
+__global__ void __launch_bounds__(kAccBlock) bin_accum_kernel(const float3 *__restrict__ rec,
+                                                             const uint32_t *__restrict__ chunk_first,
+                                                             const uint4 *__restrict__ chunk_info, int nbins,
+                                                             int l0, int log2T, int tb, int overwrite,
+                                                             float *__restrict__ gtable) {
+  extern __shared__ unsigned long long acc[];  // 2 E fixed-point sums
+  __shared__ float red[kAccBlock / kWave];
+  const int n2 = 1 << tb;  // entries of a tile (2 sums each)
+  const int n4 = n2 / 2;   // float4 (2 entries) per tile
+  ulonglong2 *a2 = reinterpret_cast<ulonglong2 *>(acc);
+  const uint32_t Q = chunk_first[nbins];
+  for (uint32_t q = blockIdx.x; q < Q; q += gridDim.x) {
+    const uint4 ci = chunk_info[q];  // bin, first record, end, chunks of the bin
+    const int b = (int)ci.x;
+    const uint32_t rb = ci.y, re = ci.z, nch = ci.w;
+    float4 *dst = tile_ptr(gtable, b, l0, log2T, tb);
+    if (rb == re) {  // no update in this tile (then nch == 1)
+      if (overwrite)
+        for (int j = threadIdx.x; j < n4; j += kAccBlock) dst[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      continue;
+    }
+    // this thread's records (at most kAccPer), read once
+    float3 v[kAccPer];
+    float m = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kAccPer; ++j) {
+      const uint32_t r = rb + threadIdx.x + j * kAccBlock;
+      v[j] = r < re ? rec[r] : make_float3(0.0f, 0.0f, 0.0f);
+      m = fmaxf(m, fmaxf(fabsf(v[j].x), fabsf(v[j].y)));
+    }
+    for (int j = threadIdx.x; j < n2; j += kAccBlock) a2[j] = make_ulonglong2(0ull, 0ull);
+    // scale: |sum of the chunk's values| <= n max|v| < 2^(ex + 13) with
+    // max|v| < 2^ex and n <= 2^13 records, so 2^s with s = 47 - ex keeps
+    // every partial sum below 2^60
+    m = block_max(m, red);  // its barriers also order the clear above
+    int ex = 0;
+    frexpf(m, &ex);  // m < 2^ex (m = 0: ex = 0)
+    const int sc = 47 - ex;
+#pragma unroll
+    for (int j = 0; j < kAccPer; ++j) {
+      if (rb + threadIdx.x + j * kAccBlock < re) {
+        const uint32_t e = __float_as_uint(v[j].z);
+        atomicAdd(&acc[2 * e], to_fixed(v[j].x, sc));
+        atomicAdd(&acc[2 * e + 1], to_fixed(v[j].y, sc));
+      }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n4; j += kAccBlock) {
+      float4 o;
+      o.x = (float)ldexp((double)(long long)acc[4 * j], -sc);
+      o.y = (float)ldexp((double)(long long)acc[4 * j + 1], -sc);
+      o.z = (float)ldexp((double)(long long)acc[4 * j + 2], -sc);
+      o.w = (float)ldexp((double)(long long)acc[4 * j + 3], -sc);
+      if (nch == 1u) {  // the only writer of this tile
+        if (!overwrite) {
+          const float4 p = dst[j];
+          o.x += p.x;
+          o.y += p.y;
+          o.z += p.z;
+          o.w += p.w;
+        }
+        dst[j] = o;
+      } else {
+        float *df = reinterpret_cast<float *>(dst + j);
+        if (o.x != 0.0f) atomicAdd(df, o.x);
+        if (o.y != 0.0f) atomicAdd(df + 1, o.y);
+        if (o.z != 0.0f) atomicAdd(df + 2, o.z);
+        if (o.w != 0.0f) atomicAdd(df + 3, o.w);
+      }
+    }
+    __syncthreads();  // the sums are cleared for the next chunk
+  }
+}
+
 int32_t make_levels(int L, int log2T, double base, double growth, Levels *lv) {
   const uint64_t T = 1ull << log2T;
   for (int l = 0; l < L; ++l) {
@@ -508,5 +964,58 @@ extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float
     xgrad_sum_kernel<<<stride_grid(ceil_div(S, kBwdBlock), dev, 1024), kBwdBlock, 0, s>>>(part, S, S_dev, L, ld,
                                                                                            grad_xc);
   }
+  return launch_status();
+}
+
+extern "C" size_t ia355_hashgrid_table_grad_workspace_size(int64_t S, int32_t L, int32_t log2T) {
+  BinGeom g;
+  if (L <= 0 || L > 16 || !bin_geom(L, S, log2T, &g)) return 0;
+  return bin_ws(g, nullptr).bytes;
+}
+
+extern "C" int32_t ia355_hashgrid_table_grad(const float *grad_feat, const float *xc, const int16_t *bone, int64_t S,
+                                             const int64_t *S_dev, int64_t ld, int32_t L, int32_t F, int32_t log2T,
+                                             double base_res, double growth, const float *aabb, float *grad_table,
+                                             uint32_t flags, void *ws, size_t ws_bytes, ia355_stream_t stream) {
+  if (S < 0 || ld < S || L <= 0 || L > 16 || F != 2 || log2T < 2 || log2T > 30) return IA355_ERR_INVALID_ARG;
+  if (!grad_table || (S > 0 && (!grad_feat || !xc))) return IA355_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(grad_table) & 15) != 0) return IA355_ERR_INVALID_ARG;  // float4 tile stores
+  const uint32_t known = IA355_OVERWRITE | IA355_TABLE_COARSE | IA355_TABLE_FINE;
+  if (flags & ~known) return IA355_ERR_INVALID_ARG;
+  Levels lv;
+  Box box;
+  if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
+  BinGeom full;
+  if (!bin_geom(L, S, log2T, &full)) return IA355_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < bin_ws(full, nullptr).bytes) return IA355_ERR_WORKSPACE;
+  int ndense = 0;
+  while (ndense < L && lv.dense[ndense] && lv.res[ndense] <= kAggMaxRes) ++ndense;
+  const bool coarse = !(flags & IA355_TABLE_FINE) || (flags & IA355_TABLE_COARSE);
+  const bool fine = !(flags & IA355_TABLE_COARSE) || (flags & IA355_TABLE_FINE);
+  const int l0 = coarse ? 0 : ndense, l1 = fine ? L : ndense;
+  if (l1 <= l0) return IA355_OK;
+  const int overwrite = (flags & IA355_OVERWRITE) != 0;
+  hipStream_t s = as_stream(stream);
+  if (S == 0) {
+    if (!overwrite) return IA355_OK;
+    const size_t level_floats = 2 * ((size_t)1 << log2T);
+    return ia355_zero(grad_table + level_floats * l0, sizeof(float) * level_floats * (l1 - l0), stream);
+  }
+  BinGeom g;
+  bin_geom(l1 - l0, S, log2T, &g);  // fewer levels than `full`: fits its workspace
+  const BinWs w = bin_ws(g, ws);
+  const size_t cnt_lds = sizeof(uint32_t) * (size_t)g.nbins;
+  bin_count_kernel<<<g.P, kBinBlock, cnt_lds, s>>>(xc, bone, S, S_dev, ld, l0, l1 - l0, log2T, g.tb, lv, box, w.hist);
+  bin_hist_scan_kernel<<<g.nchunk, 1024, 0, s>>>(w.hist, g.H, w.csum);
+  bin_plan_kernel<<<1, 1024, 0, s>>>(w.hist, w.csum, g.nchunk, g.nbins, g.P, w.chunk_first,
+                                     w.chunk_info);
+  bin_scatter_kernel<<<g.P, kBinBlock, cnt_lds, s>>>(grad_feat, xc, bone, S, S_dev, ld, l0, l1 - l0, log2T, g.tb, lv,
+                                                     box, w.hist, w.csum, w.rec);
+  if (overwrite)
+    bin_clear_split_kernel<<<g.nbins < 1024 ? g.nbins : 1024, 256, 0, s>>>(w.chunk_first, g.nbins, l0, log2T, g.tb,
+                                                                           grad_table);
+  const unsigned acc_grid = (unsigned)(g.qmax < kAccMaxGrid ? g.qmax : kAccMaxGrid);
+  bin_accum_kernel<<<acc_grid, kAccBlock, sizeof(unsigned long long) * 2 * ((size_t)1 << g.tb), s>>>(
+      w.rec, w.chunk_first, w.chunk_info, g.nbins, l0, log2T, g.tb, overwrite, grad_table);
   return launch_status();
 }

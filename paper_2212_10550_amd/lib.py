@@ -69,6 +69,9 @@ _SIGS = {
     "hashgrid_encode_bwd_workspace_size": (_sz, [_i64, _i32]),
     "hashgrid_encode_bwd": (_i32, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i32, _i32, _i32, _i32, _d, _d, _fp, _vp, _vp,
                                    ctypes.c_uint32, _vp, _sz, _vp]),
+    "hashgrid_table_grad_workspace_size": (_sz, [_i64, _i32, _i32]),
+    "hashgrid_table_grad": (_i32, [_vp, _vp, _vp, _i64, _vp, _i64, _i32, _i32, _i32, _d, _d, _fp, _vp, ctypes.c_uint32,
+                                   _vp, _sz, _vp]),
     "mlp_fwd": (_i32, [_vp, _i32, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _vp, _vp]),
     "mlp_bwd_workspace_size": (_sz, [_i64]),
     "mlp_bwd": (_i32, [_vp, _vp, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _vp, ctypes.c_uint32, _vp, _sz, _vp]),
@@ -340,6 +343,24 @@ def hashgrid_encode_bwd(grad_feat, xc, bone, S, ld, table, base_res, growth, aab
         base_res, growth, _box(aabb), _p(grad_table, torch.float32, "grad_table"),
         _p(grad_xc, torch.float32, "grad_xc"), flags, _p(ws, name="ws"),
         0 if ws is None else ws.numel() * ws.element_size(), _stream()), "hashgrid_encode_bwd")
+
+
+def hashgrid_table_grad_workspace_size(S, L, T):
+    """Workspace bytes of hashgrid_table_grad for capacity S, L levels of T entries."""
+    if T <= 0 or T & (T - 1):
+        raise ValueError(f"T must be a power of two, got {T}")
+    return lib().ia355_hashgrid_table_grad_workspace_size(S, L, T.bit_length() - 1)
+
+
+def hashgrid_table_grad(grad_feat, xc, bone, S, ld, base_res, growth, aabb, grad_table, ws, flags=0, S_dev=None):
+    """Table gradient without global atomics (binned); grad_table [L, T, 2]
+    FP32; ws: hashgrid_table_grad_workspace_size(S, L, T) bytes."""
+    L, T, F = grad_table.shape
+    _check(lib().ia355_hashgrid_table_grad(
+        _p(grad_feat, torch.float32, "grad_feat"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S,
+        _p(S_dev, torch.int64, "S_dev"), ld, L, F, T.bit_length() - 1, base_res, growth, _box(aabb),
+        _p(grad_table, torch.float32, "grad_table"), flags, _p(ws, name="ws"),
+        0 if ws is None else ws.numel() * ws.element_size(), _stream()), "hashgrid_table_grad")
 
 
 def mlp_fwd(feat, bone, S, ld, params, dtype, sigma, rgb, S_dev=None):

@@ -55,8 +55,15 @@ class StageTimer:
 
 class Pipeline:
     def __init__(self, w, device="cuda", table_dtype=torch.float32, mlp_dtype=K.F32, cap=None,
-                 grad_W=True, grad_B=True, rootinit_params=None, rootinit_dtype=K.BF16, device_count=False):
+                 grad_W=True, grad_B=True, rootinit_params=None, rootinit_dtype=K.BF16, device_count=False,
+                 table_grad="binned"):
+        """table_grad: "binned" (records binned by table tile, summed in LDS,
+        no global atomics on the hashed levels) or "atomic" (FP32 global
+        atomics, coarse and fine level groups on two streams)."""
+        if table_grad not in ("binned", "atomic"):
+            raise ValueError(f"table_grad must be 'binned' or 'atomic', got {table_grad!r}")
         self.w = w
+        self.table_grad_mode = table_grad
         self.device_count = device_count
         self.graph, self.graph_kind = None, None
         # side streams of the backward (default priority): the coarse and the
@@ -130,6 +137,9 @@ class Pipeline:
         self.grad_xc = e(3, cap)
         # per-level partial position gradients (training workloads only)
         self.ws_xgrad = None if w.target is None else e(K.hashgrid_encode_bwd_workspace_size(cap, L), dt=torch.uint8)
+        self.ws_tgrad = None
+        if w.target is not None and table_grad == "binned":
+            self.ws_tgrad = e(K.hashgrid_table_grad_workspace_size(cap, L, self.table32.shape[1]), dt=torch.uint8)
         self.grad_xp = e(3, cap)
         self.grad_B = e(*self.B.shape) if grad_B else None
         self.grad_W = e(*self.W.shape) if grad_W else None
@@ -219,13 +229,25 @@ class Pipeline:
         """Table gradient of the level group (K.TABLE_COARSE, K.TABLE_FINE,
         or 0 for every level)."""
         w = self.w
+        if self.table_grad_mode == "binned":
+            if self.ws_tgrad is None:
+                L, T, _ = self.grad_table.shape
+                self.ws_tgrad = torch.empty(K.hashgrid_table_grad_workspace_size(self.cap, L, T), dtype=torch.uint8,
+                                            device=self.dev)
+            K.hashgrid_table_grad(self.grad_feat, self.xc, self.bone, S, self.cap, w.base_res, w.growth, w.hash_aabb,
+                                  self.grad_table, self.ws_tgrad, flags=(K.OVERWRITE if overwrite else 0) | group,
+                                  S_dev=Sd)
+            return
         K.hashgrid_encode_bwd(self.grad_feat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth,
                               w.hash_aabb, self.grad_table, None, flags=(K.OVERWRITE if overwrite else 0) | group,
                               S_dev=Sd)
 
     def _zero_table_async(self):
         """Clear the table gradient on the side stream (it overlaps the
-        forward); the backward's table gradient then adds to it."""
+        forward); the backward's table gradient then adds to it.  The binned
+        table gradient writes every entry itself, so it needs no clear."""
+        if self.table_grad_mode == "binned":
+            return
         self.side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(self.side):
             K.zero(self.grad_table)
@@ -274,13 +296,13 @@ class Pipeline:
 
     # ----------------------------------------------------------- backward
     def backward(self, S=None, Sd=None):
-        """Loss, composite and MLP backward, then three independent branches:
-        the hash-table gradient of the coarse levels and of the fine levels
-        on two side streams (disjoint slices of the table; the coarse levels
-        are bound by contention on few entries, the fine ones by atomic
-        throughput, so they overlap), and the position gradient followed by
-        the implicit-function-theorem backward on this stream; the side
-        streams join back before returning."""
+        """Loss, composite and MLP backward, then independent branches: the
+        hash-table gradient on a side stream (binned: every level in one
+        call; atomic: the coarse and the fine levels on two side streams,
+        disjoint slices of the table, the coarse levels bound by contention
+        on few entries and the fine ones by atomic throughput), and the
+        position gradient followed by the implicit-function-theorem backward
+        on this stream; the side streams join back before returning."""
         if S is None:
             S, Sd = self._last
         st = dict(self.stages(S, Sd))
@@ -302,6 +324,14 @@ class Pipeline:
             return
         main = torch.cuda.current_stream()
         self.side.wait_stream(main)
+        if self.table_grad_mode == "binned":
+            # every level in one binned call beside the position gradient
+            with torch.cuda.stream(self.side):
+                self._table_grad(S, Sd, overwrite=True)
+            st["hash_bwd_x"]()
+            st["deform_bwd"]()
+            main.wait_stream(self.side)
+            return
         self.side2.wait_stream(self.side)  # after the table clear (if any) and the MLP backward
         ow = not self._table_zeroed
         with torch.cuda.stream(self.side):

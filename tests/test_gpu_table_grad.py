@@ -1,0 +1,156 @@
+"""GPU parity of the binned (atomic-free) hash-table gradient against the FP64
+oracle and against the atomic path, through the C ABI.
+
+Bar: the table-gradient bar of the other backward tests,
+|gpu - oracle| <= 1e-4 * max(|oracle|, 1e-3 * max|oracle|); with T = 4
+entries per level (thousands of terms of either sign per entry) the error
+is bounded by 1e-6 of the sum of the terms' magnitudes instead.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2212_10550_amd import synth
+from tests.gpu_util import feat_dev, dev, host, soa, up
+from tests.test_gpu_backward import gclose
+
+pytestmark = pytest.mark.gpu
+
+AABB = (0, 0, 0, 1, 1, 1)
+AABB_NP = np.array([0, 0, 0, 1, 1, 1.0])
+
+
+def _K():
+    from paper_2212_10550_amd import lib as K
+    return K
+
+
+def _inputs(S, seed, log2T):
+    x = synth.random_points(S, seed)
+    gfeat = np.random.default_rng(seed + 1).normal(size=(S, 32)).astype(np.float32)
+    bone = np.where(np.arange(S) % 11 == 5, -1, 0).astype(np.int16)
+    table = np.zeros((16, 1 << log2T, 2), np.float32)  # the table gradient does not read it
+    return x, gfeat, bone, table
+
+
+@pytest.mark.parametrize("log2T,overwrite,pad,device_count", [
+    (14, True, 0, False), (19, False, 5, False), (19, True, 0, True), (21, False, 0, True), (12, True, 3, False),
+    (2, True, 0, False)])
+def test_table_grad_binned(orc, log2T, overwrite, pad, device_count):
+    """S = 6007 puts 48k records of level 0 in one tile (split over six
+    accumulation workgroups that add with atomics) and leaves ragged blocks;
+    T = 2^12 and 2^2 give a single tile per level; pad > 0 gives ld > S; with
+    a device count the capacity exceeds the count."""
+    K = _K()
+    S = 6007
+    x, gfeat, bone, table = _inputs(S, 51, log2T)
+    cap = S + 200 if device_count else S
+    ld = cap + pad
+    xp = np.concatenate([x, np.full((cap - S, 3), 0.5, np.float32)])
+    gp = np.concatenate([gfeat, np.ones((cap - S, 32), np.float32)])
+    bp = np.concatenate([bone, np.zeros(cap - S, np.int16)])
+    start = 7.0 if overwrite else 0.25
+    gt = torch.full((16, 1 << log2T, 2), start, device=dev())
+    ws = torch.empty(K.hashgrid_table_grad_workspace_size(cap, 16, 1 << log2T), dtype=torch.uint8, device=dev())
+    Sd = torch.tensor([S], dtype=torch.int64, device=dev()) if device_count else None
+    K.hashgrid_table_grad(feat_dev(gp, ld), soa(xp, ld), up(bp), cap, ld, 16.0, 1.38, AABB, gt, ws,
+                          K.OVERWRITE if overwrite else 0, S_dev=Sd)
+    torch.cuda.synchronize()
+    rt, _ = orc.hash_encode_bwd(gfeat, x, table, orc.resolutions(16), AABB_NP, valid=bone)
+    got = host(gt) - (0.0 if overwrite else start)
+    if log2T > 4:
+        gclose(got, rt, "grad_table (binned)")
+    else:
+        # ~12k terms of either sign per entry: FP32 summation error scales
+        # with the sum of the terms' magnitudes (the oracle's gradient of
+        # |dL/dfeat|, the weights being nonnegative), not with the result
+        absum, _ = orc.hash_encode_bwd(np.abs(gfeat), x, table, orc.resolutions(16), AABB_NP, valid=bone)
+        err = np.abs(got - rt) / absum
+        assert err.max() <= 1e-6, f"grad_table (binned, T=4): error {err.max():.2e} of the terms' magnitude sum"
+
+
+@pytest.mark.parametrize("overwrite", [False, True])
+def test_table_grad_binned_level_groups(orc, overwrite):
+    """Coarse and fine groups called separately (separate workspaces, as two
+    streams need); each leaves the other group's slice as it was."""
+    K = _K()
+    S, log2T = 5003, 19
+    x, gfeat, _, table = _inputs(S, 43, log2T)
+    res = orc.resolutions(16)
+    ncoarse = int(np.sum((np.asarray(res) <= 32) & ((np.asarray(res, dtype=np.int64) + 1) ** 3 <= (1 << log2T))))
+    assert 0 < ncoarse < 16
+    start = 7.0 if overwrite else 0.25
+    gt = torch.full((16, 1 << log2T, 2), start, device=dev())
+    nbytes = K.hashgrid_table_grad_workspace_size(S, 16, 1 << log2T)
+    ws1 = torch.empty(nbytes, dtype=torch.uint8, device=dev())
+    ws2 = torch.empty(nbytes, dtype=torch.uint8, device=dev())
+    args = (feat_dev(gfeat, S), soa(x, S), None, S, S, 16.0, 1.38, AABB, gt)
+    ow = K.OVERWRITE if overwrite else 0
+    K.hashgrid_table_grad(*args, ws1, ow | K.TABLE_COARSE)
+    torch.cuda.synchronize()
+    assert (host(gt[ncoarse:]) == start).all()
+    K.hashgrid_table_grad(*args, ws2, ow | K.TABLE_FINE)
+    torch.cuda.synchronize()
+    rt, _ = orc.hash_encode_bwd(gfeat, x, table, res, AABB_NP)
+    gclose(host(gt) - (0.0 if overwrite else start), rt, "grad_table (binned, two groups)")
+
+
+def test_table_grad_binned_vs_atomic_train_size():
+    """The training step's size (8192 rays of the synthetic frame, ~36.5k
+    posed samples, T = 2^19) on the pipeline's inputs: the binned and the
+    atomic table gradients agree to FP32 summation-order rounding."""
+    K = _K()
+    from paper_2212_10550_amd.pipeline import Pipeline
+    w = synth.train_step()
+    p = Pipeline(w, device="cuda:0")
+    S = p.forward()
+    p.backward()
+    torch.cuda.synchronize()
+    ref = torch.empty_like(p.grad_table)
+    K.hashgrid_encode_bwd(p.grad_feat, p.xc, p.bone, S, p.cap, p.table, w.base_res, w.growth, w.hash_aabb, ref, None,
+                          K.OVERWRITE)
+    got = torch.full_like(p.grad_table, 9.0)
+    L, T, _ = got.shape
+    ws = torch.empty(K.hashgrid_table_grad_workspace_size(p.cap, L, T), dtype=torch.uint8, device=dev())
+    K.hashgrid_table_grad(p.grad_feat, p.xc, p.bone, S, p.cap, w.base_res, w.growth, w.hash_aabb, got, ws,
+                          K.OVERWRITE)
+    torch.cuda.synchronize()
+    r = host(ref).astype(np.float64)
+    gclose(host(got), r, "grad_table binned vs atomic")
+    assert ((host(got) == 0) == (r == 0)).mean() > 0.999
+
+
+def test_table_grad_binned_empty():
+    """No samples: an overwrite clears the slice; an add leaves it; a device
+    count of 0 with a capacity behaves the same."""
+    K = _K()
+    log2T = 14
+    gt = torch.full((16, 1 << log2T, 2), 3.0, device=dev())
+    cap = 1000
+    ws = torch.empty(K.hashgrid_table_grad_workspace_size(cap, 16, 1 << log2T), dtype=torch.uint8, device=dev())
+    x = soa(synth.random_points(cap, 3), cap)
+    gf = torch.ones(16 * cap * 2, device=dev())
+    zero = torch.zeros(1, dtype=torch.int64, device=dev())
+    K.hashgrid_table_grad(gf, x, None, cap, cap, 16.0, 1.38, AABB, gt, ws, 0, S_dev=zero)
+    torch.cuda.synchronize()
+    assert (host(gt) == 3.0).all()
+    K.hashgrid_table_grad(gf, x, None, cap, cap, 16.0, 1.38, AABB, gt, ws, K.OVERWRITE | K.TABLE_FINE, S_dev=zero)
+    torch.cuda.synchronize()
+    g = host(gt)
+    fine0 = int(np.argmax(np.any(g == 0, axis=(1, 2))))
+    assert fine0 > 0 and (g[fine0:] == 0).all() and (g[:fine0] == 3.0).all()
+    K.hashgrid_table_grad(gf, x, None, 0, 0, 16.0, 1.38, AABB, gt, ws, K.OVERWRITE)
+    torch.cuda.synchronize()
+    assert (host(gt) == 0).all()
+
+
+def test_table_grad_binned_errors():
+    K = _K()
+    gt = torch.zeros((16, 1 << 14, 2), device=dev())
+    S = 100
+    x = soa(synth.random_points(S, 3), S)
+    gf = torch.ones(16 * S * 2, device=dev())
+    small = torch.empty(K.hashgrid_table_grad_workspace_size(S, 16, 1 << 14) - 256, dtype=torch.uint8, device=dev())
+    with pytest.raises(RuntimeError):
+        K.hashgrid_table_grad(gf, x, None, S, S, 16.0, 1.38, AABB, gt, small, K.OVERWRITE)
+    assert K.hashgrid_table_grad_workspace_size(S, 16, 1 << 23) == 0  # more than 16384 tiles

@@ -26,6 +26,14 @@ def test_march_workspace_covers_masks_and_scan():
 def test_backward_and_regulariser_workspaces():
     assert K.hashgrid_encode_bwd_workspace_size(36503, 16) >= 4 * 3 * 16 * 36503
     assert K.hashgrid_encode_bwd_workspace_size(-1, 16) == 0
+    # binned table gradient: 12-byte records, 8 per sample and level, dominate
+    n = K.hashgrid_table_grad_workspace_size(36503, 16, 1 << 19)
+    assert 12 * 8 * 16 * 36503 <= n < 12 * 8 * 16 * 36503 + (8 << 20)
+    assert K.hashgrid_table_grad_workspace_size(36503, 16, 1 << 22) > 0  # 16384 tiles of 4096 entries
+    assert K.hashgrid_table_grad_workspace_size(36503, 16, 1 << 23) == 0  # beyond the tile limit
+    assert K.hashgrid_table_grad_workspace_size(1 << 26, 16, 1 << 19) == 0  # 8 L S >= 2^32 records
+    with pytest.raises(ValueError):
+        K.hashgrid_table_grad_workspace_size(100, 16, 3 << 18)
     assert K.density_reg_workspace_size(10 ** 6) >= 4 * min(-(-10 ** 6 // 256), 1024)
     assert K.occgrid_build_workspace_size(64, 16, 2, K.F32, 64, 64, 32) >= 64 ** 3 * (12 + 12 + 4 + 12 + 2 + 128)
     assert K.occgrid_build_workspace_size(257, 16, 2, K.F32, 64, 64, 32) == 0

@@ -79,7 +79,8 @@ STAGE_KERNELS = {
     "render_fwd": ["render_fwd"],
     "loss+render_bwd": ["l2_loss_kernel", "render_bwd"],
     "mlp_bwd": ["mlp_bwd_f32", "mlp_bwd_bf16", "reduce_partials"],
-    "hash_bwd_table": ["table_grad_kernel", "table_grad_dense_kernel"],
+    "hash_bwd_table": ["bin_count_kernel", "bin_hist_scan_kernel", "bin_plan_kernel", "bin_scatter_kernel",
+                       "bin_clear_split_kernel", "bin_accum_kernel"],
     "hash_bwd_x": ["xgrad_level_kernel", "xgrad_sum_kernel"],
     "deform_bwd": ["ift_v_kernel", "ift_q_kernel", "ift_contract_kernel", "ift_b_kernel"],
 }
@@ -211,10 +212,6 @@ def roofline(stage_ms, S, R, steps_total, nb):
          "peak": r["peak"], "unit": r["unit"], "frac": r["frac"], "traffic": pmc_traffic(dom),
          "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
          "work_per_launch": r["work_per_launch"], "work_unit": r["work_unit"], "ms_per_launch": r["ms"]}
-    if dom == "hash_bwd_table":
-        r["limit"] = ("FP32 global atomic adds, performed memory-side at ~20 G sector requests/s for random "
-                      "addresses; the fine-level kernel alone sustains ~93 % of that rate (about 4.5 requests "
-                      "per sample and level), so HBM bandwidth is not what bounds it")
     return r, table
 
 

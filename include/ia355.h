@@ -60,6 +60,14 @@ extern "C" {
  * slices of grad_table, so they may run concurrently on two streams. */
 #define IA355_TABLE_COARSE 2u
 #define IA355_TABLE_FINE 4u
+/* Two-phase use of ia355_hashgrid_table_grad: IA355_TABLE_PLAN runs only
+ * the passes that depend on the positions (binning the corner updates by
+ * table tile); a later call with IA355_TABLE_REUSE_PLAN, the same workspace
+ * and the same positions, bones, count, sizes and level-group flags runs the
+ * rest.  The plan can so run as soon as the positions are known (during the
+ * forward), off the backward's critical path. */
+#define IA355_TABLE_PLAN 8u
+#define IA355_TABLE_REUSE_PLAN 16u
 
 #define IA355_F32 0
 #define IA355_F16 1
@@ -344,6 +352,10 @@ int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const
  *       (S is the capacity when S_dev is given); about 96 bytes per sample
  *       and level.  Calls that may run at the same time need separate
  *       workspaces.
+ * flags: IA355_OVERWRITE, a level group (IA355_TABLE_COARSE or _FINE) and
+ * IA355_TABLE_PLAN (grad_feat and grad_table may then be NULL; nothing is
+ * written but the workspace) or IA355_TABLE_REUSE_PLAN (xc, bone, S, S_dev
+ * must be those of the plan; their contents must not have changed).
  * Limits: L <= 16, L * 2^log2T <= 2^26 entries (at most 16384 tiles),
  * 8 L S < 2^32; otherwise IA355_ERR_INVALID_ARG (the workspace size is then
  * 0).  A workspace below the size returns IA355_ERR_WORKSPACE. */

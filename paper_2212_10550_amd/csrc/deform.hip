@@ -605,9 +605,14 @@ __global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restric
                                                         const int64_t *__restrict__ S_dev, int64_t ld,
                                                         const float *__restrict__ B, int nb,
                                                         const float *__restrict__ W, Grid gr, int w_vec4,
-                                                        float *__restrict__ gxp, float *__restrict__ vbuf) {
+                                                        float *__restrict__ gxp, float *__restrict__ vbuf,
+                                                        float4 *__restrict__ Qz, int64_t nq4) {
   __shared__ float sB[kMaxBones * 12];
   for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) sB[i] = B[i];
+  // the moment buffer of ift_q is cleared here (its stores hide behind the
+  // skinning-row gathers)
+  for (int64_t i = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x; i < nq4; i += (int64_t)gridDim.x * kBwdBlock)
+    Qz[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   __syncthreads();
   const int64_t Sn = count_of(S, S_dev);
   for (int64_t n = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x; n < Sn; n += (int64_t)gridDim.x * kBwdBlock)
@@ -619,26 +624,71 @@ __global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restric
 // slots j and j + 8 (< 12) of the corner's 12 floats.  A corner's 12 floats
 // are 48 contiguous bytes and x-neighbouring corners are adjacent vertices,
 // so each wave instruction touches about four cache lines (FP32 atomics to
-// random lines are limited by L2 requests, not by floats).
+// random lines are limited by L2 requests, not by floats).  A wave takes
+// kQRun consecutive samples in turn (samples of a ray follow each other, and
+// neighbouring samples often share a skinning-grid cell): contributions are
+// summed in registers while the cell stays the same and added to Q when it
+// changes, which saves the atomics of the repeats.
+constexpr int kQRun = 8;
+
 __global__ void __launch_bounds__(kOwnBlock) ift_q_kernel(const float *__restrict__ xc_soa,
                                                         const int16_t *__restrict__ bone, const float *__restrict__ vbuf,
                                                         int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                         Grid gr, float *__restrict__ Q) {
   const int64_t Sn = count_of(S, S_dev);
   const int lane = (int)(threadIdx.x & 63), k = lane >> 3, j = lane & 7;
-  constexpr int kPerBlock = kOwnBlock / 64;
-  for (int64_t n = ((int64_t)blockIdx.x * kOwnBlock + threadIdx.x) >> 6; n < Sn; n += (int64_t)gridDim.x * kPerBlock) {
-    if (bone[n] < 0) continue;
-    const float x[3] = {xc_soa[n], xc_soa[ld + n], xc_soa[2 * ld + n]};
-    const float v[3] = {vbuf[n], vbuf[S + n], vbuf[2 * S + n]};
-    const Cell c = locate(gr, x);
-    const int64_t vtx = ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] +
-                        (c.i0[0] + (k & 1));
-    const float tw = tri_weight(c.f, k);
-    const float xh[4] = {x[0], x[1], x[2], 1.0f};
-    float *q = Q + 12 * vtx;
-    atomicAdd(q + j, tw * v[j >> 2] * xh[j & 3]);
-    if (j < 4) atomicAdd(q + 8 + j, tw * v[2] * xh[j]);
+  constexpr int kWaves = kOwnBlock / 64;
+  const int64_t nruns = ceil_div(Sn, (int64_t)kQRun);
+  for (int64_t run = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); run < nruns;
+       run += (int64_t)gridDim.x * kWaves) {
+    // lane i < kQRun loads sample n0 + i; the samples are then taken in turn
+    const int64_t n0 = run * kQRun;
+    int lb = -1;
+    float lx[3] = {0.0f, 0.0f, 0.0f}, lv[3] = {0.0f, 0.0f, 0.0f};
+    if (lane < kQRun && n0 + lane < Sn) {
+      const int64_t n = n0 + lane;
+      lb = bone[n];
+      lx[0] = xc_soa[n];
+      lx[1] = xc_soa[ld + n];
+      lx[2] = xc_soa[2 * ld + n];
+      lv[0] = vbuf[n];
+      lv[1] = vbuf[S + n];
+      lv[2] = vbuf[2 * S + n];
+    }
+    int64_t cur = -1, cur_vtx = 0;
+    float a0 = 0.0f, a1 = 0.0f;
+    for (int i = 0; i < kQRun; ++i) {
+      if (__shfl(lb, i, kWave) < 0) continue;  // wave-uniform: invalid or past the count
+      const float x[3] = {__shfl(lx[0], i, kWave), __shfl(lx[1], i, kWave), __shfl(lx[2], i, kWave)};
+      const float v[3] = {__shfl(lv[0], i, kWave), __shfl(lv[1], i, kWave), __shfl(lv[2], i, kWave)};
+      const Cell c = locate(gr, x);
+      const int64_t base = ((int64_t)c.i0[2] * gr.D[1] + c.i0[1]) * gr.D[0] + c.i0[0];
+      const int64_t vtx = ((int64_t)(c.i0[2] + ((k >> 2) & 1)) * gr.D[1] + (c.i0[1] + ((k >> 1) & 1))) * gr.D[0] +
+                          (c.i0[0] + (k & 1));
+      const float tw = tri_weight(c.f, k);
+      const float xh[4] = {x[0], x[1], x[2], 1.0f};
+      const float c0 = tw * v[j >> 2] * xh[j & 3];
+      const float c1 = j < 4 ? tw * v[2] * xh[j] : 0.0f;
+      if (base != cur) {  // wave-uniform
+        if (cur >= 0) {
+          float *q = Q + 12 * cur_vtx;
+          atomicAdd(q + j, a0);
+          if (j < 4) atomicAdd(q + 8 + j, a1);
+        }
+        cur = base;
+        cur_vtx = vtx;
+        a0 = c0;
+        a1 = c1;
+      } else {
+        a0 += c0;
+        a1 += c1;
+      }
+    }
+    if (cur >= 0) {
+      float *q = Q + 12 * cur_vtx;
+      atomicAdd(q + j, a0);
+      if (j < 4) atomicAdd(q + 8 + j, a1);
+    }
   }
 }
 
@@ -710,10 +760,10 @@ __global__ void __launch_bounds__(kConThreads) ift_contract_kernel(const float *
   }
 }
 
-// Sum of the dL/dB block partials: 64 entries x 16 partial groups per
+// Sum of the dL/dB block partials: 16 entries x 64 partial groups per
 // workgroup, each group summed in double with four accumulators, the groups
 // combined in a fixed order.
-constexpr int kRedP = 64, kRedG = 16;
+constexpr int kRedP = 16, kRedG = 64;
 __global__ void __launch_bounds__(kRedP *kRedG) ift_b_kernel(const float *__restrict__ partB, int nblk, int n,
                                                              float *__restrict__ gB, int overwrite) {
   __shared__ double part[kRedG][kRedP];
@@ -908,16 +958,23 @@ extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc,
   float *vbuf = (float *)ws;
   float *Q = (float *)((char *)ws + align256(sizeof(float) * 3 * (size_t)S));
   float *partB = (float *)((char *)Q + align256(sizeof(float) * 12 * (size_t)nvert));
+  const bool params = grad_W || grad_B;
   if (S > 0) {
     const int w_vec4 = (nb % 4 == 0) && ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
+    // Q (12 floats per vertex, 256-byte aligned in the workspace) is cleared
+    // by this kernel when the parameter gradients are wanted
     ift_v_kernel<<<stride_grid(ceil_div(S, kBwdBlock), S_dev != nullptr), kBwdBlock, 0, s>>>(
-        grad_xc, xc, bone, S, S_dev, ld, B, nb, W, g, w_vec4, grad_xp, vbuf);
+        grad_xc, xc, bone, S, S_dev, ld, B, nb, W, g, w_vec4, grad_xp, vbuf, params ? (float4 *)Q : nullptr,
+        params ? 3 * nvert : 0);
   }
-  if (grad_W || grad_B) {
-    const int32_t st = ia355_zero(Q, sizeof(float) * 12 * (size_t)nvert, stream);
-    if (st != IA355_OK) return st;
+  if (params) {
+    if (S == 0) {
+      const int32_t st = ia355_zero(Q, sizeof(float) * 12 * (size_t)nvert, stream);
+      if (st != IA355_OK) return st;
+    }
     if (S > 0)
-      ift_q_kernel<<<stride_grid(ceil_div(S * 64, kOwnBlock), S_dev != nullptr, 8192), kOwnBlock, 0, s>>>(
+      ift_q_kernel<<<stride_grid(ceil_div(ceil_div(S, kQRun) * 64, kOwnBlock), S_dev != nullptr, 8192), kOwnBlock, 0,
+                     s>>>(
           xc, bone, vbuf, S, S_dev, ld, g, Q);
     ift_contract_kernel<<<(unsigned)nblk, kConThreads, 0, s>>>(Q, B, nb, W, nvert, grad_W, grad_B ? partB : nullptr,
                                                                overwrite);

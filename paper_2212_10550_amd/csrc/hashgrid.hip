@@ -977,11 +977,15 @@ extern "C" int32_t ia355_hashgrid_table_grad(const float *grad_feat, const float
                                              const int64_t *S_dev, int64_t ld, int32_t L, int32_t F, int32_t log2T,
                                              double base_res, double growth, const float *aabb, float *grad_table,
                                              uint32_t flags, void *ws, size_t ws_bytes, ia355_stream_t stream) {
-  if (S < 0 || ld < S || L <= 0 || L > 16 || F != 2 || log2T < 2 || log2T > 30) return IA355_ERR_INVALID_ARG;
-  if (!grad_table || (S > 0 && (!grad_feat || !xc))) return IA355_ERR_INVALID_ARG;
-  if ((reinterpret_cast<uintptr_t>(grad_table) & 15) != 0) return IA355_ERR_INVALID_ARG;  // float4 tile stores
-  const uint32_t known = IA355_OVERWRITE | IA355_TABLE_COARSE | IA355_TABLE_FINE;
+  const uint32_t known =
+      IA355_OVERWRITE | IA355_TABLE_COARSE | IA355_TABLE_FINE | IA355_TABLE_PLAN | IA355_TABLE_REUSE_PLAN;
   if (flags & ~known) return IA355_ERR_INVALID_ARG;
+  const bool plan_only = (flags & IA355_TABLE_PLAN) != 0, reuse = (flags & IA355_TABLE_REUSE_PLAN) != 0;
+  if (plan_only && reuse) return IA355_ERR_INVALID_ARG;
+  if (S < 0 || ld < S || L <= 0 || L > 16 || F != 2 || log2T < 2 || log2T > 30) return IA355_ERR_INVALID_ARG;
+  if (S > 0 && !xc) return IA355_ERR_INVALID_ARG;
+  if (!plan_only && (!grad_table || (S > 0 && !grad_feat))) return IA355_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(grad_table) & 15) != 0) return IA355_ERR_INVALID_ARG;  // float4 tile stores
   Levels lv;
   Box box;
   if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
@@ -997,7 +1001,7 @@ extern "C" int32_t ia355_hashgrid_table_grad(const float *grad_feat, const float
   const int overwrite = (flags & IA355_OVERWRITE) != 0;
   hipStream_t s = as_stream(stream);
   if (S == 0) {
-    if (!overwrite) return IA355_OK;
+    if (plan_only || !overwrite) return IA355_OK;
     const size_t level_floats = 2 * ((size_t)1 << log2T);
     return ia355_zero(grad_table + level_floats * l0, sizeof(float) * level_floats * (l1 - l0), stream);
   }
@@ -1005,10 +1009,13 @@ extern "C" int32_t ia355_hashgrid_table_grad(const float *grad_feat, const float
   bin_geom(l1 - l0, S, log2T, &g);  // fewer levels than `full`: fits its workspace
   const BinWs w = bin_ws(g, ws);
   const size_t cnt_lds = sizeof(uint32_t) * (size_t)g.nbins;
-  bin_count_kernel<<<g.P, kBinBlock, cnt_lds, s>>>(xc, bone, S, S_dev, ld, l0, l1 - l0, log2T, g.tb, lv, box, w.hist);
-  bin_hist_scan_kernel<<<g.nchunk, 1024, 0, s>>>(w.hist, g.H, w.csum);
-  bin_plan_kernel<<<1, 1024, 0, s>>>(w.hist, w.csum, g.nchunk, g.nbins, g.P, w.chunk_first,
-                                     w.chunk_info);
+  if (!reuse) {  // passes 1-3 read only the positions, the bones and the count
+    bin_count_kernel<<<g.P, kBinBlock, cnt_lds, s>>>(xc, bone, S, S_dev, ld, l0, l1 - l0, log2T, g.tb, lv, box,
+                                                     w.hist);
+    bin_hist_scan_kernel<<<g.nchunk, 1024, 0, s>>>(w.hist, g.H, w.csum);
+    bin_plan_kernel<<<1, 1024, 0, s>>>(w.hist, w.csum, g.nchunk, g.nbins, g.P, w.chunk_first, w.chunk_info);
+    if (plan_only) return launch_status();
+  }
   bin_scatter_kernel<<<g.P, kBinBlock, cnt_lds, s>>>(grad_feat, xc, bone, S, S_dev, ld, l0, l1 - l0, log2T, g.tb, lv,
                                                      box, w.hist, w.csum, w.rec);
   if (overwrite)

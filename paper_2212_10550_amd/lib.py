@@ -20,6 +20,8 @@ F32, F16, BF16 = 0, 1, 2
 OVERWRITE = 1  # backward flag: write gradients instead of adding to them
 TABLE_COARSE = 2  # hash-table gradient: only the coarse dense levels
 TABLE_FINE = 4  # hash-table gradient: only the other levels
+TABLE_PLAN = 8  # binned table gradient: only the passes that depend on the positions
+TABLE_REUSE_PLAN = 16  # binned table gradient: the rest, on a plan made before
 _DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 
 _vp = ctypes.c_void_p
@@ -354,7 +356,9 @@ def hashgrid_table_grad_workspace_size(S, L, T):
 
 def hashgrid_table_grad(grad_feat, xc, bone, S, ld, base_res, growth, aabb, grad_table, ws, flags=0, S_dev=None):
     """Table gradient without global atomics (binned); grad_table [L, T, 2]
-    FP32; ws: hashgrid_table_grad_workspace_size(S, L, T) bytes."""
+    FP32; ws: hashgrid_table_grad_workspace_size(S, L, T) bytes.  With
+    TABLE_PLAN only the position-dependent passes run (grad_feat may be
+    None); TABLE_REUSE_PLAN then runs the rest on the same positions."""
     L, T, F = grad_table.shape
     _check(lib().ia355_hashgrid_table_grad(
         _p(grad_feat, torch.float32, "grad_feat"), _p(xc, torch.float32, "xc"), _p(bone, torch.int16, "bone"), S,

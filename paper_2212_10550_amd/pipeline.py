@@ -225,9 +225,10 @@ class Pipeline:
         K.mlp_bwd(self.grad_sigma, self.grad_rgb, self.feat, self.bone, S, self.cap, self.params, self.mlp_dtype,
                   self.grad_params, self.grad_feat, self.ws_mlp, flags=K.OVERWRITE, S_dev=Sd)
 
-    def _table_grad(self, S, Sd, overwrite=True, group=0):
+    def _table_grad(self, S, Sd, overwrite=True, group=0, phase=0):
         """Table gradient of the level group (K.TABLE_COARSE, K.TABLE_FINE,
-        or 0 for every level)."""
+        or 0 for every level).  Binned mode: phase K.TABLE_PLAN runs only the
+        position-dependent passes, K.TABLE_REUSE_PLAN the rest."""
         w = self.w
         if self.table_grad_mode == "binned":
             if self.ws_tgrad is None:
@@ -235,8 +236,8 @@ class Pipeline:
                 self.ws_tgrad = torch.empty(K.hashgrid_table_grad_workspace_size(self.cap, L, T), dtype=torch.uint8,
                                             device=self.dev)
             K.hashgrid_table_grad(self.grad_feat, self.xc, self.bone, S, self.cap, w.base_res, w.growth, w.hash_aabb,
-                                  self.grad_table, self.ws_tgrad, flags=(K.OVERWRITE if overwrite else 0) | group,
-                                  S_dev=Sd)
+                                  self.grad_table, self.ws_tgrad,
+                                  flags=(K.OVERWRITE if overwrite else 0) | group | phase, S_dev=Sd)
             return
         K.hashgrid_encode_bwd(self.grad_feat, self.xc, self.bone, S, self.cap, self.table, w.base_res, w.growth,
                               w.hash_aabb, self.grad_table, None, flags=(K.OVERWRITE if overwrite else 0) | group,
@@ -326,6 +327,9 @@ class Pipeline:
         self.side.wait_stream(main)
         if self.table_grad_mode == "binned":
             # every level in one binned call beside the position gradient
+            # (its position passes could run earlier, TABLE_PLAN, but beside
+            # the forward or the MLP backward they slow those more than they
+            # save here)
             with torch.cuda.stream(self.side):
                 self._table_grad(S, Sd, overwrite=True)
             st["hash_bwd_x"]()

@@ -154,3 +154,33 @@ def test_table_grad_binned_errors():
     with pytest.raises(RuntimeError):
         K.hashgrid_table_grad(gf, x, None, S, S, 16.0, 1.38, AABB, gt, small, K.OVERWRITE)
     assert K.hashgrid_table_grad_workspace_size(S, 16, 1 << 23) == 0  # more than 16384 tiles
+
+
+def test_table_grad_binned_two_phase(orc):
+    """A plan made from the positions alone (no gradient given), then the
+    rest on that plan, gives the one-call result; a plan call writes nothing
+    to the table gradient."""
+    K = _K()
+    S, log2T = 6007, 19
+    x, gfeat, bone, table = _inputs(S, 61, log2T)
+    cap = S + 100
+    xp = np.concatenate([x, np.full((cap - S, 3), 0.5, np.float32)])
+    gp = np.concatenate([gfeat, np.ones((cap - S, 32), np.float32)])
+    bp = np.concatenate([bone, np.zeros(cap - S, np.int16)])
+    Sd = torch.tensor([S], dtype=torch.int64, device=dev())
+    ws = torch.empty(K.hashgrid_table_grad_workspace_size(cap, 16, 1 << log2T), dtype=torch.uint8, device=dev())
+    xs, bs, gf = soa(xp, cap), up(bp), feat_dev(gp, cap)
+    gt = torch.full((16, 1 << log2T, 2), 5.0, device=dev())
+    K.hashgrid_table_grad(None, xs, bs, cap, cap, 16.0, 1.38, AABB, gt, ws, K.TABLE_PLAN, S_dev=Sd)
+    torch.cuda.synchronize()
+    assert (host(gt) == 5.0).all()
+    K.hashgrid_table_grad(gf, xs, bs, cap, cap, 16.0, 1.38, AABB, gt, ws, K.OVERWRITE | K.TABLE_REUSE_PLAN, S_dev=Sd)
+    one = torch.full_like(gt, 5.0)
+    ws2 = torch.empty_like(ws)
+    K.hashgrid_table_grad(gf, xs, bs, cap, cap, 16.0, 1.38, AABB, one, ws2, K.OVERWRITE, S_dev=Sd)
+    torch.cuda.synchronize()
+    rt, _ = orc.hash_encode_bwd(gfeat, x, table, orc.resolutions(16), AABB_NP, valid=bone)
+    gclose(host(gt), rt, "grad_table (two-phase)")
+    gclose(host(gt), host(one).astype(np.float64), "two-phase vs one call")
+    with pytest.raises(RuntimeError):
+        K.hashgrid_table_grad(gf, xs, bs, cap, cap, 16.0, 1.38, AABB, gt, ws, K.TABLE_PLAN | K.TABLE_REUSE_PLAN)

@@ -678,8 +678,9 @@ def learned_init_leg(params, torch, np, K, synth, out, n_poses=64):
         "deform_ms_all_poses": {"learned_bf16_guided": ms_g, "multi_init_24": ms_m},
         "deform_samples_per_s": {"learned_bf16_guided": n / ms_g * 1e3, "multi_init_24": n / ms_m * 1e3},
         "deform_ms_all_poses_4_streams": {"learned_bf16_guided": ms_g4, "multi_init_24": ms_m4},
-        "timing": "one HIP graph per method with every pose's call in order; each call includes the per-pose "
-                  "blend of the skinning grid with the bone transforms (the same work in both methods)",
+        "timing": "one HIP graph per method with every pose's call in order (4_streams: the same calls spread "
+                  "over four streams inside the graph); each call includes the per-pose blend of the skinning grid "
+                  "with the bone transforms (the same work in both methods)",
     }
 
 

@@ -355,7 +355,9 @@ int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const
  * flags: IA355_OVERWRITE, a level group (IA355_TABLE_COARSE or _FINE) and
  * IA355_TABLE_PLAN (grad_feat and grad_table may then be NULL; nothing is
  * written but the workspace) or IA355_TABLE_REUSE_PLAN (xc, bone, S, S_dev
- * must be those of the plan; their contents must not have changed).
+ * must be those of the plan; their contents must not have changed).  A
+ * reuse without a matching plan gives wrong values; device-side checks keep
+ * every access inside the workspace and the selected slice of grad_table.
  * Limits: L <= 16, L * 2^log2T <= 2^26 entries (at most 16384 tiles),
  * 8 L S < 2^32; otherwise IA355_ERR_INVALID_ARG (the workspace size is then
  * 0).  A workspace below the size returns IA355_ERR_WORKSPACE. */

@@ -673,7 +673,7 @@ __global__ void __launch_bounds__(1024) bin_plan_kernel(const uint32_t *__restri
 __global__ void __launch_bounds__(kBinBlock) bin_scatter_kernel(
     const float *__restrict__ gfeat, const float *__restrict__ xc, const int16_t *__restrict__ bone, int64_t S,
     const int64_t *__restrict__ S_dev, int64_t ld, int l0, int nl, int log2T, int tb, Levels lv, Box box,
-    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ coff, float3 *__restrict__ rec) {
+    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ coff, float3 *__restrict__ rec, uint32_t rmax) {
   extern __shared__ uint32_t cur[];
   const int tpl_log2 = log2T - tb;
   const int nbins = nl << tpl_log2;
@@ -704,7 +704,8 @@ __global__ void __launch_bounds__(kBinBlock) bin_scatter_kernel(
           const uint32_t idx = corner_index(cp, k, N, dense, T - 1u);
           const float w = corner_weight(cp, k);
           const uint32_t pos = wave_reserve(cur, (b[j].lr << tpl_log2) + (int)(idx >> tb), b[j].act);
-          if (b[j].act) rec[pos] = make_float3(w * b[j].g.x, w * b[j].g.y, __uint_as_float(idx & emask));
+          if (b[j].act && pos < rmax)
+            rec[pos] = make_float3(w * b[j].g.x, w * b[j].g.y, __uint_as_float(idx & emask));
         }
       } else if (b[j].act) {
         uint32_t idx[8], pos[8];
@@ -716,7 +717,7 @@ __global__ void __launch_bounds__(kBinBlock) bin_scatter_kernel(
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const float w = corner_weight(cp, k);
-          rec[pos[k]] = make_float3(w * b[j].g.x, w * b[j].g.y, __uint_as_float(idx[k] & emask));
+          if (pos[k] < rmax) rec[pos[k]] = make_float3(w * b[j].g.x, w * b[j].g.y, __uint_as_float(idx[k] & emask));
         }
       }
     }
@@ -763,18 +764,21 @@ __device__ __forceinline__ unsigned long long to_fixed(float v, int s) {
 __global__ void __launch_bounds__(kAccBlock) bin_accum_kernel(const float3 *__restrict__ rec,
                                                              const uint32_t *__restrict__ chunk_first,
                                                              const uint4 *__restrict__ chunk_info, int nbins,
-                                                             int l0, int log2T, int tb, int overwrite,
-                                                             float *__restrict__ gtable) {
+                                                             uint32_t qmax, uint32_t rmax, int l0, int log2T, int tb,
+                                                             int overwrite, float *__restrict__ gtable) {
   extern __shared__ unsigned long long acc[];  // 2 E fixed-point sums
   __shared__ float red[kAccBlock / kWave];
   const int n2 = 1 << tb;  // entries of a tile (2 sums each)
   const int n4 = n2 / 2;   // float4 (2 entries) per tile
   ulonglong2 *a2 = reinterpret_cast<ulonglong2 *>(acc);
-  const uint32_t Q = chunk_first[nbins];
+  const uint32_t Q = chunk_first[nbins] < qmax ? chunk_first[nbins] : qmax;
   for (uint32_t q = blockIdx.x; q < Q; q += gridDim.x) {
     const uint4 ci = chunk_info[q];  // bin, first record, end, chunks of the bin
     const int b = (int)ci.x;
     const uint32_t rb = ci.y, re = ci.z, nch = ci.w;
+    // a plan from this workspace always passes; the checks keep a misused
+    // one (IA355_TABLE_REUSE_PLAN without a plan) inside the buffers
+    if (ci.x >= (uint32_t)nbins || rb > re || re > rmax || re - rb > kAccChunk) continue;
     float4 *dst = tile_ptr(gtable, b, l0, log2T, tb);
     if (rb == re) {  // no update in this tile (then nch == 1)
       if (overwrite)
@@ -801,7 +805,7 @@ __global__ void __launch_bounds__(kAccBlock) bin_accum_kernel(const float3 *__re
 #pragma unroll
     for (int j = 0; j < kAccPer; ++j) {
       if (rb + threadIdx.x + j * kAccBlock < re) {
-        const uint32_t e = __float_as_uint(v[j].z);
+        const uint32_t e = __float_as_uint(v[j].z) & (uint32_t)(n2 - 1);  // < E for every record written here
         atomicAdd(&acc[2 * e], to_fixed(v[j].x, sc));
         atomicAdd(&acc[2 * e + 1], to_fixed(v[j].y, sc));
       }
@@ -1017,12 +1021,13 @@ extern "C" int32_t ia355_hashgrid_table_grad(const float *grad_feat, const float
     if (plan_only) return launch_status();
   }
   bin_scatter_kernel<<<g.P, kBinBlock, cnt_lds, s>>>(grad_feat, xc, bone, S, S_dev, ld, l0, l1 - l0, log2T, g.tb, lv,
-                                                     box, w.hist, w.csum, w.rec);
+                                                     box, w.hist, w.csum, w.rec, (uint32_t)g.rmax);
   if (overwrite)
     bin_clear_split_kernel<<<g.nbins < 1024 ? g.nbins : 1024, 256, 0, s>>>(w.chunk_first, g.nbins, l0, log2T, g.tb,
                                                                            grad_table);
   const unsigned acc_grid = (unsigned)(g.qmax < kAccMaxGrid ? g.qmax : kAccMaxGrid);
   bin_accum_kernel<<<acc_grid, kAccBlock, sizeof(unsigned long long) * 2 * ((size_t)1 << g.tb), s>>>(
-      w.rec, w.chunk_first, w.chunk_info, g.nbins, l0, log2T, g.tb, overwrite, grad_table);
+      w.rec, w.chunk_first, w.chunk_info, g.nbins, (uint32_t)g.qmax, (uint32_t)g.rmax, l0, log2T, g.tb, overwrite,
+      grad_table);
   return launch_status();
 }

@@ -49,23 +49,6 @@ inline unsigned stride_grid(int64_t needed, bool device_count, int64_t cap_block
   return (unsigned)needed;
 }
 
-// Work ranges by XCD.  Workgroups are dispatched to the 8 XCDs round-robin
-// (block b runs on XCD b % 8) and each XCD has its own L2.  xcd_range gives
-// XCD k the k-th eighth of n_items as a grid-stride range over chunks of
-// per_block items, so each L2 holds the gathers of one contiguous part of
-// the items (samples ordered by ray: one band of the image) instead of all
-// of them.  gridDim.x must be a multiple of 8 (xcd_grid).
-struct XcdRange {
-  int64_t begin, end, step;
-};
-__device__ __forceinline__ XcdRange xcd_range(int64_t n_items, int64_t per_block) {
-  const int64_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, nslot = gridDim.x >> 3;
-  const int64_t per = ceil_div(ceil_div(n_items, per_block), (int64_t)8) * per_block;
-  const int64_t lo = xcd * per;
-  return {lo + slot * per_block, lo + per < n_items ? lo + per : n_items, nslot * per_block};
-}
-inline unsigned xcd_grid(unsigned blocks) { return (blocks + 7u) / 8u * 8u; }
-
 // Packed occupancy bits: bricks of 8 x 8 x 16 cells (x, y, z), 1024 bits =
 // one 128-byte cache line each, bricks in x-fastest order; inside a brick,
 // cell (lx, ly, lz) is bit lx + 8 ly + 64 lz.

@@ -324,10 +324,8 @@ __global__ void __launch_bounds__(kSolveBlock) solve_kernel(
   const int j = threadIdx.x % kGroup;
   constexpr int kPerBlock = kSolveBlock / kGroup;
   // every lane of a block runs the same iterations, so the groups' shuffles
-  // always see all eight lanes; each XCD takes a contiguous eighth of the
-  // samples (its L2 then holds the blended transforms of one image band)
-  const XcdRange rg = xcd_range(Sn, kPerBlock);
-  for (int64_t n0 = rg.begin; n0 < rg.end; n0 += rg.step) {
+  // always see all eight lanes
+  for (int64_t n0 = (int64_t)blockIdx.x * kPerBlock; n0 < Sn; n0 += (int64_t)gridDim.x * kPerBlock) {
     const int64_t n = n0 + threadIdx.x / kGroup;
     const bool act = n < Sn;
     float xp[3] = {0.0f, 0.0f, 0.0f};
@@ -617,13 +615,8 @@ __global__ void __launch_bounds__(kBwdBlock) ift_v_kernel(const float *__restric
     Qz[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   __syncthreads();
   const int64_t Sn = count_of(S, S_dev);
-  // each XCD a contiguous eighth of the samples (the skinning rows of one
-  // image band in its L2)
-  const XcdRange rg = xcd_range(Sn, kBwdBlock);
-  for (int64_t n0 = rg.begin; n0 < rg.end; n0 += rg.step) {
-    const int64_t n = n0 + threadIdx.x;
-    if (n < rg.end) ift_v_one(gxc, xc_soa, bone, n, S, ld, sB, nb, W, gr, w_vec4, gxp, vbuf);
-  }
+  for (int64_t n = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x; n < Sn; n += (int64_t)gridDim.x * kBwdBlock)
+    ift_v_one(gxc, xc_soa, bone, n, S, ld, sB, nb, W, gr, w_vec4, gxp, vbuf);
 }
 
 
@@ -843,7 +836,7 @@ extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, const int64_t 
     hb.lo[a] = hash_aabb[a];
     hb.hi[a] = hash_aabb[3 + a];
   }
-  solve_kernel<<<xcd_grid(stride_grid(ceil_div(S * kGroup, kSolveBlock), S_dev != nullptr)), kSolveBlock, 0, s>>>(
+  solve_kernel<<<stride_grid(ceil_div(S * kGroup, kSolveBlock), S_dev != nullptr), kSolveBlock, 0, s>>>(
       xp, S, S_dev, ld, B, nb, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps);
   return launch_status();
 }
@@ -970,7 +963,7 @@ extern "C" int32_t ia355_snarf_deform_bwd(const float *grad_xc, const float *xc,
     const int w_vec4 = (nb % 4 == 0) && ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
     // Q (12 floats per vertex, 256-byte aligned in the workspace) is cleared
     // by this kernel when the parameter gradients are wanted
-    ift_v_kernel<<<xcd_grid(stride_grid(ceil_div(S, kBwdBlock), S_dev != nullptr)), kBwdBlock, 0, s>>>(
+    ift_v_kernel<<<stride_grid(ceil_div(S, kBwdBlock), S_dev != nullptr), kBwdBlock, 0, s>>>(
         grad_xc, xc, bone, S, S_dev, ld, B, nb, W, g, w_vec4, grad_xp, vbuf, params ? (float4 *)Q : nullptr,
         params ? 3 * nvert : 0);
   }

@@ -129,11 +129,24 @@ class _Encode(torch.autograd.Function):
         S = xc.shape[1]
         grad_xc = _empty(3, S, like=xc) if ctx.needs_input_grad[0] else None
         grad_table = _empty(*table.shape, like=table) if ctx.needs_input_grad[2] else None
-        if grad_xc is not None or grad_table is not None:
-            ws = _empty(K.hashgrid_encode_bwd_workspace_size(S, table.shape[0]), dtype=torch.uint8, like=xc)
-            K.hashgrid_encode_bwd(grad_feat.contiguous(), xc, bone, S, S, table, cfg.base_res, cfg.growth, cfg.aabb,
-                                  grad_table, grad_xc, flags=K.OVERWRITE, ws=ws)
+        _hash_bwd(grad_feat.contiguous(), xc, bone, S, table, cfg, grad_table, grad_xc)
         return grad_xc, None, grad_table, None
+
+
+def _hash_bwd(grad_feat, xc, bone, S, table, cfg, grad_table, grad_xc):
+    """Position gradient (the table is read) and table gradient: binned
+    (ia355_hashgrid_table_grad) when the table's size is within its tile
+    limit, FP32 atomics otherwise."""
+    L, T = grad_table.shape[:2] if grad_table is not None else (table.shape[0], table.shape[1])
+    binned = grad_table is not None and K.hashgrid_table_grad_workspace_size(S, L, T) > 0
+    if grad_xc is not None or (grad_table is not None and not binned):
+        ws = _empty(K.hashgrid_encode_bwd_workspace_size(S, L), dtype=torch.uint8, like=xc)
+        K.hashgrid_encode_bwd(grad_feat, xc, bone, S, S, table, cfg.base_res, cfg.growth, cfg.aabb,
+                              None if binned else grad_table, grad_xc, flags=K.OVERWRITE, ws=ws)
+    if binned:
+        ws = _empty(K.hashgrid_table_grad_workspace_size(S, L, T), dtype=torch.uint8, like=xc)
+        K.hashgrid_table_grad(grad_feat, xc, bone, S, S, cfg.base_res, cfg.growth, cfg.aabb, grad_table, ws,
+                              K.OVERWRITE)
 
 
 def hash_encode(xc, bone, table, cfg: HashConfig):
@@ -201,10 +214,7 @@ class _Field(torch.autograd.Function):
                   grad_feat, ws, flags=K.OVERWRITE)
         grad_xc = _empty(3, S, like=xc) if ctx.needs_input_grad[0] else None
         grad_table = _empty(*tshape, like=xc) if ctx.needs_input_grad[2] else None
-        if grad_xc is not None or grad_table is not None:
-            ws = _empty(K.hashgrid_encode_bwd_workspace_size(S, tshape[0]), dtype=torch.uint8, like=xc)
-            K.hashgrid_encode_bwd(grad_feat, xc, bone, S, S, table_read, hcfg.base_res, hcfg.growth, hcfg.aabb,
-                                  grad_table, grad_xc, flags=K.OVERWRITE, ws=ws)
+        _hash_bwd(grad_feat, xc, bone, S, table_read, hcfg, grad_table, grad_xc)
         return (grad_xc, None, grad_table, grad_params if ctx.needs_input_grad[3] else None, None, None, None,
                 None)
 

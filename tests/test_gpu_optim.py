@@ -44,10 +44,10 @@ def test_loss_full_matches_oracle(with_alpha):
         assert err <= 1e-5, (what, err)
 
 
-@pytest.mark.parametrize("device_step", [False, True])
-def test_adam_matches_oracle(device_step):
+@pytest.mark.parametrize("device_step,n", [(False, 100003), (True, 100003), (False, 100004), (True, 100004)])
+def test_adam_matches_oracle(device_step, n):
+    """An odd and a multiple-of-4 parameter count."""
     K = _K()
-    n = 100003
     rng = np.random.default_rng(2)
     p = rng.standard_normal(n).astype(np.float32)
     g = (rng.standard_normal(n) * 1e-3).astype(np.float32)

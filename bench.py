@@ -611,10 +611,10 @@ def learned_init_leg(params, torch, np, K, synth, out, n_poses=64):
         steps_g += int(q["sg"].to(torch.int64).sum().item())
         steps_m += int(q["sm"].to(torch.int64).sum().item())
 
-    def graph_ms(fn, reps=5):
+    def graph_ms(fn, reps=5, plist=None):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            for q in poses:
+            for q in (poses if plist is None else plist):
                 fn(q)
         g.replay()
         torch.cuda.synchronize()
@@ -669,6 +669,31 @@ def learned_init_leg(params, torch, np, K, synth, out, n_poses=64):
         return a.elapsed_time(b) / reps
 
     ms_g4, ms_m4 = graph_ms_run(spread(guided_s)), graph_ms_run(spread(multi_s))
+
+    # 16 held-out poses at 65,536 points each, where the per-pose fixed
+    # costs no longer dominate (a frame has ~10^6 samples)
+    n_big = 16
+    big = rootinit.make_dataset(range(2000, 2000 + n_big), 65536, device="cuda:0")
+    bposes = []
+    for p in range(n_big):
+        xp = big["xp"][big["pose_index"] == p].T.contiguous()
+        S = xp.shape[1]
+        bposes.append(dict(xp=xp, S=S, B=big["B"][p].contiguous(), pose=big["pose"][p].contiguous(),
+                           xg=e(3, S), bg=e(S, dt=torch.int16), sg=e(S, dt=torch.int16),
+                           xm=e(3, S), bm=e(S, dt=torch.int16), sm=e(S, dt=torch.int16)))
+    del big
+    gdb = rootinit.GuidedDeform(params, w, max(q["S"] for q in bposes), device="cuda:0")
+
+    def guided_b(q):
+        gdb.run(q["xp"], q["S"], q["S"], q["pose"], q["B"], W_t, q["xg"], q["bg"], None, q["sg"])
+
+    fb_big = 0
+    for q in bposes:
+        guided_b(q)
+        torch.cuda.synchronize()
+        fb_big += int(gdb.n_fallback.item())
+    n_b = sum(q["S"] for q in bposes)
+    ms_gb, ms_mb = graph_ms(guided_b, plist=bposes), graph_ms(multi, plist=bposes)
     err = np.concatenate(errs)
     out["learned_init"] = {
         "held_out": f"{n_poses} poses (seeds 2000-{2000 + n_poses - 1}) x 4096 posed points = {n} samples",
@@ -678,6 +703,10 @@ def learned_init_leg(params, torch, np, K, synth, out, n_poses=64):
         "deform_ms_all_poses": {"learned_bf16_guided": ms_g, "multi_init_24": ms_m},
         "deform_samples_per_s": {"learned_bf16_guided": n / ms_g * 1e3, "multi_init_24": n / ms_m * 1e3},
         "deform_ms_all_poses_4_streams": {"learned_bf16_guided": ms_g4, "multi_init_24": ms_m4},
+        "large": {"held_out": f"{n_big} poses (seeds 2000-{2000 + n_big - 1}) x 65536 posed points = {n_b} samples",
+                  "fallback_rate": fb_big / max(n_b, 1),
+                  "deform_ms_all_poses": {"learned_bf16_guided": ms_gb, "multi_init_24": ms_mb},
+                  "speedup": ms_mb / ms_gb},
         "timing": "one HIP graph per method with every pose's call in order (4_streams: the same calls spread "
                   "over four streams inside the graph); each call includes the per-pose blend of the skinning grid "
                   "with the bone transforms (the same work in both methods)",

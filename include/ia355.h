@@ -340,13 +340,15 @@ int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const
  * binned by (level, table tile of 4096 entries), written once as 12-byte
  * records (the two FP32 values, the entry in the tile) and summed per tile
  * in LDS as exact 64-bit fixed point (a power-of-two scale per group of at
- * most 8192 records, chosen from its largest value), then converted back
- * and written with plain stores.  A tile whose bin holds more than 8192
+ * most 4096 records, chosen from its largest value), then converted back
+ * and written with plain stores.  A tile whose bin holds more than 4096
  * records is summed by several workgroups that add their nonzero entries
  * with FP32 atomics.  Every tile of the selected levels is written, so
  * IA355_OVERWRITE needs no separate clear.  A tile summed by one workgroup
  * does not depend on the order of its records; split tiles may vary in the
- * last bit from run to run.  Non-finite gradients are not supported.
+ * last bit from run to run.  NaN and infinite values are kept out of the
+ * fixed-point sums and added to their entries as FP32 values, so they
+ * propagate as with ia355_hashgrid_encode_bwd.
  *   grad_table: [L][T][F] FP32, 16-byte aligned, T = 2^log2T.
  *   ws: ia355_hashgrid_table_grad_workspace_size(S, L, log2T) bytes
  *       (S is the capacity when S_dev is given); about 96 bytes per sample

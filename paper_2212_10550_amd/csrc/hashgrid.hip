@@ -417,10 +417,11 @@ constexpr int kHsPer = 4;
 constexpr int kHsChunk = 1024 * kHsPer;
 constexpr int kMaxHsChunks = 4096;
 constexpr int kAccBlock = 1024;
-constexpr uint32_t kAccChunk = 8192;  // records per accumulation workgroup
+constexpr uint32_t kAccChunk = 4096;  // records per accumulation workgroup
 constexpr int kAccPer = kAccChunk / kAccBlock;  // records per thread, held in registers
+constexpr int kAccWr = (1 << (kTileLog2Max - 1)) / kAccBlock;  // float4 of a tile per thread
 constexpr int kAccMaxGrid = 2048;
-static_assert(kAccChunk <= (1u << 13) && kAccChunk % kAccBlock == 0, "bin_accum_kernel: scale and record slots");
+static_assert(kAccChunk <= (1u << 12) && kAccChunk % kAccBlock == 0, "bin_accum_kernel: scale and record slots");
 
 struct BinGeom {
   int tb;         // log2 entries per tile
@@ -744,16 +745,32 @@ __global__ void __launch_bounds__(256) bin_clear_split_kernel(const uint32_t *__
   }
 }
 
-__device__ __forceinline__ float block_max(float v, float *red) {
+// Block-wide max of v and OR of flag (1024 threads).
+__device__ __forceinline__ float block_max(float v, bool flag, float *red, int *redf, bool *any) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  const bool wf = __ballot(flag) != 0ull;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  if (lane == 0) red[wid] = v;
+  if (lane == 0) {
+    red[wid] = v;
+    redf[wid] = wf;
+  }
   __syncthreads();
   float m = 0.0f;
-  for (int w = 0; w < kAccBlock / kWave; ++w) m = fmaxf(m, red[w]);
+  int f = 0;
+  for (int w = 0; w < kAccBlock / kWave; ++w) {
+    m = fmaxf(m, red[w]);
+    f |= redf[w];
+  }
   __syncthreads();
+  *any = f != 0;
   return m;
+}
+
+// Four consecutive fixed-point sums back to FP32 (one rounding each).
+__device__ __forceinline__ float4 from_fixed4(const unsigned long long *a, int s) {
+  return make_float4((float)ldexp((double)(long long)a[0], -s), (float)ldexp((double)(long long)a[1], -s),
+                     (float)ldexp((double)(long long)a[2], -s), (float)ldexp((double)(long long)a[3], -s));
 }
 
 // v * 2^s rounded to an integer, as two's complement bits (|v| 2^s < 2^48)
@@ -768,6 +785,7 @@ __global__ void __launch_bounds__(kAccBlock) bin_accum_kernel(const float3 *__re
                                                              int overwrite, float *__restrict__ gtable) {
   extern __shared__ unsigned long long acc[];  // 2 E fixed-point sums
   __shared__ float red[kAccBlock / kWave];
+  __shared__ int redf[kAccBlock / kWave];
   const int n2 = 1 << tb;  // entries of a tile (2 sums each)
   const int n4 = n2 / 2;   // float4 (2 entries) per tile
   ulonglong2 *a2 = reinterpret_cast<ulonglong2 *>(acc);
@@ -785,20 +803,25 @@ __global__ void __launch_bounds__(kAccBlock) bin_accum_kernel(const float3 *__re
         for (int j = threadIdx.x; j < n4; j += kAccBlock) dst[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       continue;
     }
-    // this thread's records (at most kAccPer), read once
+    // this thread's records (at most kAccPer), read once; non-finite values
+    // stay out of the scale and the integer sums (added with atomics below)
     float3 v[kAccPer];
     float m = 0.0f;
+    bool odd = false;
 #pragma unroll
     for (int j = 0; j < kAccPer; ++j) {
       const uint32_t r = rb + threadIdx.x + j * kAccBlock;
       v[j] = r < re ? rec[r] : make_float3(0.0f, 0.0f, 0.0f);
-      m = fmaxf(m, fmaxf(fabsf(v[j].x), fabsf(v[j].y)));
+      const bool fx = isfinite(v[j].x), fy = isfinite(v[j].y);
+      m = fmaxf(m, fmaxf(fx ? fabsf(v[j].x) : 0.0f, fy ? fabsf(v[j].y) : 0.0f));
+      odd = odd || !fx || !fy;
     }
     for (int j = threadIdx.x; j < n2; j += kAccBlock) a2[j] = make_ulonglong2(0ull, 0ull);
-    // scale: |sum of the chunk's values| <= n max|v| < 2^(ex + 13) with
-    // max|v| < 2^ex and n <= 2^13 records, so 2^s with s = 47 - ex keeps
-    // every partial sum below 2^60
-    m = block_max(m, red);  // its barriers also order the clear above
+    // scale: |sum of the chunk's values| <= n max|v| < 2^(ex + 12) with
+    // max|v| < 2^ex and n <= 2^12 records, so 2^s with s = 47 - ex keeps
+    // every partial sum below 2^59
+    bool odd_tile;  // some value of the chunk is NaN or infinite
+    m = block_max(m, odd, red, redf, &odd_tile);  // its barriers also order the clear above
     int ex = 0;
     frexpf(m, &ex);  // m < 2^ex (m = 0: ex = 0)
     const int sc = 47 - ex;
@@ -806,17 +829,41 @@ __global__ void __launch_bounds__(kAccBlock) bin_accum_kernel(const float3 *__re
     for (int j = 0; j < kAccPer; ++j) {
       if (rb + threadIdx.x + j * kAccBlock < re) {
         const uint32_t e = __float_as_uint(v[j].z) & (uint32_t)(n2 - 1);  // < E for every record written here
-        atomicAdd(&acc[2 * e], to_fixed(v[j].x, sc));
-        atomicAdd(&acc[2 * e + 1], to_fixed(v[j].y, sc));
+        if (isfinite(v[j].x)) atomicAdd(&acc[2 * e], to_fixed(v[j].x, sc));
+        if (isfinite(v[j].y)) atomicAdd(&acc[2 * e + 1], to_fixed(v[j].y, sc));
       }
     }
-    __syncthreads();
+    // NaN or infinite values (kept out of the integer sums) are added to a
+    // float copy of the tile in LDS, so they reach their own entries as FP32
+    // adds would; only chunks that hold such a value take this path
+    float *fv = reinterpret_cast<float *>(acc);
+    __syncthreads();  // the integer adds are complete
+    if (odd_tile) {
+      float4 tmp[kAccWr];
+#pragma unroll
+      for (int q = 0; q < kAccWr; ++q) {
+        const int j = threadIdx.x + q * kAccBlock;
+        if (j < n4) tmp[q] = from_fixed4(acc + 4 * j, sc);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kAccWr; ++q) {
+        const int j = threadIdx.x + q * kAccBlock;
+        if (j < n4) reinterpret_cast<float4 *>(fv)[j] = tmp[q];
+      }
+      __syncthreads();
+      // the records again (from cache): keeping them in registers across
+      // the write-out would cost occupancy on every chunk
+      for (uint32_t r = rb + threadIdx.x; r < re; r += kAccBlock) {
+        const float3 w = rec[r];
+        const uint32_t e = __float_as_uint(w.z) & (uint32_t)(n2 - 1);
+        if (!isfinite(w.x)) atomicAdd(&fv[2 * e], w.x);
+        if (!isfinite(w.y)) atomicAdd(&fv[2 * e + 1], w.y);
+      }
+      __syncthreads();
+    }
     for (int j = threadIdx.x; j < n4; j += kAccBlock) {
-      float4 o;
-      o.x = (float)ldexp((double)(long long)acc[4 * j], -sc);
-      o.y = (float)ldexp((double)(long long)acc[4 * j + 1], -sc);
-      o.z = (float)ldexp((double)(long long)acc[4 * j + 2], -sc);
-      o.w = (float)ldexp((double)(long long)acc[4 * j + 3], -sc);
+      float4 o = odd_tile ? reinterpret_cast<const float4 *>(fv)[j] : from_fixed4(acc + 4 * j, sc);
       if (nch == 1u) {  // the only writer of this tile
         if (!overwrite) {
           const float4 p = dst[j];

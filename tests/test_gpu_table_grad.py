@@ -37,7 +37,7 @@ def _inputs(S, seed, log2T):
     (14, True, 0, False), (19, False, 5, False), (19, True, 0, True), (21, False, 0, True), (12, True, 3, False),
     (2, True, 0, False)])
 def test_table_grad_binned(orc, log2T, overwrite, pad, device_count):
-    """S = 6007 puts 48k records of level 0 in one tile (split over six
+    """S = 6007 puts 48k records of level 0 in one tile (split over twelve
     accumulation workgroups that add with atomics) and leaves ragged blocks;
     T = 2^12 and 2^2 give a single tile per level; pad > 0 gives ld > S; with
     a device count the capacity exceeds the count."""
@@ -207,3 +207,29 @@ def test_pipeline_binned_and_atomic_steps_agree():
     gclose(b[0], a[0], "grad_table binned vs atomic (step)")
     gclose(b[1], a[1], "grad_params binned vs atomic (step)")
     gclose(b[2], a[2], "grad_B binned vs atomic (step)")
+
+
+def test_table_grad_binned_nonfinite(orc):
+    """A NaN and an infinite feature gradient reach exactly the entries of
+    their samples' corners (as FP32 adds would); every other entry matches
+    the oracle at the gradient bar."""
+    K = _K()
+    S, log2T = 3001, 14
+    x, gfeat, bone, table = _inputs(S, 71, log2T)
+    gfeat[100, 2 * 9] = np.nan      # sample 100, level 9, feature 0
+    gfeat[2000, 2 * 12 + 1] = np.inf  # sample 2000, level 12, feature 1
+    bone[[100, 2000]] = 0
+    gt = torch.full((16, 1 << log2T, 2), 7.0, device=dev())
+    ws = torch.empty(K.hashgrid_table_grad_workspace_size(S, 16, 1 << log2T), dtype=torch.uint8, device=dev())
+    K.hashgrid_table_grad(feat_dev(gfeat, S), soa(x, S), up(bone), S, S, 16.0, 1.38, AABB, gt, ws, K.OVERWRITE)
+    torch.cuda.synchronize()
+    got = host(gt).astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        rt, _ = orc.hash_encode_bwd(gfeat, x, table, orc.resolutions(16), AABB_NP, valid=bone)
+    assert np.array_equal(np.isnan(got), np.isnan(rt))
+    assert np.array_equal(np.isposinf(got), np.isposinf(rt)) and np.isposinf(got).any()
+    fin = np.isfinite(rt)
+    clean = np.asarray(gfeat, np.float64).copy()
+    clean[~np.isfinite(clean)] = 0.0
+    rc, _ = orc.hash_encode_bwd(clean, x, table, orc.resolutions(16), AABB_NP, valid=bone)
+    gclose(np.where(fin, got, 0.0), np.where(fin, rc, 0.0), "grad_table (finite entries)")

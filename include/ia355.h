@@ -51,6 +51,7 @@ extern "C" {
 #define IA355_ERR_WORKSPACE 2   /* workspace smaller than *_workspace_size() */
 #define IA355_ERR_UNSUPPORTED 3 /* valid but unimplemented combination */
 #define IA355_ERR_HIP 4         /* a HIP launch failed; see ia355_error_string */
+#define IA355_ERR_SCRATCH 5     /* the problem exceeds the fixed scratch of an allocation-free entry point */
 
 /* flags of the backward entry points */
 #define IA355_OVERWRITE 1u /* write the gradient instead of adding to it */
@@ -214,6 +215,23 @@ int32_t ia355_snarf_deform(const float *xp, int64_t S, const int64_t *S_dev, int
                            int32_t max_iter, float tol_stop, float tol_valid,
                            float *xc, int16_t *bone, float *resid, int16_t *steps,
                            void *ws, size_t ws_bytes, ia355_stream_t stream);
+
+/* Allocation-free form of ia355_snarf_deform, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments minus the workspace and
+ * the same results, bit for bit: the blended transform grid lives in a
+ * library-owned device array of IA355_DEFORM_NOALLOC_MAX_VERTS vertices x 12
+ * floats (6 MiB), which each GPU the library runs on holds until the process
+ * ends.  The call allocates and frees nothing.  Dx * Dy * Dz above the limit
+ * returns IA355_ERR_SCRATCH.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (on different streams, or from several host
+ * threads) race and must be serialised by the caller. */
+#define IA355_DEFORM_NOALLOC_MAX_VERTS (1 << 17) /* e.g. a 64 x 64 x 32 skinning grid */
+int32_t ia355_snarf_deform_noalloc(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld,
+                                   const float *B, int32_t nb, const float *W, int32_t Dx, int32_t Dy, int32_t Dz,
+                                   const float *skin_aabb, const float *hash_aabb, int32_t max_iter, float tol_stop,
+                                   float tol_valid, float *xc, int16_t *bone, float *resid, int16_t *steps,
+                                   ia355_stream_t stream);
 
 /* Backward through the root finder by the implicit function theorem (no
  * unrolling of Broyden): with J = dg/dx at x* and v = J^{-T} grad_xc,

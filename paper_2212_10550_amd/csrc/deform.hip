@@ -12,6 +12,8 @@
 //    Broyden solves in FP32 registers and pick the lowest residual with
 //    shuffles; bone inverses are staged in LDS once per block; the blended
 //    grid is read through the vector L1/L2 with float4 gathers.
+#include <mutex>
+
 #include "common.h"
 #include "geometry.h"
 
@@ -815,19 +817,25 @@ extern "C" size_t ia355_deform_workspace_size(int32_t Dx, int32_t Dy, int32_t Dz
   return align256(sizeof(float) * 12 * (size_t)Dx * Dy * Dz);
 }
 
-extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld, const float *B,
-                                      int32_t nb,
-                                      const float *W, int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
-                                      const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
-                                      float *xc, int16_t *bone, float *resid, int16_t *steps, void *ws,
-                                      size_t ws_bytes, ia355_stream_t stream) {
+namespace {
+
+// Argument checks shared by ia355_snarf_deform and its allocation-free form.
+int32_t deform_args_ok(const float *xp, int64_t S, int64_t ld, const float *B, int32_t nb, const float *W, int32_t Dx,
+                       int32_t Dy, int32_t Dz, const float *skin_aabb, const float *hash_aabb, int32_t max_iter,
+                       const float *xc, const int16_t *bone) {
   if (S < 0 || ld < S || nb <= 0 || nb > kMaxBones || max_iter < 0 || max_iter > 1000) return IA355_ERR_INVALID_ARG;
   if (!B || !W || !grid_ok(Dx, Dy, Dz, skin_aabb) || !hash_aabb) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!xp || !xc || !bone)) return IA355_ERR_INVALID_ARG;
-  if (!ws || ws_bytes < ia355_deform_workspace_size(Dx, Dy, Dz)) return IA355_ERR_WORKSPACE;
-  hipStream_t s = as_stream(stream);
+  return IA355_OK;
+}
+
+// Blend, then the multi-init solve, with the blended grid A (12 floats per
+// vertex) in device memory the caller of this function provides.
+int32_t deform_launch(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld, const float *B, int32_t nb,
+                      const float *W, int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
+                      const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid, float *xc,
+                      int16_t *bone, float *resid, int16_t *steps, float *A, hipStream_t s) {
   const int64_t nvert = (int64_t)Dx * Dy * Dz;
-  float *A = (float *)ws;
   blend_kernel<<<(unsigned)ceil_div(nvert, 256), 256, 0, s>>>(W, B, nb, nvert, A);
   if (S == 0) return launch_status();
   const Grid g = make_grid(Dx, Dy, Dz, skin_aabb);
@@ -839,6 +847,77 @@ extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, const int64_t 
   solve_kernel<<<stride_grid(ceil_div(S * kGroup, kSolveBlock), S_dev != nullptr), kSolveBlock, 0, s>>>(
       xp, S, S_dev, ld, B, nb, A, g, hb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps);
   return launch_status();
+}
+
+}  // namespace
+
+extern "C" int32_t ia355_snarf_deform(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld, const float *B,
+                                      int32_t nb,
+                                      const float *W, int32_t Dx, int32_t Dy, int32_t Dz, const float *skin_aabb,
+                                      const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid,
+                                      float *xc, int16_t *bone, float *resid, int16_t *steps, void *ws,
+                                      size_t ws_bytes, ia355_stream_t stream) {
+  const int32_t st = deform_args_ok(xp, S, ld, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter, xc, bone);
+  if (st != IA355_OK) return st;
+  if (!ws || ws_bytes < ia355_deform_workspace_size(Dx, Dy, Dz)) return IA355_ERR_WORKSPACE;
+  return deform_launch(xp, S, S_dev, ld, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid,
+                       xc, bone, resid, steps, (float *)ws, as_stream(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free form: the blended grid lives in `scratch`, a file-scope
+// device array of IA355_DEFORM_NOALLOC_MAX_VERTS vertices (each GPU the
+// library runs on holds its own copy until the process ends).  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in,
+// not a device address): the first call on a device looks its address up
+// with hipGetSymbolAddress, with that device current, and keeps it per
+// device.  The blend kernel overwrites every vertex the solve reads, so
+// nothing has to be cleared between calls; calls that overlap on one GPU
+// share the array and race.
+static __device__ __align__(256) float scratch[12 * (size_t)IA355_DEFORM_NOALLOC_MAX_VERTS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on device `dev`, looked up once per device.
+int32_t scratch_address(int dev, float **out) {
+  static std::mutex mu;
+  static float *addr[kMaxDevices] = {};
+  if (dev < 0 || dev >= kMaxDevices) return IA355_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return IA355_ERR_HIP;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return IA355_ERR_HIP;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev && hipSetDevice(cur) != hipSuccess) return IA355_ERR_HIP;
+    if (e != hipSuccess || !p) return IA355_ERR_HIP;
+    addr[dev] = (float *)p;
+  }
+  *out = addr[dev];
+  return IA355_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t ia355_snarf_deform_noalloc(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld,
+                                              const float *B, int32_t nb, const float *W, int32_t Dx, int32_t Dy,
+                                              int32_t Dz, const float *skin_aabb, const float *hash_aabb,
+                                              int32_t max_iter, float tol_stop, float tol_valid, float *xc,
+                                              int16_t *bone, float *resid, int16_t *steps, ia355_stream_t stream) {
+  int32_t st = deform_args_ok(xp, S, ld, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter, xc, bone);
+  if (st != IA355_OK) return st;
+  if ((int64_t)Dx * Dy * Dz > (int64_t)IA355_DEFORM_NOALLOC_MAX_VERTS) return IA355_ERR_SCRATCH;
+  hipStream_t s = as_stream(stream);
+  int dev = -1;
+  if ((s ? hipStreamGetDevice(s, &dev) : hipGetDevice(&dev)) != hipSuccess) return IA355_ERR_HIP;
+  float *A = nullptr;
+  st = scratch_address(dev, &A);
+  if (st != IA355_OK) return st;
+  return deform_launch(xp, S, S_dev, ld, B, nb, W, Dx, Dy, Dz, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid,
+                       xc, bone, resid, steps, A, s);
 }
 
 extern "C" int32_t ia355_snarf_deform_roots(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld,

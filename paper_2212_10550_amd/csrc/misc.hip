@@ -13,6 +13,7 @@ extern "C" const char *ia355_error_string(int32_t s) {
     case IA355_ERR_WORKSPACE: return "workspace too small";
     case IA355_ERR_UNSUPPORTED: return "unsupported combination of arguments";
     case IA355_ERR_HIP: return "HIP launch error";
+    case IA355_ERR_SCRATCH: return "problem larger than the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }

@@ -60,6 +60,8 @@ _SIGS = {
     "deform_workspace_size": (_sz, [_i32, _i32, _i32]),
     "snarf_deform": (_i32, [_vp, _i64, _vp, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _vp, _vp,
                             _vp, _vp, _sz, _vp]),
+    "snarf_deform_noalloc": (_i32, [_vp, _i64, _vp, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp,
+                                    _vp, _vp, _vp, _vp]),
     "deform_bwd_workspace_size": (_sz, [_i64, _i32, _i32, _i32, _i32]),
     "snarf_deform_bwd": (_i32, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _vp, _vp, _vp,
                                 ctypes.c_uint32, _vp, _sz, _vp]),
@@ -281,6 +283,21 @@ def snarf_deform(xp, S, ld, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_
         _box(skin_aabb), _box(hash_aabb), max_iter, tol_stop, tol_valid, _p(xc, torch.float32, "xc"),
         _p(bone, torch.int16, "bone"), _p(resid, torch.float32, "resid"), _p(steps, torch.int16, "steps"),
         _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "snarf_deform")
+
+
+DEFORM_NOALLOC_MAX_VERTS = 1 << 17  # IA355_DEFORM_NOALLOC_MAX_VERTS
+
+
+def snarf_deform_noalloc(xp, S, ld, B, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, xc, bone, resid, steps,
+                         S_dev=None):
+    """ia355_snarf_deform without a workspace (library-owned scratch)."""
+    Dz, Dy, Dx, nb = W.shape
+    _check(lib().ia355_snarf_deform_noalloc(
+        _p(xp, torch.float32, "xp"), S, _p(S_dev, torch.int64, "S_dev"), ld, _p(B, torch.float32, "B"), nb,
+        _p(W, torch.float32, "W"), Dx, Dy, Dz,
+        _box(skin_aabb), _box(hash_aabb), max_iter, tol_stop, tol_valid, _p(xc, torch.float32, "xc"),
+        _p(bone, torch.int16, "bone"), _p(resid, torch.float32, "resid"), _p(steps, torch.int16, "steps"),
+        _stream()), "snarf_deform_noalloc")
 
 
 def deform_bwd_workspace_size(S, Dx, Dy, Dz, nb):

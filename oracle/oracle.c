@@ -612,8 +612,35 @@ static void mlp_layer_offsets(const int32_t *widths, int32_t n_layers, int64_t *
     }
 }
 
+/* BF16 storage (the reduced-precision form; the paper fixes no precision,
+ * so a decision taken on a stored value -- a ReLU mask -- is taken on the
+ * value the kernels store, in their precision): x is rounded to IEEE single,
+ * then to the nearest bfloat16 (8 significant bits), ties to even. */
+static double round_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, sizeof u);
+    if ((u & 0x7f800000u) != 0x7f800000u) {   /* finite: round the low 16 bits away */
+        u += 0x7fffu + ((u >> 16) & 1u);
+        u &= 0xffff0000u;
+    } else if (u & 0x007fffffu) {
+        u |= 0x00400000u;                      /* NaN stays NaN */
+        u &= 0xffff0000u;
+    }
+    memcpy(&f, &u, sizeof f);
+    return (double)f;
+}
+
+static double store_act(double x, int32_t bf16) { return bf16 ? round_bf16(x) : x; }
+
+/* bf16 != 0: the BF16 storage form.  The input features and every stored
+ * activation are bfloat16 (the features are rounded on input, each hidden
+ * activation after its ReLU), and every weight matrix is used rounded to
+ * bfloat16; biases stay as given and the sums are exact (FP64).  With
+ * bf16 == 0 every value is FP64. */
 void oracle_mlp_fwd(const double *feat, const int32_t *valid, int64_t S, const double *params,
-                    const int32_t *widths, int32_t n_layers, double *sigma, double *rgb)
+                    const int32_t *widths, int32_t n_layers, int32_t bf16, double *sigma, double *rgb)
 {
     int64_t offW[16], offb[16];
     mlp_layer_offsets(widths, n_layers, offW, offb);
@@ -625,13 +652,13 @@ void oracle_mlp_fwd(const double *feat, const int32_t *valid, int64_t S, const d
             rgb[3 * n] = rgb[3 * n + 1] = rgb[3 * n + 2] = 0.0;
             continue;
         }
-        for (int i = 0; i < widths[0]; ++i) a[i] = feat[n * widths[0] + i];
+        for (int i = 0; i < widths[0]; ++i) a[i] = store_act(feat[n * widths[0] + i], bf16);
         for (int l = 0; l < n_layers; ++l) {
             const double *Wl = params + offW[l], *bl = params + offb[l];
             for (int o = 0; o < widths[l + 1]; ++o) {
                 double z = bl[o];
-                for (int i = 0; i < widths[l]; ++i) z += Wl[(int64_t)o * widths[l] + i] * a[i];
-                h[o] = (l < n_layers - 1 && z < 0.0) ? 0.0 : z;
+                for (int i = 0; i < widths[l]; ++i) z += store_act(Wl[(int64_t)o * widths[l] + i], bf16) * a[i];
+                h[o] = l < n_layers - 1 ? store_act(z < 0.0 ? 0.0 : z, bf16) : z;
             }
             memcpy(a, h, sizeof(double) * widths[l + 1]);
         }
@@ -640,26 +667,31 @@ void oracle_mlp_fwd(const double *feat, const int32_t *valid, int64_t S, const d
     }
 }
 
-/* grad_params accumulated (+=); grad_feat [S][widths[0]] overwritten. */
+/* grad_params accumulated (+=); grad_feat [S][widths[0]] overwritten.
+ * bf16 != 0: the BF16 storage form of the forward above; each layer's
+ * backpropagated delta, after its ReLU mask (taken on the pre-activation),
+ * is stored as bfloat16 where it multiplies (the weight-gradient products
+ * and the product with the layer's rounded weights), while the bias
+ * gradients sum the deltas unrounded. */
 void oracle_mlp_bwd(const double *grad_sigma, const double *grad_rgb, const double *feat, const int32_t *valid,
-                    int64_t S, const double *params, const int32_t *widths, int32_t n_layers,
+                    int64_t S, const double *params, const int32_t *widths, int32_t n_layers, int32_t bf16,
                     double *grad_params, double *grad_feat)
 {
     int64_t offW[16], offb[16];
     mlp_layer_offsets(widths, n_layers, offW, offb);
     for (int64_t n = 0; n < S; ++n) {
-        double act[17][MAXW], pre[16][MAXW], d[MAXW], dn[MAXW];
+        double act[17][MAXW], pre[16][MAXW], d[MAXW], dn[MAXW], dq[MAXW];
         double *gfeat = grad_feat + n * widths[0];
         for (int i = 0; i < widths[0]; ++i) gfeat[i] = 0.0;
         if (valid && valid[n] < 0) continue;
-        for (int i = 0; i < widths[0]; ++i) act[0][i] = feat[n * widths[0] + i];
+        for (int i = 0; i < widths[0]; ++i) act[0][i] = store_act(feat[n * widths[0] + i], bf16);
         for (int l = 0; l < n_layers; ++l) {
             const double *Wl = params + offW[l], *bl = params + offb[l];
             for (int o = 0; o < widths[l + 1]; ++o) {
                 double z = bl[o];
-                for (int i = 0; i < widths[l]; ++i) z += Wl[(int64_t)o * widths[l] + i] * act[l][i];
+                for (int i = 0; i < widths[l]; ++i) z += store_act(Wl[(int64_t)o * widths[l] + i], bf16) * act[l][i];
                 pre[l][o] = z;
-                act[l + 1][o] = (l < n_layers - 1 && z < 0.0) ? 0.0 : z;
+                act[l + 1][o] = l < n_layers - 1 ? store_act(z < 0.0 ? 0.0 : z, bf16) : z;
             }
         }
         const double *o = act[n_layers];
@@ -678,11 +710,12 @@ void oracle_mlp_bwd(const double *grad_sigma, const double *grad_rgb, const doub
                     if (pre[l][q] < 0.0) d[q] = 0.0;
             for (int q = 0; q < widths[l + 1]; ++q) {
                 gb[q] += d[q];
-                for (int i = 0; i < widths[l]; ++i) gW[(int64_t)q * widths[l] + i] += d[q] * act[l][i];
+                dq[q] = store_act(d[q], bf16);
+                for (int i = 0; i < widths[l]; ++i) gW[(int64_t)q * widths[l] + i] += dq[q] * act[l][i];
             }
             for (int i = 0; i < widths[l]; ++i) {
                 double v = 0.0;
-                for (int q = 0; q < widths[l + 1]; ++q) v += Wl[(int64_t)q * widths[l] + i] * d[q];
+                for (int q = 0; q < widths[l + 1]; ++q) v += store_act(Wl[(int64_t)q * widths[l] + i], bf16) * dq[q];
                 dn[i] = v;
             }
             memcpy(d, dn, sizeof(double) * widths[l]);

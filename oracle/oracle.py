@@ -50,9 +50,9 @@ def lib():
     L.oracle_hash_encode_bwd.restype = None
     L.oracle_hash_encode_bwd.argtypes = [_d, _d, _i32, _I64, _d, _I32, _I32, _I64, _i32, _d, _d, _d]
     L.oracle_mlp_fwd.restype = None
-    L.oracle_mlp_fwd.argtypes = [_d, _i32, _I64, _d, _i32, _I32, _d, _d]
+    L.oracle_mlp_fwd.argtypes = [_d, _i32, _I64, _d, _i32, _I32, _I32, _d, _d]
     L.oracle_mlp_bwd.restype = None
-    L.oracle_mlp_bwd.argtypes = [_d, _d, _d, _i32, _I64, _d, _i32, _I32, _d, _d]
+    L.oracle_mlp_bwd.argtypes = [_d, _d, _d, _i32, _I64, _d, _i32, _I32, _I32, _d, _d]
     L.oracle_composite_fwd.restype = None
     L.oracle_composite_fwd.argtypes = [_d, _d, _i64, _d, _I64, _D, _d, _d, _i32, _d]
     L.oracle_composite_bwd.restype = None
@@ -213,7 +213,10 @@ def hash_encode_bwd(grad_feat, x, table, res, aabb, valid=None):
 
 
 # ----------------------------------------------------------------- MLP
-def mlp_fwd(feat, params, widths=(32, 64, 64, 4), valid=None):
+def mlp_fwd(feat, params, widths=(32, 64, 64, 4), valid=None, bf16=False):
+    """Eq. 1-2 decoder.  bf16: the BF16 storage form (features, hidden
+    activations and weight matrices rounded to bfloat16, FP64 sums; the ReLU
+    decisions taken on those values)."""
     feat = _f64(feat)
     S = feat.shape[0]
     sigma = np.zeros(S)
@@ -221,11 +224,13 @@ def mlp_fwd(feat, params, widths=(32, 64, 64, 4), valid=None):
     v = None if valid is None else _c(valid, np.int32)
     w = np.asarray(widths, np.int32)
     lib().oracle_mlp_fwd(_p(feat, _d), _p(v, _i32), S, _p(_f64(params), _d), _p(w, _i32), len(widths) - 1,
-                         _p(sigma, _d), _p(rgb, _d))
+                         int(bool(bf16)), _p(sigma, _d), _p(rgb, _d))
     return sigma, rgb
 
 
-def mlp_bwd(grad_sigma, grad_rgb, feat, params, widths=(32, 64, 64, 4), valid=None):
+def mlp_bwd(grad_sigma, grad_rgb, feat, params, widths=(32, 64, 64, 4), valid=None, bf16=False):
+    """Backward of mlp_fwd (same bf16 form; the deltas are also stored as
+    bfloat16 where they multiply, the bias gradients sum them unrounded)."""
     feat = _f64(feat)
     S = feat.shape[0]
     params = _f64(params)
@@ -234,7 +239,7 @@ def mlp_bwd(grad_sigma, grad_rgb, feat, params, widths=(32, 64, 64, 4), valid=No
     v = None if valid is None else _c(valid, np.int32)
     w = np.asarray(widths, np.int32)
     lib().oracle_mlp_bwd(_p(_f64(grad_sigma), _d), _p(_f64(grad_rgb), _d), _p(feat, _d), _p(v, _i32), S,
-                         _p(params, _d), _p(w, _i32), len(widths) - 1, _p(gp, _d), _p(gf, _d))
+                         _p(params, _d), _p(w, _i32), len(widths) - 1, int(bool(bf16)), _p(gp, _d), _p(gf, _d))
     return gp, gf
 
 
@@ -303,28 +308,43 @@ def deform_guided(xp, x0, guide_bone, B, W, skin_aabb, hash_aabb, max_iter=10, t
 
 
 # ------------------------------------------------------- whole chain
-def forward(w, details=False, table=None, params=None):
+def forward(w, details=False, table=None, params=None, roots=None, mlp_bf16=False):
     """Fig. 2 order on a synth.Workload: march, deform, encode, MLP, composite.
-    ``table`` / ``params`` override the workload's (e.g. FP16/BF16-rounded copies)."""
+    ``table`` / ``params`` override the workload's (e.g. FP16/BF16-rounded copies).
+    ``roots`` = (xc [S,3], bone [S]) replaces the deform stage's output (the
+    root finding of Sec. 3.1 is skipped and every later stage starts from
+    these canonical points), so that a checked implementation and this
+    chain can be run from one set of points.  ``mlp_bf16``: the decoder in
+    its BF16 storage form (``mlp_fwd(bf16=True)``)."""
     m = march(w.rays_o, w.rays_d, w.occ, w.occ_aabb, w.dt, w.n_per_ray, w.max_steps)
-    d = deform(m["xs"], w.B, w.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop, w.tol_valid, details=details)
+    if roots is None:
+        d = deform(m["xs"], w.B, w.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop, w.tol_valid, details=details)
+    else:
+        xc, bone = _f64(roots[0]).reshape(-1, 3), np.asarray(roots[1]).astype(np.int32)
+        if xc.shape[0] != m["xs"].shape[0] or bone.shape != (xc.shape[0],):
+            raise ValueError("roots must hold one point and one bone per marched sample")
+        d = dict(xc=xc, bone=bone)
     res = resolutions(w.L, w.base_res, w.growth)
     tab = w.table if table is None else table
     prm = w.mlp if params is None else params
     feat = hash_encode(d["xc"], tab, res, w.hash_aabb, valid=d["bone"])
-    sigma, rgb = mlp_fwd(feat, prm, w.widths, valid=d["bone"])
+    sigma, rgb = mlp_fwd(feat, prm, w.widths, valid=d["bone"], bf16=mlp_bf16)
     c = composite_fwd(sigma, rgb, m["ray_off"], m["ray_dt"], w.T_thresh)
     return dict(march=m, deform=d, res=res, feat=feat, sigma=sigma, rgb=rgb, **c)
 
 
-def train_step(w):
+def train_step(w, table=None, params=None, roots=None, mlp_bf16=False):
     """Forward, L2 loss against w.target, and every backward pass:
-    composite -> MLP -> hash encode (table and x*) -> deform (x', B, W)."""
-    f = forward(w)
+    composite -> MLP -> hash encode (table and x*) -> deform (x', B, W).
+    ``table``, ``params``, ``roots`` and ``mlp_bf16`` as in ``forward``; the
+    backward uses the same table and MLP values and form as the forward."""
+    f = forward(w, table=table, params=params, roots=roots, mlp_bf16=mlp_bf16)
+    tab = w.table if table is None else table
+    prm = w.mlp if params is None else params
     loss, gC = l2_loss(f["color"], w.target)
     gs, gr = composite_bwd(gC, f["sigma"], f["rgb"], f["march"]["ray_off"], f["march"]["ray_dt"], f["n_used"])
-    gp, gfeat = mlp_bwd(gs, gr, f["feat"], w.mlp, w.widths, valid=f["deform"]["bone"])
-    gt, gx = hash_encode_bwd(gfeat, f["deform"]["xc"], w.table, f["res"], w.hash_aabb, valid=f["deform"]["bone"])
+    gp, gfeat = mlp_bwd(gs, gr, f["feat"], prm, w.widths, valid=f["deform"]["bone"], bf16=mlp_bf16)
+    gt, gx = hash_encode_bwd(gfeat, f["deform"]["xc"], tab, f["res"], w.hash_aabb, valid=f["deform"]["bone"])
     gxp, gB, gW = deform_bwd(gx, f["deform"]["xc"], f["deform"]["bone"], w.B, w.W, w.skin_aabb)
     f.update(loss=loss, grad_color=gC, grad_sigma=gs, grad_rgb=gr, grad_params=gp, grad_feat=gfeat,
              grad_table=gt, grad_xc=gx, grad_xp=gxp, grad_B=gB, grad_W=gW)
@@ -380,7 +400,7 @@ def occgrid_build(G, aabb, B, W, skin_aabb, hash_aabb, table, res, params, width
 # ------------------------------------------- training occupancy grid
 def jittered_points(G, aabb, u, cells=None):
     """One point per cell of the G^3 grid of ``aabb`` at a random position
-    inside it (Sec. 3.3, training stage: densities of randomly sampled
+    inside it (Sec. 3.3, training stage: the densities are taken at random
     points): for cell c = x + G (y + G z), lo + ((i + u) / G) * (hi - lo) per
     axis with u [3][M] in [0, 1) supplied by the caller, every operation in
     IEEE single.  ``cells`` [M] lists the cells (default: all G^3 in order).

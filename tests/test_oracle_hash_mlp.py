@@ -116,3 +116,72 @@ def _torch_mlp_from(x, p, widths):
         if l < len(widths) - 2:
             a = torch.relu(a)
     return torch.exp(a[:, 0]), torch.sigmoid(a[:, 1:4])
+
+
+def _one_unit_mlp(scale):
+    """Widths (1, 1, 4): h = relu(scale * f), o_0 = h, o_1..3 = 0 -- so
+    log(sigma) is the stored hidden activation."""
+    return np.array([scale, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0], np.float64)
+
+
+def test_mlp_bf16_storage_rounds_like_torch(orc):
+    """The BF16 storage form rounds a value to single precision and then to
+    the nearest bfloat16, ties to even: the same as PyTorch's float32 ->
+    bfloat16 conversion, on random values and on exact halfway cases."""
+    rng = np.random.default_rng(5)
+    f = np.concatenate([rng.uniform(0.01, 100.0, 4000),
+                        1.0 + np.arange(1, 64) * 2.0 ** -8,  # halfway points between bfloat16 neighbours of 1
+                        [3.0 * 2.0 ** -9 + 1.0, 1.0 + 2.0 ** -8 + 2.0 ** -20, 255.5, 257.0, 3.1e-5]])
+    p = _one_unit_mlp(1.0)
+    sig, _ = orc.mlp_fwd(f[:, None], p, widths=(1, 1, 4), bf16=True)
+    ref = torch.tensor(f, dtype=torch.float32).bfloat16().double().numpy()
+    np.testing.assert_allclose(np.log(sig), ref, rtol=1e-13, atol=1e-15)
+    sig64, _ = orc.mlp_fwd(f[:, None], p, widths=(1, 1, 4), bf16=False)
+    np.testing.assert_allclose(np.log(sig64), f, rtol=1e-13, atol=1e-15)
+
+
+def test_mlp_bf16_storage_exact_on_representable_values(orc):
+    """On a network whose inputs, weights and every activation are small
+    integers (exact in bfloat16), the BF16 storage form equals the FP64 form
+    bit for bit, forward and backward (with gradients of the outputs chosen
+    so that every delta is a dyadic number exact in bfloat16)."""
+    rng = np.random.default_rng(8)
+    widths = (32, 64, 64, 4)
+    W1 = np.zeros((64, 32))
+    W2 = np.zeros((64, 64))
+    for q in range(64):
+        W1[q, rng.choice(32, 2, replace=False)] = rng.choice([-1.0, 1.0], 2)
+        W2[q, rng.choice(64, 2, replace=False)] = rng.choice([-1.0, 1.0], 2)
+    W3 = np.zeros((4, 64))
+    params = np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), W3.ravel(), np.zeros(4)])
+    feat = rng.integers(-2, 3, (500, 32)).astype(np.float64)
+    s64, c64 = orc.mlp_fwd(feat, params, widths)
+    s16, c16 = orc.mlp_fwd(feat, params, widths, bf16=True)
+    assert np.array_equal(s64, s16) and np.array_equal(c64, c16)
+    # o = 0 everywhere (W3 = 0): sigma = 1 and c(1 - c) = 1/4, so the output
+    # deltas are the dyadic grad_sigma and grad_rgb / 4
+    gs = rng.choice([-1.0, 0.5, 2.0], 500)
+    gr = rng.choice([-0.5, 1.0, 4.0], (500, 3))
+    g64 = orc.mlp_bwd(gs, gr, feat, params, widths)
+    g16 = orc.mlp_bwd(gs, gr, feat, params, widths, bf16=True)
+    assert np.array_equal(g64[0], g16[0]) and np.array_equal(g64[1], g16[1])
+
+
+def test_mlp_bf16_storage_close_to_fp64(orc):
+    """On He-normal weights the BF16 storage form stays within a few BF16
+    roundings of the FP64 form (relative to the sum of the magnitudes of the
+    products): a check that no storage point is rounded twice or lost."""
+    from tests import bounds
+    rng = np.random.default_rng(9)
+    S = 3000
+    feat = torch.tensor(rng.normal(0, 0.5, (S, 32)), dtype=torch.float32).bfloat16().double().numpy()
+    params = synth.make_mlp(seed=3, sigma_bias=0.3)
+    s64, c64 = orc.mlp_fwd(feat, params)
+    s16, c16 = orc.mlp_fwd(feat, params, bf16=True)
+    om = bounds.mlp_fwd_magnitude(np.abs(feat), params)
+    u = 2.0 ** -9
+    # each output sums products of one rounded weight and one rounded
+    # activation through two rounded hidden layers: a few u of the magnitude
+    assert (np.abs(np.log(s16) - np.log(s64)) <= 8 * u * om[:, 0]).all()
+    assert (np.abs(c16 - c64) <= 2 * u * om[:, 1:]).all()
+    assert np.abs(np.log(s16) - np.log(s64)).max() > 0  # the form does round

@@ -541,7 +541,7 @@ __device__ __forceinline__ void load_frag_bft(const float *P, int r, int g, Frag
       for (int mt = 0; mt < 2; ++mt) f.w1t[mt][c][j] = (__bf16)P[OFF_W1 + k * NIN + 16 * mt + r];
     }
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) f.w3t[mt] = P[OFF_W3 + g * NH + 16 * mt + r];
+  for (int mt = 0; mt < 4; ++mt) f.w3t[mt] = (float)(__bf16)P[OFF_W3 + g * NH + 16 * mt + r];
 }
 
 __device__ __forceinline__ bf16x8 pack_raw(const f32x4 z[4], int c) {
@@ -604,11 +604,13 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_bf16(const float *__restric
 #pragma unroll
         for (int k = 0; k < 3; ++k) d3[1 + k] = grgb[k * ld + s] * c[k] * (1.0f - c[k]);
       }
+      // the 4-wide head runs on FP32 MFMA with BF16-valued operands (the
+      // forward's W3, the output delta as stored for the weight gradient)
       float b3 = 0.0f;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const float t = __shfl(d3[k], r, 64);
-        b3 = (g == k) ? t : b3;
+        b3 = (g == k) ? (float)(__bf16)t : b3;
       }
       f32x4 d2[4], d1[4];
 #pragma unroll

@@ -55,8 +55,13 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 
 # Algorithmic work per unit, counted from the method (not from the kernels'
 # actual traffic); the per-stage table of the JSON line uses these.
-DEFORM_FLOP_PER_INIT = 670.0   # start point, Jacobian, inverse
-DEFORM_FLOP_PER_STEP = 380.0   # one Broyden step (residual 290 + update 90)
+# deform, pre-blended form: per init, the start point B_i^-1 x' (18), the
+# residual and Jacobian at it (8 corners of A_c x_h and their interpolation,
+# the trilinear derivatives: ~470) and the 3x3 inverse (~45), ~564 in all;
+# per Broyden step, the step -H g (18), the residual at the new point (~230)
+# and the rank-one update of H (~78), ~326
+DEFORM_FLOP_PER_INIT = 564.0
+DEFORM_FLOP_PER_STEP = 326.0
 HASH_GATHER_BYTES = {4: 16 * 8 * 2 * 4, 2: 16 * 8 * 2 * 2}  # 16 levels x 8 corners x 2 features
 FEAT_BYTES = {4: 16 * 2 * 4, 2: 16 * 2 * 2}
 # table gradient: read-modify-write of the 256 touched FP32 entries, dL/dfeat
@@ -145,7 +150,7 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(stage):
+def pmc_traffic(stage, kernels=None):
     """HBM bytes per launch of a stage's kernels from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, each divided by the factor a plain
     copy kernel of known size reads), or None when the summary is missing or
@@ -161,7 +166,7 @@ def pmc_traffic(stage):
     per = blob["kernels"]
     tot, seen = 0.0, False
     for name, rec in per.items():
-        if any(k in name for k in STAGE_KERNELS.get(stage, [])):
+        if any(k in name for k in (kernels or STAGE_KERNELS.get(stage, []))):
             tot += rec["fetch_kib"] * 1024 / blob["copy_factor_fetch"] + rec["write_kib"] * 1024 / blob["copy_factor_write"]
             seen = True
     return tot if seen else None
@@ -201,18 +206,50 @@ def stage_rooflines(stage_ms, S, R, steps_total, nb, es, mlp_bf16, backward=True
     return out
 
 
-def roofline(stage_ms, S, R, steps_total, nb):
-    """The contract's roofline object for the dominant stage of the FP32
-    training step (its kernels are listed; the duration is the stage's, HIP
-    events on the launch stream)."""
+def roofline(stage_ms, solve_ms, S, R, steps_total, nb):
+    """The contract's roofline object for the dominant kernel of the FP32
+    training step: the multi-init solve (`solve_kernel`), its algorithmic
+    flops (every init's start, residual, Jacobian and inverse, every
+    Broyden step the kernel reports) over its own average duration (the
+    deform stage's graph replay less that of the blend alone, HIP events on
+    the launch stream)."""
     table = stage_rooflines(stage_ms, S, R, steps_total, nb, 4, False)
-    dom = max(table, key=lambda k: table[k]["ms"])
-    r = dict(table[dom])
-    r = {"stage": dom, "kernels": STAGE_KERNELS.get(dom, [dom]), "bound": r["bound"], "achieved": r["achieved"],
-         "peak": r["peak"], "unit": r["unit"], "frac": r["frac"], "traffic": pmc_traffic(dom),
+    work = DEFORM_FLOP_PER_INIT * nb * S + DEFORM_FLOP_PER_STEP * steps_total
+    ach = work / (solve_ms * 1e-3) / 1e12
+    r = {"kernel": "solve_kernel", "stage": "deform", "bound": "alu", "achieved": ach,
+         "peak": PEAK_FP32_VEC_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VEC_TFLOPS,
+         "traffic": pmc_traffic("deform", kernels=["solve_kernel"]),
          "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
-         "work_per_launch": r["work_per_launch"], "work_unit": r["work_unit"], "ms_per_launch": r["ms"]}
+         "work_per_launch": work, "work_unit": "flop", "ms_per_launch": solve_ms,
+         "work_count": f"{DEFORM_FLOP_PER_INIT:.0f} flop per init x {nb} inits x {S} samples + "
+                       f"{DEFORM_FLOP_PER_STEP:.0f} flop per Broyden step x {steps_total} steps"}
     return r, table
+
+
+def time_graph(torch, fn, n=20):
+    """GPU ms per call of fn: captured in a HIP graph, replayed n times back
+    to back between two HIP events on the current stream."""
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(n):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / n
+
+
+def blend_ms(torch, K, p, n=20):
+    """The deform stage's blend kernel alone (the call with no samples)."""
+    w = p.w
+    return time_graph(torch, lambda: K.snarf_deform(p.xs, 0, p.cap, p.B, p.W, w.skin_aabb, w.hash_aabb, w.max_iter,
+                                                     w.tol_stop, w.tol_valid, p.xc, p.bone, None, None, p.ws_deform), n)
 
 
 def time_forward(p, n, torch, stages=False):
@@ -257,16 +294,20 @@ def time_train(p, steps, warmup, torch, stages=False):
     return dt, p.read_count(), stage_ms
 
 
-def frame_leg(args, torch, np, K, synth, Pipeline, out):
-    import oracle
+def fit_initialiser(args, torch):
+    """The learned root initialiser, fitted once on the solver's own roots
+    (an input of the path, like the hash table's values)."""
     from paper_2212_10550_amd import rootinit
-    wf = synth.full_frame()
-    log("fitting the root initialiser on solver roots")
     t0 = time.perf_counter()
     data = rootinit.make_dataset(range(1000, 1000 + args.init_poses), 4096, device="cuda:0")
     params = rootinit.fit(data, epochs=args.init_epochs)
-    fit_s = time.perf_counter() - t0
     del data
+    torch.cuda.synchronize()
+    return params, f"{args.init_poses} poses x 4096 points, {args.init_epochs} epochs, {time.perf_counter() - t0:.1f} s"
+
+
+def frame_leg(args, params, fit_note, torch, np, K, synth, Pipeline, out, checks):
+    wf = synth.full_frame()
     # FP32 multi-init reference frame
     p32 = Pipeline(wf, device="cuda:0", device_count=True)
     ms32, S, st32 = time_forward(p32, 5, torch, stages=True)
@@ -282,11 +323,6 @@ def frame_leg(args, torch, np, K, synth, Pipeline, out):
     fb = int(pmx.guided.n_fallback.item())
     used = int(pmx.n_used.to(torch.int64).sum().item())
     del pmx
-    # pixel error on a seeded subset of rays against the FP64 oracle
-    sub = np.arange(0, wf.R, 97)
-    ref = oracle.forward(synth.ray_subset(wf, sub))["color"]
-    e32 = np.abs(c32[sub] - ref)
-    emx = np.abs(cmx[sub] - ref)
     dmx = np.abs(cmx - c32)
     out["frame_540"] = {
         "workload": "540x540 rays, 128^3 occupancy (~10%), <=128 samples/ray, early termination at T < 1e-4, "
@@ -294,24 +330,20 @@ def frame_leg(args, torch, np, K, synth, Pipeline, out):
         "posed_samples": S, "samples_after_termination": used,
         "f32_multi_init": {"ms_per_frame": ms32, "fps": 1e3 / ms32, "broyden_steps": steps32,
                            "stages_ms": {k: round(v, 4) for k, v in st32.items()},
-                           "stage_roofline": stage_rooflines(st32, S, wf.R, steps32, 24, 4, False, backward=False),
-                           "pixel_err_vs_oracle": {"mean": float(e32.mean()), "max": float(e32.max())}},
+                           "stage_roofline": stage_rooflines(st32, S, wf.R, steps32, 24, 4, False, backward=False)},
         "f16_bf16_learned_init": {"ms_per_frame": msmx, "fps": 1e3 / msmx, "broyden_steps": stepsmx,
                                   "stages_ms": {k: round(v, 4) for k, v in stmx.items()},
                                   "stage_roofline": stage_rooflines(stmx, Smx, wf.R, None, 24, 2, True,
                                                                     backward=False),
                                   "fallback_samples": fb,
-                                  "pixel_err_vs_oracle": {"mean": float(emx.mean()),
-                                                          "p99.9": float(np.quantile(emx, 0.999)),
-                                                          "max": float(emx.max())},
                                   "pixel_diff_vs_f32_multi_init": {"mean": float(dmx.mean()),
                                                                    "max": float(dmx.max())}},
         "speedup_learned_mixed_vs_f32_multi": ms32 / msmx,
-        "oracle_rays_compared": int(len(sub)),
-        "initialiser_fit": f"{args.init_poses} poses x 4096 points, {args.init_epochs} epochs, {fit_s:.1f} s",
-        "paper_context": "15 FPS at 540x540 on one RTX 3090 (Sec. 4.2, Tab. 3)",
+        "initialiser_fit": fit_note,
+        "paper_context": "the paper renders its avatars at ~15 FPS at 540x540 and reconstructs one in about 60 s, on "
+                         "one RTX 3090 (Sec. 4.2, Tab. 3; context only, different workload and hardware)",
     }
-    return params
+    checks["frame"] = (wf, c32, cmx)
 
 
 def extra_legs(args, params, torch, np, K, synth, Pipeline, out):
@@ -536,27 +568,16 @@ def multiroot_leg(torch, np, K, synth, out):
     out["multi_root_aggregation"] = res
 
 
-def batch_leg(args, params, poses, gen_s, torch, np, synth, out):
+def batch_leg(args, params, poses, gen_s, torch, np, synth, out, checks):
     """16 poses of one avatar (occupancy 5-25 %, 270^2 / 540^2 / 1080^2) in
     one HIP graph, FP16 table, BF16 MLP, learned root initialiser with
     multi-init fallback; the stream schedule is autotuned."""
-    import oracle
     from paper_2212_10550_amd.batch import BatchRenderer
     br = BatchRenderer(poses, params)
     tune = br.autotune((1, 2, 4), n=3)
     ms = br.time_ms(5)
     S = br.total_samples
-    # pixel error against the oracle on a seeded ray subset of one pose per
-    # resolution
-    errs = {}
-    for k in (0, 4, 2):
-        w = poses[k]
-        idx = np.arange(0, w.R, 1009)
-        ref = oracle.forward(synth.ray_subset(w, idx))["color"]
-        got = br.poses[k].color.double().cpu().numpy()[idx]
-        e = np.abs(got - ref)
-        errs[f"pose{k}_{int(round(w.R ** 0.5))}sq"] = {"rays": int(len(idx)), "mean": float(e.mean()),
-                                                       "max": float(e.max())}
+    colors = {k: br.poses[k].color.double().cpu().numpy() for k in (0, 4, 2)}
     out["batched_render"] = {
         "workload": "16 poses (seeds 3000-3015), occupancy 5 % + 20 % k/15, resolution 270^2/540^2/1080^2 by k mod 3, "
                     "<=128 samples/ray, termination at T < 1e-4; f16 table, bf16 MLP, learned init + fallback",
@@ -565,8 +586,9 @@ def batch_leg(args, params, poses, gen_s, torch, np, synth, out):
         "execution": "one HIP graph replay per batch; poses spread over streams inside the graph",
         "autotune_ms_by_streams": {str(k): v for k, v in tune.items()}, "streams": br.n_streams,
         "fallback_samples": int(sum(int(p.n_fallback.item()) for p in br.poses)),
-        "pixel_err_vs_oracle": errs, "input_generation_s": gen_s,
+        "input_generation_s": gen_s,
     }
+    checks["batch"] = (poses, colors)
     del br
 
 
@@ -713,19 +735,88 @@ def learned_init_leg(params, torch, np, K, synth, out, n_poses=64):
     }
 
 
-def mixed_leg(args, w, S0, steps_total, nb, loss32, gp32, torch, np, K, Pipeline, out):
+def mixed_leg(args, params, w, S0, steps_total, nb, loss32, gp32, torch, np, K, Pipeline, out, checks):
     """The training step with the FP16 table and the BF16 MLP (forward and
-    backward), FP32 deform and compositing."""
-    pm = Pipeline(w, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16, device_count=True)
+    backward), FP32 compositing and implicit-function-theorem backward, and
+    the learned root initialiser with the 24-init fallback (params None:
+    the 24-init solve)."""
+    pm = Pipeline(w, device="cuda:0", table_dtype=torch.float16, mlp_dtype=K.BF16, device_count=True,
+                  rootinit_params=params)
     dt, Sm, stm = time_train(pm, args.steps, args.warmup, torch, stages=True)
     gpm = pm.grad_params.double().cpu().numpy()
-    out["mixed_training_step"] = {
-        "dtype": "f16 table, bf16 MLP (MFMA, f32 accumulate), f32 deform and compositing",
+    steps_m = int(pm.steps[:Sm].to(torch.int64).sum().item())
+    res = {
+        "dtype": "f16 table, bf16 MLP (MFMA, f32 accumulate), f32 deform, compositing and IFT",
+        "root_finding": "learned initialiser + one Broyden solve, 24-init fallback" if params is not None
+        else "24-init Broyden",
         "value": Sm * args.steps / dt, "unit": "posed samples/s", "ms_per_step": dt * 1e3 / args.steps,
         "stages_ms": {k: round(v, 4) for k, v in stm.items()},
-        "stage_roofline": stage_rooflines(stm, S0, w.R, steps_total, nb, 2, True),
+        "stage_roofline": stage_rooflines(stm, S0, w.R, None if params is not None else steps_total, nb, 2, True),
+        "broyden_steps_per_step": steps_m,
         "loss_rel_diff_vs_f32": abs(float(pm.loss.item()) - loss32) / abs(loss32),
         "mlp_grad_rel_l2_diff_vs_f32": float(np.linalg.norm(gpm - gp32) / np.linalg.norm(gp32))}
+    if params is not None:
+        res["fallback_samples"] = int(pm.guided.n_fallback.item())
+        res["fallback_rate"] = res["fallback_samples"] / max(Sm, 1)
+    out["mixed_training_step"] = res
+    checks["mixed"] = (w, float(pm.loss.item()), pm.color.double().cpu().numpy(), gpm)
+    del pm
+
+
+def oracle_checks(checks, out, np, synth):
+    """The GPU results of the legs against the FP64 oracle (run on the host
+    beside the CPU baseline): pixel errors of the frames and of one batched
+    pose per resolution, and the mixed-precision training step's pixel,
+    loss and MLP-gradient errors."""
+    import oracle
+    if "frame" in checks:
+        wf, c32, cmx = checks["frame"]
+        sub = np.arange(0, wf.R, 97)
+        ref = oracle.forward(synth.ray_subset(wf, sub))["color"]
+        e32, emx = np.abs(c32[sub] - ref), np.abs(cmx[sub] - ref)
+        fr = out["frame_540"]
+        fr["oracle_rays_compared"] = int(len(sub))
+        fr["f32_multi_init"]["pixel_err_vs_oracle"] = {"mean": float(e32.mean()), "max": float(e32.max())}
+        fr["f16_bf16_learned_init"]["pixel_err_vs_oracle"] = {
+            "mean": float(emx.mean()), "p99.9": float(np.quantile(emx, 0.999)), "max": float(emx.max())}
+    if "batch" in checks:
+        poses, colors = checks["batch"]
+        errs = {}
+        for k, got in colors.items():
+            w = poses[k]
+            idx = np.arange(0, w.R, 1009)
+            e = np.abs(got[idx] - oracle.forward(synth.ray_subset(w, idx))["color"])
+            errs[f"pose{k}_{int(round(w.R ** 0.5))}sq"] = {"rays": int(len(idx)), "mean": float(e.mean()),
+                                                           "max": float(e.max())}
+        out["batched_render"]["pixel_err_vs_oracle"] = errs
+    if "mixed" in checks:
+        w, loss, color, gp = checks["mixed"]
+        ref = oracle.train_step(w)  # FP32 master table and MLP, FP64 arithmetic, the oracle's own roots
+        e = np.abs(color - ref["color"])
+        gref = np.asarray(ref["grad_params"])
+        out["mixed_training_step"]["error_vs_fp64_oracle"] = {
+            "reference": "the oracle's own training step (its roots, FP32 master values, FP64 arithmetic)",
+            "pixel": {"mean": float(e.mean()), "p99.9": float(np.quantile(e, 0.999)), "max": float(e.max())},
+            "loss_rel": abs(loss - ref["loss"]) / abs(ref["loss"]),
+            "grad_params_norm_rel": float(np.linalg.norm(gp - gref) / np.linalg.norm(gref))}
+
+
+def reap_children():
+    """Wait for (then end) any child process this run started, so that none
+    outlives the bench; reports what it found."""
+    try:
+        import psutil
+    except ImportError:
+        return []
+    kids = psutil.Process().children(recursive=True)
+    found = [(k.pid, k.name()) for k in kids]
+    for k in kids:
+        try:
+            k.terminate()
+        except psutil.Error:
+            pass
+    psutil.wait_procs(kids, timeout=5)
+    return found
 
 
 def short_kernel_name(name):
@@ -778,6 +869,37 @@ def pmc_summary(fetch_dir, write_dir):
     print(json.dumps(out, indent=1))
 
 
+def counter_table(dirs, kernels=None):
+    """Per-kernel mean of every counter found in rocprofv3 --pmc output
+    folders (one folder per pass), as a markdown table; kernels: optional
+    name filters."""
+    import csv
+    import glob
+    per = {}
+    names = set()
+    for d in dirs:
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as f:
+                for row in csv.DictReader(f):
+                    k = short_kernel_name(row["Kernel_Name"])
+                    if kernels and not any(q in k for q in kernels):
+                        continue
+                    c = row["Counter_Name"]
+                    names.add(c)
+                    key = (fn, row["Dispatch_Id"], c)
+                    per.setdefault(k, {}).setdefault(key, 0.0)
+                    per[k][key] += float(row["Counter_Value"])
+    cols = sorted(names)
+    lines = ["| kernel | " + " | ".join(cols) + " |", "|---" * (len(cols) + 1) + "|"]
+    for k in sorted(per):
+        vals = []
+        for c in cols:
+            v = [val for (fn, did, cc), val in per[k].items() if cc == c]
+            vals.append(f"{sum(v) / len(v):.4g}" if v else "")
+        lines.append(f"| {k} | " + " | ".join(vals) + " |")
+    print("\n".join(lines))
+
+
 COPY_CAL_FLOATS = 256 << 20  # 1 GiB read and written (4x the 256 MB Infinity Cache)
 
 
@@ -801,13 +923,22 @@ def main():
     ap.add_argument("--init-poses", type=int, default=256)
     ap.add_argument("--init-epochs", type=int, default=20)
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP16/BF16 training-step leg")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated subset of the frame-side legs to run (frame, init, occgrid, loop, multiroot, "
+                         "extra, batch), e.g. for a profiler run; the training step always runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain copy kernel of known size (for scaling rocprofv3 byte counters)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc output folders (no GPU needed) and exit")
+    ap.add_argument("--counter-table", nargs="+", metavar="PMC_DIR",
+                    help="per-kernel mean of every counter in rocprofv3 --pmc folders (no GPU needed), then exit")
+    ap.add_argument("--kernels", default=None, help="with --counter-table: comma-separated kernel-name filters")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
+        return
+    if args.counter_table:
+        counter_table(args.counter_table, args.kernels.split(",") if args.kernels else None)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this path runs on one GPU; rays, samples and poses are independent, so "
@@ -822,7 +953,7 @@ def main():
     # the batched render's occupancy grids are built in a process pool, which
     # forks before this process has loaded anything that touches the GPU
     poses, gen_s = None, 0.0
-    if not args.no_frame:
+    if not args.no_frame and (args.only is None or "batch" in args.only.split(",")):
         log("building the 16 batched-render poses")
         t0 = time.perf_counter()
         poses = synth.batch_poses(16, workers=min(16, os.cpu_count() or 1))
@@ -876,33 +1007,56 @@ def main():
         "host_count_eager_ms_per_step": host_count_ms,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
     }
-    out["roofline"], out["stage_roofline"] = roofline(stage_ms, S0, w.R, steps_total, nb)
+    blend = blend_ms(torch, K, p)
+    out["deform_kernels_ms"] = {"blend_kernel": round(blend, 4), "solve_kernel": round(stage_ms["deform"] - blend, 4)}
+    out["roofline"], out["stage_roofline"] = roofline(stage_ms, stage_ms["deform"] - blend, S0, w.R, steps_total, nb)
     if abs(float(p.loss.item()) - loss32) > 1e-6 * abs(loss32):
         raise RuntimeError("graph-replayed step and host-count step disagree on the loss")
     del p
-    # the same step with FP16 hash features and the BF16 MLP (forward and backward)
+    checks = {}
+    params = None
+    if not args.no_frame:
+        log("fitting the root initialiser on solver roots")
+        params, fit_note = fit_initialiser(args, torch)
+    # the same step with FP16 hash features, the BF16 MLP and the learned
+    # initialiser (the 24-init solve when it is not fitted)
     if not args.no_mixed:
-        mixed_leg(args, w, S0, steps_total, nb, loss32, gp32, torch, np, K, Pipeline, out)
+        log("FP16/BF16 training step")
+        mixed_leg(args, params, w, S0, steps_total, nb, loss32, gp32, torch, np, K, Pipeline, out, checks)
     if args.copy_calibration:
         copy_calibration(torch)
     if not args.no_frame:
-        log("540x540 frame")
-        params = frame_leg(args, torch, np, K, synth, Pipeline, out)
-        log("learned initialiser on held-out poses")
-        learned_init_leg(params, torch, np, K, synth, out)
-        log("occupancy grid construction")
-        occgrid_leg(torch, np, K, synth, out)
-        log("training loop with Adam and occupancy updates")
-        training_loop_leg(torch, np, K, synth, out)
-        log("multi-root aggregation on a folded pose")
-        multiroot_leg(torch, np, K, synth, out)
-        log("tiny forward, skipping on/off, hash stress")
-        extra_legs(args, params, torch, np, K, synth, Pipeline, out)
-        log("batched render of 16 poses")
-        batch_leg(args, params, poses, gen_s, torch, np, synth, out)
+        legs = set(args.only.split(",")) if args.only else None
+        run = lambda name: legs is None or name in legs
+        if run("frame"):
+            log("540x540 frame")
+            frame_leg(args, params, fit_note, torch, np, K, synth, Pipeline, out, checks)
+        if run("init"):
+            log("learned initialiser on held-out poses")
+            learned_init_leg(params, torch, np, K, synth, out)
+        if run("occgrid"):
+            log("occupancy grid construction")
+            occgrid_leg(torch, np, K, synth, out)
+        if run("loop"):
+            log("training loop with Adam and occupancy updates")
+            training_loop_leg(torch, np, K, synth, out)
+        if run("multiroot"):
+            log("multi-root aggregation on a folded pose")
+            multiroot_leg(torch, np, K, synth, out)
+        if run("extra"):
+            log("tiny forward, skipping on/off, hash stress")
+            extra_legs(args, params, torch, np, K, synth, Pipeline, out)
+        if run("batch") and poses is not None:
+            log("batched render of 16 poses")
+            batch_leg(args, params, poses, gen_s, torch, np, synth, out, checks)
     if not args.no_cpu_baseline:
         log("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w)
+        log("GPU results against the oracle")
+        oracle_checks(checks, out, np, synth)
+    left = reap_children()
+    if left:
+        log(f"child processes ended at exit: {left}")
     print(json.dumps(out), flush=True)
 
 

@@ -22,8 +22,8 @@
  *    [L][ld][F].  Boxes (aabb) are host float[6] = (lo x, lo y, lo z,
  *    hi x, hi y, hi z).
  *  - A sample whose `bone` is negative has no canonical correspondence: it
- *    gets density 0, zero features and zero gradients (the paper's "set
- *    their density to zero" for skipped points, Sec. 3.3).
+ *    gets density 0, zero features and zero gradients (Sec. 3.3 gives
+ *    skipped points zero density).
  *  - grad_* outputs documented as "accumulated" are added to (+=), so the
  *    caller zeroes them (ia355_zero) or sums over several calls.
  *  - Device sample counts: every entry point that takes a sample count S
@@ -52,6 +52,7 @@ extern "C" {
 #define IA355_ERR_UNSUPPORTED 3 /* valid but unimplemented combination */
 #define IA355_ERR_HIP 4         /* a HIP launch failed; see ia355_error_string */
 #define IA355_ERR_SCRATCH 5     /* the problem exceeds the fixed scratch of an allocation-free entry point */
+#define IA355_ERR_CAPACITY 6    /* the sample buffer is too small; *n_required holds the count needed */
 
 /* flags of the backward entry points */
 #define IA355_OVERWRITE 1u /* write the gradient instead of adding to it */
@@ -116,8 +117,12 @@ int32_t ia355_occ_pack(const uint8_t *occ, int32_t G, uint32_t *bits, ia355_stre
  *   n_samples [1] device int64 total kept count.
  * With cap == 0 the call only counts: ray_cnt, ray_dt and n_samples are
  * written, ray_off is not final.
- * If *n_samples > cap, samples at offsets >= cap are not written: the caller
- * must compare after the stream completes.
+ * If *n_samples > cap, samples at offsets >= cap are not written.
+ * n_required (host, nullable): NULL leaves the call asynchronous (it may then
+ * be captured in a graph) and the caller compares *n_samples with cap once
+ * the stream completes; otherwise the call waits for the stream, writes the
+ * kept count to *n_required and returns IA355_ERR_CAPACITY when it exceeds
+ * cap (the outputs then hold the first cap samples), IA355_OK otherwise.
  * ws: ia355_march_workspace_size(R, max_steps) bytes (per-block totals,
  * and each ray's keep masks, 8 bytes per 64 steps, and entry distance). */
 size_t ia355_march_workspace_size(int64_t R, int32_t max_steps);
@@ -126,7 +131,7 @@ int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d, int64_t R,
                             float dt, int32_t n_per_ray, int32_t max_steps,
                             float *xs, float *ts, int32_t *ray_id, int64_t cap,
                             int64_t *ray_off, int32_t *ray_cnt, float *ray_dt, int64_t *n_samples,
-                            void *ws, size_t ws_bytes, ia355_stream_t stream);
+                            int64_t *n_required, void *ws, size_t ws_bytes, ia355_stream_t stream);
 
 /* Occupancy from densities: cell c of the G^3 grid (c = x + G (y + G z) in
  * sigma [G^3]) is occupied when some cell within `dilate` cells of it
@@ -268,14 +273,6 @@ int32_t ia355_rootinit_fwd(const float *xp, int64_t S, const int64_t *S_dev, int
                            int32_t hidden, const float *B, int32_t nb, int32_t dtype, int16_t *init_bone,
                            float *x0, ia355_stream_t stream);
 
-/* Guided root finding: one Broyden solve per sample from x0 (H0 = J(x0)^{-1},
- * the same iteration as ia355_snarf_deform).  A root with residual below
- * tol_valid inside hash_aabb is accepted with bone = init_bone; every other
- * sample falls back to the multi-init solve of ia355_snarf_deform.
- *   steps [S] (nullable) counts the guided steps plus, on fallback, every
- *   init's steps; n_fallback [1] (device int32, nullable) receives the
- *   number of fallback samples.
- * ws: ia355_deform_guided_workspace_size(S, Dx, Dy, Dz) bytes. */
 /* Multi-root aggregation (an alternative to keeping the lowest-residual root
  * of Sec. 3.1).  ia355_snarf_deform_roots runs the same multi-init solve and
  * writes, per sample, up to K distinct valid roots in order of increasing
@@ -303,6 +300,14 @@ int32_t ia355_select_max_density(int32_t K, int64_t S, const float *sigma_k, con
                                  int64_t ld, float *xc, int16_t *bone, float *sigma, float *rgb,
                                  ia355_stream_t stream);
 
+/* Guided root finding: one Broyden solve per sample from x0 (H0 = J(x0)^{-1},
+ * the same iteration as ia355_snarf_deform).  A root with residual below
+ * tol_valid inside hash_aabb is accepted with bone = init_bone; every other
+ * sample falls back to the multi-init solve of ia355_snarf_deform.
+ *   steps [S] (nullable) counts the guided steps plus, on fallback, every
+ *   init's steps; n_fallback [1] (device int32, nullable) receives the
+ *   number of fallback samples.
+ * ws: ia355_deform_guided_workspace_size(S, Dx, Dy, Dz) bytes. */
 size_t ia355_deform_guided_workspace_size(int64_t S, int32_t Dx, int32_t Dy, int32_t Dz);
 int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, const int64_t *S_dev, int64_t ld, const float *x0,
                                   const int16_t *init_bone,
@@ -387,19 +392,26 @@ int32_t ia355_hashgrid_table_grad(const float *grad_feat, const float *xc, const
                                   double base_res, double growth, const float *aabb, float *grad_table,
                                   uint32_t flags, void *ws, size_t ws_bytes, ia355_stream_t stream);
 
-/* The decoder MLP 32 -> 64 -> 64 -> 4 with ReLU hidden layers; outputs
- * sigma = exp(o_0) (clamped at exp(80)) and c = sigmoid(o_1..3).
+/* The decoder of Sec. 3.1, Eq. 1-2: an MLP with ReLU hidden layers mapping
+ * the concatenated features to sigma = exp(o_0) (clamped at exp(80)) and
+ * c = sigmoid(o_1..3).
+ *   widths (host) [n_layers + 1], n_layers: the layer widths; this library
+ *   implements {32, 64, 64, 4} (n_layers 3), other shapes return
+ *   IA355_ERR_UNSUPPORTED (a NULL widths, IA355_ERR_INVALID_ARG)
  *   feat [L][ld][F] (L*F = 32) of feat_dtype; params FP32 flat
  *   (per layer W [out][in] row-major, then b [out]; 6532 floats)
- *   dtype: IA355_F32 (FP32 MFMA) or IA355_BF16 (BF16 MFMA, FP32 accumulate;
- *   requires feat_dtype BF16)
+ *   dtype: IA355_F32 (FP32 MFMA) or IA355_BF16 (requires feat_dtype BF16):
+ *   BF16 MFMA with FP32 accumulate; the weight matrices, the hidden
+ *   activations (after the ReLU, decided on the FP32 pre-activation) and,
+ *   in the backward, the deltas that multiply are bfloat16, the biases and
+ *   their gradients FP32
  *   sigma [S], rgb [3][ld] FP32; invalid samples (bone < 0) get 0. */
 int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int16_t *bone, int64_t S, const int64_t *S_dev,
-                      int64_t ld,
-                      const float *params, int32_t dtype, float *sigma, float *rgb, ia355_stream_t stream);
+                      int64_t ld, const float *params, const int32_t *widths, int32_t n_layers, int32_t dtype,
+                      float *sigma, float *rgb, ia355_stream_t stream);
 
 /* Backward of the MLP (the forward is recomputed from feat; nothing is
- * saved).  grad_sigma [S], grad_rgb [3][ld] FP32.
+ * saved).  grad_sigma [S], grad_rgb [3][ld] FP32; widths as in the forward.
  *   grad_params [6532] FP32 accumulated (written with IA355_OVERWRITE)
  *   grad_feat [L][ld][F] FP32 overwritten (nullable)
  * ws: ia355_mlp_bwd_workspace_size(S) bytes (per-block weight-gradient
@@ -407,8 +419,8 @@ int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int16_t *bone,
 size_t ia355_mlp_bwd_workspace_size(int64_t S);
 int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb, const void *feat, int32_t feat_dtype,
                       const int16_t *bone, int64_t S, const int64_t *S_dev, int64_t ld, const float *params,
-                      int32_t dtype, float *grad_params, float *grad_feat, uint32_t flags, void *ws, size_t ws_bytes,
-                      ia355_stream_t stream);
+                      const int32_t *widths, int32_t n_layers, int32_t dtype, float *grad_params, float *grad_feat,
+                      uint32_t flags, void *ws, size_t ws_bytes, ia355_stream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Volume rendering, Sec. 3.2 Eq. 8 (alpha_i = 1 - exp(-sigma_i delta_i)) */

@@ -27,6 +27,7 @@ struct Grid {
   int D[3];       // Dx, Dy, Dz
   float lo[3];    // box low corner
   float scale[3]; // (D - 1) / (hi - lo)
+  uint32_t dc[8]; // byte offset of corner k's transform (k = cx + 2 cy + 4 cz) from its cell's base vertex
 };
 
 struct Box {
@@ -82,31 +83,52 @@ __device__ __forceinline__ Cell locate(const Grid &g, const float x[3]) {
   return c;
 }
 
-__device__ __forceinline__ const float4 *corner_ptr(const float *A, const Grid &g, const Cell &c, int k) {
-  const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
-  const int64_t v = ((int64_t)(c.i0[2] + cz) * g.D[1] + (c.i0[1] + cy)) * g.D[0] + (c.i0[0] + cx);
-  return reinterpret_cast<const float4 *>(A + 12 * v);
+// Base vertex of a cell.  The blended grid holds fewer than 2^32 / 48
+// vertices (checked on the host), so vertex and byte offsets are 32-bit and
+// every corner load is a uniform base plus one 32-bit lane offset.
+// (byte offset of the base vertex's 12 floats)
+__device__ __forceinline__ uint32_t cell_base(const Grid &g, const Cell &c) {
+  return (((uint32_t)c.i0[2] * (uint32_t)g.D[1] + (uint32_t)c.i0[1]) * (uint32_t)g.D[0] + (uint32_t)c.i0[0]) * 48u;
 }
 
-// g = sum_c tri_c (A_c x_h) - x'.
+__device__ __forceinline__ const float4 *corner_ptr(const float *A, const Grid &g, uint32_t base, int k) {
+  return reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(A) + (base + g.dc[k]));
+}
+
+// Trilinear weights of the eight corners (k = cx + 2 cy + 4 cz).
+__device__ __forceinline__ void tri_weights(const float f[3], float t[8]) {
+  const float gx = 1.0f - f[0], gy = 1.0f - f[1], gz = 1.0f - f[2];
+  const float a00 = gy * gz, a10 = f[1] * gz, a01 = gy * f[2], a11 = f[1] * f[2];
+  t[0] = gx * a00;
+  t[1] = f[0] * a00;
+  t[2] = gx * a10;
+  t[3] = f[0] * a10;
+  t[4] = gx * a01;
+  t[5] = f[0] * a01;
+  t[6] = gx * a11;
+  t[7] = f[0] * a11;
+}
+
+// g = (sum_c tri_c A_c) x_h - x': the 12 blended channels are interpolated
+// first, then applied to x_h once.
 __device__ __forceinline__ void residual(const float *__restrict__ A, const Grid &gr, const float x[3],
                                          const float xp[3], float g[3]) {
   const Cell c = locate(gr, x);
-  g[0] = -xp[0];
-  g[1] = -xp[1];
-  g[2] = -xp[2];
+  const uint32_t base = cell_base(gr, c);
+  float t[8];
+  tri_weights(c.f, t);
+  float4 m0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), m1 = m0, m2 = m0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const float4 *p = corner_ptr(A, gr, c, k);
+    const float4 *p = corner_ptr(A, gr, base, k);
     const float4 r0 = p[0], r1 = p[1], r2 = p[2];
-    const float wx = (k & 1) ? c.f[0] : 1.0f - c.f[0];
-    const float wy = (k & 2) ? c.f[1] : 1.0f - c.f[1];
-    const float wz = (k & 4) ? c.f[2] : 1.0f - c.f[2];
-    const float t = wx * wy * wz;
-    g[0] += t * (r0.x * x[0] + r0.y * x[1] + r0.z * x[2] + r0.w);
-    g[1] += t * (r1.x * x[0] + r1.y * x[1] + r1.z * x[2] + r1.w);
-    g[2] += t * (r2.x * x[0] + r2.y * x[1] + r2.z * x[2] + r2.w);
+    m0.x += t[k] * r0.x; m0.y += t[k] * r0.y; m0.z += t[k] * r0.z; m0.w += t[k] * r0.w;
+    m1.x += t[k] * r1.x; m1.y += t[k] * r1.y; m1.z += t[k] * r1.z; m1.w += t[k] * r1.w;
+    m2.x += t[k] * r2.x; m2.y += t[k] * r2.y; m2.z += t[k] * r2.z; m2.w += t[k] * r2.w;
   }
+  g[0] = (m0.x * x[0] + m0.y * x[1] + m0.z * x[2] + m0.w) - xp[0];
+  g[1] = (m1.x * x[0] + m1.y * x[1] + m1.z * x[2] + m1.w) - xp[1];
+  g[2] = (m2.x * x[0] + m2.y * x[1] + m2.z * x[2] + m2.w) - xp[2];
 }
 
 // Derivatives of a trilinear interpolant along its cell axes, from the
@@ -129,6 +151,7 @@ __device__ __forceinline__ float tri_weight(const float f[3], int k) {
 __device__ __forceinline__ void residual_jac(const float *__restrict__ A, const Grid &gr, const float x[3],
                                              const float xp[3], float g[3], float J[3][3]) {
   const Cell c = locate(gr, x);
+  const uint32_t base = cell_base(gr, c);
   float y[3][8];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -136,7 +159,7 @@ __device__ __forceinline__ void residual_jac(const float *__restrict__ A, const 
     for (int j = 0; j < 3; ++j) J[i][j] = 0.0f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const float4 *p = corner_ptr(A, gr, c, k);
+    const float4 *p = corner_ptr(A, gr, base, k);
     const float4 r[3] = {p[0], p[1], p[2]};
     const float t = tri_weight(c.f, k);
 #pragma unroll
@@ -185,9 +208,10 @@ __device__ __forceinline__ InitResult broyden_from(const float *__restrict__ A, 
   const float detJ = inv3(J, H);
   bool ok = bone_ok && fabsf(detJ) >= 1e-12f;
   int k = 0;
+  const float tol2 = tol_stop * tol_stop;
   if (ok) {
     for (; k < max_iter; ++k) {
-      if (norm3(g) < tol_stop) break;
+      if (g[0] * g[0] + g[1] * g[1] + g[2] * g[2] < tol2) break;
       float dx[3], xn[3], gn[3], dg[3], Hdg[3], dxH[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) dx[a] = -(H[a][0] * g[0] + H[a][1] * g[1] + H[a][2] * g[2]);
@@ -211,7 +235,7 @@ __device__ __forceinline__ InitResult broyden_from(const float *__restrict__ A, 
         ++k;
         break;
       }
-      const float iden = 1.0f / den;
+      const float iden = __builtin_amdgcn_rcpf(den);  // 1 ulp: H is an approximation of J^-1 anyway
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -800,11 +824,14 @@ Grid make_grid(int Dx, int Dy, int Dz, const float *aabb) {
     g.lo[a] = aabb[a];
     g.scale[a] = (float)(g.D[a] - 1) / (aabb[3 + a] - aabb[a]);
   }
+  const uint32_t sx = 1, sy = (uint32_t)Dx, sz = (uint32_t)Dx * (uint32_t)Dy;
+  for (int k = 0; k < 8; ++k) g.dc[k] = 48u * (((k & 1) ? sx : 0) + ((k & 2) ? sy : 0) + ((k & 4) ? sz : 0));
   return g;
 }
 
 bool grid_ok(int Dx, int Dy, int Dz, const float *aabb) {
   if (Dx < 2 || Dy < 2 || Dz < 2 || !aabb) return false;
+  if ((int64_t)Dx * Dy * Dz * 48 >= ((int64_t)1 << 32)) return false;  // 32-bit byte offsets into the blended grid
   for (int a = 0; a < 3; ++a)
     if (!(aabb[3 + a] > aabb[a])) return false;
   return true;

@@ -305,8 +305,8 @@ extern "C" size_t ia355_march_workspace_size(int64_t R, int32_t max_steps) {
 extern "C" int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d, int64_t R, const uint32_t *occ_bits,
                                        int32_t G, const float *aabb, float dt, int32_t n_per_ray, int32_t max_steps,
                                        float *xs, float *ts, int32_t *ray_id, int64_t cap, int64_t *ray_off,
-                                       int32_t *ray_cnt, float *ray_dt, int64_t *n_samples, void *ws,
-                                       size_t ws_bytes, ia355_stream_t stream) {
+                                       int32_t *ray_cnt, float *ray_dt, int64_t *n_samples, int64_t *n_required,
+                                       void *ws, size_t ws_bytes, ia355_stream_t stream) {
   if (R < 0 || !aabb || max_steps < 0 || cap < 0) return IA355_ERR_INVALID_ARG;
   if (!ray_off || !n_samples) return IA355_ERR_INVALID_ARG;
   if (R > 0 && (!rays_o || !rays_d || !ray_cnt || !ray_dt)) return IA355_ERR_INVALID_ARG;
@@ -349,5 +349,12 @@ extern "C" int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d,
   if (R > 0 && cap > 0)
     march_fill<<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, mw.masks, nw, mw.tn, block_sum, chunk_sum,
                                                  ray_off, ray_dt, xs, ts, ray_id, cap);
-  return launch_status();
+  const int32_t st = launch_status();
+  if (st != IA355_OK || !n_required) return st;
+  // synchronous capacity check, on request only
+  int64_t n = 0;
+  if (hipMemcpyAsync(&n, n_samples, sizeof n, hipMemcpyDeviceToHost, s) != hipSuccess) return IA355_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return IA355_ERR_HIP;
+  *n_required = n;
+  return n > cap ? IA355_ERR_CAPACITY : IA355_OK;
 }

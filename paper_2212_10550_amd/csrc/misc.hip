@@ -14,6 +14,7 @@ extern "C" const char *ia355_error_string(int32_t s) {
     case IA355_ERR_UNSUPPORTED: return "unsupported combination of arguments";
     case IA355_ERR_HIP: return "HIP launch error";
     case IA355_ERR_SCRATCH: return "problem larger than the fixed scratch of the allocation-free entry point";
+    case IA355_ERR_CAPACITY: return "sample buffer too small (n_required holds the count needed)";
     default: return "unknown status";
   }
 }

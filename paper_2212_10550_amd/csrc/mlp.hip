@@ -783,9 +783,26 @@ unsigned fwd_blocks(int64_t S) { return grid_for(ceil_div(S, 16) * 64, kFwdBlock
 
 }  // namespace
 
+namespace {
+
+// The one decoder shape the kernels implement (Eq. 1-2 with the widths of
+// the Instant-NGP density/colour head): 32 -> 64 -> 64 -> 4.
+int32_t widths_status(const int32_t *widths, int32_t n_layers) {
+  if (!widths || n_layers < 1 || n_layers > 15) return IA355_ERR_INVALID_ARG;
+  for (int l = 0; l <= n_layers; ++l)
+    if (widths[l] <= 0) return IA355_ERR_INVALID_ARG;
+  if (n_layers != 3 || widths[0] != NIN || widths[1] != NH || widths[2] != NH || widths[3] != NOUT)
+    return IA355_ERR_UNSUPPORTED;
+  return IA355_OK;
+}
+
+}  // namespace
+
 extern "C" int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int16_t *bone, int64_t S,
-                                 const int64_t *S_dev, int64_t ld, const float *params, int32_t dtype, float *sigma,
-                                 float *rgb, ia355_stream_t stream) {
+                                 const int64_t *S_dev, int64_t ld, const float *params, const int32_t *widths,
+                                 int32_t n_layers, int32_t dtype, float *sigma, float *rgb, ia355_stream_t stream) {
+  const int32_t ws = widths_status(widths, n_layers);
+  if (ws != IA355_OK) return ws;
   if (S < 0 || ld < S || !params) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!feat || !sigma || !rgb)) return IA355_ERR_INVALID_ARG;
   if (dtype == IA355_F32 && feat_dtype != IA355_F32) return IA355_ERR_UNSUPPORTED;
@@ -807,8 +824,11 @@ extern "C" size_t ia355_mlp_bwd_workspace_size(int64_t S) {
 
 extern "C" int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb, const void *feat, int32_t feat_dtype,
                                  const int16_t *bone, int64_t S, const int64_t *S_dev, int64_t ld,
-                                 const float *params, int32_t dtype, float *grad_params, float *grad_feat,
-                                 uint32_t flags, void *ws, size_t ws_bytes, ia355_stream_t stream) {
+                                 const float *params, const int32_t *widths, int32_t n_layers, int32_t dtype,
+                                 float *grad_params, float *grad_feat, uint32_t flags, void *ws, size_t ws_bytes,
+                                 ia355_stream_t stream) {
+  const int32_t wst = widths_status(widths, n_layers);
+  if (wst != IA355_OK) return wst;
   if (S < 0 || ld < S || !params || !grad_params) return IA355_ERR_INVALID_ARG;
   if (flags & ~(uint32_t)IA355_OVERWRITE) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_sigma || !grad_rgb || !feat)) return IA355_ERR_INVALID_ARG;

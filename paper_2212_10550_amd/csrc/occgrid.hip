@@ -242,7 +242,8 @@ static int32_t lattice_density(int32_t G, const float *aabb, const float *jitter
   st = ia355_hashgrid_encode(w.xc, w.bone, N, nullptr, N, table, table_dtype, L, F, log2T, base_res, growth,
                              hash_aabb, w.feat, feat_dtype, stream);
   if (st != IA355_OK) return st;
-  return ia355_mlp_fwd(w.feat, feat_dtype, w.bone, N, nullptr, N, params, mlp_dtype, sig, w.rgb, stream);
+  static const int32_t kWidths[4] = {32, 64, 64, 4};
+  return ia355_mlp_fwd(w.feat, feat_dtype, w.bone, N, nullptr, N, params, kWidths, 3, mlp_dtype, sig, w.rgb, stream);
 }
 
 extern "C" int32_t ia355_occgrid_build(int32_t G, const float *aabb, const float *B, int32_t nb, const float *W,

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libia355.so")
 
 F32, F16, BF16 = 0, 1, 2
 OVERWRITE = 1  # backward flag: write gradients instead of adding to them
+CAPACITY = 6  # IA355_ERR_CAPACITY
+MLP_WIDTHS = (32, 64, 64, 4)  # the decoder shape the library implements
 TABLE_COARSE = 2  # hash-table gradient: only the coarse dense levels
 TABLE_FINE = 4  # hash-table gradient: only the other levels
 TABLE_PLAN = 8  # binned table gradient: only the passes that depend on the positions
@@ -56,7 +58,7 @@ _SIGS = {
     "occgrid_build": (_i32, [_i32, _fp, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _i32, _i32,
                              _i32, _i32, _d, _d, _vp, _i32, _f, _i32, _vp, _vp, _vp, _sz, _vp]),
     "occgrid_march": (_i32, [_vp, _vp, _i64, _vp, _i32, _fp, _f, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
-                             _vp, _vp, _sz, _vp]),
+                             _vp, ctypes.POINTER(ctypes.c_int64), _vp, _sz, _vp]),
     "deform_workspace_size": (_sz, [_i32, _i32, _i32]),
     "snarf_deform": (_i32, [_vp, _i64, _vp, _i64, _vp, _i32, _vp, _i32, _i32, _i32, _fp, _fp, _i32, _f, _f, _vp, _vp, _vp,
                             _vp, _vp, _sz, _vp]),
@@ -76,9 +78,10 @@ _SIGS = {
     "hashgrid_table_grad_workspace_size": (_sz, [_i64, _i32, _i32]),
     "hashgrid_table_grad": (_i32, [_vp, _vp, _vp, _i64, _vp, _i64, _i32, _i32, _i32, _d, _d, _fp, _vp, ctypes.c_uint32,
                                    _vp, _sz, _vp]),
-    "mlp_fwd": (_i32, [_vp, _i32, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _vp, _vp]),
+    "mlp_fwd": (_i32, [_vp, _i32, _vp, _i64, _vp, _i64, _vp, _vp, _i32, _i32, _vp, _vp, _vp]),
     "mlp_bwd_workspace_size": (_sz, [_i64]),
-    "mlp_bwd": (_i32, [_vp, _vp, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _vp, ctypes.c_uint32, _vp, _sz, _vp]),
+    "mlp_bwd": (_i32, [_vp, _vp, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _vp, _i32, _i32, _vp, _vp, ctypes.c_uint32, _vp,
+                       _sz, _vp]),
     "volrender_fwd": (_i32, [_vp, _vp, _i64, _vp, _vp, _i64, _f, _vp, _vp, _vp, _vp, _vp]),
     "volrender_bwd": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "l2_loss": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
@@ -258,16 +261,33 @@ def march_workspace_size(R, max_steps):
     return lib().ia355_march_workspace_size(R, max_steps)
 
 
+class CapacityError(RuntimeError):
+    """The march kept more samples than the buffers hold (IA355_ERR_CAPACITY)."""
+
+    def __init__(self, n_required, cap):
+        super().__init__(f"ia355_occgrid_march: {n_required} samples kept, capacity {cap}")
+        self.n_required = n_required
+        self.cap = cap
+
+
 def occgrid_march(rays_o, rays_d, occ_bits, G, aabb, dt, n_per_ray, max_steps, xs, ts, ray_id, cap, ray_off,
-                  ray_cnt, ray_dt, n_samples, ws):
+                  ray_cnt, ray_dt, n_samples, ws, check=False):
+    """check=False: asynchronous (n_samples holds the count on the device).
+    check=True: the call waits for the stream and returns the kept count,
+    raising CapacityError when it exceeds cap."""
     R = rays_o.shape[0]
-    _check(lib().ia355_occgrid_march(
+    req = ctypes.c_int64(-1) if check else None
+    st = lib().ia355_occgrid_march(
         _p(rays_o, torch.float32, "rays_o"), _p(rays_d, torch.float32, "rays_d"), R,
         _p(occ_bits, torch.int32, "occ_bits"), G, _box(aabb), float(dt), n_per_ray, max_steps,
         _p(xs, torch.float32, "xs"), _p(ts, torch.float32, "ts"), _p(ray_id, torch.int32, "ray_id"), cap,
         _p(ray_off, torch.int64, "ray_off"), _p(ray_cnt, torch.int32, "ray_cnt"), _p(ray_dt, torch.float32, "ray_dt"),
-        _p(n_samples, torch.int64, "n_samples"), _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()),
-        "occgrid_march")
+        _p(n_samples, torch.int64, "n_samples"), None if req is None else ctypes.byref(req),
+        _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream())
+    if st == CAPACITY:
+        raise CapacityError(req.value, cap)
+    _check(st, "occgrid_march")
+    return None if req is None else req.value
 
 
 def deform_workspace_size(Dx, Dy, Dz):
@@ -384,22 +404,30 @@ def hashgrid_table_grad(grad_feat, xc, bone, S, ld, base_res, growth, aabb, grad
         0 if ws is None else ws.numel() * ws.element_size(), _stream()), "hashgrid_table_grad")
 
 
-def mlp_fwd(feat, bone, S, ld, params, dtype, sigma, rgb, S_dev=None):
+def _widths(widths):
+    w = [int(v) for v in widths]
+    return (ctypes.c_int32 * len(w))(*w), len(w) - 1
+
+
+def mlp_fwd(feat, bone, S, ld, params, dtype, sigma, rgb, S_dev=None, widths=MLP_WIDTHS):
+    wa, nl = _widths(widths)
     _check(lib().ia355_mlp_fwd(
         _p(feat, name="feat"), _DT[feat.dtype], _p(bone, torch.int16, "bone"), S, _p(S_dev, torch.int64, "S_dev"), ld,
-        _p(params, torch.float32, "params"), dtype, _p(sigma, torch.float32, "sigma"), _p(rgb, torch.float32, "rgb"),
-        _stream()), "mlp_fwd")
+        _p(params, torch.float32, "params"), wa, nl, dtype, _p(sigma, torch.float32, "sigma"),
+        _p(rgb, torch.float32, "rgb"), _stream()), "mlp_fwd")
 
 
 def mlp_bwd_workspace_size(S):
     return lib().ia355_mlp_bwd_workspace_size(S)
 
 
-def mlp_bwd(grad_sigma, grad_rgb, feat, bone, S, ld, params, dtype, grad_params, grad_feat, ws, flags=0, S_dev=None):
+def mlp_bwd(grad_sigma, grad_rgb, feat, bone, S, ld, params, dtype, grad_params, grad_feat, ws, flags=0, S_dev=None,
+            widths=MLP_WIDTHS):
+    wa, nl = _widths(widths)
     _check(lib().ia355_mlp_bwd(
         _p(grad_sigma, torch.float32, "grad_sigma"), _p(grad_rgb, torch.float32, "grad_rgb"), _p(feat, name="feat"),
         _DT[feat.dtype], _p(bone, torch.int16, "bone"), S, _p(S_dev, torch.int64, "S_dev"), ld,
-        _p(params, torch.float32, "params"), dtype,
+        _p(params, torch.float32, "params"), wa, nl, dtype,
         _p(grad_params, torch.float32, "grad_params"), _p(grad_feat, torch.float32, "grad_feat"), flags,
         _p(ws, name="ws"), ws.numel() * ws.element_size(), _stream()), "mlp_bwd")
 

@@ -38,3 +38,36 @@ def test_workspace_sizes_without_gpu():
     assert K.march_workspace_size(0, 0) > 0 and K.march_workspace_size(-1, 128) == 0
     assert K.deform_workspace_size(64, 64, 32) == 12 * 4 * 64 * 64 * 32
     assert K.mlp_bwd_workspace_size(1 << 20) >= 6532 * 4
+
+
+def test_status_codes_and_mlp_widths_without_gpu():
+    """Every status code has its own text; the MLP entry points reject a
+    decoder shape other than 32-64-64-4 (IA355_ERR_UNSUPPORTED) or a missing
+    widths array (IA355_ERR_INVALID_ARG) before any device work."""
+    path = os.path.join(ROOT, "paper_2212_10550_amd", "libia355.so")
+    lib = ctypes.CDLL(path)
+    lib.ia355_error_string.restype = ctypes.c_char_p
+    texts = {lib.ia355_error_string(c) for c in range(7)}
+    assert len(texts) == 7 and lib.ia355_error_string(99) == b"unknown status"
+    hdr = open(os.path.join(ROOT, "include", "ia355.h")).read()
+    codes = dict(re.findall(r"#define (IA355_(?:OK|ERR_[A-Z_]+)) (\d+)", hdr))
+    assert codes["IA355_ERR_CAPACITY"] == "6" and codes["IA355_ERR_UNSUPPORTED"] == "3"
+    assert codes["IA355_ERR_INVALID_ARG"] == "1"
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the checks return first
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    f = lib.ia355_mlp_fwd
+    f.restype = i32
+    f.argtypes = [ctypes.c_void_p, i32, ctypes.c_void_p, i64, ctypes.c_void_p, i64, ctypes.c_void_p, ctypes.c_void_p,
+                  i32, i32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    ok = (i32 * 4)(32, 64, 64, 4)
+    other = (i32 * 4)(32, 128, 64, 4)
+    assert f(fake, 0, None, 16, None, 16, fake, other, 3, 0, fake, fake, None) == 3
+    assert f(fake, 0, None, 16, None, 16, fake, ok, 2, 0, fake, fake, None) == 3
+    assert f(fake, 0, None, 16, None, 16, fake, None, 3, 0, fake, fake, None) == 1
+    assert f(fake, 0, None, -1, None, 16, fake, ok, 3, 0, fake, fake, None) == 1
+    b = lib.ia355_mlp_bwd
+    b.restype = i32
+    vp = ctypes.c_void_p
+    b.argtypes = [vp, vp, vp, i32, vp, i64, vp, i64, vp, vp, i32, i32, vp, vp, ctypes.c_uint32, vp, ctypes.c_size_t,
+                  vp]
+    assert b(fake, fake, fake, 0, None, 16, None, 16, fake, other, 3, 0, fake, None, 0, fake, 1 << 30, None) == 3

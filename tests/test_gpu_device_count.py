@@ -113,3 +113,26 @@ def test_device_count_overflow_is_reported():
     with pytest.raises(RuntimeError):
         small.read_count()
     assert np.isfinite(host(small.color)).all()
+
+
+def test_march_capacity_status():
+    """ia355_occgrid_march with n_required: the kept count is returned, and a
+    capacity below it gives IA355_ERR_CAPACITY with the count needed; the
+    first cap samples equal those of a large enough buffer."""
+    from paper_2212_10550_amd import lib as K
+    from paper_2212_10550_amd.pipeline import Pipeline
+    w = synth.train_step()
+    p = Pipeline(w)
+    S = K.occgrid_march(p.rays_o, p.rays_d, p.occ_bits, p.G, w.occ_aabb, w.dt, w.n_per_ray, w.max_steps, p.xs, p.ts,
+                        p.ray_id, p.cap, p.ray_off, p.ray_cnt, p.ray_dt, p.n_samples, p.ws_march, check=True)
+    assert S == int(p.n_samples.item()) and 0 < S <= p.cap
+    cap = S // 3
+    xs = torch.full((3, cap), 7.0, device=p.dev)
+    ts = torch.empty(cap, device=p.dev)
+    rid = torch.empty(cap, dtype=torch.int32, device=p.dev)
+    with pytest.raises(K.CapacityError) as e:
+        K.occgrid_march(p.rays_o, p.rays_d, p.occ_bits, p.G, w.occ_aabb, w.dt, w.n_per_ray, w.max_steps, xs, ts, rid,
+                        cap, p.ray_off, p.ray_cnt, p.ray_dt, p.n_samples, p.ws_march, check=True)
+    assert e.value.n_required == S and e.value.cap == cap
+    torch.cuda.synchronize()
+    assert np.array_equal(host(xs), host(p.xs[:, :cap]))

@@ -226,14 +226,17 @@ def roofline(stage_ms, solve_ms, S, R, steps_total, nb):
     return r, table
 
 
-def time_graph(torch, fn, n=20):
-    """GPU ms per call of fn: captured in a HIP graph, replayed n times back
-    to back between two HIP events on the current stream."""
+def time_graph(torch, fn, n=10, reps=20):
+    """GPU ms per call of fn: `reps` calls captured back to back in one HIP
+    graph, the graph replayed n times between two HIP events on the current
+    stream (the per-launch gap of a graph replay is then paid once per reps
+    calls, not per call)."""
     fn()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        fn()
+        for _ in range(reps):
+            fn()
     g.replay()
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -242,14 +245,20 @@ def time_graph(torch, fn, n=20):
         g.replay()
     b.record()
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / n
+    return a.elapsed_time(b) / (n * reps)
 
 
-def blend_ms(torch, K, p, n=20):
-    """The deform stage's blend kernel alone (the call with no samples)."""
+def deform_kernel_ms(torch, K, p):
+    """(blend, solve) ms per call of the FP32 multi-init deform: the call
+    with no samples (the blend alone) and the full call, each repeated in one
+    graph; the solve is the difference."""
     w = p.w
-    return time_graph(torch, lambda: K.snarf_deform(p.xs, 0, p.cap, p.B, p.W, w.skin_aabb, w.hash_aabb, w.max_iter,
-                                                     w.tol_stop, w.tol_valid, p.xc, p.bone, None, None, p.ws_deform), n)
+    call = lambda S: K.snarf_deform(p.xs, S, p.cap, p.B, p.W, w.skin_aabb, w.hash_aabb, w.max_iter, w.tol_stop,
+                                    w.tol_valid, p.xc, p.bone, None, None, p.ws_deform,
+                                    S_dev=None if S == 0 else p.n_samples)
+    blend = time_graph(torch, lambda: call(0))
+    full = time_graph(torch, lambda: call(p.cap))
+    return blend, full - blend
 
 
 def time_forward(p, n, torch, stages=False):
@@ -1007,9 +1016,10 @@ def main():
         "host_count_eager_ms_per_step": host_count_ms,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
     }
-    blend = blend_ms(torch, K, p)
-    out["deform_kernels_ms"] = {"blend_kernel": round(blend, 4), "solve_kernel": round(stage_ms["deform"] - blend, 4)}
-    out["roofline"], out["stage_roofline"] = roofline(stage_ms, stage_ms["deform"] - blend, S0, w.R, steps_total, nb)
+    blend, solve = deform_kernel_ms(torch, K, p)
+    out["deform_kernels_ms"] = {"blend_kernel": round(blend, 4), "solve_kernel": round(solve, 4),
+                                "timing": "20 calls captured back to back in one graph, replayed 10 times"}
+    out["roofline"], out["stage_roofline"] = roofline(stage_ms, solve, S0, w.R, steps_total, nb)
     if abs(float(p.loss.item()) - loss32) > 1e-6 * abs(loss32):
         raise RuntimeError("graph-replayed step and host-count step disagree on the loss")
     del p

@@ -34,17 +34,51 @@ struct Box {
   float lo[3], hi[3];
 };
 
-__global__ void blend_kernel(const float *__restrict__ W, const float *__restrict__ B, int nb, int64_t nvert,
-                             float *__restrict__ A) {
+// One thread per vertex.  The block's nb-float skinning rows are contiguous
+// in W, so the block first copies them into LDS with coalesced 16-byte loads
+// (a lane walking its own row would touch a different cache line per lane
+// and weight), then each thread blends its row with the bone transforms.
+constexpr int kBlendBlock = 256;
+constexpr int kBlendMaxBones = 32;  // LDS rows: 256 x 32 floats = 32 KB
+
+// qlen (nullable): a counter the next kernel on the stream needs at zero
+// (the guided solve's fallback queue), cleared here instead of by a launch
+// of its own.
+__global__ void __launch_bounds__(kBlendBlock) blend_kernel(const float *__restrict__ W, const float *__restrict__ B,
+                                                             int nb, int64_t nvert, float *__restrict__ A,
+                                                             int32_t *__restrict__ qlen) {
+  if (qlen && blockIdx.x == 0 && threadIdx.x == 0) *qlen = 0;
   __shared__ float sB[kMaxBones * 12];
+  __shared__ __attribute__((aligned(16))) float sW[kBlendBlock * kBlendMaxBones];
   for (int i = threadIdx.x; i < nb * 12; i += blockDim.x) sB[i] = B[i];
+  const int64_t v0 = (int64_t)blockIdx.x * kBlendBlock;
+  const int64_t nv = nvert - v0 < kBlendBlock ? nvert - v0 : kBlendBlock;
+  const bool staged = nb <= kBlendMaxBones;
+  if (staged) {
+    // the block's rows: nv * nb floats starting at W + v0 * nb
+    const float *src = W + v0 * nb;
+    const int64_t n = nv * nb;
+    const int64_t head = (int64_t)((4 - (((uintptr_t)src >> 2) & 3)) & 3);  // floats before 16-byte alignment
+    const int64_t h = head < n ? head : n;
+    for (int64_t i = threadIdx.x; i < h; i += blockDim.x) sW[i] = src[i];
+    const int64_t n4 = (n - h) >> 2;
+    const float4 *src4 = reinterpret_cast<const float4 *>(src + h);
+    for (int64_t i = threadIdx.x; i < n4; i += blockDim.x) {
+      const float4 q = src4[i];
+      sW[h + 4 * i] = q.x;
+      sW[h + 4 * i + 1] = q.y;
+      sW[h + 4 * i + 2] = q.z;
+      sW[h + 4 * i + 3] = q.w;
+    }
+    for (int64_t i = h + 4 * n4 + threadIdx.x; i < n; i += blockDim.x) sW[i] = src[i];
+  }
   __syncthreads();
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nvert) return;
+  const int64_t v = v0 + threadIdx.x;
+  if (threadIdx.x >= nv) return;
   float acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0.0f;
-  const float *w = W + v * nb;
+  const float *w = staged ? sW + (int64_t)threadIdx.x * nb : W + v * nb;
   for (int b = 0; b < nb; ++b) {
     const float wb = w[b];
 #pragma unroll
@@ -863,7 +897,7 @@ int32_t deform_launch(const float *xp, int64_t S, const int64_t *S_dev, int64_t 
                       const float *hash_aabb, int32_t max_iter, float tol_stop, float tol_valid, float *xc,
                       int16_t *bone, float *resid, int16_t *steps, float *A, hipStream_t s) {
   const int64_t nvert = (int64_t)Dx * Dy * Dz;
-  blend_kernel<<<(unsigned)ceil_div(nvert, 256), 256, 0, s>>>(W, B, nb, nvert, A);
+  blend_kernel<<<(unsigned)ceil_div(nvert, kBlendBlock), kBlendBlock, 0, s>>>(W, B, nb, nvert, A, nullptr);
   if (S == 0) return launch_status();
   const Grid g = make_grid(Dx, Dy, Dz, skin_aabb);
   Box hb;
@@ -961,7 +995,7 @@ extern "C" int32_t ia355_snarf_deform_roots(const float *xp, int64_t S, const in
   hipStream_t s = as_stream(stream);
   const int64_t nvert = (int64_t)Dx * Dy * Dz;
   float *A = (float *)ws;
-  blend_kernel<<<(unsigned)ceil_div(nvert, 256), 256, 0, s>>>(W, B, nb, nvert, A);
+  blend_kernel<<<(unsigned)ceil_div(nvert, kBlendBlock), kBlendBlock, 0, s>>>(W, B, nb, nvert, A, nullptr);
   if (S == 0) return launch_status();
   const Grid g = make_grid(Dx, Dy, Dz, skin_aabb);
   Box hb;
@@ -1012,9 +1046,8 @@ extern "C" int32_t ia355_snarf_deform_guided(const float *xp, int64_t S, const i
   int32_t *qlen = (int32_t *)p;
   int32_t *queue = qlen + 1;
   int16_t *gsteps = (int16_t *)(p + align256(sizeof(int32_t) * (size_t)(S + 1)));
-  blend_kernel<<<(unsigned)ceil_div(nvert, 256), 256, 0, s>>>(W, B, nb, nvert, A);
-  int32_t st = ia355_zero(qlen, sizeof(int32_t), stream);
-  if (st != IA355_OK) return st;
+  blend_kernel<<<(unsigned)ceil_div(nvert, kBlendBlock), kBlendBlock, 0, s>>>(W, B, nb, nvert, A, qlen);
+  int32_t st = IA355_OK;
   if (S > 0) {
     const Grid g = make_grid(Dx, Dy, Dz, skin_aabb);
     Box hb;

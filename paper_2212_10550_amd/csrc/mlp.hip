@@ -51,6 +51,16 @@ __device__ __forceinline__ void head(const float o[4], float *sig, float c[3]) {
   for (int k = 0; k < 3; ++k) c[k] = 1.0f / (1.0f + expf(-o[1 + k]));
 }
 
+// The parameters (26 KB, 16-byte aligned) copied into LDS by the whole block
+// with coalesced 16-byte loads; every wave then builds its MFMA fragments
+// from LDS instead of gathering them from global memory one value at a time.
+__device__ __forceinline__ void stage_params(const float *__restrict__ P, float *sP) {
+  static_assert(NPARAM % 4 == 0, "parameter block in whole float4s");
+  const float4 *P4 = reinterpret_cast<const float4 *>(P);
+  float4 *s4 = reinterpret_cast<float4 *>(sP);
+  for (int e = threadIdx.x; e < NPARAM / 4; e += blockDim.x) s4[e] = P4[e];
+}
+
 // --------------------------------------------------------------- FP32 fwd
 // Loads the 8 features of lane group g for sample s (levels 4g..4g+3).
 __device__ __forceinline__ void load_x(const float *feat, int64_t fst, int64_t s, int g, bool ok, float X[8]) {
@@ -126,14 +136,18 @@ __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_f32(const float *__restrict
                                                          const int16_t *__restrict__ bone, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                          const float *__restrict__ P, float *__restrict__ sigma,
                                                          float *__restrict__ rgb) {
+  __shared__ __attribute__((aligned(16))) float sP[NPARAM];
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
   S = count_of(S, S_dev);
   const int64_t ntile = ceil_div(S, 16);
   const int64_t wstride = (int64_t)gridDim.x * (kFwdBlock / 64);
-  // a wave without a tile skips the weight-fragment loads (no barriers here)
+  if ((int64_t)blockIdx.x * (kFwdBlock / 64) >= ntile) return;  // the whole block (before the barrier)
+  stage_params(P, sP);
+  __syncthreads();
+  // a wave without a tile skips the fragment loads (no barriers after this)
   if ((int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6) >= ntile) return;
   Frag32 f;
-  load_frag32(P, r, g, f);
+  load_frag32(sP, r, g, f);
   for (int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6); tile < ntile; tile += wstride) {
     const int64_t s = tile * 16 + r;
     const bool ok = s < S;
@@ -231,13 +245,17 @@ __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_bf16(const __hip_bfloat16 *
                                                           const int16_t *__restrict__ bone, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                           const float *__restrict__ P, float *__restrict__ sigma,
                                                           float *__restrict__ rgb) {
+  __shared__ __attribute__((aligned(16))) float sP[NPARAM];
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
   S = count_of(S, S_dev);
   const int64_t ntile = ceil_div(S, 16);
   const int64_t wstride = (int64_t)gridDim.x * (kFwdBlock / 64);
+  if ((int64_t)blockIdx.x * (kFwdBlock / 64) >= ntile) return;  // the whole block (before the barrier)
+  stage_params(P, sP);
+  __syncthreads();
   if ((int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6) >= ntile) return;
   FragBf f;
-  load_frag_bf(P, r, g, f);
+  load_frag_bf(sP, r, g, f);
   for (int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6); tile < ntile; tile += wstride) {
     const int64_t s = tile * 16 + r;
     const bool ok = s < S;
@@ -277,7 +295,8 @@ constexpr int FT2 = FT3 + 4 * 64;      // 64 mfma  : W2[16t + 4g + i][16mt + r] 
 constexpr int FT1 = FT2 + 64 * 64;     // 32 mfma  : W1[16t + 4g + i][16mt + r]   (mt in 0..1, 4t+i)
 constexpr int FT_SIZE = FT1 + 32 * 64;
 constexpr int LDS_FLOATS = FT_SIZE + kBwdWaves * SCR_SIZE;
-static_assert(kBwdWaves * SCR_SIZE >= NPARAM, "block partial reuses the scratch region");
+static_assert(kBwdWaves * SCR_SIZE >= NPARAM, "parameters and block partial use the scratch region");
+static_assert((FT_SIZE * 4) % 16 == 0, "16-byte aligned scratch region");
 static_assert(LDS_FLOATS * 4 <= 65536, "one workgroup's LDS");
 
 __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_f32(const float *__restrict__ gsig, const float *__restrict__ grgb,
@@ -285,29 +304,34 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_f32(const float *__restrict
                                                          const int16_t *__restrict__ bone, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                          const float *__restrict__ P, float *__restrict__ gfeat,
                                                          float *__restrict__ partial) {
-  extern __shared__ float lds[];
+  extern __shared__ __attribute__((aligned(16))) float lds[];
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4, wid = threadIdx.x >> 6;
   float *ft = lds;
   float *scr = lds + FT_SIZE + wid * SCR_SIZE;
-  // stage transposed fragments
+  // the parameters go to the scratch region, which the tiles use only after
+  // the fragments are built
+  float *sP = lds + FT_SIZE;
+  stage_params(P, sP);
+  __syncthreads();
+  // transposed fragments, from the LDS copy
   for (int e = threadIdx.x; e < FT_SIZE; e += kBwdBlock) {
     const int L = e & 63, rr = L & 15, gg = L >> 4;
     float v;
     if (e < FT2) {
       const int mt = e >> 6;
-      v = P[OFF_W3 + gg * NH + 16 * mt + rr];
+      v = sP[OFF_W3 + gg * NH + 16 * mt + rr];
     } else if (e < FT1) {
       const int q = (e - FT2) >> 6, mt = q >> 4, ti = q & 15, t = ti >> 2, i = ti & 3;
-      v = P[OFF_W2 + (16 * t + 4 * gg + i) * NH + 16 * mt + rr];
+      v = sP[OFF_W2 + (16 * t + 4 * gg + i) * NH + 16 * mt + rr];
     } else {
       const int q = (e - FT1) >> 6, mt = q >> 4, ti = q & 15, t = ti >> 2, i = ti & 3;
-      v = P[OFF_W1 + (16 * t + 4 * gg + i) * NIN + 16 * mt + rr];
+      v = sP[OFF_W1 + (16 * t + 4 * gg + i) * NIN + 16 * mt + rr];
     }
     ft[e] = v;
   }
-  __syncthreads();
   Frag32 f;
-  load_frag32(P, r, g, f);
+  load_frag32(sP, r, g, f);
+  __syncthreads();  // every wave holds its fragments before the scratch is reused
   f32x4 aW1[4][2], aW2[4][4], aW3[4];
   float ab1[4][4], ab2[4][4], ab3[4];
 #pragma unroll
@@ -564,10 +588,15 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_bf16(const float *__restric
   extern __shared__ __attribute__((aligned(16))) unsigned char ldsb[];
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4, wid = threadIdx.x >> 6;
   __bf16 *scr = reinterpret_cast<__bf16 *>(ldsb + wid * SCRB_BYTES);
+  // the parameters go to the scratch region until every wave holds its fragments
+  float *sP = reinterpret_cast<float *>(ldsb);
+  stage_params(P, sP);
+  __syncthreads();
   FragBf f;
-  load_frag_bf(P, r, g, f);
+  load_frag_bf(sP, r, g, f);
   FragBfT ft;
-  load_frag_bft(P, r, g, ft);
+  load_frag_bft(sP, r, g, ft);
+  __syncthreads();
   f32x4 aW1[4][2], aW2[4][4], aW3[4];
   float ab1[4][4], ab2[4][4], ab3[4];
 #pragma unroll
@@ -803,7 +832,7 @@ extern "C" int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int
                                  int32_t n_layers, int32_t dtype, float *sigma, float *rgb, ia355_stream_t stream) {
   const int32_t ws = widths_status(widths, n_layers);
   if (ws != IA355_OK) return ws;
-  if (S < 0 || ld < S || !params) return IA355_ERR_INVALID_ARG;
+  if (S < 0 || ld < S || !params || ((uintptr_t)params & 15)) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!feat || !sigma || !rgb)) return IA355_ERR_INVALID_ARG;
   if (dtype == IA355_F32 && feat_dtype != IA355_F32) return IA355_ERR_UNSUPPORTED;
   if (dtype == IA355_BF16 && feat_dtype != IA355_BF16) return IA355_ERR_UNSUPPORTED;
@@ -829,7 +858,7 @@ extern "C" int32_t ia355_mlp_bwd(const float *grad_sigma, const float *grad_rgb,
                                  ia355_stream_t stream) {
   const int32_t wst = widths_status(widths, n_layers);
   if (wst != IA355_OK) return wst;
-  if (S < 0 || ld < S || !params || !grad_params) return IA355_ERR_INVALID_ARG;
+  if (S < 0 || ld < S || !params || !grad_params || ((uintptr_t)params & 15)) return IA355_ERR_INVALID_ARG;
   if (flags & ~(uint32_t)IA355_OVERWRITE) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!grad_sigma || !grad_rgb || !feat)) return IA355_ERR_INVALID_ARG;
   if (!((dtype == IA355_F32 && feat_dtype == IA355_F32) || (dtype == IA355_BF16 && feat_dtype == IA355_BF16)))

@@ -36,17 +36,42 @@ __global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restric
   const int nin = 3 + 6 * nb, nout = nb + 3;
   const int offW1 = 0, offb1 = H * nin, offW2 = offb1 + H, offb2 = offW2 + H * H, offW3 = offb2 + H,
             offb3 = offW3 + nout * H;
+  // a block without a tile returns before any work (uniform, ahead of the
+  // barriers): with a device-side count the grid is sized for the capacity
+  const int64_t Sn = count_of(S, S_dev);
+  if ((int64_t)blockIdx.x * (kBlock / 64) >= ceil_div(Sn, 16)) return;
   __shared__ float c1[H];        // W1[:, 3:] pose + b1
   __shared__ float w1x[H * 3];   // W1[:, :3]
   __shared__ float sBinv[64 * 12];
   __shared__ int sBok[64];
+  // the parameters, copied into LDS once per block with coalesced 16-byte
+  // loads (the pose fold walks W1 row by row; the MFMA fragments gather
+  // single values): a lane reading them from global memory one value at a
+  // time waits on a different cache line per value
+  extern __shared__ __attribute__((aligned(16))) float sP[];
+  const int np_all = offb3 + nout;
+  {
+    const int head = (int)((4 - (((uintptr_t)P >> 2) & 3)) & 3);  // floats before 16-byte alignment
+    const int h = head < np_all ? head : np_all;
+    for (int i = threadIdx.x; i < h; i += kBlock) sP[i] = P[i];
+    const int n4 = (np_all - h) >> 2;
+    const float4 *P4 = reinterpret_cast<const float4 *>(P + h);
+    for (int i = threadIdx.x; i < n4; i += kBlock) {
+      const float4 q = P4[i];
+      sP[h + 4 * i] = q.x;
+      sP[h + 4 * i + 1] = q.y;
+      sP[h + 4 * i + 2] = q.z;
+      sP[h + 4 * i + 3] = q.w;
+    }
+    for (int i = h + 4 * n4 + threadIdx.x; i < np_all; i += kBlock) sP[i] = P[i];
+  }
+  __syncthreads();
   {
     // four threads per neuron, each a strided quarter of the pose terms with
-    // four independent partial sums (loads in flight instead of one long
-    // dependent chain), combined across the four lanes
+    // four independent partial sums, combined across the four lanes
     static_assert(kBlock == 4 * H, "four threads per hidden neuron");
     const int n = threadIdx.x >> 2, q = threadIdx.x & 3;
-    const float *wrow = P + offW1 + n * nin + 3;
+    const float *wrow = sP + offW1 + n * nin + 3;
     const int np = 6 * nb;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
     int i = q;
@@ -60,9 +85,9 @@ __global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restric
     float acc = (a0 + a1) + (a2 + a3);
     acc += __shfl_xor(acc, 1, kWave);
     acc += __shfl_xor(acc, 2, kWave);
-    if (q == 0) c1[n] = acc + P[offb1 + n];
+    if (q == 0) c1[n] = acc + sP[offb1 + n];
   }
-  for (int e = threadIdx.x; e < H * 3; e += kBlock) w1x[e] = P[offW1 + (e / 3) * nin + (e % 3)];
+  for (int e = threadIdx.x; e < H * 3; e += kBlock) w1x[e] = sP[offW1 + (e / 3) * nin + (e % 3)];
   stage_bone_inverses(B, nb, sBinv, sBok);
   __syncthreads();
 
@@ -74,40 +99,40 @@ __global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restric
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) b2[mt][i] = P[offb2 + 16 * mt + 4 * g + i];
+    for (int i = 0; i < 4; ++i) b2[mt][i] = sP[offb2 + 16 * mt + 4 * g + i];
     if (!BF16) {
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) w2f[mt][4 * t + i] = P[offW2 + (16 * mt + r) * H + 16 * t + 4 * g + i];
+        for (int i = 0; i < 4; ++i) w2f[mt][4 * t + i] = sP[offW2 + (16 * mt + r) * H + 16 * t + 4 * g + i];
     } else {
 #pragma unroll
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          w2b[mt][c][j] = (__bf16)P[offW2 + (16 * mt + r) * H + 16 * (2 * c + j / 4) + 4 * g + (j % 4)];
+          w2b[mt][c][j] = (__bf16)sP[offW2 + (16 * mt + r) * H + 16 * (2 * c + j / 4) + 4 * g + (j % 4)];
     }
   }
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt) {
     const int row = 16 * mt + r;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) b3[mt][i] = (16 * mt + 4 * g + i) < nout ? P[offb3 + 16 * mt + 4 * g + i] : 0.0f;
+    for (int i = 0; i < 4; ++i) b3[mt][i] = (16 * mt + 4 * g + i) < nout ? sP[offb3 + 16 * mt + 4 * g + i] : 0.0f;
     if (!BF16) {
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) w3f[mt][4 * t + i] = row < nout ? P[offW3 + row * H + 16 * t + 4 * g + i] : 0.0f;
+        for (int i = 0; i < 4; ++i) w3f[mt][4 * t + i] = row < nout ? sP[offW3 + row * H + 16 * t + 4 * g + i] : 0.0f;
     } else {
 #pragma unroll
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          w3b[mt][c][j] = (__bf16)(row < nout ? P[offW3 + row * H + 16 * (2 * c + j / 4) + 4 * g + (j % 4)] : 0.0f);
+          w3b[mt][c][j] = (__bf16)(row < nout ? sP[offW3 + row * H + 16 * (2 * c + j / 4) + 4 * g + (j % 4)] : 0.0f);
     }
   }
 
-  S = count_of(S, S_dev);
+  S = Sn;
   const int64_t ntile = ceil_div(S, 16);
   const int64_t wstride = (int64_t)gridDim.x * (kBlock / 64);
   for (int64_t tile = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); tile < ntile; tile += wstride) {
@@ -225,11 +250,15 @@ extern "C" int32_t ia355_rootinit_fwd(const float *xp, int64_t S, const int64_t 
   if (dtype != IA355_F32 && dtype != IA355_BF16) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!xp || !init_bone || !x0)) return IA355_ERR_INVALID_ARG;
   if (S == 0) return IA355_OK;
-  const unsigned grid = grid_for(ceil_div(S, 16) * 64, kBlock, 256 * 8);
+  // at most two blocks per CU (the parameters take 61.5 KB of LDS each), each
+  // wave looping over its tiles
+  const unsigned grid = grid_for(ceil_div(S, 16) * 64, kBlock, 256 * 2);
+  const size_t lds = sizeof(float) * (size_t)(H * (3 + 6 * nb) + H + H * H + H + (nb + 3) * H + (nb + 3));
+  if (lds > 96 * 1024) return IA355_ERR_UNSUPPORTED;
   hipStream_t s = as_stream(stream);
   if (dtype == IA355_F32)
-    rootinit_kernel<false><<<grid, kBlock, 0, s>>>(xp, S, S_dev, ld, pose, params, B, nb, init_bone, x0);
+    rootinit_kernel<false><<<grid, kBlock, lds, s>>>(xp, S, S_dev, ld, pose, params, B, nb, init_bone, x0);
   else
-    rootinit_kernel<true><<<grid, kBlock, 0, s>>>(xp, S, S_dev, ld, pose, params, B, nb, init_bone, x0);
+    rootinit_kernel<true><<<grid, kBlock, lds, s>>>(xp, S, S_dev, ld, pose, params, B, nb, init_bone, x0);
   return launch_status();
 }

@@ -116,39 +116,50 @@ __device__ __forceinline__ float2 load_feat2(const __half *t, uint32_t i) {
   return __half22float2(reinterpret_cast<const __half2 *>(t)[i]);
 }
 
-// The two x-neighbouring corners (k, k + 1) of a cell usually sit in one
-// aligned block of the table: adjacent entries on dense levels, and on hashed
-// levels x + 1 flips only the low bits of x when x mod 4 != 3 (the x prime is
-// 1).  One vector load of the aligned block then serves both corners, and a
-// second load runs only for the lanes whose partner lies outside it; the L1
-// cost of a gather is one cache-line access per lane, so this cuts the
-// accesses per (sample, level) from 8 to about 5.  Values are unchanged.
-__device__ __forceinline__ uint32_t pick4(const uint4 &b, uint32_t j) {
-  return j == 0 ? b.x : (j == 1 ? b.y : (j == 2 ? b.z : b.w));
-}
+// The two x-neighbouring corners (k, k + 1) of a cell are adjacent table
+// entries on dense levels, and on hashed levels whenever x + 1 changes the
+// index by one (x even: only bit 0 flips; otherwise the flipped low bits can
+// still leave the two entries next to each other) -- about two pairs in
+// three.  Such a pair is one load of two entries at the lower index (4-byte
+// aligned for FP16 entries, 8-byte for FP32: the unaligned access mode of the
+// HSA ABI, which the compiler itself assumes).  Any other pair loads the
+// aligned two-entry block holding its first corner and the second corner on
+// its own.  Every load stays inside the level's table (T is even), and the
+// data path returns about 9.5 bytes per FP16 pair instead of a 16-byte block
+// of which half was used.  Values are unchanged.
+__device__ __forceinline__ float2 h2f(uint32_t a) { return __half22float2(__builtin_bit_cast(__half2, a)); }
 
-// FP16 table (4-byte entries): aligned 4-entry block, 16 B.
+// FP16 table (4-byte entries).
 __device__ __forceinline__ void gather_pair(const __half *t, uint32_t i0, uint32_t i1, float2 &v0, float2 &v1) {
-  const uint32_t q = i0 & ~3u;
-  const uint4 blk = reinterpret_cast<const uint4 *>(t)[q >> 2];
-  const uint32_t a = pick4(blk, i0 & 3u);
-  v0 = __half22float2(__builtin_bit_cast(__half2, a));
-  if ((i1 & ~3u) == q) {
-    v1 = __half22float2(__builtin_bit_cast(__half2, pick4(blk, i1 & 3u)));
+  const uint32_t *t32 = reinterpret_cast<const uint32_t *>(t);
+  const bool adj = i1 == i0 + 1u || i0 == i1 + 1u;
+  const uint32_t lo = i0 < i1 ? i0 : i1;
+  const uint32_t base = adj ? lo : (i0 & ~1u);
+  uint2 q;
+  __builtin_memcpy(&q, t32 + base, 8);
+  if (adj) {
+    v0 = h2f(i0 == lo ? q.x : q.y);
+    v1 = h2f(i0 == lo ? q.y : q.x);
   } else {
-    v1 = load_feat2(t, i1);
+    v0 = h2f((i0 & 1u) ? q.y : q.x);
+    v1 = h2f(t32[i1]);
   }
 }
 
-// FP32 table (8-byte entries): aligned 2-entry block, 16 B.
+// FP32 table (8-byte entries).
 __device__ __forceinline__ void gather_pair(const float *t, uint32_t i0, uint32_t i1, float2 &v0, float2 &v1) {
-  const uint32_t q = i0 & ~1u;
-  const float4 blk = reinterpret_cast<const float4 *>(t)[q >> 1];
-  v0 = (i0 & 1u) ? make_float2(blk.z, blk.w) : make_float2(blk.x, blk.y);
-  if ((i1 & ~1u) == q) {
-    v1 = (i1 & 1u) ? make_float2(blk.z, blk.w) : make_float2(blk.x, blk.y);
+  const float2 *t2 = reinterpret_cast<const float2 *>(t);
+  const bool adj = i1 == i0 + 1u || i0 == i1 + 1u;
+  const uint32_t lo = i0 < i1 ? i0 : i1;
+  const uint32_t base = adj ? lo : (i0 & ~1u);
+  float4 q;
+  __builtin_memcpy(&q, t2 + base, 16);
+  if (adj) {
+    v0 = (i0 == lo) ? make_float2(q.x, q.y) : make_float2(q.z, q.w);
+    v1 = (i0 == lo) ? make_float2(q.z, q.w) : make_float2(q.x, q.y);
   } else {
-    v1 = load_feat2(t, i1);
+    v0 = (i0 & 1u) ? make_float2(q.z, q.w) : make_float2(q.x, q.y);
+    v1 = t2[i1];
   }
 }
 

@@ -148,11 +148,18 @@ __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_f32(const float *__restrict
   if ((int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6) >= ntile) return;
   Frag32 f;
   load_frag32(sP, r, g, f);
-  for (int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6); tile < ntile; tile += wstride) {
+  // the next tile's features are loaded while this one computes
+  int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6);
+  float Xn[8];
+  load_x(feat, ld, tile * 16 + r, g, tile * 16 + r < S, Xn);
+  for (; tile < ntile; tile += wstride) {
     const int64_t s = tile * 16 + r;
     const bool ok = s < S;
     float X[8];
-    load_x(feat, ld, s, g, ok, X);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) X[c] = Xn[c];
+    const int64_t sn = (tile + wstride) * 16 + r;
+    load_x(feat, ld, sn, g, tile + wstride < ntile && sn < S, Xn);
     f32x4 z1[4], z2[4], o;
     fwd32(f, X, z1, z2, o);
     if (g == 0 && ok) {
@@ -256,10 +263,15 @@ __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_bf16(const __hip_bfloat16 *
   if ((int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6) >= ntile) return;
   FragBf f;
   load_frag_bf(sP, r, g, f);
-  for (int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6); tile < ntile; tile += wstride) {
+  // the next tile's features are loaded while this one computes
+  int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6);
+  bf16x8 Xn = load_x_bf16(feat, ld, tile * 16 + r, g, tile * 16 + r < S);
+  for (; tile < ntile; tile += wstride) {
     const int64_t s = tile * 16 + r;
     const bool ok = s < S;
-    const bf16x8 X = load_x_bf16(feat, ld, s, g, ok);
+    const bf16x8 X = Xn;
+    const int64_t sn = (tile + wstride) * 16 + r;
+    Xn = load_x_bf16(feat, ld, sn, g, tile + wstride < ntile && sn < S);
     f32x4 z1[4], z2[4], o;
     fwd_bf(f, X, z1, z2, o);
     if (g == 0 && ok) {
@@ -808,7 +820,9 @@ int bwd_blocks(int64_t S) {
   return b < 1 ? 1 : (int)b;
 }
 
-unsigned fwd_blocks(int64_t S) { return grid_for(ceil_div(S, 16) * 64, kFwdBlock, 256 * 8); }
+// as many blocks as stay resident (2 waves per SIMD by registers): each
+// wave then loops over its tiles with the next tile's loads in flight
+unsigned fwd_blocks(int64_t S) { return grid_for(ceil_div(S, 16) * 64, kFwdBlock, 256 * 2); }
 
 }  // namespace
 

@@ -348,10 +348,13 @@ class Pipeline:
         main.wait_stream(self.side)
         main.wait_stream(self.side2)
 
-    def stage_times(self, n=20, backward=True):
-        """GPU ms per stage (device counts): each stage captured in a graph of
-        its own and replayed n times back to back after a full step has put
-        its inputs in place (so its inputs are as warm as the cache allows)."""
+    def stage_times(self, n=20, backward=True, reps=10):
+        """GPU ms per stage (device counts): each stage's calls captured
+        `reps` times back to back in a graph of their own, the graph replayed
+        n times after a full step has put the inputs in place (every stage
+        overwrites its outputs, so repeating it is idempotent).  Repeating
+        the calls inside one graph keeps the host's graph-launch gap out of
+        the figure for short stages."""
         if not self.device_count:
             raise RuntimeError("stage_times needs device_count=True")
         self.forward()
@@ -364,7 +367,8 @@ class Pipeline:
             torch.cuda.synchronize()
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
-                fn()
+                for _ in range(reps):
+                    fn()
             g.replay()
             torch.cuda.synchronize()
             a = torch.cuda.Event(enable_timing=True)
@@ -374,7 +378,7 @@ class Pipeline:
                 g.replay()
             b.record()
             torch.cuda.synchronize()
-            out[name] = a.elapsed_time(b) / n
+            out[name] = a.elapsed_time(b) / (n * reps)
             del g
         return out
 

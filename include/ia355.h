@@ -477,6 +477,84 @@ int32_t ia355_count_step(int32_t *step_dev, ia355_stream_t stream);
 int32_t ia355_l2_loss(const float *color, const float *target, int64_t R, float *loss, float *grad_color,
                       ia355_stream_t stream);
 
+/* ------------------------------------------------------------------ */
+/* Batched inference render: many poses of one avatar in one          */
+/* persistent launch (the forward of Sec. 3.1-3.3 and Eq. 8 per ray). */
+/* ------------------------------------------------------------------ */
+#define IA355_BATCH_MAX_POSES 64
+
+/* One pose.  Device pointers, owned by the caller; they must stay valid
+ * (and the outputs unread) until the render calls that use them have run.
+ *   rays_o, rays_d [R][3]; occ_bits (ia355_occ_pack layout, G^3 cells over
+ *   occ_aabb; NULL keeps every step); dt / n_per_ray / max_steps as for
+ *   ia355_occgrid_march, max_steps <= 128;
+ *   B [nb][3][4] bone transforms; pose [nb][6] the initialiser's pose input;
+ *   outputs as ia355_volrender_fwd: color [R][3], opacity [R], n_used [R],
+ *   T_final [R]; n_fallback [1] (nullable) receives the number of samples
+ *   whose guided solve was rejected. */
+typedef struct ia355_batch_pose {
+  const float *rays_o, *rays_d;
+  int64_t R;
+  const uint32_t *occ_bits;
+  int32_t G;
+  float occ_aabb[6];
+  float dt;
+  int32_t n_per_ray, max_steps;
+  const float *B, *pose;
+  float *color, *opacity;
+  int32_t *n_used;
+  float *T_final;
+  int32_t *n_fallback;
+} ia355_batch_pose;
+
+/* What the poses share (device pointers, owned by the caller):
+ *   skinning grid W [Dz][Dy][Dx][nb] over skin_aabb; canonical box hash_aabb;
+ *   Broyden max_iter, tol_stop, tol_valid (ia355_snarf_deform);
+ *   FP16 hash table [L][2^log2T][2] (16-byte aligned), L = 16, per-level
+ *   resolutions floor(base_res growth^l); decoder parameters (32-64-64-4,
+ *   FP32 flat, 16-byte aligned, used as BF16 MFMA operands exactly as
+ *   ia355_mlp_fwd with IA355_BF16); initialiser parameters (FP32 flat,
+ *   hidden width init_hidden = 64, used as ia355_rootinit_fwd with
+ *   IA355_BF16); compositing threshold T_thresh. */
+typedef struct ia355_batch_model {
+  const float *W;
+  int32_t Dx, Dy, Dz, nb;
+  float skin_aabb[6], hash_aabb[6];
+  int32_t max_iter;
+  float tol_stop, tol_valid;
+  const void *table;
+  int32_t L, log2T;
+  double base_res, growth;
+  const float *mlp_params, *init_params;
+  int32_t init_hidden;
+  float T_thresh;
+} ia355_batch_model;
+
+/* Every pose rendered as the staged path renders it (ia355_occgrid_march ->
+ * ia355_rootinit_fwd -> ia355_snarf_deform_guided -> ia355_hashgrid_encode
+ * (FP16 table, BF16 features) -> ia355_mlp_fwd (BF16) ->
+ * ia355_volrender_fwd): the same operations on the same values, so the
+ * same bits, with no per-sample buffer in global memory.
+ * ia355_batch_plan validates the poses and the model and writes the plan
+ * into ws (ia355_batch_workspace_size bytes: the plan, a work counter and
+ * per pose the blended transform grid, the folded initialiser constant and
+ * the bone inverses); it copies from host memory and synchronises the
+ * stream, so it is not for graph capture.  ia355_batch_render enqueues two
+ * kernels (per-pose preparation, then the persistent render, whose
+ * workgroups take tiles of rays_per_tile rays (1..64) of one pose per wave
+ * from a work counter, in segments of at most samples_per_segment samples
+ * (256..8192)), and is capturable; it reads the plan from ws, which must be
+ * the ws the plan was written to (a ws without a valid plan renders
+ * nothing).  256 * blocks_per_cu workgroups (1..8) of 256 threads;
+ * ia355_batch_lds_bytes gives a schedule's LDS per workgroup (0: invalid
+ * shape), which must not exceed 64 KB (IA355_ERR_UNSUPPORTED). */
+size_t ia355_batch_workspace_size(int32_t n_poses, int32_t Dx, int32_t Dy, int32_t Dz, int32_t nb);
+int32_t ia355_batch_plan(const ia355_batch_pose *poses, int32_t n_poses, const ia355_batch_model *model,
+                         void *ws, size_t ws_bytes, ia355_stream_t stream);
+size_t ia355_batch_lds_bytes(int32_t rays_per_tile, int32_t samples_per_segment);
+int32_t ia355_batch_render(const void *ws, size_t ws_bytes, int32_t rays_per_tile, int32_t samples_per_segment,
+                           int32_t blocks_per_cu, ia355_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

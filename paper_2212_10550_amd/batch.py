@@ -1,18 +1,23 @@
-"""Batched render of many poses of one avatar in one HIP graph.
+"""Batched render of many poses of one avatar.
 
 Each pose runs the inference forward of the path (Fig. 2): march with
 empty-space skipping, learned root initialiser, guided Broyden with
 multi-init fallback, FP16 hash encode, BF16 MLP, compositing with early
-termination.  Every call takes its sample count from device memory, so
-the whole batch is enqueued without a host round trip and captured as one
-HIP graph; replaying it is one launch.
+termination.  Two executions of the same arithmetic:
 
-Poses are spread over a few streams inside the graph (fork from the
-capture stream, join back), so the small poses' kernels fill the CUs while
-a large pose's kernels drain.  Each stream owns one set of sample buffers
-("slot"), sized for the largest pose it runs; the exact per-pose sample
-counts come from a march prepass at build time.  ``autotune`` picks the
-number of streams by timing each candidate graph.
+* persistent (``ia355_batch_render``): one preparation kernel (per-pose
+  transform grids and initialiser constants) and one persistent kernel
+  whose waves take tiles of rays of any pose from a work counter and carry
+  each tile through the whole path on chip; the schedule is the tile shape
+  (rays per tile, samples per segment) and the workgroups per CU.
+* staged: the path's kernels per pose, every call taking its sample count
+  from device memory, poses spread over a few streams inside one graph
+  (fork from the capture stream, join back); each stream owns one set of
+  sample buffers ("slot") sized for its largest pose (exact counts from a
+  march prepass at build time).  The schedule is the number of streams.
+
+Both are captured as one HIP graph; ``autotune`` times every candidate
+schedule and keeps the fastest.  Both write the same bits for every pose.
 """
 from __future__ import annotations
 
@@ -83,6 +88,9 @@ class BatchRenderer:
         self.ri_params = t(rootinit_params)
         self.ri_dtype = rootinit_dtype
         self.poses = [_Pose(w, dev) for w in workloads]
+        self.slots = None
+        self.persistent = None  # (rays per tile, samples per segment, workgroups per CU) when chosen
+        self._ws = None
         self._prepass()
         self.set_streams(n_streams)
         self.graph = None
@@ -97,11 +105,46 @@ class BatchRenderer:
                             None, None, None, 0, p.ray_off, p.ray_cnt, p.ray_dt, n, ws)
             p.S = int(n.item())
 
-    def set_streams(self, n_streams):
-        """Assign poses to n_streams streams, longest (most samples) first onto
-        the least loaded stream, and size each stream's buffers."""
+    def set_persistent(self, rays_per_tile=32, samples_per_segment=256, blocks_per_cu=2):
+        """Render with the persistent kernel and this schedule (the staged
+        buffers are released)."""
+        if self.ri_dtype != K.BF16:
+            raise ValueError("the persistent render runs the BF16 initialiser")
+        if K.batch_lds_bytes(rays_per_tile, samples_per_segment) == 0:
+            raise ValueError(f"invalid tile shape {rays_per_tile} rays / {samples_per_segment} samples")
         self.graph = None
         self.slots = None
+        torch.cuda.empty_cache()
+        self._plan()
+        self.persistent = (rays_per_tile, samples_per_segment, blocks_per_cu)
+
+    def _plan(self):
+        if self._ws is not None:
+            return
+        w0 = self.w0
+        for p in self.poses:
+            w = p.w
+            same = (w.max_iter == w0.max_iter and w.tol_stop == w0.tol_stop and w.tol_valid == w0.tol_valid
+                    and w.T_thresh == w0.T_thresh and w.base_res == w0.base_res and w.growth == w0.growth
+                    and list(w.skin_aabb) == list(w0.skin_aabb) and list(w.hash_aabb) == list(w0.hash_aabb))
+            if not same:
+                raise ValueError("the persistent render needs one model (solver, encoding, threshold) for all poses")
+        Dz, Dy, Dx, nb = self.W.shape
+        self._ws = torch.empty(K.batch_workspace_size(len(self.poses), Dx, Dy, Dz, nb), dtype=torch.uint8,
+                               device=self.dev)
+        descs = [K.batch_pose(p.rays_o, p.rays_d, p.occ_bits, p.G, p.w.occ_aabb, p.w.dt, p.w.n_per_ray,
+                              p.w.max_steps, p.B, p.pose_t, p.color, p.opacity, p.n_used, p.T_final, p.n_fallback)
+                 for p in self.poses]
+        K.batch_plan(descs, self.W, w0.skin_aabb, w0.hash_aabb, w0.max_iter, w0.tol_stop, w0.tol_valid, self.table,
+                     w0.base_res, w0.growth, self.params, self.ri_params, w0.T_thresh, self._ws)
+
+    def set_streams(self, n_streams):
+        """Render with the staged kernels: assign poses to n_streams streams,
+        longest (most samples) first onto the least loaded stream, and size
+        each stream's buffers."""
+        self.graph = None
+        self.slots = None
+        self.persistent = None
         torch.cuda.empty_cache()
         order = sorted(range(len(self.poses)), key=lambda i: -self.poses[i].S)
         load = [0] * n_streams
@@ -139,6 +182,9 @@ class BatchRenderer:
         if self.graph is not None:
             self.graph.replay()
             return
+        if self.persistent is not None:
+            K.batch_render(self._ws, *self.persistent)
+            return
         main = torch.cuda.current_stream()
         for sl in self.slots:
             sl.stream.wait_stream(main)
@@ -174,16 +220,33 @@ class BatchRenderer:
         torch.cuda.synchronize()
         return a.elapsed_time(b) / n
 
-    def autotune(self, candidates=(1, 2, 4), n=3):
-        """Time the captured batch for each stream count and keep the fastest
-        schedule; returns {streams: ms}."""
-        res = {}
+    PERSISTENT_CANDIDATES = ((16, 256, 2), (32, 256, 2), (64, 256, 2), (32, 384, 2), (32, 256, 1), (64, 256, 1))
+
+    def autotune(self, candidates=(1, 2, 4), n=3, persistent=None):
+        """Time the captured batch for each schedule -- every stream count of
+        the staged kernels and every (rays per tile, samples per segment,
+        workgroups per CU) of the persistent kernel -- and keep the fastest;
+        returns {schedule name: ms}."""
+        if persistent is None:
+            persistent = self.PERSISTENT_CANDIDATES if self.ri_dtype == K.BF16 else ()
+        res, setters = {}, {}
         for c in candidates:
+            name = f"staged/{c} streams"
             self.set_streams(c)
-            res[c] = self.time_ms(n)
+            res[name] = self.time_ms(n)
+            setters[name] = (self.set_streams, (c,))
+        for sched in persistent:
+            if K.batch_lds_bytes(*sched[:2]) == 0 or K.batch_lds_bytes(*sched[:2]) > 64 * 1024:
+                continue
+            name = "persistent/{} rays x {} samples, {} wg per CU".format(*sched)
+            self.set_persistent(*sched)
+            res[name] = self.time_ms(n)
+            setters[name] = (self.set_persistent, sched)
         best = min(res, key=res.get)
-        self.set_streams(best)
+        fn, a = setters[best]
+        fn(*a)
         self.capture()
+        self.schedule = best
         return res
 
     @property

@@ -1,0 +1,655 @@
+// Batched inference render of many poses of one avatar in one persistent
+// launch: for every ray of every pose, the sampling with empty-space
+// skipping of Sec. 3.2-3.3, the canonical correspondence of Sec. 3.1 (learned
+// initialiser, one guided Broyden solve, the multi-init solve as fallback),
+// the hash-grid encoding and decoder MLP of Eq. 1-2 in their FP16/BF16 form,
+// and the volume rendering of Eq. 8 with early termination.
+//
+// Two kernels per call:
+//  * prep: blends each pose's transform grid A (Eq. 5-7 pre-blended, as the
+//    deform kernels do), folds the pose into the initialiser's first layer,
+//    inverts the bone transforms, and clears the work queue and counters;
+//  * render: persistent.  256 x blocks_per_cu workgroups of four waves;
+//    every wave takes tiles of consecutive rays of one pose from a global
+//    atomic counter and carries each through the whole path on its own:
+//      march   -- each ray's keep masks (one ballot per 64 steps, the march
+//                 kernels' test) and sample counts into the wave's LDS;
+//      segment -- the tile's rays are cut into segments of whole rays with
+//                 at most samples_per_segment samples; per segment, chunks
+//                 of 64 samples (one per lane) run position -> initialiser
+//                 (four 16-sample MFMA tiles) -> guided Broyden; accepted
+//                 samples go on to encode + decoder (lane r + 16 g of tile
+//                 t encodes levels 4g..4g+3 of sample 16t + r, which is
+//                 exactly the decoder's BF16 A-operand layout, so features
+//                 never leave registers); rejected samples wait in an LDS
+//                 queue and take the 24-init solve two at a time (32 lanes
+//                 each), then encode + decoder;
+//      composite -- 16 lanes per ray over the segment's densities and
+//                 colours in LDS; pixels are written to the pose's outputs.
+//    No sample ever goes to global memory.  The decoder's and initialiser's
+//    MFMA fragments are built once per workgroup into LDS and reloaded per
+//    chunk, which keeps them out of the registers the solver needs.
+// Every per-sample and per-ray operation is the same device code as in the
+// staged kernels (march_dev.h, rootinit_dev.h, deform_dev.h, hash_dev.h,
+// mlp_dev.h, render_dev.h), so a pose rendered here gives the same bits as
+// the staged path.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+#include "deform_dev.h"
+#include "geometry.h"
+#include "hash_dev.h"
+#include "march_dev.h"
+#include "mlp_dev.h"
+#include "render_dev.h"
+#include "rootinit_dev.h"
+
+using namespace ia355;
+
+namespace {
+
+constexpr int kMaxPoses = IA355_BATCH_MAX_POSES;
+constexpr int kMaxTileRays = 64;   // one lane per ray in the span pass
+constexpr int kMaxSteps = 128;     // two 64-bit keep masks per ray
+constexpr int kWaves = 4;
+constexpr int kBlock = kWaves * kWave;
+constexpr int kPrepBlock = dfm::kBlendBlock;
+constexpr int kLevels = 16;        // decoder input 32 = 16 levels x 2 features
+constexpr uint32_t kMagic = 0x1a355b01u;
+constexpr size_t kMaxLds = 64 * 1024;
+
+struct PoseDev {
+  const float *ro, *rd;
+  int64_t R;
+  const uint32_t *bits;
+  int G, pow2, n_per_ray, max_steps;
+  mch::Box box;
+  float dt_fixed;
+  const float *B, *pose;
+  float *color, *opacity, *T_final;
+  int32_t *n_used, *n_fallback;
+  float *A, *c1, *binv;  // workspace: blended grid, folded layer-1 constant, bone inverses
+  int *bok;
+};
+
+struct Plan {
+  uint32_t magic;
+  int n_poses, nb;
+  size_t ws_need;
+  const float *W;
+  int64_t nvert, nblend;
+  dfm::Grid gr;
+  dfm::Box hbox;
+  int max_iter;
+  float tol_stop, tol_valid;
+  const __half *table;
+  uint32_t T, Tmask;
+  hsh::Box ebox;
+  hsh::Levels lv;
+  const float *mlp, *init;
+  float T_thresh;
+  PoseDev pose[kMaxPoses];
+};
+
+// Workgroup-shared LDS: MFMA fragments of the decoder (14 per lane) and the
+// initialiser's layers 2-3 (12 per lane), lane-contiguous; biases; the
+// initialiser's layer-1 position weights; level constants; tile prefix.
+struct Store {
+  bf16x8 mw[14][kWave];
+  bf16x8 rw[12][kWave];
+  float mb1[64], mb2[64], mb3[4];
+  float rb2[64], rb3[rid::kMaxOut];
+  float w1x[rid::H * 3];
+  int res[kLevels], dense[kLevels];
+  int64_t tile0[kMaxPoses + 1];
+};
+
+// Per-wave LDS, carved from one block (sizes from the tile shape).
+struct WaveMem {
+  uint64_t *mask;  // [rt][2]
+  float *o, *d;    // [rt][3]
+  float *tn, *tf, *dt;
+  int *off;        // [rt + 1]
+  float *sig;      // [ch]
+  float *rgb;      // [ch][3]
+  int16_t *queue;  // [ch]
+};
+
+__host__ __device__ inline size_t wave_bytes(int rt, int ch) {
+  size_t b = 16 * (size_t)rt;                  // masks
+  b += sizeof(float) * 9 * (size_t)rt;         // o, d, tn, tf, dt
+  b += sizeof(int) * (size_t)(rt + 1);         // off
+  b += sizeof(float) * 4 * (size_t)ch;         // sig, rgb
+  b += sizeof(int16_t) * (size_t)ch;           // queue
+  return (b + 15) & ~(size_t)15;
+}
+
+__device__ inline WaveMem carve(char *p, int rt, int ch) {
+  WaveMem w;
+  w.mask = reinterpret_cast<uint64_t *>(p);
+  p += 16 * (size_t)rt;
+  w.o = reinterpret_cast<float *>(p);
+  w.d = w.o + 3 * rt;
+  w.tn = w.d + 3 * rt;
+  w.tf = w.tn + rt;
+  w.dt = w.tf + rt;
+  w.off = reinterpret_cast<int *>(w.dt + rt);
+  w.sig = reinterpret_cast<float *>(w.off + rt + 1);
+  w.rgb = w.sig + ch;
+  w.queue = reinterpret_cast<int16_t *>(w.rgb + 3 * ch);
+  return w;
+}
+
+// Position of the q-th (from 0) set bit of the 128-bit mask (m0, m1).
+__host__ __device__ inline int select_bit(uint64_t m0, uint64_t m1, int q) {
+  const int c0 = __builtin_popcountll(m0);
+  uint64_t m = q < c0 ? m0 : m1;
+  int pos = q < c0 ? 0 : 64;
+  if (q >= c0) q -= c0;
+  for (int w = 32; w >= 1; w >>= 1) {
+    const int c = __builtin_popcountll(m & ((1ull << w) - 1ull));
+    if (q >= c) {
+      q -= c;
+      m >>= w;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+// Ray (in [ra, rb)) holding tile sample j: the last ray whose first sample
+// is at or before j.
+__device__ inline int ray_of(const int *off, int ra, int rb, int j) {
+  int lo = ra, hi = rb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= j)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Posed position of tile sample j (the march's expression for its step).
+__device__ inline void sample_xp(const WaveMem &wm, int ra, int rb, int j, float xp[3]) {
+  const int rr = ray_of(wm.off, ra, rb, j);
+  const int k = select_bit(wm.mask[2 * rr], wm.mask[2 * rr + 1], j - wm.off[rr]);
+  float t;
+  mch::sample_pos(wm.o + 3 * rr, wm.d + 3 * rr, wm.tn[rr], wm.dt[rr], k, &t, xp);
+}
+
+__device__ inline void get_mfrag(const Store &st, int lane, int g, mlpd::FragBf &f) {
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f.w1[mt] = st.mw[mt][lane];
+    f.w2[mt][0] = st.mw[4 + 2 * mt][lane];
+    f.w2[mt][1] = st.mw[5 + 2 * mt][lane];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      f.b1[mt][i] = st.mb1[16 * mt + 4 * g + i];
+      f.b2[mt][i] = st.mb2[16 * mt + 4 * g + i];
+    }
+  }
+  f.w3[0] = st.mw[12][lane];
+  f.w3[1] = st.mw[13][lane];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f.b3[i] = (4 * g + i) < mlpd::NOUT ? st.mb3[4 * g + i] : 0.0f;
+}
+
+__device__ inline void get_rfrag(const Store &st, int lane, int g, rid::Frag<true> &f) {
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f.w2b[mt][0] = st.rw[2 * mt][lane];
+    f.w2b[mt][1] = st.rw[2 * mt + 1][lane];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f.b2[mt][i] = st.rb2[16 * mt + 4 * g + i];
+  }
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    f.w3b[mt][0] = st.rw[8 + 2 * mt][lane];
+    f.w3b[mt][1] = st.rw[9 + 2 * mt][lane];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f.b3[mt][i] = st.rb3[16 * mt + 4 * g + i];
+  }
+}
+
+__device__ inline __bf16 to_bf16(float v) {
+  return __builtin_bit_cast(__bf16, __builtin_bit_cast(uint16_t, __float2bfloat16(v)));
+}
+
+// Encode + decoder of one 16-sample tile: lane r + 16 g encodes levels
+// 4g..4g+3 of its row's sample (x, bone; bone < 0 gives zero features and
+// zero outputs, as the staged encode and decoder do); rows with store set
+// write sigma and colour at slot.
+__device__ inline void encode_decode(const Plan &pl, const Store &st, const mlpd::FragBf &f, const float x[3],
+                                     int bone, bool store, int slot, int g, float *sig, float *rgb, int ch) {
+  bf16x8 X;
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    const int l = 4 * g + jj;
+    float a = 0.0f, b = 0.0f;
+    if (bone >= 0)
+      hsh::encode_level(x, pl.ebox, st.res[l], st.dense[l] != 0, pl.Tmask, pl.table + (int64_t)l * pl.T * 2, &a, &b);
+    X[2 * jj] = to_bf16(a);
+    X[2 * jj + 1] = to_bf16(b);
+  }
+  f32x4 z1[4], z2[4], o;
+  mlpd::fwd_bf(f, X, z1, z2, o);
+  if (g == 0 && store) {
+    float sg = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
+    if (bone >= 0) {
+      const float ov[4] = {o[0], o[1], o[2], o[3]};
+      mlpd::head(ov, &sg, c);
+    }
+    sig[slot] = sg;
+    rgb[slot] = c[0];
+    rgb[ch + slot] = c[1];
+    rgb[2 * ch + slot] = c[2];
+  }
+}
+
+struct LdsSrc {
+  const float *sig, *rgb;
+  int ch;
+  __device__ __forceinline__ void operator()(int64_t i, float *s, float c[3]) const {
+    *s = sig[i];
+    c[0] = rgb[i];
+    c[1] = rgb[ch + i];
+    c[2] = rgb[2 * ch + i];
+  }
+};
+
+__global__ void __launch_bounds__(kPrepBlock) prep_kernel(const Plan *__restrict__ plp, size_t ws_bytes,
+                                                          int *__restrict__ queue) {
+  const Plan &pl = *plp;
+  if (pl.magic != kMagic || pl.ws_need > ws_bytes) return;
+  __shared__ float sB[dfm::kMaxBones * 12];
+  __shared__ __attribute__((aligned(16))) float sW[dfm::kBlendBlock * dfm::kBlendMaxBones];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;
+  const int64_t per = pl.nblend + 1;
+  const int64_t items = per * pl.n_poses;
+  const rid::Layout l = rid::layout(pl.nb);
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int p = (int)(it / per);
+    const int64_t sub = it - (int64_t)p * per;
+    const PoseDev &pd = pl.pose[p];
+    if (sub < pl.nblend) {
+      dfm::blend_block(pl.W, pd.B, pl.nb, pl.nvert, pd.A, sub, sB, sW);
+    } else {
+      rid::fold_pose(pl.init, l, pd.pose, pl.nb, pd.c1);
+      stage_bone_inverses(pd.B, pl.nb, pd.binv, pd.bok);
+      if (threadIdx.x == 0 && pd.n_fallback) *pd.n_fallback = 0;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kBlock, 2) render_kernel(const Plan *__restrict__ plp, size_t ws_bytes,
+                                                        int *__restrict__ queue, int rt, int ch) {
+  const Plan &pl = *plp;
+  if (pl.magic != kMagic || pl.ws_need > ws_bytes) return;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  Store &st = *reinterpret_cast<Store *>(lds);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const int nb = pl.nb;
+  // ---- workgroup set-up: fragments and constants (the same values as the
+  // staged kernels build from their LDS copies of the parameters)
+  const rid::Layout rl = rid::layout(nb);
+  if (wid == 0) {
+    rid::Frag<true> rf;
+    rid::load_frag<true>(pl.init, rl, r, g, rf);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      st.rw[2 * mt][lane] = rf.w2b[mt][0];
+      st.rw[2 * mt + 1][lane] = rf.w2b[mt][1];
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      st.rw[8 + 2 * mt][lane] = rf.w3b[mt][0];
+      st.rw[9 + 2 * mt][lane] = rf.w3b[mt][1];
+    }
+  } else if (wid == 1) {
+    mlpd::FragBf mf;
+    mlpd::load_frag_bf(pl.mlp, r, g, mf);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      st.mw[mt][lane] = mf.w1[mt];
+      st.mw[4 + 2 * mt][lane] = mf.w2[mt][0];
+      st.mw[5 + 2 * mt][lane] = mf.w2[mt][1];
+    }
+    st.mw[12][lane] = mf.w3[0];
+    st.mw[13][lane] = mf.w3[1];
+  }
+  for (int i = threadIdx.x; i < 64; i += kBlock) {
+    st.mb1[i] = pl.mlp[mlpd::OFF_B1 + i];
+    st.mb2[i] = pl.mlp[mlpd::OFF_B2 + i];
+    st.rb2[i] = pl.init[rl.offb2 + i];
+  }
+  for (int i = threadIdx.x; i < rid::kMaxOut; i += kBlock) st.rb3[i] = i < rl.nout ? pl.init[rl.offb3 + i] : 0.0f;
+  for (int i = threadIdx.x; i < 4; i += kBlock) st.mb3[i] = pl.mlp[mlpd::OFF_B3 + i];
+  for (int e = threadIdx.x; e < rid::H * 3; e += kBlock) st.w1x[e] = pl.init[rl.offW1 + (e / 3) * rl.nin + (e % 3)];
+  for (int i = threadIdx.x; i < kLevels; i += kBlock) {
+    st.res[i] = pl.lv.res[i];
+    st.dense[i] = pl.lv.dense[i];
+  }
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int p = 0; p < pl.n_poses; ++p) {
+      st.tile0[p] = t;
+      t += (pl.pose[p].R + rt - 1) / rt;
+    }
+    st.tile0[pl.n_poses] = t;
+  }
+  __syncthreads();
+  const int64_t n_tiles = st.tile0[pl.n_poses];
+  const WaveMem wm = carve(lds + sizeof(Store) + (size_t)wid * wave_bytes(rt, ch), rt, ch);
+  const uint64_t below = (1ull << lane) - 1ull;
+  const int C = ch - kMaxSteps;  // segment start stride: a segment holds at most C + 128 = ch samples
+
+  // ---- tiles, one wave each, until the queue is drained (no wave ever
+  // waits for another: the loop ends for every wave)
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(queue, 1);
+    item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, kWave));
+    if ((int64_t)item >= n_tiles) break;
+    int p = 0;
+    while (p + 1 < pl.n_poses && st.tile0[p + 1] <= item) ++p;
+    p = __builtin_amdgcn_readfirstlane(p);
+    const PoseDev &pd = pl.pose[p];
+    const int64_t ray0 = (int64_t)(item - st.tile0[p]) * rt;
+    const int nr = (int)min((int64_t)rt, pd.R - ray0);
+
+    // march: spans (one lane per ray), then keep masks (lanes = steps)
+    if (lane < nr) {
+      float o[3], d[3];
+      mch::load_ray(pd.ro, pd.rd, ray0 + lane, o, d);
+      const mch::RaySpan s = mch::ray_span(o, d, pd.box, pd.dt_fixed, pd.n_per_ray);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        wm.o[3 * lane + a] = o[a];
+        wm.d[3 * lane + a] = d[a];
+      }
+      wm.tn[lane] = s.tn;
+      wm.tf[lane] = s.hit ? s.tf : -INFINITY;
+      wm.dt[lane] = s.dt;
+    }
+    mlpd::wave_sync();
+    for (int rr = 0; rr < nr; ++rr) {
+      uint64_t m0 = 0, m1 = 0;
+      const float tf = wm.tf[rr];
+      if (tf != -INFINITY) {
+        const float o[3] = {wm.o[3 * rr], wm.o[3 * rr + 1], wm.o[3 * rr + 2]};
+        const float d[3] = {wm.d[3 * rr], wm.d[3 * rr + 1], wm.d[3 * rr + 2]};
+        const mch::RaySpan s{wm.tn[rr], tf, wm.dt[rr], true};
+        bool keep0 = false, keep1 = false;
+        float t0 = 0.0f, t1 = 0.0f, x[3];
+        if (lane < pd.max_steps)
+          keep0 = pd.pow2 ? mch::sample_at<true>(o, d, s, lane, pd.box, pd.bits, pd.G, &t0, x)
+                          : mch::sample_at<false>(o, d, s, lane, pd.box, pd.bits, pd.G, &t0, x);
+        if (lane + kWave < pd.max_steps)
+          keep1 = pd.pow2 ? mch::sample_at<true>(o, d, s, lane + kWave, pd.box, pd.bits, pd.G, &t1, x)
+                          : mch::sample_at<false>(o, d, s, lane + kWave, pd.box, pd.bits, pd.G, &t1, x);
+        m0 = __ballot(keep0 && t0 < tf);
+        m1 = __ballot(keep1 && t1 < tf);
+      }
+      if (lane == 0) {
+        wm.mask[2 * rr] = m0;
+        wm.mask[2 * rr + 1] = m1;
+      }
+    }
+    mlpd::wave_sync();
+    {
+      const int cnt = lane < nr ? __popcll(wm.mask[2 * lane]) + __popcll(wm.mask[2 * lane + 1]) : 0;
+      const int incl = wave_incl_scan(cnt);
+      if (lane < nr) wm.off[lane + 1] = incl;
+      if (lane == 0) wm.off[0] = 0;
+    }
+    mlpd::wave_sync();
+    const int total = wm.off[nr];
+    const int nseg = total == 0 ? 1 : (total + C - 1) / C;
+    const float *A = pd.A;
+    int nfb = 0;
+    int ra = 0;
+    for (int sgi = 0; sgi < nseg; ++sgi) {
+      int rb = nr;
+      if (sgi + 1 < nseg) {
+        const int v = (sgi + 1) * C;
+        const uint64_t bm = __ballot(lane < nr && wm.off[lane] >= v);
+        rb = bm ? (int)__builtin_ctzll(bm) : nr;
+      }
+      const int sb = wm.off[ra], se = wm.off[rb], n = se - sb;
+      int qn = 0;
+      for (int c0 = 0; c0 < n; c0 += kWave) {
+        const int j = sb + c0 + lane;
+        const bool act = j < se;
+        const int nt = (min(kWave, n - c0) + 15) >> 4;  // 16-sample tiles in this chunk
+        float xp[3] = {0.0f, 0.0f, 0.0f};
+        if (act) sample_xp(wm, ra, rb, j, xp);
+        // learned initialiser: lane r + 16 t's sample is row r of tile t,
+        // and that lane holds the tile's result for it
+        int ibone = 0;
+        float x0[3] = {0.0f, 0.0f, 0.0f};
+        {
+          rid::Frag<true> f;
+          get_rfrag(st, lane, g, f);
+          for (int t = 0; t < nt; ++t) {
+            const int src = 16 * t + r;
+            const float xs[3] = {__shfl(xp[0], src, kWave), __shfl(xp[1], src, kWave), __shfl(xp[2], src, kWave)};
+            int bi;
+            float off3[3];
+            rid::tile<true>(xs, pd.c1, st.w1x, f, nb, g, &bi, off3);
+            if (g == t) {
+              const int kb = bi < nb ? bi : 0;
+              ibone = kb;
+              rid::start_point(pd.binv + 12 * kb, xs, off3, x0);
+            }
+          }
+        }
+        // guided solve
+        bool fb = false;
+        int bone = -1;
+        float xc[3] = {0.0f, 0.0f, 0.0f};
+        if (act) {
+          const dfm::InitResult q = dfm::broyden_from(A, pl.gr, x0, true, xp, pl.max_iter, pl.tol_stop);
+          if (q.ok && q.r < pl.tol_valid && dfm::in_hbox(q.x, pl.hbox)) {
+            xc[0] = q.x[0];
+            xc[1] = q.x[1];
+            xc[2] = q.x[2];
+            bone = ibone;
+          } else {
+            fb = true;
+          }
+        }
+        const uint64_t fm = __ballot(fb);
+        if (fb) wm.queue[qn + __popcll(fm & below)] = (int16_t)(c0 + lane);
+        qn += __popcll(fm);
+        // encode + decoder of the accepted samples
+        {
+          mlpd::FragBf f;
+          get_mfrag(st, lane, g, f);
+          for (int t = 0; t < nt; ++t) {
+            const int src = 16 * t + r;
+            const float xs[3] = {__shfl(xc[0], src, kWave), __shfl(xc[1], src, kWave), __shfl(xc[2], src, kWave)};
+            const int bs = __shfl(bone, src, kWave);
+            encode_decode(pl, st, f, xs, bs, bs >= 0, c0 + src, g, wm.sig, wm.rgb, ch);
+          }
+        }
+      }
+      mlpd::wave_sync();
+      // fallback: the multi-init solve of the queued samples, two at a time
+      // (32 lanes each), then their encode + decoder as rows 0 and 1 of a tile
+      for (int q0 = 0; q0 < qn; q0 += 2) {
+        const int h = lane >> 5;
+        const bool qa = q0 + h < qn;
+        const int sj = qa ? (int)wm.queue[q0 + h] : 0;
+        float xp[3] = {0.0f, 0.0f, 0.0f};
+        if (qa) sample_xp(wm, ra, rb, sb + sj, xp);
+        const dfm::Choice cc = dfm::multi_init<32>(A, pl.gr, pd.binv, pd.bok, nb, xp, qa, lane & 31, pl.hbox,
+                                                   pl.max_iter, pl.tol_stop, pl.tol_valid);
+        const int src = r < 2 ? 32 * r : 0;
+        const float xs[3] = {__shfl(cc.x[0], src, kWave), __shfl(cc.x[1], src, kWave), __shfl(cc.x[2], src, kWave)};
+        const bool qs = __shfl((int)qa, src, kWave) != 0 && r < 2;
+        const int bs = qs ? __shfl(cc.bone, src, kWave) : -1;
+        const int slot = __shfl(sj, src, kWave);
+        mlpd::FragBf f;
+        get_mfrag(st, lane, g, f);
+        encode_decode(pl, st, f, xs, bs, qs, slot, g, wm.sig, wm.rgb, ch);
+      }
+      nfb += qn;
+      mlpd::wave_sync();
+      // composite: 16 lanes per ray, four rays at a time
+      const LdsSrc src{wm.sig, wm.rgb, ch};
+      for (int r0 = ra; r0 < rb; r0 += 4) {
+        const int rr = r0 + (lane >> 4), jj = lane & 15;
+        if (rr < rb) {
+          const rnd::RayOut q =
+              rnd::composite_ray(src, wm.off[rr] - sb, wm.off[rr + 1] - sb, wm.dt[rr], pl.T_thresh, jj);
+          if (jj == 0) {
+            const int64_t gr = ray0 + rr;
+            pd.color[3 * gr] = q.C[0];
+            pd.color[3 * gr + 1] = q.C[1];
+            pd.color[3 * gr + 2] = q.C[2];
+            pd.opacity[gr] = q.A;
+            pd.n_used[gr] = q.used;
+            pd.T_final[gr] = q.T;
+          }
+        }
+      }
+      mlpd::wave_sync();
+      ra = rb;
+    }
+    if (lane == 0 && nfb > 0 && pd.n_fallback) atomicAdd(pd.n_fallback, nfb);
+  }
+}
+
+struct WsLayout {
+  size_t plan, queue, pose0, A, c1, binv, bok, per_pose, total;
+};
+
+WsLayout ws_layout(int n_poses, int64_t nvert, int nb) {
+  WsLayout w;
+  w.plan = 0;
+  w.queue = align256(sizeof(Plan));
+  w.pose0 = w.queue + 256;
+  w.A = 0;
+  w.c1 = align256(sizeof(float) * 12 * (size_t)nvert);
+  w.binv = w.c1 + 256;
+  w.bok = w.binv + align256(sizeof(float) * 12 * (size_t)nb);
+  w.per_pose = w.bok + align256(sizeof(int) * (size_t)nb);
+  w.total = w.pose0 + (size_t)n_poses * w.per_pose;
+  return w;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+}  // namespace
+
+extern "C" size_t ia355_batch_workspace_size(int32_t n_poses, int32_t Dx, int32_t Dy, int32_t Dz, int32_t nb) {
+  if (n_poses < 1 || n_poses > kMaxPoses || Dx < 2 || Dy < 2 || Dz < 2 || nb < 1 || nb > dfm::kMaxBones ||
+      nb + 3 > rid::kMaxOut)
+    return 0;
+  return ws_layout(n_poses, (int64_t)Dx * Dy * Dz, nb).total;
+}
+
+extern "C" int32_t ia355_batch_plan(const ia355_batch_pose *poses, int32_t n_poses, const ia355_batch_model *m,
+                                    void *ws, size_t ws_bytes, ia355_stream_t stream) {
+  if (!poses || !m || n_poses < 1 || n_poses > kMaxPoses) return IA355_ERR_INVALID_ARG;
+  const int nb = m->nb;
+  if (nb < 1 || nb > dfm::kMaxBones || nb + 3 > rid::kMaxOut) return IA355_ERR_INVALID_ARG;
+  if (!m->W || !dfm::grid_ok(m->Dx, m->Dy, m->Dz, m->skin_aabb)) return IA355_ERR_INVALID_ARG;
+  if (m->max_iter < 0 || m->max_iter > 1000) return IA355_ERR_INVALID_ARG;
+  if (!m->table || !aligned16(m->table) || !m->mlp_params || !aligned16(m->mlp_params) || !m->init_params)
+    return IA355_ERR_INVALID_ARG;
+  if (m->L != kLevels || m->log2T < 2 || m->log2T > 30) return IA355_ERR_UNSUPPORTED;
+  if (m->init_hidden != rid::H) return IA355_ERR_UNSUPPORTED;
+  Plan pl{};
+  pl.magic = kMagic;
+  pl.n_poses = n_poses;
+  pl.nb = nb;
+  pl.W = m->W;
+  pl.nvert = (int64_t)m->Dx * m->Dy * m->Dz;
+  pl.nblend = ceil_div(pl.nvert, dfm::kBlendBlock);
+  pl.gr = dfm::make_grid(m->Dx, m->Dy, m->Dz, m->skin_aabb);
+  for (int a = 0; a < 3; ++a) {
+    pl.hbox.lo[a] = m->hash_aabb[a];
+    pl.hbox.hi[a] = m->hash_aabb[3 + a];
+  }
+  pl.max_iter = m->max_iter;
+  pl.tol_stop = m->tol_stop;
+  pl.tol_valid = m->tol_valid;
+  pl.table = (const __half *)m->table;
+  pl.T = 1u << m->log2T;
+  pl.Tmask = pl.T - 1u;
+  if (hsh::make_levels(m->L, m->log2T, m->base_res, m->growth, &pl.lv) || hsh::make_box(m->hash_aabb, &pl.ebox))
+    return IA355_ERR_INVALID_ARG;
+  pl.mlp = m->mlp_params;
+  pl.init = m->init_params;
+  pl.T_thresh = m->T_thresh;
+  const WsLayout wl = ws_layout(n_poses, pl.nvert, nb);
+  pl.ws_need = wl.total;
+  if (!ws || ws_bytes < wl.total) return IA355_ERR_WORKSPACE;
+  char *base = (char *)ws;
+  for (int p = 0; p < n_poses; ++p) {
+    const ia355_batch_pose &q = poses[p];
+    PoseDev &d = pl.pose[p];
+    if (q.R < 0 || q.R > 0x7fffffffLL - 64) return IA355_ERR_INVALID_ARG;
+    if (q.R > 0 && (!q.rays_o || !q.rays_d || !q.color || !q.opacity || !q.n_used || !q.T_final))
+      return IA355_ERR_INVALID_ARG;
+    if (!q.B || !q.pose) return IA355_ERR_INVALID_ARG;
+    if (q.occ_bits && (q.G <= 0 || q.G > 2048)) return IA355_ERR_INVALID_ARG;
+    if (q.max_steps < 0 || q.max_steps > kMaxSteps) return IA355_ERR_UNSUPPORTED;
+    if (q.n_per_ray <= 0 && !(q.dt > 0.0f)) return IA355_ERR_INVALID_ARG;
+    bool pow2 = false;
+    if (!mch::make_box(q.occ_aabb, &d.box, &pow2)) return IA355_ERR_INVALID_ARG;
+    d.pow2 = pow2;
+    d.ro = q.rays_o;
+    d.rd = q.rays_d;
+    d.R = q.R;
+    d.bits = q.occ_bits;
+    d.G = q.G;
+    d.n_per_ray = q.n_per_ray;
+    d.max_steps = q.max_steps;
+    d.dt_fixed = q.dt;
+    d.B = q.B;
+    d.pose = q.pose;
+    d.color = q.color;
+    d.opacity = q.opacity;
+    d.T_final = q.T_final;
+    d.n_used = q.n_used;
+    d.n_fallback = q.n_fallback;
+    char *pp = base + wl.pose0 + (size_t)p * wl.per_pose;
+    d.A = (float *)(pp + wl.A);
+    d.c1 = (float *)(pp + wl.c1);
+    d.binv = (float *)(pp + wl.binv);
+    d.bok = (int *)(pp + wl.bok);
+  }
+  hipStream_t s = as_stream(stream);
+  if (hipMemcpyAsync(ws, &pl, sizeof(Plan), hipMemcpyHostToDevice, s) != hipSuccess) return IA355_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return IA355_ERR_HIP;
+  return IA355_OK;
+}
+
+extern "C" size_t ia355_batch_lds_bytes(int32_t rays_per_tile, int32_t samples_per_segment) {
+  if (rays_per_tile < 1 || rays_per_tile > kMaxTileRays || samples_per_segment < 2 * kMaxSteps ||
+      samples_per_segment > 8192)
+    return 0;
+  return sizeof(Store) + kWaves * wave_bytes(rays_per_tile, samples_per_segment);
+}
+
+extern "C" int32_t ia355_batch_render(const void *ws, size_t ws_bytes, int32_t rays_per_tile,
+                                      int32_t samples_per_segment, int32_t blocks_per_cu, ia355_stream_t stream) {
+  if (!ws || ws_bytes < align256(sizeof(Plan)) + 256) return IA355_ERR_WORKSPACE;
+  if (blocks_per_cu < 1 || blocks_per_cu > 8) return IA355_ERR_INVALID_ARG;
+  const size_t lds = ia355_batch_lds_bytes(rays_per_tile, samples_per_segment);
+  if (lds == 0) return IA355_ERR_INVALID_ARG;
+  if (lds > kMaxLds) return IA355_ERR_UNSUPPORTED;
+  hipStream_t s = as_stream(stream);
+  const Plan *pl = (const Plan *)ws;
+  int *queue = (int *)((char *)ws + align256(sizeof(Plan)));
+  prep_kernel<<<1024, kPrepBlock, 0, s>>>(pl, ws_bytes, queue);
+  render_kernel<<<256 * blocks_per_cu, kBlock, lds, s>>>(pl, ws_bytes, queue, rays_per_tile, samples_per_segment);
+  return launch_status();
+}

@@ -12,6 +12,10 @@ namespace ia355 {
 
 constexpr int kWave = 64;
 
+// MFMA operand and accumulator vectors
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 inline int32_t launch_status() {
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? IA355_OK : IA355_ERR_HIP;

@@ -24,84 +24,17 @@
 #include <cmath>
 
 #include "common.h"
+#include "march_dev.h"
 
 using namespace ia355;
+using namespace ia355::mch;
 
 namespace {
-
-struct Box {
-  float lo[3], hi[3];
-  float inv_ext[3];  // 1 / (hi - lo), used only when every extent is a power of two
-};
-
-struct RaySpan {
-  float tn, tf, dt;
-  bool hit;
-};
-
-__device__ __forceinline__ RaySpan ray_span(const float o[3], const float d[3], const Box &b, float dt_fixed,
-                                            int n_per_ray) {
-#pragma clang fp contract(off)
-  float tmin = -INFINITY, tmax = INFINITY;
-  RaySpan s{0.0f, 0.0f, 0.0f, false};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (d[a] != 0.0f) {
-      const float ta = (b.lo[a] - o[a]) / d[a];
-      const float tb = (b.hi[a] - o[a]) / d[a];
-      const float t0 = ta < tb ? ta : tb;
-      const float t1 = ta < tb ? tb : ta;
-      if (t0 > tmin) tmin = t0;
-      if (t1 < tmax) tmax = t1;
-    } else if (o[a] < b.lo[a] || o[a] > b.hi[a]) {
-      return s;
-    }
-  }
-  const float tn = tmin > 0.0f ? tmin : 0.0f;
-  if (!(tmax > tn)) return s;
-  s.tn = tn;
-  s.tf = tmax;
-  s.dt = n_per_ray > 0 ? (tmax - tn) / (float)n_per_ray : dt_fixed;
-  s.hit = true;
-  return s;
-}
-
-// Sample k of a ray: position and whether its cell is occupied.
-// kPow2Ext: every box extent is a power of two, so dividing by it and
-// multiplying by its (exact) reciprocal round the same real number once and
-// give the same float; the multiply saves the division sequence.
-template <bool kPow2Ext>
-__device__ __forceinline__ bool sample_at(const float o[3], const float d[3], const RaySpan &s, int k, const Box &b,
-                                          const uint32_t *bits, int G, float *t_out, float x[3]) {
-#pragma clang fp contract(off)
-  const float t = s.tn + ((float)k + 0.5f) * s.dt;
-  *t_out = t;
-  int cell[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    x[a] = o[a] + t * d[a];
-    const float rel = kPow2Ext ? (x[a] - b.lo[a]) * b.inv_ext[a] : (x[a] - b.lo[a]) / (b.hi[a] - b.lo[a]);
-    const float u = rel * (float)G;
-    int c = (int)floorf(u);
-    cell[a] = c < 0 ? 0 : (c > G - 1 ? G - 1 : c);
-  }
-  if (!bits) return true;
-  const uint32_t word = occ_word(cell[0], cell[1], cell[2], G);
-  return (bits[word] >> occ_bit(cell[0], cell[1])) & 1u;
-}
 
 // One wave per ray: lane l handles steps k = l, l + 64, ... of its ray, so a
 // 128-step ray is two ballots.  kRays rays per workgroup.
 constexpr int kRays = 4;
 constexpr int kBlock = kRays * kWave;
-
-__device__ __forceinline__ void load_ray(const float *ro, const float *rd, int64_t r, float o[3], float d[3]) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    o[a] = ro[3 * r + a];
-    d[a] = rd[3 * r + a];
-  }
-}
 
 template <bool kPow2Ext>
 __global__ void __launch_bounds__(kBlock) march_count(const float *ro, const float *rd, int64_t R,
@@ -252,13 +185,13 @@ __global__ void __launch_bounds__(kBlock) march_fill(const float *ro, const floa
     const uint64_t m = mr[w];
     if (m == 0ull) continue;
     if ((m >> lane) & 1ull) {
-      // the count kernel's expressions for t and x (see sample_at)
-      const float t = tn + ((float)(w * kWave + lane) + 0.5f) * dt;
       const int64_t at = off + __popcll(m & below);
       if (at < cap) {
-        xs[at] = o[0] + t * d[0];
-        xs[cap + at] = o[1] + t * d[1];
-        xs[2 * cap + at] = o[2] + t * d[2];
+        float t, x[3];
+        sample_pos(o, d, tn, dt, w * kWave + lane, &t, x);
+        xs[at] = x[0];
+        xs[cap + at] = x[1];
+        xs[2 * cap + at] = x[2];
         ts[at] = t;
         ray_id[at] = (int32_t)r;
       }
@@ -316,18 +249,8 @@ extern "C" int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d,
   if ((int64_t)cap * 3 < cap) return IA355_ERR_INVALID_ARG;
   if (!ws || ws_bytes < ia355_march_workspace_size(R, max_steps)) return IA355_ERR_WORKSPACE;
   Box box;
-  for (int a = 0; a < 3; ++a) {
-    box.lo[a] = aabb[a];
-    box.hi[a] = aabb[3 + a];
-    if (!(box.hi[a] > box.lo[a])) return IA355_ERR_INVALID_ARG;
-  }
-  bool pow2 = true;
-  for (int a = 0; a < 3; ++a) {
-    const float ext = box.hi[a] - box.lo[a];
-    int e;
-    pow2 = pow2 && std::isfinite(ext) && std::frexp(ext, &e) == 0.5f && e > -100 && e < 100;
-    box.inv_ext[a] = pow2 ? 1.0f / ext : 0.0f;
-  }
+  bool pow2;
+  if (!make_box(aabb, &box, &pow2)) return IA355_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
   const int64_t nblk = ceil_div(R, kRays);
   const int64_t nchunk = ceil_div(nblk, kScanChunk);

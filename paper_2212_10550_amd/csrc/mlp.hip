@@ -16,50 +16,12 @@
 #include <hip/hip_bf16.h>
 
 #include "common.h"
+#include "mlp_dev.h"
 
 using namespace ia355;
+using namespace ia355::mlpd;
 
 namespace {
-
-constexpr int NIN = 32, NH = 64, NOUT = 4;
-constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NIN, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
-              OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NOUT * NH, NPARAM = OFF_B3 + NOUT;
-static_assert(NPARAM == 6532, "parameter count");
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// max(z, 0): one v_max_f32 (a compare-and-select keeps NaN semantics and costs two)
-__device__ __forceinline__ float relu(float z) { return fmaxf(z, 0.0f); }
-
-__device__ __forceinline__ void head(const float o[4], float *sig, float c[3]) {
-  *sig = expf(fminf(o[0], 80.0f));
-#pragma unroll
-  for (int k = 0; k < 3; ++k) c[k] = 1.0f / (1.0f + expf(-o[1 + k]));
-}
-
-// The parameters (26 KB, 16-byte aligned) copied into LDS by the whole block
-// with coalesced 16-byte loads; every wave then builds its MFMA fragments
-// from LDS instead of gathering them from global memory one value at a time.
-__device__ __forceinline__ void stage_params(const float *__restrict__ P, float *sP) {
-  static_assert(NPARAM % 4 == 0, "parameter block in whole float4s");
-  const float4 *P4 = reinterpret_cast<const float4 *>(P);
-  float4 *s4 = reinterpret_cast<float4 *>(sP);
-  for (int e = threadIdx.x; e < NPARAM / 4; e += blockDim.x) s4[e] = P4[e];
-}
 
 // --------------------------------------------------------------- FP32 fwd
 // Loads the 8 features of lane group g for sample s (levels 4g..4g+3).
@@ -174,78 +136,6 @@ __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_f32(const float *__restrict
       rgb[2 * ld + s] = c[2];
     }
   }
-}
-
-// --------------------------------------------------------------- BF16 fwd
-__device__ __forceinline__ bf16x8 load_x_bf16(const __hip_bfloat16 *feat, int64_t fst, int64_t s, int g, bool ok) {
-  bf16x8 x;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    uint32_t v = 0;
-    if (ok) v = reinterpret_cast<const uint32_t *>(feat)[(int64_t)(4 * g + j) * fst + s];
-    x[2 * j] = __builtin_bit_cast(__bf16, (uint16_t)(v & 0xffffu));
-    x[2 * j + 1] = __builtin_bit_cast(__bf16, (uint16_t)(v >> 16));
-  }
-  return x;
-}
-
-struct FragBf {
-  bf16x8 w1[4];     // [mt]: W1[16mt + r][8g + j]
-  bf16x8 w2[4][2];  // [mt][c]: W2[16mt + r][16(2c + j/4) + 4g + j%4]
-  bf16x8 w3[2];     // [c]: W3[r][...] (r < 4)
-  float b1[4][4], b2[4][4], b3[4];
-};
-
-__device__ __forceinline__ void load_frag_bf(const float *P, int r, int g, FragBf &f) {
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) f.w1[mt][j] = (__bf16)P[OFF_W1 + (16 * mt + r) * NIN + 8 * g + j];
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        f.w2[mt][c][j] = (__bf16)P[OFF_W2 + (16 * mt + r) * NH + 16 * (2 * c + j / 4) + 4 * g + (j % 4)];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      f.b1[mt][i] = P[OFF_B1 + 16 * mt + 4 * g + i];
-      f.b2[mt][i] = P[OFF_B2 + 16 * mt + 4 * g + i];
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      f.w3[c][j] = (__bf16)(r < NOUT ? P[OFF_W3 + r * NH + 16 * (2 * c + j / 4) + 4 * g + (j % 4)] : 0.0f);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) f.b3[i] = (4 * g + i) < NOUT ? P[OFF_B3 + 4 * g + i] : 0.0f;
-}
-
-// Pack the relu'd accumulators of tiles t = 2c, 2c+1 into one B operand.
-__device__ __forceinline__ bf16x8 pack_act(const f32x4 z[4], int c) {
-  bf16x8 b;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) b[j] = (__bf16)relu(z[2 * c + j / 4][j % 4]);
-  return b;
-}
-
-__device__ __forceinline__ void fwd_bf(const FragBf &f, const bf16x8 &X, f32x4 z1[4], f32x4 z2[4], f32x4 &o) {
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 acc = {f.b1[mt][0], f.b1[mt][1], f.b1[mt][2], f.b1[mt][3]};
-    z1[mt] = mfma32(f.w1[mt], X, acc);
-  }
-  const bf16x8 h1a = pack_act(z1, 0), h1b = pack_act(z1, 1);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 acc = {f.b2[mt][0], f.b2[mt][1], f.b2[mt][2], f.b2[mt][3]};
-    acc = mfma32(f.w2[mt][0], h1a, acc);
-    z2[mt] = mfma32(f.w2[mt][1], h1b, acc);
-  }
-  const bf16x8 h2a = pack_act(z2, 0), h2b = pack_act(z2, 1);
-  f32x4 acc = {f.b3[0], f.b3[1], f.b3[2], f.b3[3]};
-  acc = mfma32(f.w3[0], h2a, acc);
-  o = mfma32(f.w3[1], h2b, acc);
 }
 
 __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_bf16(const __hip_bfloat16 *__restrict__ feat,

@@ -1,0 +1,231 @@
+// The learned root initialiser (an addition to the root finding of
+// Sec. 3.1): (x', pose) -> nb bone logits and a canonical offset through
+// (3 + 6 nb) -> 64 -> 64 -> (nb + 3), shared by the initialiser kernel and
+// the fused batch renderer so that both compute the same floats (internal).
+// Layer 1's pose part is folded into a per-neuron constant c1 once per pose;
+// layers 2 and 3 run on MFMA with the decoder MLP's layouts.
+#pragma once
+#include <hip/hip_bf16.h>
+
+#include "common.h"
+
+namespace ia355 {
+namespace rid {
+
+constexpr int H = 64;        // hidden width
+constexpr int kMaxOut = 32;  // nb + 3 outputs in two 16-row MFMA tiles
+
+__device__ __forceinline__ float relu(float z) { return fmaxf(z, 0.0f); }
+
+// Offsets of the flat parameter vector (per layer W [out][in], then b).
+struct Layout {
+  int nin, nout, offW1, offb1, offW2, offb2, offW3, offb3, total;
+};
+__host__ __device__ inline Layout layout(int nb) {
+  Layout l;
+  l.nin = 3 + 6 * nb;
+  l.nout = nb + 3;
+  l.offW1 = 0;
+  l.offb1 = H * l.nin;
+  l.offW2 = l.offb1 + H;
+  l.offb2 = l.offW2 + H * H;
+  l.offW3 = l.offb2 + H;
+  l.offb3 = l.offW3 + l.nout * H;
+  l.total = l.offb3 + l.nout;
+  return l;
+}
+
+// n floats of P copied to sP by the block with coalesced 16-byte loads.
+__device__ __forceinline__ void stage_copy(const float *__restrict__ P, int n, float *sP) {
+  const int head = (int)((4 - (((uintptr_t)P >> 2) & 3)) & 3);  // floats before 16-byte alignment
+  const int h = head < n ? head : n;
+  for (int i = threadIdx.x; i < h; i += blockDim.x) sP[i] = P[i];
+  const int n4 = (n - h) >> 2;
+  const float4 *P4 = reinterpret_cast<const float4 *>(P + h);
+  for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+    const float4 q = P4[i];
+    sP[h + 4 * i] = q.x;
+    sP[h + 4 * i + 1] = q.y;
+    sP[h + 4 * i + 2] = q.z;
+    sP[h + 4 * i + 3] = q.w;
+  }
+  for (int i = h + 4 * n4 + threadIdx.x; i < n; i += blockDim.x) sP[i] = P[i];
+}
+
+// c1[n] = W1[n, 3:] . pose + b1[n] by 256 threads (four per neuron, each a
+// strided quarter of the pose terms in four independent partial sums,
+// combined across the four lanes).  P may be in LDS or global memory.
+__device__ __forceinline__ void fold_pose(const float *P, const Layout &l, const float *pose, int nb, float *c1) {
+  const int n = (threadIdx.x >> 2) & (H - 1), q = threadIdx.x & 3;
+  const float *wrow = P + l.offW1 + n * l.nin + 3;
+  const int np = 6 * nb;
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+  int i = q;
+  for (; i + 12 < np; i += 16) {
+    a0 += wrow[i] * pose[i];
+    a1 += wrow[i + 4] * pose[i + 4];
+    a2 += wrow[i + 8] * pose[i + 8];
+    a3 += wrow[i + 12] * pose[i + 12];
+  }
+  for (; i < np; i += 4) a0 += wrow[i] * pose[i];
+  float acc = (a0 + a1) + (a2 + a3);
+  acc += __shfl_xor(acc, 1, kWave);
+  acc += __shfl_xor(acc, 2, kWave);
+  if (q == 0 && threadIdx.x < 4 * H) c1[n] = acc + P[l.offb1 + n];
+}
+
+// Weight fragments of layers 2 and 3 of lane (r, g).
+template <bool BF16>
+struct Frag {
+  float w2f[4][16], w3f[2][16];
+  bf16x8 w2b[4][2], w3b[2][2];
+  float b2[4][4], b3[2][4];
+};
+
+template <bool BF16>
+__device__ __forceinline__ void load_frag(const float *sP, const Layout &l, int r, int g, Frag<BF16> &f) {
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f.b2[mt][i] = sP[l.offb2 + 16 * mt + 4 * g + i];
+    if (!BF16) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f.w2f[mt][4 * t + i] = sP[l.offW2 + (16 * mt + r) * H + 16 * t + 4 * g + i];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          f.w2b[mt][c][j] = (__bf16)sP[l.offW2 + (16 * mt + r) * H + 16 * (2 * c + j / 4) + 4 * g + (j % 4)];
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const int row = 16 * mt + r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f.b3[mt][i] = (16 * mt + 4 * g + i) < l.nout ? sP[l.offb3 + 16 * mt + 4 * g + i] : 0.0f;
+    if (!BF16) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          f.w3f[mt][4 * t + i] = row < l.nout ? sP[l.offW3 + row * H + 16 * t + 4 * g + i] : 0.0f;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          f.w3b[mt][c][j] =
+              (__bf16)(row < l.nout ? sP[l.offW3 + row * H + 16 * (2 * c + j / 4) + 4 * g + (j % 4)] : 0.0f);
+    }
+  }
+}
+
+// One 16-sample tile, called by all 64 lanes of a wave (lane r + 16 g holds
+// sample r's point x): the argmax bone (ties: the lowest) and the three
+// offsets, in every lane of sample r.  c1 [64] and w1x [64][3] in LDS.
+template <bool BF16>
+__device__ __forceinline__ void tile(const float x[3], const float *c1, const float *w1x, const Frag<BF16> &f, int nb,
+                                     int g, int *bone, float off_out[3]) {
+  // layer 1 on the VALU: lane holds neurons 16t + 4g + i of sample r
+  float h1[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int n = 16 * t + 4 * g + i;
+      h1[t][i] = relu(c1[n] + w1x[3 * n] * x[0] + w1x[3 * n + 1] * x[1] + w1x[3 * n + 2] * x[2]);
+    }
+  f32x4 z2[4], o[2];
+  if (!BF16) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 acc = {f.b2[mt][0], f.b2[mt][1], f.b2[mt][2], f.b2[mt][3]};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(f.w2f[mt][4 * t + i], h1[t][i], acc, 0, 0, 0);
+      z2[mt] = acc;
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      f32x4 acc = {f.b3[mt][0], f.b3[mt][1], f.b3[mt][2], f.b3[mt][3]};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(f.w3f[mt][4 * t + i], relu(z2[t][i]), acc, 0, 0, 0);
+      o[mt] = acc;
+    }
+  } else {
+    bf16x8 ha, hb;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      ha[j] = (__bf16)h1[j / 4][j % 4];
+      hb[j] = (__bf16)h1[2 + j / 4][j % 4];
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 acc = {f.b2[mt][0], f.b2[mt][1], f.b2[mt][2], f.b2[mt][3]};
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2b[mt][0], ha, acc, 0, 0, 0);
+      z2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2b[mt][1], hb, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      ha[j] = (__bf16)relu(z2[j / 4][j % 4]);
+      hb[j] = (__bf16)relu(z2[2 + j / 4][j % 4]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      f32x4 acc = {f.b3[mt][0], f.b3[mt][1], f.b3[mt][2], f.b3[mt][3]};
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w3b[mt][0], ha, acc, 0, 0, 0);
+      o[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w3b[mt][1], hb, acc, 0, 0, 0);
+    }
+  }
+  // argmax over the bone logits (output index 16 mt + 4 g + i < nb), ties to
+  // the lowest index; offsets are outputs nb, nb + 1, nb + 2
+  float best = -INFINITY, off[3] = {0.0f, 0.0f, 0.0f};
+  int bi = 0x7fffffff;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = 16 * mt + 4 * g + i;
+      const float v = o[mt][i];
+      if (idx < nb && (v > best || (v == best && idx < bi))) {
+        best = v;
+        bi = idx;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        if (idx == nb + a) off[a] = v;
+    }
+#pragma unroll
+  for (int m = 16; m < 64; m <<= 1) {
+    const float v2 = __shfl_xor(best, m, 64);
+    const int i2 = __shfl_xor(bi, m, 64);
+    if (v2 > best || (v2 == best && i2 < bi)) {
+      best = v2;
+      bi = i2;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) off[a] += __shfl_xor(off[a], m, 64);
+  }
+  *bone = bi;
+  off_out[0] = off[0];
+  off_out[1] = off[1];
+  off_out[2] = off[2];
+}
+
+// Broyden start point x0 = B_k^{-1} x' + offset (Bi: [M^-1 | -M^-1 t] of
+// bone k, row-major 3 x 4).
+__device__ __forceinline__ void start_point(const float *Bi, const float x[3], const float off[3], float x0[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    x0[a] = Bi[4 * a] * x[0] + Bi[4 * a + 1] * x[1] + Bi[4 * a + 2] * x[2] + Bi[4 * a + 3] + off[a];
+}
+
+}  // namespace rid
+}  // namespace ia355

@@ -12,54 +12,15 @@
 // samples kept by the termination test T_i >= T_thresh are a prefix of the
 // chunk; the ray stops at the first chunk that has an unused sample.
 #include "common.h"
+#include "render_dev.h"
 
 using namespace ia355;
+using namespace ia355::rnd;
 
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSeg = 16;  // lanes per ray
 constexpr int kRaysPerBlock = kBlock / kSeg;
-
-// Inclusive scans over the kSeg lanes of a segment (lane j of the segment
-// gets the product / sum over lanes 0..j).
-__device__ __forceinline__ float seg_scan_mul(float v, int j) {
-#pragma unroll
-  for (int o = 1; o < kSeg; o <<= 1) {
-    const float t = __shfl_up(v, o, kSeg);
-    if (j >= o) v *= t;
-  }
-  return v;
-}
-__device__ __forceinline__ float seg_scan_add(float v, int j) {
-#pragma unroll
-  for (int o = 1; o < kSeg; o <<= 1) {
-    const float t = __shfl_up(v, o, kSeg);
-    if (j >= o) v += t;
-  }
-  return v;
-}
-__device__ __forceinline__ float seg_sum(float v) {
-#pragma unroll
-  for (int o = kSeg / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kSeg);
-  return v;
-}
-
-// Transmittance before each lane's sample: T_in times the product of the
-// lower lanes' factors.  Also returns the product over all kSeg lanes.
-__device__ __forceinline__ float seg_trans(float T_in, float ex, int j, float *chunk_prod) {
-  const float incl = seg_scan_mul(ex, j);
-  const float excl = __shfl_up(incl, 1, kSeg);
-  *chunk_prod = __shfl(incl, kSeg - 1, kSeg);
-  return j == 0 ? T_in : T_in * excl;
-}
-
-// Number of lanes of this segment whose predicate holds (a prefix).
-__device__ __forceinline__ int seg_count(bool p) {
-  const int seg = (threadIdx.x & (kWave - 1)) / kSeg;
-  return __popcll((__ballot(p) >> (kSeg * seg)) & 0xffffull);
-}
-
 __global__ void __launch_bounds__(kBlock) render_fwd(const float *__restrict__ sigma, const float *__restrict__ rgb,
                                                      int64_t ld, const int64_t *__restrict__ ray_off,
                                                      const float *__restrict__ ray_dt, int64_t R, float T_thresh,
@@ -71,43 +32,14 @@ __global__ void __launch_bounds__(kBlock) render_fwd(const float *__restrict__ s
   // a march that overflowed the sample buffer (count > ld, reported by the
   // march) leaves offsets past ld: those samples were never written
   const int64_t b = min(ray_off[r], ld), e = min(ray_off[r + 1], ld);
-  const float dt = ray_dt[r];
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, A = 0.0f;
-  int used = 0;
-  for (int64_t base = b; base < e; base += kSeg) {
-    const int64_t i = base + j;
-    const bool valid = i < e;
-    const float x = valid ? sigma[i] * dt : 0.0f;
-    float prod;
-    const float Ti = seg_trans(T, valid ? expf(-x) : 1.0f, j, &prod);
-    const bool use = valid && Ti >= T_thresh;
-    if (use) {
-      const float w = Ti * -expm1f(-x);
-      C0 += w * rgb[i];
-      C1 += w * rgb[ld + i];
-      C2 += w * rgb[2 * ld + i];
-      A += w;
-    }
-    const int n = seg_count(use);
-    used += n;
-    const int len = e - base < kSeg ? (int)(e - base) : kSeg;
-    if (n < len) {  // terminated inside this chunk: T of the first unused sample
-      T = __shfl(Ti, n, kSeg);
-      break;
-    }
-    T *= prod;
-  }
-  C0 = seg_sum(C0);
-  C1 = seg_sum(C1);
-  C2 = seg_sum(C2);
-  A = seg_sum(A);
+  const RayOut q = composite_ray(PlanarSrc{sigma, rgb, ld}, b, e, ray_dt[r], T_thresh, j);
   if (j == 0) {
-    color[3 * r] = C0;
-    color[3 * r + 1] = C1;
-    color[3 * r + 2] = C2;
-    opacity[r] = A;
-    n_used[r] = used;
-    T_final[r] = T;
+    color[3 * r] = q.C[0];
+    color[3 * r + 1] = q.C[1];
+    color[3 * r + 2] = q.C[2];
+    opacity[r] = q.A;
+    n_used[r] = q.used;
+    T_final[r] = q.T;
   }
 }
 

@@ -85,7 +85,29 @@ _SIGS = {
     "volrender_fwd": (_i32, [_vp, _vp, _i64, _vp, _vp, _i64, _f, _vp, _vp, _vp, _vp, _vp]),
     "volrender_bwd": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "l2_loss": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
+    "batch_workspace_size": (_sz, [_i32, _i32, _i32, _i32, _i32]),
+    "batch_lds_bytes": (_sz, [_i32, _i32]),
+    "batch_render": (_i32, [_vp, _sz, _i32, _i32, _i32, _vp]),
 }
+
+
+class BatchPose(ctypes.Structure):
+    """``ia355_batch_pose`` (include/ia355.h)."""
+    _fields_ = [("rays_o", _vp), ("rays_d", _vp), ("R", _i64), ("occ_bits", _vp), ("G", _i32),
+                ("occ_aabb", _f * 6), ("dt", _f), ("n_per_ray", _i32), ("max_steps", _i32), ("B", _vp),
+                ("pose", _vp), ("color", _vp), ("opacity", _vp), ("n_used", _vp), ("T_final", _vp),
+                ("n_fallback", _vp)]
+
+
+class BatchModel(ctypes.Structure):
+    """``ia355_batch_model`` (include/ia355.h)."""
+    _fields_ = [("W", _vp), ("Dx", _i32), ("Dy", _i32), ("Dz", _i32), ("nb", _i32), ("skin_aabb", _f * 6),
+                ("hash_aabb", _f * 6), ("max_iter", _i32), ("tol_stop", _f), ("tol_valid", _f), ("table", _vp),
+                ("L", _i32), ("log2T", _i32), ("base_res", _d), ("growth", _d), ("mlp_params", _vp),
+                ("init_params", _vp), ("init_hidden", _i32), ("T_thresh", _f)]
+
+
+_SIGS["batch_plan"] = (_i32, [ctypes.POINTER(BatchPose), _i32, ctypes.POINTER(BatchModel), _vp, _sz, _vp])
 
 _lib = None
 
@@ -455,3 +477,56 @@ def l2_loss(color, target, loss, grad_color):
     _check(lib().ia355_l2_loss(_p(color, torch.float32, "color"), _p(target, torch.float32, "target"), R,
                                _p(loss, torch.float32, "loss"), _p(grad_color, torch.float32, "grad_color"),
                                _stream()), "l2_loss")
+
+
+BATCH_MAX_POSES = 64
+
+
+def batch_workspace_size(n_poses, Dx, Dy, Dz, nb):
+    return lib().ia355_batch_workspace_size(n_poses, Dx, Dy, Dz, nb)
+
+
+def batch_lds_bytes(rays_per_tile, samples_per_segment):
+    """LDS bytes per workgroup of a render schedule (0: invalid shape)."""
+    return lib().ia355_batch_lds_bytes(rays_per_tile, samples_per_segment)
+
+
+def batch_pose(rays_o, rays_d, occ_bits, G, occ_aabb, dt, n_per_ray, max_steps, B, pose, color, opacity, n_used,
+               T_final, n_fallback=None):
+    """One ``ia355_batch_pose`` from GPU tensors (the tensors must outlive
+    every render that uses the plan)."""
+    R = rays_o.shape[0]
+    for t, n in ((rays_d, "rays_d"), (color, "color")):
+        if t.shape[0] != R:
+            raise ValueError(f"batch_pose: {n} has {t.shape[0]} rows, rays_o {R}")
+    for t, n in ((opacity, "opacity"), (n_used, "n_used"), (T_final, "T_final")):
+        if t.numel() != R:
+            raise ValueError(f"batch_pose: {n} has {t.numel()} values for {R} rays")
+    return BatchPose(_p(rays_o, torch.float32, "rays_o"), _p(rays_d, torch.float32, "rays_d"), R,
+                     _p(occ_bits, torch.int32, "occ_bits"), G, _box(occ_aabb), float(dt), n_per_ray, max_steps,
+                     _p(B, torch.float32, "B"), _p(pose, torch.float32, "pose"), _p(color, torch.float32, "color"),
+                     _p(opacity, torch.float32, "opacity"), _p(n_used, torch.int32, "n_used"),
+                     _p(T_final, torch.float32, "T_final"), _p(n_fallback, torch.int32, "n_fallback"))
+
+
+def batch_plan(poses, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, table, base_res, growth, mlp_params,
+               init_params, T_thresh, ws, init_hidden=64):
+    """Validate the poses (a list of ``batch_pose``) and the shared model and
+    write the plan into ws (synchronises the stream)."""
+    Dz, Dy, Dx, nb = W.shape
+    L, T, F = table.shape
+    if table.dtype != torch.float16 or F != 2:
+        raise TypeError("batch_plan: the table must be FP16 [L][T][2]")
+    m = BatchModel(_p(W, torch.float32, "W"), Dx, Dy, Dz, nb, _box(skin_aabb), _box(hash_aabb), max_iter,
+                   float(tol_stop), float(tol_valid), _p(table, torch.float16, "table"), L, T.bit_length() - 1,
+                   float(base_res), float(growth), _p(mlp_params, torch.float32, "mlp_params"),
+                   _p(init_params, torch.float32, "init_params"), init_hidden, float(T_thresh))
+    arr = (BatchPose * len(poses))(*poses)
+    _check(lib().ia355_batch_plan(arr, len(poses), ctypes.byref(m), _p(ws, name="ws"),
+                                  ws.numel() * ws.element_size(), _stream()), "batch_plan")
+
+
+def batch_render(ws, rays_per_tile, samples_per_segment, blocks_per_cu):
+    """Enqueue the batched render of the plan in ws (capturable)."""
+    _check(lib().ia355_batch_render(_p(ws, name="ws"), ws.numel() * ws.element_size(), rays_per_tile,
+                                    samples_per_segment, blocks_per_cu, _stream()), "batch_render")

@@ -71,3 +71,45 @@ def test_status_codes_and_mlp_widths_without_gpu():
     b.argtypes = [vp, vp, vp, i32, vp, i64, vp, i64, vp, vp, i32, i32, vp, vp, ctypes.c_uint32, vp, ctypes.c_size_t,
                   vp]
     assert b(fake, fake, fake, 0, None, 16, None, 16, fake, other, 3, 0, fake, None, 0, fake, 1 << 30, None) == 3
+
+
+def test_batch_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of ia355_batch_pose / ia355_batch_model have the C
+    layout (every field offset and the size), checked against a host program
+    compiled from the header."""
+    import subprocess
+    from paper_2212_10550_amd import lib as K
+    src = tmp_path / "layout.c"
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ia355.h"', "int main(void) {"]
+    for cname, cls in (("ia355_batch_pose", K.BatchPose), ("ia355_batch_model", K.BatchModel)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out if l.strip())}
+    for cname, cls in (("ia355_batch_pose", K.BatchPose), ("ia355_batch_model", K.BatchModel)):
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_batch_arguments_without_gpu():
+    """Workspace and LDS sizes of the batched render, and the plan's argument
+    checks, which return before any device work."""
+    from paper_2212_10550_amd import lib as K
+    L = K.lib()
+    assert K.batch_workspace_size(16, 64, 64, 32, 24) >= 16 * 12 * 4 * 64 * 64 * 32
+    assert K.batch_workspace_size(0, 64, 64, 32, 24) == 0
+    assert K.batch_workspace_size(K.BATCH_MAX_POSES + 1, 64, 64, 32, 24) == 0
+    assert K.batch_workspace_size(1, 64, 64, 32, 33) == 0
+    assert 0 < K.batch_lds_bytes(32, 256) < K.batch_lds_bytes(64, 256) < K.batch_lds_bytes(64, 512)
+    assert K.batch_lds_bytes(0, 256) == 0 and K.batch_lds_bytes(65, 256) == 0 and K.batch_lds_bytes(16, 255) == 0
+    pose = K.BatchPose()
+    model = K.BatchModel()
+    assert L.ia355_batch_plan(ctypes.byref(pose), 0, ctypes.byref(model), None, 0, None) == 1
+    assert L.ia355_batch_plan(ctypes.byref(pose), 1, ctypes.byref(model), None, 0, None) == 1  # nb = 0
+    assert L.ia355_batch_render(None, 0, 32, 256, 2, None) == 2

@@ -1,8 +1,8 @@
 """Batched render of several poses in one HIP graph: every pose's image must
 equal the same pose rendered alone (bit for bit: the per-sample work is the
-same, only the schedule differs), on every replay, for any stream count;
-one pose is also checked against the FP64 oracle at the reduced-precision
-pixel bar."""
+same, only the schedule differs), on every replay, for any stream count and
+for the persistent kernel under every tile shape; one pose is also checked
+against the FP64 oracle at the reduced-precision pixel bar."""
 import numpy as np
 import pytest
 import torch
@@ -28,29 +28,100 @@ def small_batch():
     return ws
 
 
-@pytest.mark.parametrize("n_streams", [1, 2])
-def test_batch_matches_single_pose(small_batch, n_streams):
+_OUTS = ("color", "opacity", "n_used", "T_final")
+
+
+def _single_refs(ws, params, poses):
+    """Every pose rendered alone by the staged path: outputs and fallback count."""
     from paper_2212_10550_amd import lib as K
-    from paper_2212_10550_amd.batch import BatchRenderer
     from paper_2212_10550_amd.pipeline import Pipeline
-    params = _params()
-    br = BatchRenderer(small_batch, params, n_streams=n_streams)
-    br.capture()
     refs = []
-    for w, p in zip(small_batch, br.poses):
+    for w, p in zip(ws, poses):
         single = Pipeline(w, table_dtype=torch.float16, mlp_dtype=K.BF16, rootinit_params=params, device_count=True)
         single.forward()
         torch.cuda.synchronize()
         assert single.read_count() == p.S
-        refs.append(single.color.clone())
+        refs.append({k: getattr(single, k).clone() for k in _OUTS})
+        refs[-1]["n_fallback"] = int(single.guided.n_fallback.item())
+        del single
+    return refs
+
+
+def _check_replays(br, refs, what):
     for rep in range(2):
         for p in br.poses:
             p.color.fill_(float("nan"))
+            p.opacity.fill_(float("nan"))
+            p.T_final.fill_(float("nan"))
+            p.n_used.fill_(-1)
+            p.n_fallback.fill_(-1)
         br.render()
         torch.cuda.synchronize()
         for i, p in enumerate(br.poses):
-            assert torch.equal(p.color, refs[i]), (rep, i)
+            for k in _OUTS:
+                assert torch.equal(getattr(p, k), refs[i][k]), (what, rep, i, k)
+            assert int(p.n_fallback.item()) == refs[i]["n_fallback"], (what, rep, i)
+
+
+@pytest.mark.parametrize("n_streams", [1, 2])
+def test_batch_matches_single_pose(small_batch, n_streams):
+    from paper_2212_10550_amd.batch import BatchRenderer
+    params = _params()
+    br = BatchRenderer(small_batch, params, n_streams=n_streams)
+    br.capture()
+    refs = _single_refs(small_batch, params, br.poses)
+    _check_replays(br, refs, f"{n_streams} streams")
     print(f"batch ({n_streams} streams): samples {[p.S for p in br.poses]}")
+
+
+# tile shapes: rays per tile (ragged last tiles, 64 = one lane per ray),
+# samples per segment (256: a 64-ray tile splits into several segments),
+# workgroups per CU
+@pytest.mark.parametrize("sched", [(64, 256, 2), (13, 256, 1), (32, 384, 2), (1, 256, 2)])
+def test_persistent_matches_single_pose(small_batch, sched):
+    from paper_2212_10550_amd.batch import BatchRenderer
+    params = _params()
+    br = BatchRenderer(small_batch, params, n_streams=1)
+    br.set_persistent(*sched)
+    br.capture()
+    refs = _single_refs(small_batch, params, br.poses)
+    _check_replays(br, refs, f"persistent {sched}")
+    used = [int(p.n_used.sum().item()) for p in br.poses]
+    print(f"persistent {sched}: samples {[p.S for p in br.poses]}, used {used}, "
+          f"fallback {[r['n_fallback'] for r in refs]}")
+
+
+def test_persistent_full_poses_match_staged():
+    """Two whole poses of the batch (540^2 at 20 % and 270^2 at 5 %, the
+    workload's own sizes): persistent and staged renders agree bit for bit,
+    with the poses in one plan."""
+    from paper_2212_10550_amd.batch import BatchRenderer
+    ws = [synth.batch_pose(k) for k in (4, 3)]
+    br = BatchRenderer(ws, _params(), n_streams=2)
+    br.render()
+    torch.cuda.synchronize()
+    refs = [{k: getattr(p, k).clone() for k in _OUTS} for p in br.poses]
+    for r, p in zip(refs, br.poses):
+        r["n_fallback"] = int(p.n_fallback.item())
+    br.set_persistent(32, 256, 2)
+    br.capture()
+    _check_replays(br, refs, "full poses")
+    print(f"full poses: rays {[p.R for p in br.poses]}, samples {[p.S for p in br.poses]}")
+
+
+def test_persistent_rejects_bad_schedules(small_batch):
+    from paper_2212_10550_amd import lib as K
+    from paper_2212_10550_amd.batch import BatchRenderer
+    br = BatchRenderer(small_batch[:1], _params(), n_streams=1)
+    br.set_persistent(16, 256, 1)
+    with pytest.raises(RuntimeError, match="status 1"):
+        K.batch_render(br._ws, 65, 256, 1)  # more rays per tile than lanes
+    with pytest.raises(RuntimeError, match="status 1"):
+        K.batch_render(br._ws, 16, 128, 1)  # a segment must hold two whole rays
+    with pytest.raises(RuntimeError, match="status 1"):
+        K.batch_render(br._ws, 16, 256, 0)
+    with pytest.raises(RuntimeError, match="status 3"):
+        K.batch_render(br._ws, 64, 4096, 1)  # beyond 64 KB of LDS
 
 
 def test_batch_pose_against_oracle(orc, small_batch):

@@ -363,8 +363,11 @@ int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float *xc, const
  * binned by (level, table tile of 4096 entries), written once as 12-byte
  * records (the two FP32 values, the entry in the tile) and summed per tile
  * in LDS as exact 64-bit fixed point (a power-of-two scale per group of at
- * most 4096 records, chosen from its largest value), then converted back
- * and written with plain stores.  A tile whose bin holds more than 4096
+ * most 4096 records, chosen from its largest |value| m), then converted back
+ * and written with plain stores.  Accuracy is absolute, relative to m: each
+ * record is rounded to a quantum below m 2^-46, so an entry's error is at
+ * most its record count times m 2^-47 plus one FP32 rounding of the entry
+ * (values below m 2^-48 contribute zero).  A tile whose bin holds more than 4096
  * records is summed by several workgroups that add their nonzero entries
  * with FP32 atomics.  Every tile of the selected levels is written, so
  * IA355_OVERWRITE needs no separate clear.  A tile summed by one workgroup
@@ -540,20 +543,22 @@ typedef struct ia355_batch_model {
  * per pose the blended transform grid, the folded initialiser constant and
  * the bone inverses); it copies from host memory and synchronises the
  * stream, so it is not for graph capture.  ia355_batch_render enqueues two
- * kernels (per-pose preparation, then the persistent render, whose
- * workgroups take tiles of rays_per_tile rays (1..64) of one pose per wave
- * from a work counter, in segments of at most samples_per_segment samples
- * (256..8192)), and is capturable; it reads the plan from ws, which must be
- * the ws the plan was written to (a ws without a valid plan renders
- * nothing).  256 * blocks_per_cu workgroups (1..8) of 256 threads;
- * ia355_batch_lds_bytes gives a schedule's LDS per workgroup (0: invalid
- * shape), which must not exceed 64 KB (IA355_ERR_UNSUPPORTED). */
+ * kernels (per-pose preparation, then the persistent render) and is
+ * capturable.  Its schedule: 256 * blocks_per_cu workgroups of
+ * waves_per_group waves (4 or 8; blocks_per_cu 1-4 with 4 waves, 1-2 with 8,
+ * else IA355_ERR_UNSUPPORTED); every wave takes tiles of rays_per_tile rays
+ * (1..64) of one pose from a work counter and works through them in
+ * segments of at most samples_per_segment samples (256..8192).  It reads
+ * the plan from ws, which must be the ws the plan was written to (a ws
+ * without a valid plan renders nothing).  ia355_batch_lds_bytes gives a
+ * schedule's LDS per workgroup (0: invalid shape); a schedule needing more
+ * than the device allows per workgroup returns IA355_ERR_UNSUPPORTED. */
 size_t ia355_batch_workspace_size(int32_t n_poses, int32_t Dx, int32_t Dy, int32_t Dz, int32_t nb);
 int32_t ia355_batch_plan(const ia355_batch_pose *poses, int32_t n_poses, const ia355_batch_model *model,
                          void *ws, size_t ws_bytes, ia355_stream_t stream);
-size_t ia355_batch_lds_bytes(int32_t rays_per_tile, int32_t samples_per_segment);
+size_t ia355_batch_lds_bytes(int32_t rays_per_tile, int32_t samples_per_segment, int32_t waves_per_group);
 int32_t ia355_batch_render(const void *ws, size_t ws_bytes, int32_t rays_per_tile, int32_t samples_per_segment,
-                           int32_t blocks_per_cu, ia355_stream_t stream);
+                           int32_t waves_per_group, int32_t blocks_per_cu, ia355_stream_t stream);
 
 #ifdef __cplusplus
 }

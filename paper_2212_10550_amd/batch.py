@@ -89,7 +89,7 @@ class BatchRenderer:
         self.ri_dtype = rootinit_dtype
         self.poses = [_Pose(w, dev) for w in workloads]
         self.slots = None
-        self.persistent = None  # (rays per tile, samples per segment, workgroups per CU) when chosen
+        self.persistent = None  # (rays per tile, samples per segment, waves per workgroup, workgroups per CU)
         self._ws = None
         self._prepass()
         self.set_streams(n_streams)
@@ -105,18 +105,19 @@ class BatchRenderer:
                             None, None, None, 0, p.ray_off, p.ray_cnt, p.ray_dt, n, ws)
             p.S = int(n.item())
 
-    def set_persistent(self, rays_per_tile=32, samples_per_segment=256, blocks_per_cu=2):
+    def set_persistent(self, rays_per_tile=32, samples_per_segment=256, waves_per_group=4, blocks_per_cu=2):
         """Render with the persistent kernel and this schedule (the staged
         buffers are released)."""
         if self.ri_dtype != K.BF16:
             raise ValueError("the persistent render runs the BF16 initialiser")
-        if K.batch_lds_bytes(rays_per_tile, samples_per_segment) == 0:
-            raise ValueError(f"invalid tile shape {rays_per_tile} rays / {samples_per_segment} samples")
+        if K.batch_lds_bytes(rays_per_tile, samples_per_segment, waves_per_group) == 0:
+            raise ValueError(f"invalid tile shape {rays_per_tile} rays / {samples_per_segment} samples / "
+                             f"{waves_per_group} waves")
         self.graph = None
         self.slots = None
         torch.cuda.empty_cache()
         self._plan()
-        self.persistent = (rays_per_tile, samples_per_segment, blocks_per_cu)
+        self.persistent = (rays_per_tile, samples_per_segment, waves_per_group, blocks_per_cu)
 
     def _plan(self):
         if self._ws is not None:
@@ -220,7 +221,9 @@ class BatchRenderer:
         torch.cuda.synchronize()
         return a.elapsed_time(b) / n
 
-    PERSISTENT_CANDIDATES = ((16, 256, 2), (32, 256, 2), (64, 256, 2), (32, 384, 2), (32, 256, 1), (64, 256, 1))
+    # (rays per tile, samples per segment, waves per workgroup, workgroups per CU)
+    PERSISTENT_CANDIDATES = ((16, 256, 4, 3), (32, 256, 4, 2), (32, 256, 4, 3), (16, 256, 4, 4), (32, 256, 8, 1),
+                             (32, 256, 8, 2), (64, 256, 8, 2), (16, 384, 4, 3))
 
     def autotune(self, candidates=(1, 2, 4), n=3, persistent=None):
         """Time the captured batch for each schedule -- every stream count of
@@ -236,11 +239,14 @@ class BatchRenderer:
             res[name] = self.time_ms(n)
             setters[name] = (self.set_streams, (c,))
         for sched in persistent:
-            if K.batch_lds_bytes(*sched[:2]) == 0 or K.batch_lds_bytes(*sched[:2]) > 64 * 1024:
-                continue
-            name = "persistent/{} rays x {} samples, {} wg per CU".format(*sched)
+            name = "persistent/{} rays x {} samples, {} waves x {} wg per CU".format(*sched)
             self.set_persistent(*sched)
-            res[name] = self.time_ms(n)
+            try:
+                res[name] = self.time_ms(n)
+            except RuntimeError as e:  # a schedule the device cannot run (LDS per workgroup)
+                if "status 3" not in str(e):
+                    raise
+                continue
             setters[name] = (self.set_persistent, sched)
         best = min(res, key=res.get)
         fn, a = setters[best]

@@ -36,6 +36,9 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include <cstddef>
+#include <mutex>
+
 #include "common.h"
 #include "deform_dev.h"
 #include "geometry.h"
@@ -52,12 +55,9 @@ namespace {
 constexpr int kMaxPoses = IA355_BATCH_MAX_POSES;
 constexpr int kMaxTileRays = 64;   // one lane per ray in the span pass
 constexpr int kMaxSteps = 128;     // two 64-bit keep masks per ray
-constexpr int kWaves = 4;
-constexpr int kBlock = kWaves * kWave;
 constexpr int kPrepBlock = dfm::kBlendBlock;
 constexpr int kLevels = 16;        // decoder input 32 = 16 levels x 2 features
 constexpr uint32_t kMagic = 0x1a355b01u;
-constexpr size_t kMaxLds = 64 * 1024;
 
 struct PoseDev {
   const float *ro, *rd;
@@ -104,6 +104,9 @@ struct Store {
   int res[kLevels], dense[kLevels];
   int64_t tile0[kMaxPoses + 1];
 };
+static_assert(offsetof(Store, mb1) % 16 == 0 && offsetof(Store, mb2) % 16 == 0 && offsetof(Store, mb3) % 16 == 0 &&
+                  offsetof(Store, rb2) % 16 == 0 && offsetof(Store, rb3) % 16 == 0 && sizeof(Store) % 16 == 0,
+              "16-byte bias vectors and wave regions");
 
 // Per-wave LDS, carved from one block (sizes from the tile shape).
 struct WaveMem {
@@ -180,40 +183,44 @@ __device__ inline void sample_xp(const WaveMem &wm, int ra, int rb, int j, float
   mch::sample_pos(wm.o + 3 * rr, wm.d + 3 * rr, wm.tn[rr], wm.dt[rr], k, &t, xp);
 }
 
-__device__ inline void get_mfrag(const Store &st, int lane, int g, mlpd::FragBf &f) {
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f.w1[mt] = st.mw[mt][lane];
-    f.w2[mt][0] = st.mw[4 + 2 * mt][lane];
-    f.w2[mt][1] = st.mw[5 + 2 * mt][lane];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      f.b1[mt][i] = st.mb1[16 * mt + 4 * g + i];
-      f.b2[mt][i] = st.mb2[16 * mt + 4 * g + i];
-    }
+// Decoder weights fetched from the workgroup's LDS as the MFMAs use them
+// (the same bf16 fragments and FP32 biases as the decoder kernel's FragBf).
+struct LdsMW {
+  const Store &st;
+  int lane, g;
+  __device__ __forceinline__ bf16x8 w1(int mt) const { return st.mw[mt][lane]; }
+  __device__ __forceinline__ bf16x8 w2(int mt, int c) const { return st.mw[4 + 2 * mt + c][lane]; }
+  __device__ __forceinline__ bf16x8 w3(int c) const { return st.mw[12 + c][lane]; }
+  __device__ __forceinline__ f32x4 b1(int mt) const {
+    return *reinterpret_cast<const f32x4 *>(st.mb1 + 16 * mt + 4 * g);
   }
-  f.w3[0] = st.mw[12][lane];
-  f.w3[1] = st.mw[13][lane];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) f.b3[i] = (4 * g + i) < mlpd::NOUT ? st.mb3[4 * g + i] : 0.0f;
-}
+  __device__ __forceinline__ f32x4 b2(int mt) const {
+    return *reinterpret_cast<const f32x4 *>(st.mb2 + 16 * mt + 4 * g);
+  }
+  __device__ __forceinline__ f32x4 b3() const {
+    return g == 0 ? *reinterpret_cast<const f32x4 *>(st.mb3) : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+};
 
-__device__ inline void get_rfrag(const Store &st, int lane, int g, rid::Frag<true> &f) {
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f.w2b[mt][0] = st.rw[2 * mt][lane];
-    f.w2b[mt][1] = st.rw[2 * mt + 1][lane];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) f.b2[mt][i] = st.rb2[16 * mt + 4 * g + i];
+// Initialiser layers 2-3 from LDS (BF16 operands only).
+struct LdsRW {
+  const Store &st;
+  int lane, g;
+  __device__ __forceinline__ float w2f(int, int) const { return 0.0f; }
+  __device__ __forceinline__ float w3f(int, int) const { return 0.0f; }
+  __device__ __forceinline__ bf16x8 w2b(int mt, int c) const { return st.rw[2 * mt + c][lane]; }
+  __device__ __forceinline__ bf16x8 w3b(int mt, int c) const { return st.rw[8 + 2 * mt + c][lane]; }
+  __device__ __forceinline__ f32x4 b2(int mt) const {
+    return *reinterpret_cast<const f32x4 *>(st.rb2 + 16 * mt + 4 * g);
   }
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt) {
-    f.w3b[mt][0] = st.rw[8 + 2 * mt][lane];
-    f.w3b[mt][1] = st.rw[9 + 2 * mt][lane];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) f.b3[mt][i] = st.rb3[16 * mt + 4 * g + i];
+  __device__ __forceinline__ f32x4 b3(int mt) const {
+    return *reinterpret_cast<const f32x4 *>(st.rb3 + 16 * mt + 4 * g);
   }
-}
+};
+
+// A compiler-only barrier: keeps the fragment fetches of one tile from being
+// hoisted out of the tile loop (which would hold every fragment in registers).
+__device__ __forceinline__ void keep_in_loop() { asm volatile("" ::: "memory"); }
 
 __device__ inline __bf16 to_bf16(float v) {
   return __builtin_bit_cast(__bf16, __builtin_bit_cast(uint16_t, __float2bfloat16(v)));
@@ -223,8 +230,8 @@ __device__ inline __bf16 to_bf16(float v) {
 // 4g..4g+3 of its row's sample (x, bone; bone < 0 gives zero features and
 // zero outputs, as the staged encode and decoder do); rows with store set
 // write sigma and colour at slot.
-__device__ inline void encode_decode(const Plan &pl, const Store &st, const mlpd::FragBf &f, const float x[3],
-                                     int bone, bool store, int slot, int g, float *sig, float *rgb, int ch) {
+__device__ inline void encode_decode(const Plan &pl, const Store &st, int lane, const float x[3], int bone,
+                                     bool store, int slot, int g, float *sig, float *rgb, int ch) {
   bf16x8 X;
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) {
@@ -236,7 +243,7 @@ __device__ inline void encode_decode(const Plan &pl, const Store &st, const mlpd
     X[2 * jj + 1] = to_bf16(b);
   }
   f32x4 z1[4], z2[4], o;
-  mlpd::fwd_bf(f, X, z1, z2, o);
+  mlpd::fwd_bf_src(LdsMW{st, lane, g}, X, z1, z2, o);
   if (g == 0 && store) {
     float sg = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
     if (bone >= 0) {
@@ -260,6 +267,41 @@ struct LdsSrc {
     c[2] = rgb[2 * ch + i];
   }
 };
+
+// Keep masks of the tile's rays (lanes = steps k and k + 64), kMarchRays
+// rays at a time so that their occupancy loads are in flight together; the
+// test is the march kernels' (sample_at, then t < t_far).
+constexpr int kMarchRays = 4;
+template <bool kPow2>
+__device__ inline void march_masks(const PoseDev &pd, const WaveMem &wm, int nr, int lane) {
+  for (int rr0 = 0; rr0 < nr; rr0 += kMarchRays) {
+    bool keep[kMarchRays][2];
+#pragma unroll
+    for (int u = 0; u < kMarchRays; ++u) {
+      const int rr = min(rr0 + u, nr - 1);
+      const float tf = wm.tf[rr];
+      const float o[3] = {wm.o[3 * rr], wm.o[3 * rr + 1], wm.o[3 * rr + 2]};
+      const float d[3] = {wm.d[3 * rr], wm.d[3 * rr + 1], wm.d[3 * rr + 2]};
+      const mch::RaySpan s{wm.tn[rr], tf, wm.dt[rr], true};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = lane + h * kWave;
+        float t, x[3];
+        const bool kb = mch::sample_at<kPow2>(o, d, s, k, pd.box, pd.bits, pd.G, &t, x);
+        // a ray that misses the box has t_far = -inf: nothing is kept
+        keep[u][h] = k < pd.max_steps && kb && t < tf;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kMarchRays; ++u) {
+      const uint64_t m0 = __ballot(keep[u][0]), m1 = __ballot(keep[u][1]);
+      if (lane == 0 && rr0 + u < nr) {
+        wm.mask[2 * (rr0 + u)] = m0;
+        wm.mask[2 * (rr0 + u) + 1] = m1;
+      }
+    }
+  }
+}
 
 __global__ void __launch_bounds__(kPrepBlock) prep_kernel(const Plan *__restrict__ plp, size_t ws_bytes,
                                                           int *__restrict__ queue) {
@@ -286,41 +328,33 @@ __global__ void __launch_bounds__(kPrepBlock) prep_kernel(const Plan *__restrict
   }
 }
 
-__global__ void __launch_bounds__(kBlock, 2) render_kernel(const Plan *__restrict__ plp, size_t ws_bytes,
-                                                        int *__restrict__ queue, int rt, int ch) {
+// kW waves per workgroup, at least kMinGroups workgroups per CU: the second
+// launch bound is the waves per SIMD, kMinGroups kW / 4, which caps the
+// registers per lane at 512 / (kMinGroups kW / 4).
+template <int kW, int kMinGroups>
+__global__ void __launch_bounds__(kW * kWave, kMinGroups * kW / 4) render_kernel(const Plan *__restrict__ plp,
+                                                                        size_t ws_bytes, int *__restrict__ queue,
+                                                                        int rt, int ch) {
+  constexpr int kBlock = kW * kWave;
   const Plan &pl = *plp;
   if (pl.magic != kMagic || pl.ws_need > ws_bytes) return;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   Store &st = *reinterpret_cast<Store *>(lds);
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, r = lane & 15,
+            g = lane >> 4;
   const int nb = pl.nb;
   // ---- workgroup set-up: fragments and constants (the same values as the
   // staged kernels build from their LDS copies of the parameters)
   const rid::Layout rl = rid::layout(nb);
-  if (wid == 0) {
-    rid::Frag<true> rf;
-    rid::load_frag<true>(pl.init, rl, r, g, rf);
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      st.rw[2 * mt][lane] = rf.w2b[mt][0];
-      st.rw[2 * mt + 1][lane] = rf.w2b[mt][1];
-    }
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      st.rw[8 + 2 * mt][lane] = rf.w3b[mt][0];
-      st.rw[9 + 2 * mt][lane] = rf.w3b[mt][1];
-    }
-  } else if (wid == 1) {
-    mlpd::FragBf mf;
-    mlpd::load_frag_bf(pl.mlp, r, g, mf);
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      st.mw[mt][lane] = mf.w1[mt];
-      st.mw[4 + 2 * mt][lane] = mf.w2[mt][0];
-      st.mw[5 + 2 * mt][lane] = mf.w2[mt][1];
-    }
-    st.mw[12][lane] = mf.w3[0];
-    st.mw[13][lane] = mf.w3[1];
+  // one fragment per thread at a time (whole fragment sets in registers
+  // would set the kernel's register count)
+  for (int e = threadIdx.x; e < 14 * kWave; e += kBlock) {
+    const int q = e / kWave, ln = e % kWave;
+    st.mw[q][ln] = mlpd::frag_bf(pl.mlp, q, ln & 15, ln >> 4);
+  }
+  for (int e = threadIdx.x; e < 12 * kWave; e += kBlock) {
+    const int q = e / kWave, ln = e % kWave;
+    st.rw[q][ln] = rid::frag_bf(pl.init, rl, q, ln & 15, ln >> 4);
   }
   for (int i = threadIdx.x; i < 64; i += kBlock) {
     st.mb1[i] = pl.mlp[mlpd::OFF_B1 + i];
@@ -377,29 +411,10 @@ __global__ void __launch_bounds__(kBlock, 2) render_kernel(const Plan *__restric
       wm.dt[lane] = s.dt;
     }
     mlpd::wave_sync();
-    for (int rr = 0; rr < nr; ++rr) {
-      uint64_t m0 = 0, m1 = 0;
-      const float tf = wm.tf[rr];
-      if (tf != -INFINITY) {
-        const float o[3] = {wm.o[3 * rr], wm.o[3 * rr + 1], wm.o[3 * rr + 2]};
-        const float d[3] = {wm.d[3 * rr], wm.d[3 * rr + 1], wm.d[3 * rr + 2]};
-        const mch::RaySpan s{wm.tn[rr], tf, wm.dt[rr], true};
-        bool keep0 = false, keep1 = false;
-        float t0 = 0.0f, t1 = 0.0f, x[3];
-        if (lane < pd.max_steps)
-          keep0 = pd.pow2 ? mch::sample_at<true>(o, d, s, lane, pd.box, pd.bits, pd.G, &t0, x)
-                          : mch::sample_at<false>(o, d, s, lane, pd.box, pd.bits, pd.G, &t0, x);
-        if (lane + kWave < pd.max_steps)
-          keep1 = pd.pow2 ? mch::sample_at<true>(o, d, s, lane + kWave, pd.box, pd.bits, pd.G, &t1, x)
-                          : mch::sample_at<false>(o, d, s, lane + kWave, pd.box, pd.bits, pd.G, &t1, x);
-        m0 = __ballot(keep0 && t0 < tf);
-        m1 = __ballot(keep1 && t1 < tf);
-      }
-      if (lane == 0) {
-        wm.mask[2 * rr] = m0;
-        wm.mask[2 * rr + 1] = m1;
-      }
-    }
+    if (pd.pow2)
+      march_masks<true>(pd, wm, nr, lane);
+    else
+      march_masks<false>(pd, wm, nr, lane);
     mlpd::wave_sync();
     {
       const int cnt = lane < nr ? __popcll(wm.mask[2 * lane]) + __popcll(wm.mask[2 * lane + 1]) : 0;
@@ -408,7 +423,7 @@ __global__ void __launch_bounds__(kBlock, 2) render_kernel(const Plan *__restric
       if (lane == 0) wm.off[0] = 0;
     }
     mlpd::wave_sync();
-    const int total = wm.off[nr];
+    const int total = __builtin_amdgcn_readfirstlane(wm.off[nr]);
     const int nseg = total == 0 ? 1 : (total + C - 1) / C;
     const float *A = pd.A;
     int nfb = 0;
@@ -420,7 +435,8 @@ __global__ void __launch_bounds__(kBlock, 2) render_kernel(const Plan *__restric
         const uint64_t bm = __ballot(lane < nr && wm.off[lane] >= v);
         rb = bm ? (int)__builtin_ctzll(bm) : nr;
       }
-      const int sb = wm.off[ra], se = wm.off[rb], n = se - sb;
+      const int sb = __builtin_amdgcn_readfirstlane(wm.off[ra]), se = __builtin_amdgcn_readfirstlane(wm.off[rb]);
+      const int n = se - sb;
       int qn = 0;
       for (int c0 = 0; c0 < n; c0 += kWave) {
         const int j = sb + c0 + lane;
@@ -433,14 +449,14 @@ __global__ void __launch_bounds__(kBlock, 2) render_kernel(const Plan *__restric
         int ibone = 0;
         float x0[3] = {0.0f, 0.0f, 0.0f};
         {
-          rid::Frag<true> f;
-          get_rfrag(st, lane, g, f);
           for (int t = 0; t < nt; ++t) {
+            keep_in_loop();
             const int src = 16 * t + r;
             const float xs[3] = {__shfl(xp[0], src, kWave), __shfl(xp[1], src, kWave), __shfl(xp[2], src, kWave)};
             int bi;
-            float off3[3];
-            rid::tile<true>(xs, pd.c1, st.w1x, f, nb, g, &bi, off3);
+            float off3[3], h1[4][4];
+            rid::layer1(xs, pd.c1, st.w1x, g, h1);
+            rid::tile_tail<true>(h1, LdsRW{st, lane, g}, nb, g, &bi, off3);
             if (g == t) {
               const int kb = bi < nb ? bi : 0;
               ibone = kb;
@@ -467,15 +483,12 @@ __global__ void __launch_bounds__(kBlock, 2) render_kernel(const Plan *__restric
         if (fb) wm.queue[qn + __popcll(fm & below)] = (int16_t)(c0 + lane);
         qn += __popcll(fm);
         // encode + decoder of the accepted samples
-        {
-          mlpd::FragBf f;
-          get_mfrag(st, lane, g, f);
-          for (int t = 0; t < nt; ++t) {
-            const int src = 16 * t + r;
-            const float xs[3] = {__shfl(xc[0], src, kWave), __shfl(xc[1], src, kWave), __shfl(xc[2], src, kWave)};
-            const int bs = __shfl(bone, src, kWave);
-            encode_decode(pl, st, f, xs, bs, bs >= 0, c0 + src, g, wm.sig, wm.rgb, ch);
-          }
+        for (int t = 0; t < nt; ++t) {
+          keep_in_loop();
+          const int src = 16 * t + r;
+          const float xs[3] = {__shfl(xc[0], src, kWave), __shfl(xc[1], src, kWave), __shfl(xc[2], src, kWave)};
+          const int bs = __shfl(bone, src, kWave);
+          encode_decode(pl, st, lane, xs, bs, bs >= 0, c0 + src, g, wm.sig, wm.rgb, ch);
         }
       }
       mlpd::wave_sync();
@@ -494,9 +507,8 @@ __global__ void __launch_bounds__(kBlock, 2) render_kernel(const Plan *__restric
         const bool qs = __shfl((int)qa, src, kWave) != 0 && r < 2;
         const int bs = qs ? __shfl(cc.bone, src, kWave) : -1;
         const int slot = __shfl(sj, src, kWave);
-        mlpd::FragBf f;
-        get_mfrag(st, lane, g, f);
-        encode_decode(pl, st, f, xs, bs, qs, slot, g, wm.sig, wm.rgb, ch);
+        keep_in_loop();
+        encode_decode(pl, st, lane, xs, bs, qs, slot, g, wm.sig, wm.rgb, ch);
       }
       nfb += qn;
       mlpd::wave_sync();
@@ -632,24 +644,69 @@ extern "C" int32_t ia355_batch_plan(const ia355_batch_pose *poses, int32_t n_pos
   return IA355_OK;
 }
 
-extern "C" size_t ia355_batch_lds_bytes(int32_t rays_per_tile, int32_t samples_per_segment) {
+extern "C" size_t ia355_batch_lds_bytes(int32_t rays_per_tile, int32_t samples_per_segment,
+                                        int32_t waves_per_group) {
   if (rays_per_tile < 1 || rays_per_tile > kMaxTileRays || samples_per_segment < 2 * kMaxSteps ||
-      samples_per_segment > 8192)
+      samples_per_segment > 8192 || (waves_per_group != 4 && waves_per_group != 8))
     return 0;
-  return sizeof(Store) + kWaves * wave_bytes(rays_per_tile, samples_per_segment);
+  return sizeof(Store) + (size_t)waves_per_group * wave_bytes(rays_per_tile, samples_per_segment);
 }
 
+namespace {
+
+typedef void (*RenderFn)(const Plan *, size_t, int *, int, int);
+
+// The instantiation for (waves per workgroup, workgroups per CU), or null.
+RenderFn render_fn(int waves, int groups) {
+  if (waves == 4 && groups == 1) return render_kernel<4, 1>;
+  if (waves == 4 && groups == 2) return render_kernel<4, 2>;
+  if (waves == 4 && groups == 3) return render_kernel<4, 3>;
+  if (waves == 4 && groups == 4) return render_kernel<4, 4>;
+  if (waves == 8 && groups == 1) return render_kernel<8, 1>;
+  if (waves == 8 && groups == 2) return render_kernel<8, 2>;
+  return nullptr;
+}
+
+// LDS a workgroup may take on the current device (cached per device).
+int32_t lds_limit(size_t *limit) {
+  static std::mutex mu;
+  static int cached[64];
+  static bool have[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return IA355_ERR_HIP;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!have[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return IA355_ERR_HIP;
+    cached[dev] = v;
+    have[dev] = true;
+  }
+  *limit = (size_t)cached[dev];
+  return IA355_OK;
+}
+
+}  // namespace
+
 extern "C" int32_t ia355_batch_render(const void *ws, size_t ws_bytes, int32_t rays_per_tile,
-                                      int32_t samples_per_segment, int32_t blocks_per_cu, ia355_stream_t stream) {
+                                      int32_t samples_per_segment, int32_t waves_per_group, int32_t blocks_per_cu,
+                                      ia355_stream_t stream) {
   if (!ws || ws_bytes < align256(sizeof(Plan)) + 256) return IA355_ERR_WORKSPACE;
-  if (blocks_per_cu < 1 || blocks_per_cu > 8) return IA355_ERR_INVALID_ARG;
-  const size_t lds = ia355_batch_lds_bytes(rays_per_tile, samples_per_segment);
-  if (lds == 0) return IA355_ERR_INVALID_ARG;
-  if (lds > kMaxLds) return IA355_ERR_UNSUPPORTED;
+  const size_t lds = ia355_batch_lds_bytes(rays_per_tile, samples_per_segment, waves_per_group);
+  if (lds == 0 || blocks_per_cu < 1) return IA355_ERR_INVALID_ARG;
+  const RenderFn fn = render_fn(waves_per_group, blocks_per_cu);
+  if (!fn) return IA355_ERR_UNSUPPORTED;
+  size_t limit = 0;
+  const int32_t st = lds_limit(&limit);
+  if (st != IA355_OK) return st;
+  if (lds > limit) return IA355_ERR_UNSUPPORTED;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return IA355_ERR_HIP;
   hipStream_t s = as_stream(stream);
   const Plan *pl = (const Plan *)ws;
   int *queue = (int *)((char *)ws + align256(sizeof(Plan)));
   prep_kernel<<<1024, kPrepBlock, 0, s>>>(pl, ws_bytes, queue);
-  render_kernel<<<256 * blocks_per_cu, kBlock, lds, s>>>(pl, ws_bytes, queue, rays_per_tile, samples_per_segment);
+  hipLaunchKernelGGL(fn, dim3(256 * blocks_per_cu), dim3(waves_per_group * kWave), lds, s, pl, ws_bytes, queue,
+                     rays_per_tile, samples_per_segment);
   return launch_status();
 }

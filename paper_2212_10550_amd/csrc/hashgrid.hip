@@ -250,11 +250,15 @@ __global__ void __launch_bounds__(kDgBlock) table_grad_dense_kernel(const float 
 //     pass that clears those tiles when overwriting.
 // The LDS sums are 64-bit fixed point, added exactly: LDS float atomic adds run at
 // about a sixteenth of the rate of integer ones on gfx950, so each chunk
-// scales its values by a power of two 2^s chosen from its largest |value|
-// and record count (no overflow, quantum 2^-s far below FP32 rounding of the
-// sum), adds them as integers and converts each entry back once.  Integer
-// addition is associative, so a tile summed by one workgroup does not
-// depend on the order of its records.
+// scales its values by a power of two 2^s chosen from its largest |value| m
+// and record count (no overflow), adds them as integers and converts each
+// entry back once.  Each record is rounded to the quantum 2^-s < m 2^-46, so
+// an entry's error is at most (its records) x m 2^-47 plus one FP32
+// rounding: an absolute bound relative to the chunk's largest value.  An
+// entry near m is as accurate as FP32 adds leave it or better; one far
+// below m (under about m 2^-24) is less accurate than FP32 adds, and a
+// record below m 2^-48 rounds to zero.  Integer addition is associative, so
+// a tile summed by one workgroup does not depend on the order of its records.
 // Every tile of the selected levels is written, so an overwrite needs no
 // separate clear.  The HBM traffic is the records (12 bytes per corner
 // update, written once and read once) and one pass over the table slice.

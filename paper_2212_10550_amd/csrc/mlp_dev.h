@@ -67,16 +67,25 @@ struct FragBf {
   float b1[4][4], b2[4][4], b3[4];
 };
 
+// Parameter index of element j of lane (r, g)'s fragments (-1: zero).
+__host__ __device__ inline int w1_at(int mt, int r, int g, int j) { return OFF_W1 + (16 * mt + r) * NIN + 8 * g + j; }
+__host__ __device__ inline int w2_at(int mt, int c, int r, int g, int j) {
+  return OFF_W2 + (16 * mt + r) * NH + 16 * (2 * c + j / 4) + 4 * g + (j % 4);
+}
+__host__ __device__ inline int w3_at(int c, int r, int g, int j) {
+  return r < NOUT ? OFF_W3 + r * NH + 16 * (2 * c + j / 4) + 4 * g + (j % 4) : -1;
+}
+__device__ __forceinline__ __bf16 frag_value(const float *P, int i) { return (__bf16)(i >= 0 ? P[i] : 0.0f); }
+
 __device__ __forceinline__ void load_frag_bf(const float *P, int r, int g, FragBf &f) {
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) f.w1[mt][j] = (__bf16)P[OFF_W1 + (16 * mt + r) * NIN + 8 * g + j];
+    for (int j = 0; j < 8; ++j) f.w1[mt][j] = frag_value(P, w1_at(mt, r, g, j));
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        f.w2[mt][c][j] = (__bf16)P[OFF_W2 + (16 * mt + r) * NH + 16 * (2 * c + j / 4) + 4 * g + (j % 4)];
+      for (int j = 0; j < 8; ++j) f.w2[mt][c][j] = frag_value(P, w2_at(mt, c, r, g, j));
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       f.b1[mt][i] = P[OFF_B1 + 16 * mt + 4 * g + i];
@@ -86,10 +95,21 @@ __device__ __forceinline__ void load_frag_bf(const float *P, int r, int g, FragB
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      f.w3[c][j] = (__bf16)(r < NOUT ? P[OFF_W3 + r * NH + 16 * (2 * c + j / 4) + 4 * g + (j % 4)] : 0.0f);
+    for (int j = 0; j < 8; ++j) f.w3[c][j] = frag_value(P, w3_at(c, r, g, j));
 #pragma unroll
   for (int i = 0; i < 4; ++i) f.b3[i] = (4 * g + i) < NOUT ? P[OFF_B3 + 4 * g + i] : 0.0f;
+}
+
+// Fragment q (0-3: w1[q], 4-11: w2[(q-4)/2][(q-4)%2], 12-13: w3[q-12]) of
+// lane (r, g), built alone (the same values as load_frag_bf).
+__device__ __forceinline__ bf16x8 frag_bf(const float *P, int q, int r, int g) {
+  bf16x8 v;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int i = q < 4 ? w1_at(q, r, g, j) : (q < 12 ? w2_at((q - 4) / 2, (q - 4) % 2, r, g, j) : w3_at(q - 12, r, g, j));
+    v[j] = frag_value(P, i);
+  }
+  return v;
 }
 
 // Pack the relu'd accumulators of tiles t = 2c, 2c+1 into one B operand.
@@ -100,23 +120,45 @@ __device__ __forceinline__ bf16x8 pack_act(const f32x4 z[4], int c) {
   return b;
 }
 
-__device__ __forceinline__ void fwd_bf(const FragBf &f, const bf16x8 &X, f32x4 z1[4], f32x4 z2[4], f32x4 &o) {
+// The BF16 forward of one 16-sample tile with the weights from a source:
+// w.w1(mt), w.w2(mt, c), w.w3(c) give the A-operand fragments and
+// w.b1(mt), w.b2(mt), w.b3() the accumulator initialisers (biases), so the
+// fragments may live in registers or be fetched from LDS as they are used;
+// the operations are the same either way.
+template <class WSrc>
+__device__ __forceinline__ void fwd_bf_src(const WSrc &w, const bf16x8 &X, f32x4 z1[4], f32x4 z2[4], f32x4 &o) {
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 acc = {f.b1[mt][0], f.b1[mt][1], f.b1[mt][2], f.b1[mt][3]};
-    z1[mt] = mfma32(f.w1[mt], X, acc);
-  }
+  for (int mt = 0; mt < 4; ++mt) z1[mt] = mfma32(w.w1(mt), X, w.b1(mt));
   const bf16x8 h1a = pack_act(z1, 0), h1b = pack_act(z1, 1);
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
-    f32x4 acc = {f.b2[mt][0], f.b2[mt][1], f.b2[mt][2], f.b2[mt][3]};
-    acc = mfma32(f.w2[mt][0], h1a, acc);
-    z2[mt] = mfma32(f.w2[mt][1], h1b, acc);
+    f32x4 acc = w.b2(mt);
+    acc = mfma32(w.w2(mt, 0), h1a, acc);
+    z2[mt] = mfma32(w.w2(mt, 1), h1b, acc);
   }
   const bf16x8 h2a = pack_act(z2, 0), h2b = pack_act(z2, 1);
-  f32x4 acc = {f.b3[0], f.b3[1], f.b3[2], f.b3[3]};
-  acc = mfma32(f.w3[0], h2a, acc);
-  o = mfma32(f.w3[1], h2b, acc);
+  f32x4 acc = w.b3();
+  acc = mfma32(w.w3(0), h2a, acc);
+  o = mfma32(w.w3(1), h2b, acc);
+}
+
+// Weights held in registers (FragBf).
+struct RegW {
+  const FragBf &f;
+  __device__ __forceinline__ bf16x8 w1(int mt) const { return f.w1[mt]; }
+  __device__ __forceinline__ bf16x8 w2(int mt, int c) const { return f.w2[mt][c]; }
+  __device__ __forceinline__ bf16x8 w3(int c) const { return f.w3[c]; }
+  __device__ __forceinline__ f32x4 b1(int mt) const {
+    return f32x4{f.b1[mt][0], f.b1[mt][1], f.b1[mt][2], f.b1[mt][3]};
+  }
+  __device__ __forceinline__ f32x4 b2(int mt) const {
+    return f32x4{f.b2[mt][0], f.b2[mt][1], f.b2[mt][2], f.b2[mt][3]};
+  }
+  __device__ __forceinline__ f32x4 b3() const { return f32x4{f.b3[0], f.b3[1], f.b3[2], f.b3[3]}; }
+};
+
+__device__ __forceinline__ void fwd_bf(const FragBf &f, const bf16x8 &X, f32x4 z1[4], f32x4 z2[4], f32x4 &o) {
+  fwd_bf_src(RegW{f}, X, z1, z2, o);
 }
 
 }  // namespace mlpd

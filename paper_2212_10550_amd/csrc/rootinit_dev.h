@@ -82,6 +82,23 @@ struct Frag {
   float b2[4][4], b3[2][4];
 };
 
+// Parameter index of lane (r, g)'s operand element: layer 2 (FP32 k = 4t + i,
+// BF16 (c, j)) of output tile mt, layer 3 likewise (-1: a padded row, zero).
+__host__ __device__ inline int w2f_at(const Layout &l, int mt, int k, int r, int g) {
+  return l.offW2 + (16 * mt + r) * H + 16 * (k / 4) + 4 * g + (k % 4);
+}
+__host__ __device__ inline int w2b_at(const Layout &l, int mt, int c, int j, int r, int g) {
+  return l.offW2 + (16 * mt + r) * H + 16 * (2 * c + j / 4) + 4 * g + (j % 4);
+}
+__host__ __device__ inline int w3f_at(const Layout &l, int mt, int k, int r, int g) {
+  const int row = 16 * mt + r;
+  return row < l.nout ? l.offW3 + row * H + 16 * (k / 4) + 4 * g + (k % 4) : -1;
+}
+__host__ __device__ inline int w3b_at(const Layout &l, int mt, int c, int j, int r, int g) {
+  const int row = 16 * mt + r;
+  return row < l.nout ? l.offW3 + row * H + 16 * (2 * c + j / 4) + 4 * g + (j % 4) : -1;
+}
+
 template <bool BF16>
 __device__ __forceinline__ void load_frag(const float *sP, const Layout &l, int r, int g, Frag<BF16> &f) {
 #pragma unroll
@@ -90,73 +107,77 @@ __device__ __forceinline__ void load_frag(const float *sP, const Layout &l, int 
     for (int i = 0; i < 4; ++i) f.b2[mt][i] = sP[l.offb2 + 16 * mt + 4 * g + i];
     if (!BF16) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) f.w2f[mt][4 * t + i] = sP[l.offW2 + (16 * mt + r) * H + 16 * t + 4 * g + i];
+      for (int k = 0; k < 16; ++k) f.w2f[mt][k] = sP[w2f_at(l, mt, k, r, g)];
     } else {
 #pragma unroll
       for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          f.w2b[mt][c][j] = (__bf16)sP[l.offW2 + (16 * mt + r) * H + 16 * (2 * c + j / 4) + 4 * g + (j % 4)];
+        for (int j = 0; j < 8; ++j) f.w2b[mt][c][j] = (__bf16)sP[w2b_at(l, mt, c, j, r, g)];
     }
   }
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt) {
-    const int row = 16 * mt + r;
 #pragma unroll
     for (int i = 0; i < 4; ++i) f.b3[mt][i] = (16 * mt + 4 * g + i) < l.nout ? sP[l.offb3 + 16 * mt + 4 * g + i] : 0.0f;
     if (!BF16) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          f.w3f[mt][4 * t + i] = row < l.nout ? sP[l.offW3 + row * H + 16 * t + 4 * g + i] : 0.0f;
+      for (int k = 0; k < 16; ++k) {
+        const int i = w3f_at(l, mt, k, r, g);
+        f.w3f[mt][k] = i >= 0 ? sP[i] : 0.0f;
+      }
     } else {
 #pragma unroll
       for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          f.w3b[mt][c][j] =
-              (__bf16)(row < l.nout ? sP[l.offW3 + row * H + 16 * (2 * c + j / 4) + 4 * g + (j % 4)] : 0.0f);
+        for (int j = 0; j < 8; ++j) {
+          const int i = w3b_at(l, mt, c, j, r, g);
+          f.w3b[mt][c][j] = (__bf16)(i >= 0 ? sP[i] : 0.0f);
+        }
     }
   }
 }
 
-// One 16-sample tile, called by all 64 lanes of a wave (lane r + 16 g holds
-// sample r's point x): the argmax bone (ties: the lowest) and the three
-// offsets, in every lane of sample r.  c1 [64] and w1x [64][3] in LDS.
-template <bool BF16>
-__device__ __forceinline__ void tile(const float x[3], const float *c1, const float *w1x, const Frag<BF16> &f, int nb,
-                                     int g, int *bone, float off_out[3]) {
-  // layer 1 on the VALU: lane holds neurons 16t + 4g + i of sample r
-  float h1[4][4];
+// BF16 fragment q (0-7: layer 2 (mt, c) = (q / 2, q % 2); 8-11: layer 3
+// (mt, c) = ((q - 8) / 2, q % 2)) of lane (r, g), built alone (the same
+// values as load_frag<true>).
+__device__ __forceinline__ bf16x8 frag_bf(const float *P, const Layout &l, int q, int r, int g) {
+  bf16x8 v;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int n = 16 * t + 4 * g + i;
-      h1[t][i] = relu(c1[n] + w1x[3 * n] * x[0] + w1x[3 * n + 1] * x[1] + w1x[3 * n + 2] * x[2]);
-    }
+  for (int j = 0; j < 8; ++j) {
+    const int i = q < 8 ? w2b_at(l, q / 2, q % 2, j, r, g) : w3b_at(l, (q - 8) / 2, q % 2, j, r, g);
+    v[j] = (__bf16)(i >= 0 ? P[i] : 0.0f);
+  }
+  return v;
+}
+
+// Layers 2-3 and the argmax of one 16-sample tile from the layer-1
+// activations h1 (lane r + 16 g holds neurons 16t + 4g + i of sample r),
+// with the weight fragments from a source: w.w2f(mt, k) / w.w3f(mt, k)
+// (FP32 16x16x4 operands), w.w2b(mt, c) / w.w3b(mt, c) (BF16 16x16x32
+// operands), w.b2(mt) / w.b3(mt) (accumulator initialisers).  The bone
+// (ties: the lowest) and the three offsets land in every lane of sample r.
+template <bool BF16, class WSrc>
+__device__ __forceinline__ void tile_tail(const float h1[4][4], const WSrc &w, int nb, int g, int *bone,
+                                          float off_out[3]) {
   f32x4 z2[4], o[2];
   if (!BF16) {
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-      f32x4 acc = {f.b2[mt][0], f.b2[mt][1], f.b2[mt][2], f.b2[mt][3]};
+      f32x4 acc = w.b2(mt);
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(f.w2f[mt][4 * t + i], h1[t][i], acc, 0, 0, 0);
+        for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w2f(mt, 4 * t + i), h1[t][i], acc, 0, 0, 0);
       z2[mt] = acc;
     }
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
-      f32x4 acc = {f.b3[mt][0], f.b3[mt][1], f.b3[mt][2], f.b3[mt][3]};
+      f32x4 acc = w.b3(mt);
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(f.w3f[mt][4 * t + i], relu(z2[t][i]), acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w3f(mt, 4 * t + i), relu(z2[t][i]), acc, 0, 0, 0);
       o[mt] = acc;
     }
   } else {
@@ -168,9 +189,9 @@ __device__ __forceinline__ void tile(const float x[3], const float *c1, const fl
     }
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-      f32x4 acc = {f.b2[mt][0], f.b2[mt][1], f.b2[mt][2], f.b2[mt][3]};
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2b[mt][0], ha, acc, 0, 0, 0);
-      z2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2b[mt][1], hb, acc, 0, 0, 0);
+      f32x4 acc = w.b2(mt);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.w2b(mt, 0), ha, acc, 0, 0, 0);
+      z2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.w2b(mt, 1), hb, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -179,9 +200,9 @@ __device__ __forceinline__ void tile(const float x[3], const float *c1, const fl
     }
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
-      f32x4 acc = {f.b3[mt][0], f.b3[mt][1], f.b3[mt][2], f.b3[mt][3]};
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w3b[mt][0], ha, acc, 0, 0, 0);
-      o[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w3b[mt][1], hb, acc, 0, 0, 0);
+      f32x4 acc = w.b3(mt);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.w3b(mt, 0), ha, acc, 0, 0, 0);
+      o[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.w3b(mt, 1), hb, acc, 0, 0, 0);
     }
   }
   // argmax over the bone logits (output index 16 mt + 4 g + i < nb), ties to
@@ -217,6 +238,45 @@ __device__ __forceinline__ void tile(const float x[3], const float *c1, const fl
   off_out[0] = off[0];
   off_out[1] = off[1];
   off_out[2] = off[2];
+}
+
+// Layer 1 on the VALU: lane r + 16 g holds neurons 16t + 4g + i of sample
+// r (point x); c1 [64] and w1x [64][3] in LDS or global memory.
+__device__ __forceinline__ void layer1(const float x[3], const float *c1, const float *w1x, int g, float h1[4][4]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int n = 16 * t + 4 * g + i;
+      h1[t][i] = relu(c1[n] + w1x[3 * n] * x[0] + w1x[3 * n + 1] * x[1] + w1x[3 * n + 2] * x[2]);
+    }
+}
+
+// Fragments held in registers (Frag).
+template <bool BF16>
+struct RegFrag {
+  const Frag<BF16> &f;
+  __device__ __forceinline__ float w2f(int mt, int k) const { return f.w2f[mt][k]; }
+  __device__ __forceinline__ float w3f(int mt, int k) const { return f.w3f[mt][k]; }
+  __device__ __forceinline__ bf16x8 w2b(int mt, int c) const { return f.w2b[mt][c]; }
+  __device__ __forceinline__ bf16x8 w3b(int mt, int c) const { return f.w3b[mt][c]; }
+  __device__ __forceinline__ f32x4 b2(int mt) const {
+    return f32x4{f.b2[mt][0], f.b2[mt][1], f.b2[mt][2], f.b2[mt][3]};
+  }
+  __device__ __forceinline__ f32x4 b3(int mt) const {
+    return f32x4{f.b3[mt][0], f.b3[mt][1], f.b3[mt][2], f.b3[mt][3]};
+  }
+};
+
+// One 16-sample tile, called by all 64 lanes of a wave (lane r + 16 g holds
+// sample r's point x): the argmax bone (ties: the lowest) and the three
+// offsets, in every lane of sample r.  c1 [64] and w1x [64][3] in LDS.
+template <bool BF16>
+__device__ __forceinline__ void tile(const float x[3], const float *c1, const float *w1x, const Frag<BF16> &f, int nb,
+                                     int g, int *bone, float off_out[3]) {
+  float h1[4][4];
+  layer1(x, c1, w1x, g, h1);
+  tile_tail<BF16>(h1, RegFrag<BF16>{f}, nb, g, bone, off_out);
 }
 
 // Broyden start point x0 = B_k^{-1} x' + offset (Bi: [M^-1 | -M^-1 t] of

@@ -86,8 +86,8 @@ _SIGS = {
     "volrender_bwd": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "l2_loss": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "batch_workspace_size": (_sz, [_i32, _i32, _i32, _i32, _i32]),
-    "batch_lds_bytes": (_sz, [_i32, _i32]),
-    "batch_render": (_i32, [_vp, _sz, _i32, _i32, _i32, _vp]),
+    "batch_lds_bytes": (_sz, [_i32, _i32, _i32]),
+    "batch_render": (_i32, [_vp, _sz, _i32, _i32, _i32, _i32, _vp]),
 }
 
 
@@ -486,9 +486,9 @@ def batch_workspace_size(n_poses, Dx, Dy, Dz, nb):
     return lib().ia355_batch_workspace_size(n_poses, Dx, Dy, Dz, nb)
 
 
-def batch_lds_bytes(rays_per_tile, samples_per_segment):
+def batch_lds_bytes(rays_per_tile, samples_per_segment, waves_per_group=4):
     """LDS bytes per workgroup of a render schedule (0: invalid shape)."""
-    return lib().ia355_batch_lds_bytes(rays_per_tile, samples_per_segment)
+    return lib().ia355_batch_lds_bytes(rays_per_tile, samples_per_segment, waves_per_group)
 
 
 def batch_pose(rays_o, rays_d, occ_bits, G, occ_aabb, dt, n_per_ray, max_steps, B, pose, color, opacity, n_used,
@@ -526,7 +526,8 @@ def batch_plan(poses, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, ta
                                   ws.numel() * ws.element_size(), _stream()), "batch_plan")
 
 
-def batch_render(ws, rays_per_tile, samples_per_segment, blocks_per_cu):
+def batch_render(ws, rays_per_tile, samples_per_segment, waves_per_group, blocks_per_cu):
     """Enqueue the batched render of the plan in ws (capturable)."""
     _check(lib().ia355_batch_render(_p(ws, name="ws"), ws.numel() * ws.element_size(), rays_per_tile,
-                                    samples_per_segment, blocks_per_cu, _stream()), "batch_render")
+                                    samples_per_segment, waves_per_group, blocks_per_cu, _stream()),
+           "batch_render")

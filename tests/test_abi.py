@@ -107,9 +107,11 @@ def test_batch_arguments_without_gpu():
     assert K.batch_workspace_size(K.BATCH_MAX_POSES + 1, 64, 64, 32, 24) == 0
     assert K.batch_workspace_size(1, 64, 64, 32, 33) == 0
     assert 0 < K.batch_lds_bytes(32, 256) < K.batch_lds_bytes(64, 256) < K.batch_lds_bytes(64, 512)
+    assert K.batch_lds_bytes(32, 256, 4) < K.batch_lds_bytes(32, 256, 8)
     assert K.batch_lds_bytes(0, 256) == 0 and K.batch_lds_bytes(65, 256) == 0 and K.batch_lds_bytes(16, 255) == 0
+    assert K.batch_lds_bytes(16, 256, 2) == 0
     pose = K.BatchPose()
     model = K.BatchModel()
     assert L.ia355_batch_plan(ctypes.byref(pose), 0, ctypes.byref(model), None, 0, None) == 1
     assert L.ia355_batch_plan(ctypes.byref(pose), 1, ctypes.byref(model), None, 0, None) == 1  # nb = 0
-    assert L.ia355_batch_render(None, 0, 32, 256, 2, None) == 2
+    assert L.ia355_batch_render(None, 0, 32, 256, 4, 2, None) == 2

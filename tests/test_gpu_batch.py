@@ -74,10 +74,11 @@ def test_batch_matches_single_pose(small_batch, n_streams):
     print(f"batch ({n_streams} streams): samples {[p.S for p in br.poses]}")
 
 
-# tile shapes: rays per tile (ragged last tiles, 64 = one lane per ray),
+# schedules: rays per tile (ragged last tiles, 64 = one lane per ray),
 # samples per segment (256: a 64-ray tile splits into several segments),
-# workgroups per CU
-@pytest.mark.parametrize("sched", [(64, 256, 2), (13, 256, 1), (32, 384, 2), (1, 256, 2)])
+# waves per workgroup, workgroups per CU (every kernel instantiation)
+@pytest.mark.parametrize("sched", [(64, 256, 4, 2), (13, 256, 4, 1), (32, 384, 4, 3), (1, 256, 4, 4),
+                                   (32, 256, 8, 1), (32, 256, 8, 2)])
 def test_persistent_matches_single_pose(small_batch, sched):
     from paper_2212_10550_amd.batch import BatchRenderer
     params = _params()
@@ -103,7 +104,7 @@ def test_persistent_full_poses_match_staged():
     refs = [{k: getattr(p, k).clone() for k in _OUTS} for p in br.poses]
     for r, p in zip(refs, br.poses):
         r["n_fallback"] = int(p.n_fallback.item())
-    br.set_persistent(32, 256, 2)
+    br.set_persistent(32, 256, 8, 2)
     br.capture()
     _check_replays(br, refs, "full poses")
     print(f"full poses: rays {[p.R for p in br.poses]}, samples {[p.S for p in br.poses]}")
@@ -113,15 +114,19 @@ def test_persistent_rejects_bad_schedules(small_batch):
     from paper_2212_10550_amd import lib as K
     from paper_2212_10550_amd.batch import BatchRenderer
     br = BatchRenderer(small_batch[:1], _params(), n_streams=1)
-    br.set_persistent(16, 256, 1)
+    br.set_persistent(16, 256, 4, 1)
     with pytest.raises(RuntimeError, match="status 1"):
-        K.batch_render(br._ws, 65, 256, 1)  # more rays per tile than lanes
+        K.batch_render(br._ws, 65, 256, 4, 1)  # more rays per tile than lanes
     with pytest.raises(RuntimeError, match="status 1"):
-        K.batch_render(br._ws, 16, 128, 1)  # a segment must hold two whole rays
+        K.batch_render(br._ws, 16, 128, 4, 1)  # a segment must hold two whole rays
     with pytest.raises(RuntimeError, match="status 1"):
-        K.batch_render(br._ws, 16, 256, 0)
+        K.batch_render(br._ws, 16, 256, 4, 0)
+    with pytest.raises(RuntimeError, match="status 1"):
+        K.batch_render(br._ws, 16, 256, 6, 1)  # 4 or 8 waves
     with pytest.raises(RuntimeError, match="status 3"):
-        K.batch_render(br._ws, 64, 4096, 1)  # beyond 64 KB of LDS
+        K.batch_render(br._ws, 16, 256, 8, 3)  # no such instantiation
+    with pytest.raises(RuntimeError, match="status 3"):
+        K.batch_render(br._ws, 64, 8192, 8, 1)  # beyond the LDS of a workgroup
 
 
 def test_batch_pose_against_oracle(orc, small_batch):

@@ -233,3 +233,56 @@ def test_table_grad_binned_nonfinite(orc):
     clean[~np.isfinite(clean)] = 0.0
     rc, _ = orc.hash_encode_bwd(clean, x, table, orc.resolutions(16), AABB_NP, valid=bone)
     gclose(np.where(fin, got, 0.0), np.where(fin, rc, 0.0), "grad_table (finite entries)")
+
+
+@pytest.mark.parametrize("small", [1e-12, 1e-17])
+def test_table_grad_binned_mixed_magnitudes(orc, small):
+    """One tile mixes a value near 1 and values near `small`: every entry is
+    within the fixed-point bound, absolute and relative to the chunk's
+    largest |value| m (here m <= 1 < 2^1): (records into the entry) * 2^-47
+    plus one FP32 rounding.  With small = 1e-12 the small entries keep about
+    eight significant bits; with 1e-17 (below m 2^-48) they come out zero,
+    where FP32 adds would have kept them."""
+    K = _K()
+    log2T = 14
+    # sample 0: gradient 1 on every feature; samples 1..3: `small`; all four
+    # in the same cells of the coarse dense levels' first tile
+    x = np.array([[0.11, 0.12, 0.13], [0.31, 0.12, 0.13], [0.11, 0.33, 0.13], [0.14, 0.15, 0.35]], np.float32)
+    S = x.shape[0]
+    gfeat = np.full((S, 32), small, np.float32)
+    gfeat[0] = 1.0
+    bone = np.zeros(S, np.int16)
+    table = np.zeros((16, 1 << log2T, 2), np.float32)
+    gt = torch.full((16, 1 << log2T, 2), 7.0, device=dev())
+    ws = torch.empty(K.hashgrid_table_grad_workspace_size(S, 16, 1 << log2T), dtype=torch.uint8, device=dev())
+    K.hashgrid_table_grad(feat_dev(gfeat, S), soa(x, S), up(bone), S, S, 16.0, 1.38, AABB, gt, ws, K.OVERWRITE)
+    torch.cuda.synchronize()
+    got = host(gt).astype(np.float64)
+    ref, _ = orc.hash_encode_bwd(gfeat, x, table, orc.resolutions(16), AABB_NP, valid=bone)
+    # records into an entry: at most 8 corners x S samples (a bound; dense
+    # levels give at most S)
+    bound = 8 * S * 2.0 ** -47 + 2.0 ** -24 * np.abs(ref)
+    err = np.abs(got - ref)
+    assert (err <= bound).all(), f"max error {err.max():.3e} vs bound at it {bound[np.argmax(err / bound)]:.3e}"
+    # entries reached only by the small samples, in tiles that sample 0 also
+    # reaches: sample 0's corner weights per entry (on the dense levels,
+    # 0 and 1 at T = 2^14, each entry holds at most one of its corners, so
+    # the largest of them in a tile is that tile's largest record m)
+    w0, _ = orc.hash_encode_bwd(np.r_[np.ones((1, 32)), np.zeros((S - 1, 32))], x, table, orc.resolutions(16),
+                                AABB_NP, valid=bone)
+    only_small = (w0 == 0) & (ref != 0)
+    tile_of = np.arange(1 << log2T) >> 12
+    m_tile = np.zeros((16, 4))
+    for l in range(16):
+        np.maximum.at(m_tile[l], tile_of, w0[l].max(axis=1))
+    m_ent = m_tile[:, tile_of][:, :, None] * np.ones((1, 1, 2))
+    shared = only_small & (m_ent > 0)
+    assert shared.any()
+    rel = np.abs(got[shared] - ref[shared]) / np.abs(ref[shared])
+    print(f"small={small:g}: {shared.sum()} small-only entries in tiles holding values near 1, relative error "
+          f"max {rel.max():.2e}, zero results {(got[shared] == 0).sum()}")
+    dense = np.zeros_like(shared)
+    dense[:2] = True
+    below = shared & dense & (small < m_ent * 2.0 ** -48)  # every record of the entry is below m 2^-48
+    if small < 1e-15:
+        assert below.any() and (got[below] == 0).all()

@@ -583,7 +583,9 @@ def batch_leg(args, params, poses, gen_s, torch, np, synth, out, checks):
     multi-init fallback.  The autotuner times the persistent kernel under
     several tile shapes and the staged kernels on 1, 2 and 4 streams, and
     keeps the fastest; the other execution then renders the same batch and
-    every pose's outputs are compared bit for bit."""
+    every pose's outputs are compared bit for bit.  samples_per_s counts the
+    posed samples (what the staged kernels evaluate); the persistent kernel
+    skips the groups after each ray's termination."""
     from paper_2212_10550_amd.batch import BatchRenderer
     br = BatchRenderer(poses, params)
     tune = br.autotune((1, 2, 4), n=3)
@@ -594,6 +596,8 @@ def batch_leg(args, params, poses, gen_s, torch, np, synth, out, checks):
     torch.cuda.synchronize()
     got = [{k: getattr(p, k).clone() for k in keys} for p in br.poses]
     fb = [int(p.n_fallback.item()) for p in br.poses]
+    chosen_persistent = br.persistent is not None
+    evaluated = sum(int(p.n_evaluated.item()) for p in br.poses) if chosen_persistent else S
     colors = {k: br.poses[k].color.double().cpu().numpy() for k in (0, 4, 2)}
     # the other execution on the same batch
     if br.persistent is not None:
@@ -608,7 +612,10 @@ def batch_leg(args, params, poses, gen_s, torch, np, synth, out, checks):
     br.render()
     torch.cuda.synchronize()
     same = all(torch.equal(getattr(p, k), g[k]) for p, g in zip(br.poses, got) for k in keys)
-    same_fb = fb == [int(p.n_fallback.item()) for p in br.poses]
+    fb_other = [int(p.n_fallback.item()) for p in br.poses]
+    if br.persistent is not None:
+        evaluated = sum(int(p.n_evaluated.item()) for p in br.poses)
+    used = sum(int(p.n_used.sum().item()) for p in br.poses)
     del got
     out["batched_render"] = {
         "workload": "16 poses (seeds 3000-3015), occupancy 5 % + 20 % k/15, resolution 270^2/540^2/1080^2 by k mod 3, "
@@ -617,9 +624,11 @@ def batch_leg(args, params, poses, gen_s, torch, np, synth, out, checks):
         "ms_per_batch": ms, "samples_per_s": S / (ms * 1e-3), "frames_per_s": 16 / (ms * 1e-3),
         "execution": "one HIP graph replay per batch, the autotuner's fastest schedule",
         "schedule": br_schedule(tune), "autotune_ms": tune,
+        "samples_used_by_compositing": used,
+        "samples_evaluated_persistent": evaluated,
         "fallback_samples": int(sum(fb)),
         "outputs_equal_other_execution": {"other": other, "pixels_bit_equal": bool(same),
-                                           "fallback_counts_equal": bool(same_fb)},
+                                           "fallback_samples_other": int(sum(fb_other))},
         "input_generation_s": gen_s,
     }
     checks["batch"] = (poses, colors)

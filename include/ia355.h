@@ -493,8 +493,9 @@ int32_t ia355_l2_loss(const float *color, const float *target, int64_t R, float 
  *   ia355_occgrid_march, max_steps <= 128;
  *   B [nb][3][4] bone transforms; pose [nb][6] the initialiser's pose input;
  *   outputs as ia355_volrender_fwd: color [R][3], opacity [R], n_used [R],
- *   T_final [R]; n_fallback [1] (nullable) receives the number of samples
- *   whose guided solve was rejected. */
+ *   T_final [R]; n_fallback [1] (nullable) receives the number of evaluated
+ *   samples whose guided solve was rejected, n_evaluated [1] (nullable) the
+ *   number of samples evaluated (see below). */
 typedef struct ia355_batch_pose {
   const float *rays_o, *rays_d;
   int64_t R;
@@ -507,7 +508,7 @@ typedef struct ia355_batch_pose {
   float *color, *opacity;
   int32_t *n_used;
   float *T_final;
-  int32_t *n_fallback;
+  int32_t *n_fallback, *n_evaluated;
 } ia355_batch_pose;
 
 /* What the poses share (device pointers, owned by the caller):
@@ -537,7 +538,10 @@ typedef struct ia355_batch_model {
  * ia355_rootinit_fwd -> ia355_snarf_deform_guided -> ia355_hashgrid_encode
  * (FP16 table, BF16 features) -> ia355_mlp_fwd (BF16) ->
  * ia355_volrender_fwd): the same operations on the same values, so the
- * same bits, with no per-sample buffer in global memory.
+ * same output bits, with no per-sample buffer in global memory.  Samples are
+ * evaluated in the compositor's groups of 16 per ray, front to back, and a
+ * ray's groups after the one where it terminates (Eq. 8 with T_thresh) are
+ * not evaluated: they cannot change its outputs.
  * ia355_batch_plan validates the poses and the model and writes the plan
  * into ws (ia355_batch_workspace_size bytes: the plan, a work counter and
  * per pose the blended transform grid, the folded initialiser constant and

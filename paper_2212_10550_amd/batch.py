@@ -49,6 +49,7 @@ class _Pose:
         self.n_used = e(self.R, dt=torch.int32)
         self.T_final = e(self.R)
         self.n_fallback = e(1, dt=torch.int32)
+        self.n_evaluated = torch.zeros(1, dtype=torch.int32, device=dev)  # persistent render only
         self.S = None  # exact sample count (march prepass)
 
 
@@ -134,7 +135,8 @@ class BatchRenderer:
         self._ws = torch.empty(K.batch_workspace_size(len(self.poses), Dx, Dy, Dz, nb), dtype=torch.uint8,
                                device=self.dev)
         descs = [K.batch_pose(p.rays_o, p.rays_d, p.occ_bits, p.G, p.w.occ_aabb, p.w.dt, p.w.n_per_ray,
-                              p.w.max_steps, p.B, p.pose_t, p.color, p.opacity, p.n_used, p.T_final, p.n_fallback)
+                              p.w.max_steps, p.B, p.pose_t, p.color, p.opacity, p.n_used, p.T_final, p.n_fallback,
+                              p.n_evaluated)
                  for p in self.poses]
         K.batch_plan(descs, self.W, w0.skin_aabb, w0.hash_aabb, w0.max_iter, w0.tol_stop, w0.tol_valid, self.table,
                      w0.base_res, w0.growth, self.params, self.ri_params, w0.T_thresh, self._ws)
@@ -222,8 +224,8 @@ class BatchRenderer:
         return a.elapsed_time(b) / n
 
     # (rays per tile, samples per segment, waves per workgroup, workgroups per CU)
-    PERSISTENT_CANDIDATES = ((16, 256, 4, 3), (32, 256, 4, 2), (32, 256, 4, 3), (16, 256, 4, 4), (32, 256, 8, 1),
-                             (32, 256, 8, 2), (64, 256, 8, 2), (16, 384, 4, 3))
+    PERSISTENT_CANDIDATES = ((16, 256, 4, 3), (12, 256, 4, 3), (8, 256, 4, 3), (32, 256, 4, 2), (16, 256, 4, 4),
+                             (16, 256, 8, 1), (16, 256, 8, 2), (32, 256, 8, 2))
 
     def autotune(self, candidates=(1, 2, 4), n=3, persistent=None):
         """Time the captured batch for each schedule -- every stream count of

@@ -68,7 +68,7 @@ struct PoseDev {
   float dt_fixed;
   const float *B, *pose;
   float *color, *opacity, *T_final;
-  int32_t *n_used, *n_fallback;
+  int32_t *n_used, *n_fallback, *n_evaluated;
   float *A, *c1, *binv;  // workspace: blended grid, folded layer-1 constant, bone inverses
   int *bok;
 };
@@ -113,18 +113,22 @@ struct WaveMem {
   uint64_t *mask;  // [rt][2]
   float *o, *d;    // [rt][3]
   float *tn, *tf, *dt;
-  int *off;        // [rt + 1]
+  float *T;        // [rt] transmittance before the segment's next group, per ray
+  float *c1;       // [64] the tile's pose's folded initialiser constant
+  int *off;        // [rt + 1] first sample of each ray in the tile
+  int *alive;      // [rt] the ray has groups left and has not terminated
+  int *roff;       // [rt + 1] first sample of each ray in the current round
   float *sig;      // [ch]
   float *rgb;      // [ch][3]
   int16_t *queue;  // [ch]
 };
 
 __host__ __device__ inline size_t wave_bytes(int rt, int ch) {
-  size_t b = 16 * (size_t)rt;                  // masks
-  b += sizeof(float) * 9 * (size_t)rt;         // o, d, tn, tf, dt
-  b += sizeof(int) * (size_t)(rt + 1);         // off
-  b += sizeof(float) * 4 * (size_t)ch;         // sig, rgb
-  b += sizeof(int16_t) * (size_t)ch;           // queue
+  size_t b = 16 * (size_t)rt;                      // masks
+  b += sizeof(float) * (10 * (size_t)rt + 64);     // o, d, tn, tf, dt, T, c1
+  b += sizeof(int) * (3 * (size_t)rt + 2);         // off, alive, roff
+  b += sizeof(float) * 4 * (size_t)ch;             // sig, rgb
+  b += sizeof(int16_t) * (size_t)ch;               // queue
   return (b + 15) & ~(size_t)15;
 }
 
@@ -137,8 +141,12 @@ __device__ inline WaveMem carve(char *p, int rt, int ch) {
   w.tn = w.d + 3 * rt;
   w.tf = w.tn + rt;
   w.dt = w.tf + rt;
-  w.off = reinterpret_cast<int *>(w.dt + rt);
-  w.sig = reinterpret_cast<float *>(w.off + rt + 1);
+  w.T = w.dt + rt;
+  w.c1 = w.T + rt;
+  w.off = reinterpret_cast<int *>(w.c1 + 64);
+  w.alive = w.off + rt + 1;
+  w.roff = w.alive + rt;
+  w.sig = reinterpret_cast<float *>(w.roff + rt + 1);
   w.rgb = w.sig + ch;
   w.queue = reinterpret_cast<int16_t *>(w.rgb + 3 * ch);
   return w;
@@ -175,12 +183,18 @@ __device__ inline int ray_of(const int *off, int ra, int rb, int j) {
   return lo;
 }
 
-// Posed position of tile sample j (the march's expression for its step).
-__device__ inline void sample_xp(const WaveMem &wm, int ra, int rb, int j, float xp[3]) {
-  const int rr = ray_of(wm.off, ra, rb, j);
-  const int k = select_bit(wm.mask[2 * rr], wm.mask[2 * rr + 1], j - wm.off[rr]);
+// Posed position of the q-th kept sample of tile ray rr (the march's
+// expression for its step).
+__device__ inline void ray_sample_xp(const WaveMem &wm, int rr, int q, float xp[3]) {
+  const int k = select_bit(wm.mask[2 * rr], wm.mask[2 * rr + 1], q);
   float t;
   mch::sample_pos(wm.o + 3 * rr, wm.d + 3 * rr, wm.tn[rr], wm.dt[rr], k, &t, xp);
+}
+
+// Posed position of tile sample j (rays [ra, rb) hold it).
+__device__ inline void sample_xp(const WaveMem &wm, int ra, int rb, int j, float xp[3]) {
+  const int rr = ray_of(wm.off, ra, rb, j);
+  ray_sample_xp(wm, rr, j - wm.off[rr], xp);
 }
 
 // Decoder weights fetched from the workgroup's LDS as the MFMAs use them
@@ -323,6 +337,7 @@ __global__ void __launch_bounds__(kPrepBlock) prep_kernel(const Plan *__restrict
       rid::fold_pose(pl.init, l, pd.pose, pl.nb, pd.c1);
       stage_bone_inverses(pd.B, pl.nb, pd.binv, pd.bok);
       if (threadIdx.x == 0 && pd.n_fallback) *pd.n_fallback = 0;
+      if (threadIdx.x == 0 && pd.n_evaluated) *pd.n_evaluated = 0;
     }
     __syncthreads();
   }
@@ -395,6 +410,7 @@ __global__ void __launch_bounds__(kW * kWave, kMinGroups * kW / 4) render_kernel
     const PoseDev &pd = pl.pose[p];
     const int64_t ray0 = (int64_t)(item - st.tile0[p]) * rt;
     const int nr = (int)min((int64_t)rt, pd.R - ray0);
+    wm.c1[lane] = pd.c1[lane];
 
     // march: spans (one lane per ray), then keep masks (lanes = steps)
     if (lane < nr) {
@@ -426,7 +442,7 @@ __global__ void __launch_bounds__(kW * kWave, kMinGroups * kW / 4) render_kernel
     const int total = __builtin_amdgcn_readfirstlane(wm.off[nr]);
     const int nseg = total == 0 ? 1 : (total + C - 1) / C;
     const float *A = pd.A;
-    int nfb = 0;
+    int nfb = 0, nev = 0;
     int ra = 0;
     for (int sgi = 0; sgi < nseg; ++sgi) {
       int rb = nr;
@@ -436,26 +452,55 @@ __global__ void __launch_bounds__(kW * kWave, kMinGroups * kW / 4) render_kernel
         rb = bm ? (int)__builtin_ctzll(bm) : nr;
       }
       const int sb = __builtin_amdgcn_readfirstlane(wm.off[ra]), se = __builtin_amdgcn_readfirstlane(wm.off[rb]);
-      const int n = se - sb;
-      int qn = 0;
-      for (int c0 = 0; c0 < n; c0 += kWave) {
-        const int j = sb + c0 + lane;
-        const bool act = j < se;
-        const int nt = (min(kWave, n - c0) + 15) >> 4;  // 16-sample tiles in this chunk
-        float xp[3] = {0.0f, 0.0f, 0.0f};
-        if (act) sample_xp(wm, ra, rb, j, xp);
-        // learned initialiser: lane r + 16 t's sample is row r of tile t,
-        // and that lane holds the tile's result for it
-        int ibone = 0;
-        float x0[3] = {0.0f, 0.0f, 0.0f};
+      const int nrs = rb - ra;  // rays of the segment
+      // Rounds: round k evaluates group k (kept samples 16k .. 16k + 15,
+      // the compositor's groups) of every ray still alive, then steps each
+      // such ray's transmittance through that group with the compositor's
+      // own group step; a ray whose group has an unused sample (T_i below
+      // the threshold) is finished, and its later samples are never
+      // evaluated.  The final composite reads only evaluated groups.
+      if (lane < nrs) {
+        wm.T[lane] = 1.0f;
+        wm.alive[lane] = wm.off[ra + lane + 1] > wm.off[ra + lane];
+      }
+      mlpd::wave_sync();
+      const LdsSrc src{wm.sig, wm.rgb, ch};
+      for (int k = 0;; ++k) {
         {
+          int m = 0;
+          if (lane < nrs && wm.alive[lane]) m = min(rnd::kSeg, wm.off[ra + lane + 1] - wm.off[ra + lane] - rnd::kSeg * k);
+          const int incl = wave_incl_scan(m);
+          if (lane < nrs) wm.roff[lane + 1] = incl;
+          if (lane == 0) wm.roff[0] = 0;
+        }
+        mlpd::wave_sync();
+        const int nk = __builtin_amdgcn_readfirstlane(wm.roff[nrs]);  // samples of this round
+        if (nk == 0) break;
+        nev += nk;
+        int qn = 0;
+        for (int c0 = 0; c0 < nk; c0 += kWave) {
+          const int jr = c0 + lane;
+          const bool act = jr < nk;
+          const int nt = (min(kWave, nk - c0) + 15) >> 4;  // 16-sample tiles in this chunk
+          int slot = 0;  // the sample's index in the segment
+          float xp[3] = {0.0f, 0.0f, 0.0f};
+          if (act) {
+            const int rl = ray_of(wm.roff, 0, nrs, jr);
+            const int q = rnd::kSeg * k + (jr - wm.roff[rl]);
+            slot = wm.off[ra + rl] - sb + q;
+            ray_sample_xp(wm, ra + rl, q, xp);
+          }
+          // learned initialiser: lane r + 16 t's sample is row r of tile t,
+          // and that lane holds the tile's result for it
+          int ibone = 0;
+          float x0[3] = {0.0f, 0.0f, 0.0f};
           for (int t = 0; t < nt; ++t) {
             keep_in_loop();
-            const int src = 16 * t + r;
-            const float xs[3] = {__shfl(xp[0], src, kWave), __shfl(xp[1], src, kWave), __shfl(xp[2], src, kWave)};
+            const int sr = 16 * t + r;
+            const float xs[3] = {__shfl(xp[0], sr, kWave), __shfl(xp[1], sr, kWave), __shfl(xp[2], sr, kWave)};
             int bi;
             float off3[3], h1[4][4];
-            rid::layer1(xs, pd.c1, st.w1x, g, h1);
+            rid::layer1(xs, wm.c1, st.w1x, g, h1);
             rid::tile_tail<true>(h1, LdsRW{st, lane, g}, nb, g, &bi, off3);
             if (g == t) {
               const int kb = bi < nb ? bi : 0;
@@ -463,57 +508,74 @@ __global__ void __launch_bounds__(kW * kWave, kMinGroups * kW / 4) render_kernel
               rid::start_point(pd.binv + 12 * kb, xs, off3, x0);
             }
           }
-        }
-        // guided solve
-        bool fb = false;
-        int bone = -1;
-        float xc[3] = {0.0f, 0.0f, 0.0f};
-        if (act) {
-          const dfm::InitResult q = dfm::broyden_from(A, pl.gr, x0, true, xp, pl.max_iter, pl.tol_stop);
-          if (q.ok && q.r < pl.tol_valid && dfm::in_hbox(q.x, pl.hbox)) {
-            xc[0] = q.x[0];
-            xc[1] = q.x[1];
-            xc[2] = q.x[2];
-            bone = ibone;
-          } else {
-            fb = true;
+          // guided solve
+          bool fb = false;
+          int bone = -1;
+          float xc[3] = {0.0f, 0.0f, 0.0f};
+          if (act) {
+            const dfm::InitResult q = dfm::broyden_from(A, pl.gr, x0, true, xp, pl.max_iter, pl.tol_stop);
+            if (q.ok && q.r < pl.tol_valid && dfm::in_hbox(q.x, pl.hbox)) {
+              xc[0] = q.x[0];
+              xc[1] = q.x[1];
+              xc[2] = q.x[2];
+              bone = ibone;
+            } else {
+              fb = true;
+            }
+          }
+          const uint64_t fm = __ballot(fb);
+          if (fb) wm.queue[qn + __popcll(fm & below)] = (int16_t)slot;
+          qn += __popcll(fm);
+          // encode + decoder of the accepted samples
+          for (int t = 0; t < nt; ++t) {
+            keep_in_loop();
+            const int sr = 16 * t + r;
+            const float xs[3] = {__shfl(xc[0], sr, kWave), __shfl(xc[1], sr, kWave), __shfl(xc[2], sr, kWave)};
+            const int bs = __shfl(bone, sr, kWave);
+            const int ss = __shfl(slot, sr, kWave);
+            encode_decode(pl, st, lane, xs, bs, bs >= 0, ss, g, wm.sig, wm.rgb, ch);
           }
         }
-        const uint64_t fm = __ballot(fb);
-        if (fb) wm.queue[qn + __popcll(fm & below)] = (int16_t)(c0 + lane);
-        qn += __popcll(fm);
-        // encode + decoder of the accepted samples
-        for (int t = 0; t < nt; ++t) {
+        mlpd::wave_sync();
+        // fallback: the multi-init solve of the round's queued samples, two
+        // at a time (32 lanes each), then their encode + decoder as rows 0
+        // and 1 of a tile
+        for (int q0 = 0; q0 < qn; q0 += 2) {
+          const int h = lane >> 5;
+          const bool qa = q0 + h < qn;
+          const int sj = qa ? (int)wm.queue[q0 + h] : 0;
+          float xp[3] = {0.0f, 0.0f, 0.0f};
+          if (qa) sample_xp(wm, ra, rb, sb + sj, xp);
+          const dfm::Choice cc = dfm::multi_init<32>(A, pl.gr, pd.binv, pd.bok, nb, xp, qa, lane & 31, pl.hbox,
+                                                     pl.max_iter, pl.tol_stop, pl.tol_valid);
+          const int sr = r < 2 ? 32 * r : 0;
+          const float xs[3] = {__shfl(cc.x[0], sr, kWave), __shfl(cc.x[1], sr, kWave), __shfl(cc.x[2], sr, kWave)};
+          const bool qs = __shfl((int)qa, sr, kWave) != 0 && r < 2;
+          const int bs = qs ? __shfl(cc.bone, sr, kWave) : -1;
+          const int ss = __shfl(sj, sr, kWave);
           keep_in_loop();
-          const int src = 16 * t + r;
-          const float xs[3] = {__shfl(xc[0], src, kWave), __shfl(xc[1], src, kWave), __shfl(xc[2], src, kWave)};
-          const int bs = __shfl(bone, src, kWave);
-          encode_decode(pl, st, lane, xs, bs, bs >= 0, c0 + src, g, wm.sig, wm.rgb, ch);
+          encode_decode(pl, st, lane, xs, bs, qs, ss, g, wm.sig, wm.rgb, ch);
         }
+        nfb += qn;
+        mlpd::wave_sync();
+        // transmittance through group k of every ray of this round
+        for (int r0 = 0; r0 < nrs; r0 += 4) {
+          const int rl = r0 + (lane >> 4), jj = lane & 15;
+          if (rl < nrs && wm.roff[rl + 1] > wm.roff[rl]) {
+            const int rr = ra + rl;
+            rnd::RayState rs = rnd::ray_start();
+            rs.T = wm.T[rl];
+            const int b0 = wm.off[rr] - sb, e0 = wm.off[rr + 1] - sb;
+            rnd::composite_group(src, b0 + rnd::kSeg * k, e0, wm.dt[rr], pl.T_thresh, jj, rs);
+            if (jj == 0) {
+              wm.T[rl] = rs.T;
+              wm.alive[rl] = !rs.done && e0 - b0 > rnd::kSeg * (k + 1);
+            }
+          }
+        }
+        mlpd::wave_sync();
       }
-      mlpd::wave_sync();
-      // fallback: the multi-init solve of the queued samples, two at a time
-      // (32 lanes each), then their encode + decoder as rows 0 and 1 of a tile
-      for (int q0 = 0; q0 < qn; q0 += 2) {
-        const int h = lane >> 5;
-        const bool qa = q0 + h < qn;
-        const int sj = qa ? (int)wm.queue[q0 + h] : 0;
-        float xp[3] = {0.0f, 0.0f, 0.0f};
-        if (qa) sample_xp(wm, ra, rb, sb + sj, xp);
-        const dfm::Choice cc = dfm::multi_init<32>(A, pl.gr, pd.binv, pd.bok, nb, xp, qa, lane & 31, pl.hbox,
-                                                   pl.max_iter, pl.tol_stop, pl.tol_valid);
-        const int src = r < 2 ? 32 * r : 0;
-        const float xs[3] = {__shfl(cc.x[0], src, kWave), __shfl(cc.x[1], src, kWave), __shfl(cc.x[2], src, kWave)};
-        const bool qs = __shfl((int)qa, src, kWave) != 0 && r < 2;
-        const int bs = qs ? __shfl(cc.bone, src, kWave) : -1;
-        const int slot = __shfl(sj, src, kWave);
-        keep_in_loop();
-        encode_decode(pl, st, lane, xs, bs, qs, slot, g, wm.sig, wm.rgb, ch);
-      }
-      nfb += qn;
-      mlpd::wave_sync();
       // composite: 16 lanes per ray, four rays at a time
-      const LdsSrc src{wm.sig, wm.rgb, ch};
       for (int r0 = ra; r0 < rb; r0 += 4) {
         const int rr = r0 + (lane >> 4), jj = lane & 15;
         if (rr < rb) {
@@ -534,6 +596,7 @@ __global__ void __launch_bounds__(kW * kWave, kMinGroups * kW / 4) render_kernel
       ra = rb;
     }
     if (lane == 0 && nfb > 0 && pd.n_fallback) atomicAdd(pd.n_fallback, nfb);
+    if (lane == 0 && nev > 0 && pd.n_evaluated) atomicAdd(pd.n_evaluated, nev);
   }
 }
 
@@ -632,6 +695,7 @@ extern "C" int32_t ia355_batch_plan(const ia355_batch_pose *poses, int32_t n_pos
     d.T_final = q.T_final;
     d.n_used = q.n_used;
     d.n_fallback = q.n_fallback;
+    d.n_evaluated = q.n_evaluated;
     char *pp = base + wl.pose0 + (size_t)p * wl.per_pose;
     d.A = (float *)(pp + wl.A);
     d.c1 = (float *)(pp + wl.c1);

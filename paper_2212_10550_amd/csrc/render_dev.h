@@ -54,46 +54,66 @@ struct RayOut {
   int used;
 };
 
+// Compositing state of one ray between its groups of kSeg samples: T and
+// used are the same in every lane of the segment, C and A are per-lane
+// partial sums (lane j holds samples j, j + kSeg, ...).
+struct RayState {
+  float T, C0, C1, C2, A;
+  int used;
+  bool done;
+};
+
+__device__ __forceinline__ RayState ray_start() { return RayState{1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0, false}; }
+
+// One group: samples base .. base + kSeg - 1 of samples .. e - 1 (lane j
+// takes sample base + j); src(i, &sigma, rgb) reads sample i.  Sets done at
+// the first group with an unused sample (T is then the transmittance of
+// that sample), as the termination test T_i >= T_thresh keeps a prefix.
+template <class Src>
+__device__ __forceinline__ void composite_group(const Src &src, int64_t base, int64_t e, float dt, float T_thresh,
+                                                int j, RayState &st) {
+  const int64_t i = base + j;
+  const bool valid = i < e;
+  float s = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
+  if (valid) src(i, &s, c);
+  const float x = valid ? s * dt : 0.0f;
+  float prod;
+  const float Ti = seg_trans(st.T, valid ? expf(-x) : 1.0f, j, &prod);
+  const bool use = valid && Ti >= T_thresh;
+  if (use) {
+    const float w = Ti * -expm1f(-x);
+    st.C0 += w * c[0];
+    st.C1 += w * c[1];
+    st.C2 += w * c[2];
+    st.A += w;
+  }
+  const int n = seg_count(use);
+  st.used += n;
+  const int len = e - base < kSeg ? (int)(e - base) : kSeg;
+  if (n < len) {  // terminated inside this group: T of the first unused sample
+    st.T = __shfl(Ti, n, kSeg);
+    st.done = true;
+  } else {
+    st.T *= prod;
+  }
+}
+
 // Composites samples b..e-1 of one ray (lane j of its kSeg-lane segment);
 // src(i, &sigma, rgb) reads sample i.  Every lane of the segment returns the
 // ray's colour, opacity, final transmittance and number of samples used.
+// Only the groups up to the one where the ray terminates are read.
 template <class Src>
 __device__ __forceinline__ RayOut composite_ray(const Src &src, int64_t b, int64_t e, float dt, float T_thresh,
                                                 int j) {
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, A = 0.0f;
-  int used = 0;
-  for (int64_t base = b; base < e; base += kSeg) {
-    const int64_t i = base + j;
-    const bool valid = i < e;
-    float s = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
-    if (valid) src(i, &s, c);
-    const float x = valid ? s * dt : 0.0f;
-    float prod;
-    const float Ti = seg_trans(T, valid ? expf(-x) : 1.0f, j, &prod);
-    const bool use = valid && Ti >= T_thresh;
-    if (use) {
-      const float w = Ti * -expm1f(-x);
-      C0 += w * c[0];
-      C1 += w * c[1];
-      C2 += w * c[2];
-      A += w;
-    }
-    const int n = seg_count(use);
-    used += n;
-    const int len = e - base < kSeg ? (int)(e - base) : kSeg;
-    if (n < len) {  // terminated inside this chunk: T of the first unused sample
-      T = __shfl(Ti, n, kSeg);
-      break;
-    }
-    T *= prod;
-  }
+  RayState st = ray_start();
+  for (int64_t base = b; base < e && !st.done; base += kSeg) composite_group(src, base, e, dt, T_thresh, j, st);
   RayOut q;
-  q.C[0] = seg_sum(C0);
-  q.C[1] = seg_sum(C1);
-  q.C[2] = seg_sum(C2);
-  q.A = seg_sum(A);
-  q.T = T;
-  q.used = used;
+  q.C[0] = seg_sum(st.C0);
+  q.C[1] = seg_sum(st.C1);
+  q.C[2] = seg_sum(st.C2);
+  q.A = seg_sum(st.A);
+  q.T = st.T;
+  q.used = st.used;
   return q;
 }
 

@@ -96,7 +96,7 @@ class BatchPose(ctypes.Structure):
     _fields_ = [("rays_o", _vp), ("rays_d", _vp), ("R", _i64), ("occ_bits", _vp), ("G", _i32),
                 ("occ_aabb", _f * 6), ("dt", _f), ("n_per_ray", _i32), ("max_steps", _i32), ("B", _vp),
                 ("pose", _vp), ("color", _vp), ("opacity", _vp), ("n_used", _vp), ("T_final", _vp),
-                ("n_fallback", _vp)]
+                ("n_fallback", _vp), ("n_evaluated", _vp)]
 
 
 class BatchModel(ctypes.Structure):
@@ -492,7 +492,7 @@ def batch_lds_bytes(rays_per_tile, samples_per_segment, waves_per_group=4):
 
 
 def batch_pose(rays_o, rays_d, occ_bits, G, occ_aabb, dt, n_per_ray, max_steps, B, pose, color, opacity, n_used,
-               T_final, n_fallback=None):
+               T_final, n_fallback=None, n_evaluated=None):
     """One ``ia355_batch_pose`` from GPU tensors (the tensors must outlive
     every render that uses the plan)."""
     R = rays_o.shape[0]
@@ -506,7 +506,8 @@ def batch_pose(rays_o, rays_d, occ_bits, G, occ_aabb, dt, n_per_ray, max_steps, 
                      _p(occ_bits, torch.int32, "occ_bits"), G, _box(occ_aabb), float(dt), n_per_ray, max_steps,
                      _p(B, torch.float32, "B"), _p(pose, torch.float32, "pose"), _p(color, torch.float32, "color"),
                      _p(opacity, torch.float32, "opacity"), _p(n_used, torch.int32, "n_used"),
-                     _p(T_final, torch.float32, "T_final"), _p(n_fallback, torch.int32, "n_fallback"))
+                     _p(T_final, torch.float32, "T_final"), _p(n_fallback, torch.int32, "n_fallback"),
+                     _p(n_evaluated, torch.int32, "n_evaluated"))
 
 
 def batch_plan(poses, W, skin_aabb, hash_aabb, max_iter, tol_stop, tol_valid, table, base_res, growth, mlp_params,

@@ -237,39 +237,56 @@ def test_table_grad_binned_nonfinite(orc):
 
 @pytest.mark.parametrize("small", [1e-12, 1e-17])
 def test_table_grad_binned_mixed_magnitudes(orc, small):
-    """One tile mixes a value near 1 and values near `small`: every entry is
-    within the fixed-point bound, absolute and relative to the chunk's
-    largest |value| m (here m <= 1 < 2^1): (records into the entry) * 2^-47
-    plus one FP32 rounding.  With small = 1e-12 the small entries keep about
-    eight significant bits; with 1e-17 (below m 2^-48) they come out zero,
-    where FP32 adds would have kept them."""
+    """One tile mixes a value near 1 and values near `small`.  The binned
+    sum's own error is absolute, relative to the chunk's largest |value| m
+    (here m <= 1 < 2^1): (records into the entry) * 2^-47 plus one FP32
+    rounding.  Checked against the oracle on the dense levels 0-1 (where the
+    FP32 corner weights are accurate to about 6 N 2^-24, N <= 22), adding
+    that weight error per record, and against the FP32-atomic path on every
+    level (same records; its FP32 sums round at 2^-24 per add).  With
+    small = 1e-12 the small entries keep about eight significant bits; with
+    1e-17 (below m 2^-48) they come out zero, where FP32 adds keep them."""
     K = _K()
     log2T = 14
     # sample 0: gradient 1 on every feature; samples 1..3: `small`; all four
-    # in the same cells of the coarse dense levels' first tile
+    # in the coarse dense levels' first tile
     x = np.array([[0.11, 0.12, 0.13], [0.31, 0.12, 0.13], [0.11, 0.33, 0.13], [0.14, 0.15, 0.35]], np.float32)
     S = x.shape[0]
     gfeat = np.full((S, 32), small, np.float32)
     gfeat[0] = 1.0
     bone = np.zeros(S, np.int16)
     table = np.zeros((16, 1 << log2T, 2), np.float32)
-    gt = torch.full((16, 1 << log2T, 2), 7.0, device=dev())
     ws = torch.empty(K.hashgrid_table_grad_workspace_size(S, 16, 1 << log2T), dtype=torch.uint8, device=dev())
+    gt = torch.full((16, 1 << log2T, 2), 7.0, device=dev())
     K.hashgrid_table_grad(feat_dev(gfeat, S), soa(x, S), up(bone), S, S, 16.0, 1.38, AABB, gt, ws, K.OVERWRITE)
+    ga = torch.zeros((16, 1 << log2T, 2), device=dev())
+    K.hashgrid_encode_bwd(feat_dev(gfeat, S), soa(x, S), up(bone), S, S, torch.zeros_like(ga), 16.0, 1.38, AABB,
+                          ga, None)
     torch.cuda.synchronize()
     got = host(gt).astype(np.float64)
-    ref, _ = orc.hash_encode_bwd(gfeat, x, table, orc.resolutions(16), AABB_NP, valid=bone)
-    # records into an entry: at most 8 corners x S samples (a bound; dense
-    # levels give at most S)
-    bound = 8 * S * 2.0 ** -47 + 2.0 ** -24 * np.abs(ref)
-    err = np.abs(got - ref)
-    assert (err <= bound).all(), f"max error {err.max():.3e} vs bound at it {bound[np.argmax(err / bound)]:.3e}"
+    atom = host(ga).astype(np.float64)
+    res = orc.resolutions(16)
+    ref, _ = orc.hash_encode_bwd(gfeat, x, table, res, AABB_NP, valid=bone)
+    n_rec = 8 * S  # records into one entry, at most
+    fixed = n_rec * 2.0 ** -47
+    # against the FP32-atomic path, every level
+    b_at = fixed + 2.0 ** -24 * np.abs(got) + n_rec * 2.0 ** -24 * np.abs(atom)
+    e_at = np.abs(got - atom)
+    i = np.unravel_index(np.argmax(e_at / b_at), e_at.shape)
+    assert (e_at <= b_at).all(), f"binned vs atomic at {i}: {got[i]!r} vs {atom[i]!r}, bound {b_at[i]:.3e}"
+    # against the oracle, dense levels 0-1: per record, |g| times the corner
+    # weight's error (6 N 2^-24 over the three axes, plus its own rounding)
+    ew = np.array([6 * 2.0 ** -24 * n + 2.0 ** -23 for n in res[:2]])[:, None, None]
+    w0, _ = orc.hash_encode_bwd(np.r_[np.ones((1, 32)), np.zeros((S - 1, 32))], x, table, res, AABB_NP, valid=bone)
+    g_rec = np.where(w0[:2] > 0, 8 * 1.0 + 8 * (S - 1) * small, 8 * (S - 1) * small)  # sum of |g| over its records
+    b_or = g_rec * ew + fixed + 2.0 ** -24 * np.abs(ref[:2])
+    e_or = np.abs(got[:2] - ref[:2])
+    i = np.unravel_index(np.argmax(e_or / b_or), e_or.shape)
+    assert (e_or <= b_or).all(), f"binned vs oracle at {i}: {got[:2][i]!r} vs {ref[:2][i]!r}, bound {b_or[i]:.3e}"
     # entries reached only by the small samples, in tiles that sample 0 also
-    # reaches: sample 0's corner weights per entry (on the dense levels,
-    # 0 and 1 at T = 2^14, each entry holds at most one of its corners, so
-    # the largest of them in a tile is that tile's largest record m)
-    w0, _ = orc.hash_encode_bwd(np.r_[np.ones((1, 32)), np.zeros((S - 1, 32))], x, table, orc.resolutions(16),
-                                AABB_NP, valid=bone)
+    # reaches (on the dense levels each entry holds at most one corner of a
+    # sample, so sample 0's largest weight in a tile is that tile's largest
+    # record m, a lower bound of the chunk's)
     only_small = (w0 == 0) & (ref != 0)
     tile_of = np.arange(1 << log2T) >> 12
     m_tile = np.zeros((16, 4))
@@ -280,9 +297,10 @@ def test_table_grad_binned_mixed_magnitudes(orc, small):
     assert shared.any()
     rel = np.abs(got[shared] - ref[shared]) / np.abs(ref[shared])
     print(f"small={small:g}: {shared.sum()} small-only entries in tiles holding values near 1, relative error "
-          f"max {rel.max():.2e}, zero results {(got[shared] == 0).sum()}")
+          f"max {rel.max():.2e}, zero results {(got[shared] == 0).sum()}, atomic path zero results "
+          f"{(atom[shared] == 0).sum()}")
     dense = np.zeros_like(shared)
     dense[:2] = True
     below = shared & dense & (small < m_ent * 2.0 ** -48)  # every record of the entry is below m 2^-48
     if small < 1e-15:
-        assert below.any() and (got[below] == 0).all()
+        assert below.any() and (got[below] == 0).all() and (atom[below] != 0).all()

@@ -331,7 +331,22 @@ def frame_leg(args, params, fit_note, torch, np, K, synth, Pipeline, out, checks
     stepsmx = int(pmx.steps[:Smx].to(torch.int64).sum().item())
     fb = int(pmx.guided.n_fallback.item())
     used = int(pmx.n_used.to(torch.int64).sum().item())
+    keys = ("color", "opacity", "n_used", "T_final")
+    staged_out = {k: getattr(pmx, k).clone() for k in keys}
     del pmx
+    # the same frame through the persistent kernel (one pose of a batch):
+    # the same arithmetic, rays evaluated front to back up to termination
+    from paper_2212_10550_amd.batch import BatchRenderer
+    br = BatchRenderer([wf], params)
+    tune_p = br.autotune((), n=5, persistent=((16, 256, 4, 3), (8, 256, 4, 3), (12, 256, 4, 3), (32, 256, 4, 2)))
+    msp = br.time_ms(10)
+    br.render()
+    torch.cuda.synchronize()
+    pp = br.poses[0]
+    persistent = {"ms_per_frame": msp, "fps": 1e3 / msp, "schedule": br.schedule, "autotune_ms": tune_p,
+                  "samples_evaluated": int(pp.n_evaluated.item()), "fallback_samples": int(pp.n_fallback.item()),
+                  "outputs_bit_equal_staged": all(torch.equal(getattr(pp, k), staged_out[k]) for k in keys)}
+    del br, staged_out
     dmx = np.abs(cmx - c32)
     out["frame_540"] = {
         "workload": "540x540 rays, 128^3 occupancy (~10%), <=128 samples/ray, early termination at T < 1e-4, "
@@ -346,8 +361,10 @@ def frame_leg(args, params, fit_note, torch, np, K, synth, Pipeline, out, checks
                                                                     backward=False),
                                   "fallback_samples": fb,
                                   "pixel_diff_vs_f32_multi_init": {"mean": float(dmx.mean()),
-                                                                   "max": float(dmx.max())}},
+                                                                   "max": float(dmx.max())},
+                                  "persistent_kernel": persistent},
         "speedup_learned_mixed_vs_f32_multi": ms32 / msmx,
+        "speedup_persistent_mixed_vs_f32_multi": ms32 / msp,
         "initialiser_fit": fit_note,
         "paper_context": "the paper renders its avatars at ~15 FPS at 540x540 and reconstructs one in about 60 s, on "
                          "one RTX 3090 (Sec. 4.2, Tab. 3; context only, different workload and hardware)",
@@ -947,6 +964,55 @@ def counter_table(dirs, kernels=None):
     print("\n".join(lines))
 
 
+def kernel_stats(trace_dir, replay_of=None):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats folder: every
+    kernel's calls and durations (from its kernel_stats.csv) and, with
+    replay_of, the kernels of one launch sequence that starts with a kernel
+    of that name (one graph replay of a step or frame) with grid, start and
+    duration, from its kernel_trace.csv."""
+    import csv
+    import glob
+    out = []
+    if replay_of:
+        for fn in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+            with open(fn) as f:
+                rows = [(short_kernel_name(r["Kernel_Name"]), int(r["Grid_Size_X"]) if "Grid_Size_X" in r else
+                         int(r.get("Grid_Size", 0)), int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                        for r in csv.DictReader(f)]
+            rows.sort(key=lambda t: t[2])
+            starts = [i for i, r in enumerate(rows) if r[0].startswith(replay_of)] + [len(rows)]
+            seqs = [rows[a:b] for a, b in zip(starts[:-1], starts[1:])]
+            if not seqs:
+                continue
+            # the sequences with the most distinct kernels (whole steps or
+            # frames), and of those the one with the shortest span (a graph
+            # replay rather than an eagerly launched one)
+            most = max(len({k for k, *_ in q}) for q in seqs)
+            full = [q for q in seqs if len({k for k, *_ in q}) == most]
+            seq = min(full, key=lambda q: max(e for *_, e in q) - q[0][2])
+            t0 = seq[0][2]
+            out += [f"## One launch sequence starting with {replay_of} (the tightest of the {len(full)} with every "
+                    "kernel)", "", "| kernel | grid (work-items) | start us | duration us |", "|---|---|---|---|"]
+            tot = 0.0
+            for name, grid, st, en in seq:
+                tot += (en - st) / 1e3
+                out.append(f"| {name} | {grid} | {(st - t0) / 1e3:.1f} | {(en - st) / 1e3:.1f} |")
+            span = (max(e for _, _, _, e in seq) - t0) / 1e3
+            out += ["", f"Kernel time {tot:.1f} us over a {span:.1f} us span from the first kernel's start to the "
+                    "last one's end.", ""]
+            break
+    for fn in glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True):
+        with open(fn) as f:
+            rows = list(csv.DictReader(f))
+        out += ["## All kernels of the run", "", "| kernel | calls | avg us | min us | max us | % of GPU time |",
+                "|---|---|---|---|---|---|"]
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+            out.append(f"| {short_kernel_name(r['Name'])[:70]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                       f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+        break
+    print("\n".join(out))
+
+
 COPY_CAL_FLOATS = 256 << 20  # 1 GiB read and written (4x the 256 MB Infinity Cache)
 
 
@@ -980,7 +1046,14 @@ def main():
     ap.add_argument("--counter-table", nargs="+", metavar="PMC_DIR",
                     help="per-kernel mean of every counter in rocprofv3 --pmc folders (no GPU needed), then exit")
     ap.add_argument("--kernels", default=None, help="with --counter-table: comma-separated kernel-name filters")
+    ap.add_argument("--kernel-stats", metavar="TRACE_DIR",
+                    help="summarise a rocprofv3 --kernel-trace --stats folder (no GPU needed), then exit")
+    ap.add_argument("--replay-of", default=None,
+                    help="with --kernel-stats: list one launch sequence starting with this kernel name")
     args = ap.parse_args()
+    if args.kernel_stats:
+        kernel_stats(args.kernel_stats, args.replay_of)
+        return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
         return

@@ -301,9 +301,10 @@ __device__ inline void march_masks(const PoseDev &pd, const WaveMem &wm, int nr,
       for (int h = 0; h < 2; ++h) {
         const int k = lane + h * kWave;
         float t, x[3];
-        const bool kb = mch::sample_at<kPow2>(o, d, s, k, pd.box, pd.bits, pd.G, &t, x);
-        // a ray that misses the box has t_far = -inf: nothing is kept
-        keep[u][h] = k < pd.max_steps && kb && t < tf;
+        // a step past t_far is not kept, so its cell is not looked up (a ray
+        // that misses the box has t_far = -inf: nothing is kept)
+        keep[u][h] = k < pd.max_steps && mch::step_t(s, k) < tf &&
+                     mch::sample_at<kPow2>(o, d, s, k, pd.box, pd.bits, pd.G, &t, x) && t < tf;
       }
     }
 #pragma unroll

@@ -31,53 +31,71 @@ using namespace ia355::mch;
 
 namespace {
 
-// One wave per ray: lane l handles steps k = l, l + 64, ... of its ray, so a
-// 128-step ray is two ballots.  kRays rays per workgroup.
-constexpr int kRays = 4;
-constexpr int kBlock = kRays * kWave;
+// kRaysPerWave rays per wave, four waves per workgroup: lane l handles
+// steps k = l, l + 64, ... of each of the wave's rays, so a 128-step ray is
+// two ballots, and the occupancy loads of the wave's rays (two words at a
+// time) are in flight together.  Large ray counts take four rays per wave
+// (fewer, longer waves); small ones one ray per wave, which keeps enough
+// waves in flight.
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWavesPerBlock * kWave;
+constexpr int64_t kManyRays = 65536;  // from here on, four rays per wave
 
-template <bool kPow2Ext>
+__host__ __device__ inline int rays_per_wave(int64_t R) { return R >= kManyRays ? 4 : 1; }
+__host__ __device__ inline int rays_per_block(int64_t R) { return rays_per_wave(R) * kWavesPerBlock; }
+
+template <bool kPow2Ext, int kRaysPerWave>
 __global__ void __launch_bounds__(kBlock) march_count(const float *ro, const float *rd, int64_t R,
                                                       const uint32_t *bits, int G, Box box, float dt_fixed,
                                                       int n_per_ray, int max_steps, int64_t *ray_off,
                                                       int32_t *ray_cnt, float *ray_dt, int64_t *block_sum,
                                                       uint64_t *masks, int nw, float *ray_tn) {
+  constexpr int kRays = kRaysPerWave * kWavesPerBlock;
   __shared__ int cnts[kRays];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int64_t r = (int64_t)blockIdx.x * kRays + wid;
-  int cnt = 0;
-  if (r < R) {
-    float o[3], d[3];
-    load_ray(ro, rd, r, o, d);
-    const RaySpan s = ray_span(o, d, box, dt_fixed, n_per_ray);
-    uint64_t *mr = masks + r * nw;
-    int words = 0;  // mask words written; the rest are cleared below
-    if (s.hit) {
-      for (int k0 = 0; k0 < max_steps; k0 += kWave) {
-        const int k = k0 + lane;
-        float t = 0.0f, x[3];
-        bool keep = false, inside = false;
-        if (k < max_steps) {
-          keep = sample_at<kPow2Ext>(o, d, s, k, box, bits, G, &t, x);
-          inside = t < s.tf;
-          keep = keep && inside;
-        }
-        const uint64_t m = __ballot(keep);
-        cnt += __popcll(m);
-        if (lane == 0) mr[words] = m;
-        ++words;
-        // t grows with k: once the last lane is beyond t_far, so is every later step
-        if (!__shfl((int)inside, kWave - 1, kWave)) break;
-      }
-    }
-    for (int j = words + lane; j < nw; j += kWave) mr[j] = 0ull;
-    if (lane == 0) {
-      ray_cnt[r] = cnt;
-      ray_dt[r] = s.dt;
-      ray_tn[r] = s.tn;
-    }
+  const int64_t r0 = (int64_t)blockIdx.x * kRays + wid * kRaysPerWave;
+  float o[kRaysPerWave][3], d[kRaysPerWave][3];
+  RaySpan s[kRaysPerWave];
+#pragma unroll
+  for (int u = 0; u < kRaysPerWave; ++u) {
+    const int64_t r = r0 + u < R ? r0 + u : R - 1;  // a tail wave repeats the last ray, writes nothing for it
+    load_ray(ro, rd, r, o[u], d[u]);
+    s[u] = ray_span(o[u], d[u], box, dt_fixed, n_per_ray);
   }
-  if (lane == 0) cnts[wid] = cnt;
+  int cnt[kRaysPerWave];
+#pragma unroll
+  for (int u = 0; u < kRaysPerWave; ++u) cnt[u] = 0;
+  for (int w0 = 0; w0 < nw; w0 += 2) {
+    bool keep[kRaysPerWave][2];
+#pragma unroll
+    for (int u = 0; u < kRaysPerWave; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = (w0 + h) * kWave + lane;
+        float t = 0.0f, x[3];
+        keep[u][h] = false;
+        // a step past t_far is not kept, so its cell is not looked up
+        if (s[u].hit && k < max_steps && step_t(s[u], k) < s[u].tf)
+          keep[u][h] = sample_at<kPow2Ext>(o[u], d[u], s[u], k, box, bits, G, &t, x) && t < s[u].tf;
+      }
+#pragma unroll
+    for (int u = 0; u < kRaysPerWave; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint64_t m = __ballot(keep[u][h]);
+        cnt[u] += __popcll(m);
+        if (lane == 0 && r0 + u < R && w0 + h < nw) masks[(r0 + u) * nw + w0 + h] = m;
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < kRaysPerWave; ++u) {
+    if (lane == 0 && r0 + u < R) {
+      ray_cnt[r0 + u] = cnt[u];
+      ray_dt[r0 + u] = s[u].dt;
+      ray_tn[r0 + u] = s[u].tn;
+    }
+    if (lane == 0) cnts[wid * kRaysPerWave + u] = r0 + u < R ? cnt[u] : 0;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     int64_t acc = 0;
@@ -164,39 +182,55 @@ __global__ void __launch_bounds__(1024) march_scan_top(int64_t *chunk_sum, int64
   }
 }
 
+template <int kRaysPerWave>
 __global__ void __launch_bounds__(kBlock) march_fill(const float *ro, const float *rd, int64_t R,
                                                      const uint64_t *masks, int nw, const float *ray_tn,
                                                      const int64_t *block_off, const int64_t *chunk_off,
                                                      int64_t *ray_off, const float *ray_dt, float *xs, float *ts,
                                                      int32_t *ray_id, int64_t cap) {
 #pragma clang fp contract(off)
+  constexpr int kRays = kRaysPerWave * kWavesPerBlock;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int64_t r = (int64_t)blockIdx.x * kRays + wid;
-  if (r >= R) return;
-  int64_t off = ray_off[r] + block_off[blockIdx.x] + chunk_off[blockIdx.x / kScanChunk];
-  __builtin_amdgcn_wave_barrier();
-  if (lane == 0) ray_off[r] = off;
-  float o[3], d[3];
-  load_ray(ro, rd, r, o, d);
-  const float tn = ray_tn[r], dt = ray_dt[r];
-  const uint64_t *mr = masks + r * nw;
+  const int64_t r0 = (int64_t)blockIdx.x * kRays + wid * kRaysPerWave;
+  if (r0 >= R) return;
+  const int64_t base = block_off[blockIdx.x] + chunk_off[blockIdx.x / kScanChunk];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  for (int w = 0; w < nw; ++w) {
-    const uint64_t m = mr[w];
-    if (m == 0ull) continue;
-    if ((m >> lane) & 1ull) {
-      const int64_t at = off + __popcll(m & below);
-      if (at < cap) {
-        float t, x[3];
-        sample_pos(o, d, tn, dt, w * kWave + lane, &t, x);
-        xs[at] = x[0];
-        xs[cap + at] = x[1];
-        xs[2 * cap + at] = x[2];
-        ts[at] = t;
-        ray_id[at] = (int32_t)r;
+  // every ray's inputs first, so that their loads are in flight together
+  float o[kRaysPerWave][3], d[kRaysPerWave][3], tn[kRaysPerWave], dt[kRaysPerWave];
+  int64_t off[kRaysPerWave];
+#pragma unroll
+  for (int u = 0; u < kRaysPerWave; ++u) {
+    const int64_t r = r0 + u < R ? r0 + u : R - 1;
+    load_ray(ro, rd, r, o[u], d[u]);
+    tn[u] = ray_tn[r];
+    dt[u] = ray_dt[r];
+    off[u] = ray_off[r] + base;
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int u = 0; u < kRaysPerWave; ++u) {
+    const int64_t r = r0 + u;
+    if (r >= R) break;
+    if (lane == 0) ray_off[r] = off[u];
+    const uint64_t *mr = masks + r * nw;
+    int64_t at0 = off[u];
+    for (int w = 0; w < nw; ++w) {
+      const uint64_t m = mr[w];
+      if (m == 0ull) continue;
+      if ((m >> lane) & 1ull) {
+        const int64_t at = at0 + __popcll(m & below);
+        if (at < cap) {
+          float t, x[3];
+          sample_pos(o[u], d[u], tn[u], dt[u], w * kWave + lane, &t, x);
+          xs[at] = x[0];
+          xs[cap + at] = x[1];
+          xs[2 * cap + at] = x[2];
+          ts[at] = t;
+          ray_id[at] = (int32_t)r;
+        }
       }
+      at0 += __popcll(m);
     }
-    off += __popcll(m);
   }
 }
 
@@ -213,7 +247,7 @@ struct MarchWs {
 
 static MarchWs march_ws(void *base, int64_t R, int32_t max_steps) {
   const int64_t Rp = R > 0 ? R : 1;
-  const int64_t nblk = ceil_div(Rp, kRays);
+  const int64_t nblk = ceil_div(Rp, rays_per_block(Rp));
   const int64_t nw = ceil_div(max_steps > 0 ? max_steps : 1, kWave);
   char *p = (char *)base;
   MarchWs w;
@@ -252,26 +286,40 @@ extern "C" int32_t ia355_occgrid_march(const float *rays_o, const float *rays_d,
   bool pow2;
   if (!make_box(aabb, &box, &pow2)) return IA355_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
-  const int64_t nblk = ceil_div(R, kRays);
+  const int64_t nblk = ceil_div(R, rays_per_block(R));
   const int64_t nchunk = ceil_div(nblk, kScanChunk);
   const int nw = (int)ceil_div(max_steps, kWave);
   const MarchWs mw = march_ws(ws, R, max_steps);
   int64_t *block_sum = mw.block_sum, *chunk_sum = mw.chunk_sum;
+  const bool many = rays_per_wave(R) == 4;
   if (R > 0) {
-    if (pow2)
-      march_count<true><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray,
-                                                          max_steps, ray_off, ray_cnt, ray_dt, block_sum,
-                                                          mw.masks, nw, mw.tn);
+    if (pow2 && many)
+      march_count<true, 4><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray,
+                                                             max_steps, ray_off, ray_cnt, ray_dt, block_sum,
+                                                             mw.masks, nw, mw.tn);
+    else if (pow2)
+      march_count<true, 1><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray,
+                                                             max_steps, ray_off, ray_cnt, ray_dt, block_sum,
+                                                             mw.masks, nw, mw.tn);
+    else if (many)
+      march_count<false, 4><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray,
+                                                              max_steps, ray_off, ray_cnt, ray_dt, block_sum,
+                                                              mw.masks, nw, mw.tn);
     else
-      march_count<false><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray,
-                                                           max_steps, ray_off, ray_cnt, ray_dt, block_sum,
-                                                           mw.masks, nw, mw.tn);
+      march_count<false, 1><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, occ_bits, G, box, dt, n_per_ray,
+                                                              max_steps, ray_off, ray_cnt, ray_dt, block_sum,
+                                                              mw.masks, nw, mw.tn);
     march_scan_chunk<<<(unsigned)nchunk, 1024, 0, s>>>(block_sum, nblk, chunk_sum, ray_off, R, n_samples);
   }
   if (nchunk != 1) march_scan_top<<<1, 1024, 0, s>>>(chunk_sum, nchunk, ray_off, R, n_samples);
-  if (R > 0 && cap > 0)
-    march_fill<<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, mw.masks, nw, mw.tn, block_sum, chunk_sum,
-                                                 ray_off, ray_dt, xs, ts, ray_id, cap);
+  if (R > 0 && cap > 0) {
+    if (many)
+      march_fill<4><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, mw.masks, nw, mw.tn, block_sum, chunk_sum,
+                                                      ray_off, ray_dt, xs, ts, ray_id, cap);
+    else
+      march_fill<1><<<(unsigned)nblk, kBlock, 0, s>>>(rays_o, rays_d, R, mw.masks, nw, mw.tn, block_sum, chunk_sum,
+                                                      ray_off, ray_dt, xs, ts, ray_id, cap);
+  }
   const int32_t st = launch_status();
   if (st != IA355_OK || !n_required) return st;
   // synchronous capacity check, on request only

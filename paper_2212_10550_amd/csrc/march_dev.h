@@ -47,6 +47,12 @@ __device__ __forceinline__ RaySpan ray_span(const float o[3], const float d[3], 
   return s;
 }
 
+// Ray parameter of step k: the midpoint of the k-th interval.
+__device__ __forceinline__ float step_t(const RaySpan &s, int k) {
+#pragma clang fp contract(off)
+  return s.tn + ((float)k + 0.5f) * s.dt;
+}
+
 // Sample k of a ray: position and whether its cell is occupied.
 // kPow2Ext: every box extent is a power of two, so dividing by it and
 // multiplying by its (exact) reciprocal round the same real number once and
@@ -55,7 +61,7 @@ template <bool kPow2Ext>
 __device__ __forceinline__ bool sample_at(const float o[3], const float d[3], const RaySpan &s, int k, const Box &b,
                                           const uint32_t *bits, int G, float *t_out, float x[3]) {
 #pragma clang fp contract(off)
-  const float t = s.tn + ((float)k + 0.5f) * s.dt;
+  const float t = step_t(s, k);
   *t_out = t;
   int cell[3];
 #pragma unroll

@@ -93,6 +93,8 @@ __device__ __forceinline__ void fwd32(const Frag32 &f, const float X[8], f32x4 z
 }
 
 constexpr int kFwdBlock = 256;
+constexpr int kFwdPre = 4;    // tiles whose features are in flight per wave (BF16)
+constexpr int kFwdPre32 = 2;  // the same for FP32 features (eight registers a tile)
 
 __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_f32(const float *__restrict__ feat,
                                                          const int16_t *__restrict__ bone, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
@@ -110,30 +112,47 @@ __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_f32(const float *__restrict
   if ((int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6) >= ntile) return;
   Frag32 f;
   load_frag32(sP, r, g, f);
-  // the next tile's features are loaded while this one computes
-  int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6);
-  float Xn[8];
-  load_x(feat, ld, tile * 16 + r, g, tile * 16 + r < S, Xn);
-  for (; tile < ntile; tile += wstride) {
-    const int64_t s = tile * 16 + r;
-    const bool ok = s < S;
-    float X[8];
+  // the features and bone of the next kFwdPre32 tiles of this wave are in
+  // flight while a tile computes (a tile's MFMA chain is far shorter than
+  // a load's latency)
+  const int64_t tile0 = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6);
+  float Xq[kFwdPre32][8];
+  int Bq[kFwdPre32];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) X[c] = Xn[c];
-    const int64_t sn = (tile + wstride) * 16 + r;
-    load_x(feat, ld, sn, g, tile + wstride < ntile && sn < S, Xn);
-    f32x4 z1[4], z2[4], o;
-    fwd32(f, X, z1, z2, o);
-    if (g == 0 && ok) {
-      float sg = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
-      if (!bone || bone[s] >= 0) {
-        const float ov[4] = {o[0], o[1], o[2], o[3]};
-        head(ov, &sg, c);
+  for (int u = 0; u < kFwdPre32; ++u) {
+    const int64_t su = (tile0 + u * wstride) * 16 + r;
+    const bool okn = tile0 + u * wstride < ntile && su < S;
+    load_x(feat, ld, su, g, okn, Xq[u]);
+    Bq[u] = okn && bone && g == 0 ? bone[su] : 0;
+  }
+  for (int64_t tile = tile0; tile < ntile; tile += kFwdPre32 * wstride) {
+#pragma unroll
+    for (int u = 0; u < kFwdPre32; ++u) {
+      const int64_t tu = tile + u * wstride;
+      if (tu >= ntile) break;
+      const int64_t s = tu * 16 + r;
+      const bool ok = s < S;
+      float X[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) X[c] = Xq[u][c];
+      const int bn = Bq[u];
+      const int64_t tn = tu + kFwdPre32 * wstride, sn = tn * 16 + r;
+      const bool okn = tn < ntile && sn < S;
+      load_x(feat, ld, sn, g, okn, Xq[u]);
+      Bq[u] = okn && bone && g == 0 ? bone[sn] : 0;
+      f32x4 z1[4], z2[4], o;
+      fwd32(f, X, z1, z2, o);
+      if (g == 0 && ok) {
+        float sg = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
+        if (!bone || bn >= 0) {
+          const float ov[4] = {o[0], o[1], o[2], o[3]};
+          head(ov, &sg, c);
+        }
+        sigma[s] = sg;
+        rgb[s] = c[0];
+        rgb[ld + s] = c[1];
+        rgb[2 * ld + s] = c[2];
       }
-      sigma[s] = sg;
-      rgb[s] = c[0];
-      rgb[ld + s] = c[1];
-      rgb[2 * ld + s] = c[2];
     }
   }
 }
@@ -153,27 +172,44 @@ __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_bf16(const __hip_bfloat16 *
   if ((int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6) >= ntile) return;
   FragBf f;
   load_frag_bf(sP, r, g, f);
-  // the next tile's features are loaded while this one computes
-  int64_t tile = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6);
-  bf16x8 Xn = load_x_bf16(feat, ld, tile * 16 + r, g, tile * 16 + r < S);
-  for (; tile < ntile; tile += wstride) {
-    const int64_t s = tile * 16 + r;
-    const bool ok = s < S;
-    const bf16x8 X = Xn;
-    const int64_t sn = (tile + wstride) * 16 + r;
-    Xn = load_x_bf16(feat, ld, sn, g, tile + wstride < ntile && sn < S);
-    f32x4 z1[4], z2[4], o;
-    fwd_bf(f, X, z1, z2, o);
-    if (g == 0 && ok) {
-      float sg = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
-      if (!bone || bone[s] >= 0) {
-        const float ov[4] = {o[0], o[1], o[2], o[3]};
-        head(ov, &sg, c);
+  // the features and bone of the next kFwdPre tiles of this wave are in
+  // flight while a tile computes
+  const int64_t tile0 = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6);
+  bf16x8 Xq[kFwdPre];
+  int Bq[kFwdPre];
+#pragma unroll
+  for (int u = 0; u < kFwdPre; ++u) {
+    const int64_t su = (tile0 + u * wstride) * 16 + r;
+    const bool okn = tile0 + u * wstride < ntile && su < S;
+    Xq[u] = load_x_bf16(feat, ld, su, g, okn);
+    Bq[u] = okn && bone && g == 0 ? bone[su] : 0;
+  }
+  for (int64_t tile = tile0; tile < ntile; tile += kFwdPre * wstride) {
+#pragma unroll
+    for (int u = 0; u < kFwdPre; ++u) {
+      const int64_t tu = tile + u * wstride;
+      if (tu >= ntile) break;
+      const int64_t s = tu * 16 + r;
+      const bool ok = s < S;
+      const bf16x8 X = Xq[u];
+      const int bn = Bq[u];
+      const int64_t tn = tu + kFwdPre * wstride, sn = tn * 16 + r;
+      const bool okn = tn < ntile && sn < S;
+      Xq[u] = load_x_bf16(feat, ld, sn, g, okn);
+      Bq[u] = okn && bone && g == 0 ? bone[sn] : 0;
+      f32x4 z1[4], z2[4], o;
+      fwd_bf(f, X, z1, z2, o);
+      if (g == 0 && ok) {
+        float sg = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
+        if (!bone || bn >= 0) {
+          const float ov[4] = {o[0], o[1], o[2], o[3]};
+          head(ov, &sg, c);
+        }
+        sigma[s] = sg;
+        rgb[s] = c[0];
+        rgb[ld + s] = c[1];
+        rgb[2 * ld + s] = c[2];
       }
-      sigma[s] = sg;
-      rgb[s] = c[0];
-      rgb[ld + s] = c[1];
-      rgb[2 * ld + s] = c[2];
     }
   }
 }

@@ -16,8 +16,8 @@ def test_occ_words_is_whole_bricks():
 
 
 def test_march_workspace_covers_masks_and_scan():
-    for R, steps in ((1, 1), (8192, 128), (291600, 128), (1166400, 128), (1000, 300)):
-        nblk = -(-R // 4)
+    for R, steps in ((1, 1), (8192, 128), (291600, 128), (1166400, 128), (1000, 300), (65535, 128), (65536, 128)):
+        nblk = -(-R // (16 if R >= 65536 else 4))  # rays per workgroup: 4 per wave from 65536 rays, else 1
         need = 8 * nblk + 8 * (-(-nblk // 4096)) + 8 * R * (-(-steps // 64)) + 4 * R
         assert K.march_workspace_size(R, steps) >= need
     assert K.march_workspace_size(-1, 128) == 0 and K.march_workspace_size(10, -1) == 0

@@ -990,6 +990,12 @@ def kernel_stats(trace_dir, replay_of=None):
             most = max(len({k for k, *_ in q}) for q in seqs)
             full = [q for q in seqs if len({k for k, *_ in q}) == most]
             seq = min(full, key=lambda q: max(e for *_, e in q) - q[0][2])
+            # cut at the first idle gap over 50 us (the launches that follow
+            # belong to other work)
+            for j in range(1, len(seq)):
+                if seq[j][2] - max(e for *_, e in seq[:j]) > 50_000:
+                    seq = seq[:j]
+                    break
             t0 = seq[0][2]
             out += [f"## One launch sequence starting with {replay_of} (the tightest of the {len(full)} with every "
                     "kernel)", "", "| kernel | grid (work-items) | start us | duration us |", "|---|---|---|---|"]

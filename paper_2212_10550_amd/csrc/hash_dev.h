@@ -114,7 +114,10 @@ __device__ __forceinline__ float2 load_feat2(const __half *t, uint32_t i) {
 // of which half was used.  Values are unchanged.
 __device__ __forceinline__ float2 h2f(uint32_t a) { return __half22float2(__builtin_bit_cast(__half2, a)); }
 
-// FP16 table (4-byte entries).
+// FP16 table (4-byte entries).  The second corner's own load (non-adjacent
+// pairs only) sits alone in its branch and both corners are picked after it,
+// so no branch waits for a load: the pairs' loads of a cell, and of the
+// levels a lane holds, are in flight together.
 __device__ __forceinline__ void gather_pair(const __half *t, uint32_t i0, uint32_t i1, float2 &v0, float2 &v1) {
   const uint32_t *t32 = reinterpret_cast<const uint32_t *>(t);
   const bool adj = i1 == i0 + 1u || i0 == i1 + 1u;
@@ -122,16 +125,14 @@ __device__ __forceinline__ void gather_pair(const __half *t, uint32_t i0, uint32
   const uint32_t base = adj ? lo : (i0 & ~1u);
   uint2 q;
   __builtin_memcpy(&q, t32 + base, 8);
-  if (adj) {
-    v0 = h2f(i0 == lo ? q.x : q.y);
-    v1 = h2f(i0 == lo ? q.y : q.x);
-  } else {
-    v0 = h2f((i0 & 1u) ? q.y : q.x);
-    v1 = h2f(t32[i1]);
-  }
+  uint32_t e1 = 0u;
+  if (!adj) e1 = t32[i1];
+  const bool first = adj ? i0 == lo : (i0 & 1u) == 0u;
+  v0 = h2f(first ? q.x : q.y);
+  v1 = h2f(adj ? (first ? q.y : q.x) : e1);
 }
 
-// FP32 table (8-byte entries).
+// FP32 table (8-byte entries), the same scheme.
 __device__ __forceinline__ void gather_pair(const float *t, uint32_t i0, uint32_t i1, float2 &v0, float2 &v1) {
   const float2 *t2 = reinterpret_cast<const float2 *>(t);
   const bool adj = i1 == i0 + 1u || i0 == i1 + 1u;
@@ -139,13 +140,11 @@ __device__ __forceinline__ void gather_pair(const float *t, uint32_t i0, uint32_
   const uint32_t base = adj ? lo : (i0 & ~1u);
   float4 q;
   __builtin_memcpy(&q, t2 + base, 16);
-  if (adj) {
-    v0 = (i0 == lo) ? make_float2(q.x, q.y) : make_float2(q.z, q.w);
-    v1 = (i0 == lo) ? make_float2(q.z, q.w) : make_float2(q.x, q.y);
-  } else {
-    v0 = (i0 & 1u) ? make_float2(q.z, q.w) : make_float2(q.x, q.y);
-    v1 = t2[i1];
-  }
+  float2 e1 = make_float2(0.0f, 0.0f);
+  if (!adj) e1 = t2[i1];
+  const bool first = adj ? i0 == lo : (i0 & 1u) == 0u;
+  v0 = first ? make_float2(q.x, q.y) : make_float2(q.z, q.w);
+  v1 = adj ? (first ? make_float2(q.z, q.w) : make_float2(q.x, q.y)) : e1;
 }
 
 // The eight corner values of a cell (table of one level, 16-byte aligned,

@@ -30,31 +30,71 @@ namespace {
 
 constexpr int kFwdBlock = 256;
 
-// Block b works for XCD b % 8 on level (b % 8) + 8 * (slot % per_xcd) with
-// slot = b / 8, on 256-sample chunks slot / per_xcd, + nslot, + 2 nslot ...
-template <typename TT, typename FT>
+// Block b works for XCD b % 8 on the kLv levels (b % 8) + 8 (kLv g + t),
+// t < kLv, of level group g = slot % ngroup (slot = b / 8), on 256-sample
+// chunks slot / ngroup, + nslot, + 2 nslot ...  A lane reads its sample's
+// position and bone once for its kLv levels and has all their corner gathers
+// in flight together.
+template <typename TT, typename FT, int kLv>
 __global__ void __launch_bounds__(kFwdBlock) encode_kernel(const float *__restrict__ xc, const int16_t *__restrict__ bone,
                                                            int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                            const TT *__restrict__ table, int L, int log2T, Levels lv,
-                                                           Box box, FT *__restrict__ feat, int per_xcd) {
+                                                           Box box, FT *__restrict__ feat, int ngroup) {
   const int xcd = blockIdx.x % kXcd;
   const int slot = blockIdx.x / kXcd;
-  const int level = xcd + kXcd * (slot % per_xcd);
-  if (level >= L) return;
+  const int level0 = xcd + kXcd * kLv * (slot % ngroup);
+  if (level0 >= L) return;
   const int64_t Sn = count_of(S, S_dev);
-  const int64_t nslot = gridDim.x / (kXcd * per_xcd);
+  const int64_t nslot = gridDim.x / (kXcd * ngroup);
   const uint32_t T = 1u << log2T;
-  const TT *tl = table + (int64_t)level * T * 2;
-  for (int64_t chunk = slot / per_xcd; chunk * kFwdBlock < Sn; chunk += nslot) {
+  for (int64_t chunk = slot / ngroup; chunk * kFwdBlock < Sn; chunk += nslot) {
     const int64_t n = chunk * kFwdBlock + threadIdx.x;
     if (n >= Sn) break;
-    float a = 0.0f, b = 0.0f;
+    float a[kLv], b[kLv];
+#pragma unroll
+    for (int t = 0; t < kLv; ++t) a[t] = b[t] = 0.0f;
+    // position and bone loaded together (one round trip)
+    const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
     if (!bone || bone[n] >= 0) {
-      const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
-      encode_level(x, box, lv.res[level], lv.dense[level], T - 1u, tl, &a, &b);
+#pragma unroll
+      for (int t = 0; t < kLv; ++t) {
+        const int level = level0 + kXcd * t;
+        if (level < L)
+          encode_level(x, box, lv.res[level], lv.dense[level], T - 1u, table + (int64_t)level * T * 2, &a[t], &b[t]);
+      }
     }
-    store_feat2(feat, (int64_t)level * ld + n, a, b);
+#pragma unroll
+    for (int t = 0; t < kLv; ++t) {
+      const int level = level0 + kXcd * t;
+      if (level < L) store_feat2(feat, (int64_t)level * ld + n, a[t], b[t]);
+    }
   }
+}
+
+struct EncodeArgs {
+  const float *xc;
+  const int16_t *bone;
+  int64_t S;
+  const int64_t *S_dev;
+  int64_t ld;
+  const void *table;
+  int L, log2T;
+  Levels lv;
+  Box box;
+  void *feat;
+  int ngroup;
+};
+
+template <typename TT, typename FT>
+void launch_encode(const EncodeArgs &a, int lv_lane, unsigned g, hipStream_t s) {
+  const TT *t = static_cast<const TT *>(a.table);
+  FT *f = static_cast<FT *>(a.feat);
+  if (lv_lane == 2)
+    encode_kernel<TT, FT, 2><<<g, kFwdBlock, 0, s>>>(a.xc, a.bone, a.S, a.S_dev, a.ld, t, a.L, a.log2T, a.lv, a.box, f,
+                                                     a.ngroup);
+  else
+    encode_kernel<TT, FT, 1><<<g, kFwdBlock, 0, s>>>(a.xc, a.bone, a.S, a.S_dev, a.ld, t, a.L, a.log2T, a.lv, a.box, f,
+                                                     a.ngroup);
 }
 
 // Position gradient dL/dx = sum_l sum_c (grad w_c) (theta_c . dL/dfeat_l),
@@ -755,26 +795,26 @@ extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, i
   if (make_levels(L, log2T, base_res, growth, &lv) || make_box(aabb, &box)) return IA355_ERR_INVALID_ARG;
   if (S == 0) return IA355_OK;
   const int per_xcd = (L + kXcd - 1) / kXcd;
-  // chunk slots per (XCD, level slot); with a device count at most 1024 per
-  // level, the blocks loop over the rest (blocks past the count exit at once)
+  // two levels per lane where an XCD serves several levels
+  const int lv_lane = per_xcd >= 2 ? 2 : 1;
+  const int ngroup = (per_xcd + lv_lane - 1) / lv_lane;
+  // chunk slots per (XCD, level group); with a device count at most 1024 per
+  // group, the blocks loop over the rest (blocks past the count exit at once)
   int64_t nslot = ceil_div(S, kFwdBlock);
   if (S_dev && nslot > 1024) nslot = 1024;
-  const int64_t blocks = nslot * per_xcd * kXcd;
+  const int64_t blocks = nslot * ngroup * kXcd;
   if (blocks > 0x7fffffffLL) return IA355_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
   const unsigned g = (unsigned)blocks;
+  const EncodeArgs ea{xc, bone, S, S_dev, ld, table, L, log2T, lv, box, feat, ngroup};
   if (table_dtype == IA355_F32 && feat_dtype == IA355_F32)
-    encode_kernel<float, float><<<g, kFwdBlock, 0, s>>>(xc, bone, S, S_dev, ld, (const float *)table, L, log2T, lv,
-                                                        box, (float *)feat, per_xcd);
+    launch_encode<float, float>(ea, lv_lane, g, s);
   else if (table_dtype == IA355_F32)
-    encode_kernel<float, __hip_bfloat16><<<g, kFwdBlock, 0, s>>>(xc, bone, S, S_dev, ld, (const float *)table, L,
-                                                                 log2T, lv, box, (__hip_bfloat16 *)feat, per_xcd);
+    launch_encode<float, __hip_bfloat16>(ea, lv_lane, g, s);
   else if (feat_dtype == IA355_F32)
-    encode_kernel<__half, float><<<g, kFwdBlock, 0, s>>>(xc, bone, S, S_dev, ld, (const __half *)table, L, log2T, lv,
-                                                         box, (float *)feat, per_xcd);
+    launch_encode<__half, float>(ea, lv_lane, g, s);
   else
-    encode_kernel<__half, __hip_bfloat16><<<g, kFwdBlock, 0, s>>>(xc, bone, S, S_dev, ld, (const __half *)table, L,
-                                                                  log2T, lv, box, (__hip_bfloat16 *)feat, per_xcd);
+    launch_encode<__half, __hip_bfloat16>(ea, lv_lane, g, s);
   return launch_status();
 }
 

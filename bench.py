@@ -969,14 +969,52 @@ def counter_table(dirs, kernels=None):
                     per.setdefault(k, {}).setdefault(key, 0.0)
                     per[k][key] += float(row["Counter_Value"])
     cols = sorted(names)
-    lines = ["| kernel | " + " | ".join(cols) + " |", "|---" * (len(cols) + 1) + "|"]
+    means = {}
+    lines = ["## Every counter, per kernel (means over dispatches)", "",
+             "| kernel | " + " | ".join(cols) + " |", "|---" * (len(cols) + 1) + "|"]
     for k in sorted(per):
         vals = []
         for c in cols:
             v = [val for (fn, did, cc), val in per[k].items() if cc == c]
-            vals.append(f"{sum(v) / len(v):.4g}" if v else "")
+            if v:
+                means[(k, c)] = sum(v) / len(v)
+            vals.append(f"{means[(k, c)]:.4g}" if v else "")
         lines.append(f"| {k} | " + " | ".join(vals) + " |")
-    print("\n".join(lines))
+    print("\n".join(derived_counters(sorted(per), means) + [""] + lines))
+
+
+def derived_counters(kernels, means):
+    """Derived per-kernel figures from counter means (MI355X: 256 CUs in 8
+    XCDs, 4 SIMDs per CU).  GRBM_GUI_ACTIVE is the sum of the 8 XCDs'
+    busy-cycle counts (their ratio to a kernel's timed duration at 2.4 GHz
+    is 8), so a dispatch lasts GRBM_GUI_ACTIVE / 8 cycles; the texture
+    address (TA) and data (TD) units are one per CU, MFMA busy cycles are
+    counted per SIMD."""
+    def m(k, c):
+        return means.get((k, c))
+
+    def ratio(a, b, scale=1.0):
+        return None if a is None or not b else a / (b * scale)
+
+    out = ["## Derived per kernel", "",
+           "| kernel | cycles per dispatch | TA busy | TD busy | TA cycles per vector-memory read | L1 hit rate | "
+           "L2 hit rate | MFMA busy | vector-memory reads per wave | VALU per wave |",
+           "|---|---|---|---|---|---|---|---|---|---|"]
+    for k in kernels:
+        g = m(k, "GRBM_GUI_ACTIVE")
+        cyc = g / 8 if g else None
+        hit, miss = m(k, "TCC_HIT_sum"), m(k, "TCC_MISS_sum")
+        acc, req = m(k, "TCP_TOTAL_CACHE_ACCESSES_sum"), m(k, "TCP_TCC_READ_REQ_sum")
+        waves = m(k, "SQ_WAVES")
+        row = [cyc, ratio(m(k, "TA_TA_BUSY_sum"), cyc, 256), ratio(m(k, "TD_TD_BUSY_sum"), cyc, 256),
+               ratio(m(k, "TA_TA_BUSY_sum"), m(k, "SQ_INSTS_VMEM_RD")),
+               None if not acc or req is None else 1.0 - req / acc,
+               None if hit is None or miss is None or hit + miss == 0 else hit / (hit + miss),
+               ratio(m(k, "SQ_VALU_MFMA_BUSY_CYCLES"), cyc, 1024),
+               ratio(m(k, "SQ_INSTS_VMEM_RD"), waves), ratio(m(k, "SQ_INSTS_VALU"), waves)]
+        fmt = ["{:.4g}", "{:.2f}", "{:.2f}", "{:.1f}", "{:.3f}", "{:.3f}", "{:.3f}", "{:.1f}", "{:.0f}"]
+        out.append(f"| {k} | " + " | ".join("" if v is None else f.format(v) for v, f in zip(row, fmt)) + " |")
+    return out
 
 
 def kernel_stats(trace_dir, replay_of=None):

@@ -106,43 +106,76 @@ void launch_encode(const EncodeArgs &a, int lv_lane, unsigned g, hipStream_t s) 
 constexpr int kBwdBlock = 256;
 constexpr int kBwdMaxLevels = 16;  // the backward's level limit
 
-template <typename TT>
+template <typename TT, int kLv>
 __global__ void __launch_bounds__(kBwdBlock) xgrad_level_kernel(
     const float *__restrict__ gfeat, const float *__restrict__ xc, const int16_t *__restrict__ bone, int64_t S,
     const int64_t *__restrict__ S_dev, int64_t ld, const TT *__restrict__ table, int L, int log2T, Levels lv, Box box,
-    float *__restrict__ part, int per_xcd) {
+    float *__restrict__ part, int ngroup) {
+  // the encode's mapping: kLv levels (b % 8) + 8 (kLv g + t) per lane
   const int xcd = blockIdx.x % kXcd;
   const int slot = blockIdx.x / kXcd;
-  const int level = xcd + kXcd * (slot % per_xcd);
-  if (level >= L) return;
+  const int level0 = xcd + kXcd * kLv * (slot % ngroup);
+  if (level0 >= L) return;
   const int64_t Sn = count_of(S, S_dev);
-  const int64_t nslot = gridDim.x / (kXcd * per_xcd);
+  const int64_t nslot = gridDim.x / (kXcd * ngroup);
   const uint32_t T = 1u << log2T;
-  const TT *tl = table + (int64_t)level * T * 2;
-  float *pl = part + (int64_t)level * 3 * S;
-  for (int64_t chunk = slot / per_xcd; chunk * kBwdBlock < Sn; chunk += nslot) {
+  for (int64_t chunk = slot / ngroup; chunk * kBwdBlock < Sn; chunk += nslot) {
     const int64_t n = chunk * kBwdBlock + threadIdx.x;
     if (n >= Sn) break;
-    float gx[3] = {0.0f, 0.0f, 0.0f};
-    if (!bone || bone[n] >= 0) {
-      const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
-      const float2 g = reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * ld + n];
-      Corners c;
-      level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c, true);
-      float2 vv[8];
-      gather8(tl, c, vv);
+    float gx[kLv][3];
+    float2 g[kLv];
+    // position, incoming gradients and bone loaded together (one round trip)
+    const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const float d = vv[k].x * g.x + vv[k].y * g.y;
-        gx[0] += c.dw[k][0] * d;
-        gx[1] += c.dw[k][1] * d;
-        gx[2] += c.dw[k][2] * d;
-      }
+    for (int t = 0; t < kLv; ++t) {
+      const int level = level0 + kXcd * t;
+      g[t] = level < L ? reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * ld + n] : make_float2(0.0f, 0.0f);
+      gx[t][0] = gx[t][1] = gx[t][2] = 0.0f;
     }
-    pl[n] = gx[0];
-    pl[S + n] = gx[1];
-    pl[2 * S + n] = gx[2];
+    if (!bone || bone[n] >= 0) {
+      // every level's gathers first, then the sums (a level past L repeats
+      // level0 with a zero gradient and is not stored)
+      Corners c[kLv];
+      float2 vv[kLv][8];
+#pragma unroll
+      for (int t = 0; t < kLv; ++t) {
+        const int level = level0 + kXcd * t < L ? level0 + kXcd * t : level0;
+        level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c[t], true);
+        gather8(table + (int64_t)level * T * 2, c[t], vv[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < kLv; ++t)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float d = vv[t][k].x * g[t].x + vv[t][k].y * g[t].y;
+          gx[t][0] += c[t].dw[k][0] * d;
+          gx[t][1] += c[t].dw[k][1] * d;
+          gx[t][2] += c[t].dw[k][2] * d;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kLv; ++t) {
+      const int level = level0 + kXcd * t;
+      if (level >= L) continue;
+      float *pl = part + (int64_t)level * 3 * S;
+      pl[n] = gx[t][0];
+      pl[S + n] = gx[t][1];
+      pl[2 * S + n] = gx[t][2];
+    }
   }
+}
+
+template <typename TT>
+void launch_xgrad(int lv_lane, unsigned blocks, hipStream_t s, const float *gfeat, const float *xc,
+                  const int16_t *bone, int64_t S, const int64_t *S_dev, int64_t ld, const void *table, int L, int log2T,
+                  const Levels &lv, const Box &box, float *part, int ngroup) {
+  const TT *t = static_cast<const TT *>(table);
+  if (lv_lane == 2)
+    xgrad_level_kernel<TT, 2><<<blocks, kBwdBlock, 0, s>>>(gfeat, xc, bone, S, S_dev, ld, t, L, log2T, lv, box, part,
+                                                           ngroup);
+  else
+    xgrad_level_kernel<TT, 1><<<blocks, kBwdBlock, 0, s>>>(gfeat, xc, bone, S, S_dev, ld, t, L, log2T, lv, box, part,
+                                                           ngroup);
 }
 
 __global__ void __launch_bounds__(kBwdBlock) xgrad_sum_kernel(const float *__restrict__ part, int64_t S,
@@ -872,18 +905,18 @@ extern "C" int32_t ia355_hashgrid_encode_bwd(const float *grad_feat, const float
   if (grad_xc && S > 0) {
     float *part = (float *)ws;
     const int per_xcd = (L + kXcd - 1) / kXcd;
+    const int lv_lane = per_xcd >= 2 ? 2 : 1;
+    const int ngroup = (per_xcd + lv_lane - 1) / lv_lane;
     int64_t nslot = ceil_div(S, kBwdBlock);
     if (dev && nslot > 1024) nslot = 1024;
-    const int64_t blocks = nslot * per_xcd * kXcd;
+    const int64_t blocks = nslot * ngroup * kXcd;
     if (blocks > 0x7fffffffLL) return IA355_ERR_INVALID_ARG;
     if (table_dtype == IA355_F32)
-      xgrad_level_kernel<float><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, S_dev, ld,
-                                                                       (const float *)table, L, log2T, lv, box, part,
-                                                                       per_xcd);
+      launch_xgrad<float>(lv_lane, (unsigned)blocks, s, grad_feat, xc, bone, S, S_dev, ld, table, L, log2T, lv, box,
+                          part, ngroup);
     else
-      xgrad_level_kernel<__half><<<(unsigned)blocks, kBwdBlock, 0, s>>>(grad_feat, xc, bone, S, S_dev, ld,
-                                                                        (const __half *)table, L, log2T, lv, box,
-                                                                        part, per_xcd);
+      launch_xgrad<__half>(lv_lane, (unsigned)blocks, s, grad_feat, xc, bone, S, S_dev, ld, table, L, log2T, lv, box,
+                           part, ngroup);
     xgrad_sum_kernel<<<stride_grid(ceil_div(S, kBwdBlock), dev, 1024), kBwdBlock, 0, s>>>(part, S, S_dev, L, ld,
                                                                                            grad_xc);
   }

@@ -93,7 +93,7 @@ __device__ __forceinline__ void fwd32(const Frag32 &f, const float X[8], f32x4 z
 }
 
 constexpr int kFwdBlock = 256;
-constexpr int kFwdPre = 4;    // tiles whose features are in flight per wave (BF16)
+constexpr int kFwdPre = 2;    // tiles whose features are in flight per wave (BF16)
 constexpr int kFwdPre32 = 2;  // the same for FP32 features (eight registers a tile)
 
 __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_f32(const float *__restrict__ feat,
@@ -157,21 +157,21 @@ __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_f32(const float *__restrict
   }
 }
 
-__global__ void __launch_bounds__(kFwdBlock) mlp_fwd_bf16(const __hip_bfloat16 *__restrict__ feat,
+__global__ void __launch_bounds__(kFwdBlock, 4) mlp_fwd_bf16(const __hip_bfloat16 *__restrict__ feat,
                                                           const int16_t *__restrict__ bone, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                           const float *__restrict__ P, float *__restrict__ sigma,
                                                           float *__restrict__ rgb) {
-  __shared__ __attribute__((aligned(16))) float sP[NPARAM];
+  __shared__ __attribute__((aligned(16))) FragLds sF;
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
   S = count_of(S, S_dev);
   const int64_t ntile = ceil_div(S, 16);
   const int64_t wstride = (int64_t)gridDim.x * (kFwdBlock / 64);
   if ((int64_t)blockIdx.x * (kFwdBlock / 64) >= ntile) return;  // the whole block (before the barrier)
-  stage_params(P, sP);
+  stage_frag_lds(P, sF);
   __syncthreads();
   if ((int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6) >= ntile) return;
-  FragBf f;
-  load_frag_bf(sP, r, g, f);
+  // the fragments stay in LDS and are read as each MFMA needs them (held in
+  // registers they cost 90 registers a lane, two waves per SIMD)
   // the features and bone of the next kFwdPre tiles of this wave are in
   // flight while a tile computes
   const int64_t tile0 = (int64_t)blockIdx.x * (kFwdBlock / 64) + (threadIdx.x >> 6);
@@ -198,7 +198,8 @@ __global__ void __launch_bounds__(kFwdBlock) mlp_fwd_bf16(const __hip_bfloat16 *
       Xq[u] = load_x_bf16(feat, ld, sn, g, okn);
       Bq[u] = okn && bone && g == 0 ? bone[sn] : 0;
       f32x4 z1[4], z2[4], o;
-      fwd_bf(f, X, z1, z2, o);
+      pin_in_loop();
+      fwd_bf_src(LdsW{sF, lane, g}, X, z1, z2, o);
       if (g == 0 && ok) {
         float sg = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
         if (!bone || bn >= 0) {
@@ -524,14 +525,17 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_bf16(const float *__restric
                                                           const float *__restrict__ P, float *__restrict__ gfeat,
                                                           float *__restrict__ partial) {
   extern __shared__ __attribute__((aligned(16))) unsigned char ldsb[];
+  // the forward's fragments stay in LDS (read as each MFMA needs them); held
+  // in registers beside the weight-gradient accumulators they spill
+  __shared__ __attribute__((aligned(16))) FragLds sF;
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4, wid = threadIdx.x >> 6;
   __bf16 *scr = reinterpret_cast<__bf16 *>(ldsb + wid * SCRB_BYTES);
-  // the parameters go to the scratch region until every wave holds its fragments
+  stage_frag_lds(P, sF);
+  // the parameters go to the scratch region until every wave holds its
+  // transposed fragments
   float *sP = reinterpret_cast<float *>(ldsb);
   stage_params(P, sP);
   __syncthreads();
-  FragBf f;
-  load_frag_bf(sP, r, g, f);
   FragBfT ft;
   load_frag_bft(sP, r, g, ft);
   __syncthreads();
@@ -561,7 +565,8 @@ __global__ void __launch_bounds__(kBwdBlock) mlp_bwd_bf16(const float *__restric
       const bool ok = s < S;
       const bf16x8 X = load_x_bf16(feat, ld, s, g, ok);
       f32x4 z1[4], z2[4], o;
-      fwd_bf(f, X, z1, z2, o);
+      pin_in_loop();
+      fwd_bf_src(LdsW{sF, lane, g}, X, z1, z2, o);
       float d3[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       if (g == 0 && ok && (!bone || bone[s] >= 0)) {
         const float ov[4] = {o[0], o[1], o[2], o[3]};
@@ -748,7 +753,9 @@ int bwd_blocks(int64_t S) {
 
 // as many blocks as stay resident (2 waves per SIMD by registers): each
 // wave then loops over its tiles with the next tile's loads in flight
-unsigned fwd_blocks(int64_t S) { return grid_for(ceil_div(S, 16) * 64, kFwdBlock, 256 * 2); }
+// workgroups per CU the forward kernels keep resident: two for FP32 (256
+// registers a lane), four for BF16 (fragments in LDS, 100 registers)
+unsigned fwd_blocks(int64_t S, int per_cu) { return grid_for(ceil_div(S, 16) * 64, kFwdBlock, 256 * per_cu); }
 
 }  // namespace
 
@@ -780,9 +787,9 @@ extern "C" int32_t ia355_mlp_fwd(const void *feat, int32_t feat_dtype, const int
   if (S == 0) return IA355_OK;
   hipStream_t s = as_stream(stream);
   if (dtype == IA355_F32)
-    mlp_fwd_f32<<<fwd_blocks(S), kFwdBlock, 0, s>>>((const float *)feat, bone, S, S_dev, ld, params, sigma, rgb);
+    mlp_fwd_f32<<<fwd_blocks(S, 2), kFwdBlock, 0, s>>>((const float *)feat, bone, S, S_dev, ld, params, sigma, rgb);
   else
-    mlp_fwd_bf16<<<fwd_blocks(S), kFwdBlock, 0, s>>>((const __hip_bfloat16 *)feat, bone, S, S_dev, ld, params, sigma,
+    mlp_fwd_bf16<<<fwd_blocks(S, 4), kFwdBlock, 0, s>>>((const __hip_bfloat16 *)feat, bone, S, S_dev, ld, params, sigma,
                                                      rgb);
   return launch_status();
 }

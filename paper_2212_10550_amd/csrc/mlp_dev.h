@@ -28,13 +28,21 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// max(z, 0): one v_max_f32 (a compare-and-select keeps NaN semantics and costs two)
-__device__ __forceinline__ float relu(float z) { return fmaxf(z, 0.0f); }
+// max(z, 0) as a signed-integer max of the bits: one v_max_i32 (fmaxf
+// first quiets its MFMA-produced input, a second instruction).  Every
+// non-negative float keeps its bits, every negative one (and -0) gives +0;
+// a NaN with the sign bit clear propagates.
+__device__ __forceinline__ float relu(float z) {
+  const int b = __builtin_bit_cast(int, z);
+  return __builtin_bit_cast(float, b > 0 ? b : 0);
+}
 
+// Density exp(o0) (clamped at exp(80)) and colour sigmoid(o1..3); the
+// sigmoid's reciprocal is the hardware one (1 ulp), not a division.
 __device__ __forceinline__ void head(const float o[4], float *sig, float c[3]) {
   *sig = expf(fminf(o[0], 80.0f));
 #pragma unroll
-  for (int k = 0; k < 3; ++k) c[k] = 1.0f / (1.0f + expf(-o[1 + k]));
+  for (int k = 0; k < 3; ++k) c[k] = __builtin_amdgcn_rcpf(1.0f + expf(-o[1 + k]));
 }
 
 // The parameters (26 KB, 16-byte aligned) copied into LDS by the whole block
@@ -111,6 +119,67 @@ __device__ __forceinline__ bf16x8 frag_bf(const float *P, int q, int r, int g) {
   }
   return v;
 }
+
+// First parameter of half h (elements 4h .. 4h + 3, consecutive parameters)
+// of fragment q of lane (r, g); -1: a zero half.
+__host__ __device__ inline int frag_half_at(int q, int r, int g, int h) {
+  return q < 4 ? w1_at(q, r, g, 4 * h) : (q < 12 ? w2_at((q - 4) / 2, (q - 4) % 2, r, g, 4 * h) : w3_at(q - 12, r, g, 4 * h));
+}
+
+// The BF16 decoder's fragments in LDS, one 16-byte slot per lane so that a
+// wave reads a fragment with one conflict-free load: mw[q][lane] holds
+// fragment q (0-3 layer 1, 4 + 2 mt + c layer 2, 12 + c layer 3) of lane
+// (lane % 16, lane / 16); b1, b2, b3 the biases.
+struct FragLds {
+  bf16x8 mw[14][64];
+  float b1[NH], b2[NH], b3[NOUT];
+};
+static_assert(offsetof(FragLds, b1) % 16 == 0 && offsetof(FragLds, b2) % 16 == 0 && offsetof(FragLds, b3) % 16 == 0,
+              "16-byte bias vectors");
+
+// A whole block fills the store from the parameters in global memory (16-byte
+// aligned): each fragment is two 16-byte loads of consecutive parameters,
+// converted as frag_value converts them.
+__device__ __forceinline__ void stage_frag_lds(const float *__restrict__ P, FragLds &s) {
+  for (int e = threadIdx.x; e < 14 * 64; e += blockDim.x) {
+    const int q = e >> 6, l = e & 63;
+    bf16x8 v;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = frag_half_at(q, l & 15, l >> 4, h);
+      const float4 p = i >= 0 ? *reinterpret_cast<const float4 *>(P + i) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      v[4 * h] = (__bf16)p.x;
+      v[4 * h + 1] = (__bf16)p.y;
+      v[4 * h + 2] = (__bf16)p.z;
+      v[4 * h + 3] = (__bf16)p.w;
+    }
+    s.mw[q][l] = v;
+  }
+  for (int i = threadIdx.x; i < NH; i += blockDim.x) {
+    s.b1[i] = P[OFF_B1 + i];
+    s.b2[i] = P[OFF_B2 + i];
+  }
+  if (threadIdx.x < NOUT) s.b3[threadIdx.x] = P[OFF_B3 + threadIdx.x];
+}
+
+// Weights fetched from a FragLds as each MFMA needs them.
+struct LdsW {
+  const FragLds &s;
+  int lane, g;
+  __device__ __forceinline__ bf16x8 w1(int mt) const { return s.mw[mt][lane]; }
+  __device__ __forceinline__ bf16x8 w2(int mt, int c) const { return s.mw[4 + 2 * mt + c][lane]; }
+  __device__ __forceinline__ bf16x8 w3(int c) const { return s.mw[12 + c][lane]; }
+  __device__ __forceinline__ f32x4 b1(int mt) const { return *reinterpret_cast<const f32x4 *>(s.b1 + 16 * mt + 4 * g); }
+  __device__ __forceinline__ f32x4 b2(int mt) const { return *reinterpret_cast<const f32x4 *>(s.b2 + 16 * mt + 4 * g); }
+  __device__ __forceinline__ f32x4 b3() const {
+    return g == 0 ? *reinterpret_cast<const f32x4 *>(s.b3) : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+};
+
+// A compiler-only barrier inside a loop: the LDS fragment reads after it
+// cannot be hoisted out of the loop (which would hold every fragment in
+// registers again).
+__device__ __forceinline__ void pin_in_loop() { asm volatile("" ::: "memory"); }
 
 // Pack the relu'd accumulators of tiles t = 2c, 2c+1 into one B operand.
 __device__ __forceinline__ bf16x8 pack_act(const f32x4 z[4], int c) {

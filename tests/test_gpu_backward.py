@@ -152,6 +152,30 @@ def test_hash_bwd(orc, log2T, tdt, overwrite, pad):
     assert (host(gx[:, S:]) == 3.0).all()
 
 
+@pytest.mark.parametrize("L", [6, 12])
+def test_hash_bwd_level_counts(orc, L):
+    """Table and position gradients for level counts other than 16 (one level
+    per lane with L <= 8; XCDs 4-7 with a single level at L = 12)."""
+    K = _K()
+    S = 3001
+    x = synth.random_points(S, 43)
+    table = synth.make_hash_table(L, 1 << 16, 2, seed=9, scale=0.3).astype(np.float32)
+    rng = np.random.default_rng(8)
+    gfeat = rng.normal(size=(S, 2 * L)).astype(np.float32)
+    bone = np.where(np.arange(S) % 9 == 4, -1, 0).astype(np.int16)
+    gt = torch.full((L, 1 << 16, 2), 7.0, device=dev())
+    gx = torch.full((3, S), 3.0, device=dev())
+    ws = torch.empty(K.hashgrid_encode_bwd_workspace_size(S, L), dtype=torch.uint8, device=dev())
+    gf = up(gfeat.reshape(S, L, 2).transpose(1, 0, 2).reshape(-1))
+    K.hashgrid_encode_bwd(gf, soa(x), up(bone), S, S, up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), gt, gx,
+                          K.OVERWRITE, ws=ws)
+    torch.cuda.synchronize()
+    rt, rx = orc.hash_encode_bwd(gfeat, x, table, orc.resolutions(L), np.array([0, 0, 0, 1, 1, 1.0]), valid=bone)
+    gclose(host(gt), rt, f"grad_table L={L}")
+    gclose_rows(host(gx).T, rx, f"grad_x L={L}")
+    assert (host(gx).T[bone < 0] == 0).all()
+
+
 @pytest.mark.parametrize("overwrite", [False, True])
 def test_hash_bwd_level_groups(orc, overwrite):
     """The coarse and the fine level groups, called separately (as two

@@ -192,6 +192,26 @@ def test_hash_encode(orc, log2T, scale, tdt):
     print(f"hash T=2^{log2T} scale {scale} {tdt}: max err {err:.2e}")
 
 
+@pytest.mark.parametrize("L", [6, 12])
+def test_hash_encode_level_counts(orc, L):
+    """Level counts other than 16: with L <= 8 each XCD serves one level (a
+    lane takes one level), with L = 12 XCDs 0-3 serve two levels and 4-7
+    one (a lane's second level is past L)."""
+    K = _K()
+    S = 3001
+    x = synth.random_points(S, 33)
+    table = synth.make_hash_table(L, 1 << 16, 2, seed=8, scale=0.5).astype(np.float32)
+    bone = np.where(np.arange(S) % 5 == 1, -1, 0).astype(np.int16)
+    feat = torch.full((L * S * 2,), 9.0, device=dev())
+    K.hashgrid_encode(soa(x), up(bone), S, S, up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), feat)
+    torch.cuda.synchronize()
+    got = host(feat).reshape(L, S, 2).transpose(1, 0, 2).reshape(S, 2 * L)
+    ref = orc.hash_encode(x, table, orc.resolutions(L), np.array([0, 0, 0, 1, 1, 1.0]), valid=bone)
+    err = assert_mixed(got, ref, TOL, f"hash L={L}")
+    assert (got[bone < 0] == 0).all()
+    print(f"hash L={L}: max err {err:.2e}")
+
+
 def test_hash_encode_bf16_features(orc):
     K = _K()
     S = 2049

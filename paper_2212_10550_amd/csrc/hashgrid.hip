@@ -29,45 +29,92 @@ using namespace ia355::hsh;
 namespace {
 
 constexpr int kFwdBlock = 256;
+constexpr int64_t kTwoSampleMin = (int64_t)1 << 22;  // samples (or capacity) from which a lane takes two
 
-// Block b works for XCD b % 8 on the kLv levels (b % 8) + 8 (kLv g + t),
-// t < kLv, of level group g = slot % ngroup (slot = b / 8), on 256-sample
-// chunks slot / ngroup, + nslot, + 2 nslot ...  A lane reads its sample's
-// position and bone once for its kLv levels and has all their corner gathers
-// in flight together.
-template <typename TT, typename FT, int kLv>
+// Level of a lane's slot t in level group g on XCD x, or -1 (no level).  With
+// two levels per lane and at most 16 levels, XCD x serves level x and level
+// L - 1 - x (when that is 8 or more): coarse levels, whose samples share
+// cells, pair with fine ones, whose gathers are scattered, so every XCD gets
+// a similar load and at most one fine table.  Otherwise XCD x serves levels
+// x + 8 (kLv g + t).
+template <int kLv>
+__device__ __forceinline__ int xcd_level(int x, int g, int t, int L) {
+  if (kLv == 2 && L <= 2 * kXcd) {
+    const int l = t == 0 ? x : L - 1 - x;
+    return (t == 0 ? l < L : l >= kXcd) ? l : -1;
+  }
+  const int l = x + kXcd * (kLv * g + t);
+  return l < L ? l : -1;
+}
+
+// Block b works for XCD b % 8 on the levels xcd_level gives its slots t <
+// kLv in level group g = slot % ngroup (slot = b / 8), on chunks of
+// 256 kSp samples slot / ngroup, + nslot, + 2 nslot ...  A lane takes kSp
+// samples of a chunk (256 apart) and reads each sample's position and bone
+// once for its kLv levels; all their corner gathers are in flight together.
+template <typename TT, typename FT, int kLv, int kSp>
 __global__ void __launch_bounds__(kFwdBlock) encode_kernel(const float *__restrict__ xc, const int16_t *__restrict__ bone,
                                                            int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
                                                            const TT *__restrict__ table, int L, int log2T, Levels lv,
                                                            Box box, FT *__restrict__ feat, int ngroup) {
   const int xcd = blockIdx.x % kXcd;
   const int slot = blockIdx.x / kXcd;
-  const int level0 = xcd + kXcd * kLv * (slot % ngroup);
-  if (level0 >= L) return;
+  int lev[kLv];
+#pragma unroll
+  for (int t = 0; t < kLv; ++t) lev[t] = xcd_level<kLv>(xcd, slot % ngroup, t, L);
+  if (lev[0] < 0) return;
   const int64_t Sn = count_of(S, S_dev);
   const int64_t nslot = gridDim.x / (kXcd * ngroup);
   const uint32_t T = 1u << log2T;
-  for (int64_t chunk = slot / ngroup; chunk * kFwdBlock < Sn; chunk += nslot) {
-    const int64_t n = chunk * kFwdBlock + threadIdx.x;
-    if (n >= Sn) break;
-    float a[kLv], b[kLv];
+  constexpr int64_t kSpan = (int64_t)kFwdBlock * kSp;
+  for (int64_t chunk = slot / ngroup; chunk * kSpan < Sn; chunk += nslot) {
+    int64_t n[kSp];
+    float x[kSp][3];
+    int bv[kSp];
+    bool in[kSp], use[kSp];
+    // positions and bones loaded together (one round trip; the bones are
+    // tested only after every load is issued)
 #pragma unroll
-    for (int t = 0; t < kLv; ++t) a[t] = b[t] = 0.0f;
-    // position and bone loaded together (one round trip)
-    const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
-    if (!bone || bone[n] >= 0) {
+    for (int sp = 0; sp < kSp; ++sp) {
+      n[sp] = chunk * kSpan + sp * kFwdBlock + threadIdx.x;
+      in[sp] = n[sp] < Sn;
+      const int64_t m = in[sp] ? n[sp] : 0;
+      x[sp][0] = xc[m];
+      x[sp][1] = xc[ld + m];
+      x[sp][2] = xc[2 * ld + m];
+      bv[sp] = 0;
+    }
+    if (bone)
+#pragma unroll
+      for (int sp = 0; sp < kSp; ++sp) bv[sp] = bone[in[sp] ? n[sp] : 0];
+#pragma unroll
+    for (int sp = 0; sp < kSp; ++sp) use[sp] = in[sp] && bv[sp] >= 0;
+    float a[kSp][kLv], b[kSp][kLv];
+#pragma unroll
+    for (int sp = 0; sp < kSp; ++sp)
+#pragma unroll
+      for (int t = 0; t < kLv; ++t) a[sp][t] = b[sp][t] = 0.0f;
+    // every lane encodes (no branch around the gathers, so all of them are
+    // in flight together; any position gives in-range cells); samples
+    // without a root then store zeros
+#pragma unroll
+    for (int sp = 0; sp < kSp; ++sp)
 #pragma unroll
       for (int t = 0; t < kLv; ++t) {
-        const int level = level0 + kXcd * t;
-        if (level < L)
-          encode_level(x, box, lv.res[level], lv.dense[level], T - 1u, table + (int64_t)level * T * 2, &a[t], &b[t]);
+        const int level = lev[t];
+        if (level >= 0)
+          encode_level(x[sp], box, lv.res[level], lv.dense[level], T - 1u, table + (int64_t)level * T * 2, &a[sp][t],
+                       &b[sp][t]);
       }
-    }
 #pragma unroll
-    for (int t = 0; t < kLv; ++t) {
-      const int level = level0 + kXcd * t;
-      if (level < L) store_feat2(feat, (int64_t)level * ld + n, a[t], b[t]);
-    }
+    for (int sp = 0; sp < kSp; ++sp)
+      if (in[sp])
+#pragma unroll
+        for (int t = 0; t < kLv; ++t) {
+          const int level = lev[t];
+          if (level >= 0)
+            store_feat2(feat, (int64_t)level * ld + n[sp], use[sp] ? a[sp][t] : 0.0f, use[sp] ? b[sp][t] : 0.0f);
+        }
   }
 }
 
@@ -86,20 +133,23 @@ struct EncodeArgs {
 };
 
 template <typename TT, typename FT>
-void launch_encode(const EncodeArgs &a, int lv_lane, unsigned g, hipStream_t s) {
+void launch_encode(const EncodeArgs &a, int lv_lane, int sp_lane, unsigned g, hipStream_t s) {
   const TT *t = static_cast<const TT *>(a.table);
   FT *f = static_cast<FT *>(a.feat);
-  if (lv_lane == 2)
-    encode_kernel<TT, FT, 2><<<g, kFwdBlock, 0, s>>>(a.xc, a.bone, a.S, a.S_dev, a.ld, t, a.L, a.log2T, a.lv, a.box, f,
-                                                     a.ngroup);
+  if (lv_lane == 2 && sp_lane == 2)
+    encode_kernel<TT, FT, 2, 2><<<g, kFwdBlock, 0, s>>>(a.xc, a.bone, a.S, a.S_dev, a.ld, t, a.L, a.log2T, a.lv, a.box,
+                                                        f, a.ngroup);
+  else if (lv_lane == 2)
+    encode_kernel<TT, FT, 2, 1><<<g, kFwdBlock, 0, s>>>(a.xc, a.bone, a.S, a.S_dev, a.ld, t, a.L, a.log2T, a.lv, a.box,
+                                                        f, a.ngroup);
   else
-    encode_kernel<TT, FT, 1><<<g, kFwdBlock, 0, s>>>(a.xc, a.bone, a.S, a.S_dev, a.ld, t, a.L, a.log2T, a.lv, a.box, f,
-                                                     a.ngroup);
+    encode_kernel<TT, FT, 1, 1><<<g, kFwdBlock, 0, s>>>(a.xc, a.bone, a.S, a.S_dev, a.ld, t, a.L, a.log2T, a.lv, a.box,
+                                                        f, a.ngroup);
 }
 
 // Position gradient dL/dx = sum_l sum_c (grad w_c) (theta_c . dL/dfeat_l),
 // in two kernels.  The first has the forward's mapping (block b on XCD
-// b % 8, levels b % 8 and b % 8 + 8, one lane per sample): every sample of a
+// b % 8, the levels xcd_level gives, one lane per sample): every sample of a
 // level is served by one XCD's L2, so cells shared by samples are fetched
 // once rather than once per XCD; it writes each level's contribution to a
 // workspace part [L][3][S].  The second sums the levels in a fixed order.
@@ -114,8 +164,10 @@ __global__ void __launch_bounds__(kBwdBlock) xgrad_level_kernel(
   // the encode's mapping: kLv levels (b % 8) + 8 (kLv g + t) per lane
   const int xcd = blockIdx.x % kXcd;
   const int slot = blockIdx.x / kXcd;
-  const int level0 = xcd + kXcd * kLv * (slot % ngroup);
-  if (level0 >= L) return;
+  int lev[kLv];
+#pragma unroll
+  for (int t = 0; t < kLv; ++t) lev[t] = xcd_level<kLv>(xcd, slot % ngroup, t, L);
+  if (lev[0] < 0) return;
   const int64_t Sn = count_of(S, S_dev);
   const int64_t nslot = gridDim.x / (kXcd * ngroup);
   const uint32_t T = 1u << log2T;
@@ -128,18 +180,18 @@ __global__ void __launch_bounds__(kBwdBlock) xgrad_level_kernel(
     const float x[3] = {xc[n], xc[ld + n], xc[2 * ld + n]};
 #pragma unroll
     for (int t = 0; t < kLv; ++t) {
-      const int level = level0 + kXcd * t;
-      g[t] = level < L ? reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * ld + n] : make_float2(0.0f, 0.0f);
+      const int level = lev[t];
+      g[t] = level >= 0 ? reinterpret_cast<const float2 *>(gfeat)[(int64_t)level * ld + n] : make_float2(0.0f, 0.0f);
       gx[t][0] = gx[t][1] = gx[t][2] = 0.0f;
     }
     if (!bone || bone[n] >= 0) {
-      // every level's gathers first, then the sums (a level past L repeats
-      // level0 with a zero gradient and is not stored)
+      // every level's gathers first, then the sums (a missing second level
+      // repeats the first with a zero gradient and is not stored)
       Corners c[kLv];
       float2 vv[kLv][8];
 #pragma unroll
       for (int t = 0; t < kLv; ++t) {
-        const int level = level0 + kXcd * t < L ? level0 + kXcd * t : level0;
+        const int level = lev[t] >= 0 ? lev[t] : lev[0];
         level_cell(x, box, lv.res[level], lv.dense[level], T - 1u, c[t], true);
         gather8(table + (int64_t)level * T * 2, c[t], vv[t]);
       }
@@ -155,8 +207,8 @@ __global__ void __launch_bounds__(kBwdBlock) xgrad_level_kernel(
     }
 #pragma unroll
     for (int t = 0; t < kLv; ++t) {
-      const int level = level0 + kXcd * t;
-      if (level >= L) continue;
+      const int level = lev[t];
+      if (level < 0) continue;
       float *pl = part + (int64_t)level * 3 * S;
       pl[n] = gx[t][0];
       pl[S + n] = gx[t][1];
@@ -831,9 +883,12 @@ extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, i
   // two levels per lane where an XCD serves several levels
   const int lv_lane = per_xcd >= 2 ? 2 : 1;
   const int ngroup = (per_xcd + lv_lane - 1) / lv_lane;
+  // two samples per lane as well for frame-sized calls (more gathers in
+  // flight per lane; at training-step sizes the halved lane count costs more)
+  const int sp_lane = lv_lane == 2 && S >= kTwoSampleMin ? 2 : 1;
   // chunk slots per (XCD, level group); with a device count at most 1024 per
   // group, the blocks loop over the rest (blocks past the count exit at once)
-  int64_t nslot = ceil_div(S, kFwdBlock);
+  int64_t nslot = ceil_div(S, (int64_t)kFwdBlock * sp_lane);
   if (S_dev && nslot > 1024) nslot = 1024;
   const int64_t blocks = nslot * ngroup * kXcd;
   if (blocks > 0x7fffffffLL) return IA355_ERR_INVALID_ARG;
@@ -841,13 +896,13 @@ extern "C" int32_t ia355_hashgrid_encode(const float *xc, const int16_t *bone, i
   const unsigned g = (unsigned)blocks;
   const EncodeArgs ea{xc, bone, S, S_dev, ld, table, L, log2T, lv, box, feat, ngroup};
   if (table_dtype == IA355_F32 && feat_dtype == IA355_F32)
-    launch_encode<float, float>(ea, lv_lane, g, s);
+    launch_encode<float, float>(ea, lv_lane, sp_lane, g, s);
   else if (table_dtype == IA355_F32)
-    launch_encode<float, __hip_bfloat16>(ea, lv_lane, g, s);
+    launch_encode<float, __hip_bfloat16>(ea, lv_lane, sp_lane, g, s);
   else if (feat_dtype == IA355_F32)
-    launch_encode<__half, float>(ea, lv_lane, g, s);
+    launch_encode<__half, float>(ea, lv_lane, sp_lane, g, s);
   else
-    launch_encode<__half, __hip_bfloat16>(ea, lv_lane, g, s);
+    launch_encode<__half, __hip_bfloat16>(ea, lv_lane, sp_lane, g, s);
   return launch_status();
 }
 

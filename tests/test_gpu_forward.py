@@ -212,6 +212,31 @@ def test_hash_encode_level_counts(orc, L):
     print(f"hash L={L}: max err {err:.2e}")
 
 
+def test_hash_encode_two_samples_per_lane(orc):
+    """A frame-sized capacity (2^22 samples, from which a lane takes two
+    samples) with a device-side count of 3001: the counted samples match the
+    oracle, the rest of the feature array is untouched."""
+    K = _K()
+    cap, S = 1 << 22, 3001
+    x = synth.random_points(S, 34)
+    xs = torch.zeros((3, cap), device=dev())
+    xs[:, :S] = up(x.T, torch.float32)
+    bone = torch.zeros(cap, dtype=torch.int16, device=dev())
+    bone[:S] = up(np.where(np.arange(S) % 6 == 2, -1, 1).astype(np.int16))
+    table = synth.make_hash_table(16, 1 << 19, 2, seed=10, scale=0.5).astype(np.float16)
+    feat = torch.full((16, cap, 2), 5.0, device=dev())
+    count = torch.tensor([S], dtype=torch.int64, device=dev())
+    K.hashgrid_encode(xs, bone, cap, cap, up(table), 16.0, 1.38, (0, 0, 0, 1, 1, 1), feat, S_dev=count)
+    torch.cuda.synchronize()
+    got = host(feat[:, :S, :]).transpose(1, 0, 2).reshape(S, 32)
+    valid = host(bone[:S])
+    ref = orc.hash_encode(x, table, orc.resolutions(16), np.array([0, 0, 0, 1, 1, 1.0]), valid=valid)
+    err = assert_mixed(got, ref, TOL, "hash two samples per lane")
+    assert (got[valid < 0] == 0).all()
+    assert bool((feat[:, S:, :] == 5.0).all())
+    print(f"hash two samples per lane: max err {err:.2e}")
+
+
 def test_hash_encode_bf16_features(orc):
     K = _K()
     S = 2049

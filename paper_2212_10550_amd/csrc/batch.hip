@@ -216,22 +216,6 @@ struct LdsMW {
   }
 };
 
-// Initialiser layers 2-3 from LDS (BF16 operands only).
-struct LdsRW {
-  const Store &st;
-  int lane, g;
-  __device__ __forceinline__ float w2f(int, int) const { return 0.0f; }
-  __device__ __forceinline__ float w3f(int, int) const { return 0.0f; }
-  __device__ __forceinline__ bf16x8 w2b(int mt, int c) const { return st.rw[2 * mt + c][lane]; }
-  __device__ __forceinline__ bf16x8 w3b(int mt, int c) const { return st.rw[8 + 2 * mt + c][lane]; }
-  __device__ __forceinline__ f32x4 b2(int mt) const {
-    return *reinterpret_cast<const f32x4 *>(st.rb2 + 16 * mt + 4 * g);
-  }
-  __device__ __forceinline__ f32x4 b3(int mt) const {
-    return *reinterpret_cast<const f32x4 *>(st.rb3 + 16 * mt + 4 * g);
-  }
-};
-
 // A compiler-only barrier: keeps the fragment fetches of one tile from being
 // hoisted out of the tile loop (which would hold every fragment in registers).
 __device__ __forceinline__ void keep_in_loop() { asm volatile("" ::: "memory"); }
@@ -502,7 +486,7 @@ __global__ void __launch_bounds__(kW * kWave, kMinGroups * kW / 4) render_kernel
             int bi;
             float off3[3], h1[4][4];
             rid::layer1(xs, wm.c1, st.w1x, g, h1);
-            rid::tile_tail<true>(h1, LdsRW{st, lane, g}, nb, g, &bi, off3);
+            rid::tile_tail<true>(h1, rid::LdsFragW{st.rw, st.rb2, st.rb3, lane, g}, nb, g, &bi, off3);
             if (g == t) {
               const int kb = bi < nb ? bi : 0;
               ibone = kb;

@@ -22,12 +22,16 @@ constexpr int kBlock = 256;
 using rid::H;
 using rid::kMaxOut;
 
+// BF16: the parameters are read from global memory once per block (the pose
+// fold, layer 1's x weights, the layer 2-3 fragments into a 12 KB LDS store
+// read as each MFMA needs them), so a block needs ~17 KB of LDS and ~100
+// registers a lane: four waves per SIMD.  FP32: the whole parameter block
+// is staged in LDS (61.5 KB) and the fragments held in registers.
 template <bool BF16>
-__global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restrict__ xp_soa, int64_t S,
-                                                          const int64_t *__restrict__ S_dev, int64_t ld,
-                                                          const float *__restrict__ pose, const float *__restrict__ P,
-                                                          const float *__restrict__ B, int nb,
-                                                          int16_t *__restrict__ bone_out, float *__restrict__ x0_soa) {
+__global__ void __launch_bounds__(kBlock, BF16 ? 4 : 1) rootinit_kernel(
+    const float *__restrict__ xp_soa, int64_t S, const int64_t *__restrict__ S_dev, int64_t ld,
+    const float *__restrict__ pose, const float *__restrict__ P, const float *__restrict__ B, int nb,
+    int16_t *__restrict__ bone_out, float *__restrict__ x0_soa) {
   const rid::Layout l = rid::layout(nb);
   // a block without a tile returns before any work (uniform, ahead of the
   // barriers): with a device-side count the grid is sized for the capacity
@@ -37,22 +41,30 @@ __global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restric
   __shared__ float w1x[H * 3];   // W1[:, :3]
   __shared__ float sBinv[64 * 12];
   __shared__ int sBok[64];
-  // the parameters, copied into LDS once per block with coalesced 16-byte
-  // loads (the pose fold walks W1 row by row; the MFMA fragments gather
-  // single values): a lane reading them from global memory one value at a
-  // time waits on a different cache line per value
+  __shared__ __attribute__((aligned(16))) bf16x8 sRw[BF16 ? 12 : 1][kWave];
+  __shared__ __attribute__((aligned(16))) float sRb2[BF16 ? H : 4], sRb3[BF16 ? kMaxOut : 4];
+  // FP32: the parameters, copied into LDS once per block with coalesced
+  // 16-byte loads (the pose fold walks W1 row by row; the MFMA fragments
+  // gather single values)
   extern __shared__ __attribute__((aligned(16))) float sP[];
-  rid::stage_copy(P, l.total, sP);
-  __syncthreads();
   static_assert(kBlock == 4 * H, "four threads per hidden neuron");
-  rid::fold_pose(sP, l, pose, nb, c1);
-  for (int e = threadIdx.x; e < H * 3; e += kBlock) w1x[e] = sP[l.offW1 + (e / 3) * l.nin + (e % 3)];
+  const float *Pw;  // where the fold and layer 1 read the parameters
+  if constexpr (BF16) {
+    Pw = P;
+    rid::stage_frag_lds(P, l, sRw, sRb2, sRb3);
+  } else {
+    rid::stage_copy(P, l.total, sP);
+    __syncthreads();
+    Pw = sP;
+  }
+  rid::fold_pose(Pw, l, pose, nb, c1);
+  for (int e = threadIdx.x; e < H * 3; e += kBlock) w1x[e] = Pw[l.offW1 + (e / 3) * l.nin + (e % 3)];
   stage_bone_inverses(B, nb, sBinv, sBok);
   __syncthreads();
 
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
   rid::Frag<BF16> f;
-  rid::load_frag<BF16>(sP, l, r, g, f);
+  if constexpr (!BF16) rid::load_frag<BF16>(sP, l, r, g, f);
   S = Sn;
   const int64_t ntile = ceil_div(S, 16);
   const int64_t wstride = (int64_t)gridDim.x * (kBlock / 64);
@@ -67,7 +79,16 @@ __global__ void __launch_bounds__(kBlock) rootinit_kernel(const float *__restric
     }
     int bi;
     float off[3];
-    rid::tile<BF16>(x, c1, w1x, f, nb, g, &bi, off);
+    if constexpr (BF16) {
+      float h1[4][4];
+      rid::layer1(x, c1, w1x, g, h1);
+      // the fragment reads stay in the loop (hoisted, they would hold every
+      // fragment in registers)
+      asm volatile("" ::: "memory");
+      rid::tile_tail<true>(h1, rid::LdsFragW{sRw, sRb2, sRb3, lane, g}, nb, g, &bi, off);
+    } else {
+      rid::tile<BF16>(x, c1, w1x, f, nb, g, &bi, off);
+    }
     if (g == 0 && ok) {
       const int k = bi < nb ? bi : 0;
       const float *Bi = sBinv + 12 * k;
@@ -91,15 +112,16 @@ extern "C" int32_t ia355_rootinit_fwd(const float *xp, int64_t S, const int64_t 
   if (dtype != IA355_F32 && dtype != IA355_BF16) return IA355_ERR_INVALID_ARG;
   if (S > 0 && (!xp || !init_bone || !x0)) return IA355_ERR_INVALID_ARG;
   if (S == 0) return IA355_OK;
-  // at most two blocks per CU (the parameters take 61.5 KB of LDS each), each
-  // wave looping over its tiles
-  const unsigned grid = grid_for(ceil_div(S, 16) * 64, kBlock, 256 * 2);
+  // FP32: at most two blocks per CU (the parameters take 61.5 KB of LDS
+  // each); BF16: four; each wave loops over its tiles
   const size_t lds = sizeof(float) * (size_t)(H * (3 + 6 * nb) + H + H * H + H + (nb + 3) * H + (nb + 3));
   if (lds > 96 * 1024) return IA355_ERR_UNSUPPORTED;
   hipStream_t s = as_stream(stream);
   if (dtype == IA355_F32)
-    rootinit_kernel<false><<<grid, kBlock, lds, s>>>(xp, S, S_dev, ld, pose, params, B, nb, init_bone, x0);
+    rootinit_kernel<false><<<grid_for(ceil_div(S, 16) * 64, kBlock, 256 * 2), kBlock, lds, s>>>(
+        xp, S, S_dev, ld, pose, params, B, nb, init_bone, x0);
   else
-    rootinit_kernel<true><<<grid, kBlock, lds, s>>>(xp, S, S_dev, ld, pose, params, B, nb, init_bone, x0);
+    rootinit_kernel<true><<<grid_for(ceil_div(S, 16) * 64, kBlock, 256 * 4), kBlock, 0, s>>>(
+        xp, S, S_dev, ld, pose, params, B, nb, init_bone, x0);
   return launch_status();
 }

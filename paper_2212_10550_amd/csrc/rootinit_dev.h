@@ -268,6 +268,51 @@ struct RegFrag {
   }
 };
 
+// BF16 fragments of layers 2-3 read from LDS as each MFMA needs them:
+// rw[q][lane] is fragment q of lane (lane % 16, lane / 16) (q as frag_bf:
+// 0-7 layer 2, 8-11 layer 3), rb2 [64] and rb3 [kMaxOut] the biases
+// (16-byte aligned, rb3 zero past nb + 3).
+struct LdsFragW {
+  const bf16x8 (*rw)[kWave];
+  const float *rb2, *rb3;
+  int lane, g;
+  __device__ __forceinline__ float w2f(int, int) const { return 0.0f; }
+  __device__ __forceinline__ float w3f(int, int) const { return 0.0f; }
+  __device__ __forceinline__ bf16x8 w2b(int mt, int c) const { return rw[2 * mt + c][lane]; }
+  __device__ __forceinline__ bf16x8 w3b(int mt, int c) const { return rw[8 + 2 * mt + c][lane]; }
+  __device__ __forceinline__ f32x4 b2(int mt) const { return *reinterpret_cast<const f32x4 *>(rb2 + 16 * mt + 4 * g); }
+  __device__ __forceinline__ f32x4 b3(int mt) const { return *reinterpret_cast<const f32x4 *>(rb3 + 16 * mt + 4 * g); }
+};
+
+// The block fills an LdsFragW's arrays from the parameters P (global
+// memory), one fragment per thread at a time.
+__device__ __forceinline__ void stage_frag_lds(const float *__restrict__ P, const Layout &l, bf16x8 (*rw)[kWave],
+                                               float *rb2, float *rb3) {
+  // a fragment's elements j = 0..3 and 4..7 are consecutive parameters at
+  // 16-byte aligned offsets: two 16-byte loads when P is 16-byte aligned
+  const bool al = ((uintptr_t)P & 15) == 0;
+  for (int e = threadIdx.x; e < 12 * kWave; e += blockDim.x) {
+    const int q = e / kWave, ln = e % kWave, r = ln & 15, g = ln >> 4;
+    if (al) {
+      bf16x8 v;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = q < 8 ? w2b_at(l, q / 2, q % 2, 4 * h, r, g) : w3b_at(l, (q - 8) / 2, q % 2, 4 * h, r, g);
+        const float4 p4 = i >= 0 ? *reinterpret_cast<const float4 *>(P + i) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        v[4 * h] = (__bf16)p4.x;
+        v[4 * h + 1] = (__bf16)p4.y;
+        v[4 * h + 2] = (__bf16)p4.z;
+        v[4 * h + 3] = (__bf16)p4.w;
+      }
+      rw[q][ln] = v;
+    } else {
+      rw[q][ln] = frag_bf(P, l, q, r, g);
+    }
+  }
+  for (int i = threadIdx.x; i < H; i += blockDim.x) rb2[i] = P[l.offb2 + i];
+  for (int i = threadIdx.x; i < kMaxOut; i += blockDim.x) rb3[i] = i < l.nout ? P[l.offb3 + i] : 0.0f;
+}
+
 // One 16-sample tile, called by all 64 lanes of a wave (lane r + 16 g holds
 // sample r's point x): the argmax bone (ties: the lowest) and the three
 // offsets, in every lane of sample r.  c1 [64] and w1x [64][3] in LDS.

@@ -183,14 +183,17 @@ __global__ void __launch_bounds__(1024) march_scan_top(int64_t *chunk_sum, int64
 }
 
 template <int kRaysPerWave>
-__global__ void __launch_bounds__(kBlock) march_fill(const float *ro, const float *rd, int64_t R,
-                                                     const uint64_t *masks, int nw, const float *ray_tn,
-                                                     const int64_t *block_off, const int64_t *chunk_off,
-                                                     int64_t *ray_off, const float *ray_dt, float *xs, float *ts,
+__global__ void __launch_bounds__(kBlock) march_fill(const float *__restrict__ ro, const float *__restrict__ rd,
+                                                     int64_t R, const uint64_t *__restrict__ masks, int nw,
+                                                     const float *__restrict__ ray_tn, const int64_t *block_off,
+                                                     const int64_t *chunk_off, int64_t *ray_off,
+                                                     const float *__restrict__ ray_dt, float *xs, float *ts,
                                                      int32_t *ray_id, int64_t cap) {
 #pragma clang fp contract(off)
   constexpr int kRays = kRaysPerWave * kWavesPerBlock;
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  // the wave index is uniform: a ray's inputs and masks go through the
+  // scalar cache
+  const int lane = threadIdx.x & (kWave - 1), wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int64_t r0 = (int64_t)blockIdx.x * kRays + wid * kRaysPerWave;
   if (r0 >= R) return;
   const int64_t base = block_off[blockIdx.x] + chunk_off[blockIdx.x / kScanChunk];

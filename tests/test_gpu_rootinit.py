@@ -48,6 +48,33 @@ def test_rootinit_fwd(orc, dtype):
         assert np.abs(gx - rx0)[agree].mean() < 1e-2
 
 
+def test_rootinit_bf16_unaligned_params():
+    """BF16 initialiser with its parameter block at an address that is not a
+    multiple of 16 bytes (the fragments are then gathered one value at a
+    time instead of two 16-byte loads): outputs bit-equal to the aligned
+    call's."""
+    K = _K()
+    w = synth.train_step()
+    skel = synth.make_skeleton(0)
+    S = 2001
+    xp = synth.sample_posed_points(skel, w.B.astype(np.float64), S, 5)
+    params = _params()
+    pa = up(params)
+    buf = torch.zeros(params.size + 1, device=dev())
+    buf[1:] = pa
+    pu = buf[1:]  # 4 bytes past a 16-byte boundary
+    assert pu.data_ptr() % 16 != 0
+    outs = []
+    for p in (pa, pu):
+        bone = torch.empty(S, dtype=torch.int16, device=dev())
+        x0 = torch.empty(3, S, device=dev())
+        K.rootinit_fwd(soa(xp), S, S, up(w.pose_params.reshape(-1)), p, up(w.B), K.BF16, bone, x0)
+        torch.cuda.synchronize()
+        outs.append((host(bone), host(x0)))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1].view(np.uint32), outs[1][1].view(np.uint32))
+
+
 def test_deform_guided(orc):
     K = _K()
     w = synth.train_step()

@@ -359,9 +359,11 @@ __global__ void __launch_bounds__(kDgBlock) table_grad_dense_kernel(const float 
 // (level, entry, w_c dL/dfeat_l) belongs to bin (level, tile), bins in
 // level-major order.  Five passes:
 //  1. count: every block counts its updates per bin in LDS and writes its
-//     column of the histogram hist[bin][block];
-//  2. scan: exclusive scan of the histogram in bin-major order, in chunks of
-//     4096 (offsets inside the chunk, chunk totals);
+//     row of the histogram hist[block][bin] (contiguous: a column per block
+//     would cost a 32-byte sector per 4-byte count, written and read back);
+//  2. scan: exclusive scan of the histogram in bin-major order (bin, then
+//     block), in chunks of 4096 (offsets inside the chunk, chunk totals),
+//     each count replaced by its offset in place;
 //  3. plan (one block): offsets of the chunks, the record range of every bin
 //     and the number of accumulation chunks it needs (<= kAccChunk records
 //     each);
@@ -578,25 +580,31 @@ __global__ void __launch_bounds__(kBinBlock) bin_count_kernel(const float *__res
     }
   }
   __syncthreads();
-  const int P = gridDim.x;
-  for (int i = threadIdx.x; i < nbins; i += kBinBlock) hist[(int64_t)i * P + blockIdx.x] = cnt[i];
+  for (int i = threadIdx.x; i < nbins; i += kBinBlock) hist[(int64_t)blockIdx.x * nbins + i] = cnt[i];
 }
 
-__global__ void __launch_bounds__(1024) bin_hist_scan_kernel(uint32_t *__restrict__ hist, int64_t H,
+// Position in hist[block][bin] of element j of the bin-major order (bin j / P,
+// block j % P); H = nbins P < 2^23.
+__device__ __forceinline__ uint32_t hist_at(uint32_t j, uint32_t P, uint32_t nbins) {
+  return (j % P) * nbins + j / P;
+}
+
+__global__ void __launch_bounds__(1024) bin_hist_scan_kernel(uint32_t *__restrict__ hist, int64_t H, int P, int nbins,
                                                             uint32_t *__restrict__ csum) {
   __shared__ uint32_t wsum[1024 / kWave];
   const int64_t i0 = (int64_t)blockIdx.x * kHsChunk + (int64_t)threadIdx.x * kHsPer;
-  uint32_t v[kHsPer], run = 0;
+  uint32_t v[kHsPer], a[kHsPer], run = 0;
 #pragma unroll
   for (int j = 0; j < kHsPer; ++j) {
-    v[j] = i0 + j < H ? hist[i0 + j] : 0u;
+    a[j] = hist_at((uint32_t)(i0 + j), (uint32_t)P, (uint32_t)nbins);
+    v[j] = i0 + j < H ? hist[a[j]] : 0u;
     run += v[j];
   }
   uint32_t total;
   uint32_t off = block_scan_u32(run, wsum, &total);
 #pragma unroll
   for (int j = 0; j < kHsPer; ++j) {
-    if (i0 + j < H) hist[i0 + j] = off;
+    if (i0 + j < H) hist[a[j]] = off;
     off += v[j];
   }
   if (threadIdx.x == 0) csum[blockIdx.x] = total;
@@ -625,12 +633,13 @@ __global__ void __launch_bounds__(1024) bin_plan_kernel(const uint32_t *__restri
     const int b = b0 + threadIdx.x;
     uint32_t nch = 0, st = 0, en = 0;
     if (b < nbins) {
+      // block 0's offset of bin b (row 0 of hist[block][bin])
       const int64_t j = (int64_t)b * P;
-      st = hist[j] + coff[j / kHsChunk];
+      st = hist[b] + coff[j / kHsChunk];
       en = n_rec;
       if (b + 1 < nbins) {
         const int64_t j1 = j + P;
-        en = hist[j1] + coff[j1 / kHsChunk];
+        en = hist[b + 1] + coff[j1 / kHsChunk];
       }
       nch = en > st ? (en - st + kAccChunk - 1) / kAccChunk : 1u;
     }
@@ -659,8 +668,8 @@ __global__ void __launch_bounds__(kBinBlock) bin_scatter_kernel(
   const int nbins = nl << tpl_log2;
   const int P = gridDim.x;
   for (int i = threadIdx.x; i < nbins; i += kBinBlock) {
-    const int64_t j = (int64_t)i * P + blockIdx.x;
-    cur[i] = hist[j] + coff[j / kHsChunk];
+    const int64_t j = (int64_t)i * P + blockIdx.x;  // bin-major position
+    cur[i] = hist[(int64_t)blockIdx.x * nbins + i] + coff[j / kHsChunk];
   }
   __syncthreads();
   const int64_t Sn = count_of(S, S_dev);
@@ -1023,7 +1032,7 @@ extern "C" int32_t ia355_hashgrid_table_grad(const float *grad_feat, const float
   if (!reuse) {  // passes 1-3 read only the positions, the bones and the count
     bin_count_kernel<<<g.P, kBinBlock, cnt_lds, s>>>(xc, bone, S, S_dev, ld, l0, l1 - l0, log2T, g.tb, lv, box,
                                                      w.hist);
-    bin_hist_scan_kernel<<<g.nchunk, 1024, 0, s>>>(w.hist, g.H, w.csum);
+    bin_hist_scan_kernel<<<g.nchunk, 1024, 0, s>>>(w.hist, g.H, g.P, g.nbins, w.csum);
     bin_plan_kernel<<<1, 1024, 0, s>>>(w.hist, w.csum, g.nchunk, g.nbins, g.P, w.chunk_first, w.chunk_info);
     if (plan_only) return launch_status();
   }

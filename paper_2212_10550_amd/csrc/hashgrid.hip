@@ -583,29 +583,52 @@ __global__ void __launch_bounds__(kBinBlock) bin_count_kernel(const float *__res
   for (int i = threadIdx.x; i < nbins; i += kBinBlock) hist[(int64_t)blockIdx.x * nbins + i] = cnt[i];
 }
 
-// Position in hist[block][bin] of element j of the bin-major order (bin j / P,
-// block j % P); H = nbins P < 2^23.
-__device__ __forceinline__ uint32_t hist_at(uint32_t j, uint32_t P, uint32_t nbins) {
-  return (j % P) * nbins + j / P;
-}
-
+// Exclusive scan of one chunk of the histogram in bin-major order (element
+// j = bin P + block), in place in hist[block][bin].  The chunk's elements
+// sit in a rectangle of rows (blocks) by a few bins; they are read and
+// written row by row (neighbouring threads, neighbouring bins) through an
+// LDS copy in j order, whose rows of P are padded by one word so a row
+// walk does not fall on one bank.  H = nbins P < 2^23.
 __global__ void __launch_bounds__(1024) bin_hist_scan_kernel(uint32_t *__restrict__ hist, int64_t H, int P, int nbins,
                                                             uint32_t *__restrict__ csum) {
   __shared__ uint32_t wsum[1024 / kWave];
-  const int64_t i0 = (int64_t)blockIdx.x * kHsChunk + (int64_t)threadIdx.x * kHsPer;
-  uint32_t v[kHsPer], a[kHsPer], run = 0;
+  __shared__ uint32_t sv[2 * kHsChunk + 1];  // e + e / P for e < kHsChunk
+  const uint32_t up = (uint32_t)P;
+  const uint32_t j0 = (uint32_t)blockIdx.x * kHsChunk;
+  const uint32_t j1 = (int64_t)j0 + kHsChunk < H ? j0 + kHsChunk : (uint32_t)H;
+  const uint32_t b_lo = j0 / up, nb = (j1 - 1) / up - b_lo + 1;  // bins the chunk touches
+  const uint32_t R = up * nb;                                     // rectangle: P rows by nb bins
+  for (uint32_t r = threadIdx.x; r < R; r += 1024) {
+    const uint32_t p = r / nb, b = b_lo + r % nb, j = b * up + p;
+    if (j >= j0 && j < j1) {
+      const uint32_t e = j - j0;
+      sv[e + e / up] = hist[(int64_t)p * nbins + b];
+    }
+  }
+  __syncthreads();
+  const uint32_t e0 = threadIdx.x * kHsPer;
+  uint32_t v[kHsPer], run = 0;
 #pragma unroll
-  for (int j = 0; j < kHsPer; ++j) {
-    a[j] = hist_at((uint32_t)(i0 + j), (uint32_t)P, (uint32_t)nbins);
-    v[j] = i0 + j < H ? hist[a[j]] : 0u;
-    run += v[j];
+  for (int q = 0; q < kHsPer; ++q) {
+    const uint32_t e = e0 + q;
+    v[q] = j0 + e < j1 ? sv[e + e / up] : 0u;
+    run += v[q];
   }
   uint32_t total;
-  uint32_t off = block_scan_u32(run, wsum, &total);
+  uint32_t off = block_scan_u32(run, wsum, &total);  // its barriers order the reads above and the writes below
 #pragma unroll
-  for (int j = 0; j < kHsPer; ++j) {
-    if (i0 + j < H) hist[a[j]] = off;
-    off += v[j];
+  for (int q = 0; q < kHsPer; ++q) {
+    const uint32_t e = e0 + q;
+    if (j0 + e < j1) sv[e + e / up] = off;
+    off += v[q];
+  }
+  __syncthreads();
+  for (uint32_t r = threadIdx.x; r < R; r += 1024) {
+    const uint32_t p = r / nb, b = b_lo + r % nb, j = b * up + p;
+    if (j >= j0 && j < j1) {
+      const uint32_t e = j - j0;
+      hist[(int64_t)p * nbins + b] = sv[e + e / up];
+    }
   }
   if (threadIdx.x == 0) csum[blockIdx.x] = total;
 }
